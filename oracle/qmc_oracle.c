@@ -1,0 +1,795 @@
+/*
+ * qmc_oracle.c -- plain, slow CPU oracle for the real-time QMC population dynamics of
+ * Shen & Lidar, arXiv:2502.18929 (main text eqs. (1)-(3) and the End Matter on spawn and
+ * annihilation population dynamics).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests/, by the package smoke check and by the CPU-baseline
+ * leg of bench.py, never by the product path.  It shares no code with the HIP library.
+ *
+ * Where the paper is silent or its printed formula cannot be used as written, this file follows
+ * these readings (each also listed in the design notes of the repository):
+ *  R1  The dissipator is D[L]rho = 2 L rho L^dagger - {L^dagger L, rho} and the vectorized
+ *      Liouvillian of eq. (2) is built from it with conj(L) (x) L, I (x) L^dagger L and
+ *      (L^dagger L)^T (x) I; the printed forms drop a dagger / conjugate.
+ *  R2  Key of |i><j| is (j << n) | i (column stacking; the printed vec(|i> (x) |j>) is garbled).
+ *  R3  Spawning (End Matter, spawn step) draws a binomial count and a multinomial over the
+ *      (target, Re/Im) channels of the column; here every channel amount dt * L_col * N is
+ *      rounded stochastically with one systematic comb per parent, in Q32 fixed point.  The
+ *      expectation is the one the paper states (E[children] = dt L N) and no p <= 1 is needed.
+ *  R4  The diagonal entry of the column ("any state", including |i,j> itself) is applied as
+ *      death/cloning to N(t) itself, with its own comb draw, before annihilation.
+ *  R5  Coefficients are evaluated at the left end of the step (t_s = s * dt): the caller passes
+ *      s_m(t_s) and gamma_k(t_s) per step.
+ *  R6  No population control by default (the Liouvillian is trace preserving, so the paper uses
+ *      none); an optional constant diagonal shift S per replica enters death as L_diag + S.
+ *
+ * Floating point: the only FP64 arithmetic is the coefficient quantization, done in a fixed
+ * operation order (compile with -ffp-contract=off).  Everything the walkers touch is integer.
+ */
+#include "qmc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10: Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as 1, 2, 3",  */
+/* SC'11.  Ten rounds of the Philox S-box on a 4x32-bit counter, key bumped by the Weyl        */
+/* constants between rounds.                                                                  */
+/* ------------------------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Systematic comb rounding (reading R3).  E[out[k]] = x[k] / 2^32 exactly for U uniform. */
+void orc_comb(uint32_t m, const int64_t* x, uint32_t U, int64_t* out) {
+  uint64_t r = U;
+  for (uint32_t k = 0; k < m; ++k) {
+    uint64_t mag = x[k] < 0 ? (uint64_t)0 - (uint64_t)x[k] : (uint64_t)x[k];
+    uint64_t t = r + mag;
+    uint64_t cnt = t >> 32;
+    r = t & 0xFFFFFFFFull;
+    out[k] = x[k] < 0 ? -(int64_t)cnt : (int64_t)cnt;
+  }
+}
+
+static int popc64(uint64_t v) { return __builtin_popcountll(v); }
+static int parity64(uint64_t v) { return __builtin_parityll(v); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Context                                                                                     */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t xmask, zmask; /* key-space masks of the map rho -> kappa A rho B */
+  double kre, kim;       /* kappa0: coefficient before the time-dependent weight */
+  uint32_t kind, index;  /* 0: weight s_m(t), m = index; 1: weight gamma_k(t), k = index */
+} term_t;
+
+typedef struct {
+  uint64_t* key;
+  int32_t* re;
+  int32_t* im;
+  uint64_t n;
+} store_t;
+
+struct orc_ctx {
+  uint32_t n, R;
+  uint64_t seed;
+  double dt;
+  uint32_t n_h, n_l;
+  uint32_t n_terms;
+  term_t* terms;
+  store_t* st; /* [R] */
+  double* shift; /* [R] */
+  uint32_t step;
+};
+
+/* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
+ * as rho -> kappa * A rho B with A = X^xa Z^za (left) and B = X^xb Z^zb (right).  On the key
+ * (j << n) | i this gives the target key ^ ((xb << n) | xa) with sign
+ * (-1)^{popc(za & i) + popc(zb & j)} * (-1)^{popc(zb & xb)}; the last, key-independent factor is
+ * folded into kappa0 below. */
+static int compile_terms(orc_ctx* c, const orc_monomial* h, const uint32_t* l_off,
+                         const orc_monomial* l) {
+  const uint32_t n = c->n;
+  uint64_t cnt = 2ull * c->n_h;
+  for (uint32_t k = 0; k < c->n_l; ++k) {
+    uint64_t na = l_off[k + 1] - l_off[k];
+    cnt += 3ull * na * na;
+  }
+  c->terms = (term_t*)calloc(cnt ? cnt : 1, sizeof(term_t));
+  if (!c->terms) return ORC_ERR_NOMEM;
+  uint32_t t = 0;
+  /* -i[H, rho] = -i H rho + i rho H, eq. (1). */
+  for (uint32_t m = 0; m < c->n_h; ++m) {
+    uint64_t x = h[m].x, z = h[m].z;
+    double hre = h[m].re, him = h[m].im;
+    /* -i * H_m rho: A = P_m, B = I, kappa = -i h. */
+    c->terms[t++] = (term_t){x, z, him, -hre, 0, m};
+    /* +i * rho H_m: A = I, B = P_m, kappa = +i h, times the folded (-1)^{popc(x & z)}. */
+    double f = (popc64(x & z) & 1) ? -1.0 : 1.0;
+    c->terms[t++] = (term_t){x << n, z << n, f * -him, f * hre, 0, m};
+  }
+  /* (1/2) gamma D[L] rho = gamma L rho L^dagger - (gamma/2) {L^dagger L, rho}, L = sum_a c_a P_a. */
+  for (uint32_t k = 0; k < c->n_l; ++k) {
+    for (uint32_t a = l_off[k]; a < l_off[k + 1]; ++a) {
+      for (uint32_t b = l_off[k]; b < l_off[k + 1]; ++b) {
+        uint64_t xa = l[a].x, za = l[a].z, xb = l[b].x, zb = l[b].z;
+        double ar = l[a].re, ai = l[a].im, br = l[b].re, bi = l[b].im;
+        /* Jump term c_a conj(c_b) P_a rho P_b^dagger.  P_b^dagger = (-1)^{popc(xb&zb)} P_b, and
+         * that sign cancels the folded constant of the right factor, so kappa0 = c_a conj(c_b). */
+        c->terms[t++] = (term_t){(xb << n) | xa, (zb << n) | za, ar * br + ai * bi,
+                                 ai * br - ar * bi, 1, k};
+        /* conj(c_a) c_b P_a^dagger P_b = mu * X^{xa^xb} Z^{za^zb}, using
+         * P_a^dagger = (-1)^{popc(xa&za)} P_a and Z^za X^xb = (-1)^{popc(za&xb)} X^xb Z^za. */
+        double sg = ((popc64(xa & za) + popc64(za & xb)) & 1) ? -1.0 : 1.0;
+        double mre = sg * (ar * br + ai * bi);
+        double mim = sg * (ar * bi - ai * br);
+        uint64_t x = xa ^ xb, z = za ^ zb;
+        /* -(1/2) mu M rho */
+        c->terms[t++] = (term_t){x, z, -0.5 * mre, -0.5 * mim, 1, k};
+        /* -(1/2) mu rho M, with the folded (-1)^{popc(x & z)}. */
+        double f = (popc64(x & z) & 1) ? -1.0 : 1.0;
+        c->terms[t++] = (term_t){x << n, z << n, f * (-0.5 * mre), f * (-0.5 * mim), 1, k};
+      }
+    }
+  }
+  c->n_terms = t;
+  return ORC_OK;
+}
+
+int orc_create(uint32_t n_qubits, uint32_t n_replicas, uint64_t seed, double dt, uint32_t n_h,
+               const orc_monomial* h, uint32_t n_l, const uint32_t* l_off, const orc_monomial* l,
+               const uint64_t* keys, const int32_t* re, const int32_t* im, uint64_t n0,
+               orc_ctx** out) {
+  if (!out || n_qubits < 1 || n_qubits > 32 || n_replicas < 1 || n_replicas >= (1u << 24))
+    return ORC_ERR_ARG;
+  if (!(dt > 0.0) || !isfinite(dt)) return ORC_ERR_ARG;
+  uint64_t kmask = n_qubits == 32 ? ~0ull : ((1ull << (2 * n_qubits)) - 1);
+  uint64_t qmask = n_qubits == 32 ? 0xFFFFFFFFull : ((1ull << n_qubits) - 1);
+  for (uint32_t m = 0; m < n_h; ++m)
+    if ((h[m].x & ~qmask) || (h[m].z & ~qmask)) return ORC_ERR_ARG;
+  for (uint32_t k = 0; k < n_l; ++k)
+    if (l_off[k + 1] < l_off[k]) return ORC_ERR_ARG;
+  for (uint32_t a = 0; n_l && a < l_off[n_l]; ++a)
+    if ((l[a].x & ~qmask) || (l[a].z & ~qmask)) return ORC_ERR_ARG;
+  for (uint64_t i = 0; i < n0; ++i) {
+    if (keys[i] & ~kmask) return ORC_ERR_ARG;
+    if (i && keys[i] <= keys[i - 1]) return ORC_ERR_ARG;
+    if (re[i] == 0 && im[i] == 0) return ORC_ERR_ARG;
+  }
+  orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
+  if (!c) return ORC_ERR_NOMEM;
+  c->n = n_qubits;
+  c->R = n_replicas;
+  c->seed = seed;
+  c->dt = dt;
+  c->n_h = n_h;
+  c->n_l = n_l;
+  int rc = compile_terms(c, h, l_off, l);
+  if (rc) {
+    orc_destroy(c);
+    return rc;
+  }
+  c->st = (store_t*)calloc(n_replicas, sizeof(store_t));
+  c->shift = (double*)calloc(n_replicas, sizeof(double));
+  if (!c->st || !c->shift) {
+    orc_destroy(c);
+    return ORC_ERR_NOMEM;
+  }
+  for (uint32_t r = 0; r < n_replicas; ++r) {
+    rc = orc_import(c, r, keys, re, im, n0, 0);
+    if (rc) {
+      orc_destroy(c);
+      return rc;
+    }
+  }
+  *out = c;
+  return ORC_OK;
+}
+
+static void store_free(store_t* s) {
+  free(s->key);
+  free(s->re);
+  free(s->im);
+  s->key = NULL;
+  s->re = s->im = NULL;
+  s->n = 0;
+}
+
+void orc_destroy(orc_ctx* c) {
+  if (!c) return;
+  if (c->st)
+    for (uint32_t r = 0; r < c->R; ++r) store_free(&c->st[r]);
+  free(c->st);
+  free(c->shift);
+  free(c->terms);
+  free(c);
+}
+
+uint32_t orc_n_terms(const orc_ctx* c) { return c->n_terms; }
+
+int orc_get_terms(const orc_ctx* c, uint64_t* xmask, uint64_t* zmask, double* kre, double* kim,
+                  uint32_t* kind, uint32_t* index) {
+  for (uint32_t t = 0; t < c->n_terms; ++t) {
+    xmask[t] = c->terms[t].xmask;
+    zmask[t] = c->terms[t].zmask;
+    kre[t] = c->terms[t].kre;
+    kim[t] = c->terms[t].kim;
+    kind[t] = c->terms[t].kind;
+    index[t] = c->terms[t].index;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Per-step coefficient table: quantize every source term to Q32, merge, group, check bound.  */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t xmask, zmask;
+  int64_t qre, qim;
+} qterm_t;
+
+typedef struct {
+  uint32_t n_groups;   /* including the diagonal group 0 */
+  uint64_t* gx;        /* [n_groups] */
+  uint32_t* gs;        /* [n_groups + 1] */
+  uint32_t n_terms;
+  qterm_t* t;          /* [n_terms], grouped */
+} table_t;
+
+static int cmp_qterm(const void* a, const void* b) {
+  const qterm_t* x = (const qterm_t*)a;
+  const qterm_t* y = (const qterm_t*)b;
+  if (x->xmask != y->xmask) return x->xmask < y->xmask ? -1 : 1;
+  if (x->zmask != y->zmask) return x->zmask < y->zmask ? -1 : 1;
+  return 0;
+}
+
+static void table_free(table_t* T) {
+  free(T->gx);
+  free(T->gs);
+  free(T->t);
+  memset(T, 0, sizeof(*T));
+}
+
+/* Q32 value of dt * w * kappa0 for one component: the product w * kappa0 first, then dt, then
+ * an exact scaling by 2^32 and round-half-even to an integer. */
+static int q32(double dt, double w, double k, int64_t* out) {
+  double v = ldexp(dt * (w * k), 32);
+  if (!isfinite(v) || fabs(v) >= 4611686018427387904.0 /* 2^62 */) return ORC_ERR_DT;
+  *out = (int64_t)llrint(v);
+  return ORC_OK;
+}
+
+static int build_table(const orc_ctx* c, const double* s, const double* gamma, table_t* T) {
+  memset(T, 0, sizeof(*T));
+  qterm_t* q = (qterm_t*)malloc((c->n_terms ? c->n_terms : 1) * sizeof(qterm_t));
+  if (!q) return ORC_ERR_NOMEM;
+  for (uint32_t i = 0; i < c->n_terms; ++i) {
+    const term_t* tm = &c->terms[i];
+    double w = tm->kind == 0 ? s[tm->index] : gamma[tm->index];
+    if (!isfinite(w)) {
+      free(q);
+      return ORC_ERR_ARG;
+    }
+    q[i].xmask = tm->xmask;
+    q[i].zmask = tm->zmask;
+    if (q32(c->dt, w, tm->kre, &q[i].qre) || q32(c->dt, w, tm->kim, &q[i].qim)) {
+      free(q);
+      return ORC_ERR_DT;
+    }
+  }
+  /* Merge terms with equal (xmask, zmask) by exact integer addition. */
+  qsort(q, c->n_terms, sizeof(qterm_t), cmp_qterm);
+  uint32_t m = 0;
+  for (uint32_t i = 0; i < c->n_terms;) {
+    qterm_t acc = q[i];
+    uint32_t j = i + 1;
+    while (j < c->n_terms && q[j].xmask == acc.xmask && q[j].zmask == acc.zmask) {
+      acc.qre += q[j].qre;
+      acc.qim += q[j].qim;
+      ++j;
+    }
+    if (acc.qre != 0 || acc.qim != 0) q[m++] = acc;
+    i = j;
+  }
+  /* Groups by xmask; group 0 is the diagonal one and always exists. */
+  T->t = q;
+  T->n_terms = m;
+  T->gx = (uint64_t*)malloc((m + 1) * sizeof(uint64_t));
+  T->gs = (uint32_t*)malloc((m + 2) * sizeof(uint32_t));
+  if (!T->gx || !T->gs) {
+    table_free(T);
+    return ORC_ERR_NOMEM;
+  }
+  uint32_t g = 0;
+  T->gx[0] = 0;
+  T->gs[0] = 0;
+  g = 1;
+  for (uint32_t i = 0; i < m; ++i) {
+    if (q[i].xmask == 0) continue;
+    if (i == 0 || q[i].xmask != q[i - 1].xmask) {
+      T->gs[g] = i;
+      T->gx[g] = q[i].xmask;
+      ++g;
+    }
+  }
+  T->n_groups = g;
+  T->gs[g] = m;
+  /* Bound: per group sum of |q_re| + |q_im| < 2^31, so |c_re| + |c_im| < 2^31 for any key. */
+  for (uint32_t gi = 0; gi < g; ++gi) {
+    uint64_t sum = 0;
+    for (uint32_t i = T->gs[gi]; i < T->gs[gi + 1]; ++i)
+      sum += (uint64_t)llabs(q[i].qre) + (uint64_t)llabs(q[i].qim);
+    if (sum >= (1ull << 31)) {
+      table_free(T);
+      return ORC_ERR_DT;
+    }
+  }
+  return ORC_OK;
+}
+
+int orc_table(const orc_ctx* c, const double* s, const double* gamma,
+              uint32_t cap_groups, uint32_t cap_terms, uint32_t* n_groups, uint64_t* gxmask,
+              uint32_t* gstart, uint32_t* n_terms, uint64_t* tzmask, int64_t* tq) {
+  table_t T;
+  int rc = build_table(c, s, gamma, &T);
+  if (rc) return rc;
+  *n_groups = T.n_groups;
+  *n_terms = T.n_terms;
+  if (T.n_groups > cap_groups || T.n_terms > cap_terms) {
+    table_free(&T);
+    return ORC_ERR_ARG;
+  }
+  for (uint32_t g = 0; g < T.n_groups; ++g) {
+    gxmask[g] = T.gx[g];
+    gstart[g] = T.gs[g];
+  }
+  gstart[T.n_groups] = T.gs[T.n_groups];
+  for (uint32_t i = 0; i < T.n_terms; ++i) {
+    tzmask[i] = T.t[i].zmask;
+    tq[2 * i] = T.t[i].qre;
+    tq[2 * i + 1] = T.t[i].qim;
+  }
+  table_free(&T);
+  return ORC_OK;
+}
+
+/* Coefficient of group g at `key`: c = sum over the group's terms of (-1)^parity(zmask & key) q. */
+static void group_coeff(const table_t* T, uint32_t g, uint64_t key, int64_t* cre, int64_t* cim) {
+  int64_t re = 0, im = 0;
+  for (uint32_t i = T->gs[g]; i < T->gs[g + 1]; ++i) {
+    int neg = parity64(T->t[i].zmask & key);
+    re += neg ? -T->t[i].qre : T->t[i].qre;
+    im += neg ? -T->t[i].qim : T->t[i].qim;
+  }
+  *cre = re;
+  *cim = im;
+}
+
+typedef struct {
+  uint64_t key;
+  double re, im;
+} fent_t;
+
+static int cmp_fent(const void* a, const void* b) {
+  uint64_t x = ((const fent_t*)a)->key, y = ((const fent_t*)b)->key;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int orc_column_fp(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
+                  uint32_t cap, uint32_t* n, uint64_t* tkey, double* val) {
+  fent_t* e = (fent_t*)malloc((c->n_terms ? c->n_terms : 1) * sizeof(fent_t));
+  if (!e) return ORC_ERR_NOMEM;
+  for (uint32_t i = 0; i < c->n_terms; ++i) {
+    const term_t* tm = &c->terms[i];
+    double w = tm->kind == 0 ? s[tm->index] : gamma[tm->index];
+    double sg = parity64(tm->zmask & key) ? -1.0 : 1.0;
+    e[i].key = key ^ tm->xmask;
+    e[i].re = sg * c->dt * (w * tm->kre);
+    e[i].im = sg * c->dt * (w * tm->kim);
+  }
+  qsort(e, c->n_terms, sizeof(fent_t), cmp_fent);
+  uint32_t m = 0;
+  for (uint32_t i = 0; i < c->n_terms;) {
+    fent_t acc = e[i];
+    uint32_t j = i + 1;
+    while (j < c->n_terms && e[j].key == acc.key) {
+      acc.re += e[j].re;
+      acc.im += e[j].im;
+      ++j;
+    }
+    if (m < cap) {
+      tkey[m] = acc.key;
+      val[2 * m] = acc.re;
+      val[2 * m + 1] = acc.im;
+    }
+    ++m;
+    i = j;
+  }
+  free(e);
+  *n = m;
+  return m > cap ? ORC_ERR_ARG : ORC_OK;
+}
+
+int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
+                 uint32_t cap, uint32_t* n, uint64_t* tkey, int64_t* val) {
+  table_t T;
+  int rc = build_table(c, s, gamma, &T);
+  if (rc) return rc;
+  uint32_t m = 0;
+  for (uint32_t g = 0; g < T.n_groups; ++g) {
+    int64_t cre, cim;
+    group_coeff(&T, g, key, &cre, &cim);
+    if (cre == 0 && cim == 0) continue;
+    if (m < cap) {
+      tkey[m] = key ^ T.gx[g];
+      val[2 * m] = cre;
+      val[2 * m + 1] = cim;
+    }
+    ++m;
+  }
+  table_free(&T);
+  *n = m;
+  return m > cap ? ORC_ERR_ARG : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* One Euler step of the spawn / death / annihilation dynamics for one replica.                */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t key;
+  int64_t re, im;
+} rec_t;
+
+static int cmp_rec(const void* a, const void* b) {
+  uint64_t x = ((const rec_t*)a)->key, y = ((const rec_t*)b)->key;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int step_replica(const orc_ctx* c, uint32_t r, const table_t* T, int64_t qs_re,
+                        store_t* out) {
+  const store_t* in = &c->st[r];
+  const uint32_t G = T->n_groups;
+  uint64_t cap = in->n * (uint64_t)G + 1;
+  rec_t* rec = (rec_t*)malloc(cap * sizeof(rec_t));
+  int64_t* xs = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
+  int64_t* ns = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
+  if (!rec || !xs || !ns) {
+    free(rec);
+    free(xs);
+    free(ns);
+    return ORC_ERR_NOMEM;
+  }
+  const uint32_t pkey[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+  uint64_t nr = 0;
+  for (uint64_t p = 0; p < in->n; ++p) {
+    const uint64_t key = in->key[p];
+    const int64_t a = in->re[p], b = in->im[p];
+    /* Philox counter: the walker's key, the step, and (replica << 8) | stream, stream 0. */
+    const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step, (r << 8) | 0u};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, pkey, w);
+
+    /* Death / cloning from the diagonal entry of the column (reading R4), applied to N(t). */
+    int64_t dre, dim;
+    group_coeff(T, 0, key, &dre, &dim);
+    dre += qs_re;
+    int64_t x2[2] = {a * dre - b * dim, a * dim + b * dre};
+    int64_t n2[2];
+    orc_comb(2, x2, w[1], n2);
+    rec[nr++] = (rec_t){key, a + n2[0], b + n2[1]};
+
+    /* Spawn into every off-diagonal target of the column, Re and Im channel of each, in group
+     * (xmask ascending) order, with one comb over the whole list (reading R3). */
+    for (uint32_t g = 1; g < G; ++g) {
+      int64_t cre, cim;
+      group_coeff(T, g, key, &cre, &cim);
+      xs[2 * (g - 1)] = a * cre - b * cim;
+      xs[2 * (g - 1) + 1] = a * cim + b * cre;
+    }
+    if (G > 1) orc_comb(2 * (G - 1), xs, w[0], ns);
+    for (uint32_t g = 1; g < G; ++g) {
+      int64_t cr = ns[2 * (g - 1)], ci = ns[2 * (g - 1) + 1];
+      if (cr != 0 || ci != 0) rec[nr++] = (rec_t){key ^ T->gx[g], cr, ci};
+    }
+  }
+  free(xs);
+  free(ns);
+
+  /* Annihilation (End Matter): merge children with the surviving parents, sum by location,
+   * opposite signs cancel, empty locations disappear. */
+  qsort(rec, nr, sizeof(rec_t), cmp_rec);
+  uint64_t m = 0;
+  for (uint64_t i = 0; i < nr;) {
+    rec_t acc = rec[i];
+    uint64_t j = i + 1;
+    while (j < nr && rec[j].key == acc.key) {
+      acc.re += rec[j].re;
+      acc.im += rec[j].im;
+      ++j;
+    }
+    if (acc.re < INT32_MIN || acc.re > INT32_MAX || acc.im < INT32_MIN || acc.im > INT32_MAX) {
+      free(rec);
+      return ORC_ERR_COUNT_OVERFLOW;
+    }
+    if (acc.re != 0 || acc.im != 0) rec[m++] = acc;
+    i = j;
+  }
+  out->n = m;
+  out->key = (uint64_t*)malloc((m ? m : 1) * sizeof(uint64_t));
+  out->re = (int32_t*)malloc((m ? m : 1) * sizeof(int32_t));
+  out->im = (int32_t*)malloc((m ? m : 1) * sizeof(int32_t));
+  if (!out->key || !out->re || !out->im) {
+    store_free(out);
+    free(rec);
+    return ORC_ERR_NOMEM;
+  }
+  for (uint64_t i = 0; i < m; ++i) {
+    out->key[i] = rec[i].key;
+    out->re[i] = (int32_t)rec[i].re;
+    out->im[i] = (int32_t)rec[i].im;
+  }
+  free(rec);
+  return ORC_OK;
+}
+
+static int one_step(orc_ctx* c, const double* s, const double* gamma, int threads) {
+  table_t T;
+  int rc = build_table(c, s, gamma, &T);
+  if (rc) return rc;
+  store_t* nxt = (store_t*)calloc(c->R, sizeof(store_t));
+  int* rcs = (int*)calloc(c->R, sizeof(int));
+  if (!nxt || !rcs) {
+    free(nxt);
+    free(rcs);
+    table_free(&T);
+    return ORC_ERR_NOMEM;
+  }
+  /* Death-group bound including the shift. */
+  uint64_t dsum = 0;
+  for (uint32_t i = T.gs[0]; i < T.gs[1]; ++i)
+    dsum += (uint64_t)llabs(T.t[i].qre) + (uint64_t)llabs(T.t[i].qim);
+  int64_t* qs = (int64_t*)calloc(c->R, sizeof(int64_t));
+  for (uint32_t r = 0; r < c->R && qs; ++r) {
+    if (q32(c->dt, 1.0, c->shift[r], &qs[r]) || dsum + (uint64_t)llabs(qs[r]) >= (1ull << 31))
+      rc = ORC_ERR_DT;
+  }
+  if (!qs) rc = ORC_ERR_NOMEM;
+  if (rc == ORC_OK) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads > 0 ? threads : 1)
+#endif
+    for (uint32_t r = 0; r < c->R; ++r) rcs[r] = step_replica(c, r, &T, qs[r], &nxt[r]);
+    for (uint32_t r = 0; r < c->R; ++r)
+      if (rcs[r] && !rc) rc = rcs[r];
+  }
+  (void)threads;
+  if (rc == ORC_OK) {
+    for (uint32_t r = 0; r < c->R; ++r) {
+      store_free(&c->st[r]);
+      c->st[r] = nxt[r];
+    }
+    c->step += 1;
+  } else {
+    for (uint32_t r = 0; r < c->R; ++r) store_free(&nxt[r]);
+  }
+  free(qs);
+  free(nxt);
+  free(rcs);
+  table_free(&T);
+  return rc;
+}
+
+int orc_step(orc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) {
+  for (uint32_t k = 0; k < nsteps; ++k) {
+    int rc = one_step(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, 1);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+int orc_step_threads(orc_ctx* c, uint32_t nsteps, const double* s, const double* gamma,
+                     int threads, int* threads_used) {
+  int used = 1;
+#ifdef _OPENMP
+  if (threads <= 0) threads = omp_get_max_threads();
+  used = threads < (int)c->R ? threads : (int)c->R;
+#else
+  threads = 1;
+#endif
+  if (threads_used) *threads_used = used;
+  for (uint32_t k = 0; k < nsteps; ++k) {
+    int rc = one_step(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, used);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+/* Ideal instantaneous Pauli pulse: P |i><j| P^dagger = (-1)^{popc(z&i) + popc(z&j)} |i^x><j^x|. */
+int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z) {
+  const uint32_t n = c->n;
+  const uint64_t qmask = n == 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
+  if ((x & ~qmask) || (z & ~qmask)) return ORC_ERR_ARG;
+  for (uint32_t r = 0; r < c->R; ++r) {
+    store_t* st = &c->st[r];
+    rec_t* rec = (rec_t*)malloc((st->n ? st->n : 1) * sizeof(rec_t));
+    if (!rec) return ORC_ERR_NOMEM;
+    for (uint64_t p = 0; p < st->n; ++p) {
+      uint64_t i = st->key[p] & qmask, j = st->key[p] >> n;
+      if (n == 32) j = st->key[p] >> 32;
+      int neg = (popc64(z & i) + popc64(z & j)) & 1;
+      uint64_t nk = ((j ^ x) << n) | (i ^ x);
+      rec[p] = (rec_t){nk, neg ? -(int64_t)st->re[p] : st->re[p],
+                       neg ? -(int64_t)st->im[p] : st->im[p]};
+    }
+    qsort(rec, st->n, sizeof(rec_t), cmp_rec);
+    for (uint64_t p = 0; p < st->n; ++p) {
+      if (rec[p].re > INT32_MAX || rec[p].im > INT32_MAX) {
+        free(rec);
+        return ORC_ERR_COUNT_OVERFLOW;
+      }
+    }
+    for (uint64_t p = 0; p < st->n; ++p) {
+      st->key[p] = rec[p].key;
+      st->re[p] = (int32_t)rec[p].re;
+      st->im[p] = (int32_t)rec[p].im;
+    }
+    free(rec);
+  }
+  return ORC_OK;
+}
+
+int orc_set_shift(orc_ctx* c, uint32_t replica, double shift) {
+  if (replica >= c->R || !isfinite(shift)) return ORC_ERR_ARG;
+  c->shift[replica] = shift;
+  return ORC_OK;
+}
+
+uint32_t orc_get_step(const orc_ctx* c) { return c->step; }
+
+uint64_t orc_size(const orc_ctx* c, uint32_t replica) {
+  return replica < c->R ? c->st[replica].n : 0;
+}
+
+int orc_export(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+               uint64_t cap, uint64_t* n) {
+  if (replica >= c->R) return ORC_ERR_ARG;
+  const store_t* st = &c->st[replica];
+  *n = st->n;
+  if (st->n > cap) return ORC_ERR_ARG;
+  memcpy(keys, st->key, st->n * sizeof(uint64_t));
+  memcpy(re, st->re, st->n * sizeof(int32_t));
+  memcpy(im, st->im, st->n * sizeof(int32_t));
+  return ORC_OK;
+}
+
+int orc_import(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+               const int32_t* im, uint64_t n, uint32_t step) {
+  if (replica >= c->R) return ORC_ERR_ARG;
+  const uint64_t kmask = c->n == 32 ? ~0ull : ((1ull << (2 * c->n)) - 1);
+  for (uint64_t i = 0; i < n; ++i) {
+    if (keys[i] & ~kmask) return ORC_ERR_ARG;
+    if (i && keys[i] <= keys[i - 1]) return ORC_ERR_ARG;
+    if (re[i] == 0 && im[i] == 0) return ORC_ERR_ARG;
+  }
+  store_t* st = &c->st[replica];
+  store_free(st);
+  st->key = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  st->re = (int32_t*)malloc((n ? n : 1) * sizeof(int32_t));
+  st->im = (int32_t*)malloc((n ? n : 1) * sizeof(int32_t));
+  if (!st->key || !st->re || !st->im) return ORC_ERR_NOMEM;
+  memcpy(st->key, keys, n * sizeof(uint64_t));
+  memcpy(st->re, re, n * sizeof(int32_t));
+  memcpy(st->im, im, n * sizeof(int32_t));
+  st->n = n;
+  c->step = step;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Estimator numerators: eq. (3) normalization, trace (replica-aggregation paragraph),        */
+/* sign angle and anti-Hermiticity (End Matter), all as exact integers.                        */
+/* ------------------------------------------------------------------------------------------ */
+static int64_t find_key(const store_t* st, uint64_t key, int64_t* re, int64_t* im) {
+  uint64_t lo = 0, hi = st->n;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (st->key[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo < st->n && st->key[lo] == key) {
+    *re = st->re[lo];
+    *im = st->im[lo];
+    return 1;
+  }
+  *re = 0;
+  *im = 0;
+  return 0;
+}
+
+/* v^2 for |v| < 2^32, exact in uint64. */
+static uint64_t sq_abs(int64_t v) {
+  uint64_t m = v < 0 ? (uint64_t)(-v) : (uint64_t)v;
+  return m * m;
+}
+
+static void add128(uint64_t* lo, uint64_t* hi, uint64_t v) {
+  uint64_t o = *lo;
+  *lo = o + v;
+  if (*lo < o) *hi += 1;
+}
+
+int orc_observe(const orc_ctx* c, uint32_t replica, uint32_t n_pauli, const uint64_t* px,
+                const uint64_t* pz, uint32_t n_lookup, const uint64_t* lk, uint64_t* n_occ,
+                uint64_t* n_tot, int64_t* ndiag, int64_t* pauli, int64_t* lookup,
+                uint64_t* eps2) {
+  if (replica >= c->R) return ORC_ERR_ARG;
+  const store_t* st = &c->st[replica];
+  const uint32_t n = c->n;
+  const uint64_t qmask = n == 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
+  uint64_t tot = 0;
+  int64_t dre = 0, dim = 0;
+  for (uint32_t k = 0; k < n_pauli; ++k) pauli[2 * k] = pauli[2 * k + 1] = 0;
+  uint64_t elo = 0, ehi = 0;
+  for (uint64_t p = 0; p < st->n; ++p) {
+    const uint64_t key = st->key[p];
+    const uint64_t i = key & qmask, j = n == 32 ? key >> 32 : key >> n;
+    const int64_t a = st->re[p], b = st->im[p];
+    tot += (uint64_t)(a < 0 ? -a : a) + (uint64_t)(b < 0 ? -b : b);
+    if (i == j) {
+      dre += a;
+      dim += b;
+    }
+    /* Tr(P rho) with P = X^x Z^z: sum_i (-1)^{popc(z & i)} rho_{i, i^x}. */
+    for (uint32_t k = 0; k < n_pauli; ++k) {
+      if ((i ^ j) != px[k]) continue;
+      int neg = popc64(pz[k] & i) & 1;
+      pauli[2 * k] += neg ? -a : a;
+      pauli[2 * k + 1] += neg ? -b : b;
+    }
+    /* |N_ij - conj(N_ji)|^2, and |N_ij|^2 for the (j,i) element when that one is empty. */
+    const uint64_t kt = (i << n) | j;
+    int64_t c2, d2;
+    int64_t found = find_key(st, kt, &c2, &d2);
+    add128(&elo, &ehi, sq_abs(a - c2));
+    add128(&elo, &ehi, sq_abs(b + d2));
+    if (!found) {
+      add128(&elo, &ehi, sq_abs(a));
+      add128(&elo, &ehi, sq_abs(b));
+    }
+  }
+  for (uint32_t k = 0; k < n_lookup; ++k) find_key(st, lk[k], &lookup[2 * k], &lookup[2 * k + 1]);
+  *n_occ = st->n;
+  *n_tot = tot;
+  ndiag[0] = dre;
+  ndiag[1] = dim;
+  eps2[0] = elo;
+  eps2[1] = ehi;
+  return ORC_OK;
+}

@@ -1,0 +1,115 @@
+/*
+ * qmc_oracle.h -- CPU oracle for one population-dynamics time step of the real-time,
+ * sign-problem-suppressed QMC of Shen & Lidar, arXiv:2502.18929.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the package smoke check and the CPU-baseline leg of
+ * bench.py may load this library.  It shares no code with the HIP path under
+ * paper_2502_18929_amd/csrc: it has its own Philox, its own Liouvillian term compiler, its own
+ * fixed-point quantizer, its own step and its own estimators, all written to be read against
+ * the paper by eye, with no blocking or fusion.
+ *
+ * Conventions (the same contract the HIP library implements independently):
+ *  - Qubit q of a basis state |i> is bit q of i.  The density-matrix element |i><j| (ket i,
+ *    bra j) of an n-qubit system lives at key (j << n) | i: the column-stacking vec() of the
+ *    paper's QMC-algorithm paragraph, eq. (2).
+ *  - A Pauli monomial (x, z, c) is the operator c * X^x Z^z with
+ *    X^x Z^z |i> = (-1)^popcount(z & i) |i ^ x>.
+ *  - Walker populations are Gaussian integers re + i*im (signs {+-1, +-i}, End Matter on
+ *    spawn and annihilation).
+ */
+#ifndef QMC_ORACLE_H
+#define QMC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { uint64_t x, z; double re, im; } orc_monomial;
+
+typedef struct orc_ctx orc_ctx;
+
+enum {
+  ORC_OK = 0,
+  ORC_ERR_ARG = -1,
+  ORC_ERR_DT = -2,             /* a column group breaks the fixed-point bound (see orc_quantize) */
+  ORC_ERR_COUNT_OVERFLOW = -5, /* an annihilated population left the int32 range */
+  ORC_ERR_NOMEM = -7
+};
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): one block of four 32-bit words. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Systematic ("comb") stochastic rounding of m signed Q32 values with one 32-bit uniform U:
+ * out[k] = sign(x[k]) * floor((r_k + |x[k]|) / 2^32), r_0 = U, r_{k+1} = (r_k + |x[k]|) mod 2^32.
+ * Requires |x[k]| < 2^63. */
+void orc_comb(uint32_t m, const int64_t* x, uint32_t U, int64_t* out);
+
+/* Create a context: n qubits, R replicas, Philox seed, time step dt, the model of eq. (1)
+ * (H(t) = sum_m s_m(t) h_m, L_k = sum_{a in [l_off[k], l_off[k+1])} l[a] with rates gamma_k(t))
+ * and the initial population vector N(0) (same integer records for every replica, keys sorted
+ * ascending and unique, no (0,0) entries). */
+int orc_create(uint32_t n_qubits, uint32_t n_replicas, uint64_t seed, double dt,
+               uint32_t n_h, const orc_monomial* h,
+               uint32_t n_l, const uint32_t* l_off, const orc_monomial* l,
+               const uint64_t* keys, const int32_t* re, const int32_t* im, uint64_t n0,
+               orc_ctx** out);
+void orc_destroy(orc_ctx* c);
+
+/* Number of compiled source terms, and the terms themselves (unquantized kappa0, before the
+ * time-dependent weight; kind 0 = H monomial `index`, kind 1 = Lindblad operator `index`). */
+uint32_t orc_n_terms(const orc_ctx* c);
+int orc_get_terms(const orc_ctx* c, uint64_t* xmask, uint64_t* zmask, double* kre, double* kim,
+                  uint32_t* kind, uint32_t* index);
+
+/* The quantized, merged, grouped coefficient table for one step with weights s[n_h], gamma[n_l].
+ * Groups are ordered by xmask ascending; group 0 is always the diagonal (xmask 0, possibly empty).
+ * gstart has n_groups+1 entries. Returns ORC_ERR_DT if the bound fails. */
+int orc_table(const orc_ctx* c, const double* s, const double* gamma,
+              uint32_t cap_groups, uint32_t cap_terms,
+              uint32_t* n_groups, uint64_t* gxmask, uint32_t* gstart,
+              uint32_t* n_terms, uint64_t* tzmask, int64_t* tq /* [n][2] */);
+
+/* Column `key` of dt*L(t) (unquantized, FP64), merged by target key, targets ascending. */
+int orc_column_fp(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
+                  uint32_t cap, uint32_t* n, uint64_t* tkey, double* val /* [n][2] */);
+/* Column `key` of the quantized table (Q32 integers), merged by target key, targets ascending. */
+int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
+                 uint32_t cap, uint32_t* n, uint64_t* tkey, int64_t* val /* [n][2] */);
+
+/* Advance every replica by nsteps Euler steps; s is [nsteps][n_h], gamma [nsteps][n_l]. */
+int orc_step(orc_ctx* c, uint32_t nsteps, const double* s, const double* gamma);
+/* Apply the ideal instantaneous Pauli conjugation rho -> P rho P^dagger, P = X^x Z^z. */
+int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z);
+/* Constant diagonal shift S added to the death coefficient (0 = none, the paper's setting). */
+int orc_set_shift(orc_ctx* c, uint32_t replica, double shift);
+
+uint32_t orc_get_step(const orc_ctx* c);
+uint64_t orc_size(const orc_ctx* c, uint32_t replica);
+int orc_export(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+               uint64_t cap, uint64_t* n);
+int orc_import(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+               const int32_t* im, uint64_t n, uint32_t step);
+
+/* Estimator numerators for one replica (exact integers):
+ *  n_occ, n_tot = sum(|re|+|im|), ndiag = sum over i==j of N (re, im),
+ *  pauli[k] = sum over keys with ket^bra == px[k] of (-1)^popcount(pz[k] & ket) * N (re, im),
+ *  lookup[k] = N at key lk[k] (0 if absent),
+ *  eps2 = sum over all (i,j) of |N_ij - conj(N_ji)|^2 as a 128-bit (lo, hi) pair. */
+int orc_observe(const orc_ctx* c, uint32_t replica,
+                uint32_t n_pauli, const uint64_t* px, const uint64_t* pz,
+                uint32_t n_lookup, const uint64_t* lk,
+                uint64_t* n_occ, uint64_t* n_tot, int64_t* ndiag /* [2] */,
+                int64_t* pauli /* [n_pauli][2] */, int64_t* lookup /* [n_lookup][2] */,
+                uint64_t* eps2 /* [2] lo, hi */);
+
+/* Wall-clock helper for the CPU baseline: runs orc_step with OpenMP across replicas when
+ * threads > 1 and reports the threads used. */
+int orc_step_threads(orc_ctx* c, uint32_t nsteps, const double* s, const double* gamma,
+                     int threads, int* threads_used);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,396 @@
+"""Pins of the CPU oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle (``oracle/qmc_oracle.c`` via ctypes, and ``oracle/dense.py``) against
+something other than itself: published known-answer vectors, the textbook vectorization identity
+of eq. (2), closed forms, exhaustive enumeration, and the unbiasedness identity of the End
+Matter (E[spawn] = dt L N) as a statistical test.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from paper_2502_18929_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---- Philox4x32-10: published known answers --------------------------------------------------
+
+def test_philox_known_answers(orc):
+    n = 0
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(t, 16) for t in line.split()]
+        out = orc.philox4x32_10(w[:4], w[4:6])
+        assert [int(v) for v in out] == w[6:]
+        n += 1
+    assert n == 3
+
+
+def test_philox_uniformity(orc):
+    # chi^2 on the top byte of 4 * 20000 words from consecutive counters.
+    counts = np.zeros(256)
+    for c in range(20000):
+        out = orc.philox4x32_10([c, 0, 7, 3], [1, 0])
+        for v in out:
+            counts[int(v) >> 24] += 1
+    exp = counts.sum() / 256
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert chi2 < 255 + 5 * math.sqrt(2 * 255)
+
+
+# ---- comb rounding: exact expectation by enumeration over U --------------------------------
+
+def _comb_exact_sum(orc, x):
+    """sum_{U=0}^{2^32-1} out_k(U), evaluated exactly on the pieces where out is constant."""
+    mags = [abs(int(v)) for v in x]
+    prefix = np.cumsum([0] + mags)
+    # out_k changes only where U + prefix_j crosses a multiple of 2^32.
+    bps = {0, 1 << 32}
+    for p in prefix:
+        b = (-int(p)) % (1 << 32)
+        bps.add(b)
+    bps = sorted(bps)
+    tot = np.zeros(len(x), dtype=object)
+    for a, b in zip(bps[:-1], bps[1:]):
+        if b <= a:
+            continue
+        out = orc.comb(x, a)
+        # constant on [a, b): check the right end too
+        out2 = orc.comb(x, b - 1)
+        assert np.array_equal(out, out2)
+        tot += np.array([int(v) for v in out], dtype=object) * (b - a)
+    return tot
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_comb_exact_expectation(orc, seed):
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(1, 9))
+    scale = [1 << 20, 1 << 31, 1 << 40, 1 << 60][seed % 4]
+    x = [int(v) for v in rng.integers(-scale, scale, size=m)]
+    if seed == 5:
+        x[0] = 0
+    tot = _comb_exact_sum(orc, x)
+    for k in range(m):
+        assert tot[k] == x[k]   # sum over all 2^32 values of U equals x_k: E[out_k] = x_k / 2^32
+    for U in rng.integers(0, 1 << 32, size=50):
+        out = orc.comb(x, int(U))
+        for k in range(m):
+            lo = abs(x[k]) >> 32
+            assert abs(int(out[k])) in (lo, lo + 1)
+            assert int(out[k]) == 0 or np.sign(out[k]) == np.sign(x[k])
+
+
+# ---- Liouvillian term compiler vs the dense eq. (2) ------------------------------------------
+
+def _dense_L(n, h, lops, s, gamma):
+    return dense.DenseModel(n, h, lops).L(s, gamma)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (2, 2), (3, 3)])
+def test_columns_match_dense_liouvillian(orc, n, seed):
+    rng = np.random.default_rng(seed)
+    h, lops = W.random_model(n, rng, n_h=5, n_l=3, max_l_terms=3)
+    dt = 0.01
+    s = rng.normal(size=len(h))
+    gamma = rng.normal(size=len(lops))     # negative rates included (non-Markovian)
+    o = orc.Oracle(n, 1, 1, dt, h, lops, [0], [1], [0])
+    Ld = _dense_L(n, h, lops, s, gamma)
+    D2 = 1 << (2 * n)
+    Lc = np.zeros((D2, D2), dtype=complex)
+    for key in range(D2):
+        tk, v = o.column_fp(s, gamma, key)
+        Lc[tk.astype(np.int64), key] = v
+    assert np.allclose(Lc, dt * Ld, atol=1e-13, rtol=0)
+
+
+@pytest.mark.parametrize("n,seed", [(2, 4), (3, 5)])
+def test_quantized_columns_within_rounding(orc, n, seed):
+    rng = np.random.default_rng(seed)
+    h, lops = W.random_model(n, rng, n_h=4, n_l=2)
+    dt = 0.005
+    s = rng.normal(size=len(h))
+    gamma = np.abs(rng.normal(size=len(lops)))
+    o = orc.Oracle(n, 1, 1, dt, h, lops, [0], [1], [0])
+    nterms = len(o.terms()["xmask"])
+    Ld = dt * _dense_L(n, h, lops, s, gamma) * 2.0 ** 32
+    for key in range(1 << (2 * n)):
+        tk, v = o.column_q(s, gamma, key)
+        col = np.zeros(1 << (2 * n), dtype=complex)
+        col[tk.astype(np.int64)] = v[:, 0] + 1j * v[:, 1]
+        err = np.abs(col - Ld[:, key])
+        assert err.max() <= 0.5 * nterms + 1e-3
+
+
+def test_gate_hamiltonians_are_the_gates():
+    """Over unit time, (pi/2)(X+Z)/sqrt2 gives -i*Hadamard and (pi/4)(I-Z_c-X_t+Z_cX_t) gives CNOT
+    (up to a global phase), checked on the dense operators the workloads use."""
+    import scipy.linalg as sla
+    w = W.ghz(n=2)
+    Hh = dense.operator(2, w.h[:2])
+    U = sla.expm(-1j * Hh)
+    had = np.kron(np.eye(2), np.array([[1, 1], [1, -1]]) / np.sqrt(2))   # qubit 0 = bit 0
+    assert np.allclose(U, -1j * had, atol=1e-12)
+    Hc = dense.operator(2, w.h[2:5]) + np.pi / 4 * np.eye(4)
+    U = sla.expm(-1j * Hc)
+    cnot = np.zeros((4, 4))
+    for i in range(4):
+        j = i ^ 2 if i & 1 else i          # control bit 0, target bit 1
+        cnot[j, i] = 1
+    assert np.allclose(U, cnot, atol=1e-12)
+
+
+def test_sigma_minus_monomials():
+    sm = dense.operator(1, [(1, 0, 0.5), (1, 1, -0.5)])
+    assert np.allclose(sm, [[0, 1], [0, 0]])          # |0><1|, damping towards |0>
+    # in the X frame the workload uses H sigma^- H
+    had = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+    w = W.dd(n=2, nsteps=10)
+    smx = dense.operator(2, w.lops[2])
+    assert np.allclose(smx, np.kron(np.eye(2), had @ sm @ had))
+
+
+# ---- dense reference pinned to closed forms ------------------------------------------------
+
+def test_dense_closed_forms():
+    n, g = 1, 0.3
+    # amplitude damping: rho_11(t) = e^{-g t} rho_11(0), coherence e^{-g t / 2}
+    m = dense.DenseModel(n, [], [[(1, 0, 0.5), (1, 1, -0.5)]])
+    rho = np.array([[0.5, 0.5], [0.5, 0.5]], dtype=complex)
+    t, steps = 2.0, 400
+    v = dense.rk4(m, lambda t: [], lambda t: [g], t / steps, steps, dense.vec(rho))
+    r = dense.unvec(v, n)
+    assert abs(r[1, 1] - 0.5 * math.exp(-g * t)) < 1e-9
+    assert abs(r[0, 1] - 0.5 * math.exp(-g * t / 2)) < 1e-9
+    assert abs(np.trace(r) - 1) < 1e-12
+    # dephasing L = Z with (1/2) gamma D[Z]: coherence decays as e^{-2 g t}
+    m = dense.DenseModel(n, [], [[(0, 1, 1.0)]])
+    v = dense.rk4(m, lambda t: [], lambda t: [g], t / steps, steps, dense.vec(rho))
+    r = dense.unvec(v, n)
+    assert abs(r[0, 1] - 0.5 * math.exp(-2 * g * t)) < 1e-9
+    # non-Markovian dephasing a cos(w t): coherence e^{-2 a sin(w t) / w}
+    a, w = 0.4, 0.5
+    v = dense.rk4(m, lambda t: [], lambda t: [a * math.cos(w * t)], t / steps, steps,
+                  dense.vec(rho))
+    r = dense.unvec(v, n)
+    assert abs(r[0, 1] - 0.5 * math.exp(-2 * a * math.sin(w * t) / w)) < 1e-9
+    # Rabi: H = (w/2) X from |0>: rho_11 = sin^2(w t / 2)
+    m = dense.DenseModel(n, [(1, 0, 0.5)], [])
+    rho0 = np.array([[1, 0], [0, 0]], dtype=complex)
+    v = dense.rk4(m, lambda t: [1.3], lambda t: [], t / steps, steps, dense.vec(rho0))
+    assert abs(dense.unvec(v, n)[1, 1] - math.sin(1.3 * t / 2) ** 2) < 1e-9
+
+
+def test_dense_trace_and_hermiticity_preservation():
+    rng = np.random.default_rng(11)
+    n = 2
+    h, lops = W.random_model(n, rng)
+    L = dense.DenseModel(n, h, lops).L(rng.normal(size=len(h)), rng.normal(size=len(lops)))
+    D = 1 << n
+    diag = [(i * D + i) for i in range(D)]
+    assert np.allclose(L[diag, :].sum(axis=0), 0, atol=1e-12)     # Tr[L rho] = 0
+    for ki in range(D * D):
+        i, j = ki % D, ki // D
+        for ko in range(D * D):
+            k, l = ko % D, ko // D
+            assert abs(L[ko, ki] - np.conj(L[k * D + l, i * D + j])) < 1e-12
+
+
+# ---- the step: unbiasedness (End Matter: E[children] = dt L N) --------------------------------
+
+def _q_matrix(o, n, s, gamma):
+    D2 = 1 << (2 * n)
+    M = np.zeros((D2, D2), dtype=object)
+    for key in range(D2):
+        tk, v = o.column_q(s, gamma, key)
+        for t, (a, b) in zip(tk, v):
+            M[int(t), key] = (int(a), int(b))
+    return M
+
+
+def test_one_step_unbiased(orc):
+    """Mean of many independent one-step samples vs the exact (I + dt L_q) N (z-test)."""
+    rng = np.random.default_rng(21)
+    n = 2
+    h, lops = W.random_model(n, rng, n_h=4, n_l=2)
+    s = rng.normal(size=len(h))
+    gamma = np.abs(rng.normal(size=len(lops)))
+    dt = 0.05
+    keys, re, im = W.random_records(n, rng, 6, scale=40)
+    R = 6000
+    o = orc.Oracle(n, R, 12345, dt, h, lops, keys, re, im)
+    o.step(s[None, :], gamma[None, :])
+    D2 = 1 << (2 * n)
+    samples = np.zeros((R, D2), dtype=complex)
+    for r in range(R):
+        k, a, b = o.export(r)
+        samples[r, k.astype(np.int64)] = a + 1j * b
+    # exact expectation: N + L_q N / 2^32 with the quantized columns
+    Q = _q_matrix(o, n, s, gamma)
+    expect = np.zeros(D2, dtype=complex)
+    expect[keys.astype(np.int64)] = re + 1j * im
+    N0 = expect.copy()
+    for key in range(D2):
+        if N0[key] == 0:
+            continue
+        a, b = int(N0[key].real), int(N0[key].imag)
+        for t in range(D2):
+            if Q[t, key] != 0:
+                cr, ci = Q[t, key]
+                expect[t] += complex(a * cr - b * ci, a * ci + b * cr) / 2.0 ** 32
+    mean = samples.mean(axis=0)
+    for part in (np.real, np.imag):
+        sd = part(samples).std(axis=0, ddof=1)
+        diff = part(mean) - part(expect)
+        z = np.where(sd > 0, diff / np.maximum(sd, 1e-300) * math.sqrt(R), 0.0)
+        assert np.all(np.abs(z) < 5.0), z
+        assert np.all(np.abs(diff[sd == 0]) < 1e-9)   # deterministic components are exact
+
+
+def test_death_only_closed_form(orc):
+    """Pure dephasing: every column is diagonal (no spawning); diagonal keys never change and an
+    off-diagonal key with i_q != j_q decays in expectation as (1 - 2 gamma dt)^s."""
+    n, g, dt, steps = 1, 0.5, 0.02, 30
+    lops = [[(0, 1, 1.0)]]
+    keys = np.array([0, (0 << 1) | 1, (1 << 1) | 0, 3], dtype=np.uint64)
+    re = np.array([1000, 800, 800, 1000], dtype=np.int32)
+    im = np.array([0, 50, -50, 0], dtype=np.int32)
+    R = 800
+    o = orc.Oracle(n, R, 5, dt, [], lops, keys, re, im)
+    o.step(np.zeros((steps, 0)), np.full((steps, 1), g))
+    vals = np.zeros((R, 4), dtype=complex)
+    for r in range(R):
+        k, a, b = o.export(r)
+        d = dict(zip(k.tolist(), (a + 1j * b).tolist()))
+        vals[r] = [d.get(int(x), 0) for x in keys]
+    assert np.all(vals[:, 0] == 1000) and np.all(vals[:, 3] == 1000)
+    f = (1 - 2 * g * dt) ** steps
+    for c in (1, 2):
+        mean = vals[:, c].mean()
+        sd = vals[:, c].real.std(ddof=1) / math.sqrt(R) + 1e-9
+        assert abs(mean.real - f * re[c]) < 5 * sd + 1
+        sdi = vals[:, c].imag.std(ddof=1) / math.sqrt(R) + 1e-9
+        assert abs(mean.imag - f * im[c]) < 5 * sdi + 1
+
+
+def _run_oracle_obs(orc, w, R):
+    o = orc.Oracle(w.n, R, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    obs = [(x, z) for _, x, z, _ in w.pauli_obs]
+    out = []
+    for a, b, pl in w.segments():
+        for (px, pz) in pl:
+            o.pulse(px, pz)
+        o.step(w.s[a:b], w.gamma[a:b])
+        out.append(b)
+    return o, obs
+
+
+def test_multi_step_matches_dense_euler_map(orc):
+    """The noisy GHZ circuit at n=4: oracle replica means of <Z_q>, the GHZ fidelity and the trace
+    agree with the dense Euler map (their exact expectation) within 5 sigma."""
+    w = W.config_ghz4()
+    R = 48
+    checkpoints = [100, 250, 400]
+    o = orc.Oracle(w.n, R, 77, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    dm = dense.DenseModel(w.n, w.h, w.lops)
+    D = 1 << w.n
+    rho0 = np.zeros((D, D), dtype=complex); rho0[0, 0] = 1
+    v = dense.vec(rho0)
+    done = 0
+    psi = np.zeros(D, dtype=complex)
+    for i, a in w.psi:
+        psi[i] = a
+    for cp in checkpoints:
+        o.step(w.s[done:cp], w.gamma[done:cp])
+        v = dense.euler_map(dm, w.s[done:cp], w.gamma[done:cp], w.dt, v)
+        done = cp
+        rho = dense.unvec(v, w.n)
+        exact = [np.real(np.trace(dense.pauli(w.n, 0, 1 << q) @ rho)) for q in range(w.n)]
+        exact += [np.real(psi.conj() @ rho @ psi), np.real(np.trace(rho))]
+        per = np.zeros((R, w.n + 2))
+        for r in range(R):
+            k, a, b = o.export(r)
+            N = np.zeros(D * D, dtype=complex)
+            N[k.astype(np.int64)] = a + 1j * b
+            Nm = dense.unvec(N, w.n) / w.walker_target
+            per[r] = [np.real(np.trace(dense.pauli(w.n, 0, 1 << q) @ Nm)) for q in range(w.n)] + \
+                     [np.real(psi.conj() @ Nm @ psi), np.real(np.trace(Nm))]
+        mean = per.mean(axis=0)
+        se = per.std(axis=0, ddof=1) / math.sqrt(R)
+        assert np.all(np.abs(mean - exact) < 5 * se + 1e-4), (cp, mean, exact, se)
+
+
+def test_replica_trajectory_independent_of_replica_count(orc):
+    w = W.config_ghz4()
+    a = orc.Oracle(w.n, 2, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    b = orc.Oracle(w.n, 5, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    a.step(w.s[:150], w.gamma[:150])
+    b.step(w.s[:150], w.gamma[:150])
+    for r in range(2):
+        for x, y in zip(a.export(r), b.export(r)):
+            assert np.array_equal(x, y)
+    assert not np.array_equal(a.export(0)[1], a.export(1)[1]) or \
+        not np.array_equal(a.export(0)[0], a.export(1)[0])
+
+
+# ---- pulses and estimators against dense linear algebra --------------------------------------
+
+def test_pulse_matches_dense_conjugation(orc):
+    rng = np.random.default_rng(3)
+    n = 3
+    keys, re, im = W.random_records(n, rng, 25)
+    o = orc.Oracle(n, 1, 1, 0.01, [], [], keys, re, im)
+    D = 1 << n
+    N = np.zeros(D * D, dtype=complex); N[keys.astype(np.int64)] = re + 1j * im
+    for x, z in [(0, 5), (3, 0), (6, 3)]:
+        o.pulse(x, z)
+        N = dense.pulse_superop(n, x, z) @ N
+        k, a, b = o.export(0)
+        M = np.zeros(D * D, dtype=complex); M[k.astype(np.int64)] = a + 1j * b
+        assert np.array_equal(M, N)
+
+
+def test_observe_matches_dense_matrix(orc):
+    rng = np.random.default_rng(8)
+    n = 3
+    D = 1 << n
+    keys, re, im = W.random_records(n, rng, 40, scale=1000)
+    o = orc.Oracle(n, 1, 1, 0.01, [], [], keys, re, im)
+    N = np.zeros(D * D, dtype=complex); N[keys.astype(np.int64)] = re + 1j * im
+    Nm = dense.unvec(N, n)
+    paulis = [(0, 1), (0, 6), (5, 0), (3, 3), (7, 2)]
+    look = [int(keys[3]), 1, int(keys[-1]), (1 << (2 * n)) - 1]
+    ob = o.observe(0, paulis, look)
+    assert ob["n_occ"] == len(keys)
+    assert ob["n_tot"] == int(np.abs(re).sum() + np.abs(im).sum())
+    assert ob["ndiag"] == np.trace(Nm)
+    for (x, z), v in zip(paulis, ob["pauli"]):
+        assert complex(v[0], v[1]) == np.trace(dense.pauli(n, x, z) @ Nm)
+    for kk, v in zip(look, ob["lookup"]):
+        assert complex(v[0], v[1]) == N[kk]
+    assert ob["eps2"] == round(np.sum(np.abs(Nm - Nm.conj().T) ** 2))
+
+
+# ---- failure handling ------------------------------------------------------------------------
+
+def test_dt_bound_error(orc):
+    w = W.config_ghz4()
+    o = orc.Oracle(w.n, 1, 1, 0.2, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    with pytest.raises(orc.OracleError) as e:
+        o.step(w.s[:1] * 40, w.gamma[:1])
+    assert e.value.code == orc.ORC_ERR_DT
+
+
+def test_count_overflow_keeps_state(orc):
+    o = orc.Oracle(1, 1, 1, 0.01, [], [], [0], [2_000_000_000], [0])
+    o.set_shift(0, 20.0)      # cloning at rate 20: 2e9 * (1 + 0.2) > INT32_MAX
+    with pytest.raises(orc.OracleError) as e:
+        o.step(np.zeros((1, 0)), np.zeros((1, 0)))
+    assert e.value.code == orc.ORC_ERR_COUNT_OVERFLOW
+    k, a, b = o.export(0)
+    assert a[0] == 2_000_000_000 and o.step_index == 0

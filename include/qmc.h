@@ -1,0 +1,209 @@
+/*
+ * qmc.h -- C ABI of libqmc, an MI355X (gfx950) implementation of one population-dynamics time
+ * step of the real-time, sign-problem-suppressed quantum Monte Carlo of Shen & Lidar,
+ * arXiv:2502.18929.
+ *
+ * The problem (eq. (1)): d rho/dt = -i[H(t), rho] + (1/2) sum_k gamma_k(t) D[L_k] rho with
+ * D[L] rho = 2 L rho L^dagger - {L^dagger L, rho}.  The density matrix is column-stacked
+ * (eq. (2)) and represented per replica by an integer population vector |N(t)> of complex
+ * walkers (eq. (3) and the End Matter on spawn and annihilation).
+ *
+ * Conventions
+ *  - Qubit q of the basis state |i> is bit q of i.  The element |i><j| (ket i, bra j) has the
+ *    walker key (j << n) | i (2n bits).
+ *  - A monomial (x, z, re, im) is the operator (re + i im) X^x Z^z with
+ *    X^x Z^z |i> = (-1)^popcount(z & i) |i ^ x>.  x and z use the low n bits.
+ *  - A population is a Gaussian integer (re, im) of int32 walker counts (signs +-1, +-i).
+ *
+ * Arithmetic contract (identical in the CPU oracle that checks this library bit for bit)
+ *  - Every source term of the Liouvillian (kappa0 * A rho B for Pauli monomials A, B) is scaled
+ *    per step by its weight w (s_m(t_s) for H monomial m, gamma_k(t_s) for L_k) and quantized
+ *    as q = llrint(ldexp(dt * (w * kappa0), 32)) separately for Re and Im; equal (target mask,
+ *    sign mask) pairs are then merged by integer addition.  A column group (all terms with the
+ *    same key-XOR mask) must satisfy sum(|q_re| + |q_im|) < 2^31, else QMC_ERR_DT.
+ *  - Per parent (key, a + ib) and step s, Philox4x32-10 with key (seed_lo, seed_hi) and counter
+ *    (key_lo32, key_hi32, s, replica << 8) yields words w0 (spawn) and w1 (death).
+ *  - Death/cloning: the diagonal coefficient d(key) times (a + ib), both components rounded
+ *    with one systematic comb started at w1, added to N(t).  Spawning: the off-diagonal groups
+ *    in increasing mask order, Re then Im of each, rounded with one comb started at w0; nonzero
+ *    children go to key ^ mask.  A comb over Q32 values x_k with start U emits
+ *    sign(x_k) * floor((r_k + |x_k|) / 2^32), r_0 = U, r_{k+1} = (r_k + |x_k|) mod 2^32, whose
+ *    expectation is exactly x_k / 2^32 (the unbiasedness identity of the End Matter).
+ *  - Annihilation: parents and children are summed per key in int64; a sum outside int32 is
+ *    QMC_ERR_COUNT_OVERFLOW; (0, 0) locations disappear.
+ *
+ * Memory and threading
+ *  - The caller owns every host array passed in (copied during the call) and every output
+ *    array (written during the call).
+ *  - The caller owns the device workspace (any device allocation, e.g. a torch uint8 tensor of
+ *    qmc_workspace_bytes bytes) and the HIP stream; all device work of a context is enqueued
+ *    on that stream.  The library never allocates device memory; it allocates pinned host
+ *    staging memory in qmc_init and frees it in qmc_destroy.
+ *  - One context per stream; calls on one context must not overlap.
+ *
+ * Errors: every int-returning function returns QMC_OK (0) or a negative code; no exception
+ * crosses the ABI.  After an error qmc_last_error gives a message.  Device-side errors are
+ * detected at the end of each qmc_step batch; the context then holds the last good step
+ * (the step before the one that failed), so a caller may re-initialize with more capacity,
+ * qmc_import that state and repeat the step with an identical result.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QMC_OK 0
+#define QMC_ERR_ARG (-1)            /* invalid argument (sizes, masks, ordering, capacity) */
+#define QMC_ERR_DT (-2)             /* a column group violates the Q32 bound; nothing ran */
+#define QMC_ERR_STORE_CAP (-3)      /* more occupied keys than the store capacity */
+#define QMC_ERR_SPAWN_CAP (-4)      /* more child records in one step than the spawn capacity */
+#define QMC_ERR_COUNT_OVERFLOW (-5) /* an annihilated population left the int32 range */
+#define QMC_ERR_HIP (-6)            /* a HIP runtime call failed (no device, launch failure) */
+#define QMC_ERR_STATE (-8)          /* the context is unusable after an earlier HIP error */
+
+typedef struct { uint64_t x, z; double re, im; } qmc_monomial;
+
+typedef struct {
+  uint32_t n_qubits;        /* 1..32, and 2*n_qubits + ceil(log2(n_replicas)) <= 64 */
+  uint32_t n_replicas;      /* independent samples of eq. (3), all advanced together */
+  uint64_t seed;            /* Philox key */
+  double dt;                /* Euler time step (End Matter on simulation methodology) */
+  uint64_t walker_target;   /* N^diag of the eq. (3) paragraph; only used for reporting */
+  uint64_t store_capacity;  /* occupied keys per replica the store can hold */
+  uint64_t spawn_capacity;  /* child records per replica per step */
+} qmc_config;
+
+/* H(t) = sum_m s_m(t) h[m] with real weights s_m(t) given per step; L_k = sum of the monomials
+ * l[l_off[k]] .. l[l_off[k+1]-1] with real rates gamma_k(t) given per step (negative rates are
+ * allowed: the time-local, non-Markovian case of eq. (1)).  l_off has n_l + 1 entries. */
+typedef struct {
+  uint32_t n_h;
+  const qmc_monomial* h;
+  uint32_t n_l;
+  const uint32_t* l_off;
+  const qmc_monomial* l;
+} qmc_model;
+
+typedef struct qmc_ctx qmc_ctx;
+
+/* Bytes of device workspace a context with this configuration needs.  QMC_ERR_ARG on an
+ * invalid configuration. */
+int qmc_workspace_bytes(const qmc_config* cfg, const qmc_model* model, size_t* bytes);
+
+/* Create a context (eq. (3) paragraph: N(0) := N^diag rho(0)).  keys/re/im are the n0 initial
+ * records of every replica: keys < 2^(2n) sorted ascending and unique, no (0, 0) population.
+ * d_workspace is a device pointer to ws_bytes >= qmc_workspace_bytes bytes, 256-byte aligned,
+ * owned by the caller and kept alive until qmc_destroy.  hip_stream is a hipStream_t (NULL =
+ * the default stream).  Errors: QMC_ERR_ARG, QMC_ERR_HIP. */
+int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys,
+             const int32_t* re, const int32_t* im, uint64_t n0, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, qmc_ctx** out);
+
+/* Advance every replica by nsteps Euler steps (End Matter, spawn and annihilation steps,
+ * Euler solver).  s is [nsteps][n_h] and gamma is [nsteps][n_l], row k holding the weights at
+ * the left end t = (step0 + k) * dt of step k.  Tables are quantized and bound-checked on the
+ * host before anything is launched (QMC_ERR_DT leaves the state untouched); device errors
+ * (QMC_ERR_STORE_CAP, QMC_ERR_SPAWN_CAP, QMC_ERR_COUNT_OVERFLOW) roll the context back to the
+ * last good step.  Synchronizes the stream once at the end. */
+int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma);
+
+/* Ideal instantaneous Pauli pulse on every replica: rho -> P rho P^dagger with P = X^x Z^z,
+ * i.e. |i><j| -> (-1)^{popc(z & i) + popc(z & j)} |i ^ x><j ^ x| (used for the staggered-XX
+ * dynamical-decoupling pulses of Fig. 1(c)). */
+int qmc_pulse(qmc_ctx* ctx, uint64_t x, uint64_t z);
+
+/* Constant diagonal shift S for one replica (death coefficient L_diag + S).  The paper needs
+ * none (the Liouvillian is trace preserving); S != 0 biases the estimator. */
+int qmc_set_shift(qmc_ctx* ctx, uint32_t replica, double shift);
+
+typedef struct {
+  uint32_t n_pauli;          /* observables P = X^px Z^pz: sum_i (-1)^popc(pz&i) N_{i,i^px} */
+  const uint64_t* px;
+  const uint64_t* pz;
+  uint32_t n_psi;            /* sparse |psi> for the fidelity <psi|rho|psi> (Fig. 2 caption) */
+  const uint64_t* psi_index;
+  const double* psi_re;
+  const double* psi_im;
+  uint32_t want_eps;         /* nonzero: anti-Hermiticity numerator (End Matter) */
+} qmc_obs_spec;
+
+/* Outputs, arrays of length n_replicas (times the per-replica counts shown), caller-owned.
+ * Integer numerators are exact.  FP64 values are normalized by N^diag(0) of that replica
+ * (eq. (3)): trace = Re N^diag(t) / Re N^diag(0) (replica-aggregation paragraph), theta =
+ * atan2(Im N^diag, Re N^diag) (End Matter on sign-problem suppression), pauli_val = numerator
+ * / Re N^diag(0), fidelity = Re sum_{u,v} conj(psi_u) psi_v N_{uv} / Re N^diag(0) with N_{uv}
+ * at key (v << n) | u, eps = sqrt(sum |N_ij - conj N_ji|^2) / Re N^diag(0). */
+typedef struct {
+  uint64_t* n_occ;           /* [R] occupied keys (dim H_QMC of the scaling paragraph) */
+  uint64_t* n_tot;           /* [R] sum |re| + |im| (N^tot) */
+  int64_t* ndiag;            /* [R][2] */
+  int64_t* pauli;            /* [R][n_pauli][2] */
+  uint64_t* eps2;            /* [R][2] 128-bit (lo, hi) */
+  double* trace;             /* [R] */
+  double* theta;             /* [R] */
+  double* pauli_val;         /* [R][n_pauli][2] */
+  double* fidelity;          /* [R][2] (Re, Im) */
+  double* eps;               /* [R] */
+} qmc_obs_out;
+
+/* Estimators of the current state (any NULL output pointer is skipped). */
+int qmc_observe(qmc_ctx* ctx, const qmc_obs_spec* spec, qmc_obs_out* out);
+
+/* Copy one replica's store to host arrays (keys ascending).  *n receives the size; if it
+ * exceeds cap nothing is copied and QMC_ERR_ARG is returned. */
+int qmc_export(qmc_ctx* ctx, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+               uint64_t cap, uint64_t* n);
+
+/* Replace one replica's store (same rules as qmc_init's records) and set the step counter
+ * of the context to `step` (the Philox counter of the next step). */
+int qmc_import(qmc_ctx* ctx, uint32_t replica, const uint64_t* keys, const int32_t* re,
+               const int32_t* im, uint64_t n, uint32_t step);
+
+/* Counters of a context: the step counter, the occupied keys of all replicas now, and running
+ * sums since qmc_init over the parents of every step of N^tot (walker_steps), occupied keys
+ * (key_steps), child records (child_steps) and annihilated output keys (out_steps).  The sums
+ * give the walker-steps/s and key-steps/s rates and the algorithmic bytes of the kernels. */
+typedef struct {
+  uint32_t step;
+  uint64_t n_occ_total;
+  uint64_t walker_steps;
+  uint64_t key_steps;
+  uint64_t child_steps;
+  uint64_t out_steps;
+} qmc_stats;
+
+int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
+
+/* Live timing of one kernel class with HIP events recorded on the context's stream around
+ * every launch of that class in qmc_step: kernel_class 0 = spawn, 1 = child sort (all radix
+ * passes), 2 = merge (partition + annihilation), -1 = off.  qmc_profile resets the totals;
+ * qmc_profile_read returns the summed milliseconds and the number of timed launches. */
+int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
+int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches);
+
+/* The quantized coefficient table of one step for this configuration and model, computed on
+ * the host only (no device, no context): n_groups groups (group 0 = diagonal, always present)
+ * with masks gxmask[g] and term ranges gstart[g] .. gstart[g+1]-1; term t has sign mask
+ * tzmask[t] and Q32 coefficient tq[t][0] + i tq[t][1].  For checking the table against an
+ * independent implementation.  QMC_ERR_ARG if a capacity is too small, QMC_ERR_DT if the
+ * Q32 bound fails. */
+int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double* s,
+                    const double* gamma, uint32_t cap_groups, uint32_t cap_terms,
+                    uint32_t* n_groups, uint64_t* gxmask, uint32_t* gstart, uint32_t* n_terms,
+                    uint64_t* tzmask, int64_t* tq);
+
+/* Message of the last error on this context (owned by the context, valid until its next
+ * call), or a static string when ctx is NULL. */
+const char* qmc_last_error(const qmc_ctx* ctx);
+
+void qmc_destroy(qmc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -76,6 +76,8 @@ def lib():
                                        P(ctypes.c_int)]
         L.orc_pulse.argtypes = [ctypes.c_void_p, u64, u64]
         L.orc_set_shift.argtypes = [ctypes.c_void_p, u32, dbl]
+        L.orc_counters.argtypes = [ctypes.c_void_p, P(u64), P(u64), P(u64), P(u64)]
+        L.orc_counters.restype = None
         L.orc_get_step.argtypes = [ctypes.c_void_p]
         L.orc_get_step.restype = u32
         L.orc_size.argtypes = [ctypes.c_void_p, u32]
@@ -235,6 +237,13 @@ class Oracle:
 
     def set_shift(self, replica, shift):
         _check(lib().orc_set_shift(self._ctx, int(replica), float(shift)), "set_shift")
+
+    def counters(self):
+        w, k, ch, mx = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        lib().orc_counters(self._ctx, ctypes.byref(w), ctypes.byref(k), ctypes.byref(ch),
+                           ctypes.byref(mx))
+        return dict(walker_steps=w.value, key_steps=k.value, child_steps=ch.value,
+                    max_children=mx.value)
 
     @property
     def step_index(self):

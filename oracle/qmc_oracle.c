@@ -104,6 +104,11 @@ struct orc_ctx {
   store_t* st; /* [R] */
   double* shift; /* [R] */
   uint32_t step;
+  uint64_t walker_steps; /* sum over steps and replicas of the parents' N^tot */
+  uint64_t key_steps;    /* sum over steps and replicas of the parents' occupied keys */
+  uint64_t child_steps;  /* sum over steps and replicas of emitted child records */
+  uint64_t max_children; /* largest number of child records of one step (all replicas) */
+  uint64_t* nchild;      /* [R] child records of the last step, per replica */
 };
 
 /* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
@@ -195,7 +200,8 @@ int orc_create(uint32_t n_qubits, uint32_t n_replicas, uint64_t seed, double dt,
   }
   c->st = (store_t*)calloc(n_replicas, sizeof(store_t));
   c->shift = (double*)calloc(n_replicas, sizeof(double));
-  if (!c->st || !c->shift) {
+  c->nchild = (uint64_t*)calloc(n_replicas, sizeof(uint64_t));
+  if (!c->st || !c->shift || !c->nchild) {
     orc_destroy(c);
     return ORC_ERR_NOMEM;
   }
@@ -225,6 +231,7 @@ void orc_destroy(orc_ctx* c) {
     for (uint32_t r = 0; r < c->R; ++r) store_free(&c->st[r]);
   free(c->st);
   free(c->shift);
+  free(c->nchild);
   free(c->terms);
   free(c);
 }
@@ -471,7 +478,7 @@ static int cmp_rec(const void* a, const void* b) {
 }
 
 static int step_replica(const orc_ctx* c, uint32_t r, const table_t* T, int64_t qs_re,
-                        store_t* out) {
+                        store_t* out, uint64_t* nchild) {
   const store_t* in = &c->st[r];
   const uint32_t G = T->n_groups;
   uint64_t cap = in->n * (uint64_t)G + 1;
@@ -519,6 +526,7 @@ static int step_replica(const orc_ctx* c, uint32_t r, const table_t* T, int64_t 
   }
   free(xs);
   free(ns);
+  *nchild = nr - in->n;
 
   /* Annihilation (End Matter): merge children with the surviving parents, sum by location,
    * opposite signs cancel, empty locations disappear. */
@@ -583,13 +591,22 @@ static int one_step(orc_ctx* c, const double* s, const double* gamma, int thread
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads > 0 ? threads : 1)
 #endif
-    for (uint32_t r = 0; r < c->R; ++r) rcs[r] = step_replica(c, r, &T, qs[r], &nxt[r]);
+    for (uint32_t r = 0; r < c->R; ++r)
+      rcs[r] = step_replica(c, r, &T, qs[r], &nxt[r], &c->nchild[r]);
     for (uint32_t r = 0; r < c->R; ++r)
       if (rcs[r] && !rc) rc = rcs[r];
   }
   (void)threads;
   if (rc == ORC_OK) {
+    uint64_t tot_children = 0;
+    for (uint32_t r = 0; r < c->R; ++r) tot_children += c->nchild[r];
+    c->child_steps += tot_children;
+    if (tot_children > c->max_children) c->max_children = tot_children;
     for (uint32_t r = 0; r < c->R; ++r) {
+      for (uint64_t p = 0; p < c->st[r].n; ++p)
+        c->walker_steps += (uint64_t)llabs((int64_t)c->st[r].re[p]) +
+                           (uint64_t)llabs((int64_t)c->st[r].im[p]);
+      c->key_steps += c->st[r].n;
       store_free(&c->st[r]);
       c->st[r] = nxt[r];
     }
@@ -670,6 +687,14 @@ int orc_set_shift(orc_ctx* c, uint32_t replica, double shift) {
 }
 
 uint32_t orc_get_step(const orc_ctx* c) { return c->step; }
+
+void orc_counters(const orc_ctx* c, uint64_t* walker_steps, uint64_t* key_steps,
+                  uint64_t* child_steps, uint64_t* max_children) {
+  *walker_steps = c->walker_steps;
+  *key_steps = c->key_steps;
+  *child_steps = c->child_steps;
+  *max_children = c->max_children;
+}
 
 uint64_t orc_size(const orc_ctx* c, uint32_t replica) {
   return replica < c->R ? c->st[replica].n : 0;

@@ -86,6 +86,10 @@ int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z);
 int orc_set_shift(orc_ctx* c, uint32_t replica, double shift);
 
 uint32_t orc_get_step(const orc_ctx* c);
+/* Sums over all steps so far and all replicas of the parents' N^tot, of their occupied keys and
+ * of the child records emitted, and the largest child-record count of one step. */
+void orc_counters(const orc_ctx* c, uint64_t* walker_steps, uint64_t* key_steps,
+                  uint64_t* child_steps, uint64_t* max_children);
 uint64_t orc_size(const orc_ctx* c, uint32_t replica);
 int orc_export(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
                uint64_t cap, uint64_t* n);

@@ -1,0 +1,319 @@
+"""ctypes binding of libqmc (include/qmc.h): argument marshalling only.
+
+Every step of the population dynamics runs in the HIP kernels of ``csrc/``; PyTorch provides
+the device workspace (a uint8 tensor) and the stream.  There is no CPU fallback: without the
+built library or without a GPU, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqmc.so")
+
+QMC_OK = 0
+QMC_ERR_ARG = -1
+QMC_ERR_DT = -2
+QMC_ERR_STORE_CAP = -3
+QMC_ERR_SPAWN_CAP = -4
+QMC_ERR_COUNT_OVERFLOW = -5
+QMC_ERR_HIP = -6
+QMC_ERR_STATE = -8
+
+EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_pulse", "qmc_set_shift",
+            "qmc_observe", "qmc_export", "qmc_import", "qmc_counters", "qmc_profile",
+            "qmc_profile_read", "qmc_coeff_table", "qmc_last_error", "qmc_destroy"]
+
+
+class Monomial(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_uint64), ("z", ctypes.c_uint64),
+                ("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_uint32), ("n_replicas", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("dt", ctypes.c_double),
+                ("walker_target", ctypes.c_uint64), ("store_capacity", ctypes.c_uint64),
+                ("spawn_capacity", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_uint32), ("n_occ_total", ctypes.c_uint64),
+                ("walker_steps", ctypes.c_uint64), ("key_steps", ctypes.c_uint64),
+                ("child_steps", ctypes.c_uint64), ("out_steps", ctypes.c_uint64)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("n_h", ctypes.c_uint32), ("h", ctypes.POINTER(Monomial)),
+                ("n_l", ctypes.c_uint32), ("l_off", ctypes.POINTER(ctypes.c_uint32)),
+                ("l", ctypes.POINTER(Monomial))]
+
+
+class ObsSpec(ctypes.Structure):
+    _fields_ = [("n_pauli", ctypes.c_uint32), ("px", ctypes.POINTER(ctypes.c_uint64)),
+                ("pz", ctypes.POINTER(ctypes.c_uint64)), ("n_psi", ctypes.c_uint32),
+                ("psi_index", ctypes.POINTER(ctypes.c_uint64)),
+                ("psi_re", ctypes.POINTER(ctypes.c_double)),
+                ("psi_im", ctypes.POINTER(ctypes.c_double)), ("want_eps", ctypes.c_uint32)]
+
+
+P64 = ctypes.POINTER(ctypes.c_uint64)
+PI64 = ctypes.POINTER(ctypes.c_int64)
+PD = ctypes.POINTER(ctypes.c_double)
+
+
+class ObsOut(ctypes.Structure):
+    _fields_ = [("n_occ", P64), ("n_tot", P64), ("ndiag", PI64), ("pauli", PI64), ("eps2", P64),
+                ("trace", PD), ("theta", PD), ("pauli_val", PD), ("fidelity", PD), ("eps", PD)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqmc.so (built by ``paper_2502_18929_amd.build``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        u32, u64, i32, dbl, vp = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_void_p)
+        P = ctypes.POINTER
+        L.qmc_workspace_bytes.argtypes = [P(Config), P(Model), P(ctypes.c_size_t)]
+        L.qmc_init.argtypes = [P(Config), P(Model), P(u64), P(i32), P(i32), u64, vp,
+                               ctypes.c_size_t, vp, P(vp)]
+        L.qmc_step.argtypes = [vp, u32, P(dbl), P(dbl)]
+        L.qmc_pulse.argtypes = [vp, u64, u64]
+        L.qmc_set_shift.argtypes = [vp, u32, dbl]
+        L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
+        L.qmc_export.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
+        L.qmc_import.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, u32]
+        L.qmc_counters.argtypes = [vp, P(Stats)]
+        L.qmc_profile.argtypes = [vp, ctypes.c_int32]
+        L.qmc_profile_read.argtypes = [vp, P(dbl), P(u64)]
+        L.qmc_coeff_table.argtypes = [P(Config), P(Model), P(dbl), P(dbl), u32, u32, P(u32),
+                                      P(u64), P(u32), P(u32), P(u64), P(ctypes.c_int64)]
+        L.qmc_last_error.argtypes = [vp]
+        L.qmc_last_error.restype = ctypes.c_char_p
+        L.qmc_destroy.argtypes = [vp]
+        L.qmc_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+class QMCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libqmc error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _monos(lst):
+    arr = (Monomial * max(1, len(lst)))()
+    for i, (x, z, c) in enumerate(lst):
+        c = complex(c)
+        arr[i] = Monomial(int(x), int(z), c.real, c.imag)
+    return arr
+
+
+class QMC:
+    """One libqmc context: R replicas of one model, advanced on one HIP stream."""
+
+    def __init__(self, n, n_replicas, seed, dt, h, lops, keys, re, im, store_capacity,
+                 spawn_capacity, walker_target=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libqmc needs a HIP device; none is visible")
+        L = lib()
+        self.n, self.R, self.n_h, self.n_l = int(n), int(n_replicas), len(h), len(lops)
+        self._h = _monos(h)
+        self._l = _monos([m for op in lops for m in op])
+        off = np.zeros(len(lops) + 1, dtype=np.uint32)
+        for k, op in enumerate(lops):
+            off[k + 1] = off[k] + len(op)
+        self._off = off
+        self._cfg = Config(self.n, self.R, int(seed), float(dt), int(walker_target),
+                           int(store_capacity), int(spawn_capacity))
+        self._model = Model(self.n_h, self._h, self.n_l, _ptr(self._off, ctypes.c_uint32),
+                            self._l)
+        nb = ctypes.c_size_t()
+        rc = L.qmc_workspace_bytes(ctypes.byref(self._cfg), ctypes.byref(self._model),
+                                   ctypes.byref(nb))
+        if rc:
+            raise QMCError(rc, "invalid configuration")
+        self.ws_bytes = nb.value
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        re = np.ascontiguousarray(re, dtype=np.int32)
+        im = np.ascontiguousarray(im, dtype=np.int32)
+        self._ctx = ctypes.c_void_p()
+        rc = L.qmc_init(ctypes.byref(self._cfg), ctypes.byref(self._model),
+                        _ptr(keys, ctypes.c_uint64), _ptr(re, ctypes.c_int32),
+                        _ptr(im, ctypes.c_int32), len(keys), ctypes.c_void_p(aligned),
+                        self.ws_bytes, ctypes.c_void_p(stream.cuda_stream),
+                        ctypes.byref(self._ctx))
+        if rc:
+            raise QMCError(rc, "qmc_init failed")
+
+    @classmethod
+    def from_workload(cls, w, store_capacity=None, spawn_capacity=None, n_replicas=None,
+                      seed=None):
+        R = w.n_replicas if n_replicas is None else n_replicas
+        if store_capacity is None:
+            store_capacity = min(1 << (2 * w.n), 1 << 20)
+        if spawn_capacity is None:
+            spawn_capacity = store_capacity
+        return cls(w.n, R, w.seed if seed is None else seed, w.dt, w.h, w.lops, w.init_keys,
+                   w.init_re, w.init_im, store_capacity, spawn_capacity,
+                   walker_target=w.walker_target)
+
+    def _check(self, rc):
+        if rc:
+            msg = lib().qmc_last_error(self._ctx)
+            raise QMCError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().qmc_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, s, gamma):
+        """s: [nsteps, n_h] weights, gamma: [nsteps, n_l] rates."""
+        s = np.asarray(s, dtype=np.float64)
+        g = np.asarray(gamma, dtype=np.float64)
+        nsteps = s.shape[0] if s.ndim == 2 else g.shape[0]
+        s = np.ascontiguousarray(s.reshape(nsteps, self.n_h) if self.n_h else np.zeros((nsteps, 1)))
+        g = np.ascontiguousarray(g.reshape(nsteps, self.n_l) if self.n_l else np.zeros((nsteps, 1)))
+        self._check(lib().qmc_step(self._ctx, nsteps, _ptr(s, ctypes.c_double),
+                                   _ptr(g, ctypes.c_double)))
+
+    def run_workload(self, w, start=0, stop=None):
+        """Advance through steps [start, stop) of a workload, applying its ideal pulses."""
+        stop = w.nsteps if stop is None else stop
+        for a, b, pulses in w.segments():
+            if b <= start or a >= stop:
+                continue
+            if a >= start:
+                for (px, pz) in pulses:
+                    self.pulse(px, pz)
+            lo, hi = max(a, start), min(b, stop)
+            self.step(w.s[lo:hi], w.gamma[lo:hi])
+        if stop == w.nsteps:
+            for (px, pz) in w.pulses.get(w.nsteps, []):
+                self.pulse(px, pz)
+
+    def pulse(self, x, z):
+        self._check(lib().qmc_pulse(self._ctx, int(x), int(z)))
+
+    def set_shift(self, replica, shift):
+        self._check(lib().qmc_set_shift(self._ctx, int(replica), float(shift)))
+
+    def observe(self, pauli=(), psi=(), want_eps=False):
+        R = self.R
+        npl = len(pauli)
+        px = np.ascontiguousarray([p[0] for p in pauli] or [0], dtype=np.uint64)
+        pz = np.ascontiguousarray([p[1] for p in pauli] or [0], dtype=np.uint64)
+        pidx = np.ascontiguousarray([p[0] for p in psi] or [0], dtype=np.uint64)
+        pre = np.ascontiguousarray([complex(p[1]).real for p in psi] or [0.0])
+        pim = np.ascontiguousarray([complex(p[1]).imag for p in psi] or [0.0])
+        spec = ObsSpec(npl, _ptr(px, ctypes.c_uint64), _ptr(pz, ctypes.c_uint64), len(psi),
+                       _ptr(pidx, ctypes.c_uint64), _ptr(pre, ctypes.c_double),
+                       _ptr(pim, ctypes.c_double), 1 if want_eps else 0)
+        o = dict(n_occ=np.zeros(R, np.uint64), n_tot=np.zeros(R, np.uint64),
+                 ndiag=np.zeros((R, 2), np.int64), pauli=np.zeros((R, max(npl, 1), 2), np.int64),
+                 eps2=np.zeros((R, 2), np.uint64), trace=np.zeros(R), theta=np.zeros(R),
+                 pauli_val=np.zeros((R, max(npl, 1), 2)), fidelity=np.zeros((R, 2)),
+                 eps=np.zeros(R))
+        out = ObsOut(_ptr(o["n_occ"], ctypes.c_uint64), _ptr(o["n_tot"], ctypes.c_uint64),
+                     _ptr(o["ndiag"], ctypes.c_int64), _ptr(o["pauli"], ctypes.c_int64),
+                     _ptr(o["eps2"], ctypes.c_uint64), _ptr(o["trace"], ctypes.c_double),
+                     _ptr(o["theta"], ctypes.c_double), _ptr(o["pauli_val"], ctypes.c_double),
+                     _ptr(o["fidelity"], ctypes.c_double), _ptr(o["eps"], ctypes.c_double))
+        self._check(lib().qmc_observe(self._ctx, ctypes.byref(spec), ctypes.byref(out)))
+        o["pauli"] = o["pauli"][:, :npl]
+        o["pauli_val"] = o["pauli_val"][:, :npl]
+        o["eps2_int"] = [int(a) + (int(b) << 64) for a, b in o["eps2"]]
+        return o
+
+    def export(self, replica):
+        n = ctypes.c_uint64()
+        cap = 0
+        rc = lib().qmc_export(self._ctx, int(replica), None, None, None, cap, ctypes.byref(n))
+        if rc not in (QMC_OK, QMC_ERR_ARG):
+            self._check(rc)
+        m = n.value
+        k = np.zeros(max(m, 1), np.uint64)
+        a = np.zeros(max(m, 1), np.int32)
+        b = np.zeros(max(m, 1), np.int32)
+        self._check(lib().qmc_export(self._ctx, int(replica), _ptr(k, ctypes.c_uint64),
+                                     _ptr(a, ctypes.c_int32), _ptr(b, ctypes.c_int32), m,
+                                     ctypes.byref(n)))
+        return k[:m].copy(), a[:m].copy(), b[:m].copy()
+
+    def import_(self, replica, keys, re, im, step):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        re = np.ascontiguousarray(re, dtype=np.int32)
+        im = np.ascontiguousarray(im, dtype=np.int32)
+        self._check(lib().qmc_import(self._ctx, int(replica), _ptr(keys, ctypes.c_uint64),
+                                     _ptr(re, ctypes.c_int32), _ptr(im, ctypes.c_int32),
+                                     len(keys), int(step)))
+
+    def counters(self):
+        st = Stats()
+        self._check(lib().qmc_counters(self._ctx, ctypes.byref(st)))
+        return dict(step=st.step, n_occ=st.n_occ_total, walker_steps=st.walker_steps,
+                    key_steps=st.key_steps, child_steps=st.child_steps, out_steps=st.out_steps)
+
+    def profile(self, kernel_class):
+        """Time one kernel class with HIP events: 'spawn', 'sort', 'merge' or None."""
+        cls = {None: -1, "spawn": 0, "sort": 1, "merge": 2}[kernel_class]
+        self._check(lib().qmc_profile(self._ctx, cls))
+
+    def profile_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_uint64()
+        self._check(lib().qmc_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1):
+    """Host-only: the quantized step table the library would use (no device needed)."""
+    L = lib()
+    hm = _monos(h)
+    lm = _monos([m for op in lops for m in op])
+    off = np.zeros(len(lops) + 1, dtype=np.uint32)
+    for k, op in enumerate(lops):
+        off[k + 1] = off[k] + len(op)
+    cfg = Config(int(n), int(n_replicas), 0, float(dt), 0, 1, 1)
+    model = Model(len(h), hm, len(lops), _ptr(off, ctypes.c_uint32), lm)
+    s = np.ascontiguousarray(s if len(h) else np.zeros(1), dtype=np.float64)
+    g = np.ascontiguousarray(gamma if len(lops) else np.zeros(1), dtype=np.float64)
+    cap = 8192
+    ng, nt = ctypes.c_uint32(), ctypes.c_uint32()
+    gx = np.zeros(cap, np.uint64); gs = np.zeros(cap + 1, np.uint32)
+    tz = np.zeros(cap, np.uint64); tq = np.zeros((cap, 2), np.int64)
+    rc = L.qmc_coeff_table(ctypes.byref(cfg), ctypes.byref(model), _ptr(s, ctypes.c_double),
+                           _ptr(g, ctypes.c_double), cap, cap, ctypes.byref(ng),
+                           _ptr(gx, ctypes.c_uint64), _ptr(gs, ctypes.c_uint32), ctypes.byref(nt),
+                           _ptr(tz, ctypes.c_uint64), _ptr(tq, ctypes.c_int64))
+    if rc:
+        raise QMCError(rc, "qmc_coeff_table failed")
+    G, T = ng.value, nt.value
+    return dict(gxmask=gx[:G].copy(), gstart=gs[:G + 1].copy(), zmask=tz[:T].copy(),
+                q=tq[:T].copy())

@@ -1,0 +1,894 @@
+// qmc_host.cpp -- host runtime of libqmc: the C ABI of include/qmc.h.
+//
+// Responsibilities: validate the problem, compile the model of eq. (1) into Liouville-space
+// source terms (eq. (2)), quantize them per step into Q32 tables with exact integer merging and
+// the per-group bound, carve the caller's device workspace, enqueue the kernels of each step on
+// the caller's stream, and turn device error flags into status codes with rollback to the last
+// good step.  No device memory is allocated here; pinned host staging is.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qmc.h"
+#include "qmc_device.hpp"
+#include "qmc_kernels.h"
+
+namespace {
+
+constexpr uint32_t kMaxPauli = 256;
+constexpr uint32_t kMaxLookup = 4096;
+constexpr size_t kTableArea = 8u << 20;   // device bytes for the step tables of one chunk
+constexpr uint32_t kMaxChunkSteps = 16384;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// A Liouville-space source term: rho -> w(t) * kappa0 * A rho B, acting on key k as
+// k -> k ^ xmask with sign (-1)^parity(zmask & k) (the key-independent sign of the right factor
+// is folded into kappa0).
+struct SrcTerm {
+  uint64_t xmask, zmask;
+  double kre, kim;
+  uint32_t weight_kind;  // 0: s_m, 1: gamma_k
+  uint32_t weight_index;
+};
+
+struct QTerm {
+  uint64_t xmask, zmask;
+  int64_t qre, qim;
+};
+
+struct Layout {
+  size_t counters, sk0, sk1, sv0, sv1, ck0, ck1, cv0, cv1, hist, splits, status, tab, qshift,
+      obs_out, obs_in, look_keys, look_out, total;
+  uint64_t cap_store, cap_child;
+  uint32_t max_tiles;
+};
+
+int pc_parity(uint64_t v) { return __builtin_popcountll(v) & 1; }
+
+uint32_t replica_bits(uint32_t R) {
+  uint32_t b = 0;
+  while ((1ull << b) < R) ++b;
+  return b;
+}
+
+bool compute_layout(const qmc_config& c, Layout& L) {
+  const uint64_t S = c.store_capacity * (uint64_t)c.n_replicas;
+  const uint64_t C = c.spawn_capacity * (uint64_t)c.n_replicas;
+  if (S == 0 || C == 0 || S >= (1ull << 31) || C >= (1ull << 31) || S + C >= (1ull << 31))
+    return false;
+  L.cap_store = S;
+  L.cap_child = C;
+  L.max_tiles = (uint32_t)((S + C + qmc::kMergeTile - 1) / qmc::kMergeTile) + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.counters = take(sizeof(qmc::Counters));
+  L.sk0 = take(S * 8);
+  L.sk1 = take(S * 8);
+  L.sv0 = take(S * 8);
+  L.sv1 = take(S * 8);
+  L.ck0 = take(C * 8);
+  L.ck1 = take(C * 8);
+  L.cv0 = take(C * 8);
+  L.cv1 = take(C * 8);
+  L.hist = take((size_t)qmc::kRadixBins * qmc::kSortBlocks * 4);
+  L.splits = take(((size_t)L.max_tiles + 2) * 8);
+  L.status = take((size_t)L.max_tiles * 8);
+  L.tab = take(kTableArea);
+  L.qshift = take((size_t)c.n_replicas * 8);
+  L.obs_out = take((size_t)c.n_replicas * (5 + 2 * kMaxPauli) * 8);
+  L.obs_in = take((size_t)kMaxPauli * 16);
+  L.look_keys = take((size_t)kMaxLookup * 8);
+  L.look_out = take((size_t)c.n_replicas * kMaxLookup * 16);
+  L.total = o;
+  return true;
+}
+
+}  // namespace
+
+struct qmc_ctx {
+  qmc_config cfg{};
+  uint32_t n = 0, R = 0, kbits = 0, rbits = 0;
+  uint32_t n_h = 0, n_l = 0;
+  std::vector<SrcTerm> terms;
+  Layout L{};
+  uint8_t* ws = nullptr;
+  hipStream_t stream = nullptr;
+  uint32_t step = 0;
+  uint32_t cur = 0;
+  std::vector<double> shift;
+  std::vector<int64_t> nd0_re;
+  uint8_t* pinned = nullptr;     // table staging, kTableArea bytes
+  uint8_t* pinned_small = nullptr;  // counters and estimator staging
+  size_t pinned_small_bytes = 0;
+  std::string err;
+  bool broken = false;
+  int32_t prof_class = -1;
+  std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
+  double prof_ms = 0.0;
+  uint64_t prof_launches = 0;
+
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  uint64_t* sk(uint32_t b) const { return at<uint64_t>(b ? L.sk1 : L.sk0); }
+  int2* sv(uint32_t b) const { return at<int2>(b ? L.sv1 : L.sv0); }
+  uint64_t* ck(uint32_t b) const { return at<uint64_t>(b ? L.ck1 : L.ck0); }
+  int2* cv(uint32_t b) const { return at<int2>(b ? L.cv1 : L.cv0); }
+  qmc::Counters* counters() const { return at<qmc::Counters>(L.counters); }
+};
+
+namespace {
+
+int fail(qmc_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(qmc_ctx* c, hipError_t e, const char* what) {
+  if (c) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    c->broken = true;
+  }
+  return QMC_ERR_HIP;
+}
+
+#define HIPCHK(ctx, expr)                                  \
+  do {                                                     \
+    hipError_t e_ = (hipError_t)(expr);                    \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+// Source terms of eqs. (1)-(2): -i H rho, +i rho H, gamma L rho L^dagger and
+// -(gamma/2){L^dagger L, rho} for L_k = sum_a c_a X^xa Z^za.  The FP64 expressions are part of
+// the arithmetic contract (the same operation order as the CPU oracle).
+void compile_model(const qmc_model& m, uint32_t n, std::vector<SrcTerm>& out) {
+  out.clear();
+  auto emit = [&](uint64_t xm, uint64_t zm, double re, double im, uint32_t kind, uint32_t idx) {
+    out.push_back(SrcTerm{xm, zm, re, im, kind, idx});
+  };
+  for (uint32_t i = 0; i < m.n_h; ++i) {
+    const qmc_monomial& h = m.h[i];
+    // left factor: kappa = -i h
+    emit(h.x, h.z, h.im, -h.re, 0, i);
+    // right factor: kappa = +i h times (-1)^popc(x & z)
+    const double f = pc_parity(h.x & h.z) ? -1.0 : 1.0;
+    emit(h.x << n, h.z << n, f * -h.im, f * h.re, 0, i);
+  }
+  for (uint32_t k = 0; k < m.n_l; ++k) {
+    for (uint32_t a = m.l_off[k]; a < m.l_off[k + 1]; ++a) {
+      for (uint32_t b = m.l_off[k]; b < m.l_off[k + 1]; ++b) {
+        const qmc_monomial& A = m.l[a];
+        const qmc_monomial& B = m.l[b];
+        // gamma c_a conj(c_b) P_a rho P_b^dagger
+        emit((B.x << n) | A.x, (B.z << n) | A.z, A.re * B.re + A.im * B.im,
+             A.im * B.re - A.re * B.im, 1, k);
+        // -(gamma/2) mu M rho and -(gamma/2) mu rho M, mu = conj(c_a) c_b * sign
+        const double sg = ((__builtin_popcountll(A.x & A.z) + __builtin_popcountll(A.z & B.x)) & 1)
+                              ? -1.0 : 1.0;
+        const double mre = sg * (A.re * B.re + A.im * B.im);
+        const double mim = sg * (A.re * B.im - A.im * B.re);
+        const uint64_t x = A.x ^ B.x, z = A.z ^ B.z;
+        emit(x, z, -0.5 * mre, -0.5 * mim, 1, k);
+        const double f = pc_parity(x & z) ? -1.0 : 1.0;
+        emit(x << n, z << n, f * (-0.5 * mre), f * (-0.5 * mim), 1, k);
+      }
+    }
+  }
+}
+
+bool quantize(double dt, double w, double k, int64_t& q) {
+  const double v = std::ldexp(dt * (w * k), 32);
+  if (!std::isfinite(v) || std::fabs(v) >= 4611686018427387904.0) return false;
+  q = (int64_t)std::llrint(v);
+  return true;
+}
+
+uint64_t uabs(int64_t v) { return v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v; }
+
+// Quantized, merged, grouped table for one step.
+struct HostTable {
+  std::vector<QTerm> t;          // grouped: diagonal first, then xmask ascending
+  std::vector<uint64_t> gx;      // group masks (gx[0] = 0)
+  std::vector<uint32_t> gs;      // group starts, size n_groups + 1
+  uint64_t q_off = 0, q_diag = 0;
+};
+
+int build_table(const qmc_ctx* c, const double* s, const double* g, HostTable& T,
+                std::string& why) {
+  std::vector<QTerm> q;
+  q.reserve(c->terms.size());
+  for (const SrcTerm& st : c->terms) {
+    const double w = st.weight_kind == 0 ? s[st.weight_index] : g[st.weight_index];
+    if (!std::isfinite(w)) {
+      why = "non-finite weight";
+      return QMC_ERR_ARG;
+    }
+    QTerm qt{st.xmask, st.zmask, 0, 0};
+    if (!quantize(c->cfg.dt, w, st.kre, qt.qre) || !quantize(c->cfg.dt, w, st.kim, qt.qim)) {
+      why = "coefficient too large for Q32";
+      return QMC_ERR_DT;
+    }
+    q.push_back(qt);
+  }
+  std::sort(q.begin(), q.end(), [](const QTerm& a, const QTerm& b) {
+    return a.xmask != b.xmask ? a.xmask < b.xmask : a.zmask < b.zmask;
+  });
+  T.t.clear();
+  for (size_t i = 0; i < q.size();) {
+    QTerm acc = q[i];
+    size_t j = i + 1;
+    for (; j < q.size() && q[j].xmask == acc.xmask && q[j].zmask == acc.zmask; ++j) {
+      acc.qre += q[j].qre;
+      acc.qim += q[j].qim;
+    }
+    if (acc.qre != 0 || acc.qim != 0) T.t.push_back(acc);
+    i = j;
+  }
+  T.gx.assign(1, 0);
+  T.gs.assign(1, 0);
+  for (size_t i = 0; i < T.t.size(); ++i) {
+    if (T.t[i].xmask == 0) continue;
+    if (i == 0 || T.t[i].xmask != T.t[i - 1].xmask) {
+      T.gs.push_back((uint32_t)i);
+      T.gx.push_back(T.t[i].xmask);
+    }
+  }
+  T.gs.push_back((uint32_t)T.t.size());
+  if (T.gx.size() - 1 > (size_t)qmc::kMaxGroups || T.t.size() > (size_t)qmc::kMaxTerms) {
+    why = "too many column groups or terms in one step table";
+    return QMC_ERR_ARG;
+  }
+  T.q_off = T.q_diag = 0;
+  for (size_t g2 = 0; g2 + 1 < T.gs.size(); ++g2) {
+    uint64_t sum = 0;
+    for (uint32_t i = T.gs[g2]; i < T.gs[g2 + 1]; ++i) sum += uabs(T.t[i].qre) + uabs(T.t[i].qim);
+    if (sum >= (1ull << 31)) {
+      why = "dt * |column group| >= 1/2: Q32 bound violated";
+      return QMC_ERR_DT;
+    }
+    if (g2 == 0)
+      T.q_diag = sum;
+    else
+      T.q_off += sum;
+  }
+  return QMC_OK;
+}
+
+size_t pack_table(const HostTable& T, uint8_t* dst) {
+  const uint32_t G = (uint32_t)T.gx.size(), NT = (uint32_t)T.t.size();
+  qmc::TableHeader h{};
+  h.n_groups = G;
+  h.n_terms = NT;
+  h.gx_off = (uint32_t)sizeof(qmc::TableHeader);
+  h.gs_off = h.gx_off + 8 * G;
+  h.t_off = (uint32_t)((h.gs_off + 4 * (G + 1) + 15) & ~15u);
+  h.bytes = (uint32_t)((h.t_off + sizeof(qmc::Term) * NT + 15) & ~15u);
+  h.q_off = T.q_off;
+  h.q_diag = T.q_diag;
+  if (!dst) return h.bytes;
+  std::memset(dst, 0, h.bytes);
+  std::memcpy(dst, &h, sizeof(h));
+  std::memcpy(dst + h.gx_off, T.gx.data(), 8 * G);
+  std::memcpy(dst + h.gs_off, T.gs.data(), 4 * (G + 1));
+  qmc::Term* tt = reinterpret_cast<qmc::Term*>(dst + h.t_off);
+  for (uint32_t i = 0; i < NT; ++i) {
+    tt[i].zmask = T.t[i].zmask;
+    tt[i].qre = (int32_t)T.t[i].qre;
+    tt[i].qim = (int32_t)T.t[i].qim;
+  }
+  return h.bytes;
+}
+
+int check_records(uint32_t n, const uint64_t* keys, const int32_t* re, const int32_t* im,
+                  uint64_t n0, std::string& why) {
+  const uint64_t kmask = n >= 32 ? ~0ull : ((1ull << (2 * n)) - 1);
+  for (uint64_t i = 0; i < n0; ++i) {
+    if (keys[i] & ~kmask) {
+      why = "key outside 2n bits";
+      return QMC_ERR_ARG;
+    }
+    if (i && keys[i] <= keys[i - 1]) {
+      why = "keys not sorted ascending and unique";
+      return QMC_ERR_ARG;
+    }
+    if (re[i] == 0 && im[i] == 0) {
+      why = "empty (0,0) record";
+      return QMC_ERR_ARG;
+    }
+  }
+  return QMC_OK;
+}
+
+int validate(const qmc_config* cfg, const qmc_model* m, std::string& why) {
+  if (!cfg || !m) {
+    why = "null config or model";
+    return QMC_ERR_ARG;
+  }
+  if (cfg->n_qubits < 1 || cfg->n_qubits > 32 || cfg->n_replicas < 1 ||
+      cfg->n_replicas >= (1u << 24)) {
+    why = "n_qubits must be 1..32 and n_replicas 1..2^24-1";
+    return QMC_ERR_ARG;
+  }
+  if (2 * cfg->n_qubits + replica_bits(cfg->n_replicas) > 64) {
+    why = "2n + ceil(log2 R) must not exceed 64";
+    return QMC_ERR_ARG;
+  }
+  if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) {
+    why = "dt must be positive and finite";
+    return QMC_ERR_ARG;
+  }
+  const uint64_t qmask = cfg->n_qubits >= 32 ? 0xFFFFFFFFull : ((1ull << cfg->n_qubits) - 1);
+  for (uint32_t i = 0; i < m->n_h; ++i)
+    if ((m->h[i].x | m->h[i].z) & ~qmask) {
+      why = "H monomial mask outside n bits";
+      return QMC_ERR_ARG;
+    }
+  if (m->n_l && !m->l_off) {
+    why = "missing l_off";
+    return QMC_ERR_ARG;
+  }
+  for (uint32_t k = 0; k < m->n_l; ++k)
+    if (m->l_off[k + 1] < m->l_off[k]) {
+      why = "l_off not monotone";
+      return QMC_ERR_ARG;
+    }
+  for (uint32_t a = 0; m->n_l && a < m->l_off[m->n_l]; ++a)
+    if ((m->l[a].x | m->l[a].z) & ~qmask) {
+      why = "L monomial mask outside n bits";
+      return QMC_ERR_ARG;
+    }
+  Layout L;
+  if (!compute_layout(*cfg, L)) {
+    why = "capacities must be nonzero and R*(store+spawn) < 2^31";
+    return QMC_ERR_ARG;
+  }
+  return QMC_OK;
+}
+
+// Upload the records of all replicas (sorted composite keys) into store buffer `b`.
+int upload_store(qmc_ctx* c, uint32_t b, const std::vector<uint64_t>& ck,
+                 const std::vector<int2>& cv) {
+  const uint64_t n = ck.size();
+  if (n > c->L.cap_store) return fail(c, QMC_ERR_STORE_CAP, "store capacity too small");
+  if (n) {
+    HIPCHK(c, hipMemcpyAsync(c->sk(b), ck.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->sv(b), cv.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(&c->counters()->n_store[b], &n, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return QMC_OK;
+}
+
+int download_store(qmc_ctx* c, std::vector<uint64_t>& ck, std::vector<int2>& cv) {
+  uint64_t n = 0;
+  HIPCHK(c, hipMemcpyAsync(&n, &c->counters()->n_store[c->cur], 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  ck.resize(n);
+  cv.resize(n);
+  if (n) {
+    HIPCHK(c, hipMemcpyAsync(ck.data(), c->sk(c->cur), n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cv.data(), c->sv(c->cur), n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return QMC_OK;
+}
+
+int read_counters(qmc_ctx* c, qmc::Counters& out) {
+  HIPCHK(c, hipMemcpyAsync(c->pinned_small, c->counters(), sizeof(qmc::Counters),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(&out, c->pinned_small, sizeof(out));
+  return QMC_OK;
+}
+
+int upload_qshift(qmc_ctx* c, const std::vector<int64_t>& qs) {
+  std::memcpy(c->pinned_small, qs.data(), qs.size() * 8);
+  HIPCHK(c, hipMemcpyAsync(c->at<int64_t>(c->L.qshift), c->pinned_small, qs.size() * 8,
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return QMC_OK;
+}
+
+int shifts_q32(const qmc_ctx* c, std::vector<int64_t>& qs) {
+  qs.resize(c->R);
+  for (uint32_t r = 0; r < c->R; ++r)
+    if (!quantize(c->cfg.dt, 1.0, c->shift[r], qs[r])) return QMC_ERR_DT;
+  return QMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qmc_workspace_bytes(const qmc_config* cfg, const qmc_model* model, size_t* bytes) {
+  std::string why;
+  int rc = validate(cfg, model, why);
+  if (rc) return rc;
+  Layout L;
+  compute_layout(*cfg, L);
+  if (bytes) *bytes = L.total;
+  return QMC_OK;
+}
+
+int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys,
+             const int32_t* re, const int32_t* im, uint64_t n0, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, qmc_ctx** out) {
+  static thread_local std::string g_why;
+  if (!out) return QMC_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  int rc = validate(cfg, model, why);
+  if (!rc) rc = check_records(cfg->n_qubits, keys, re, im, n0, why);
+  if (rc) return rc;
+  if (n0 > cfg->store_capacity) return QMC_ERR_ARG;
+  qmc_ctx* c = new qmc_ctx();
+  c->cfg = *cfg;
+  c->n = cfg->n_qubits;
+  c->R = cfg->n_replicas;
+  c->kbits = 2 * c->n;
+  c->rbits = replica_bits(c->R);
+  c->n_h = model->n_h;
+  c->n_l = model->n_l;
+  compute_layout(*cfg, c->L);
+  if (!d_workspace || ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) {
+    delete c;
+    return QMC_ERR_ARG;
+  }
+  c->ws = (uint8_t*)d_workspace;
+  c->stream = (hipStream_t)hip_stream;
+  compile_model(*model, c->n, c->terms);
+  c->shift.assign(c->R, 0.0);
+  int64_t nd = 0;
+  for (uint64_t i = 0; i < n0; ++i) {
+    const uint64_t ket = keys[i] & ((c->n >= 32) ? 0xFFFFFFFFull : ((1ull << c->n) - 1));
+    const uint64_t bra = c->n >= 32 ? keys[i] >> 32 : keys[i] >> c->n;
+    if (ket == bra) nd += re[i];
+  }
+  c->nd0_re.assign(c->R, nd);
+  hipError_t e = hipHostMalloc((void**)&c->pinned, kTableArea, hipHostMallocDefault);
+  c->pinned_small_bytes = std::max<size_t>(1 << 16, (size_t)c->R * kMaxLookup * 16 + 4096);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->pinned_small, c->pinned_small_bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    qmc_destroy(c);
+    return QMC_ERR_HIP;
+  }
+  // zero counters, then the initial store (replica tag in the high bits)
+  e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
+  if (e != hipSuccess) {
+    qmc_destroy(c);
+    return QMC_ERR_HIP;
+  }
+  std::vector<uint64_t> ck;
+  std::vector<int2> cv;
+  ck.reserve(n0 * c->R);
+  cv.reserve(n0 * c->R);
+  for (uint32_t r = 0; r < c->R; ++r)
+    for (uint64_t i = 0; i < n0; ++i) {
+      ck.push_back((c->kbits >= 64 ? 0 : ((uint64_t)r << c->kbits)) | keys[i]);
+      cv.push_back(make_int2(re[i], im[i]));
+    }
+  c->cur = 0;
+  rc = upload_store(c, 0, ck, cv);
+  if (!rc) {
+    std::vector<int64_t> qs(c->R, 0);
+    rc = upload_qshift(c, qs);
+  }
+  if (rc) {
+    g_why = c->err;
+    qmc_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return QMC_OK;
+}
+
+int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) {
+  if (!c) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (nsteps == 0) return QMC_OK;
+  if ((c->n_h && !s) || (c->n_l && !gamma)) return fail(c, QMC_ERR_ARG, "missing weights");
+  std::vector<int64_t> qs;
+  if (shifts_q32(c, qs)) return fail(c, QMC_ERR_DT, "shift too large for Q32");
+  uint64_t max_qs = 0;
+  for (int64_t v : qs) max_qs = std::max(max_qs, uabs(v));
+
+  // Build and check every table of the batch before launching anything.
+  std::vector<HostTable> tabs(nsteps);
+  for (uint32_t k = 0; k < nsteps; ++k) {
+    std::string why;
+    int rc = build_table(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, tabs[k], why);
+    if (rc) return fail(c, rc, "step " + std::to_string(c->step + k) + ": " + why);
+    if (tabs[k].q_diag + max_qs >= (1ull << 31))
+      return fail(c, QMC_ERR_DT, "diagonal group with shift violates the Q32 bound");
+  }
+  const uint32_t kbits = c->kbits;
+  const uint32_t sort_bits = c->kbits + c->rbits;
+  qmc::Counters* dcnt = c->counters();
+  uint32_t k0 = 0;
+  while (k0 < nsteps) {
+    // chunk: as many steps as fit the table area
+    size_t bytes = 0;
+    uint32_t k1 = k0;
+    std::vector<size_t> offs;
+    while (k1 < nsteps && k1 - k0 < kMaxChunkSteps) {
+      size_t b = pack_table(tabs[k1], nullptr);
+      if (bytes + b > kTableArea) break;
+      offs.push_back(bytes);
+      bytes += b;
+      ++k1;
+    }
+    if (k1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
+    for (uint32_t k = k0; k < k1; ++k) pack_table(tabs[k], c->pinned + offs[k - k0]);
+    uint8_t* dtab = c->at<uint8_t>(c->L.tab);
+    HIPCHK(c, hipMemcpyAsync(dtab, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
+    const uint32_t step0 = c->step, cur0 = c->cur;
+    HIPCHK(c, qmck_batch_begin(c->stream, dcnt, step0, c->at<uint64_t>(c->L.status),
+                               c->L.max_tiles));
+    uint32_t cur = cur0;
+    const uint32_t nev = 2 * (k1 - k0);
+    if (c->prof_class >= 0) {
+      while (c->prof_ev.size() < nev) {
+        hipEvent_t ev;
+        HIPCHK(c, hipEventCreate(&ev));
+        c->prof_ev.push_back(ev);
+      }
+    }
+    auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
+      if (c->prof_class != cls) return hipSuccess;
+      return hipEventRecord(c->prof_ev[2 * (k - k0) + which], c->stream);
+    };
+    for (uint32_t k = k0; k < k1; ++k) {
+      const uint32_t st = c->step + (k - k0);
+      const uint8_t* tab = dtab + offs[k - k0];
+      const uint32_t csel = st & 1;
+      HIPCHK(c, mark(0, k, 0));
+      HIPCHK(c, qmck_spawn(c->stream, c->sk(cur), c->sv(cur), dcnt, cur, tab, st, c->cfg.seed,
+                           kbits, c->ck(0), c->cv(0), c->L.cap_child, c->L.cap_store));
+      HIPCHK(c, mark(0, k, 1));
+      int second = 0;
+      HIPCHK(c, mark(1, k, 0));
+      HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel,
+                          sort_bits, c->at<uint32_t>(c->L.hist), &second));
+      HIPCHK(c, mark(1, k, 1));
+      HIPCHK(c, mark(2, k, 0));
+      HIPCHK(c, qmck_merge(c->stream, c->sk(cur), c->sv(cur), c->ck(second), c->cv(second), dcnt,
+                           cur, csel, c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status),
+                           (st + 1) & 0xFFFFu, tab, c->at<int64_t>(c->L.qshift), st, c->cfg.seed,
+                           kbits, c->sk(cur ^ 1), c->sv(cur ^ 1), c->L.cap_store,
+                           c->L.cap_store + c->L.cap_child));
+      HIPCHK(c, mark(2, k, 1));
+      cur ^= 1;
+    }
+    qmc::Counters hc;
+    int rc = read_counters(c, hc);
+    if (rc) return rc;
+    if (c->prof_class >= 0) {
+      for (uint32_t k = k0; k < k1; ++k) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * (k - k0)], c->prof_ev[2 * (k - k0) + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+      }
+    }
+    if (hc.err) {
+      const uint32_t es = hc.err_step;
+      if (es < step0 || es >= step0 + (k1 - k0)) {
+        c->broken = true;
+        return fail(c, QMC_ERR_HIP, "device error flag without a valid step");
+      }
+      c->step = es;
+      c->cur = cur0 ^ ((es - step0) & 1);
+      if (hc.err & qmc::kErrLookback) {
+        c->broken = true;
+        return fail(c, QMC_ERR_HIP, "merge look-back did not complete");
+      }
+      if (hc.err & qmc::kErrOverflow)
+        return fail(c, QMC_ERR_COUNT_OVERFLOW,
+                    "step " + std::to_string(es) + ": population outside int32");
+      if (hc.err & qmc::kErrSpawnCap)
+        return fail(c, QMC_ERR_SPAWN_CAP,
+                    "step " + std::to_string(es) + ": spawn capacity exceeded");
+      return fail(c, QMC_ERR_STORE_CAP, "step " + std::to_string(es) + ": store capacity exceeded");
+    }
+    c->step = step0 + (k1 - k0);
+    c->cur = cur;
+    k0 = k1;
+  }
+  return QMC_OK;
+}
+
+int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
+  if (!c) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  const uint64_t qmask = c->n >= 32 ? 0xFFFFFFFFull : ((1ull << c->n) - 1);
+  if ((x | z) & ~qmask) return fail(c, QMC_ERR_ARG, "pulse mask outside n bits");
+  qmc::Counters* dcnt = c->counters();
+  if (x != 0) {
+    qmc::Counters hc0;
+    int rc0 = read_counters(c, hc0);
+    if (rc0) return rc0;
+    if (hc0.n_store[c->cur] > c->L.cap_child)
+      return fail(c, QMC_ERR_SPAWN_CAP, "a pulse with x != 0 re-sorts the store through the "
+                                        "child buffers, which are smaller than the store");
+  }
+  HIPCHK(c, qmck_batch_begin(c->stream, dcnt, c->step, c->at<uint64_t>(c->L.status), 0));
+  HIPCHK(c, qmck_pulse(c->stream, c->sk(c->cur), c->sv(c->cur), dcnt, c->cur, c->n, x, z,
+                       c->ck(0), c->cv(0), 0, c->L.cap_store));
+  if (x != 0) {
+    int second = 0;
+    HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, 0,
+                        c->kbits + c->rbits, c->at<uint32_t>(c->L.hist), &second));
+    HIPCHK(c, qmck_copy_store(c->stream, c->ck(second), c->cv(second), c->sk(c->cur),
+                              c->sv(c->cur), dcnt, 0, c->L.cap_store));
+  }
+  qmc::Counters hc;
+  int rc = read_counters(c, hc);
+  if (rc) return rc;
+  if (hc.err & qmc::kErrOverflow)
+    return fail(c, QMC_ERR_COUNT_OVERFLOW, "pulse negated INT32_MIN");
+  return QMC_OK;
+}
+
+int qmc_set_shift(qmc_ctx* c, uint32_t replica, double shift) {
+  if (!c || replica >= c->R || !std::isfinite(shift)) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  c->shift[replica] = shift;
+  std::vector<int64_t> qs;
+  if (shifts_q32(c, qs)) return fail(c, QMC_ERR_DT, "shift too large for Q32");
+  return upload_qshift(c, qs);
+}
+
+int qmc_observe(qmc_ctx* c, const qmc_obs_spec* spec, qmc_obs_out* out) {
+  if (!c || !spec || !out) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (spec->n_pauli > kMaxPauli) return fail(c, QMC_ERR_ARG, "too many Pauli observables");
+  const uint64_t nlook = (uint64_t)spec->n_psi * spec->n_psi;
+  if (nlook > kMaxLookup) return fail(c, QMC_ERR_ARG, "|psi| support too large");
+  const uint32_t R = c->R, NPl = spec->n_pauli;
+  const uint32_t stride = 5 + 2 * NPl;
+  std::vector<uint64_t> pxz(2 * (size_t)std::max<uint32_t>(NPl, 1), 0);
+  for (uint32_t k = 0; k < NPl; ++k) {
+    pxz[2 * k] = spec->px[k];
+    pxz[2 * k + 1] = spec->pz[k];
+  }
+  unsigned long long* dout = c->at<unsigned long long>(c->L.obs_out);
+  HIPCHK(c, hipMemsetAsync(dout, 0, (size_t)R * stride * 8, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->at<uint64_t>(c->L.obs_in), pxz.data(), pxz.size() * 8,
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, qmck_observe(c->stream, c->sk(c->cur), c->sv(c->cur), c->counters(), c->cur, c->n,
+                         c->kbits, R, NPl, c->at<uint64_t>(c->L.obs_in), spec->want_eps ? 1 : 0,
+                         dout, stride, c->cfg.store_capacity));
+  std::vector<unsigned long long> acc((size_t)R * stride);
+  HIPCHK(c, hipMemcpyAsync(acc.data(), dout, acc.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  std::vector<int64_t> look;
+  std::vector<uint64_t> lk;
+  if (nlook) {
+    for (uint32_t u = 0; u < spec->n_psi; ++u)
+      for (uint32_t v = 0; v < spec->n_psi; ++v)
+        lk.push_back((spec->psi_index[v] << c->n) | spec->psi_index[u]);
+    HIPCHK(c, hipMemcpyAsync(c->at<uint64_t>(c->L.look_keys), lk.data(), lk.size() * 8,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, qmck_lookup(c->stream, c->sk(c->cur), c->sv(c->cur), c->counters(), c->cur,
+                          c->kbits, c->at<uint64_t>(c->L.look_keys), (uint32_t)nlook, R,
+                          c->at<int64_t>(c->L.look_out)));
+    look.resize((size_t)R * nlook * 2);
+    HIPCHK(c, hipMemcpyAsync(look.data(), c->at<int64_t>(c->L.look_out), look.size() * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  // per-replica occupied counts from the segment bounds
+  std::vector<uint64_t> bounds(R + 1, 0);
+  {
+    std::vector<uint64_t> ck;
+    std::vector<int2> cv;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint64_t n = 0;
+    HIPCHK(c, hipMemcpy(&n, &c->counters()->n_store[c->cur], 8, hipMemcpyDeviceToHost));
+    bounds[R] = n;
+    // binary search of each replica's first key over device memory
+    for (uint32_t r = 1; r < R; ++r) {
+      const uint64_t target = (uint64_t)r << c->kbits;
+      uint64_t lo = 0, hi = n;
+      while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2, v = 0;
+        HIPCHK(c, hipMemcpy(&v, c->sk(c->cur) + mid, 8, hipMemcpyDeviceToHost));
+        if (v < target)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      bounds[r] = lo;
+    }
+  }
+  for (uint32_t r = 0; r < R; ++r) {
+    const unsigned long long* a = acc.data() + (size_t)r * stride;
+    const double nd0 = (double)c->nd0_re[r];
+    if (out->n_occ) out->n_occ[r] = bounds[r + 1] - bounds[r];
+    if (out->n_tot) out->n_tot[r] = a[0];
+    const int64_t dre = (int64_t)a[1], dim = (int64_t)a[2];
+    if (out->ndiag) {
+      out->ndiag[2 * r] = dre;
+      out->ndiag[2 * r + 1] = dim;
+    }
+    if (out->trace) out->trace[r] = (double)dre / nd0;
+    if (out->theta) out->theta[r] = std::atan2((double)dim, (double)dre);
+    for (uint32_t k = 0; k < NPl; ++k) {
+      const int64_t pre = (int64_t)a[5 + 2 * k], pim = (int64_t)a[6 + 2 * k];
+      if (out->pauli) {
+        out->pauli[((size_t)r * NPl + k) * 2] = pre;
+        out->pauli[((size_t)r * NPl + k) * 2 + 1] = pim;
+      }
+      if (out->pauli_val) {
+        out->pauli_val[((size_t)r * NPl + k) * 2] = (double)pre / nd0;
+        out->pauli_val[((size_t)r * NPl + k) * 2 + 1] = (double)pim / nd0;
+      }
+    }
+    if (out->eps2) {
+      out->eps2[2 * r] = a[3];
+      out->eps2[2 * r + 1] = a[4];
+    }
+    if (out->eps)
+      out->eps[r] = std::sqrt((double)a[4] * 18446744073709551616.0 + (double)a[3]) / nd0;
+    if (out->fidelity) {
+      double fre = 0.0, fim = 0.0;
+      if (nlook) {
+        size_t idx = 0;
+        for (uint32_t u = 0; u < spec->n_psi; ++u)
+          for (uint32_t v = 0; v < spec->n_psi; ++v, ++idx) {
+            const double ur = spec->psi_re[u], ui = spec->psi_im[u];
+            const double vr = spec->psi_re[v], vi = spec->psi_im[v];
+            const double pr = ur * vr + ui * vi, pi = ur * vi - ui * vr;
+            const double A = (double)look[((size_t)r * nlook + idx) * 2];
+            const double B = (double)look[((size_t)r * nlook + idx) * 2 + 1];
+            fre += pr * A - pi * B;
+            fim += pr * B + pi * A;
+          }
+      }
+      out->fidelity[2 * r] = fre / nd0;
+      out->fidelity[2 * r + 1] = fim / nd0;
+    }
+  }
+  return QMC_OK;
+}
+
+int qmc_export(qmc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+               uint64_t cap, uint64_t* n) {
+  if (!c || replica >= c->R || !n) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  std::vector<uint64_t> ck;
+  std::vector<int2> cv;
+  int rc = download_store(c, ck, cv);
+  if (rc) return rc;
+  const uint64_t lo = c->kbits >= 64 ? 0 : (uint64_t)replica << c->kbits;
+  const uint64_t hi = c->kbits >= 64 ? ~0ull : (((uint64_t)replica + 1) << c->kbits) - 1;
+  auto b = std::lower_bound(ck.begin(), ck.end(), lo);
+  auto e = std::upper_bound(ck.begin(), ck.end(), hi);
+  const uint64_t m = (uint64_t)(e - b);
+  *n = m;
+  if (m > cap) return fail(c, QMC_ERR_ARG, "export capacity too small");
+  const uint64_t kmask = c->kbits >= 64 ? ~0ull : ((1ull << c->kbits) - 1);
+  const size_t off = (size_t)(b - ck.begin());
+  for (uint64_t i = 0; i < m; ++i) {
+    keys[i] = ck[off + i] & kmask;
+    re[i] = cv[off + i].x;
+    im[i] = cv[off + i].y;
+  }
+  return QMC_OK;
+}
+
+int qmc_import(qmc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+               const int32_t* im, uint64_t n, uint32_t step) {
+  if (!c || replica >= c->R) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  std::string why;
+  int rc = check_records(c->n, keys, re, im, n, why);
+  if (rc) return fail(c, rc, why);
+  if (n > c->cfg.store_capacity) return fail(c, QMC_ERR_ARG, "more records than store capacity");
+  std::vector<uint64_t> ck;
+  std::vector<int2> cv;
+  rc = download_store(c, ck, cv);
+  if (rc) return rc;
+  const uint64_t tag = c->kbits >= 64 ? 0 : (uint64_t)replica << c->kbits;
+  const uint64_t lo = tag;
+  const uint64_t hi = c->kbits >= 64 ? ~0ull : (((uint64_t)replica + 1) << c->kbits) - 1;
+  const size_t b = (size_t)(std::lower_bound(ck.begin(), ck.end(), lo) - ck.begin());
+  const size_t e = (size_t)(std::upper_bound(ck.begin(), ck.end(), hi) - ck.begin());
+  std::vector<uint64_t> nk(ck.begin(), ck.begin() + b);
+  std::vector<int2> nv(cv.begin(), cv.begin() + b);
+  for (uint64_t i = 0; i < n; ++i) {
+    nk.push_back(tag | keys[i]);
+    nv.push_back(make_int2(re[i], im[i]));
+  }
+  nk.insert(nk.end(), ck.begin() + e, ck.end());
+  nv.insert(nv.end(), cv.begin() + e, cv.end());
+  rc = upload_store(c, c->cur, nk, nv);
+  if (rc) return rc;
+  c->step = step;
+  return QMC_OK;
+}
+
+int qmc_counters(qmc_ctx* c, qmc_stats* out) {
+  if (!c || !out) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  qmc::Counters hc;
+  int rc = read_counters(c, hc);
+  if (rc) return rc;
+  out->step = c->step;
+  out->n_occ_total = hc.n_store[c->cur];
+  out->walker_steps = hc.walker_steps;
+  out->key_steps = hc.key_steps;
+  out->child_steps = hc.child_steps;
+  out->out_steps = hc.out_steps;
+  return QMC_OK;
+}
+
+int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
+  if (!c || kernel_class < -1 || kernel_class > 2) return QMC_ERR_ARG;
+  c->prof_class = kernel_class;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  return QMC_OK;
+}
+
+int qmc_profile_read(qmc_ctx* c, double* ms, uint64_t* launches) {
+  if (!c) return QMC_ERR_ARG;
+  if (ms) *ms = c->prof_ms;
+  if (launches) *launches = c->prof_launches;
+  return QMC_OK;
+}
+
+int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double* s,
+                    const double* gamma, uint32_t cap_groups, uint32_t cap_terms,
+                    uint32_t* n_groups, uint64_t* gxmask, uint32_t* gstart, uint32_t* n_terms,
+                    uint64_t* tzmask, int64_t* tq) {
+  std::string why;
+  int rc = validate(cfg, model, why);
+  if (rc) return rc;
+  qmc_ctx tmp;
+  tmp.cfg = *cfg;
+  tmp.n = cfg->n_qubits;
+  compile_model(*model, tmp.n, tmp.terms);
+  HostTable T;
+  rc = build_table(&tmp, s, gamma, T, why);
+  if (rc) return rc;
+  *n_groups = (uint32_t)T.gx.size();
+  *n_terms = (uint32_t)T.t.size();
+  if (T.gx.size() > cap_groups || T.t.size() > cap_terms) return QMC_ERR_ARG;
+  for (size_t g = 0; g < T.gx.size(); ++g) {
+    gxmask[g] = T.gx[g];
+    gstart[g] = T.gs[g];
+  }
+  gstart[T.gx.size()] = T.gs.back();
+  for (size_t i = 0; i < T.t.size(); ++i) {
+    tzmask[i] = T.t[i].zmask;
+    tq[2 * i] = T.t[i].qre;
+    tq[2 * i + 1] = T.t[i].qim;
+  }
+  return QMC_OK;
+}
+
+const char* qmc_last_error(const qmc_ctx* c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+void qmc_destroy(qmc_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pinned_small) (void)hipHostFree(c->pinned_small);
+  delete c;
+}
+
+}  // extern "C"

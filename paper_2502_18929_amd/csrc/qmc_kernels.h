@@ -1,0 +1,32 @@
+// qmc_kernels.h -- host-callable launch wrappers of the HIP kernels in qmc_kernels.hip.
+// Every wrapper enqueues on the given stream and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+extern "C" {
+int qmck_batch_begin(hipStream_t st, void* counters, uint32_t step, uint64_t* status,
+                     uint32_t n_status);
+int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
+               const uint8_t* tab, uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ck,
+               int2* cv, uint64_t cap_child, uint64_t max_parents);
+int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
+              uint32_t nsel, uint32_t key_bits, uint32_t* hist, int* in_second);
+int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
+               const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
+               uint64_t* status, uint32_t epoch, const uint8_t* tab, const int64_t* qshift,
+               uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok, int2* ov,
+               uint64_t cap_store, uint64_t max_items);
+int qmck_reset_child(hipStream_t st, void* counters, uint32_t sel);
+int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t cur, uint32_t n,
+               uint64_t x, uint64_t z, uint64_t* ck, int2* cv, uint32_t csel,
+               uint64_t max_parents);
+int qmck_copy_store(hipStream_t st, const uint64_t* ki, const int2* vi, uint64_t* ko, int2* vo,
+                    void* counters, uint32_t csel, uint64_t max_items);
+int qmck_observe(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
+                 uint32_t n, uint32_t kbits, uint32_t nrep, uint32_t n_pauli, const uint64_t* pxz,
+                 uint32_t want_eps, unsigned long long* out, uint32_t out_stride,
+                 uint64_t max_per_replica);
+int qmck_lookup(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
+                uint32_t kbits, const uint64_t* keys, uint32_t nk, uint32_t nrep, int64_t* out);
+}

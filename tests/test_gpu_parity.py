@@ -1,0 +1,302 @@
+"""GPU parity: the HIP step through the C ABI against the CPU oracle, bit for bit.
+
+Every comparison is of whole per-replica stores (sorted keys, int32 re, int32 im) after a step
+or a batch of steps, on seeded synthetic inputs; both sides run their own trajectories from the
+same initial records (nothing flows from the GPU into the oracle).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2502_18929_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_18929_amd import binding
+    binding.lib()
+    return binding
+
+
+def _pair(B, orc, w, R=None, store=None, spawn=None, seed=None):
+    R = w.n_replicas if R is None else R
+    seed = w.seed if seed is None else seed
+    g = B.QMC.from_workload(w, store_capacity=store, spawn_capacity=spawn, n_replicas=R,
+                            seed=seed)
+    o = orc.Oracle(w.n, R, seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    return g, o
+
+
+def _assert_same(g, o, R, where=""):
+    for r in range(R):
+        gk, ga, gb = g.export(r)
+        ok, oa, ob = o.export(r)
+        if not (np.array_equal(gk, ok) and np.array_equal(ga, oa) and np.array_equal(gb, ob)):
+            n = min(len(gk), len(ok))
+            bad = np.nonzero((gk[:n] != ok[:n]) | (ga[:n] != oa[:n]) | (gb[:n] != ob[:n]))[0]
+            first = int(bad[0]) if len(bad) else n
+            raise AssertionError(f"{where} replica {r}: sizes gpu {len(gk)} oracle {len(ok)}, "
+                                 f"first difference at {first}: gpu "
+                                 f"{(gk[first:first+1], ga[first:first+1], gb[first:first+1])} "
+                                 f"oracle {(ok[first:first+1], oa[first:first+1], ob[first:first+1])}")
+
+
+def _run_both(g, o, w, start, stop, threads=1):
+    for a, b, pulses in w.segments():
+        if b <= start or a >= stop:
+            continue
+        if a >= start:
+            for (px, pz) in pulses:
+                g.pulse(px, pz)
+                o.pulse(px, pz)
+        lo, hi = max(a, start), min(b, stop)
+        g.step(w.s[lo:hi], w.gamma[lo:hi])
+        o.step(w.s[lo:hi], w.gamma[lo:hi], threads=threads)
+
+
+# ---- small random models: every step, several replicas --------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_models_every_step(B, orc, seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 5))
+    h, lops = W.random_model(n, rng, n_h=int(rng.integers(1, 6)), n_l=int(rng.integers(0, 4)))
+    keys, re, im = W.random_records(n, rng, int(rng.integers(1, 12)), scale=3000)
+    R = int(rng.integers(1, 5))
+    dt = 0.01
+    _say(f"random model seed={seed} n={n} R={R} keys={len(keys)}")
+    g = B.QMC(n, R, 1000 + seed, dt, h, lops, keys, re, im, store_capacity=1 << (2 * n),
+              spawn_capacity=4096)
+    o = orc.Oracle(n, R, 1000 + seed, dt, h, lops, keys, re, im)
+    s = rng.normal(size=(40, len(h))) * 0.5
+    gam = np.abs(rng.normal(size=(40, len(lops)))) * 0.5
+    for k in range(40):
+        g.step(s[k:k + 1], gam[k:k + 1])
+        o.step(s[k:k + 1], gam[k:k + 1])
+        _assert_same(g, o, R, f"step {k}")
+
+
+def test_ghz4_full_trajectory(B, orc):
+    w = W.config_ghz4()
+    _say(f"{w.name}: {w.nsteps} steps x {w.n_replicas} replicas")
+    g, o = _pair(B, orc, w, store=256, spawn=4096)
+    for k0 in range(0, w.nsteps, 20):
+        _run_both(g, o, w, k0, k0 + 20)
+        _assert_same(g, o, w.n_replicas, f"step {k0 + 20}")
+    c = g.counters()
+    assert c["step"] == w.nsteps
+
+
+def test_multi_tile_ragged_one_step(B, orc):
+    """Thousands of keys spread over many merge tiles and a ragged tail."""
+    rng = np.random.default_rng(9)
+    n = 7
+    h, lops = W.random_model(n, rng, n_h=6, n_l=3)
+    for count in (1, 1023, 1024, 1025, 5000, 12289):
+        keys, re, im = W.random_records(n, rng, count, scale=200)
+        R = 3
+        _say(f"multi-tile one step: {count} keys x {R} replicas")
+        g = B.QMC(n, R, 7, 0.01, h, lops, keys, re, im, store_capacity=1 << 14,
+                  spawn_capacity=1 << 20)
+        o = orc.Oracle(n, R, 7, 0.01, h, lops, keys, re, im)
+        s = rng.normal(size=(3, len(h)))
+        gam = np.abs(rng.normal(size=(3, len(lops))))
+        for k in range(3):
+            g.step(s[k:k + 1], gam[k:k + 1])
+            o.step(s[k:k + 1], gam[k:k + 1])
+            _assert_same(g, o, R, f"count {count} step {k}")
+        g.close()
+
+
+def test_dd_small_with_pulses(B, orc):
+    w = W.dd(n=6, n_replicas=4, walker_target=20000, nsteps=800, seed=11)
+    _say(f"dd n=6: {w.nsteps} steps with ideal pulses")
+    g, o = _pair(B, orc, w, store=4096, spawn=1 << 16)
+    for k0 in range(0, w.nsteps, 100):
+        _run_both(g, o, w, k0, k0 + 100)
+        _assert_same(g, o, w.n_replicas, f"step {k0 + 100}")
+
+
+def test_general_pauli_pulse_resorts(B, orc):
+    rng = np.random.default_rng(4)
+    n = 5
+    keys, re, im = W.random_records(n, rng, 300, scale=1000)
+    g = B.QMC(n, 2, 1, 0.01, [], [], keys, re, im, store_capacity=1024, spawn_capacity=1024)
+    o = orc.Oracle(n, 2, 1, 0.01, [], [], keys, re, im)
+    for x, z in [(0, 3), (5, 0), (31, 17), (1, 1)]:
+        g.pulse(x, z)
+        o.pulse(x, z)
+        _assert_same(g, o, 2, f"pulse {x},{z}")
+
+
+# ---- the three configurations at full size ---------------------------------------------------
+
+def test_ghz20_nm_full_size(B, orc):
+    """n=20 non-Markovian GHZ, 8 replicas x 1e7 walkers, all 3000 steps (the benchmarked
+    workload, same launch configuration), every replica compared every 250 steps."""
+    w = W.config_ghz20_nm()
+    _say(f"{w.name}: full size {w.nsteps} steps x {w.n_replicas} replicas")
+    g, o = _pair(B, orc, w, store=1 << 17, spawn=1 << 19)
+    t0 = time.time()
+    for k0 in range(0, w.nsteps, 250):
+        g.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250])
+        o.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250], threads=16)
+        _assert_same(g, o, w.n_replicas, f"step {k0 + 250}")
+        _say(f"  step {k0 + 250} equal ({time.time() - t0:.1f}s)")
+
+
+def test_dd12_full_size_first_steps(B, orc):
+    """n=12 DD at full size (16 replicas x 1e6 walkers) over the first 600 steps (five pulse
+    times), every replica against the oracle."""
+    w = W.config_dd12()
+    _say(f"{w.name}: 16 replicas, first 600 steps")
+    g = B.QMC.from_workload(w, store_capacity=1 << 20, spawn_capacity=1 << 18)
+    o = orc.Oracle(w.n, 16, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    _run_both(g, o, w, 0, 600, threads=16)
+    _assert_same(g, o, 16, "step 600")
+
+
+# ---- estimators ------------------------------------------------------------------------------
+
+def test_observe_matches_oracle(B, orc):
+    w = W.config_ghz4()
+    g, o = _pair(B, orc, w, store=256, spawn=4096)
+    _run_both(g, o, w, 0, 260)
+    pauli = [(x, z) for _, x, z, _ in w.pauli_obs] + [(3, 5), (15, 15), (0, 0)]
+    got = g.observe(pauli=pauli, psi=w.psi, want_eps=True)
+    lk = [(v << w.n) | u for u, _ in w.psi for v, _ in w.psi]
+    for r in range(w.n_replicas):
+        ref = o.observe(r, pauli, lk)
+        assert int(got["n_occ"][r]) == ref["n_occ"]
+        assert int(got["n_tot"][r]) == ref["n_tot"]
+        assert tuple(got["ndiag"][r]) == ref["ndiag_int"]
+        assert np.array_equal(got["pauli"][r], ref["pauli"])
+        assert got["eps2_int"][r] == ref["eps2"]
+        nd0 = float(w.walker_target)
+        F = 0.0
+        idx = 0
+        for u, au in w.psi:
+            for v, av in w.psi:
+                F += (np.conj(au) * av * complex(*ref["lookup"][idx])).real
+                idx += 1
+        assert abs(got["fidelity"][r, 0] - F / nd0) < 1e-12
+        assert got["trace"][r] == ref["ndiag_int"][0] / nd0
+
+
+# ---- invariances and failure handling --------------------------------------------------------
+
+def test_replica_count_invariance(B, orc):
+    w = W.config_ghz4()
+    a = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096, n_replicas=2)
+    b = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096, n_replicas=7)
+    a.step(w.s[:200], w.gamma[:200])
+    b.step(w.s[:200], w.gamma[:200])
+    for r in range(2):
+        for x, y in zip(a.export(r), b.export(r)):
+            assert np.array_equal(x, y)
+
+
+def test_export_import_resume(B, orc):
+    w = W.config_ghz4()
+    a = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    a.step(w.s[:300], w.gamma[:300])
+    b = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    b.step(w.s[:150], w.gamma[:150])
+    c = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    for r in range(w.n_replicas):
+        c.import_(r, *b.export(r), step=150)
+    c.step(w.s[150:300], w.gamma[150:300])
+    for r in range(w.n_replicas):
+        for x, y in zip(a.export(r), c.export(r)):
+            assert np.array_equal(x, y)
+
+
+def test_empty_replica_stays_empty(B, orc):
+    w = W.config_ghz4()
+    g, o = _pair(B, orc, w, store=256, spawn=4096)
+    e = np.zeros(0, np.uint64), np.zeros(0, np.int32), np.zeros(0, np.int32)
+    g.import_(1, *e, step=0)
+    o.import_(1, *e, step=0)
+    _run_both(g, o, w, 0, 120)
+    _assert_same(g, o, w.n_replicas, "empty replica")
+    assert len(g.export(1)[0]) == 0
+
+
+def test_spawn_capacity_error_rolls_back(B, orc):
+    w = W.config_ghz4()
+    g = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=2)
+    with pytest.raises(B.QMCError) as e:
+        g.step(w.s[:50], w.gamma[:50])
+    assert e.value.code == B.QMC_ERR_SPAWN_CAP
+    st = g.counters()["step"]
+    snap = [g.export(r) for r in range(w.n_replicas)]
+    # retry that step with enough capacity: identical to an uninterrupted run
+    big = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    for r in range(w.n_replicas):
+        big.import_(r, *snap[r], step=st)
+    big.step(w.s[st:60], w.gamma[st:60])
+    ref = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    ref.step(w.s[:60], w.gamma[:60])
+    for r in range(w.n_replicas):
+        for x, y in zip(big.export(r), ref.export(r)):
+            assert np.array_equal(x, y)
+
+
+def test_store_capacity_error(B, orc):
+    w = W.config_ghz4()
+    g = B.QMC.from_workload(w, store_capacity=3, spawn_capacity=4096)
+    with pytest.raises(B.QMCError) as e:
+        g.step(w.s[:400], w.gamma[:400])
+    assert e.value.code == B.QMC_ERR_STORE_CAP
+    st = g.counters()["step"]
+    o = orc.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
+                   w.init_im)
+    o.step(w.s[:st], w.gamma[:st])
+    _assert_same(g, o, w.n_replicas, "rolled back")
+
+
+def test_count_overflow_error(B, orc):
+    g = B.QMC(1, 1, 1, 0.01, [], [], [0], [2_000_000_000], [0], store_capacity=4,
+              spawn_capacity=4)
+    g.set_shift(0, 20.0)
+    with pytest.raises(B.QMCError) as e:
+        g.step(np.zeros((1, 0)), np.zeros((1, 0)))
+    assert e.value.code == B.QMC_ERR_COUNT_OVERFLOW
+    k, a, b = g.export(0)
+    assert a[0] == 2_000_000_000 and g.counters()["step"] == 0
+
+
+def test_shift_matches_oracle(B, orc):
+    w = W.config_ghz4()
+    g, o = _pair(B, orc, w, store=256, spawn=4096)
+    for r in range(w.n_replicas):
+        g.set_shift(r, 0.3 * (r - 1.5))
+        o.set_shift(r, 0.3 * (r - 1.5))
+    _run_both(g, o, w, 0, 100)
+    _assert_same(g, o, w.n_replicas, "shifted")
+
+
+def test_dt_error_leaves_state(B, orc):
+    w = W.config_ghz4()
+    g = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    g.step(w.s[:10], w.gamma[:10])
+    before = g.export(0)
+    with pytest.raises(B.QMCError) as e:
+        g.step(w.s[10:11] * 1e4, w.gamma[10:11])
+    assert e.value.code == B.QMC_ERR_DT
+    after = g.export(0)
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert g.counters()["step"] == 10

@@ -112,6 +112,15 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
  * last good step.  Synchronizes the stream once at the end. */
 int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma);
 
+/* Which implementation qmc_step launches; every choice gives the same result bit for bit.
+ * path 0 (default): automatic -- the fused persistent kernel (one launch per batch of steps,
+ * one grid barrier per step, every key range owned by one workgroup) while the store holds at
+ * most 8192 keys per co-resident workgroup and no key range overflows its segment or its
+ * per-step inbox, otherwise the streamed kernels (spawn, radix sort of the children, merge)
+ * for the next 256 steps.  path 1: fused only (an overflowing key range is reported as
+ * QMC_ERR_STORE_CAP or QMC_ERR_SPAWN_CAP).  path 2: streamed only.  QMC_ERR_ARG otherwise. */
+int qmc_step_path(qmc_ctx* ctx, int32_t path);
+
 /* Ideal instantaneous Pauli pulse on every replica: rho -> P rho P^dagger with P = X^x Z^z,
  * i.e. |i><j| -> (-1)^{popc(z & i) + popc(z & j)} |i ^ x><j ^ x| (used for the staggered-XX
  * dynamical-decoupling pulses of Fig. 1(c)). */
@@ -180,8 +189,9 @@ typedef struct {
 int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
 
 /* Live timing of one kernel class with HIP events recorded on the context's stream around
- * every launch of that class in qmc_step: kernel_class 0 = spawn, 1 = child sort (all radix
- * passes), 2 = merge (partition + annihilation), -1 = off.  qmc_profile resets the totals;
+ * every launch of that class in qmc_step: kernel_class 0 = streamed spawn, 1 = streamed child
+ * sort (all radix passes), 2 = streamed merge (partition + annihilation + next spawn), 3 = one
+ * launch of the fused persistent kernel (a batch of whole steps), -1 = off.  qmc_profile resets the totals;
  * qmc_profile_read returns the summed milliseconds and the number of timed launches. */
 int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
 int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches);

@@ -23,9 +23,10 @@ QMC_ERR_COUNT_OVERFLOW = -5
 QMC_ERR_HIP = -6
 QMC_ERR_STATE = -8
 
-EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_pulse", "qmc_set_shift",
-            "qmc_observe", "qmc_export", "qmc_import", "qmc_counters", "qmc_profile",
-            "qmc_profile_read", "qmc_coeff_table", "qmc_last_error", "qmc_destroy"]
+EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path", "qmc_pulse",
+            "qmc_set_shift", "qmc_observe", "qmc_export", "qmc_import", "qmc_counters",
+            "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
+            "qmc_destroy"]
 
 
 class Monomial(ctypes.Structure):
@@ -94,6 +95,7 @@ def lib():
         L.qmc_import.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, u32]
         L.qmc_counters.argtypes = [vp, P(Stats)]
         L.qmc_profile.argtypes = [vp, ctypes.c_int32]
+        L.qmc_step_path.argtypes = [vp, ctypes.c_int32]
         L.qmc_profile_read.argtypes = [vp, P(dbl), P(u64)]
         L.qmc_coeff_table.argtypes = [P(Config), P(Model), P(dbl), P(dbl), u32, u32, P(u32),
                                       P(u64), P(u32), P(u32), P(u64), P(ctypes.c_int64)]
@@ -282,9 +284,14 @@ class QMC:
         return dict(step=st.step, n_occ=st.n_occ_total, walker_steps=st.walker_steps,
                     key_steps=st.key_steps, child_steps=st.child_steps, out_steps=st.out_steps)
 
+    def set_path(self, path):
+        """Step implementation: 'auto' (default), 'fused' (persistent kernel) or 'streamed'."""
+        self._check(lib().qmc_step_path(self._ctx, {"auto": 0, "fused": 1, "streamed": 2}[path]))
+
     def profile(self, kernel_class):
-        """Time one kernel class with HIP events: 'spawn', 'sort', 'merge' or None."""
-        cls = {None: -1, "spawn": 0, "sort": 1, "merge": 2}[kernel_class]
+        """Time one kernel class with HIP events: 'spawn', 'sort', 'merge' (streamed path),
+        'fused' (one persistent launch) or None."""
+        cls = {None: -1, "spawn": 0, "sort": 1, "merge": 2, "fused": 3}[kernel_class]
         self._check(lib().qmc_profile(self._ctx, cls))
 
     def profile_read(self):

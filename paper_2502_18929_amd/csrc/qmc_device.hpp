@@ -17,17 +17,26 @@ constexpr int kMaxTerms = 4096;      // merged terms per step table
 constexpr int kMergeIpt = 4;         // merged items per thread
 constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kMergeSlack = kMaxGroups + 1;  // a key's run of children is at most one per group
-constexpr int kSpawnSeg = 512;       // per-wave LDS staging segment for child records
-constexpr int kRadixBits = 8;
+constexpr int kMergeCap = kMergeTile + kMergeSlack + 8;
+constexpr int kSpawnSeg = 512;       // per-wave LDS staging of child records in k_spawn
+constexpr int kMergeSpawnSeg = 256;  // the same inside the merge (aliases the child tile)
+constexpr int kRadixBits = 11;       // digit width of the onesweep passes
 constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kSortBlocks = 256;     // fixed grid of the radix passes
+constexpr int kMaxPasses = 6;        // ceil(64 / 11)
+constexpr int kSortIpt = 16;         // records per thread of a sort tile
+constexpr int kSortTile = kBlock * kSortIpt;
+constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
+constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
+constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)
 
 // Device error bits (counters.err).
 enum : uint32_t {
   kErrSpawnCap = 1u,
   kErrStoreCap = 2u,
   kErrOverflow = 4u,
-  kErrLookback = 8u,
+  kErrLookback = 8u,   // a bounded wait expired (look-back, grid barrier) or a layout check failed
+  kErrSegCap = 16u,    // one key range outgrew its segment (cured by rebalancing)
+  kErrInbox = 32u,     // one key range received more records than its inbox holds
 };
 
 // One quantized term of a step table: sign mask and Q32 coefficient.
@@ -62,25 +71,30 @@ struct Counters {
   uint64_t out_steps;      // running sum of annihilated output keys of every step
   uint32_t err;
   uint32_t err_step;
-  uint32_t tile_counter;
+  uint32_t tile_counter;   // merge tile ticket
   uint32_t pad;
+  uint32_t sort_ticket[2][kMaxPasses + 2];  // onesweep tile tickets per step parity and pass
 };
+
+// Epoch tags of the look-back status words (never 0, distinct within a batch of <= 8000 steps).
+__host__ __device__ inline uint32_t merge_epoch(uint32_t step) { return 1u + step % 65535u; }
+__host__ __device__ inline uint32_t sort_epoch(uint32_t step, uint32_t pass) {
+  return 1u + (step * 8u + pass) % 65535u;
+}
 
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
   // Salmon et al., SC'11: ten rounds, multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key bumps.
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
     c0 = n0;
-    c1 = lo1;
     c2 = n2;
-    c3 = lo0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -136,6 +150,114 @@ __device__ __forceinline__ uint64_t atomic_load_agent(const uint64_t* p) {
 
 __device__ __forceinline__ void atomic_store_agent(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct TableView {
+  const TableHeader* h;
+  const uint64_t* gx;
+  const uint32_t* gs;
+  const Term* t;
+};
+
+__device__ __forceinline__ TableView table_view(const uint8_t* tab) {
+  TableView v;
+  v.h = reinterpret_cast<const TableHeader*>(tab);
+  v.gx = reinterpret_cast<const uint64_t*>(tab + v.h->gx_off);
+  v.gs = reinterpret_cast<const uint32_t*>(tab + v.h->gs_off);
+  v.t = reinterpret_cast<const Term*>(tab + v.h->t_off);
+  return v;
+}
+
+struct KeyLayout {
+  uint32_t kbits;   // 2n
+  uint64_t kmask;   // (1 << 2n) - 1
+  __device__ __forceinline__ uint64_t key(uint64_t ck) const { return ck & kmask; }
+  __device__ __forceinline__ uint32_t replica(uint64_t ck) const {
+    return kbits >= 64 ? 0u : (uint32_t)(ck >> kbits);
+  }
+};
+
+__device__ __forceinline__ void walker_random(uint64_t key, uint32_t step, uint32_t replica,
+                                              uint64_t seed, uint32_t w[4]) {
+  philox4x32_10((uint32_t)key, (uint32_t)(key >> 32), step, replica << 8, (uint32_t)seed,
+                (uint32_t)(seed >> 32), w);
+}
+
+// Group coefficient c = sum_t (-1)^parity(zmask_t & key) q_t; |c_re| + |c_im| < 2^31.
+__device__ __forceinline__ void group_coeff(const Term* __restrict__ t, uint32_t b, uint32_t e,
+                                            uint64_t key, int32_t& cre, int32_t& cim) {
+  int32_t re = 0, im = 0;
+  for (uint32_t i = b; i < e; ++i) {
+    const Term tm = t[i];
+    const int32_t s = -(int32_t)parity64(tm.zmask & key);  // 0 or -1
+    re += (tm.qre ^ s) - s;
+    im += (tm.qim ^ s) - s;
+  }
+  cre = re;
+  cim = im;
+}
+
+__device__ __forceinline__ void cmul_q32(int64_t a, int64_t b, int32_t cre, int32_t cim,
+                                         int64_t& xre, int64_t& xim) {
+  xre = a * (int64_t)cre - b * (int64_t)cim;
+  xim = a * (int64_t)cim + b * (int64_t)cre;
+}
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t shift) {
+  return (uint32_t)(k >> shift) & (kRadixBins - 1);
+}
+
+// Lanes of the wave (among `active`) holding the same radix digit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
+  uint64_t peers = active;
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const uint64_t bm = __ballot((d >> b) & 1u);
+    peers &= ((d >> b) & 1u) ? bm : ~bm;
+  }
+  return peers;
+}
+
+// Merge of parents (unique keys) with sorted child records, parents first on equal keys.
+template <class KA, class KB>
+__device__ __forceinline__ uint32_t merge_path(const KA& A, uint32_t na, const KB& B, uint32_t nb,
+                                               uint32_t d) {
+  uint32_t lo = d > nb ? d - nb : 0u;
+  uint32_t hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (A(mid) <= B(d - 1 - mid))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Split at diagonal d moved forward past the run of the key just before it.
+template <class KA, class KB>
+__device__ __forceinline__ void run_split(const KA& A, uint32_t na, const KB& B, uint32_t nb,
+                                          uint32_t d, uint32_t& i, uint32_t& j) {
+  i = merge_path(A, na, B, nb, d);
+  j = d - i;
+  if (d == 0 || d >= na + nb) return;
+  uint64_t last = 0;
+  if (i > 0) last = A(i - 1);
+  if (j > 0) {
+    const uint64_t c = B(j - 1);
+    if (i == 0 || c > last) last = c;
+  }
+  // Only children can continue the run (a parent equal to `last` would precede it).
+  uint32_t lo = j, hi = nb;
+  if (hi - lo > (uint32_t)kMergeSlack) hi = lo + kMergeSlack;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (B(mid) <= last)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  j = lo;
 }
 
 }  // namespace qmc

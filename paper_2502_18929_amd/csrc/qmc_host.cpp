@@ -17,13 +17,14 @@
 #include "../../include/qmc.h"
 #include "qmc_device.hpp"
 #include "qmc_kernels.h"
+#include "qmc_persist.h"
 
 namespace {
 
 constexpr uint32_t kMaxPauli = 256;
 constexpr uint32_t kMaxLookup = 4096;
 constexpr size_t kTableArea = 8u << 20;   // device bytes for the step tables of one chunk
-constexpr uint32_t kMaxChunkSteps = 16384;
+constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -43,10 +44,13 @@ struct QTerm {
 };
 
 struct Layout {
-  size_t counters, sk0, sk1, sv0, sv1, ck0, ck1, cv0, cv1, hist, splits, status, tab, qshift,
-      obs_out, obs_in, look_keys, look_out, total;
-  uint64_t cap_store, cap_child;
-  uint32_t max_tiles;
+  size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
+      obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, in_k, in_v, in_n, split, tab_off,
+      slots, ctl, done, total;
+  uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
+  uint32_t P;          // key ranges / workgroups of the persistent step
+  uint64_t segcap;     // records per segment
+  uint32_t incap;      // records per inbox
 };
 
 int pc_parity(uint64_t v) { return __builtin_popcountll(v) & 1; }
@@ -57,14 +61,20 @@ uint32_t replica_bits(uint32_t R) {
   return b;
 }
 
-bool compute_layout(const qmc_config& c, Layout& L) {
+bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
   const uint64_t S = c.store_capacity * (uint64_t)c.n_replicas;
   const uint64_t C = c.spawn_capacity * (uint64_t)c.n_replicas;
-  if (S == 0 || C == 0 || S >= (1ull << 31) || C >= (1ull << 31) || S + C >= (1ull << 31))
-    return false;
+  if (S == 0 || C == 0 || S >= (1ull << 31) || C >= (1ull << 31) || P == 0) return false;
   L.cap_store = S;
   L.cap_child = C;
-  L.max_tiles = (uint32_t)((S + C + qmc::kMergeTile - 1) / qmc::kMergeTile) + 1;
+  // the child buffers hold one step's children, or the whole store when a pulse with x != 0
+  // re-sorts it
+  L.cap_sort = std::max(S, C);
+  L.n_sort_status = ((L.cap_sort + qmc::kSortTile - 1) / qmc::kSortTile) * qmc::kRadixBins;
+  L.max_tiles = (S + C + qmc::kMergeTile - 1) / qmc::kMergeTile;
+  L.P = P;
+  L.segcap = std::max<uint64_t>(4096, (2 * S + P - 1) / P);
+  L.incap = qmc::kInboxMax;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -73,24 +83,42 @@ bool compute_layout(const qmc_config& c, Layout& L) {
   };
   L.counters = take(sizeof(qmc::Counters));
   L.sk0 = take(S * 8);
-  L.sk1 = take(S * 8);
   L.sv0 = take(S * 8);
-  L.sv1 = take(S * 8);
-  L.ck0 = take(C * 8);
-  L.ck1 = take(C * 8);
-  L.cv0 = take(C * 8);
-  L.cv1 = take(C * 8);
-  L.hist = take((size_t)qmc::kRadixBins * qmc::kSortBlocks * 4);
-  L.splits = take(((size_t)L.max_tiles + 2) * 8);
-  L.status = take((size_t)L.max_tiles * 8);
+  L.ck0 = take(L.cap_sort * 8);
+  L.ck1 = take(L.cap_sort * 8);
+  L.cv0 = take(L.cap_sort * 8);
+  L.cv1 = take(L.cap_sort * 8);
+  L.ghist = take((size_t)2 * qmc::kMaxPasses * qmc::kRadixBins * 4);
+  L.sort_status = take(L.n_sort_status * 8);
+  L.status = take(L.max_tiles * 8);
+  L.splits = take((L.max_tiles + 1) * 8);
   L.tab = take(kTableArea);
   L.qshift = take((size_t)c.n_replicas * 8);
   L.obs_out = take((size_t)c.n_replicas * (5 + 2 * kMaxPauli) * 8);
   L.obs_in = take((size_t)kMaxPauli * 16);
   L.look_keys = take((size_t)kMaxLookup * 8);
   L.look_out = take((size_t)c.n_replicas * kMaxLookup * 16);
+  L.seg_k = take((size_t)2 * P * L.segcap * 8);
+  L.seg_v = take((size_t)2 * P * L.segcap * 8);
+  L.seg_n = take((size_t)2 * P * 4);
+  L.in_k = take((size_t)2 * P * L.incap * 8);
+  L.in_v = take((size_t)2 * P * L.incap * 8);
+  L.in_n = take((size_t)2 * P * 4);
+  L.split = take((size_t)P * 8);
+  L.tab_off = take((size_t)kMaxChunkSteps * 4);
+  L.slots = take((size_t)P * 4 * 8);
+  L.ctl = take(16 * 8);
+  L.done = take(8);
   L.total = o;
   return true;
+}
+
+// Workgroups of the persistent step that can be co-resident on the current device.
+int persist_segments(uint32_t* P) {
+  int p = 0;
+  if (qmcp_max_segments(&p) != 0 || p <= 0) return QMC_ERR_HIP;
+  *P = (uint32_t)p;
+  return QMC_OK;
 }
 
 }  // namespace
@@ -113,17 +141,28 @@ struct qmc_ctx {
   std::string err;
   bool broken = false;
   int32_t prof_class = -1;
+  uint64_t epoch = 0;               // last barrier epoch used by the persistent step
+  int32_t path = 0;                 // 0 automatic, 1 fused persistent kernel only, 2 streamed only
+  uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
+  uint32_t streamed_until = 0;      // automatic mode: steps before this one run streamed
   std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
   double prof_ms = 0.0;
   uint64_t prof_launches = 0;
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  uint64_t* sk(uint32_t b) const { return at<uint64_t>(b ? L.sk1 : L.sk0); }
-  int2* sv(uint32_t b) const { return at<int2>(b ? L.sv1 : L.sv0); }
+  // The store: always in the canonical buffer between calls.  The streamed step alternates
+  // between it and the segment area of the persistent step (at least 4x the store capacity).
+  uint64_t* sk(uint32_t) const { return at<uint64_t>(L.sk0); }
+  int2* sv(uint32_t) const { return at<int2>(L.sv0); }
+  uint64_t* alt_k() const { return at<uint64_t>(L.seg_k); }
+  int2* alt_v() const { return at<int2>(L.seg_v); }
   uint64_t* ck(uint32_t b) const { return at<uint64_t>(b ? L.ck1 : L.ck0); }
   int2* cv(uint32_t b) const { return at<int2>(b ? L.cv1 : L.cv0); }
   qmc::Counters* counters() const { return at<qmc::Counters>(L.counters); }
+  uint32_t* ghist(uint32_t parity) const {
+    return at<uint32_t>(L.ghist) + (size_t)parity * qmc::kMaxPasses * qmc::kRadixBins;
+  }
 };
 
 namespace {
@@ -347,7 +386,7 @@ int validate(const qmc_config* cfg, const qmc_model* m, std::string& why) {
       return QMC_ERR_ARG;
     }
   Layout L;
-  if (!compute_layout(*cfg, L)) {
+  if (!compute_layout(*cfg, 1, L)) {
     why = "capacities must be nonzero and R*(store+spawn) < 2^31";
     return QMC_ERR_ARG;
   }
@@ -365,6 +404,7 @@ int upload_store(qmc_ctx* c, uint32_t b, const std::vector<uint64_t>& ck,
   }
   HIPCHK(c, hipMemcpyAsync(&c->counters()->n_store[b], &n, 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->n_occ = n;
   return QMC_OK;
 }
 
@@ -414,8 +454,11 @@ int qmc_workspace_bytes(const qmc_config* cfg, const qmc_model* model, size_t* b
   std::string why;
   int rc = validate(cfg, model, why);
   if (rc) return rc;
+  uint32_t P = 0;
+  rc = persist_segments(&P);
+  if (rc) return rc;
   Layout L;
-  compute_layout(*cfg, L);
+  compute_layout(*cfg, P, L);
   if (bytes) *bytes = L.total;
   return QMC_OK;
 }
@@ -439,7 +482,12 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   c->rbits = replica_bits(c->R);
   c->n_h = model->n_h;
   c->n_l = model->n_l;
-  compute_layout(*cfg, c->L);
+  uint32_t P = 0;
+  if (persist_segments(&P)) {
+    delete c;
+    return QMC_ERR_HIP;
+  }
+  compute_layout(*cfg, P, c->L);
   if (!d_workspace || ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) {
     delete c;
     return QMC_ERR_ARG;
@@ -465,6 +513,9 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   }
   // zero counters, then the initial store (replica tag in the high bits)
   e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)c->L.P * 4 * 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->at<uint64_t>(c->L.ctl), 0, 16 * 8, c->stream);
   if (e != hipSuccess) {
     qmc_destroy(c);
     return QMC_ERR_HIP;
@@ -493,6 +544,178 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   return QMC_OK;
 }
 
+namespace {
+
+constexpr uint64_t kFusedKeysPerSegment = 8192;  // automatic mode: larger stores run streamed
+constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a fused overflow
+
+// Steps [step, step + nst) as one launch of the fused persistent kernel (tables already on the
+// device at dtab, offsets at tab_off).  On return kd = completed steps, reason = the kernel's stop
+// reason (0 end, 1 rebalance, 2 error), hc = the counters; the store and c->step reflect kd.
+int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& reason,
+              qmc::Counters& hc) {
+  uint32_t* pin_done = reinterpret_cast<uint32_t*>(c->pinned_small + 1024);
+  PersistLaunch pl;
+  pl.ck = c->sk(0);
+  pl.cv = c->sv(0);
+  pl.ck_w = c->sk(0);
+  pl.cv_w = c->sv(0);
+  pl.counters = c->counters();
+  pl.cur = c->cur;
+  pl.sk = c->at<uint64_t>(c->L.seg_k);
+  pl.sv = c->at<int2>(c->L.seg_v);
+  pl.segcap = c->L.segcap;
+  pl.seg_n = c->at<uint32_t>(c->L.seg_n);
+  pl.ik = c->at<uint64_t>(c->L.in_k);
+  pl.iv = c->at<int2>(c->L.in_v);
+  pl.incap = c->L.incap;
+  pl.in_n = c->at<uint32_t>(c->L.in_n);
+  pl.split = c->at<uint64_t>(c->L.split);
+  pl.split_w = c->at<uint64_t>(c->L.split);
+  pl.P = c->L.P;
+  pl.tab_base = dtab;
+  pl.tab_off = c->at<uint32_t>(c->L.tab_off);
+  pl.step0 = c->step;
+  pl.nsteps = nst;
+  pl.seed = c->cfg.seed;
+  pl.kbits = c->kbits;
+  pl.qshift = c->at<int64_t>(c->L.qshift);
+  pl.slots = c->at<uint64_t>(c->L.slots);
+  pl.ctl = c->at<uint64_t>(c->L.ctl);
+  pl.epoch0 = c->epoch + 1;
+  c->epoch += (uint64_t)nst + 1;  // barriers of this launch: batch start + one per step
+  pl.cap_store = c->L.cap_store;
+  pl.cap_inbox = c->L.cap_child;
+  pl.rebal_min = 1024;
+  pl.done = c->at<uint32_t>(c->L.done);
+  const bool prof = c->prof_class == 3;
+  if (prof) {
+    while (c->prof_ev.size() < 2) {
+      hipEvent_t ev;
+      HIPCHK(c, hipEventCreate(&ev));
+      c->prof_ev.push_back(ev);
+    }
+    HIPCHK(c, hipEventRecord(c->prof_ev[0], c->stream));
+  }
+  HIPCHK(c, qmcp_run(c->stream, &pl));
+  if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[1], c->stream));
+  HIPCHK(c, hipMemcpyAsync(pin_done, pl.done, 8, hipMemcpyDeviceToHost, c->stream));
+  int rc = read_counters(c, hc);  // synchronizes the stream
+  if (rc) return rc;
+  if (prof) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]));
+    c->prof_ms += ms;
+    c->prof_launches += 1;
+  }
+  kd = pin_done[0];
+  reason = pin_done[1];
+  if (reason == 2 || hc.err) {
+    const uint32_t es = hc.err_step;
+    if (es < pl.step0 || es > pl.step0 + pl.nsteps) {
+      c->broken = true;
+      return fail(c, QMC_ERR_HIP, "device error flag without a valid step");
+    }
+    kd = es - pl.step0;
+  }
+  // The state after kd completed steps is in segment buffer kd & 1 (kd = 0: untouched store).
+  if (kd > 0) {
+    HIPCHK(c, qmcp_gather(c->stream, &pl, kd & 1u));
+    rc = read_counters(c, hc);
+    if (rc) return rc;
+  }
+  c->step = pl.step0 + kd;
+  c->n_occ = hc.n_store[c->cur];
+  return QMC_OK;
+}
+
+// Steps [step, step + nst) as separate kernels per step: spawn (first step only), LSD radix sort
+// of the children, and the merge, which also spawns the next step's children.  The store
+// alternates between the canonical buffer and the segment area and ends in the canonical buffer.
+int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& offs, uint32_t nst,
+                 uint32_t& kd, qmc::Counters& hc) {
+  qmc::Counters* dcnt = c->counters();
+  const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits);
+  const uint32_t step0 = c->step, cur0 = c->cur;
+  uint64_t* bk[2] = {c->sk(0), c->alt_k()};
+  int2* bv[2] = {c->sv(0), c->alt_v()};
+  HIPCHK(c, qmck_batch_begin(c->stream, dcnt, c->at<uint64_t>(c->L.status), c->L.max_tiles,
+                             c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
+                             2 * qmc::kMaxPasses * qmc::kRadixBins));
+  const uint32_t nev = 2 * nst;
+  if (c->prof_class >= 0 && c->prof_class <= 2) {
+    while (c->prof_ev.size() < nev) {
+      hipEvent_t ev;
+      HIPCHK(c, hipEventCreate(&ev));
+      c->prof_ev.push_back(ev);
+    }
+  }
+  auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
+    if (c->prof_class != cls) return hipSuccess;
+    return hipEventRecord(c->prof_ev[2 * k + which], c->stream);
+  };
+  uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
+  HIPCHK(c, mark(0, 0, 0));
+  HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, cur0, dtab + offs[0], step0, c->cfg.seed,
+                       c->kbits, c->ck(cb), c->cv(cb), c->L.cap_child, c->L.cap_store,
+                       c->ghist(step0 & 1), passes));
+  HIPCHK(c, mark(0, 0, 1));
+  for (uint32_t k = 0; k < nst; ++k) {
+    const uint32_t st = step0 + k, b = k & 1u, cur = cur0 ^ b;
+    const uint8_t* tab = dtab + offs[k];
+    const uint8_t* tab_next = (k + 1 < nst) ? dtab + offs[k + 1] : nullptr;
+    const uint32_t csel = st & 1;
+    HIPCHK(c, mark(1, k, 0));
+    HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
+                        c->ghist(csel), c->at<uint64_t>(c->L.sort_status), st, cb,
+                        c->L.cap_child));
+    HIPCHK(c, mark(1, k, 1));
+    const uint32_t cf = cb ^ (passes & 1);  // sorted children
+    HIPCHK(c, mark(2, k, 0));
+    HIPCHK(c, qmck_merge(c->stream, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
+                         c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), tab, tab_next,
+                         c->at<int64_t>(c->L.qshift), st, c->cfg.seed, c->kbits, bk[b ^ 1],
+                         bv[b ^ 1], c->L.cap_store, c->L.cap_store + c->L.cap_child,
+                         c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
+                         passes));
+    HIPCHK(c, mark(2, k, 1));
+    cb = cf ^ 1;
+  }
+  int rc = read_counters(c, hc);
+  if (rc) return rc;
+  if (c->prof_class >= 0 && c->prof_class <= 2) {
+    const uint32_t kend = c->prof_class == 0 ? 1 : nst;  // the spawn kernel runs once
+    for (uint32_t k = 0; k < kend; ++k) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
+      c->prof_ms += ms;
+      c->prof_launches += 1;
+    }
+  }
+  kd = nst;
+  if (hc.err) {
+    const uint32_t es = hc.err_step;
+    if (es < step0 || es >= step0 + nst) {
+      c->broken = true;
+      return fail(c, QMC_ERR_HIP, "device error flag without a valid step");
+    }
+    kd = es - step0;
+  }
+  const uint32_t cur = cur0 ^ (kd & 1u);
+  if (kd & 1u) {
+    HIPCHK(c, qmck_copy_store(c->stream, bk[1], bv[1], bk[0], bv[0], &dcnt->n_store[cur],
+                              c->L.cap_store));
+    rc = read_counters(c, hc);
+    if (rc) return rc;
+  }
+  c->cur = cur;
+  c->step = step0 + kd;
+  c->n_occ = hc.n_store[cur];
+  return QMC_OK;
+}
+
+}  // namespace
+
 int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) {
   if (!c) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
@@ -505,106 +728,84 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
 
   // Build and check every table of the batch before launching anything.
   std::vector<HostTable> tabs(nsteps);
+  std::vector<size_t> tbytes(nsteps);
   for (uint32_t k = 0; k < nsteps; ++k) {
     std::string why;
     int rc = build_table(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, tabs[k], why);
     if (rc) return fail(c, rc, "step " + std::to_string(c->step + k) + ": " + why);
     if (tabs[k].q_diag + max_qs >= (1ull << 31))
       return fail(c, QMC_ERR_DT, "diagonal group with shift violates the Q32 bound");
+    tbytes[k] = pack_table(tabs[k], nullptr);
   }
-  const uint32_t kbits = c->kbits;
-  const uint32_t sort_bits = c->kbits + c->rbits;
-  qmc::Counters* dcnt = c->counters();
-  uint32_t k0 = 0;
-  while (k0 < nsteps) {
-    // chunk: as many steps as fit the table area
+  const uint32_t first_step = c->step;
+  const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
+  uint32_t last_local_fail = 0xFFFFFFFFu;
+  while (c->step < first_step + nsteps) {
+    const uint32_t k0 = c->step - first_step;
+    const bool fused = c->path == 1 || (c->path == 0 && c->step >= c->streamed_until &&
+                                        c->n_occ <= fused_max_keys);
+    // One launch (fused) or one stream of launches: as many of the remaining steps as fit the
+    // table area; an automatic streamed run stops where the fused kernel may be tried again.
+    uint32_t kmax = nsteps;
+    if (!fused && c->path == 0 && c->step < c->streamed_until)
+      kmax = std::min<uint32_t>(nsteps, c->streamed_until - first_step);
     size_t bytes = 0;
     uint32_t k1 = k0;
-    std::vector<size_t> offs;
-    while (k1 < nsteps && k1 - k0 < kMaxChunkSteps) {
-      size_t b = pack_table(tabs[k1], nullptr);
-      if (bytes + b > kTableArea) break;
-      offs.push_back(bytes);
-      bytes += b;
+    std::vector<uint32_t> offs;
+    while (k1 < kmax && k1 - k0 < kMaxChunkSteps && bytes + tbytes[k1] <= kTableArea) {
+      offs.push_back((uint32_t)bytes);
+      bytes += tbytes[k1];
       ++k1;
     }
     if (k1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
     for (uint32_t k = k0; k < k1; ++k) pack_table(tabs[k], c->pinned + offs[k - k0]);
     uint8_t* dtab = c->at<uint8_t>(c->L.tab);
     HIPCHK(c, hipMemcpyAsync(dtab, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
-    const uint32_t step0 = c->step, cur0 = c->cur;
-    HIPCHK(c, qmck_batch_begin(c->stream, dcnt, step0, c->at<uint64_t>(c->L.status),
-                               c->L.max_tiles));
-    uint32_t cur = cur0;
-    const uint32_t nev = 2 * (k1 - k0);
-    if (c->prof_class >= 0) {
-      while (c->prof_ev.size() < nev) {
-        hipEvent_t ev;
-        HIPCHK(c, hipEventCreate(&ev));
-        c->prof_ev.push_back(ev);
-      }
-    }
-    auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
-      if (c->prof_class != cls) return hipSuccess;
-      return hipEventRecord(c->prof_ev[2 * (k - k0) + which], c->stream);
-    };
-    for (uint32_t k = k0; k < k1; ++k) {
-      const uint32_t st = c->step + (k - k0);
-      const uint8_t* tab = dtab + offs[k - k0];
-      const uint32_t csel = st & 1;
-      HIPCHK(c, mark(0, k, 0));
-      HIPCHK(c, qmck_spawn(c->stream, c->sk(cur), c->sv(cur), dcnt, cur, tab, st, c->cfg.seed,
-                           kbits, c->ck(0), c->cv(0), c->L.cap_child, c->L.cap_store));
-      HIPCHK(c, mark(0, k, 1));
-      int second = 0;
-      HIPCHK(c, mark(1, k, 0));
-      HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel,
-                          sort_bits, c->at<uint32_t>(c->L.hist), &second));
-      HIPCHK(c, mark(1, k, 1));
-      HIPCHK(c, mark(2, k, 0));
-      HIPCHK(c, qmck_merge(c->stream, c->sk(cur), c->sv(cur), c->ck(second), c->cv(second), dcnt,
-                           cur, csel, c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status),
-                           (st + 1) & 0xFFFFu, tab, c->at<int64_t>(c->L.qshift), st, c->cfg.seed,
-                           kbits, c->sk(cur ^ 1), c->sv(cur ^ 1), c->L.cap_store,
-                           c->L.cap_store + c->L.cap_child));
-      HIPCHK(c, mark(2, k, 1));
-      cur ^= 1;
-    }
     qmc::Counters hc;
-    int rc = read_counters(c, hc);
+    uint32_t kd = 0, reason = 0;
+    int rc;
+    if (fused) {
+      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), offs.data(), offs.size() * 4,
+                               hipMemcpyHostToDevice, c->stream));
+      rc = run_fused(c, dtab, k1 - k0, kd, reason, hc);
+    } else {
+      rc = run_streamed(c, dtab, offs, k1 - k0, kd, hc);
+    }
     if (rc) return rc;
-    if (c->prof_class >= 0) {
-      for (uint32_t k = k0; k < k1; ++k) {
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * (k - k0)], c->prof_ev[2 * (k - k0) + 1]));
-        c->prof_ms += ms;
-        c->prof_launches += 1;
-      }
-    }
     if (hc.err) {
-      const uint32_t es = hc.err_step;
-      if (es < step0 || es >= step0 + (k1 - k0)) {
+      const uint32_t e = hc.err;
+      const std::string at = "step " + std::to_string(c->step) + ": ";
+      if (e & qmc::kErrLookback) {
         c->broken = true;
-        return fail(c, QMC_ERR_HIP, "device error flag without a valid step");
+        return fail(c, QMC_ERR_HIP, at + "a bounded wait expired");
       }
-      c->step = es;
-      c->cur = cur0 ^ ((es - step0) & 1);
-      if (hc.err & qmc::kErrLookback) {
-        c->broken = true;
-        return fail(c, QMC_ERR_HIP, "merge look-back did not complete");
+      if (e & qmc::kErrOverflow) return fail(c, QMC_ERR_COUNT_OVERFLOW, at + "population outside int32");
+      if (e & qmc::kErrStoreCap) return fail(c, QMC_ERR_STORE_CAP, at + "store capacity exceeded");
+      if (e & qmc::kErrSpawnCap) return fail(c, QMC_ERR_SPAWN_CAP, at + "spawn capacity exceeded");
+      // A key range outgrew its segment or inbox: rebalance once per step; then, in automatic
+      // mode, run the next steps streamed.
+      if (c->step == last_local_fail) {
+        if (c->path == 0) {
+          c->streamed_until = c->step + kStreamedWindow;
+          continue;
+        }
+        if (e & qmc::kErrSegCap)
+          return fail(c, QMC_ERR_STORE_CAP, at + "a key range exceeds one segment");
+        return fail(c, QMC_ERR_SPAWN_CAP, at + "a key range receives more than one inbox");
       }
-      if (hc.err & qmc::kErrOverflow)
-        return fail(c, QMC_ERR_COUNT_OVERFLOW,
-                    "step " + std::to_string(es) + ": population outside int32");
-      if (hc.err & qmc::kErrSpawnCap)
-        return fail(c, QMC_ERR_SPAWN_CAP,
-                    "step " + std::to_string(es) + ": spawn capacity exceeded");
-      return fail(c, QMC_ERR_STORE_CAP, "step " + std::to_string(es) + ": store capacity exceeded");
+      last_local_fail = c->step;
+    } else if (reason == 2) {
+      c->broken = true;
+      return fail(c, QMC_ERR_HIP, "fused step stopped without an error flag");
     }
-    c->step = step0 + (k1 - k0);
-    c->cur = cur;
-    k0 = k1;
   }
+  return QMC_OK;
+}
+
+int qmc_step_path(qmc_ctx* c, int32_t path) {
+  if (!c || path < 0 || path > 2) return QMC_ERR_ARG;
+  c->path = path;
+  c->streamed_until = 0;
   return QMC_OK;
 }
 
@@ -614,23 +815,20 @@ int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
   const uint64_t qmask = c->n >= 32 ? 0xFFFFFFFFull : ((1ull << c->n) - 1);
   if ((x | z) & ~qmask) return fail(c, QMC_ERR_ARG, "pulse mask outside n bits");
   qmc::Counters* dcnt = c->counters();
-  if (x != 0) {
-    qmc::Counters hc0;
-    int rc0 = read_counters(c, hc0);
-    if (rc0) return rc0;
-    if (hc0.n_store[c->cur] > c->L.cap_child)
-      return fail(c, QMC_ERR_SPAWN_CAP, "a pulse with x != 0 re-sorts the store through the "
-                                        "child buffers, which are smaller than the store");
-  }
-  HIPCHK(c, qmck_batch_begin(c->stream, dcnt, c->step, c->at<uint64_t>(c->L.status), 0));
+  HIPCHK(c, qmck_batch_begin(c->stream, dcnt, nullptr, 0,
+                             c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
+                             2 * qmc::kMaxPasses * qmc::kRadixBins));
   HIPCHK(c, qmck_pulse(c->stream, c->sk(c->cur), c->sv(c->cur), dcnt, c->cur, c->n, x, z,
                        c->ck(0), c->cv(0), 0, c->L.cap_store));
   if (x != 0) {
-    int second = 0;
-    HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, 0,
-                        c->kbits + c->rbits, c->at<uint32_t>(c->L.hist), &second));
-    HIPCHK(c, qmck_copy_store(c->stream, c->ck(second), c->cv(second), c->sk(c->cur),
-                              c->sv(c->cur), dcnt, 0, c->L.cap_store));
+    const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits);
+    HIPCHK(c, qmck_digit_hist(c->stream, c->ck(0), dcnt, 0, passes, c->ghist(0), c->L.cap_store));
+    HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, 0, passes,
+                        c->ghist(0), c->at<uint64_t>(c->L.sort_status), c->step, 0,
+                        c->L.cap_sort));
+    const uint32_t out = passes & 1;
+    HIPCHK(c, qmck_copy_store(c->stream, c->ck(out), c->cv(out), c->sk(c->cur), c->sv(c->cur),
+                              &dcnt->n_child[0], c->L.cap_store));
   }
   qmc::Counters hc;
   int rc = read_counters(c, hc);
@@ -833,7 +1031,7 @@ int qmc_counters(qmc_ctx* c, qmc_stats* out) {
 }
 
 int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
-  if (!c || kernel_class < -1 || kernel_class > 2) return QMC_ERR_ARG;
+  if (!c || kernel_class < -1 || kernel_class > 3) return QMC_ERR_ARG;
   c->prof_class = kernel_class;
   c->prof_ms = 0.0;
   c->prof_launches = 0;

@@ -1,267 +1,405 @@
 // qmc_kernels.hip -- HIP kernels of one population-dynamics time step (gfx950, wave64).
 //
 // Step s (End Matter, spawn and annihilation; Euler solver):
-//   k_spawn          parents N(s) -> child records (key ^ mask, comb-rounded dt L N), unsorted
-//   k_radix_*        LSD radix sort of the child records by composite key (LDS ranking)
+//   children(s)      spawned from N(s): key ^ mask, comb-rounded dt L N, unsorted, with the
+//                    radix digit histograms of every pass accumulated while they are written
+//   k_onesweep x P   single-pass LSD radix sort of the children by composite key: per tile,
+//                    wave-local stable ranking in LDS, decoupled look-back per digit, scatter
 //   k_merge_part     merge-path split points of (parents, sorted children), moved to run ends
 //   k_merge          death/cloning of each parent (diagonal of the column, applied to N(s)),
 //                    merge with the children, int64 segmented sum per key, drop (0, 0),
-//                    decoupled look-back for the compacted output offset -> N(s+1)
-// plus k_pulse (ideal Pauli conjugation), k_observe / k_lookup (estimator numerators) and
-// small utility kernels.  Every kernel reads its problem sizes from device memory, so a whole
-// batch of steps is enqueued without host synchronization.
+//                    decoupled look-back for the compacted output offset -> N(s+1); then the
+//                    children of step s+1 are spawned from the outputs still in LDS
+// The first step of a batch spawns with k_spawn.  Plus k_pulse (ideal Pauli conjugation),
+// k_observe / k_lookup (estimator numerators) and small utility kernels.  Every kernel reads its
+// problem sizes from device memory, so a batch of steps is enqueued without host sync.
 #include "qmc_device.hpp"
 #include "qmc_kernels.h"
 
 namespace qmc {
 
-struct TableView {
-  const TableHeader* h;
-  const uint64_t* gx;
-  const uint32_t* gs;
-  const Term* t;
-};
+// Spawn emitter: per-wave LDS staging of child records, flushed to the child buffer with one
+// atomic per flush; every flushed record is also counted into the digit histograms of all
+// radix passes of the next sort (wave-aggregated atomics).
+struct Emitter {
+  uint64_t* s_key;      // this wave's staging segment
+  int2* s_val;
+  uint32_t seg;         // segment capacity (records)
+  uint32_t fill;        // wave-uniform
+  Counters* cnt;
+  uint32_t nsel;        // child counter parity
+  uint32_t step;        // the step the children belong to
+  uint64_t* ck_out;
+  int2* cv_out;
+  uint64_t cap;
+  uint32_t* ghist;      // [passes][kRadixBins]
+  uint32_t passes;
 
-__device__ __forceinline__ TableView table_view(const uint8_t* tab) {
-  TableView v;
-  v.h = reinterpret_cast<const TableHeader*>(tab);
-  v.gx = reinterpret_cast<const uint64_t*>(tab + v.h->gx_off);
-  v.gs = reinterpret_cast<const uint32_t*>(tab + v.h->gs_off);
-  v.t = reinterpret_cast<const Term*>(tab + v.h->t_off);
-  return v;
-}
+  __device__ void flush() {
+    const uint32_t lane = __lane_id();
+    wave_lds_fence();
+    uint64_t base = 0;
+    if (lane == 0)
+      base = atomicAdd((unsigned long long*)&cnt->n_child[nsel], (unsigned long long)fill);
+    base = __shfl(base, 0);
+    const bool ok = base + fill <= cap;
+    if (!ok && lane == 0) {
+      atomicOr(&cnt->err, kErrSpawnCap);
+      atomicMin(&cnt->err_step, step);
+    }
+    for (uint32_t i0 = 0; i0 < fill; i0 += kWave) {
+      const uint32_t i = i0 + lane;
+      const bool v = i < fill;
+      uint64_t k = 0;
+      if (v) {
+        k = s_key[i];
+        if (ok) {
+          ck_out[base + i] = k;
+          cv_out[base + i] = s_val[i];
+        }
+      }
+      const uint64_t act = __ballot(v);
+      for (uint32_t p = 0; p < passes; ++p) {
+        const uint32_t d = digit_of(k, p * kRadixBits);
+        const uint64_t peers = match_digit(d, act);
+        if (v && (peers & lanemask_lt()) == 0)
+          atomicAdd(&ghist[p * kRadixBins + d], (uint32_t)__popcll(peers));
+      }
+    }
+    wave_lds_fence();
+    fill = 0;
+  }
 
-struct KeyLayout {
-  uint32_t kbits;   // 2n
-  uint64_t kmask;   // (1 << 2n) - 1
-  __device__ __forceinline__ uint64_t key(uint64_t ck) const { return ck & kmask; }
-  __device__ __forceinline__ uint32_t replica(uint64_t ck) const {
-    return kbits >= 64 ? 0u : (uint32_t)(ck >> kbits);
+  // All lanes call; lanes with has == true append (key, val).
+  __device__ __forceinline__ void emit(bool has, uint64_t key, int2 val) {
+    const uint64_t m = __ballot(has);
+    if (m == 0) return;
+    if (has) {
+      const uint32_t pos = fill + mbcnt64(m);
+      s_key[pos] = key;
+      s_val[pos] = val;
+    }
+    fill += (uint32_t)__popcll(m);
+    if (fill > seg - kWave) flush();
   }
 };
 
-__device__ __forceinline__ void walker_random(uint64_t key, uint32_t step, uint32_t replica,
-                                              uint64_t seed, uint32_t w[4]) {
-  philox4x32_10((uint32_t)key, (uint32_t)(key >> 32), step, replica << 8, (uint32_t)seed,
-                (uint32_t)(seed >> 32), w);
-}
-
-// Group coefficient c = sum_t (-1)^parity(zmask_t & key) q_t; |c_re| + |c_im| < 2^31.
-__device__ __forceinline__ void group_coeff(const Term* __restrict__ t, uint32_t b, uint32_t e,
-                                            uint64_t key, int32_t& cre, int32_t& cim) {
-  int32_t re = 0, im = 0;
-  for (uint32_t i = b; i < e; ++i) {
-    const Term tm = t[i];
-    const int32_t s = -(int32_t)parity64(tm.zmask & key);  // 0 or -1
-    re += (tm.qre ^ s) - s;
-    im += (tm.qim ^ s) - s;
+// Children of one parent (called by every lane of a wave; `valid` lanes hold a parent).
+__device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, bool valid,
+                                             uint64_t ck, int2 v, uint32_t step, uint64_t seed,
+                                             const KeyLayout& kl) {
+  const uint32_t G = tv.h->n_groups;
+  if (G <= 1) return;
+  uint32_t w[4] = {0, 0, 0, 0};
+  bool active = false;
+  if (valid) {
+    walker_random(kl.key(ck), step, kl.replica(ck), seed, w);
+    active = !comb_all_zero(uabs64(v.x) + uabs64(v.y), tv.h->q_off, w[0]);
   }
-  cre = re;
-  cim = im;
-}
-
-__device__ __forceinline__ void cmul_q32(int64_t a, int64_t b, int32_t cre, int32_t cim,
-                                         int64_t& xre, int64_t& xim) {
-  xre = a * (int64_t)cre - b * (int64_t)cim;
-  xim = a * (int64_t)cim + b * (int64_t)cre;
+  if (__ballot(active) == 0) return;
+  const uint64_t key = kl.key(ck);
+  uint64_t r = w[0];
+  for (uint32_t g = 1; g < G; ++g) {
+    int2 child = make_int2(0, 0);
+    if (active) {
+      int32_t cre, cim;
+      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      child.x = (int32_t)comb_step(r, xre);
+      child.y = (int32_t)comb_step(r, xim);
+    }
+    em.emit((child.x | child.y) != 0, ck ^ tv.gx[g], child);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
-// k_spawn: one lane per parent; child records are staged per wave in LDS and flushed to the
-// child buffer with one global atomic per flush.
+// k_spawn: children of the first step of a batch (later steps spawn inside k_merge).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_spawn(
     const uint64_t* __restrict__ pk, const int2* __restrict__ pv, Counters* __restrict__ cnt,
     uint32_t cur, const uint8_t* __restrict__ tab, uint32_t step, uint64_t seed, KeyLayout kl,
-    uint64_t* __restrict__ ck_out, int2* __restrict__ cv_out, uint64_t cap_child) {
+    uint64_t* __restrict__ ck_out, int2* __restrict__ cv_out, uint64_t cap_child,
+    uint32_t* __restrict__ ghist, uint32_t passes) {
   __shared__ uint64_t s_key[kWaves][kSpawnSeg];
   __shared__ int2 s_val[kWaves][kSpawnSeg];
   if (cnt->err) return;
   const uint64_t np = cnt->n_store[cur];
   const TableView tv = table_view(tab);
-  const uint32_t G = tv.h->n_groups;
-  const uint64_t q_off = tv.h->q_off;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
-  uint32_t fill = 0;  // wave-uniform
-  uint64_t* my_key = s_key[wave];
-  int2* my_val = s_val[wave];
+  Emitter em{s_key[wave], s_val[wave], kSpawnSeg, 0, cnt, step & 1u, step, ck_out, cv_out,
+             cap_child, ghist, passes};
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-
-  auto flush = [&]() {
-    wave_lds_fence();
-    uint64_t base = 0;
-    if (lane == 0) base = atomicAdd((unsigned long long*)&cnt->n_child[step & 1], (unsigned long long)fill);
-    base = __shfl(base, 0);
-    if (base + fill > cap_child) {
-      if (lane == 0) {
-        atomicOr(&cnt->err, kErrSpawnCap);
-        atomicMin(&cnt->err_step, step);
-      }
-    } else {
-      for (uint32_t i = lane; i < fill; i += kWave) {
-        ck_out[base + i] = my_key[i];
-        cv_out[base + i] = my_val[i];
-      }
-    }
-    wave_lds_fence();
-    fill = 0;
-  };
-
-  if (G > 1) {
+  if (tv.h->n_groups > 1) {
     for (uint64_t wbase = (uint64_t)blockIdx.x * kBlock + wave * kWave; wbase < np;
          wbase += stride) {
       const uint64_t p = wbase + lane;
       const bool valid = p < np;
       uint64_t ck = 0;
       int2 v = make_int2(0, 0);
-      uint32_t w[4] = {0, 0, 0, 0};
-      bool active = false;
       if (valid) {
         ck = pk[p];
         v = pv[p];
-        walker_random(kl.key(ck), step, kl.replica(ck), seed, w);
-        const uint64_t s = uabs64(v.x) + uabs64(v.y);
-        active = !comb_all_zero(s, q_off, w[0]);
       }
-      if (__ballot(active) == 0) continue;
-      const uint64_t key = kl.key(ck);
-      uint64_t r = w[0];
-      for (uint32_t g = 1; g < G; ++g) {
-        int2 child = make_int2(0, 0);
-        if (active) {
-          int32_t cre, cim;
-          group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
-          int64_t xre, xim;
-          cmul_q32(v.x, v.y, cre, cim, xre, xim);
-          child.x = (int32_t)comb_step(r, xre);
-          child.y = (int32_t)comb_step(r, xim);
-        }
-        const bool has = (child.x | child.y) != 0;
-        const uint64_t m = __ballot(has);
-        if (m == 0) continue;
-        if (has) {
-          const uint32_t pos = fill + mbcnt64(m);
-          my_key[pos] = ck ^ tv.gx[g];
-          my_val[pos] = child;
-        }
-        fill += (uint32_t)__popcll(m);
-        if (fill > kSpawnSeg - kWave) flush();
-      }
+      spawn_parent(em, tv, valid, ck, v, step, seed, kl);
     }
   }
-  if (fill) flush();
+  if (em.fill) em.flush();
 }
 
-// ---------------------------------------------------------------------------------------------
-// LSD radix sort of (key, value) records, 8-bit digits, fixed grid of kSortBlocks blocks, each
-// owning one contiguous chunk; per-pass: digit histogram, exclusive scan, stable scatter.
-// ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ void chunk_range(uint64_t n, uint64_t& b, uint64_t& e) {
-  const uint64_t per = ((n + kSortBlocks - 1) / kSortBlocks + kBlock - 1) / kBlock * kBlock;
-  b = per * blockIdx.x;
-  e = b + per;
-  if (b > n) b = n;
-  if (e > n) e = n;
-}
-
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys,
+// Digit histograms of n_child[nsel] records (used where records did not come from a spawn).
+__global__ __launch_bounds__(kBlock) void k_digit_hist(const uint64_t* __restrict__ keys,
                                                        const Counters* __restrict__ cnt,
-                                                       uint32_t nsel, uint32_t shift,
-                                                       uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRadixBins];
+                                                       uint32_t nsel, uint32_t passes,
+                                                       uint32_t* __restrict__ ghist) {
   if (cnt->err) return;
   const uint64_t n = cnt->n_child[nsel];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  uint64_t b, e;
-  chunk_range(n, b, e);
-  for (uint64_t i = b + threadIdx.x; i < e; i += kBlock)
-    atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadixBins - 1)], 1u);
-  __syncthreads();
-  hist[threadIdx.x * kSortBlocks + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive scan of kRadixBins * kSortBlocks counts (digit-major), one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist,
-                                                     const Counters* __restrict__ cnt) {
-  constexpr int N = kRadixBins * kSortBlocks;
-  constexpr int PER = N / 1024;
-  __shared__ uint32_t part[1024];
-  if (cnt->err) return;
-  uint32_t loc[PER];
-  uint32_t s = 0;
-  const int base = threadIdx.x * PER;
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    loc[i] = hist[base + i];
-    s += loc[i];
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[threadIdx.x] - s;
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    hist[base + i] = run;
-    run += loc[i];
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); base < n;
+       base += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t i = base + __lane_id();
+    const bool v = i < n;
+    const uint64_t k = v ? keys[i] : 0;
+    const uint64_t act = __ballot(v);
+    for (uint32_t p = 0; p < passes; ++p) {
+      const uint32_t d = digit_of(k, p * kRadixBits);
+      const uint64_t peers = match_digit(d, act);
+      if (v && (peers & lanemask_lt()) == 0)
+        atomicAdd(&ghist[p * kRadixBins + d], (uint32_t)__popcll(peers));
+    }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+// ---------------------------------------------------------------------------------------------
+// k_onesweep: one LSD radix pass.  Tiles of kSortTile records are taken in order from a ticket
+// counter; wave w of a block ranks records [w*1024, (w+1)*1024) of the tile stably in LDS; the
+// tile's per-digit counts are published and the exclusive prefix over earlier tiles is found by
+// decoupled look-back (Merrill & Garland), one status word per (tile, digit).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint32_t flag, uint64_t v) {
+  return ((uint64_t)(epoch & 0xFFFFu) << 48) | ((uint64_t)flag << 46) | (v & ((1ull << 46) - 1));
+}
+__device__ __forceinline__ uint32_t lb_epoch(uint64_t s) { return (uint32_t)(s >> 48); }
+__device__ __forceinline__ uint32_t lb_flag(uint64_t s) { return (uint32_t)(s >> 46) & 3u; }
+__device__ __forceinline__ uint64_t lb_value(uint64_t s) { return s & ((1ull << 46) - 1); }
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Exclusive prefix of `tile` by decoupled look-back, executed by all 64 lanes of one wave: each
+// round reads 64 predecessors at once, and stops at the nearest one with an inclusive prefix.
+// Returns false if a predecessor did not publish within the spin limit.
+__device__ bool lookback_wave(const uint64_t* status, uint32_t tile, uint32_t epoch,
+                              uint64_t& prefix) {
+  const uint32_t lane = __lane_id();
+  const uint32_t ep = epoch & 0xFFFFu;
+  prefix = 0;
+  int64_t hi = (int64_t)tile - 1;
+  uint32_t spins = 0;
+  while (hi >= 0) {
+    const int64_t j = hi - (int64_t)lane;
+    uint64_t s = 0;
+    bool ready = true, inc = true;
+    if (j >= 0) {
+      s = atomic_load_agent(&status[j]);
+      ready = lb_epoch(s) == ep && lb_flag(s) != 0;
+      inc = ready && lb_flag(s) == 2;
+    }
+    const uint64_t inc_m = __ballot(inc);
+    const uint64_t wait_m = __ballot(!ready);
+    const uint32_t first = inc_m ? (uint32_t)__ffsll((unsigned long long)inc_m) - 1 : 64u;
+    const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+    if (wait_m & need) {
+      if (++spins > (1u << 22)) return false;
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    prefix += wave_sum64((lane <= first && j >= 0) ? lb_value(s) : 0);
+    if (first < 64) break;
+    hi -= 64;
+  }
+  return true;
+}
+
+// Merge-path split for diagonal d computed by one wave with 64-ary search (few dependent
+// rounds instead of log2 of them): the number of A elements among the first d of the merge,
+// A winning ties.
+template <class KA, class KB>
+__device__ uint32_t merge_path_wave(const KA& A, uint32_t na, const KB& B, uint32_t nb,
+                                    uint32_t d) {
+  const uint32_t lane = __lane_id();
+  uint32_t lo = d > nb ? d - nb : 0u;
+  uint32_t hi = d < na ? d : na;
+  // invariant: answer in [lo, hi]; pred(p) = A[p] <= B[d-1-p] holds exactly for p < answer
+  while (hi - lo > 64) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t p = lo + lane * step;
+    const bool t = p < hi && A(p) <= B(d - 1 - p);
+    const uint32_t c = (uint32_t)__popcll(__ballot(t));
+    const uint32_t nlo = c ? lo + (c - 1) * step + 1 : lo;
+    const uint32_t nhi = lo + c * step < hi ? lo + c * step : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  const uint32_t p = lo + lane;
+  const bool t = p < hi && A(p) <= B(d - 1 - p);
+  return lo + (uint32_t)__popcll(__ballot(t));
+}
+
+__global__ __launch_bounds__(kBlock) void k_onesweep(
     const uint64_t* __restrict__ kin, const int2* __restrict__ vin, uint64_t* __restrict__ kout,
-    int2* __restrict__ vout, const Counters* __restrict__ cnt, uint32_t nsel, uint32_t shift,
-    const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t off[kRadixBins];
-  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    int2* __restrict__ vout, Counters* __restrict__ cnt, uint32_t nsel, uint32_t pass,
+    const uint32_t* __restrict__ ghist, uint64_t* __restrict__ status, uint32_t epoch,
+    uint32_t step) {
+  constexpr int DPT = kRadixBins / kBlock;  // digits per thread
+  __shared__ uint32_t s_gbase[kRadixBins];
+  __shared__ uint32_t s_wcnt[kWaves][kRadixBins];
+  __shared__ uint32_t s_pref[kRadixBins];
+  __shared__ uint32_t s_part[kBlock];
+  __shared__ uint32_t s_tile;
   if (cnt->err) return;
   const uint64_t n = cnt->n_child[nsel];
-  const uint32_t wave = threadIdx.x / kWave;
-  off[threadIdx.x] = hist[threadIdx.x * kSortBlocks + blockIdx.x];
-  for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
+  const uint32_t ntiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  const uint32_t shift = pass * kRadixBits;
+  const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = __lane_id();
+  const uint32_t* gh = ghist + pass * kRadixBins;
+  uint32_t* ticket = &cnt->sort_ticket[nsel][pass];
+
+  // First ticket before the prologue, so blocks without a tile leave at once.
+  if (tid == 0) s_tile = atomicAdd(ticket, 1u);
   __syncthreads();
-  uint64_t b, e;
-  chunk_range(n, b, e);
-  const uint64_t lt = lanemask_lt();
-  for (uint64_t base = b; base < e; base += kBlock) {
-    const uint64_t i = base + threadIdx.x;
-    const bool valid = i < e;
-    uint64_t k = 0;
-    int2 v = make_int2(0, 0);
-    uint32_t d = 0;
-    if (valid) {
-      k = kin[i];
-      v = vin[i];
-      d = (uint32_t)(k >> shift) & (kRadixBins - 1);
-    }
-    uint64_t peers = __ballot(valid);
+  if (s_tile >= ntiles) return;
+  // Global exclusive digit offsets of this pass (thread t owns digits t*DPT .. t*DPT+DPT-1).
+  {
+    uint32_t loc[DPT], s = 0;
 #pragma unroll
-    for (int bit = 0; bit < kRadixBits; ++bit) {
-      const uint64_t bm = __ballot((d >> bit) & 1u);
-      peers &= ((d >> bit) & 1u) ? bm : ~bm;
+    for (int i = 0; i < DPT; ++i) {
+      loc[i] = gh[tid * DPT + i];
+      s += loc[i];
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    s_part[tid] = s;
     __syncthreads();
-    if (valid) {
-      uint32_t pos = off[d] + rank;
-      for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][d];
-      kout[pos] = k;
-      vout[pos] = v;
+    for (int o = 1; o < kBlock; o <<= 1) {
+      const uint32_t v = tid >= (uint32_t)o ? s_part[tid - o] : 0u;
+      __syncthreads();
+      s_part[tid] += v;
+      __syncthreads();
+    }
+    uint32_t run = s_part[tid] - s;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      s_gbase[tid * DPT + i] = run;
+      run += loc[i];
+    }
+  }
+  const uint64_t lt = lanemask_lt();
+  bool first_tile = true;
+
+  while (true) {
+    if (tid == 0 && !first_tile) s_tile = atomicAdd(ticket, 1u);
+    first_tile = false;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i)
+      for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid * DPT + i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const uint64_t tbase = (uint64_t)tile * kSortTile + (uint64_t)wave * (kSortIpt * kWave);
+    uint64_t key[kSortIpt];
+    int2 val[kSortIpt];
+    uint32_t rk[kSortIpt];
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k) {
+      const uint64_t i = tbase + (uint64_t)k * kWave + lane;
+      const bool v = i < n;
+      key[k] = v ? kin[i] : 0;
+      val[k] = v ? vin[i] : make_int2(0, 0);
+      const uint32_t d = digit_of(key[k], shift);
+      const uint64_t peers = match_digit(d, __ballot(v));
+      const uint32_t before = (uint32_t)__popcll(peers & lt);
+      uint32_t seen = 0;
+      if (v) seen = s_wcnt[wave][d];
+      rk[k] = seen + before;
+      wave_lds_fence();
+      if (v && before == 0) s_wcnt[wave][d] = seen + (uint32_t)__popcll(peers);
+      wave_lds_fence();
     }
     __syncthreads();
-    {
-      const uint32_t dd = threadIdx.x;
-      uint32_t add = 0;
+    // Per digit: exclusive prefix over waves, and the tile total.
+    uint32_t tot[DPT];
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const uint32_t d = tid * DPT + i;
+      uint32_t run = 0;
       for (int w = 0; w < kWaves; ++w) {
-        add += wcnt[w][dd];
-        wcnt[w][dd] = 0;
+        const uint32_t c = s_wcnt[w][d];
+        s_wcnt[w][d] = run;
+        run += c;
       }
-      off[dd] += add;
+      tot[i] = run;
+    }
+    // Publish and look back (all DPT digits of a thread advance through predecessors together).
+    uint64_t* row = status + (uint64_t)tile * kRadixBins + tid * DPT;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i)
+      atomic_store_agent(&row[i], lb_pack(epoch, tile == 0 ? 2 : 1, tot[i]));
+    uint32_t pref[DPT];
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) pref[i] = 0;
+    if (tile > 0) {
+      uint32_t done = 0;  // bit i: digit i has reached an inclusive predecessor
+      int32_t j = (int32_t)tile - 1;
+      uint32_t spins = 0;
+      while (done != (1u << DPT) - 1 && j >= 0) {
+        const uint64_t* prow = status + (uint64_t)j * kRadixBins + tid * DPT;
+        uint64_t sw[DPT];
+        bool ready = true;
+#pragma unroll
+        for (int i = 0; i < DPT; ++i) {
+          sw[i] = ((done >> i) & 1u) ? 0 : atomic_load_agent(&prow[i]);
+          if (!((done >> i) & 1u) &&
+              (lb_epoch(sw[i]) != (epoch & 0xFFFFu) || lb_flag(sw[i]) == 0))
+            ready = false;
+        }
+        if (!ready) {
+          if (++spins > (1u << 22)) {
+            atomicOr(&cnt->err, kErrLookback);
+            atomicMin(&cnt->err_step, step);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+#pragma unroll
+        for (int i = 0; i < DPT; ++i) {
+          if ((done >> i) & 1u) continue;
+          pref[i] += (uint32_t)lb_value(sw[i]);
+          if (lb_flag(sw[i]) == 2) done |= 1u << i;
+        }
+        --j;
+      }
+#pragma unroll
+      for (int i = 0; i < DPT; ++i)
+        atomic_store_agent(&row[i], lb_pack(epoch, 2, pref[i] + tot[i]));
+    }
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) s_pref[tid * DPT + i] = s_gbase[tid * DPT + i] + pref[i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k) {
+      const uint64_t i = tbase + (uint64_t)k * kWave + lane;
+      if (i < n) {
+        const uint32_t d = digit_of(key[k], shift);
+        const uint32_t pos = s_pref[d] + s_wcnt[wave][d] + rk[k];
+        if (pos < n) {
+          kout[pos] = key[k];
+          vout[pos] = val[k];
+        } else {
+          atomicOr(&cnt->err, kErrLookback);  // inconsistent digit histogram: refuse the write
+          atomicMin(&cnt->err_step, step);
+        }
+      }
     }
     __syncthreads();
   }
@@ -271,315 +409,331 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
 // Merge of parents (unique keys) with sorted children, split into tiles whose boundaries never
 // cut a key's run (parents win ties, so a run is [parent] children...).
 // ---------------------------------------------------------------------------------------------
-template <class KA, class KB>
-__device__ __forceinline__ uint32_t merge_path(const KA& A, uint32_t na, const KB& B, uint32_t nb,
-                                               uint32_t d) {
-  uint32_t lo = d > nb ? d - nb : 0u;
-  uint32_t hi = d < na ? d : na;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (A(mid) <= B(d - 1 - mid))
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Split at diagonal d moved forward past the run of the key just before it.
-template <class KA, class KB>
-__device__ __forceinline__ void run_split(const KA& A, uint32_t na, const KB& B, uint32_t nb,
-                                          uint32_t d, uint32_t& i, uint32_t& j) {
-  i = merge_path(A, na, B, nb, d);
-  j = d - i;
-  if (d == 0 || d >= na + nb) return;
-  uint64_t last = 0;
-  if (i > 0) last = A(i - 1);
-  if (j > 0) {
-    const uint64_t c = B(j - 1);
-    if (i == 0 || c > last) last = c;
-  }
-  // Only children can continue the run (a parent equal to `last` would precede it).
-  uint32_t lo = j, hi = nb;
-  if (hi - lo > (uint32_t)kMergeSlack) hi = lo + kMergeSlack;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (B(mid) <= last)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  j = lo;
-}
-
+// Split points (one wave per tile boundary), plus the per-step resets of the counters the next
+// step's kernels use.
 __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restrict__ pk,
                                                        const uint64_t* __restrict__ ckeys,
                                                        Counters* __restrict__ cnt, uint32_t cur,
                                                        uint32_t csel, uint2* __restrict__ splits,
-                                                       uint32_t max_tiles) {
+                                                       uint32_t max_tiles,
+                                                       uint32_t* __restrict__ ghist_next) {
   if (cnt->err) return;
+  const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
+  // The next step's child counter, sort tickets and digit histograms were last used two steps
+  // ago; this step's merge, which spawns the next step's children, runs after this kernel.
+  for (uint32_t i = gt; i < (uint32_t)(kMaxPasses * kRadixBins); i += gridDim.x * kBlock)
+    ghist_next[i] = 0;
+  if (gt == 0) {
+    cnt->tile_counter = 0;
+    cnt->n_child[csel ^ 1] = 0;
+    for (int p = 0; p < kMaxPasses + 2; ++p) cnt->sort_ticket[csel ^ 1][p] = 0;
+  }
   const uint32_t np = (uint32_t)cnt->n_store[cur];
   const uint32_t nc = (uint32_t)cnt->n_child[csel];
   const uint32_t total = np + nc;
   const uint32_t ntiles = (total + kMergeTile - 1) / kMergeTile;
-  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-  if (t == 0) {
-    cnt->tile_counter = 0;
-    cnt->n_child[csel ^ 1] = 0;  // counter of the next step's children (last used two steps ago)
-  }
-  if (t > ntiles || t > max_tiles) return;
-  uint32_t d = t * kMergeTile;
-  if (d > total) d = total;
+  const uint32_t lane = __lane_id();
   auto A = [&](uint32_t x) { return pk[x]; };
   auto B = [&](uint32_t x) { return ckeys[x]; };
-  uint32_t i, j;
-  run_split(A, np, B, nc, d, i, j);
-  splits[t] = make_uint2(i, j);
+  for (uint32_t t = gt / kWave; t <= ntiles && t <= max_tiles; t += gridDim.x * kWaves) {
+    uint32_t d = t * kMergeTile;
+    if (d > total) d = total;
+    const uint32_t i = merge_path_wave(A, np, B, nc, d);
+    uint32_t j = d - i;
+    if (d > 0 && d < total) {
+      uint64_t last = 0;
+      if (i > 0) last = A(i - 1);
+      if (j > 0) {
+        const uint64_t c = B(j - 1);
+        if (i == 0 || c > last) last = c;
+      }
+      // children continuing the run of `last` (at most one per column group)
+      for (int r = 0; r < (kMergeSlack + kWave - 1) / kWave; ++r) {
+        const uint32_t q = j + lane;
+        const uint64_t m = __ballot(q < nc && B(q) <= last);
+        const uint32_t c = (uint32_t)__popcll(m);
+        j += c;
+        if (c < (uint32_t)kWave) break;
+      }
+    }
+    if (lane == 0) splits[t] = make_uint2(i, j);
+  }
 }
 
-// Look-back status word: epoch (16) | flag (2) | value (46).
-__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint32_t flag, uint64_t v) {
-  return ((uint64_t)(epoch & 0xFFFFu) << 48) | ((uint64_t)flag << 46) | (v & ((1ull << 46) - 1));
-}
+struct MergeArgs {
+  const uint64_t* pk;
+  const int2* pv;
+  const uint64_t* ckeys;
+  const int2* cvals;
+  Counters* cnt;
+  uint32_t cur, csel;
+  const uint2* splits;
+  uint64_t* status;
+  uint32_t epoch;
+  const uint8_t* tab;        // table of step s (death)
+  const uint8_t* tab_next;   // table of step s+1 (spawn), or null
+  const int64_t* qshift;
+  uint32_t step;
+  uint64_t seed;
+  KeyLayout kl;
+  uint64_t* ok;
+  int2* ov;
+  uint64_t cap_store;
+  uint64_t* ck_next;         // children of step s+1
+  int2* cv_next;
+  uint64_t cap_child;
+  uint32_t* ghist_next;
+  uint32_t passes;
+};
 
-__global__ __launch_bounds__(kBlock) void k_merge(
-    const uint64_t* __restrict__ pk, const int2* __restrict__ pv,
-    const uint64_t* __restrict__ ckeys, const int2* __restrict__ cvals, Counters* __restrict__ cnt,
-    uint32_t cur, uint32_t csel, const uint2* __restrict__ splits, uint64_t* __restrict__ status,
-    uint32_t epoch, const uint8_t* __restrict__ tab, const int64_t* __restrict__ qshift,
-    uint32_t step, uint64_t seed, KeyLayout kl, uint64_t* __restrict__ ok,
-    int2* __restrict__ ov, uint64_t cap_store) {
-  constexpr int CAP = kMergeTile + kMergeSlack + 8;
+__global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
+  constexpr int CAP = kMergeCap;
   __shared__ uint64_t s_pk[CAP];
   __shared__ int64_t s_pre[CAP];
   __shared__ int64_t s_pim[CAP];
-  __shared__ uint64_t s_ck[CAP];
+  __shared__ uint64_t s_ck[CAP];   // children of the tile; later the spawn staging
   __shared__ int2 s_cv[CAP];
+  __shared__ uint64_t s_ok[CAP];   // annihilated outputs of the tile
+  __shared__ int2 s_ov[CAP];
   __shared__ uint32_t s_scan[kBlock];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base;
   __shared__ uint64_t s_ws[kWaves];
+  static_assert(kWaves * kMergeSpawnSeg <= CAP, "spawn staging must fit the child tile");
 
+  Counters* cnt = A.cnt;
   if (cnt->err) return;
-  const uint32_t np = (uint32_t)cnt->n_store[cur];
-  const uint32_t nc = (uint32_t)cnt->n_child[csel];
+  const uint32_t np = (uint32_t)cnt->n_store[A.cur];
+  const uint32_t nc = (uint32_t)cnt->n_child[A.csel];
   const uint32_t total = np + nc;
   const uint32_t ntiles = (total + kMergeTile - 1) / kMergeTile;
-  if (threadIdx.x == 0) {
-    s_tile = atomicAdd(&cnt->tile_counter, 1u);
-    if (ntiles == 0 && blockIdx.x == 0) cnt->n_store[cur ^ 1] = 0;
-  }
-  __syncthreads();
-  const uint32_t tile = s_tile;
-  if (tile >= ntiles) return;
-  const uint2 s0 = splits[tile], s1 = splits[tile + 1];
-  if (s1.x < s0.x || s1.y < s0.y || (s1.x - s0.x) + (s1.y - s0.y) > (uint32_t)CAP ||
-      s1.x > np || s1.y > nc) {
-    // cannot happen for runs shorter than the slack; refuse rather than overrun LDS
-    if (threadIdx.x == 0) {
-      atomicOr(&cnt->err, kErrLookback);
-      atomicMin(&cnt->err_step, step);
-      atomic_store_agent(&status[tile], lb_pack(epoch, 2, 0));
-    }
+  if (ntiles == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_store[A.cur ^ 1] = 0;
     return;
   }
-  const uint32_t pa = s0.x, pn = s1.x - s0.x;
-  const uint32_t ca = s0.y, cn = s1.y - s0.y;
-
-  // Load parents with their death/cloning update (diagonal of the column, applied to N(s)).
-  const TableView tv = table_view(tab);
+  const TableView tv = table_view(A.tab);
   const uint32_t d_end = tv.h->n_groups > 0 ? tv.gs[1] : 0u;
   const uint64_t q_diag = tv.h->q_diag;
-  uint64_t wsum = 0;
-  for (uint32_t x = threadIdx.x; x < pn; x += kBlock) {
-    const uint64_t ck = pk[pa + x];
-    const int2 v = pv[pa + x];
-    const uint32_t rep = kl.replica(ck);
-    const int64_t qs = qshift[rep];
-    int64_t a = v.x, b = v.y;
-    uint32_t w[4];
-    walker_random(kl.key(ck), step, rep, seed, w);
-    const uint64_t sab = uabs64(a) + uabs64(b);
-    wsum += sab;
-    if (!comb_all_zero(sab, q_diag + uabs64(qs), w[1])) {
-      int32_t dre, dim;
-      group_coeff(tv.t, 0, d_end, kl.key(ck), dre, dim);
-      int64_t xre, xim;
-      cmul_q32(a, b, dre + (int32_t)qs, dim, xre, xim);
-      uint64_t r = w[1];
-      const int64_t nre = comb_step(r, xre);
-      const int64_t nim = comb_step(r, xim);
-      a += nre;
-      b += nim;
-    }
-    s_pk[x] = ck;
-    s_pre[x] = a;
-    s_pim[x] = b;
-  }
-  for (uint32_t x = threadIdx.x; x < cn; x += kBlock) {
-    s_ck[x] = ckeys[ca + x];
-    s_cv[x] = cvals[ca + x];
-  }
-  // walker statistics of the parents of this step
-  for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
-  if (__lane_id() == 0) s_ws[threadIdx.x / kWave] = wsum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t = 0;
-    for (int w = 0; w < kWaves; ++w) t += s_ws[w];
-    atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)t);
-    atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)pn);
-  }
+  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
+  const KeyLayout kl = A.kl;
 
-  // Per-thread ranges of the local merge, cut only at run ends.
-  auto A = [&](uint32_t x) { return s_pk[x]; };
-  auto B = [&](uint32_t x) { return s_ck[x]; };
-  const uint32_t tot = pn + cn;
-  uint32_t d0 = threadIdx.x * kMergeIpt, d1 = d0 + kMergeIpt;
-  if (d0 > tot) d0 = tot;
-  if (d1 > tot) d1 = tot;
-  uint32_t i0, j0, i1, j1;
-  run_split(A, pn, B, cn, d0, i0, j0);
-  run_split(A, pn, B, cn, d1, i1, j1);
-  if (threadIdx.x == kBlock - 1) {
-    i1 = pn;
-    j1 = cn;
-  }
-  if (i1 + j1 < i0 + j0) {  // an earlier thread's run already covers this range
-    i1 = i0;
-    j1 = j0;
-  }
-
-  // Pass 1: count nonzero outputs.
-  uint32_t count = 0;
-  bool overflow = false;
-  {
-    uint32_t i = i0, j = j0;
-    while (i < i1 || j < j1) {
-      uint64_t k;
-      int64_t re = 0, im = 0;
-      if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
-        k = s_pk[i];
-        re = s_pre[i];
-        im = s_pim[i];
-        ++i;
-      } else {
-        k = s_ck[j];
-      }
-      while (j < j1 && s_ck[j] == k) {
-        re += s_cv[j].x;
-        im += s_cv[j].y;
-        ++j;
-      }
-      if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
-      count += (re != 0 || im != 0) ? 1u : 0u;
-    }
-  }
-  if (overflow) {
-    atomicOr(&cnt->err, kErrOverflow);
-    atomicMin(&cnt->err_step, step);
-  }
-
-  // Block exclusive scan of counts.
-  s_scan[threadIdx.x] = count;
-  __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0u;
+  while (true) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->tile_counter, 1u);
     __syncthreads();
-    s_scan[threadIdx.x] += v;
-    __syncthreads();
-  }
-  const uint32_t excl = s_scan[threadIdx.x] - count;
-  const uint32_t agg = s_scan[kBlock - 1];
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const uint2 s0 = A.splits[tile], s1 = A.splits[tile + 1];
+    if (s1.x < s0.x || s1.y < s0.y || (s1.x - s0.x) + (s1.y - s0.y) > (uint32_t)CAP ||
+        s1.x > np || s1.y > nc) {
+      // cannot happen for runs shorter than the slack; refuse rather than overrun LDS
+      if (threadIdx.x == 0) {
+        atomicOr(&cnt->err, kErrLookback);
+        atomicMin(&cnt->err_step, A.step);
+        atomic_store_agent(&A.status[tile], lb_pack(A.epoch, 2, 0));
+      }
+      __syncthreads();
+      continue;
+    }
+    const uint32_t pa = s0.x, pn = s1.x - s0.x;
+    const uint32_t ca = s0.y, cn = s1.y - s0.y;
 
-  // Decoupled look-back (Merrill & Garland) for the tile's output offset.
-  if (threadIdx.x == 0) {
-    uint64_t prefix = 0;
-    if (tile == 0) {
-      atomic_store_agent(&status[0], lb_pack(epoch, 2, agg));
-    } else {
-      atomic_store_agent(&status[tile], lb_pack(epoch, 1, agg));
-      int32_t j = (int32_t)tile - 1;
-      uint32_t spins = 0;
-      while (j >= 0) {
-        const uint64_t sw = atomic_load_agent(&status[j]);
-        const uint32_t ep = (uint32_t)(sw >> 48), fl = (uint32_t)(sw >> 46) & 3u;
-        if (ep != (epoch & 0xFFFFu) || fl == 0) {
-          if (++spins > (1u << 24)) {
-            atomicOr(&cnt->err, kErrLookback);
-            atomicMin(&cnt->err_step, step);
-            break;
+    // Parents with their death/cloning update (diagonal of the column, applied to N(s)).
+    uint64_t wsum = 0;
+    for (uint32_t x = threadIdx.x; x < pn; x += kBlock) {
+      const uint64_t ck = A.pk[pa + x];
+      const int2 v = A.pv[pa + x];
+      const uint32_t rep = kl.replica(ck);
+      const int64_t qs = A.qshift[rep];
+      int64_t a = v.x, b = v.y;
+      uint32_t w[4];
+      walker_random(kl.key(ck), A.step, rep, A.seed, w);
+      const uint64_t sab = uabs64(a) + uabs64(b);
+      wsum += sab;
+      if (!comb_all_zero(sab, q_diag + uabs64(qs), w[1])) {
+        int32_t dre, dim;
+        group_coeff(tv.t, 0, d_end, kl.key(ck), dre, dim);
+        int64_t xre, xim;
+        cmul_q32(a, b, dre + (int32_t)qs, dim, xre, xim);
+        uint64_t r = w[1];
+        a += comb_step(r, xre);
+        b += comb_step(r, xim);
+      }
+      s_pk[x] = ck;
+      s_pre[x] = a;
+      s_pim[x] = b;
+    }
+    for (uint32_t x = threadIdx.x; x < cn; x += kBlock) {
+      s_ck[x] = A.ckeys[ca + x];
+      s_cv[x] = A.cvals[ca + x];
+    }
+    for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+    if (lane == 0) s_ws[wave] = wsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+      for (int w = 0; w < kWaves; ++w) t += s_ws[w];
+      atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)t);
+      atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)pn);
+    }
+
+    // Per-thread ranges of the local merge, cut only at run ends.
+    auto KA = [&](uint32_t x) { return s_pk[x]; };
+    auto KB = [&](uint32_t x) { return s_ck[x]; };
+    const uint32_t tot = pn + cn;
+    uint32_t d0 = threadIdx.x * kMergeIpt, d1 = d0 + kMergeIpt;
+    if (d0 > tot) d0 = tot;
+    if (d1 > tot) d1 = tot;
+    uint32_t i0, j0, i1, j1;
+    run_split(KA, pn, KB, cn, d0, i0, j0);
+    run_split(KA, pn, KB, cn, d1, i1, j1);
+    if (threadIdx.x == kBlock - 1) {
+      i1 = pn;
+      j1 = cn;
+    }
+
+    // Pass 1: count nonzero outputs.
+    uint32_t count = 0;
+    bool overflow = false;
+    {
+      uint32_t i = i0, j = j0;
+      while (i < i1 || j < j1) {
+        uint64_t k;
+        int64_t re = 0, im = 0;
+        if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
+          k = s_pk[i];
+          re = s_pre[i];
+          im = s_pim[i];
+          ++i;
+        } else {
+          k = s_ck[j];
+        }
+        while (j < j1 && s_ck[j] == k) {
+          re += s_cv[j].x;
+          im += s_cv[j].y;
+          ++j;
+        }
+        if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
+        count += (re != 0 || im != 0) ? 1u : 0u;
+      }
+    }
+    if (overflow) {
+      atomicOr(&cnt->err, kErrOverflow);
+      atomicMin(&cnt->err_step, A.step);
+    }
+
+    // Block exclusive scan of counts.
+    s_scan[threadIdx.x] = count;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+      const uint32_t v = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0u;
+      __syncthreads();
+      s_scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const uint32_t excl = s_scan[threadIdx.x] - count;
+    const uint32_t agg = s_scan[kBlock - 1];
+
+    // Decoupled look-back for the tile's output offset (wave 0, 64 predecessors per round).
+    if (threadIdx.x == 0)
+      atomic_store_agent(&A.status[tile], lb_pack(A.epoch, tile == 0 ? 2 : 1, agg));
+    if (wave == 0) {
+      uint64_t prefix = 0;
+      bool ok = true;
+      if (tile > 0) ok = lookback_wave(A.status, tile, A.epoch, prefix);
+      if (lane == 0) {
+        if (!ok) {
+          atomicOr(&cnt->err, kErrLookback);
+          atomicMin(&cnt->err_step, A.step);
+        }
+        if (tile > 0) atomic_store_agent(&A.status[tile], lb_pack(A.epoch, 2, prefix + agg));
+        s_base = prefix;
+        if (tile == ntiles - 1) {
+          cnt->n_store[A.cur ^ 1] = prefix + agg;
+          atomicAdd((unsigned long long*)&cnt->child_steps, (unsigned long long)nc);
+          atomicAdd((unsigned long long*)&cnt->out_steps, (unsigned long long)(prefix + agg));
+          if (prefix + agg > A.cap_store) {
+            atomicOr(&cnt->err, kErrStoreCap);
+            atomicMin(&cnt->err_step, A.step);
           }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        prefix += sw & ((1ull << 46) - 1);
-        if (fl == 2) break;
-        --j;
-      }
-      atomic_store_agent(&status[tile], lb_pack(epoch, 2, prefix + agg));
-    }
-    s_base = prefix;
-    if (tile == ntiles - 1) {
-      cnt->n_store[cur ^ 1] = prefix + agg;
-      atomicAdd((unsigned long long*)&cnt->child_steps, (unsigned long long)nc);
-      atomicAdd((unsigned long long*)&cnt->out_steps, (unsigned long long)(prefix + agg));
-      if (prefix + agg > cap_store) {
-        atomicOr(&cnt->err, kErrStoreCap);
-        atomicMin(&cnt->err_step, step);
       }
     }
-  }
-  __syncthreads();
-  const uint64_t base = s_base + excl;
+    __syncthreads();
+    const uint64_t gbase = s_base;
 
-  // Pass 2: write the annihilated, compacted records.
-  {
-    uint32_t i = i0, j = j0;
-    uint64_t o = base;
-    while (i < i1 || j < j1) {
-      uint64_t k;
-      int64_t re = 0, im = 0;
-      if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
-        k = s_pk[i];
-        re = s_pre[i];
-        im = s_pim[i];
-        ++i;
-      } else {
-        k = s_ck[j];
-      }
-      while (j < j1 && s_ck[j] == k) {
-        re += s_cv[j].x;
-        im += s_cv[j].y;
-        ++j;
-      }
-      if (re != 0 || im != 0) {
-        if (o < cap_store) {
-          ok[o] = k;
-          ov[o] = make_int2((int32_t)re, (int32_t)im);
+    // Pass 2: the annihilated, compacted records, to global memory and to LDS.
+    {
+      uint32_t i = i0, j = j0;
+      uint32_t o = excl;
+      while (i < i1 || j < j1) {
+        uint64_t k;
+        int64_t re = 0, im = 0;
+        if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
+          k = s_pk[i];
+          re = s_pre[i];
+          im = s_pim[i];
+          ++i;
+        } else {
+          k = s_ck[j];
         }
-        ++o;
+        while (j < j1 && s_ck[j] == k) {
+          re += s_cv[j].x;
+          im += s_cv[j].y;
+          ++j;
+        }
+        if (re != 0 || im != 0) {
+          const int2 v = make_int2((int32_t)re, (int32_t)im);
+          if (gbase + o < A.cap_store) {
+            A.ok[gbase + o] = k;
+            A.ov[gbase + o] = v;
+          }
+          s_ok[o] = k;
+          s_ov[o] = v;
+          ++o;
+        }
       }
     }
+    __syncthreads();
+
+    // Children of step s+1 from the outputs of this tile (the staging aliases the child tile).
+    if (A.tab_next) {
+      const TableView tn = table_view(A.tab_next);
+      Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
+                 cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child, A.ghist_next,
+                 A.passes};
+      for (uint32_t wb = wave * kWave; wb < agg; wb += kBlock) {
+        const uint32_t p = wb + lane;
+        const bool valid = p < agg;
+        const uint64_t ck = valid ? s_ok[p] : 0;
+        const int2 v = valid ? s_ov[p] : make_int2(0, 0);
+        spawn_parent(em, tn, valid, ck, v, A.step + 1, A.seed, kl);
+      }
+      if (em.fill) em.flush();
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Utility and estimator kernels.
 // ---------------------------------------------------------------------------------------------
-__global__ void k_batch_begin(Counters* cnt, uint32_t step, uint64_t* status, uint32_t n_status) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_batch_begin(Counters* cnt, uint64_t* status, uint64_t n_status,
+                              uint64_t* sort_status, uint64_t n_sort_status, uint32_t* ghist,
+                              uint32_t n_ghist) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   if (t == 0) {
     cnt->n_child[0] = 0;
     cnt->n_child[1] = 0;
     cnt->err = 0;
     cnt->err_step = 0xFFFFFFFFu;
+    cnt->tile_counter = 0;
+    for (int s = 0; s < 2; ++s)
+      for (int p = 0; p < kMaxPasses + 2; ++p) cnt->sort_ticket[s][p] = 0;
   }
-  for (uint32_t i = t; i < n_status; i += gridDim.x * blockDim.x) status[i] = 0;
-}
-
-__global__ void k_reset_child(Counters* cnt, uint32_t sel) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) cnt->n_child[sel] = 0;
+  for (uint64_t i = t; i < n_status; i += stride) status[i] = 0;
+  for (uint64_t i = t; i < n_sort_status; i += stride) sort_status[i] = 0;
+  for (uint64_t i = t; i < n_ghist; i += stride) ghist[i] = 0;
 }
 
 // In-place sign flips of an ideal diagonal Pauli pulse, or key transform into (ck, cv) for a
@@ -617,9 +771,8 @@ __global__ __launch_bounds__(kBlock) void k_copy_store(const uint64_t* __restric
                                                        const int2* __restrict__ vi,
                                                        uint64_t* __restrict__ ko,
                                                        int2* __restrict__ vo,
-                                                       const Counters* __restrict__ cnt,
-                                                       uint32_t csel) {
-  const uint64_t n = cnt->n_child[csel];
+                                                       const uint64_t* __restrict__ count) {
+  const uint64_t n = *count;
   for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < n;
        p += (uint64_t)gridDim.x * kBlock) {
     ko[p] = ki[p];
@@ -627,9 +780,6 @@ __global__ __launch_bounds__(kBlock) void k_copy_store(const uint64_t* __restric
   }
 }
 
-// Per-replica estimator numerators; blockIdx.y is the replica, whose segment of the sorted
-// store is found by binary search.  Output per replica (int64 words):
-//   [0] n_tot, [1] ndiag_re, [2] ndiag_im, [3] eps2_lo, [4] eps2_hi, [5..] pauli re/im pairs.
 __device__ __forceinline__ uint64_t lower_bound64(const uint64_t* __restrict__ a, uint64_t n,
                                                   uint64_t v) {
   uint64_t lo = 0, hi = n;
@@ -650,6 +800,9 @@ __device__ __forceinline__ void add_u128(unsigned long long* lo, unsigned long l
   if (old + v < old) atomicAdd(hi, 1ull);
 }
 
+// Per-replica estimator numerators; blockIdx.y is the replica, whose segment of the sorted
+// store is found by binary search.  Output per replica (int64 words):
+//   [0] n_tot, [1] ndiag_re, [2] ndiag_im, [3] eps2_lo, [4] eps2_hi, [5..] pauli re/im pairs.
 __global__ __launch_bounds__(kBlock) void k_observe(const uint64_t* __restrict__ pk,
                                                     const int2* __restrict__ pv,
                                                     const Counters* __restrict__ cnt, uint32_t cur,
@@ -663,7 +816,8 @@ __global__ __launch_bounds__(kBlock) void k_observe(const uint64_t* __restrict__
   const uint32_t rep = blockIdx.y;
   const uint64_t lo_ck = kl.kbits >= 64 ? 0 : ((uint64_t)rep << kl.kbits);
   const uint64_t seg_b = lower_bound64(pk, np, lo_ck);
-  const uint64_t seg_e = (kl.kbits >= 64) ? np : lower_bound64(pk, np, (uint64_t)(rep + 1) << kl.kbits);
+  const uint64_t seg_e =
+      (kl.kbits >= 64) ? np : lower_bound64(pk, np, (uint64_t)(rep + 1) << kl.kbits);
   for (uint32_t i = threadIdx.x; i < out_stride; i += kBlock) s_acc[i] = 0;
   __syncthreads();
   const uint64_t qm = n >= 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
@@ -738,14 +892,15 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t* __restrict__ 
   out[2 * t + 1] = b;
 }
 
-// ---------------------------------------------------------------------------------------------
-// Host-side launch wrappers.
-// ---------------------------------------------------------------------------------------------
 static inline uint32_t grid_for(uint64_t n, uint32_t cap_blocks) {
   uint64_t g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
   if (g > cap_blocks) g = cap_blocks;
   return (uint32_t)g;
+}
+
+static inline KeyLayout key_layout(uint32_t kbits) {
+  return KeyLayout{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1)};
 }
 
 }  // namespace qmc
@@ -754,68 +909,96 @@ using namespace qmc;
 
 extern "C" {
 
-int qmck_batch_begin(hipStream_t st, void* counters, uint32_t step, uint64_t* status,
-                     uint32_t n_status) {
-  uint32_t g = grid_for(n_status, 1024);
-  hipLaunchKernelGGL(k_batch_begin, dim3(g), dim3(kBlock), 0, st, (Counters*)counters, step,
-                     status, n_status);
+uint32_t qmck_sort_passes(uint32_t key_bits) {
+  return key_bits == 0 ? 1u : (key_bits + kRadixBits - 1) / kRadixBits;
+}
+
+int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t n_status,
+                     uint64_t* sort_status, uint64_t n_sort_status, uint32_t* ghist,
+                     uint32_t n_ghist) {
+  uint64_t big = n_status > n_sort_status ? n_status : n_sort_status;
+  uint32_t g = grid_for(big, 2048);
+  hipLaunchKernelGGL(k_batch_begin, dim3(g), dim3(kBlock), 0, st, (Counters*)counters, status,
+                     n_status, sort_status, n_sort_status, ghist, n_ghist);
   return (int)hipGetLastError();
 }
 
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
-               const uint8_t* tab, uint32_t step, uint64_t seed, uint32_t kbits,
-               uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents) {
-  KeyLayout kl{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1)};
-  uint32_t g = grid_for(max_parents, 4096);
+               const uint8_t* tab, uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ck,
+               int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
+               uint32_t passes) {
+  uint32_t g = grid_for(max_parents, 1024);
   hipLaunchKernelGGL(k_spawn, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, cur, tab,
-                     step, seed, kl, ck, cv, cap_child);
+                     step, seed, key_layout(kbits), ck, cv, cap_child, ghist, passes);
   return (int)hipGetLastError();
 }
 
-// Sorts n_child[nsel] records found in (k0, v0); returns in *in_second whether the result is in
-// (k1, v1).
+int qmck_digit_hist(hipStream_t st, const uint64_t* keys, void* counters, uint32_t nsel,
+                    uint32_t passes, uint32_t* ghist, uint64_t max_items) {
+  uint32_t g = grid_for(max_items, 1024);
+  hipLaunchKernelGGL(k_digit_hist, dim3(g), dim3(kBlock), 0, st, keys, (const Counters*)counters,
+                     nsel, passes, ghist);
+  return (int)hipGetLastError();
+}
+
+// Sorts n_child[nsel] records found in buffer pair `src` (0/1 of (k0,v0)/(k1,v1)); the result
+// lands in pair src ^ (passes & 1).
 int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
-              uint32_t nsel, uint32_t key_bits, uint32_t* hist, int* in_second) {
-  uint32_t passes = (key_bits + kRadixBits - 1) / kRadixBits;
-  uint64_t* ka = k0;
-  int2* va = v0;
-  uint64_t* kb = k1;
-  int2* vb = v1;
+              uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint64_t* sort_status,
+              uint32_t step, uint32_t src, uint64_t max_items) {
+  uint64_t* kb[2] = {k0, k1};
+  int2* vb[2] = {v0, v1};
+  const uint64_t max_tiles = (max_items + kSortTile - 1) / kSortTile;
+  const uint32_t g = (uint32_t)(max_tiles < (uint64_t)kPersistBlocks ? (max_tiles ? max_tiles : 1)
+                                                                       : kPersistBlocks);
+  uint32_t s = src;
   for (uint32_t p = 0; p < passes; ++p) {
-    const uint32_t shift = p * kRadixBits;
-    hipLaunchKernelGGL(k_radix_hist, dim3(kSortBlocks), dim3(kBlock), 0, st, ka,
-                       (const Counters*)counters, nsel, shift, hist);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, hist, (const Counters*)counters);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(kBlock), 0, st, ka, va, kb, vb,
-                       (const Counters*)counters, nsel, shift, hist);
-    uint64_t* tk = ka;
-    ka = kb;
-    kb = tk;
-    int2* tv = va;
-    va = vb;
-    vb = tv;
+    hipLaunchKernelGGL(k_onesweep, dim3(g), dim3(kBlock), 0, st, kb[s], vb[s], kb[s ^ 1],
+                       vb[s ^ 1], (Counters*)counters, nsel, p, ghist, sort_status,
+                       sort_epoch(step, p), step);
+    s ^= 1;
   }
-  *in_second = (passes & 1) ? 1 : 0;
   return (int)hipGetLastError();
 }
 
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, uint32_t epoch, const uint8_t* tab, const int64_t* qshift,
-               uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok, int2* ov,
-               uint64_t cap_store, uint64_t max_items) {
-  KeyLayout kl{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1)};
+               uint64_t* status, const uint8_t* tab, const uint8_t* tab_next,
+               const int64_t* qshift, uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok,
+               int2* ov, uint64_t cap_store, uint64_t max_items, uint64_t* ck_next,
+               int2* cv_next, uint64_t cap_child, uint32_t* ghist_next, uint32_t passes) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
-  hipLaunchKernelGGL(k_merge_part, dim3(grid_for((uint64_t)max_tiles + 1, 1u << 20)), dim3(kBlock),
-                     0, st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles);
-  hipLaunchKernelGGL(k_merge, dim3(max_tiles > 0 ? max_tiles : 1), dim3(kBlock), 0, st, pk, pv,
-                     ck, cv, (Counters*)counters, cur, csel, splits, status, epoch, tab, qshift,
-                     step, seed, kl, ok, ov, cap_store);
-  return (int)hipGetLastError();
-}
-
-int qmck_reset_child(hipStream_t st, void* counters, uint32_t sel) {
-  hipLaunchKernelGGL(k_reset_child, dim3(1), dim3(64), 0, st, (Counters*)counters, sel);
+  hipLaunchKernelGGL(k_merge_part,
+                     dim3(grid_for(((uint64_t)max_tiles + 1) * kWave, 2048)), dim3(kBlock), 0,
+                     st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next);
+  MergeArgs a;
+  a.pk = pk;
+  a.pv = pv;
+  a.ckeys = ck;
+  a.cvals = cv;
+  a.cnt = (Counters*)counters;
+  a.cur = cur;
+  a.csel = csel;
+  a.splits = splits;
+  a.status = status;
+  a.epoch = merge_epoch(step);
+  a.tab = tab;
+  a.tab_next = tab_next;
+  a.qshift = qshift;
+  a.step = step;
+  a.seed = seed;
+  a.kl = key_layout(kbits);
+  a.ok = ok;
+  a.ov = ov;
+  a.cap_store = cap_store;
+  a.ck_next = ck_next;
+  a.cv_next = cv_next;
+  a.cap_child = cap_child;
+  a.ghist_next = ghist_next;
+  a.passes = passes;
+  const uint32_t g = max_tiles < (uint32_t)kPersistBlocks ? (max_tiles ? max_tiles : 1)
+                                                          : (uint32_t)kPersistBlocks;
+  hipLaunchKernelGGL(k_merge, dim3(g), dim3(kBlock), 0, st, a);
   return (int)hipGetLastError();
 }
 
@@ -829,10 +1012,9 @@ int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t 
 }
 
 int qmck_copy_store(hipStream_t st, const uint64_t* ki, const int2* vi, uint64_t* ko, int2* vo,
-                    void* counters, uint32_t csel, uint64_t max_items) {
+                    const uint64_t* count, uint64_t max_items) {
   uint32_t g = grid_for(max_items, 8192);
-  hipLaunchKernelGGL(k_copy_store, dim3(g), dim3(kBlock), 0, st, ki, vi, ko, vo,
-                     (const Counters*)counters, csel);
+  hipLaunchKernelGGL(k_copy_store, dim3(g), dim3(kBlock), 0, st, ki, vi, ko, vo, count);
   return (int)hipGetLastError();
 }
 
@@ -840,23 +1022,21 @@ int qmck_observe(hipStream_t st, const uint64_t* pk, const int2* pv, void* count
                  uint32_t n, uint32_t kbits, uint32_t nrep, uint32_t n_pauli,
                  const uint64_t* pxz, uint32_t want_eps, unsigned long long* out,
                  uint32_t out_stride, uint64_t max_per_replica) {
-  KeyLayout kl{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1)};
   uint32_t gx = grid_for(max_per_replica, 1024);
   hipLaunchKernelGGL(k_observe, dim3(gx, nrep), dim3(kBlock),
                      out_stride * sizeof(unsigned long long), st, pk, pv,
-                     (const Counters*)counters, cur, n, kl, n_pauli, pxz, want_eps, out,
-                     out_stride);
+                     (const Counters*)counters, cur, n, key_layout(kbits), n_pauli, pxz, want_eps,
+                     out, out_stride);
   return (int)hipGetLastError();
 }
 
 int qmck_lookup(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
                 uint32_t kbits, const uint64_t* keys, uint32_t nk, uint32_t nrep, int64_t* out) {
-  KeyLayout kl{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1)};
   uint64_t tot = (uint64_t)nk * nrep;
   if (tot == 0) return 0;
   uint32_t g = (uint32_t)((tot + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_lookup, dim3(g), dim3(kBlock), 0, st, pk, pv, (const Counters*)counters,
-                     cur, kl, keys, nk, nrep, out);
+                     cur, key_layout(kbits), keys, nk, nrep, out);
   return (int)hipGetLastError();
 }
 

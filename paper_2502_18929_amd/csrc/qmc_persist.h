@@ -1,0 +1,43 @@
+// qmc_persist.h -- host-side launch interface of the persistent segmented step (qmc_persist.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct PersistLaunch {
+  const uint64_t* ck;   // canonical store (read at batch start)
+  const int2* cv;
+  uint64_t* ck_w;       // canonical store (written by the gather)
+  int2* cv_w;
+  void* counters;
+  uint32_t cur;
+  uint64_t* sk;         // segments [2][P][segcap]
+  int2* sv;
+  uint64_t segcap;
+  uint32_t* seg_n;      // [2][P]
+  uint64_t* ik;         // inboxes [2][P][incap]
+  int2* iv;
+  uint32_t incap;
+  uint32_t* in_n;       // [2][P]
+  const uint64_t* split;
+  uint64_t* split_w;
+  uint32_t P;
+  const uint8_t* tab_base;
+  const uint32_t* tab_off;  // [nsteps] byte offsets of the step tables
+  uint32_t step0, nsteps;
+  uint64_t seed;
+  uint32_t kbits;
+  const int64_t* qshift;
+  uint64_t* slots;      // [P][4] epoch-tagged per-workgroup barrier slots (zeroed once)
+  uint64_t* ctl;        // [10] released epoch and reduced totals (zeroed once)
+  uint64_t epoch0;      // first barrier epoch of the launch
+  uint64_t cap_store;
+  uint64_t cap_inbox;
+  uint32_t rebal_min;
+  uint32_t* done;       // [2]
+};
+
+extern "C" {
+int qmcp_max_segments(int* P);
+int qmcp_run(hipStream_t st, const PersistLaunch* L);
+int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t par);
+}

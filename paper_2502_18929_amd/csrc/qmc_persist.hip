@@ -1,0 +1,818 @@
+// qmc_persist.hip -- the population-dynamics step as one persistent, key-range-segmented
+// cooperative kernel per batch of steps (gfx950, wave64).
+//
+// The sorted store (all replicas, composite keys) is cut by P splitter keys taken from the store
+// itself into P key ranges; workgroup p owns range p for the whole batch: its parents live in a
+// sorted segment, and every record destined to its range (spawned children, and the death/cloning
+// delta of each of its own parents) arrives in its inbox.  One step of workgroup p:
+//   1. sort the inbox in LDS (bitonic);
+//   2. stream the parents of the segment in register tiles, merge them with the inbox, sum every
+//      key in int64 (annihilation, End Matter), drop empty keys, write the new segment;
+//   3. for every new parent draw Philox once (step s+1) and, only for the parents whose column
+//      can produce a nonzero amount (|a|+|b|)*sum|q| + U >= 2^32, evaluate the death delta
+//      (diagonal of the column applied to N(s+1)) and the off-diagonal children, and route each
+//      record to the inbox of the workgroup owning its key (wave-aggregated atomics);
+//   4. grid barrier.
+// One grid barrier per step, no global sort passes, parents read and written once per step.
+#include "qmc_device.hpp"
+#include "qmc_persist.h"
+
+namespace qmc {
+
+constexpr int kPBlock = 512;               // threads per workgroup
+constexpr int kPWaves = kPBlock / kWave;   // 8
+constexpr int kPTile = 1024;               // parents per tile (staged in LDS)
+constexpr int kRing = 128;                 // per-wave queue of active new parents
+constexpr int kStage = 256;                // per-wave staging of routed records
+constexpr int kTabLds = 8192;              // bytes of a step table kept in LDS
+
+struct PersistArgs {
+  // canonical store: sorted records of all replicas (read in phase A)
+  const uint64_t* ck;
+  const int2* cv;
+  Counters* cnt;
+  uint32_t cur;
+  // segments [2][P][segcap] and counts [2][P]
+  uint64_t* sk;
+  int2* sv;
+  uint64_t segcap;
+  uint32_t* seg_n;
+  // inboxes [2][P][incap] and counts [2][P]
+  uint64_t* ik;
+  int2* iv;
+  uint32_t incap;
+  uint32_t* in_n;
+  // key ranges: split[p] <= key < split[p+1]
+  const uint64_t* split;
+  uint32_t P;
+  // per-step tables of the batch
+  const uint8_t* tab_base;
+  const uint32_t* tab_off;
+  uint32_t step0, nsteps;
+  uint64_t seed;
+  KeyLayout kl;
+  const int64_t* qshift;
+  // synchronization and reporting
+  uint64_t* slots;        // [P][4] per workgroup: epoch, keys out, inbox records, error bits
+  uint64_t* ctl;          // [0] released epoch, [2 + 4*(e&1) ..] reduced totals of epoch e
+  uint64_t cap_store;     // total occupied keys allowed
+  uint64_t cap_inbox;     // total inbox records allowed per step
+  uint32_t rebal_min;     // imbalance slack before a rebalancing stop
+  uint64_t epoch0;        // first barrier epoch of this launch (epochs only grow)
+  uint32_t* done;         // [0] steps completed, [1] stop reason (0 end, 1 rebalance, 2 error)
+};
+
+struct Shared {
+  uint64_t split[kMaxSegments];
+  uint64_t in_k[kInboxMax];
+  int2 in_v[kInboxMax];
+  uint64_t pa_k[kPTile];
+  int2 pa_v[kPTile];
+  uint32_t scan[kPBlock];
+  uint64_t ring_k[kPWaves][kRing];
+  int2 ring_v[kPWaves][kRing];
+  uint2 ring_w[kPWaves][kRing];
+  uint64_t st_k[kPWaves][kStage];
+  int2 st_v[kPWaves][kStage];
+  uint64_t red[kPWaves];
+  uint64_t dec[4];
+  uint8_t tab[kTabLds] __attribute__((aligned(16)));        // reduced totals of the last barrier: keys, max segment, inbox, errors
+  uint32_t flag;
+  uint32_t err;           // error bits this workgroup raised in the current step
+};
+
+// Cross-workgroup data (inbox records and counts, barrier slots) is written and read only with
+// agent-scope atomic accesses: on gfx950 these go through to the device coherence point and never
+// leave dirty or stale lines in an XCD's L2, so the barrier needs no L2 writeback or invalidate,
+// only the completion of the workgroup's own stores (s_waitcnt vmcnt(0)).
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(int2* p, int2 v) {
+  const uint64_t u = (uint64_t)(uint32_t)v.x | ((uint64_t)(uint32_t)v.y << 32);
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int2 ld_agent(const int2* p) {
+  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return make_int2((int32_t)(uint32_t)u, (int32_t)(uint32_t)(u >> 32));
+}
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory access this wave issued has completed (for the atomic stores above:
+// reached the coherence point).  The signal fences keep the compiler from moving accesses across.
+__device__ __forceinline__ void wait_mem() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Errors go to the context's flags (reported to the host) and to this workgroup's error word of
+// the current step, which the next barrier reduces over all workgroups: every workgroup decides
+// to stop from the reduced value only, so the decision is identical everywhere.
+__device__ __forceinline__ void raise_err(Counters* cnt, uint32_t* my_err, uint32_t bit,
+                                          uint32_t step) {
+  atomicOr(&cnt->err, bit);
+  atomicMin(&cnt->err_step, step);
+  atomicOr(my_err, bit);
+}
+
+// Grid-wide barrier with reduction over the co-resident workgroups of a cooperative launch.
+// Each workgroup publishes (epoch, keys out, inbox records, error bits) in its own slot and then
+// reads every slot itself (one thread per slot) until all carry this epoch, reducing the values
+// locally: two memory round trips, no master workgroup, identical totals everywhere (S.dec).
+// All cross-workgroup writes before the barrier are agent-scope atomics, so publishing only waits
+// for their completion.  Waits are bounded: on expiry the totals carry kErrLookback and false is
+// returned.
+__device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint64_t epoch,
+                                          uint64_t nout, uint64_t nin) {
+  const uint32_t t = threadIdx.x, p = blockIdx.x, P = A.P;
+  wait_mem();
+  __syncthreads();
+  if (t == 0) {
+    uint64_t* sl = A.slots + 4 * (uint64_t)p;
+    st_agent(&sl[1], nout);
+    st_agent(&sl[2], nin);
+    st_agent(&sl[3], (uint64_t)S.err);
+    wait_mem();
+    st_agent(&sl[0], epoch);
+  }
+  uint64_t tot = 0, mx = 0, nn = 0, er = 0;
+  for (uint32_t q = t; q < P; q += kPBlock) {
+    const uint64_t* sl = A.slots + 4 * (uint64_t)q;
+    uint32_t spins = 0;
+    while (ld_agent(&sl[0]) < epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 24)) {
+        er |= kErrLookback;
+        break;
+      }
+    }
+    wait_mem();
+    const uint64_t v1 = ld_agent(&sl[1]);
+    const uint64_t v2 = ld_agent(&sl[2]);
+    const uint64_t v3 = ld_agent(&sl[3]);
+    tot += v1;
+    mx = v1 > mx ? v1 : mx;
+    nn += v2;
+    er |= v3;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    tot += __shfl_xor(tot, o);
+    const uint64_t m2 = __shfl_xor(mx, o);
+    mx = m2 > mx ? m2 : mx;
+    nn += __shfl_xor(nn, o);
+    er |= __shfl_xor(er, o);
+  }
+  __syncthreads();  // the reduction scratch below may still be read by a slow wave
+  if (__lane_id() == 0) {
+    S.ring_k[t / kWave][0] = tot;
+    S.ring_k[t / kWave][1] = mx;
+    S.ring_k[t / kWave][2] = nn;
+    S.ring_k[t / kWave][3] = er;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kPWaves; ++w) {
+      tot += S.ring_k[w][0];
+      mx = S.ring_k[w][1] > mx ? S.ring_k[w][1] : mx;
+      nn += S.ring_k[w][2];
+      er |= S.ring_k[w][3];
+    }
+    S.dec[0] = tot;
+    S.dec[1] = mx;
+    S.dec[2] = nn;
+    S.dec[3] = er;
+    if (er & kErrLookback) raise_err(A.cnt, &S.err, kErrLookback, A.step0);
+    S.err = 0;  // the next step starts clean
+  }
+  __syncthreads();
+  return (S.dec[3] & kErrLookback) == 0;
+}
+
+__device__ __forceinline__ uint32_t upper_bound_lds(const uint64_t* a, uint32_t n, uint64_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t lower_bound_glb(const uint64_t* a, uint64_t n, uint64_t v) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// In-place bitonic sort of m (a power of two) records in LDS, by key.
+__device__ __forceinline__ void bitonic_sort(uint64_t* k, int2* v, uint32_t m) {
+  for (uint32_t size = 2; size <= m; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = threadIdx.x; t < (m >> 1); t += kPBlock) {
+        const uint32_t lo = 2 * t - (t & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t a = k[lo], b = k[hi];
+        if ((a > b) == asc) {
+          k[lo] = b;
+          k[hi] = a;
+          const int2 x = v[lo];
+          v[lo] = v[hi];
+          v[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Routed emission.  Records are staged per wave in LDS; a flush routes them to the inbox of the
+// workgroup owning each key (binary search in the splitters), reserving space with one atomic per
+// distinct destination per chunk of 64 records; the atomics of all chunks of a flush are issued
+// before any of their results is needed, so a flush costs about one atomic round trip.
+struct Router {
+  uint32_t* in_n;          // [2][P]
+  uint64_t* ik;            // [2][P][incap]
+  int2* iv;
+  uint32_t incap;
+  Counters* cnt;
+  const uint64_t* split;   // LDS copy
+  uint32_t P, pbits;
+  uint32_t par;            // inbox parity of the destination step
+  uint32_t step;           // destination step (for error reports)
+  uint32_t* my_err;        // this workgroup's error word (LDS)
+  uint64_t* sk;            // this wave's LDS staging
+  int2* sv;
+  uint32_t fill;           // wave-uniform
+
+  __device__ __forceinline__ void flush() {
+    if (fill == 0) return;
+    wave_lds_fence();
+    const uint32_t lane = __lane_id();
+    const uint64_t lt = lanemask_lt();
+    constexpr int NC = kStage / kWave;
+    uint32_t q[NC], rank[NC], base[NC];
+    uint64_t key[NC];
+    int2 val[NC];
+    bool has[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint32_t i = c * kWave + lane;
+      has[c] = i < fill;
+      key[c] = has[c] ? sk[i] : 0;
+      val[c] = has[c] ? sv[i] : make_int2(0, 0);
+      q[c] = has[c] ? upper_bound_lds(split, P, key[c]) - 1 : 0u;
+      uint64_t peers = __ballot(has[c]);
+      for (uint32_t b = 0; b < pbits; ++b) {
+        const uint64_t bm = __ballot((q[c] >> b) & 1u);
+        peers &= ((q[c] >> b) & 1u) ? bm : ~bm;
+      }
+      rank[c] = (uint32_t)__popcll(peers & lt);
+      base[c] = 0;
+      if (has[c] && rank[c] == 0) base[c] = atomicAdd(&in_n[par * P + q[c]], (uint32_t)__popcll(peers));
+      // leader lane of my destination group
+      rank[c] |= (has[c] ? ((uint32_t)__ffsll((unsigned long long)peers) - 1) : 0u) << 16;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint32_t b = __shfl(base[c], (int)(rank[c] >> 16));
+      if (has[c]) {
+        const uint32_t pos = b + (rank[c] & 0xFFFFu);
+        if (pos < incap) {
+          const uint64_t off = ((uint64_t)par * P + q[c]) * incap + pos;
+          st_agent(&ik[off], key[c]);
+          st_agent(&iv[off], val[c]);
+        } else {
+          raise_err(cnt, my_err, kErrInbox, step);
+        }
+      }
+    }
+    wave_lds_fence();
+    fill = 0;
+  }
+
+  // All lanes of the wave call; lanes with `has` stage (key, val).
+  __device__ __forceinline__ void emit(bool has, uint64_t key, int2 val) {
+    const uint64_t m = __ballot(has);
+    if (m == 0) return;
+    if (has) {
+      const uint32_t pos = fill + mbcnt64(m);
+      sk[pos] = key;
+      sv[pos] = val;
+    }
+    fill += (uint32_t)__popcll(m);
+    if (fill > kStage - kWave) flush();
+  }
+};
+
+// Death delta and children of up to 64 queued active parents of one wave (dense: every lane
+// holds one parent).
+__device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, Router& R, const TableView& tn,
+                               uint32_t wave, uint32_t n, uint32_t step) {
+  const uint32_t lane = __lane_id();
+  const bool valid = lane < n;
+  const uint64_t ck = valid ? S.ring_k[wave][lane] : 0;
+  const int2 v = valid ? S.ring_v[wave][lane] : make_int2(0, 0);
+  const uint2 w = valid ? S.ring_w[wave][lane] : make_uint2(0, 0);
+  const KeyLayout kl = A.kl;
+  const uint64_t key = kl.key(ck);
+  const uint32_t rep = kl.replica(ck);
+  const int64_t qs = valid ? A.qshift[rep] : 0;
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+  // Death/cloning delta from the diagonal group (applied to N(t) in the next merge).
+  {
+    const bool act = valid && !comb_all_zero(sab, tn.h->q_diag + uabs64(qs), w.y);
+    int2 d = make_int2(0, 0);
+    if (__ballot(act)) {
+      if (act) {
+        int32_t dre, dim;
+        group_coeff(tn.t, 0, tn.gs[1], key, dre, dim);
+        int64_t xre, xim;
+        cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
+        uint64_t r = w.y;
+        d.x = (int32_t)comb_step(r, xre);
+        d.y = (int32_t)comb_step(r, xim);
+      }
+      R.emit((d.x | d.y) != 0, ck, d);
+    }
+  }
+  // Children into every off-diagonal target, one comb over all groups (Re, Im) in order.
+  const uint32_t G = tn.h->n_groups;
+  const bool act = valid && G > 1 && !comb_all_zero(sab, tn.h->q_off, w.x);
+  if (__ballot(act) == 0) return;
+  uint64_t r = w.x;
+  for (uint32_t g = 1; g < G; ++g) {
+    int2 child = make_int2(0, 0);
+    if (act) {
+      int32_t cre, cim;
+      group_coeff(tn.t, tn.gs[g], tn.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      child.x = (int32_t)comb_step(r, xre);
+      child.y = (int32_t)comb_step(r, xim);
+    }
+    R.emit((child.x | child.y) != 0, ck ^ tn.gx[g], child);
+  }
+  (void)step;
+}
+
+// Draw Philox for new parents [o0, o1) of segment buffer (seg_k, seg_v) at step `step` and
+// route their death deltas and children.  Uniform loop; active parents are compacted per wave.
+__device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router& R, const TableView& tn,
+                        const uint64_t* seg_k, const int2* seg_v, uint64_t o0, uint64_t o1,
+                        uint32_t step) {
+  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
+  const KeyLayout kl = A.kl;
+  const uint64_t q_diag = tn.h->q_diag, q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
+  uint32_t fill = 0;  // wave-uniform
+  for (uint64_t wb = o0 + (uint64_t)wave * kWave; wb < o1; wb += kPBlock) {
+    const uint64_t i = wb + lane;
+    const bool valid = i < o1;
+    uint64_t ck = 0;
+    int2 v = make_int2(0, 0);
+    bool act = false;
+    uint32_t w[4] = {0, 0, 0, 0};
+    if (valid) {
+      ck = seg_k[i];
+      v = seg_v[i];
+      const uint32_t rep = kl.replica(ck);
+      walker_random(kl.key(ck), step, rep, A.seed, w);
+      const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+      act = !comb_all_zero(sab, q_diag + uabs64(A.qshift[rep]), w[1]) ||
+            !comb_all_zero(sab, q_off, w[0]);
+    }
+    const uint64_t m = __ballot(act);
+    if (m) {
+      if (act) {
+        const uint32_t pos = fill + mbcnt64(m);
+        S.ring_k[wave][pos] = ck;
+        S.ring_v[wave][pos] = v;
+        S.ring_w[wave][pos] = make_uint2(w[0], w[1]);
+      }
+      fill += (uint32_t)__popcll(m);
+      wave_lds_fence();
+      if (fill >= kWave) {
+        process_active(A, S, R, tn, wave, kWave, step);
+        // move the overflow (fill - 64 < 64 entries) to the front of the queue
+        const uint32_t rest = fill - kWave;
+        uint64_t rk = 0;
+        int2 rv = make_int2(0, 0);
+        uint2 rw = make_uint2(0, 0);
+        if (lane < rest) {
+          rk = S.ring_k[wave][kWave + lane];
+          rv = S.ring_v[wave][kWave + lane];
+          rw = S.ring_w[wave][kWave + lane];
+        }
+        wave_lds_fence();
+        if (lane < rest) {
+          S.ring_k[wave][lane] = rk;
+          S.ring_v[wave][lane] = rv;
+          S.ring_w[wave][lane] = rw;
+        }
+        wave_lds_fence();
+        fill = rest;
+      }
+    }
+  }
+  if (fill) process_active(A, S, R, tn, wave, fill, step);
+  R.flush();
+}
+
+// The table of one step in LDS when it fits (terms are then read at LDS latency).
+__device__ __forceinline__ TableView stage_table(Shared& S, const uint8_t* g) {
+  const uint32_t bytes = reinterpret_cast<const TableHeader*>(g)->bytes;
+  __syncthreads();  // previous readers of S.tab are done
+  if (bytes > (uint32_t)kTabLds) return table_view(g);
+  const uint4* src = reinterpret_cast<const uint4*>(g);
+  uint4* dst = reinterpret_cast<uint4*>(S.tab);
+  for (uint32_t i = threadIdx.x; i < bytes / 16; i += kPBlock) dst[i] = src[i];
+  __syncthreads();
+  return table_view(S.tab);
+}
+
+// Merge one segment's parents (sorted, global) with its sorted inbox (LDS), sum per key,
+// write the surviving keys to the output segment, and (if `spawn`) draw the next step from them.
+// The parents go through LDS in tiles of kPTile; each tile takes the inbox records up to its last
+// parent (the last tile takes the rest), and the merged items of the tile are split evenly over
+// the threads by a merge-path search that never cuts a key's run.  Returns the number of keys
+// written in S.red[0] and the walker sum of the parents in S.red[1] (block-uniform).
+__device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, const uint64_t* pk,
+                                              const int2* pv, uint64_t np, uint32_t c, uint64_t* ok,
+                                              int2* ov, uint32_t step, bool spawn, Router R,
+                                              const TableView tn, uint32_t nstep) {
+  const uint32_t t = threadIdx.x;
+  uint64_t out_run = 0;   // block-uniform
+  uint64_t wsum = 0;
+  uint32_t jb = 0;        // first inbox record not yet merged (block-uniform)
+  const uint64_t ntile = np > 0 ? (np + kPTile - 1) / kPTile : (c > 0 ? 1 : 0);
+  for (uint64_t tt = 0; tt < ntile; ++tt) {
+    const uint64_t f = tt * kPTile;
+    const uint32_t pn = np > f ? (uint32_t)((np - f) < (uint64_t)kPTile ? (np - f) : kPTile) : 0u;
+    for (uint32_t i = t; i < pn; i += kPBlock) {
+      S.pa_k[i] = pk[f + i];
+      const int2 v = pv[f + i];
+      S.pa_v[i] = v;
+      wsum += uabs64(v.x) + uabs64(v.y);
+    }
+    __syncthreads();
+    // inbox window of this tile: records up to its last parent, or all the rest on the last tile
+    const bool last_tile = tt + 1 == ntile;
+    const uint32_t je = last_tile ? c : upper_bound_lds(S.in_k, c, S.pa_k[pn - 1]);
+    const uint32_t cn = je - jb;
+    const uint64_t* ck = S.in_k + jb;
+    const int2* cv = S.in_v + jb;
+    // this thread's share of the tile's merged items
+    auto KA = [&](uint32_t x) { return S.pa_k[x]; };
+    auto KB = [&](uint32_t x) { return ck[x]; };
+    const uint32_t tot = pn + cn;
+    const uint32_t per = (tot + kPBlock - 1) / kPBlock;
+    uint32_t d0 = t * per, d1 = d0 + per;
+    if (d0 > tot) d0 = tot;
+    if (d1 > tot) d1 = tot;
+    uint32_t i0, j0, i1, j1;
+    run_split(KA, pn, KB, cn, d0, i0, j0);
+    run_split(KA, pn, KB, cn, d1, i1, j1);
+    if (t == kPBlock - 1) {
+      i1 = pn;
+      j1 = cn;
+    }
+    auto walk = [&](auto&& out) __attribute__((always_inline)) {
+      uint32_t i = i0, j = j0;
+      while (i < i1 || j < j1) {
+        uint64_t key;
+        int64_t re = 0, im = 0;
+        if (j >= j1 || (i < i1 && S.pa_k[i] <= ck[j])) {
+          key = S.pa_k[i];
+          re = S.pa_v[i].x;
+          im = S.pa_v[i].y;
+          ++i;
+        } else {
+          key = ck[j];
+        }
+        while (j < j1 && ck[j] == key) {
+          re += cv[j].x;
+          im += cv[j].y;
+          ++j;
+        }
+        out(key, re, im);
+      }
+    };
+    // Pass 1: count the nonzero sums.
+    uint32_t count = 0;
+    bool overflow = false;
+    walk([&](uint64_t, int64_t re, int64_t im) __attribute__((always_inline)) {
+      if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
+      count += (re != 0 || im != 0) ? 1u : 0u;
+    });
+    if (overflow) raise_err(A.cnt, &S.err, kErrOverflow, step);
+    // Block exclusive scan of the counts: inclusive scan within each wave, then wave totals.
+    uint32_t incl = count;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t x = __shfl_up(incl, o);
+      if (__lane_id() >= (uint32_t)o) incl += x;
+    }
+    if (__lane_id() == kWave - 1) S.scan[t / kWave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, agg = 0;
+    for (uint32_t w = 0; w < (uint32_t)kPWaves; ++w) {
+      const uint32_t v = S.scan[w];
+      wpre += w < t / kWave ? v : 0u;
+      agg += v;
+    }
+    const uint32_t excl = wpre + incl - count;
+    const uint64_t o0 = out_run;
+    if (o0 + agg > A.segcap) {
+      if (t == 0) raise_err(A.cnt, &S.err, kErrSegCap, step);
+    } else {
+      // Pass 2: write.
+      uint64_t o = o0 + excl;
+      walk([&](uint64_t key, int64_t re, int64_t im) __attribute__((always_inline)) {
+        if (re != 0 || im != 0) {
+          ok[o] = key;
+          ov[o] = make_int2((int32_t)re, (int32_t)im);
+          ++o;
+        }
+      });
+    }
+    out_run = o0 + agg;
+    jb = je;
+    __syncthreads();  // this tile's outputs are visible to the whole workgroup
+    if (spawn && o0 + agg <= A.segcap) advance(A, S, R, tn, ok, ov, o0, o0 + agg, nstep);
+    __syncthreads();
+  }
+  // block reduction of the walker sum
+  for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+  if (__lane_id() == 0) S.red[t / kWave] = wsum;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t s = 0;
+    for (int w = 0; w < kPWaves; ++w) s += S.red[w];
+    S.red[0] = out_run;
+    S.red[1] = s;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
+  __shared__ Shared S;
+  const uint32_t p = blockIdx.x, t = threadIdx.x;
+  const uint32_t P = A.P;
+  Counters* cnt = A.cnt;
+  uint32_t pbits = 0;
+  while ((1u << pbits) < P) ++pbits;
+  for (uint32_t i = t; i < P; i += kPBlock) S.split[i] = A.split[i];
+  __syncthreads();
+  const uint64_t lo_key = S.split[p];
+  const uint64_t n_can = cnt->n_store[A.cur];
+
+  if (t == 0) S.err = 0;
+  // Phase A: this workgroup's slice of the canonical store becomes its segment (buffer 0), and
+  // the death deltas and children of the first step go to the inboxes (parity 0).
+  if (t == 0) {
+    const uint64_t b = lower_bound_glb(A.ck, n_can, lo_key);
+    const uint64_t e = p + 1 < P ? lower_bound_glb(A.ck, n_can, S.split[p + 1]) : n_can;
+    S.red[0] = b;
+    S.red[1] = e;
+    st_agent(&A.in_n[1 * P + p], 0u);  // inbox of step 1 (parity 1) starts empty
+  }
+  __syncthreads();
+  const uint64_t cb = S.red[0], ce = S.red[1];
+  __syncthreads();
+  uint64_t np = ce - cb;
+  if (np > A.segcap) {
+    if (t == 0) raise_err(cnt, &S.err, kErrSegCap, A.step0);
+    np = 0;
+  }
+  uint64_t* seg_k0 = A.sk + (uint64_t)p * A.segcap;
+  int2* seg_v0 = A.sv + (uint64_t)p * A.segcap;
+  for (uint64_t i = t; i < np; i += kPBlock) {
+    seg_k0[i] = A.ck[cb + i];
+    seg_v0[i] = A.cv[cb + i];
+  }
+  if (t == 0) A.seg_n[p] = (uint32_t)np;
+  __syncthreads();
+  {
+    const TableView tn = stage_table(S, A.tab_base + A.tab_off[0]);
+    Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, 0u, A.step0, &S.err,
+             S.st_k[t / kWave], S.st_v[t / kWave], 0u};
+    advance(A, S, R, tn, seg_k0, seg_v0, 0, np, A.step0);
+  }
+  uint64_t epoch = A.epoch0;
+  if (!grid_sync(S, A, epoch, np, 0) || S.dec[3]) {
+    if (p == 0 && t == 0) {
+      A.done[0] = 0;
+      A.done[1] = 2;
+    }
+    return;
+  }
+
+  uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
+  uint32_t reason = 0, kdone = A.nsteps;
+  for (uint32_t k = 0; k < A.nsteps; ++k) {
+    const uint32_t s = A.step0 + k;
+    const uint32_t par = k & 1u;
+    // inbox of this step -> LDS, sorted
+    const uint32_t c_raw = ld_agent(&A.in_n[par * P + p]);
+    const uint32_t c = c_raw < A.incap ? c_raw : A.incap;
+    if (t == 0 && c_raw > A.incap) raise_err(cnt, &S.err, kErrInbox, s);
+    uint32_t m2 = 1;
+    while (m2 < c) m2 <<= 1;
+    const uint64_t* ibk = A.ik + ((uint64_t)par * P + p) * A.incap;
+    const int2* ibv = A.iv + ((uint64_t)par * P + p) * A.incap;
+    for (uint32_t i = t; i < m2; i += kPBlock) {
+      S.in_k[i] = i < c ? ld_agent(&ibk[i]) : ~0ull;
+      S.in_v[i] = i < c ? ld_agent(&ibv[i]) : make_int2(0, 0);
+    }
+    __syncthreads();
+    if (t == 0) st_agent(&A.in_n[par * P + p], 0u);  // refilled during step k+1 (for step k+2)
+    if (c > 1) bitonic_sort(S.in_k, S.in_v, m2);
+    // The padding records (key ~0, value 0) are merged too: harmless zero terms, and exact even
+    // when ~0 is a real key.
+    const uint32_t cm = c > 0 ? m2 : 0u;
+    // merge; spawn the next step from the outputs
+    const uint64_t np_k = A.seg_n[par * P + p];
+    const uint64_t* pk = A.sk + ((uint64_t)par * P + p) * A.segcap;
+    const int2* pv = A.sv + ((uint64_t)par * P + p) * A.segcap;
+    uint64_t* okp = A.sk + ((uint64_t)(par ^ 1u) * P + p) * A.segcap;
+    int2* ovp = A.sv + ((uint64_t)(par ^ 1u) * P + p) * A.segcap;
+    const bool last = k + 1 == A.nsteps;
+    const TableView tn = stage_table(S, A.tab_base + A.tab_off[last ? k : k + 1]);
+    Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, s + 1, &S.err,
+             S.st_k[t / kWave], S.st_v[t / kWave], 0u};
+    merge_segment(A, S, pk, pv, np_k, cm, okp, ovp, s, !last, R, tn, s + 1);
+    const uint64_t nout = S.red[0], wsum = S.red[1];
+    if (t == 0) {
+      A.seg_n[(par ^ 1u) * P + p] = (uint32_t)(nout <= A.segcap ? nout : 0);
+      st_w += wsum;
+      st_k += np_k;
+      st_c += c;
+      st_o += nout;
+    }
+    ++epoch;
+    if (!grid_sync(S, A, epoch, nout, c)) {
+      reason = 2;
+      kdone = k;
+      break;
+    }
+    // every workgroup reads the same reduced totals and takes the same decision
+    const uint64_t tot = S.dec[0], mx = S.dec[1], nin = S.dec[2], ebits = S.dec[3];
+    const bool cap_store = tot > A.cap_store, cap_in = nin > A.cap_inbox;
+    if (ebits || cap_store || cap_in) {
+      if (p == 0 && t == 0) {
+        if (cap_store) raise_err(cnt, &S.err, kErrStoreCap, s);
+        if (cap_in) raise_err(cnt, &S.err, kErrSpawnCap, s);
+      }
+      reason = 2;
+      kdone = k;  // refined by the host from err_step
+      break;
+    }
+    if (!last && mx > 2 * (tot / P) + A.rebal_min) {
+      reason = 1;
+      kdone = k + 1;
+      break;
+    }
+  }
+  if (t == 0) {
+    atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)st_w);
+    atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)st_k);
+    atomicAdd((unsigned long long*)&cnt->child_steps, (unsigned long long)st_c);
+    atomicAdd((unsigned long long*)&cnt->out_steps, (unsigned long long)st_o);
+    if (p == 0) {
+      A.done[0] = kdone;
+      A.done[1] = reason;
+    }
+  }
+}
+
+// Splitters: split[0] = 0, split[p] = key at index p*n/P of the canonical store.
+__global__ void k_splitters(const uint64_t* __restrict__ ck, const Counters* __restrict__ cnt,
+                            uint32_t cur, uint32_t P, uint64_t* __restrict__ split) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const uint64_t n = cnt->n_store[cur];
+  split[p] = (p == 0 || n == 0) ? 0ull : ck[((uint64_t)p * n) / P];
+}
+
+// Batch prologue: empty inboxes of the first step, error flags reset.
+__global__ void k_persist_prep(Counters* cnt, uint32_t* in_n, uint32_t P, uint32_t* done) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t i = t; i < 2 * P; i += gridDim.x * blockDim.x) in_n[i] = 0;
+  if (t == 0) {
+    done[0] = 0;
+    done[1] = 0;
+    cnt->err = 0;
+    cnt->err_step = 0xFFFFFFFFu;
+  }
+}
+
+// Segments of buffer `par` -> canonical store (concatenation in segment order is sorted).
+__global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ sk,
+                                                const int2* __restrict__ sv,
+                                                const uint32_t* __restrict__ seg_n, uint32_t par,
+                                                uint32_t P, uint64_t segcap,
+                                                uint64_t* __restrict__ ck, int2* __restrict__ cv,
+                                                Counters* __restrict__ cnt, uint32_t cur) {
+  __shared__ uint64_t s_off;
+  const uint32_t p = blockIdx.x;
+  if (threadIdx.x == 0) {
+    uint64_t o = 0;
+    for (uint32_t q = 0; q < p; ++q) o += seg_n[par * P + q];
+    s_off = o;
+    if (p == P - 1) cnt->n_store[cur] = o + seg_n[par * P + p];
+  }
+  __syncthreads();
+  const uint64_t off = s_off;
+  const uint64_t n = seg_n[par * P + p];
+  const uint64_t* k = sk + ((uint64_t)par * P + p) * segcap;
+  const int2* v = sv + ((uint64_t)par * P + p) * segcap;
+  for (uint64_t i = threadIdx.x; i < n; i += 256) {
+    ck[off + i] = k[i];
+    cv[off + i] = v[i];
+  }
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" {
+
+int qmcp_max_segments(int* P) {
+  int dev = 0, ncu = 0, nb = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_persist),
+                                                     kPBlock, 0);
+  if (e != hipSuccess) return (int)e;
+  long long tot = (long long)ncu * (nb > 0 ? nb : 0);
+  if (tot > kMaxSegments) tot = kMaxSegments;
+  *P = (int)tot;
+  return 0;
+}
+
+int qmcp_run(hipStream_t st, const PersistLaunch* L) {
+  PersistArgs a;
+  a.ck = L->ck;
+  a.cv = L->cv;
+  a.cnt = (Counters*)L->counters;
+  a.cur = L->cur;
+  a.sk = L->sk;
+  a.sv = L->sv;
+  a.segcap = L->segcap;
+  a.seg_n = L->seg_n;
+  a.ik = L->ik;
+  a.iv = L->iv;
+  a.incap = L->incap;
+  a.in_n = L->in_n;
+  a.split = L->split;
+  a.P = L->P;
+  a.tab_base = L->tab_base;
+  a.tab_off = L->tab_off;
+  a.step0 = L->step0;
+  a.nsteps = L->nsteps;
+  a.seed = L->seed;
+  a.kl = KeyLayout{L->kbits, L->kbits >= 64 ? ~0ull : ((1ull << L->kbits) - 1)};
+  a.qshift = L->qshift;
+  a.slots = L->slots;
+  a.ctl = L->ctl;
+  a.epoch0 = L->epoch0;
+  a.cap_store = L->cap_store;
+  a.cap_inbox = L->cap_inbox;
+  a.rebal_min = L->rebal_min;
+  a.done = L->done;
+  hipLaunchKernelGGL(k_persist_prep, dim3(1), dim3(256), 0, st, a.cnt, a.in_n, a.P, a.done);
+  hipLaunchKernelGGL(k_splitters, dim3((a.P + 255) / 256), dim3(256), 0, st, a.ck, a.cnt, a.cur,
+                     a.P, L->split_w);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persist), dim3(a.P),
+                                            dim3(kPBlock), args, 0, st);
+  if (e != hipSuccess) return (int)e;
+  return (int)hipGetLastError();
+}
+
+int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t par) {
+  hipLaunchKernelGGL(k_gather, dim3(L->P), dim3(256), 0, st, L->sk, L->sv, L->seg_n, par, L->P,
+                     L->segcap, L->ck_w, L->cv_w, (Counters*)L->counters, L->cur);
+  return (int)hipGetLastError();
+}
+
+}  // extern "C"

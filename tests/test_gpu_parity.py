@@ -30,11 +30,15 @@ def B():
     return binding
 
 
-def _pair(B, orc, w, R=None, store=None, spawn=None, seed=None):
+PATHS = ["fused", "streamed"]
+
+
+def _pair(B, orc, w, R=None, store=None, spawn=None, seed=None, path="auto"):
     R = w.n_replicas if R is None else R
     seed = w.seed if seed is None else seed
     g = B.QMC.from_workload(w, store_capacity=store, spawn_capacity=spawn, n_replicas=R,
                             seed=seed)
+    g.set_path(path)
     o = orc.Oracle(w.n, R, seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
     return g, o
 
@@ -68,17 +72,19 @@ def _run_both(g, o, w, start, stop, threads=1):
 
 # ---- small random models: every step, several replicas --------------------------------------
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("seed", range(6))
-def test_random_models_every_step(B, orc, seed):
+def test_random_models_every_step(B, orc, seed, path):
     rng = np.random.default_rng(500 + seed)
     n = int(rng.integers(1, 5))
     h, lops = W.random_model(n, rng, n_h=int(rng.integers(1, 6)), n_l=int(rng.integers(0, 4)))
     keys, re, im = W.random_records(n, rng, int(rng.integers(1, 12)), scale=3000)
     R = int(rng.integers(1, 5))
     dt = 0.01
-    _say(f"random model seed={seed} n={n} R={R} keys={len(keys)}")
+    _say(f"random model seed={seed} n={n} R={R} keys={len(keys)} path={path}")
     g = B.QMC(n, R, 1000 + seed, dt, h, lops, keys, re, im, store_capacity=1 << (2 * n),
               spawn_capacity=4096)
+    g.set_path(path)
     o = orc.Oracle(n, R, 1000 + seed, dt, h, lops, keys, re, im)
     s = rng.normal(size=(40, len(h))) * 0.5
     gam = np.abs(rng.normal(size=(40, len(lops)))) * 0.5
@@ -88,10 +94,11 @@ def test_random_models_every_step(B, orc, seed):
         _assert_same(g, o, R, f"step {k}")
 
 
-def test_ghz4_full_trajectory(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_ghz4_full_trajectory(B, orc, path):
     w = W.config_ghz4()
-    _say(f"{w.name}: {w.nsteps} steps x {w.n_replicas} replicas")
-    g, o = _pair(B, orc, w, store=256, spawn=4096)
+    _say(f"{w.name}: {w.nsteps} steps x {w.n_replicas} replicas, {path}")
+    g, o = _pair(B, orc, w, store=256, spawn=4096, path=path)
     for k0 in range(0, w.nsteps, 20):
         _run_both(g, o, w, k0, k0 + 20)
         _assert_same(g, o, w.n_replicas, f"step {k0 + 20}")
@@ -99,7 +106,8 @@ def test_ghz4_full_trajectory(B, orc):
     assert c["step"] == w.nsteps
 
 
-def test_multi_tile_ragged_one_step(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_multi_tile_ragged_one_step(B, orc, path):
     """Thousands of keys spread over many merge tiles and a ragged tail."""
     rng = np.random.default_rng(9)
     n = 7
@@ -107,9 +115,10 @@ def test_multi_tile_ragged_one_step(B, orc):
     for count in (1, 1023, 1024, 1025, 5000, 12289):
         keys, re, im = W.random_records(n, rng, count, scale=200)
         R = 3
-        _say(f"multi-tile one step: {count} keys x {R} replicas")
+        _say(f"multi-tile one step: {count} keys x {R} replicas, {path}")
         g = B.QMC(n, R, 7, 0.01, h, lops, keys, re, im, store_capacity=1 << 14,
                   spawn_capacity=1 << 20)
+        g.set_path(path)
         o = orc.Oracle(n, R, 7, 0.01, h, lops, keys, re, im)
         s = rng.normal(size=(3, len(h)))
         gam = np.abs(rng.normal(size=(3, len(lops))))
@@ -120,10 +129,11 @@ def test_multi_tile_ragged_one_step(B, orc):
         g.close()
 
 
-def test_dd_small_with_pulses(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_dd_small_with_pulses(B, orc, path):
     w = W.dd(n=6, n_replicas=4, walker_target=20000, nsteps=800, seed=11)
-    _say(f"dd n=6: {w.nsteps} steps with ideal pulses")
-    g, o = _pair(B, orc, w, store=4096, spawn=1 << 16)
+    _say(f"dd n=6: {w.nsteps} steps with ideal pulses, {path}")
+    g, o = _pair(B, orc, w, store=4096, spawn=1 << 16, path=path)
     for k0 in range(0, w.nsteps, 100):
         _run_both(g, o, w, k0, k0 + 100)
         _assert_same(g, o, w.n_replicas, f"step {k0 + 100}")
@@ -143,12 +153,13 @@ def test_general_pauli_pulse_resorts(B, orc):
 
 # ---- the three configurations at full size ---------------------------------------------------
 
-def test_ghz20_nm_full_size(B, orc):
+@pytest.mark.parametrize("path", ["auto", "streamed"])
+def test_ghz20_nm_full_size(B, orc, path):
     """n=20 non-Markovian GHZ, 8 replicas x 1e7 walkers, all 3000 steps (the benchmarked
     workload, same launch configuration), every replica compared every 250 steps."""
     w = W.config_ghz20_nm()
-    _say(f"{w.name}: full size {w.nsteps} steps x {w.n_replicas} replicas")
-    g, o = _pair(B, orc, w, store=1 << 17, spawn=1 << 19)
+    _say(f"{w.name}: full size {w.nsteps} steps x {w.n_replicas} replicas, {path}")
+    g, o = _pair(B, orc, w, store=1 << 17, spawn=1 << 19, path=path)
     t0 = time.time()
     for k0 in range(0, w.nsteps, 250):
         g.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250])
@@ -157,12 +168,14 @@ def test_ghz20_nm_full_size(B, orc):
         _say(f"  step {k0 + 250} equal ({time.time() - t0:.1f}s)")
 
 
-def test_dd12_full_size_first_steps(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_dd12_full_size_first_steps(B, orc, path):
     """n=12 DD at full size (16 replicas x 1e6 walkers) over the first 600 steps (five pulse
     times), every replica against the oracle."""
     w = W.config_dd12()
-    _say(f"{w.name}: 16 replicas, first 600 steps")
+    _say(f"{w.name}: 16 replicas, first 600 steps, {path}")
     g = B.QMC.from_workload(w, store_capacity=1 << 20, spawn_capacity=1 << 18)
+    g.set_path(path)
     o = orc.Oracle(w.n, 16, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
     _run_both(g, o, w, 0, 600, threads=16)
     _assert_same(g, o, 16, "step 600")
@@ -234,9 +247,11 @@ def test_empty_replica_stays_empty(B, orc):
     assert len(g.export(1)[0]) == 0
 
 
-def test_spawn_capacity_error_rolls_back(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_spawn_capacity_error_rolls_back(B, orc, path):
     w = W.config_ghz4()
     g = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=2)
+    g.set_path(path)
     with pytest.raises(B.QMCError) as e:
         g.step(w.s[:50], w.gamma[:50])
     assert e.value.code == B.QMC_ERR_SPAWN_CAP
@@ -254,9 +269,11 @@ def test_spawn_capacity_error_rolls_back(B, orc):
             assert np.array_equal(x, y)
 
 
-def test_store_capacity_error(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_store_capacity_error(B, orc, path):
     w = W.config_ghz4()
     g = B.QMC.from_workload(w, store_capacity=3, spawn_capacity=4096)
+    g.set_path(path)
     with pytest.raises(B.QMCError) as e:
         g.step(w.s[:400], w.gamma[:400])
     assert e.value.code == B.QMC_ERR_STORE_CAP
@@ -267,9 +284,11 @@ def test_store_capacity_error(B, orc):
     _assert_same(g, o, w.n_replicas, "rolled back")
 
 
-def test_count_overflow_error(B, orc):
+@pytest.mark.parametrize("path", PATHS)
+def test_count_overflow_error(B, orc, path):
     g = B.QMC(1, 1, 1, 0.01, [], [], [0], [2_000_000_000], [0], store_capacity=4,
               spawn_capacity=4)
+    g.set_path(path)
     g.set_shift(0, 20.0)
     with pytest.raises(B.QMCError) as e:
         g.step(np.zeros((1, 0)), np.zeros((1, 0)))
@@ -286,6 +305,45 @@ def test_shift_matches_oracle(B, orc):
         o.set_shift(r, 0.3 * (r - 1.5))
     _run_both(g, o, w, 0, 100)
     _assert_same(g, o, w.n_replicas, "shifted")
+
+
+def _dense_spawner(n=8, R=4, seed=21):
+    """Every key of an n-qubit register occupied, with a model of many column groups: each key
+    range of the fused kernel receives far more than one inbox of children per step."""
+    rng = np.random.default_rng(seed)
+    h, lops = W.random_model(n, rng, n_h=24, n_l=4)
+    keys = np.arange(1 << (2 * n), dtype=np.uint64)
+    re = rng.integers(-3000, 3000, size=len(keys)).astype(np.int32)
+    im = rng.integers(-3000, 3000, size=len(keys)).astype(np.int32)
+    re[(re == 0) & (im == 0)] = 1
+    s = rng.normal(size=(3, len(h)))
+    gam = np.abs(rng.normal(size=(3, len(lops))))
+    return n, R, h, lops, keys, re, im, s, gam
+
+
+def test_auto_path_falls_back_to_streamed(B, orc):
+    n, R, h, lops, keys, re, im, s, gam = _dense_spawner()
+    _say(f"dense spawner: {len(keys)} keys x {R} replicas, automatic path")
+    g = B.QMC(n, R, 5, 0.01, h, lops, keys, re, im, store_capacity=1 << 17,
+              spawn_capacity=1 << 23)
+    o = orc.Oracle(n, R, 5, 0.01, h, lops, keys, re, im)
+    g.step(s, gam)
+    o.step(s, gam, threads=8)
+    _assert_same(g, o, R, "after 3 steps")
+
+
+def test_fused_only_reports_inbox_overflow(B, orc):
+    n, R, h, lops, keys, re, im, s, gam = _dense_spawner()
+    g = B.QMC(n, R, 5, 0.01, h, lops, keys, re, im, store_capacity=1 << 17,
+              spawn_capacity=1 << 23)
+    g.set_path("fused")
+    with pytest.raises(B.QMCError) as e:
+        g.step(s, gam)
+    assert e.value.code == B.QMC_ERR_SPAWN_CAP
+    st = g.counters()["step"]
+    o = orc.Oracle(n, R, 5, 0.01, h, lops, keys, re, im)
+    o.step(s[:st], gam[:st])
+    _assert_same(g, o, R, f"rolled back to step {st}")
 
 
 def test_dt_error_leaves_state(B, orc):

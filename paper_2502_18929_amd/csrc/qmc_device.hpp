@@ -28,6 +28,7 @@ constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
 constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)
+constexpr int kTermPad = 4;          // terms per group are a multiple of this in a packed table
 
 // Device error bits (counters.err).
 enum : uint32_t {
@@ -48,7 +49,8 @@ struct Term {
 // Packed per-step table (host-built, 16-byte aligned):
 //   TableHeader | uint64 gx[n_groups] | uint32 gs[n_groups + 1] (padded to 16 B) | Term t[n_terms]
 // Group 0 is the diagonal group (gx[0] == 0, possibly empty); groups 1.. are off-diagonal in
-// increasing xmask order.  q_off / q_diag bound sum(|c_re| + |c_im|) over all off-diagonal
+// increasing xmask order.  Every group's term range is padded with zero terms to a nonzero
+// multiple of kTermPad terms (a zero term adds nothing whatever its sign).  q_off / q_diag bound sum(|c_re| + |c_im|) over all off-diagonal
 // groups / over the diagonal group of any key.
 struct TableHeader {
   uint32_t n_groups;
@@ -152,19 +154,32 @@ __device__ __forceinline__ void atomic_store_agent(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct TableView {
-  const TableHeader* h;
-  const uint64_t* gx;
-  const uint32_t* gs;
-  const Term* t;
-};
+// Step tables are read-only while any kernel runs and every lane of a wave reads the same
+// entry, so they are addressed in the constant address space: the loads go through the scalar
+// unit and cache, and the values arrive in scalar registers.
+// A kernel that copies the table into LDS first reads it there instead (lptr).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+using lptr = const T*;
 
-__device__ __forceinline__ TableView table_view(const uint8_t* tab) {
-  TableView v;
-  v.h = reinterpret_cast<const TableHeader*>(tab);
-  v.gx = reinterpret_cast<const uint64_t*>(tab + v.h->gx_off);
-  v.gs = reinterpret_cast<const uint32_t*>(tab + v.h->gs_off);
-  v.t = reinterpret_cast<const Term*>(tab + v.h->t_off);
+template <template <class> class Ptr>
+struct TableViewT {
+  Ptr<TableHeader> h;
+  Ptr<uint64_t> gx;
+  Ptr<uint32_t> gs;
+  Ptr<Term> t;
+};
+using TableView = TableViewT<cptr>;
+
+template <template <class> class Ptr = cptr>
+__device__ __forceinline__ TableViewT<Ptr> table_view(const uint8_t* tab) {
+  const Ptr<uint8_t> b = (Ptr<uint8_t>)tab;
+  TableViewT<Ptr> v;
+  v.h = (Ptr<TableHeader>)b;
+  v.gx = (Ptr<uint64_t>)(b + v.h->gx_off);
+  v.gs = (Ptr<uint32_t>)(b + v.h->gs_off);
+  v.t = (Ptr<Term>)(b + v.h->t_off);
   return v;
 }
 
@@ -183,16 +198,24 @@ __device__ __forceinline__ void walker_random(uint64_t key, uint32_t step, uint3
                 (uint32_t)(seed >> 32), w);
 }
 
-// Group coefficient c = sum_t (-1)^parity(zmask_t & key) q_t; |c_re| + |c_im| < 2^31.
-__device__ __forceinline__ void group_coeff(const Term* __restrict__ t, uint32_t b, uint32_t e,
-                                            uint64_t key, int32_t& cre, int32_t& cim) {
+// Group coefficient c = sum_t (-1)^parity(zmask_t & key) q_t; |c_re| + |c_im| < 2^31, so every
+// partial sum fits int32.  [b, e) is a padded group range: a nonzero multiple of kTermPad terms.
+template <class TP>
+__device__ __forceinline__ void group_coeff(TP t, uint32_t b, uint32_t e, uint64_t key,
+                                            int32_t& cre, int32_t& cim) {
   int32_t re = 0, im = 0;
-  for (uint32_t i = b; i < e; ++i) {
-    const Term tm = t[i];
-    const int32_t s = -(int32_t)parity64(tm.zmask & key);  // 0 or -1
-    re += (tm.qre ^ s) - s;
-    im += (tm.qim ^ s) - s;
-  }
+  uint32_t i = b;
+  do {
+#pragma unroll
+    for (int u = 0; u < kTermPad; ++u) {
+      const uint64_t zm = t[i + u].zmask;
+      const int32_t qre = t[i + u].qre, qim = t[i + u].qim;
+      const int32_t s = -(int32_t)parity64(zm & key);  // 0 or -1
+      re += (qre ^ s) - s;
+      im += (qim ^ s) - s;
+    }
+    i += kTermPad;
+  } while (i < e);
   cre = re;
   cim = im;
 }

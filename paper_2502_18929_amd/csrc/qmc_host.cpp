@@ -46,7 +46,7 @@ struct QTerm {
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, in_k, in_v, in_n, split, tab_off,
-      slots, ctl, done, total;
+      slots, done, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -107,7 +107,6 @@ bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
   L.split = take((size_t)P * 8);
   L.tab_off = take((size_t)kMaxChunkSteps * 4);
   L.slots = take((size_t)P * 4 * 8);
-  L.ctl = take(16 * 8);
   L.done = take(8);
   L.total = o;
   return true;
@@ -303,7 +302,15 @@ int build_table(const qmc_ctx* c, const double* s, const double* g, HostTable& T
 }
 
 size_t pack_table(const HostTable& T, uint8_t* dst) {
-  const uint32_t G = (uint32_t)T.gx.size(), NT = (uint32_t)T.t.size();
+  // device layout: every group's terms padded with zero terms to a nonzero multiple of kTermPad
+  const uint32_t G = (uint32_t)T.gx.size();
+  std::vector<uint32_t> gs(G + 1, 0);
+  for (uint32_t g = 0; g < G; ++g) {
+    const uint32_t len = T.gs[g + 1] - T.gs[g];
+    const uint32_t blocks = len == 0 ? 1u : (len + qmc::kTermPad - 1) / qmc::kTermPad;
+    gs[g + 1] = gs[g] + blocks * qmc::kTermPad;
+  }
+  const uint32_t NT = gs[G];
   qmc::TableHeader h{};
   h.n_groups = G;
   h.n_terms = NT;
@@ -317,13 +324,15 @@ size_t pack_table(const HostTable& T, uint8_t* dst) {
   std::memset(dst, 0, h.bytes);
   std::memcpy(dst, &h, sizeof(h));
   std::memcpy(dst + h.gx_off, T.gx.data(), 8 * G);
-  std::memcpy(dst + h.gs_off, T.gs.data(), 4 * (G + 1));
+  std::memcpy(dst + h.gs_off, gs.data(), 4 * (G + 1));
   qmc::Term* tt = reinterpret_cast<qmc::Term*>(dst + h.t_off);
-  for (uint32_t i = 0; i < NT; ++i) {
-    tt[i].zmask = T.t[i].zmask;
-    tt[i].qre = (int32_t)T.t[i].qre;
-    tt[i].qim = (int32_t)T.t[i].qim;
-  }
+  for (uint32_t g = 0; g < G; ++g)
+    for (uint32_t i = T.gs[g]; i < T.gs[g + 1]; ++i) {
+      qmc::Term& o = tt[gs[g] + (i - T.gs[g])];
+      o.zmask = T.t[i].zmask;
+      o.qre = (int32_t)T.t[i].qre;
+      o.qim = (int32_t)T.t[i].qim;
+    }
   return h.bytes;
 }
 
@@ -515,7 +524,6 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
   if (e == hipSuccess)
     e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)c->L.P * 4 * 8, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->at<uint64_t>(c->L.ctl), 0, 16 * 8, c->stream);
   if (e != hipSuccess) {
     qmc_destroy(c);
     return QMC_ERR_HIP;
@@ -579,9 +587,9 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
   pl.nsteps = nst;
   pl.seed = c->cfg.seed;
   pl.kbits = c->kbits;
+  pl.n_replicas = c->R;
   pl.qshift = c->at<int64_t>(c->L.qshift);
   pl.slots = c->at<uint64_t>(c->L.slots);
-  pl.ctl = c->at<uint64_t>(c->L.ctl);
   pl.epoch0 = c->epoch + 1;
   c->epoch += (uint64_t)nst + 1;  // barriers of this launch: batch start + one per step
   pl.cap_store = c->L.cap_store;
@@ -595,9 +603,10 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
       HIPCHK(c, hipEventCreate(&ev));
       c->prof_ev.push_back(ev);
     }
-    HIPCHK(c, hipEventRecord(c->prof_ev[0], c->stream));
   }
-  HIPCHK(c, qmcp_run(c->stream, &pl));
+  HIPCHK(c, qmcp_prepare(c->stream, &pl));
+  if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[0], c->stream));
+  HIPCHK(c, qmcp_launch(c->stream, &pl));
   if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[1], c->stream));
   HIPCHK(c, hipMemcpyAsync(pin_done, pl.done, 8, hipMemcpyDeviceToHost, c->stream));
   int rc = read_counters(c, hc);  // synchronizes the stream
@@ -739,10 +748,17 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
   }
   const uint32_t first_step = c->step;
   const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
+  size_t max_tbytes = 0;
+  for (size_t b : tbytes) max_tbytes = std::max(max_tbytes, b);
+  const bool fused_fits = max_tbytes <= kPersistTableBytes;
+  if (c->path == 1 && !fused_fits)
+    return fail(c, QMC_ERR_ARG, "step table larger than the fused kernel takes; use the "
+                                "automatic or streamed path");
   uint32_t last_local_fail = 0xFFFFFFFFu;
   while (c->step < first_step + nsteps) {
     const uint32_t k0 = c->step - first_step;
-    const bool fused = c->path == 1 || (c->path == 0 && c->step >= c->streamed_until &&
+    const bool fused = c->path == 1 || (c->path == 0 && fused_fits &&
+                                        c->step >= c->streamed_until &&
                                         c->n_occ <= fused_max_keys);
     // One launch (fused) or one stream of launches: as many of the remaining steps as fit the
     // table area; an automatic streamed run stops where the fused kernel may be tried again.

@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Largest packed step table the persistent kernel takes (it keeps the table in LDS); batches
+// with larger tables run on the streamed kernels.
+constexpr uint32_t kPersistTableBytes = 8192;
+
 struct PersistLaunch {
   const uint64_t* ck;   // canonical store (read at batch start)
   const int2* cv;
@@ -26,9 +30,9 @@ struct PersistLaunch {
   uint32_t step0, nsteps;
   uint64_t seed;
   uint32_t kbits;
+  uint32_t n_replicas;
   const int64_t* qshift;
   uint64_t* slots;      // [P][4] epoch-tagged per-workgroup barrier slots (zeroed once)
-  uint64_t* ctl;        // [10] released epoch and reduced totals (zeroed once)
   uint64_t epoch0;      // first barrier epoch of the launch
   uint64_t cap_store;
   uint64_t cap_inbox;
@@ -38,6 +42,9 @@ struct PersistLaunch {
 
 extern "C" {
 int qmcp_max_segments(int* P);
-int qmcp_run(hipStream_t st, const PersistLaunch* L);
+// Zero the inbox counts and error flags and compute the splitters of the canonical store.
+int qmcp_prepare(hipStream_t st, const PersistLaunch* L);
+// The cooperative launch of the persistent step kernel (after qmcp_prepare).
+int qmcp_launch(hipStream_t st, const PersistLaunch* L);
 int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t par);
 }

@@ -6,14 +6,16 @@
 // sorted segment, and every record destined to its range (spawned children, and the death/cloning
 // delta of each of its own parents) arrives in its inbox.  One step of workgroup p:
 //   1. sort the inbox in LDS (bitonic);
-//   2. stream the parents of the segment in register tiles, merge them with the inbox, sum every
+//   2. stream the parents of the segment through LDS in tiles, merge them with the inbox, sum every
 //      key in int64 (annihilation, End Matter), drop empty keys, write the new segment;
 //   3. for every new parent draw Philox once (step s+1) and, only for the parents whose column
 //      can produce a nonzero amount (|a|+|b|)*sum|q| + U >= 2^32, evaluate the death delta
 //      (diagonal of the column applied to N(s+1)) and the off-diagonal children, and route each
-//      record to the inbox of the workgroup owning its key (wave-aggregated atomics);
+//      record to the inbox of the workgroup owning its key (one atomic per destination);
 //   4. grid barrier.
-// One grid barrier per step, no global sort passes, parents read and written once per step.
+// The batch starts with the same pass over the canonical store with an empty inbox, which copies
+// each workgroup's slice into its segment and draws the first step.  One grid barrier per step,
+// no global sort passes, parents read and written once per step.
 #include "qmc_device.hpp"
 #include "qmc_persist.h"
 
@@ -24,10 +26,9 @@ constexpr int kPWaves = kPBlock / kWave;   // 8
 constexpr int kPTile = 1024;               // parents per tile (staged in LDS)
 constexpr int kRing = 128;                 // per-wave queue of active new parents
 constexpr int kStage = 256;                // per-wave staging of routed records
-constexpr int kTabLds = 8192;              // bytes of a step table kept in LDS
 
 struct PersistArgs {
-  // canonical store: sorted records of all replicas (read in phase A)
+  // canonical store: sorted records of all replicas (read by the first pass)
   const uint64_t* ck;
   const int2* cv;
   Counters* cnt;
@@ -51,10 +52,10 @@ struct PersistArgs {
   uint32_t step0, nsteps;
   uint64_t seed;
   KeyLayout kl;
+  uint32_t n_replicas;
   const int64_t* qshift;
   // synchronization and reporting
   uint64_t* slots;        // [P][4] per workgroup: epoch, keys out, inbox records, error bits
-  uint64_t* ctl;          // [0] released epoch, [2 + 4*(e&1) ..] reduced totals of epoch e
   uint64_t cap_store;     // total occupied keys allowed
   uint64_t cap_inbox;     // total inbox records allowed per step
   uint32_t rebal_min;     // imbalance slack before a rebalancing stop
@@ -72,14 +73,16 @@ struct Shared {
   uint64_t ring_k[kPWaves][kRing];
   int2 ring_v[kPWaves][kRing];
   uint2 ring_w[kPWaves][kRing];
+  int64_t ring_s[kPWaves][kRing];
   uint64_t st_k[kPWaves][kStage];
   int2 st_v[kPWaves][kStage];
   uint64_t red[kPWaves];
-  uint64_t dec[4];
-  uint8_t tab[kTabLds] __attribute__((aligned(16)));        // reduced totals of the last barrier: keys, max segment, inbox, errors
-  uint32_t flag;
+  uint64_t xch[kPWaves][4];
+  uint64_t dec[4];        // reduced totals of the last barrier: keys, max segment, inbox, errors
+  uint4 tab[kPersistTableBytes / 16];  // the step table of the spawns drawn in this pass
   uint32_t err;           // error bits this workgroup raised in the current step
 };
+using LTable = TableViewT<lptr>;
 
 // Cross-workgroup data (inbox records and counts, barrier slots) is written and read only with
 // agent-scope atomic accesses: on gfx950 these go through to the device coherence point and never
@@ -172,20 +175,19 @@ __device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint6
     nn += __shfl_xor(nn, o);
     er |= __shfl_xor(er, o);
   }
-  __syncthreads();  // the reduction scratch below may still be read by a slow wave
   if (__lane_id() == 0) {
-    S.ring_k[t / kWave][0] = tot;
-    S.ring_k[t / kWave][1] = mx;
-    S.ring_k[t / kWave][2] = nn;
-    S.ring_k[t / kWave][3] = er;
+    S.xch[t / kWave][0] = tot;
+    S.xch[t / kWave][1] = mx;
+    S.xch[t / kWave][2] = nn;
+    S.xch[t / kWave][3] = er;
   }
   __syncthreads();
   if (t == 0) {
     for (int w = 1; w < kPWaves; ++w) {
-      tot += S.ring_k[w][0];
-      mx = S.ring_k[w][1] > mx ? S.ring_k[w][1] : mx;
-      nn += S.ring_k[w][2];
-      er |= S.ring_k[w][3];
+      tot += S.xch[w][0];
+      mx = S.xch[w][1] > mx ? S.xch[w][1] : mx;
+      nn += S.xch[w][2];
+      er |= S.xch[w][3];
     }
     S.dec[0] = tot;
     S.dec[1] = mx;
@@ -222,21 +224,121 @@ __device__ __forceinline__ uint64_t lower_bound_glb(const uint64_t* a, uint64_t 
   return lo;
 }
 
-// In-place bitonic sort of m (a power of two) records in LDS, by key.
-__device__ __forceinline__ void bitonic_sort(uint64_t* k, int2* v, uint32_t m) {
+// Inbox order: by key, and among equal keys a padding record (value (0, 0), which no routed
+// record carries) after the real ones, so that the first c sorted records are the c real ones
+// even when a real key equals the padding key ~0.
+__device__ __forceinline__ bool inbox_less(uint64_t ka, int2 va, uint64_t kb, int2 vb) {
+  if (ka != kb) return ka < kb;
+  const bool pa = (va.x | va.y) == 0, pb = (vb.x | vb.y) == 0;
+  return !pa && pb;
+}
+
+// Compare-exchange of a bitonic network on the element held by this thread (index i) and its
+// partner (index i ^ stride, holding pk/pv): the lower index of an ascending pair keeps the
+// smaller record.  Equal records stay where they are.
+__device__ __forceinline__ void bitonic_keep(uint32_t i, uint32_t size, uint32_t stride,
+                                             uint64_t& k, int2& v, uint64_t pk, int2 pv) {
+  const bool asc = (i & size) == 0, lower = (i & stride) == 0;
+  const bool take = (asc == lower) ? inbox_less(pk, pv, k, v) : inbox_less(k, v, pk, pv);
+  if (take) {
+    k = pk;
+    v = pv;
+  }
+}
+
+// Sorts the m (a power of two) records of the inbox in LDS (c real ones, then padding).  Up to
+// one record per thread the network runs in registers: partners within a wave are exchanged by
+// lane shuffles, only the strides of 64 and more go through LDS.  When the composite keys leave
+// 12 bits free, the network sorts one 64-bit word per record, (key << 12) | index, with ~0 for
+// the padding, and the values follow by index.  Larger inboxes take the LDS network.
+__device__ __forceinline__ void sort_inbox(Shared& S, uint32_t m, uint32_t c, bool packed) {
+  const uint32_t t = threadIdx.x;
+  if (packed && m <= (uint32_t)kPBlock) {
+    // Each wave sorts its 64 words in registers (lane shuffles only); the final position of a
+    // word is the number of smaller words over all sorted chunks (distinct words: the index
+    // makes them unique), found by binary search in each chunk.
+    const uint32_t lane = __lane_id(), nch = (c + kWave - 1) / kWave;
+    uint64_t k = ~0ull;
+    if (t / kWave < nch) {
+      k = t < c ? (S.in_k[t] << 12) | t : ~0ull;
+      for (uint32_t size = 2; size <= (uint32_t)kWave; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+          const uint64_t pk = __shfl_xor(k, (int)stride);
+          const bool asc = (lane & size) == 0, lower = (lane & stride) == 0;
+          if ((asc == lower) ? (pk < k) : (pk > k)) k = pk;
+        }
+      }
+      S.pa_k[t] = k;
+    }
+    __syncthreads();
+    uint32_t rank = 0;
+    if (t < nch * kWave && k != ~0ull) {
+      for (uint32_t w = 0; w < nch; ++w) {
+        const uint64_t* ch = S.pa_k + w * kWave;
+        uint32_t pos = 0;
+#pragma unroll
+        for (uint32_t st = kWave / 2; st > 0; st >>= 1)
+          if (ch[pos + st - 1] < k) pos += st;
+        if (ch[pos] < k) ++pos;  // the search leaves pos <= 63; this counts the last word
+        rank += pos;
+      }
+    }
+    int2 v = make_int2(0, 0);
+    const bool real = t < nch * kWave && k != ~0ull;
+    if (real) v = S.in_v[k & 0xFFFu];
+    __syncthreads();
+    if (real) {
+      S.in_k[rank] = k >> 12;
+      S.in_v[rank] = v;
+    }
+    __syncthreads();
+    return;
+  }
+  if (m <= (uint32_t)kPBlock) {
+    uint64_t k = t < m ? S.in_k[t] : 0;
+    int2 v = t < m ? S.in_v[t] : make_int2(0, 0);
+    for (uint32_t size = 2; size <= m; size <<= 1) {
+      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        uint64_t pk;
+        int2 pv;
+        if (stride >= (uint32_t)kWave) {
+          __syncthreads();
+          if (t < m) {
+            S.in_k[t] = k;
+            S.in_v[t] = v;
+          }
+          __syncthreads();
+          pk = S.in_k[(t ^ stride) & (m - 1)];
+          pv = S.in_v[(t ^ stride) & (m - 1)];
+        } else {
+          pk = __shfl_xor(k, (int)stride);
+          pv.x = __shfl_xor(v.x, (int)stride);
+          pv.y = __shfl_xor(v.y, (int)stride);
+        }
+        if (t < m) bitonic_keep(t, size, stride, k, v, pk, pv);
+      }
+    }
+    __syncthreads();
+    if (t < m) {
+      S.in_k[t] = k;
+      S.in_v[t] = v;
+    }
+    __syncthreads();
+    return;
+  }
   for (uint32_t size = 2; size <= m; size <<= 1) {
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t t = threadIdx.x; t < (m >> 1); t += kPBlock) {
-        const uint32_t lo = 2 * t - (t & (stride - 1));
+      for (uint32_t i = t; i < (m >> 1); i += kPBlock) {
+        const uint32_t lo = 2 * i - (i & (stride - 1));
         const uint32_t hi = lo + stride;
         const bool asc = (lo & size) == 0;
-        const uint64_t a = k[lo], b = k[hi];
-        if ((a > b) == asc) {
-          k[lo] = b;
-          k[hi] = a;
-          const int2 x = v[lo];
-          v[lo] = v[hi];
-          v[hi] = x;
+        const uint64_t a = S.in_k[lo], b = S.in_k[hi];
+        const int2 va = S.in_v[lo], vb = S.in_v[hi];
+        if (asc ? inbox_less(b, vb, a, va) : inbox_less(a, va, b, vb)) {
+          S.in_k[lo] = b;
+          S.in_k[hi] = a;
+          S.in_v[lo] = vb;
+          S.in_v[hi] = va;
         }
       }
       __syncthreads();
@@ -244,10 +346,10 @@ __device__ __forceinline__ void bitonic_sort(uint64_t* k, int2* v, uint32_t m) {
   }
 }
 
-// Routed emission.  Records are staged per wave in LDS; a flush routes them to the inbox of the
-// workgroup owning each key (binary search in the splitters), reserving space with one atomic per
-// distinct destination per chunk of 64 records; the atomics of all chunks of a flush are issued
-// before any of their results is needed, so a flush costs about one atomic round trip.
+// Routed emission.  Records are staged per wave in LDS; a flush finds the workgroup owning each
+// key (fixed-length binary search in the splitters, all chunks interleaved), groups the records
+// of each destination, and reserves inbox space with one atomic per distinct destination, all
+// issued by one instruction, so a flush costs one atomic round trip.
 struct Router {
   uint32_t* in_n;          // [2][P]
   uint64_t* ik;            // [2][P][incap]
@@ -269,9 +371,9 @@ struct Router {
     const uint32_t lane = __lane_id();
     const uint64_t lt = lanemask_lt();
     constexpr int NC = kStage / kWave;
-    uint32_t q[NC], rank[NC], base[NC];
     uint64_t key[NC];
     int2 val[NC];
+    uint32_t q[NC];
     bool has[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -279,23 +381,49 @@ struct Router {
       has[c] = i < fill;
       key[c] = has[c] ? sk[i] : 0;
       val[c] = has[c] ? sv[i] : make_int2(0, 0);
-      q[c] = has[c] ? upper_bound_lds(split, P, key[c]) - 1 : 0u;
+      q[c] = 0;
+    }
+    // destination: the largest p with split[p] <= key (split[0] == 0)
+    for (uint32_t st = pbits ? 1u << (pbits - 1) : 0u; st > 0; st >>= 1) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const uint32_t cand = q[c] + st;
+        if (cand < P && split[cand] <= key[c]) q[c] = cand;
+      }
+    }
+    wave_lds_fence();  // the staging area becomes the table of distinct destinations
+    uint32_t* pq = reinterpret_cast<uint32_t*>(sk);            // [kStage] destination
+    uint32_t* pc = reinterpret_cast<uint32_t*>(sv);            // [kStage] records
+    uint32_t* pb = reinterpret_cast<uint32_t*>(sv) + kStage;   // [kStage] reserved base
+    uint32_t np = 0;  // distinct (chunk, destination) pairs so far, wave-uniform
+    uint32_t rank[NC], pidx[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
       uint64_t peers = __ballot(has[c]);
       for (uint32_t b = 0; b < pbits; ++b) {
         const uint64_t bm = __ballot((q[c] >> b) & 1u);
         peers &= ((q[c] >> b) & 1u) ? bm : ~bm;
       }
       rank[c] = (uint32_t)__popcll(peers & lt);
-      base[c] = 0;
-      if (has[c] && rank[c] == 0) base[c] = atomicAdd(&in_n[par * P + q[c]], (uint32_t)__popcll(peers));
-      // leader lane of my destination group
-      rank[c] |= (has[c] ? ((uint32_t)__ffsll((unsigned long long)peers) - 1) : 0u) << 16;
+      const bool lead = has[c] && rank[c] == 0;
+      const uint64_t lm = __ballot(lead);
+      const uint32_t my = np + (uint32_t)__popcll(lm & lt);
+      if (lead) {
+        pq[my] = q[c];
+        pc[my] = (uint32_t)__popcll(peers);
+      }
+      const int leader = has[c] ? __ffsll((unsigned long long)peers) - 1 : 0;
+      pidx[c] = __shfl(my, leader);
+      np += (uint32_t)__popcll(lm);
     }
+    wave_lds_fence();
+    for (uint32_t j = lane; j < np; j += kWave)
+      pb[j] = atomicAdd(&in_n[par * P + pq[j]], pc[j]);
+    wave_lds_fence();
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const uint32_t b = __shfl(base[c], (int)(rank[c] >> 16));
       if (has[c]) {
-        const uint32_t pos = b + (rank[c] & 0xFFFFu);
+        const uint32_t pos = pb[pidx[c]] + rank[c];
         if (pos < incap) {
           const uint64_t off = ((uint64_t)par * P + q[c]) * incap + pos;
           st_agent(&ik[off], key[c]);
@@ -325,17 +453,15 @@ struct Router {
 
 // Death delta and children of up to 64 queued active parents of one wave (dense: every lane
 // holds one parent).
-__device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, Router& R, const TableView& tn,
-                               uint32_t wave, uint32_t n, uint32_t step) {
+__device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, Router& R,
+                                               const LTable& tn, uint32_t wave, uint32_t n) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < n;
   const uint64_t ck = valid ? S.ring_k[wave][lane] : 0;
   const int2 v = valid ? S.ring_v[wave][lane] : make_int2(0, 0);
   const uint2 w = valid ? S.ring_w[wave][lane] : make_uint2(0, 0);
-  const KeyLayout kl = A.kl;
-  const uint64_t key = kl.key(ck);
-  const uint32_t rep = kl.replica(ck);
-  const int64_t qs = valid ? A.qshift[rep] : 0;
+  const int64_t qs = valid ? S.ring_s[wave][lane] : 0;
+  const uint64_t key = A.kl.key(ck);
   const uint64_t sab = uabs64(v.x) + uabs64(v.y);
   // Death/cloning delta from the diagonal group (applied to N(t) in the next merge).
   {
@@ -359,26 +485,30 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
   const bool act = valid && G > 1 && !comb_all_zero(sab, tn.h->q_off, w.x);
   if (__ballot(act) == 0) return;
   uint64_t r = w.x;
+  uint32_t gb = tn.gs[1];
   for (uint32_t g = 1; g < G; ++g) {
+    const uint32_t ge = tn.gs[g + 1];
+    const uint64_t gxm = tn.gx[g];
     int2 child = make_int2(0, 0);
     if (act) {
       int32_t cre, cim;
-      group_coeff(tn.t, tn.gs[g], tn.gs[g + 1], key, cre, cim);
+      group_coeff(tn.t, gb, ge, key, cre, cim);
       int64_t xre, xim;
       cmul_q32(v.x, v.y, cre, cim, xre, xim);
       child.x = (int32_t)comb_step(r, xre);
       child.y = (int32_t)comb_step(r, xim);
     }
-    R.emit((child.x | child.y) != 0, ck ^ tn.gx[g], child);
+    R.emit((child.x | child.y) != 0, ck ^ gxm, child);
+    gb = ge;
   }
-  (void)step;
 }
 
 // Draw Philox for new parents [o0, o1) of segment buffer (seg_k, seg_v) at step `step` and
 // route their death deltas and children.  Uniform loop; active parents are compacted per wave.
-__device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router& R, const TableView& tn,
-                        const uint64_t* seg_k, const int2* seg_v, uint64_t o0, uint64_t o1,
-                        uint32_t step) {
+__device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router& R,
+                                        const LTable& tn, const uint64_t* seg_k,
+                                        const int2* seg_v, uint64_t o0, uint64_t o1,
+                                        uint32_t step) {
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
   const uint64_t q_diag = tn.h->q_diag, q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
@@ -390,14 +520,15 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
     int2 v = make_int2(0, 0);
     bool act = false;
     uint32_t w[4] = {0, 0, 0, 0};
+    int64_t qs = 0;
     if (valid) {
       ck = seg_k[i];
       v = seg_v[i];
       const uint32_t rep = kl.replica(ck);
+      qs = A.qshift[rep];
       walker_random(kl.key(ck), step, rep, A.seed, w);
       const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-      act = !comb_all_zero(sab, q_diag + uabs64(A.qshift[rep]), w[1]) ||
-            !comb_all_zero(sab, q_off, w[0]);
+      act = !comb_all_zero(sab, q_diag + uabs64(qs), w[1]) || !comb_all_zero(sab, q_off, w[0]);
     }
     const uint64_t m = __ballot(act);
     if (m) {
@@ -406,46 +537,38 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
         S.ring_k[wave][pos] = ck;
         S.ring_v[wave][pos] = v;
         S.ring_w[wave][pos] = make_uint2(w[0], w[1]);
+        S.ring_s[wave][pos] = qs;
       }
       fill += (uint32_t)__popcll(m);
       wave_lds_fence();
       if (fill >= kWave) {
-        process_active(A, S, R, tn, wave, kWave, step);
+        process_active(A, S, R, tn, wave, kWave);
         // move the overflow (fill - 64 < 64 entries) to the front of the queue
         const uint32_t rest = fill - kWave;
         uint64_t rk = 0;
         int2 rv = make_int2(0, 0);
         uint2 rw = make_uint2(0, 0);
+        int64_t rs = 0;
         if (lane < rest) {
           rk = S.ring_k[wave][kWave + lane];
           rv = S.ring_v[wave][kWave + lane];
           rw = S.ring_w[wave][kWave + lane];
+          rs = S.ring_s[wave][kWave + lane];
         }
         wave_lds_fence();
         if (lane < rest) {
           S.ring_k[wave][lane] = rk;
           S.ring_v[wave][lane] = rv;
           S.ring_w[wave][lane] = rw;
+          S.ring_s[wave][lane] = rs;
         }
         wave_lds_fence();
         fill = rest;
       }
     }
   }
-  if (fill) process_active(A, S, R, tn, wave, fill, step);
+  if (fill) process_active(A, S, R, tn, wave, fill);
   R.flush();
-}
-
-// The table of one step in LDS when it fits (terms are then read at LDS latency).
-__device__ __forceinline__ TableView stage_table(Shared& S, const uint8_t* g) {
-  const uint32_t bytes = reinterpret_cast<const TableHeader*>(g)->bytes;
-  __syncthreads();  // previous readers of S.tab are done
-  if (bytes > (uint32_t)kTabLds) return table_view(g);
-  const uint4* src = reinterpret_cast<const uint4*>(g);
-  uint4* dst = reinterpret_cast<uint4*>(S.tab);
-  for (uint32_t i = threadIdx.x; i < bytes / 16; i += kPBlock) dst[i] = src[i];
-  __syncthreads();
-  return table_view(S.tab);
 }
 
 // Merge one segment's parents (sorted, global) with its sorted inbox (LDS), sum per key,
@@ -457,7 +580,7 @@ __device__ __forceinline__ TableView stage_table(Shared& S, const uint8_t* g) {
 __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, const uint64_t* pk,
                                               const int2* pv, uint64_t np, uint32_t c, uint64_t* ok,
                                               int2* ov, uint32_t step, bool spawn, Router R,
-                                              const TableView tn, uint32_t nstep) {
+                                              const LTable tn, uint32_t nstep) {
   const uint32_t t = threadIdx.x;
   uint64_t out_run = 0;   // block-uniform
   uint64_t wsum = 0;
@@ -573,63 +696,38 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
 
 __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   __shared__ Shared S;
-  const uint32_t p = blockIdx.x, t = threadIdx.x;
+  const uint32_t t = threadIdx.x, p = blockIdx.x;
   const uint32_t P = A.P;
   Counters* cnt = A.cnt;
   uint32_t pbits = 0;
   while ((1u << pbits) < P) ++pbits;
+  // composite keys below 2^52: the inbox sort can pack a 12-bit record index under the key
+  uint32_t rbits = 0;
+  while ((1ull << rbits) < (uint64_t)A.n_replicas) ++rbits;
+  const bool packed = A.kl.kbits + rbits <= 52;
   for (uint32_t i = t; i < P; i += kPBlock) S.split[i] = A.split[i];
-  __syncthreads();
-  const uint64_t lo_key = S.split[p];
-  const uint64_t n_can = cnt->n_store[A.cur];
-
-  if (t == 0) S.err = 0;
-  // Phase A: this workgroup's slice of the canonical store becomes its segment (buffer 0), and
-  // the death deltas and children of the first step go to the inboxes (parity 0).
   if (t == 0) {
-    const uint64_t b = lower_bound_glb(A.ck, n_can, lo_key);
-    const uint64_t e = p + 1 < P ? lower_bound_glb(A.ck, n_can, S.split[p + 1]) : n_can;
-    S.red[0] = b;
-    S.red[1] = e;
-    st_agent(&A.in_n[1 * P + p], 0u);  // inbox of step 1 (parity 1) starts empty
+    S.err = 0;
+    // this workgroup's slice of the canonical store
+    const uint64_t n_can = cnt->n_store[A.cur];
+    S.red[0] = lower_bound_glb(A.ck, n_can, A.split[p]);
+    S.red[1] = p + 1 < P ? lower_bound_glb(A.ck, n_can, A.split[p + 1]) : n_can;
   }
   __syncthreads();
   const uint64_t cb = S.red[0], ce = S.red[1];
   __syncthreads();
-  uint64_t np = ce - cb;
-  if (np > A.segcap) {
-    if (t == 0) raise_err(cnt, &S.err, kErrSegCap, A.step0);
-    np = 0;
-  }
-  uint64_t* seg_k0 = A.sk + (uint64_t)p * A.segcap;
-  int2* seg_v0 = A.sv + (uint64_t)p * A.segcap;
-  for (uint64_t i = t; i < np; i += kPBlock) {
-    seg_k0[i] = A.ck[cb + i];
-    seg_v0[i] = A.cv[cb + i];
-  }
-  if (t == 0) A.seg_n[p] = (uint32_t)np;
-  __syncthreads();
-  {
-    const TableView tn = stage_table(S, A.tab_base + A.tab_off[0]);
-    Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, 0u, A.step0, &S.err,
-             S.st_k[t / kWave], S.st_v[t / kWave], 0u};
-    advance(A, S, R, tn, seg_k0, seg_v0, 0, np, A.step0);
-  }
-  uint64_t epoch = A.epoch0;
-  if (!grid_sync(S, A, epoch, np, 0) || S.dec[3]) {
-    if (p == 0 && t == 0) {
-      A.done[0] = 0;
-      A.done[1] = 2;
-    }
-    return;
-  }
 
+  // Pass k = -1 merges the canonical slice with an empty inbox into segment buffer 0 and draws
+  // step0 from it; pass k >= 0 is step step0 + k: segment buffer k & 1 and inbox parity k & 1
+  // in, buffer and parity (k & 1) ^ 1 out.
+  uint64_t epoch = A.epoch0 - 1;
   uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
   uint32_t reason = 0, kdone = A.nsteps;
-  for (uint32_t k = 0; k < A.nsteps; ++k) {
-    const uint32_t s = A.step0 + k;
-    const uint32_t par = k & 1u;
-    // inbox of this step -> LDS, sorted
+  for (int32_t k = -1; k < (int32_t)A.nsteps; ++k) {
+    const bool first = k < 0;
+    const uint32_t s = first ? A.step0 : A.step0 + (uint32_t)k;
+    const uint32_t par = (uint32_t)k & 1u;  // 1 for the first pass
+    // inbox of this step -> LDS, sorted (empty on the first pass: zeroed before the launch)
     const uint32_t c_raw = ld_agent(&A.in_n[par * P + p]);
     const uint32_t c = c_raw < A.incap ? c_raw : A.incap;
     if (t == 0 && c_raw > A.incap) raise_err(cnt, &S.err, kErrInbox, s);
@@ -637,39 +735,43 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     while (m2 < c) m2 <<= 1;
     const uint64_t* ibk = A.ik + ((uint64_t)par * P + p) * A.incap;
     const int2* ibv = A.iv + ((uint64_t)par * P + p) * A.incap;
+    const bool last = k + 1 == (int32_t)A.nsteps;
+    // table of the spawns drawn in this pass (step s + 1; step0 on the first pass) -> LDS
+    const uint4* tg = reinterpret_cast<const uint4*>(A.tab_base + A.tab_off[last ? k : k + 1]);
+    const uint32_t tw = reinterpret_cast<const TableHeader*>(tg)->bytes / 16;
+    for (uint32_t i = t; i < tw; i += kPBlock) S.tab[i] = tg[i];
     for (uint32_t i = t; i < m2; i += kPBlock) {
       S.in_k[i] = i < c ? ld_agent(&ibk[i]) : ~0ull;
       S.in_v[i] = i < c ? ld_agent(&ibv[i]) : make_int2(0, 0);
     }
     __syncthreads();
-    if (t == 0) st_agent(&A.in_n[par * P + p], 0u);  // refilled during step k+1 (for step k+2)
-    if (c > 1) bitonic_sort(S.in_k, S.in_v, m2);
-    // The padding records (key ~0, value 0) are merged too: harmless zero terms, and exact even
-    // when ~0 is a real key.
-    const uint32_t cm = c > 0 ? m2 : 0u;
-    // merge; spawn the next step from the outputs
-    const uint64_t np_k = A.seg_n[par * P + p];
-    const uint64_t* pk = A.sk + ((uint64_t)par * P + p) * A.segcap;
-    const int2* pv = A.sv + ((uint64_t)par * P + p) * A.segcap;
+    if (t == 0) st_agent(&A.in_n[par * P + p], 0u);  // refilled during pass k+1 (for k+2)
+    if (c > 1) sort_inbox(S, m2, c, packed);  // the c real records first, then the padding
+    // parents: the canonical slice, or the segment written by the previous pass
+    const uint64_t np_k = first ? ce - cb : A.seg_n[par * P + p];
+    const uint64_t* pk = first ? A.ck + cb : A.sk + ((uint64_t)par * P + p) * A.segcap;
+    const int2* pv = first ? A.cv + cb : A.sv + ((uint64_t)par * P + p) * A.segcap;
     uint64_t* okp = A.sk + ((uint64_t)(par ^ 1u) * P + p) * A.segcap;
     int2* ovp = A.sv + ((uint64_t)(par ^ 1u) * P + p) * A.segcap;
-    const bool last = k + 1 == A.nsteps;
-    const TableView tn = stage_table(S, A.tab_base + A.tab_off[last ? k : k + 1]);
-    Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, s + 1, &S.err,
+    const uint32_t nstep = first ? A.step0 : s + 1;
+    const LTable tn = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab));
+    Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, nstep, &S.err,
              S.st_k[t / kWave], S.st_v[t / kWave], 0u};
-    merge_segment(A, S, pk, pv, np_k, cm, okp, ovp, s, !last, R, tn, s + 1);
+    merge_segment(A, S, pk, pv, np_k, c, okp, ovp, s, !last, R, tn, nstep);
     const uint64_t nout = S.red[0], wsum = S.red[1];
     if (t == 0) {
       A.seg_n[(par ^ 1u) * P + p] = (uint32_t)(nout <= A.segcap ? nout : 0);
-      st_w += wsum;
-      st_k += np_k;
-      st_c += c;
-      st_o += nout;
+      if (!first) {
+        st_w += wsum;
+        st_k += np_k;
+        st_c += c;
+        st_o += nout;
+      }
     }
     ++epoch;
     if (!grid_sync(S, A, epoch, nout, c)) {
       reason = 2;
-      kdone = k;
+      kdone = first ? 0u : (uint32_t)k;
       break;
     }
     // every workgroup reads the same reduced totals and takes the same decision
@@ -681,12 +783,12 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         if (cap_in) raise_err(cnt, &S.err, kErrSpawnCap, s);
       }
       reason = 2;
-      kdone = k;  // refined by the host from err_step
+      kdone = first ? 0u : (uint32_t)k;  // refined by the host from err_step
       break;
     }
-    if (!last && mx > 2 * (tot / P) + A.rebal_min) {
+    if (!first && !last && mx > 2 * (tot / P) + A.rebal_min) {
       reason = 1;
-      kdone = k + 1;
+      kdone = (uint32_t)k + 1;
       break;
     }
   }
@@ -749,27 +851,7 @@ __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ sk,
   }
 }
 
-}  // namespace qmc
-
-using namespace qmc;
-
-extern "C" {
-
-int qmcp_max_segments(int* P) {
-  int dev = 0, ncu = 0, nb = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_persist),
-                                                     kPBlock, 0);
-  if (e != hipSuccess) return (int)e;
-  long long tot = (long long)ncu * (nb > 0 ? nb : 0);
-  if (tot > kMaxSegments) tot = kMaxSegments;
-  *P = (int)tot;
-  return 0;
-}
-
-int qmcp_run(hipStream_t st, const PersistLaunch* L) {
+PersistArgs make_args(const PersistLaunch* L) {
   PersistArgs a;
   a.ck = L->ck;
   a.cv = L->cv;
@@ -791,17 +873,47 @@ int qmcp_run(hipStream_t st, const PersistLaunch* L) {
   a.nsteps = L->nsteps;
   a.seed = L->seed;
   a.kl = KeyLayout{L->kbits, L->kbits >= 64 ? ~0ull : ((1ull << L->kbits) - 1)};
+  a.n_replicas = L->n_replicas;
   a.qshift = L->qshift;
   a.slots = L->slots;
-  a.ctl = L->ctl;
   a.epoch0 = L->epoch0;
   a.cap_store = L->cap_store;
   a.cap_inbox = L->cap_inbox;
   a.rebal_min = L->rebal_min;
   a.done = L->done;
-  hipLaunchKernelGGL(k_persist_prep, dim3(1), dim3(256), 0, st, a.cnt, a.in_n, a.P, a.done);
-  hipLaunchKernelGGL(k_splitters, dim3((a.P + 255) / 256), dim3(256), 0, st, a.ck, a.cnt, a.cur,
-                     a.P, L->split_w);
+  return a;
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" {
+
+int qmcp_max_segments(int* P) {
+  int dev = 0, ncu = 0, nb = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_persist),
+                                                     kPBlock, 0);
+  if (e != hipSuccess) return (int)e;
+  long long tot = (long long)ncu * (nb > 0 ? nb : 0);
+  if (tot > kMaxSegments) tot = kMaxSegments;
+  *P = (int)tot;
+  return 0;
+}
+
+int qmcp_prepare(hipStream_t st, const PersistLaunch* L) {
+  hipLaunchKernelGGL(k_persist_prep, dim3(1), dim3(256), 0, st, (Counters*)L->counters, L->in_n,
+                     L->P, L->done);
+  hipLaunchKernelGGL(k_splitters, dim3((L->P + 255) / 256), dim3(256), 0, st, L->ck,
+                     (const Counters*)L->counters, L->cur, L->P, L->split_w);
+  return (int)hipGetLastError();
+}
+
+int qmcp_launch(hipStream_t st, const PersistLaunch* L) {
+  PersistArgs a = make_args(L);
   void* args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persist), dim3(a.P),
                                             dim3(kPBlock), args, 0, st);

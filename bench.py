@@ -3,16 +3,18 @@
 Workload (default): noisy GHZ preparation on n=20 qubits with non-Markovian dephasing
 0.02 cos(0.5 t) and damping 0.002, dt=0.005, 8 replicas x 1e7 walkers, the whole 3000-step
 trajectory.  A step is one Euler step of the population dynamics for all replicas (per-step
-coefficient table, spawn, child sort, merge with death and annihilation).  Synthetic inputs;
-the initial state is resident on the GPU before timing starts.
+coefficient table, death/cloning, spawn, annihilation by key).  Synthetic inputs; the initial
+state is resident on the GPU before timing starts.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -20,21 +22,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {"fused": "k_persist", "spawn": "k_spawn", "sort": "k_onesweep", "merge": "k_merge"}
+KERNEL_SOURCES = ["paper_2502_18929_amd/csrc/qmc_persist.hip",
+                  "paper_2502_18929_amd/csrc/qmc_kernels.hip",
+                  "paper_2502_18929_amd/csrc/qmc_device.hpp"]
 
 
 def algorithmic_bytes(kind, st0, st1):
-    """Bytes the method must move for one kernel class between two counter snapshots:
-    spawn reads each parent record (16 B) and writes each child record (16 B); merge reads
-    parents and children and writes the annihilated store (16 B each); the child sort moves
-    every child record once in and once out (32 B)."""
+    """Bytes the method must move for one kernel class between two counter snapshots (16 B per
+    record: u64 key, i32 re, i32 im).
+    fused (one launch = whole steps): read each parent, write each surviving key, and each
+      routed record (child or death delta) once written by its sender and once read by its
+      owner: 16 (N_p + N_out + 2 N_c);
+    spawn: read parents, write children; merge: read parents and sorted children, write the new
+    store; sort: every child record in and out once."""
     keys = st1["key_steps"] - st0["key_steps"]
     ch = st1["child_steps"] - st0["child_steps"]
     out = st1["out_steps"] - st0["out_steps"]
+    if kind == "fused":
+        return 16 * (keys + out + 2 * ch)
     if kind == "spawn":
         return 16 * (keys + ch)
     if kind == "merge":
         return 16 * (keys + ch + out)
     return 32 * ch
+
+
+def sources_digest():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kind, workload):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when there is no
+    summary for this kernel and workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kind]}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sources_digest:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != sources_digest():
+        return None
+    return float(b.group(1))
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -67,15 +101,21 @@ def main():
                     help="timed steps (default: the whole trajectory of the workload)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="ghz20_nm", choices=["ghz20_nm", "dd12", "ghz4"])
-    ap.add_argument("--roofline-kernel", default="merge", choices=["spawn", "sort", "merge"])
+    ap.add_argument("--path", default="auto", choices=["auto", "fused", "streamed"])
+    ap.add_argument("--roofline-kernel", default=None, choices=list(KERNEL_NAMES),
+                    help="kernel class timed for the roofline (default: fused, or merge on the "
+                         "streamed path)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB before the timed region (the "
+                         "known-size kernel that calibrates HBM counter runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(replicas and key-space shards would each map to one GPU).", file=sys.stderr)
         sys.exit(2)
+    kind = args.roofline_kernel or ("merge" if args.path == "streamed" else "fused")
 
-    import numpy as np
     import torch
     from paper_2502_18929_amd import binding, workloads as W
 
@@ -86,16 +126,23 @@ def main():
     store_cap, spawn_cap = caps[args.workload]
     torch.cuda.set_device(0)
     g = binding.QMC.from_workload(w, store_capacity=store_cap, spawn_capacity=spawn_cap)
+    g.set_path(args.path)
     init = [g.export(r) for r in range(w.n_replicas)]
 
     # warmup: W steps from the initial state, then restore the initial state (untimed)
     g.run_workload(w, 0, Wm)
     for r in range(w.n_replicas):
         g.import_(r, *init[r], step=0)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib << 18  # float32 elements
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        del a, b
     torch.cuda.synchronize()
 
     st0 = g.counters()
-    g.profile(args.roofline_kernel)
+    g.profile(kind)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.run_workload(w, 0, K)
@@ -109,11 +156,11 @@ def main():
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
     key_steps = st1["key_steps"] - st0["key_steps"]
     value = walker_steps / elapsed
-    abytes = algorithmic_bytes(args.roofline_kernel, st0, st1)
-    achieved = (abytes / prof_n) / (prof_ms / prof_n * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
+    abytes = algorithmic_bytes(kind, st0, st1)
+    per_launch = abytes / prof_n if prof_n else None
+    avg_ms = prof_ms / prof_n if prof_n else None
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
     obs = g.observe(pauli=[(x, z) for _, x, z, _ in w.pauli_obs], psi=w.psi)
-    nd0 = float(w.walker_target)
-    agg_fid = float(obs["fidelity"][:, 0].mean())
     res = {
         "metric": "walker-steps/sec on 1 GPU at n=20; wall time to fixed error bar vs exact",
         "value": value,
@@ -131,17 +178,19 @@ def main():
             "workload": f"{w.name}: n={w.n}, {w.n_replicas} replicas x {w.walker_target:g} "
                         f"walkers, dt={w.dt}, {w.nsteps} steps",
             "n_qubits": w.n, "replicas": w.n_replicas, "walker_target": w.walker_target,
-            "dt": w.dt, "steps_timed": K, "parallelism": "1 GPU, replicas batched in one store",
+            "dt": w.dt, "steps_timed": K, "step_path": args.path,
+            "parallelism": "1 GPU, replicas batched in one store",
         },
         "key_steps_per_s": key_steps / elapsed,
         "roofline": {
-            "bound": "hbm", "kernel": args.roofline_kernel,
+            "bound": "hbm", "kernel": KERNEL_NAMES[kind],
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_ms": prof_ms / prof_n if prof_n else None,
-            "launches": prof_n, "algorithmic_bytes_per_launch": abytes / prof_n if prof_n else None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(kind, w.name),
+            "avg_launch_ms": avg_ms, "launches": prof_n,
+            "algorithmic_bytes_per_launch": per_launch,
         },
-        "final": {"n_occ_total": st1["n_occ"], "fidelity_mean": agg_fid,
+        "final": {"n_occ_total": st1["n_occ"],
+                  "fidelity_mean": float(obs["fidelity"][:, 0].mean()),
                   "trace_mean": float(obs["trace"].mean())},
     }
     if not args.no_cpu:

@@ -22,27 +22,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {"fused": "k_persist", "spawn": "k_spawn", "sort": "k_onesweep", "merge": "k_merge"}
+KERNEL_NAMES = {"fused": "k_persist", "sort": "k_onesweep", "merge": "k_merge"}
+# the dominant kernel of each workload on the automatic path
+DOMINANT = {"ghz20_nm": "fused", "dd12": "merge", "ghz4": "fused"}
 KERNEL_SOURCES = ["paper_2502_18929_amd/csrc/qmc_persist.hip",
                   "paper_2502_18929_amd/csrc/qmc_kernels.hip",
                   "paper_2502_18929_amd/csrc/qmc_device.hpp"]
 
 
-def algorithmic_bytes(kind, st0, st1):
-    """Bytes the method must move for one kernel class between two counter snapshots (16 B per
-    record: u64 key, i32 re, i32 im).
+def algorithmic_bytes(kind, cov):
+    """Bytes the method must move in the steps a kernel class ran (counter sums `cov` of those
+    steps; 16 B per record: u64 key, i32 re, i32 im).
     fused (one launch = whole steps): read each parent, write each surviving key, and each
       routed record (child or death delta) once written by its sender and once read by its
       owner: 16 (N_p + N_out + 2 N_c);
-    spawn: read parents, write children; merge: read parents and sorted children, write the new
-    store; sort: every child record in and out once."""
-    keys = st1["key_steps"] - st0["key_steps"]
-    ch = st1["child_steps"] - st0["child_steps"]
-    out = st1["out_steps"] - st0["out_steps"]
+    merge: read parents and sorted children, write the new store (the children of the next step,
+      which the streamed merge also writes, are not counted); sort: every child record in and
+      out once."""
+    keys, ch, out = cov["key_steps"], cov["child_steps"], cov["out_steps"]
     if kind == "fused":
         return 16 * (keys + out + 2 * ch)
-    if kind == "spawn":
-        return 16 * (keys + ch)
     if kind == "merge":
         return 16 * (keys + ch + out)
     return 32 * ch
@@ -103,8 +102,8 @@ def main():
     ap.add_argument("--workload", default="ghz20_nm", choices=["ghz20_nm", "dd12", "ghz4"])
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "streamed"])
     ap.add_argument("--roofline-kernel", default=None, choices=list(KERNEL_NAMES),
-                    help="kernel class timed for the roofline (default: fused, or merge on the "
-                         "streamed path)")
+                    help="kernel class timed for the roofline (default: the workload's "
+                         "dominant kernel)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB before the timed region (the "
                          "known-size kernel that calibrates HBM counter runs)")
@@ -114,7 +113,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(replicas and key-space shards would each map to one GPU).", file=sys.stderr)
         sys.exit(2)
-    kind = args.roofline_kernel or ("merge" if args.path == "streamed" else "fused")
+    kind = args.roofline_kernel or ("merge" if args.path == "streamed"
+                                    else DOMINANT[args.workload])
 
     import torch
     from paper_2502_18929_amd import binding, workloads as W
@@ -122,7 +122,7 @@ def main():
     w = W.CONFIGS[args.workload]()
     K = w.nsteps if args.steps is None else min(args.steps, w.nsteps)
     Wm = min(args.warmup, w.nsteps)
-    caps = {"ghz20_nm": (1 << 17, 1 << 19), "dd12": (1 << 22, 1 << 19), "ghz4": (256, 4096)}
+    caps = {"ghz20_nm": (1 << 17, 1 << 19), "dd12": (1 << 24, 1 << 21), "ghz4": (256, 4096)}
     store_cap, spawn_cap = caps[args.workload]
     torch.cuda.set_device(0)
     g = binding.QMC.from_workload(w, store_capacity=store_cap, spawn_capacity=spawn_cap)
@@ -149,14 +149,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = g.counters()
-    prof_ms, prof_n = g.profile_read()
+    prof_ms, prof_n, cov = g.profile_read()
     g.profile(None)
 
     elapsed = t1 - t0
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
     key_steps = st1["key_steps"] - st0["key_steps"]
     value = walker_steps / elapsed
-    abytes = algorithmic_bytes(kind, st0, st1)
+    abytes = algorithmic_bytes(kind, cov)
     per_launch = abytes / prof_n if prof_n else None
     avg_ms = prof_ms / prof_n if prof_n else None
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
@@ -186,7 +186,7 @@ def main():
             "bound": "hbm", "kernel": KERNEL_NAMES[kind],
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(kind, w.name),
-            "avg_launch_ms": avg_ms, "launches": prof_n,
+            "avg_launch_ms": avg_ms, "launches": prof_n, "steps_covered": cov["steps"],
             "algorithmic_bytes_per_launch": per_launch,
         },
         "final": {"n_occ_total": st1["n_occ"],

@@ -191,10 +191,14 @@ int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
 /* Live timing of one kernel class with HIP events recorded on the context's stream around
  * every launch of that class in qmc_step: kernel_class 0 = streamed spawn, 1 = streamed child
  * sort (all radix passes), 2 = streamed merge (partition + annihilation + next spawn), 3 = one
- * launch of the fused persistent kernel (a batch of whole steps), -1 = off.  qmc_profile resets the totals;
- * qmc_profile_read returns the summed milliseconds and the number of timed launches. */
+ * launch of the fused persistent kernel (a batch of whole steps), -1 = off.  qmc_profile resets
+ * the totals.  qmc_profile_read returns the summed milliseconds, the number of timed launches
+ * and, in `covered` (may be NULL), the counter sums (walker_steps, key_steps, child_steps,
+ * out_steps, and in `step` the number of steps) of exactly the steps that the timed launches
+ * ran -- for classes 1, 2 and 3; zeros for class 0, which runs for the first step of a batch
+ * only.  The algorithmic bytes of the timed kernels follow from these sums. */
 int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
-int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches);
+int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches, qmc_stats* covered);
 
 /* The quantized coefficient table of one step for this configuration and model, computed on
  * the host only (no device, no context): n_groups groups (group 0 = diagonal, always present)

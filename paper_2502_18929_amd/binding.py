@@ -96,7 +96,7 @@ def lib():
         L.qmc_counters.argtypes = [vp, P(Stats)]
         L.qmc_profile.argtypes = [vp, ctypes.c_int32]
         L.qmc_step_path.argtypes = [vp, ctypes.c_int32]
-        L.qmc_profile_read.argtypes = [vp, P(dbl), P(u64)]
+        L.qmc_profile_read.argtypes = [vp, P(dbl), P(u64), P(Stats)]
         L.qmc_coeff_table.argtypes = [P(Config), P(Model), P(dbl), P(dbl), u32, u32, P(u32),
                                       P(u64), P(u32), P(u32), P(u64), P(ctypes.c_int64)]
         L.qmc_last_error.argtypes = [vp]
@@ -295,9 +295,14 @@ class QMC:
         self._check(lib().qmc_profile(self._ctx, cls))
 
     def profile_read(self):
-        ms, n = ctypes.c_double(), ctypes.c_uint64()
-        self._check(lib().qmc_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        """(milliseconds, launches, covered): the timed launches of the profiled class and the
+        counter sums of the steps they ran (see qmc_profile_read)."""
+        ms, n, st = ctypes.c_double(), ctypes.c_uint64(), Stats()
+        self._check(lib().qmc_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n),
+                                           ctypes.byref(st)))
+        cov = dict(steps=st.step, walker_steps=st.walker_steps, key_steps=st.key_steps,
+                   child_steps=st.child_steps, out_steps=st.out_steps)
+        return ms.value, n.value, cov
 
 def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1):
     """Host-only: the quantized step table the library would use (no device needed)."""

@@ -147,6 +147,8 @@ struct qmc_ctx {
   std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
   double prof_ms = 0.0;
   uint64_t prof_launches = 0;
+  qmc_stats prof_cover{};            // counter deltas of the steps run by the timed class
+  qmc::Counters last_hc{};           // counters at the last device read
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -437,6 +439,7 @@ int read_counters(qmc_ctx* c, qmc::Counters& out) {
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::memcpy(&out, c->pinned_small, sizeof(out));
+  c->last_hc = out;
   return QMC_OK;
 }
 
@@ -554,6 +557,15 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
 
 namespace {
 
+// Adds the running-sum deltas between two counter reads to the timed class's coverage.
+void add_cover(qmc_ctx* c, const qmc::Counters& a, const qmc::Counters& b, uint32_t steps) {
+  c->prof_cover.step += steps;
+  c->prof_cover.walker_steps += b.walker_steps - a.walker_steps;
+  c->prof_cover.key_steps += b.key_steps - a.key_steps;
+  c->prof_cover.child_steps += b.child_steps - a.child_steps;
+  c->prof_cover.out_steps += b.out_steps - a.out_steps;
+}
+
 constexpr uint64_t kFusedKeysPerSegment = 8192;  // automatic mode: larger stores run streamed
 constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a fused overflow
 
@@ -562,6 +574,7 @@ constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a 
 // reason (0 end, 1 rebalance, 2 error), hc = the counters; the store and c->step reflect kd.
 int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& reason,
               qmc::Counters& hc) {
+  const qmc::Counters before = c->last_hc;
   uint32_t* pin_done = reinterpret_cast<uint32_t*>(c->pinned_small + 1024);
   PersistLaunch pl;
   pl.ck = c->sk(0);
@@ -635,6 +648,7 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
   }
   c->step = pl.step0 + kd;
   c->n_occ = hc.n_store[c->cur];
+  if (prof) add_cover(c, before, hc, kd);
   return QMC_OK;
 }
 
@@ -644,6 +658,7 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
 int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& offs, uint32_t nst,
                  uint32_t& kd, qmc::Counters& hc) {
   qmc::Counters* dcnt = c->counters();
+  const qmc::Counters before = c->last_hc;
   const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits);
   const uint32_t step0 = c->step, cur0 = c->cur;
   uint64_t* bk[2] = {c->sk(0), c->alt_k()};
@@ -720,6 +735,7 @@ int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& o
   c->cur = cur;
   c->step = step0 + kd;
   c->n_occ = hc.n_store[cur];
+  if (c->prof_class == 1 || c->prof_class == 2) add_cover(c, before, hc, kd);
   return QMC_OK;
 }
 
@@ -1051,13 +1067,15 @@ int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
   c->prof_class = kernel_class;
   c->prof_ms = 0.0;
   c->prof_launches = 0;
+  c->prof_cover = qmc_stats{};
   return QMC_OK;
 }
 
-int qmc_profile_read(qmc_ctx* c, double* ms, uint64_t* launches) {
+int qmc_profile_read(qmc_ctx* c, double* ms, uint64_t* launches, qmc_stats* covered) {
   if (!c) return QMC_ERR_ARG;
   if (ms) *ms = c->prof_ms;
   if (launches) *launches = c->prof_launches;
+  if (covered) *covered = c->prof_cover;
   return QMC_OK;
 }
 

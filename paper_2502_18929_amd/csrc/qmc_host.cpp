@@ -607,7 +607,7 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
   c->epoch += (uint64_t)nst + 1;  // barriers of this launch: batch start + one per step
   pl.cap_store = c->L.cap_store;
   pl.cap_inbox = c->L.cap_child;
-  pl.rebal_min = 1024;
+  pl.rebal_min = 64;
   pl.done = c->at<uint32_t>(c->L.done);
   const bool prof = c->prof_class == 3;
   if (prof) {

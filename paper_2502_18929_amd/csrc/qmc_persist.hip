@@ -24,7 +24,7 @@ namespace qmc {
 constexpr int kPBlock = 512;               // threads per workgroup
 constexpr int kPWaves = kPBlock / kWave;   // 8
 constexpr int kPTile = 1024;               // parents per tile (staged in LDS)
-constexpr int kRing = 128;                 // per-wave queue of active new parents
+constexpr int kActCap = 2 * kPBlock;       // block list of active new parents
 constexpr int kStage = 256;                // per-wave staging of routed records
 
 struct PersistArgs {
@@ -58,7 +58,7 @@ struct PersistArgs {
   uint64_t* slots;        // [P][4] per workgroup: epoch, keys out, inbox records, error bits
   uint64_t cap_store;     // total occupied keys allowed
   uint64_t cap_inbox;     // total inbox records allowed per step
-  uint32_t rebal_min;     // imbalance slack before a rebalancing stop
+  uint32_t rebal_min;     // stop to rebalance when the largest range exceeds 1.25 x mean + this
   uint64_t epoch0;        // first barrier epoch of this launch (epochs only grow)
   uint32_t* done;         // [0] steps completed, [1] stop reason (0 end, 1 rebalance, 2 error)
 };
@@ -70,10 +70,10 @@ struct Shared {
   uint64_t pa_k[kPTile];
   int2 pa_v[kPTile];
   uint32_t scan[kPBlock];
-  uint64_t ring_k[kPWaves][kRing];
-  int2 ring_v[kPWaves][kRing];
-  uint2 ring_w[kPWaves][kRing];
-  int64_t ring_s[kPWaves][kRing];
+  uint64_t act_k[kActCap];   // active new parents: key, value, comb words (w0, w1), shift
+  int2 act_v[kActCap];
+  uint2 act_w[kActCap];
+  int64_t act_s[kActCap];
   uint64_t st_k[kPWaves][kStage];
   int2 st_v[kPWaves][kStage];
   uint64_t red[kPWaves];
@@ -233,95 +233,124 @@ __device__ __forceinline__ bool inbox_less(uint64_t ka, int2 va, uint64_t kb, in
   return !pa && pb;
 }
 
-// Compare-exchange of a bitonic network on the element held by this thread (index i) and its
-// partner (index i ^ stride, holding pk/pv): the lower index of an ascending pair keeps the
-// smaller record.  Equal records stay where they are.
-__device__ __forceinline__ void bitonic_keep(uint32_t i, uint32_t size, uint32_t stride,
-                                             uint64_t& k, int2& v, uint64_t pk, int2 pv) {
-  const bool asc = (i & size) == 0, lower = (i & stride) == 0;
-  const bool take = (asc == lower) ? inbox_less(pk, pv, k, v) : inbox_less(k, v, pk, pv);
-  if (take) {
-    k = pk;
-    v = pv;
+// Bitonic sort of 64 words held one per lane, ascending along the lanes (descending if `desc`,
+// as the first levels of a longer bitonic network need for odd chunks).
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t k, bool desc) {
+  const uint32_t lane = __lane_id();
+  for (uint32_t size = 2; size <= (uint32_t)kWave; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t pk = __shfl_xor(k, (int)stride);
+      const bool asc = size == (uint32_t)kWave ? !desc : (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      if ((asc == lower) ? (pk < k) : (pk > k)) k = pk;
+    }
   }
+  return k;
 }
 
-// Sorts the m (a power of two) records of the inbox in LDS (c real ones, then padding).  Up to
-// one record per thread the network runs in registers: partners within a wave are exchanged by
-// lane shuffles, only the strides of 64 and more go through LDS.  When the composite keys leave
-// 12 bits free, the network sorts one 64-bit word per record, (key << 12) | index, with ~0 for
-// the padding, and the values follow by index.  Larger inboxes take the LDS network.
+// Sorts the c real records of the inbox in LDS (then m - c padding records, m a power of two).
+// When the composite keys leave 12 bits free, the sort runs on one 64-bit word per record,
+// (key << 12) | index, and the values follow by index at the end:
+//  - up to 1024 records: every wave sorts 64-word chunks in registers (lane shuffles); the final
+//    position of a word is the number of smaller words over all chunks (words are distinct),
+//    found by binary search in each sorted chunk;
+//  - up to 4096 records: a bitonic network on the words in place, whose strides below 64 run in
+//    registers per 64-word chunk and only the larger strides go through LDS.
+// Wider keys take a bitonic network on the records in LDS.
 __device__ __forceinline__ void sort_inbox(Shared& S, uint32_t m, uint32_t c, bool packed) {
-  const uint32_t t = threadIdx.x;
-  if (packed && m <= (uint32_t)kPBlock) {
-    // Each wave sorts its 64 words in registers (lane shuffles only); the final position of a
-    // word is the number of smaller words over all sorted chunks (distinct words: the index
-    // makes them unique), found by binary search in each chunk.
-    const uint32_t lane = __lane_id(), nch = (c + kWave - 1) / kWave;
-    uint64_t k = ~0ull;
-    if (t / kWave < nch) {
-      k = t < c ? (S.in_k[t] << 12) | t : ~0ull;
-      for (uint32_t size = 2; size <= (uint32_t)kWave; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-          const uint64_t pk = __shfl_xor(k, (int)stride);
-          const bool asc = (lane & size) == 0, lower = (lane & stride) == 0;
-          if ((asc == lower) ? (pk < k) : (pk > k)) k = pk;
+  const uint32_t t = threadIdx.x, wave = t / kWave, lane = __lane_id();
+  if (packed && c <= 2u * kPBlock) {
+    const uint32_t nch = (c + kWave - 1) / kWave;  // <= 16 chunks of 64 words in S.pa_k
+    for (uint32_t ch = wave; ch < nch; ch += kPWaves) {
+      const uint32_t i = ch * kWave + lane;
+      const uint64_t k = i < c ? (S.in_k[i] << 12) | i : ~0ull;
+      S.pa_k[i] = wave_sort64(k, false);
+    }
+    __syncthreads();
+    uint64_t wd[2];
+    uint32_t rank[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t i = t + h * kPBlock;
+      wd[h] = i < nch * kWave ? S.pa_k[i] : ~0ull;
+      rank[h] = 0;
+      if (wd[h] != ~0ull) {
+        for (uint32_t ch = 0; ch < nch; ++ch) {
+          const uint64_t* a = S.pa_k + ch * kWave;
+          uint32_t pos = 0;
+#pragma unroll
+          for (uint32_t st = kWave / 2; st > 0; st >>= 1)
+            if (a[pos + st - 1] < wd[h]) pos += st;
+          if (a[pos] < wd[h]) ++pos;  // the search leaves pos <= 63; this counts the last word
+          rank[h] += pos;
         }
       }
-      S.pa_k[t] = k;
     }
-    __syncthreads();
-    uint32_t rank = 0;
-    if (t < nch * kWave && k != ~0ull) {
-      for (uint32_t w = 0; w < nch; ++w) {
-        const uint64_t* ch = S.pa_k + w * kWave;
-        uint32_t pos = 0;
+    int2 v[2];
 #pragma unroll
-        for (uint32_t st = kWave / 2; st > 0; st >>= 1)
-          if (ch[pos + st - 1] < k) pos += st;
-        if (ch[pos] < k) ++pos;  // the search leaves pos <= 63; this counts the last word
-        rank += pos;
-      }
-    }
-    int2 v = make_int2(0, 0);
-    const bool real = t < nch * kWave && k != ~0ull;
-    if (real) v = S.in_v[k & 0xFFFu];
+    for (int h = 0; h < 2; ++h)
+      v[h] = wd[h] != ~0ull ? S.in_v[wd[h] & 0xFFFu] : make_int2(0, 0);
     __syncthreads();
-    if (real) {
-      S.in_k[rank] = k >> 12;
-      S.in_v[rank] = v;
-    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (wd[h] != ~0ull) {
+        S.in_k[rank[h]] = wd[h] >> 12;
+        S.in_v[rank[h]] = v[h];
+      }
     __syncthreads();
     return;
   }
-  if (m <= (uint32_t)kPBlock) {
-    uint64_t k = t < m ? S.in_k[t] : 0;
-    int2 v = t < m ? S.in_v[t] : make_int2(0, 0);
-    for (uint32_t size = 2; size <= m; size <<= 1) {
-      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-        uint64_t pk;
-        int2 pv;
-        if (stride >= (uint32_t)kWave) {
-          __syncthreads();
-          if (t < m) {
-            S.in_k[t] = k;
-            S.in_v[t] = v;
-          }
-          __syncthreads();
-          pk = S.in_k[(t ^ stride) & (m - 1)];
-          pv = S.in_v[(t ^ stride) & (m - 1)];
-        } else {
-          pk = __shfl_xor(k, (int)stride);
-          pv.x = __shfl_xor(v.x, (int)stride);
-          pv.y = __shfl_xor(v.y, (int)stride);
-        }
-        if (t < m) bitonic_keep(t, size, stride, k, v, pk, pv);
-      }
+  if (packed) {
+    // m in (1024, 4096]: words in place in S.in_k
+    for (uint32_t i = t; i < m; i += kPBlock) S.in_k[i] = i < c ? (S.in_k[i] << 12) | i : ~0ull;
+    __syncthreads();
+    const uint32_t nch = m / kWave;
+    for (uint32_t ch = wave; ch < nch; ch += kPWaves) {
+      const uint32_t i = ch * kWave + lane;
+      S.in_k[i] = wave_sort64(S.in_k[i], (ch & 1u) != 0);
     }
     __syncthreads();
-    if (t < m) {
-      S.in_k[t] = k;
-      S.in_v[t] = v;
+    for (uint32_t size = 2 * kWave; size <= m; size <<= 1) {
+      for (uint32_t stride = size >> 1; stride >= (uint32_t)kWave; stride >>= 1) {
+        for (uint32_t x = t; x < (m >> 1); x += kPBlock) {
+          const uint32_t lo = 2 * x - (x & (stride - 1));
+          const uint32_t hi = lo + stride;
+          const uint64_t a = S.in_k[lo], b = S.in_k[hi];
+          if ((a > b) == ((lo & size) == 0)) {
+            S.in_k[lo] = b;
+            S.in_k[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+      for (uint32_t ch = wave; ch < nch; ch += kPWaves) {
+        const uint32_t i = ch * kWave + lane;
+        uint64_t k = S.in_k[i];
+        for (uint32_t stride = kWave / 2; stride > 0; stride >>= 1) {
+          const uint64_t pk = __shfl_xor(k, (int)stride);
+          const bool asc = (i & size) == 0, lower = (lane & stride) == 0;
+          if ((asc == lower) ? (pk < k) : (pk > k)) k = pk;
+        }
+        S.in_k[i] = k;
+      }
+      __syncthreads();
+    }
+    uint64_t wd[kInboxMax / kPBlock];
+    int2 v[kInboxMax / kPBlock];
+#pragma unroll
+    for (int h = 0; h < kInboxMax / kPBlock; ++h) {
+      const uint32_t i = t + h * kPBlock;
+      wd[h] = i < c ? S.in_k[i] : ~0ull;
+      v[h] = i < c ? S.in_v[wd[h] & 0xFFFu] : make_int2(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < kInboxMax / kPBlock; ++h) {
+      const uint32_t i = t + h * kPBlock;
+      if (i < c) {
+        S.in_k[i] = wd[h] >> 12;
+        S.in_v[i] = v[h];
+      }
     }
     __syncthreads();
     return;
@@ -451,16 +480,15 @@ struct Router {
   }
 };
 
-// Death delta and children of up to 64 queued active parents of one wave (dense: every lane
-// holds one parent).
+// Death delta and children of the n <= 64 active parents at list offset b (one per lane).
 __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, Router& R,
-                                               const LTable& tn, uint32_t wave, uint32_t n) {
+                                               const LTable& tn, uint32_t b, uint32_t n) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < n;
-  const uint64_t ck = valid ? S.ring_k[wave][lane] : 0;
-  const int2 v = valid ? S.ring_v[wave][lane] : make_int2(0, 0);
-  const uint2 w = valid ? S.ring_w[wave][lane] : make_uint2(0, 0);
-  const int64_t qs = valid ? S.ring_s[wave][lane] : 0;
+  const uint64_t ck = valid ? S.act_k[b + lane] : 0;
+  const int2 v = valid ? S.act_v[b + lane] : make_int2(0, 0);
+  const uint2 w = valid ? S.act_w[b + lane] : make_uint2(0, 0);
+  const int64_t qs = valid ? S.act_s[b + lane] : 0;
   const uint64_t key = A.kl.key(ck);
   const uint64_t sab = uabs64(v.x) + uabs64(v.y);
   // Death/cloning delta from the diagonal group (applied to N(t) in the next merge).
@@ -504,17 +532,20 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
 }
 
 // Draw Philox for new parents [o0, o1) of segment buffer (seg_k, seg_v) at step `step` and
-// route their death deltas and children.  Uniform loop; active parents are compacted per wave.
+// route their death deltas and children.  The parents that can produce a nonzero amount are
+// compacted over the whole workgroup into a list, which is processed in full 64-parent batches
+// spread over the waves (a batch costs the same whatever its lane count), so a busy key range
+// needs few batches and they run on different SIMDs.  Block-uniform control flow.
 __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router& R,
                                         const LTable& tn, const uint64_t* seg_k,
                                         const int2* seg_v, uint64_t o0, uint64_t o1,
                                         uint32_t step) {
-  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
+  const uint32_t t = threadIdx.x, wave = t / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
   const uint64_t q_diag = tn.h->q_diag, q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
-  uint32_t fill = 0;  // wave-uniform
-  for (uint64_t wb = o0 + (uint64_t)wave * kWave; wb < o1; wb += kPBlock) {
-    const uint64_t i = wb + lane;
+  uint32_t nl = 0;  // entries in the list (block-uniform)
+  for (uint64_t base = o0; base < o1; base += kPBlock) {
+    const uint64_t i = base + t;
     const bool valid = i < o1;
     uint64_t ck = 0;
     int2 v = make_int2(0, 0);
@@ -530,44 +561,57 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
       const uint64_t sab = uabs64(v.x) + uabs64(v.y);
       act = !comb_all_zero(sab, q_diag + uabs64(qs), w[1]) || !comb_all_zero(sab, q_off, w[0]);
     }
+    // workgroup-wide compaction of the active parents, in index order
     const uint64_t m = __ballot(act);
-    if (m) {
-      if (act) {
-        const uint32_t pos = fill + mbcnt64(m);
-        S.ring_k[wave][pos] = ck;
-        S.ring_v[wave][pos] = v;
-        S.ring_w[wave][pos] = make_uint2(w[0], w[1]);
-        S.ring_s[wave][pos] = qs;
+    if (lane == 0) S.scan[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (uint32_t x = 0; x < (uint32_t)kPWaves; ++x) {
+      const uint32_t cnt = S.scan[x];
+      off += x < wave ? cnt : 0u;
+      tot += cnt;
+    }
+    if (act) {
+      const uint32_t at = nl + off + mbcnt64(m);
+      S.act_k[at] = ck;
+      S.act_v[at] = v;
+      S.act_w[at] = make_uint2(w[0], w[1]);
+      S.act_s[at] = qs;
+    }
+    nl += tot;
+    __syncthreads();
+    const bool end = base + kPBlock >= o1;
+    if (end || nl >= (uint32_t)kPBlock) {
+      // full batches now (all of them at the end), the rest moves to the front of the list
+      const uint32_t nb = end ? (nl + kWave - 1) / kWave : nl / kWave;
+      for (uint32_t b = wave; b < nb; b += kPWaves) {
+        const uint32_t b0 = b * kWave;
+        process_active(A, S, R, tn, b0, nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave);
       }
-      fill += (uint32_t)__popcll(m);
-      wave_lds_fence();
-      if (fill >= kWave) {
-        process_active(A, S, R, tn, wave, kWave);
-        // move the overflow (fill - 64 < 64 entries) to the front of the queue
-        const uint32_t rest = fill - kWave;
-        uint64_t rk = 0;
-        int2 rv = make_int2(0, 0);
-        uint2 rw = make_uint2(0, 0);
-        int64_t rs = 0;
-        if (lane < rest) {
-          rk = S.ring_k[wave][kWave + lane];
-          rv = S.ring_v[wave][kWave + lane];
-          rw = S.ring_w[wave][kWave + lane];
-          rs = S.ring_s[wave][kWave + lane];
-        }
-        wave_lds_fence();
-        if (lane < rest) {
-          S.ring_k[wave][lane] = rk;
-          S.ring_v[wave][lane] = rv;
-          S.ring_w[wave][lane] = rw;
-          S.ring_s[wave][lane] = rs;
-        }
-        wave_lds_fence();
-        fill = rest;
+      const uint32_t done = nb * kWave < nl ? nb * kWave : nl;
+      const uint32_t rest = nl - done;
+      __syncthreads();
+      uint64_t rk = 0;
+      int2 rv = make_int2(0, 0);
+      uint2 rw = make_uint2(0, 0);
+      int64_t rs = 0;
+      if (t < rest) {
+        rk = S.act_k[done + t];
+        rv = S.act_v[done + t];
+        rw = S.act_w[done + t];
+        rs = S.act_s[done + t];
       }
+      __syncthreads();
+      if (t < rest) {
+        S.act_k[t] = rk;
+        S.act_v[t] = rv;
+        S.act_w[t] = rw;
+        S.act_s[t] = rs;
+      }
+      nl = rest;
+      __syncthreads();
     }
   }
-  if (fill) process_active(A, S, R, tn, wave, fill);
   R.flush();
 }
 
@@ -786,7 +830,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       kdone = first ? 0u : (uint32_t)k;  // refined by the host from err_step
       break;
     }
-    if (!first && !last && mx > 2 * (tot / P) + A.rebal_min) {
+    if (!first && !last && mx > tot / P + tot / (4 * P) + A.rebal_min) {
       reason = 1;
       kdone = (uint32_t)k + 1;
       break;

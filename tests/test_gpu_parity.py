@@ -321,6 +321,33 @@ def _dense_spawner(n=8, R=4, seed=21):
     return n, R, h, lops, keys, re, im, s, gam
 
 
+@pytest.mark.parametrize("n_h", [6, 16])
+def test_fused_large_inboxes(B, orc, n_h):
+    """Every key of an n=7 register occupied (16384 keys) under a model of ~2*n_h column groups:
+    each key range of the fused kernel receives about a thousand (n_h=6) to a few thousand
+    (n_h=16) records per step, so the inbox sorts beyond 512 and 1024 records run."""
+    rng = np.random.default_rng(40 + n_h)
+    n, R = 7, 1
+    h, lops = W.random_model(n, rng, n_h=n_h, n_l=2)
+    keys = np.arange(1 << (2 * n), dtype=np.uint64)
+    re = rng.integers(-3000, 3000, size=len(keys)).astype(np.int32)
+    im = rng.integers(-3000, 3000, size=len(keys)).astype(np.int32)
+    re[(re == 0) & (im == 0)] = 1
+    s = rng.normal(size=(3, len(h))) * 0.5
+    gam = np.abs(rng.normal(size=(3, len(lops)))) * 0.5
+    _say(f"fused large inboxes: n_h={n_h}, {len(keys)} keys")
+    g = B.QMC(n, R, 11, 0.01, h, lops, keys, re, im, store_capacity=1 << 15,
+              spawn_capacity=1 << 22)
+    g.set_path("fused")
+    o = orc.Oracle(n, R, 11, 0.01, h, lops, keys, re, im)
+    for k in range(3):
+        g.step(s[k:k + 1], gam[k:k + 1])
+        o.step(s[k:k + 1], gam[k:k + 1])
+        _assert_same(g, o, R, f"n_h={n_h} step {k}")
+    c = g.counters()
+    _say(f"  routed records per key range per step: {c['child_steps'] / 3 / 256:.0f}")
+
+
 def test_auto_path_falls_back_to_streamed(B, orc):
     n, R, h, lops, keys, re, im, s, gam = _dense_spawner()
     _say(f"dense spawner: {len(keys)} keys x {R} replicas, automatic path")

@@ -65,11 +65,11 @@ def lib():
         L.orc_n_terms.restype = u32
         L.orc_get_terms.argtypes = [ctypes.c_void_p, P(u64), P(u64), P(dbl), P(dbl), P(u32),
                                     P(u32)]
-        L.orc_table.argtypes = [ctypes.c_void_p, P(dbl), P(dbl), u32, u32, P(u32), P(u64),
+        L.orc_table.argtypes = [ctypes.c_void_p, P(dbl), P(dbl), dbl, u32, u32, P(u32), P(u64),
                                 P(u32), P(u32), P(u64), P(i64)]
         L.orc_column_fp.argtypes = [ctypes.c_void_p, P(dbl), P(dbl), u64, u32, P(u32), P(u64),
                                     P(dbl)]
-        L.orc_column_q.argtypes = [ctypes.c_void_p, P(dbl), P(dbl), u64, u32, P(u32), P(u64),
+        L.orc_column_q.argtypes = [ctypes.c_void_p, P(dbl), P(dbl), dbl, u64, u32, P(u32), P(u64),
                                    P(i64)]
         L.orc_step.argtypes = [ctypes.c_void_p, u32, P(dbl), P(dbl)]
         L.orc_step_threads.argtypes = [ctypes.c_void_p, u32, P(dbl), P(dbl), ctypes.c_int,
@@ -84,6 +84,11 @@ def lib():
         L.orc_size.restype = u64
         L.orc_export.argtypes = [ctypes.c_void_p, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.orc_import.argtypes = [ctypes.c_void_p, u32, P(u64), P(i32), P(i32), u64, u32]
+        L.orc_set_integrator.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_prev.argtypes = [ctypes.c_void_p, u32, P(u64), P(i32), P(i32), u64, P(dbl),
+                                   P(dbl)]
+        L.orc_export_prev.argtypes = [ctypes.c_void_p, u32, P(u64), P(i32), P(i32), u64,
+                                      P(u64)]
         L.orc_observe.argtypes = [ctypes.c_void_p, u32, u32, P(u64), P(u64), u32, P(u64),
                                   P(u64), P(u64), P(i64), P(i64), P(i64), P(u64)]
         _lib = L
@@ -128,8 +133,9 @@ def _check(rc, what):
 class Oracle:
     """One oracle context: n qubits, R replicas, the model, and the initial records."""
 
-    def __init__(self, n, n_replicas, seed, dt, h, lops, keys, re, im):
-        """h: list of (x, z, coeff); lops: list of lists of (x, z, coeff) (one list per L_k)."""
+    def __init__(self, n, n_replicas, seed, dt, h, lops, keys, re, im, integrator="euler"):
+        """h: list of (x, z, coeff); lops: list of lists of (x, z, coeff) (one list per L_k);
+        integrator: "euler" or "ab2" (End Matter on simulation methodology)."""
         self.n, self.R, self.n_h, self.n_l = int(n), int(n_replicas), len(h), len(lops)
         hm = _monos(h)
         flat = [m for op in lops for m in op]
@@ -145,6 +151,8 @@ class Oracle:
                                 _p(off, ctypes.c_uint32), lm, _p(keys, ctypes.c_uint64),
                                 _p(re, ctypes.c_int32), _p(im, ctypes.c_int32), len(keys),
                                 ctypes.byref(self._ctx)), "create")
+        if integrator != "euler":
+            _check(lib().orc_set_integrator(self._ctx, {"ab2": 1}[integrator]), "integrator")
 
     def close(self):
         if self._ctx:
@@ -173,14 +181,14 @@ class Oracle:
         g = np.ascontiguousarray(gamma if self.n_l else np.zeros(1), dtype=np.float64)
         return s, g
 
-    def table(self, s, gamma):
+    def table(self, s, gamma, scale=1.0):
         s, g = self._w(s, gamma)
         cap_t = lib().orc_n_terms(self._ctx) + 1
         ng = ctypes.c_uint32(); nt = ctypes.c_uint32()
         gx = np.zeros(cap_t + 1, np.uint64); gs = np.zeros(cap_t + 2, np.uint32)
         tz = np.zeros(cap_t, np.uint64); tq = np.zeros((cap_t, 2), np.int64)
         _check(lib().orc_table(self._ctx, _p(s, ctypes.c_double), _p(g, ctypes.c_double),
-                               cap_t + 1, cap_t, ctypes.byref(ng), _p(gx, ctypes.c_uint64),
+                               float(scale), cap_t + 1, cap_t, ctypes.byref(ng), _p(gx, ctypes.c_uint64),
                                _p(gs, ctypes.c_uint32), ctypes.byref(nt),
                                _p(tz, ctypes.c_uint64), _p(tq, ctypes.c_int64)), "table")
         G, T = ng.value, nt.value
@@ -197,12 +205,12 @@ class Oracle:
         m = n.value
         return tk[:m].copy(), v[:m, 0] + 1j * v[:m, 1]
 
-    def column_q(self, s, gamma, key):
+    def column_q(self, s, gamma, key, scale=1.0):
         s, g = self._w(s, gamma)
         cap = lib().orc_n_terms(self._ctx) + 1
         n = ctypes.c_uint32(); tk = np.zeros(cap, np.uint64); v = np.zeros((cap, 2), np.int64)
         _check(lib().orc_column_q(self._ctx, _p(s, ctypes.c_double), _p(g, ctypes.c_double),
-                                  int(key), cap, ctypes.byref(n), _p(tk, ctypes.c_uint64),
+                                  float(scale), int(key), cap, ctypes.byref(n), _p(tk, ctypes.c_uint64),
                                   _p(v, ctypes.c_int64)), "column_q")
         m = n.value
         return tk[:m].copy(), v[:m].copy()
@@ -265,6 +273,28 @@ class Oracle:
         _check(lib().orc_import(self._ctx, int(replica), _p(keys, ctypes.c_uint64),
                                 _p(re, ctypes.c_int32), _p(im, ctypes.c_int32), len(keys),
                                 int(step)), "import")
+
+    def set_prev(self, replica, keys, re, im, s_prev, gamma_prev):
+        """AB2: N(s-1) of one replica and the weights of step s-1."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        re = np.ascontiguousarray(re, dtype=np.int32)
+        im = np.ascontiguousarray(im, dtype=np.int32)
+        s, g = self._w(s_prev, gamma_prev)
+        _check(lib().orc_set_prev(self._ctx, int(replica), _p(keys, ctypes.c_uint64),
+                                  _p(re, ctypes.c_int32), _p(im, ctypes.c_int32), len(keys),
+                                  _p(s, ctypes.c_double), _p(g, ctypes.c_double)), "set_prev")
+
+    def export_prev(self, replica):
+        """AB2: N(s-1) of one replica."""
+        n = ctypes.c_uint64()
+        lib().orc_export_prev(self._ctx, int(replica), None, None, None, 0, ctypes.byref(n))
+        m = n.value
+        k = np.zeros(max(m, 1), np.uint64); a = np.zeros(max(m, 1), np.int32)
+        b = np.zeros(max(m, 1), np.int32)
+        _check(lib().orc_export_prev(self._ctx, int(replica), _p(k, ctypes.c_uint64),
+                                     _p(a, ctypes.c_int32), _p(b, ctypes.c_int32), m,
+                                     ctypes.byref(n)), "export_prev")
+        return k[:m].copy(), a[:m].copy(), b[:m].copy()
 
     def observe(self, replica, pauli=(), lookup=()):
         px = np.ascontiguousarray([p[0] for p in pauli] or [0], dtype=np.uint64)

@@ -109,6 +109,12 @@ struct orc_ctx {
   uint64_t child_steps;  /* sum over steps and replicas of emitted child records */
   uint64_t max_children; /* largest number of child records of one step (all replicas) */
   uint64_t* nchild;      /* [R] child records of the last step, per replica */
+  /* AB2 (End Matter on simulation methodology): N(s-1) per replica and the weights of step
+   * s-1, both needed by the second term of the two-step formula. */
+  int ab2;
+  store_t* prev;         /* [R] */
+  double* w_prev;        /* [n_h + n_l] */
+  int have_prev;         /* N(s-1) and w_prev are valid (false at step 0: Euler first step) */
 };
 
 /* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
@@ -201,7 +207,9 @@ int orc_create(uint32_t n_qubits, uint32_t n_replicas, uint64_t seed, double dt,
   c->st = (store_t*)calloc(n_replicas, sizeof(store_t));
   c->shift = (double*)calloc(n_replicas, sizeof(double));
   c->nchild = (uint64_t*)calloc(n_replicas, sizeof(uint64_t));
-  if (!c->st || !c->shift || !c->nchild) {
+  c->prev = (store_t*)calloc(n_replicas, sizeof(store_t));
+  c->w_prev = (double*)calloc((size_t)n_h + n_l + 1, sizeof(double));
+  if (!c->st || !c->shift || !c->nchild || !c->prev || !c->w_prev) {
     orc_destroy(c);
     return ORC_ERR_NOMEM;
   }
@@ -229,7 +237,11 @@ void orc_destroy(orc_ctx* c) {
   if (!c) return;
   if (c->st)
     for (uint32_t r = 0; r < c->R; ++r) store_free(&c->st[r]);
+  if (c->prev)
+    for (uint32_t r = 0; r < c->R; ++r) store_free(&c->prev[r]);
   free(c->st);
+  free(c->prev);
+  free(c->w_prev);
   free(c->shift);
   free(c->nchild);
   free(c->terms);
@@ -282,16 +294,18 @@ static void table_free(table_t* T) {
   memset(T, 0, sizeof(*T));
 }
 
-/* Q32 value of dt * w * kappa0 for one component: the product w * kappa0 first, then dt, then
- * an exact scaling by 2^32 and round-half-even to an integer. */
-static int q32(double dt, double w, double k, int64_t* out) {
-  double v = ldexp(dt * (w * k), 32);
+/* Q32 value of scale * dt * w * kappa0 for one component: the product w * kappa0 first, then dt,
+ * then the integrator's factor (1 for Euler; 3/2 and -1/2 for the two AB2 terms), then an exact
+ * scaling by 2^32 and round-half-even to an integer. */
+static int q32(double dt, double w, double k, double scale, int64_t* out) {
+  double v = ldexp(scale * (dt * (w * k)), 32);
   if (!isfinite(v) || fabs(v) >= 4611686018427387904.0 /* 2^62 */) return ORC_ERR_DT;
   *out = (int64_t)llrint(v);
   return ORC_OK;
 }
 
-static int build_table(const orc_ctx* c, const double* s, const double* gamma, table_t* T) {
+static int build_table(const orc_ctx* c, const double* s, const double* gamma, double scale,
+                       table_t* T) {
   memset(T, 0, sizeof(*T));
   qterm_t* q = (qterm_t*)malloc((c->n_terms ? c->n_terms : 1) * sizeof(qterm_t));
   if (!q) return ORC_ERR_NOMEM;
@@ -304,7 +318,7 @@ static int build_table(const orc_ctx* c, const double* s, const double* gamma, t
     }
     q[i].xmask = tm->xmask;
     q[i].zmask = tm->zmask;
-    if (q32(c->dt, w, tm->kre, &q[i].qre) || q32(c->dt, w, tm->kim, &q[i].qim)) {
+    if (q32(c->dt, w, tm->kre, scale, &q[i].qre) || q32(c->dt, w, tm->kim, scale, &q[i].qim)) {
       free(q);
       return ORC_ERR_DT;
     }
@@ -359,11 +373,11 @@ static int build_table(const orc_ctx* c, const double* s, const double* gamma, t
   return ORC_OK;
 }
 
-int orc_table(const orc_ctx* c, const double* s, const double* gamma,
+int orc_table(const orc_ctx* c, const double* s, const double* gamma, double scale,
               uint32_t cap_groups, uint32_t cap_terms, uint32_t* n_groups, uint64_t* gxmask,
               uint32_t* gstart, uint32_t* n_terms, uint64_t* tzmask, int64_t* tq) {
   table_t T;
-  int rc = build_table(c, s, gamma, &T);
+  int rc = build_table(c, s, gamma, scale, &T);
   if (rc) return rc;
   *n_groups = T.n_groups;
   *n_terms = T.n_terms;
@@ -442,10 +456,10 @@ int orc_column_fp(const orc_ctx* c, const double* s, const double* gamma, uint64
   return m > cap ? ORC_ERR_ARG : ORC_OK;
 }
 
-int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
-                 uint32_t cap, uint32_t* n, uint64_t* tkey, int64_t* val) {
+int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, double scale,
+                 uint64_t key, uint32_t cap, uint32_t* n, uint64_t* tkey, int64_t* val) {
   table_t T;
-  int rc = build_table(c, s, gamma, &T);
+  int rc = build_table(c, s, gamma, scale, &T);
   if (rc) return rc;
   uint32_t m = 0;
   for (uint32_t g = 0; g < T.n_groups; ++g) {
@@ -465,7 +479,7 @@ int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, uint64_
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* One Euler step of the spawn / death / annihilation dynamics for one replica.                */
+/* One step of the spawn / death / annihilation dynamics for one replica: Euler, or AB2.       */
 /* ------------------------------------------------------------------------------------------ */
 typedef struct {
   uint64_t key;
@@ -477,41 +491,45 @@ static int cmp_rec(const void* a, const void* b) {
   return x < y ? -1 : (x > y ? 1 : 0);
 }
 
-static int step_replica(const orc_ctx* c, uint32_t r, const table_t* T, int64_t qs_re,
-                        store_t* out, uint64_t* nchild) {
-  const store_t* in = &c->st[r];
+/* The records one population vector `in` contributes through one table T (the quantized
+ * dt*L(t), scaled by the integrator's factor) and Philox stream `stream`, appended to rec[*nr]:
+ *  - diagonal (death / cloning, reading R4): the comb of the diagonal group (plus the Q32 shift
+ *    qs) applied to the parent with the uniform w1; with `keep_parent` the parent's own record
+ *    carries it, (key, a + d_re, b + d_im), otherwise it is a record (key, d_re, d_im) of its own
+ *    when nonzero (the second AB2 term adds to N(s+1), it does not carry N(s-1) over);
+ *  - off-diagonal (spawn, reading R3): every group in table order, Re then Im, one comb with w0,
+ *    a record (key ^ xmask, n_re, n_im) when nonzero. */
+static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const table_t* T,
+                       int64_t qs_re, uint32_t stream, int keep_parent, rec_t* rec,
+                       uint64_t* nr) {
   const uint32_t G = T->n_groups;
-  uint64_t cap = in->n * (uint64_t)G + 1;
-  rec_t* rec = (rec_t*)malloc(cap * sizeof(rec_t));
   int64_t* xs = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
   int64_t* ns = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
-  if (!rec || !xs || !ns) {
-    free(rec);
+  if (!xs || !ns) {
     free(xs);
     free(ns);
     return ORC_ERR_NOMEM;
   }
   const uint32_t pkey[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
-  uint64_t nr = 0;
   for (uint64_t p = 0; p < in->n; ++p) {
     const uint64_t key = in->key[p];
     const int64_t a = in->re[p], b = in->im[p];
-    /* Philox counter: the walker's key, the step, and (replica << 8) | stream, stream 0. */
-    const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step, (r << 8) | 0u};
+    /* Philox counter: the walker's key, the step, and (replica << 8) | stream. */
+    const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step, (r << 8) | stream};
     uint32_t w[4];
     orc_philox4x32_10(ctr, pkey, w);
 
-    /* Death / cloning from the diagonal entry of the column (reading R4), applied to N(t). */
     int64_t dre, dim;
     group_coeff(T, 0, key, &dre, &dim);
     dre += qs_re;
     int64_t x2[2] = {a * dre - b * dim, a * dim + b * dre};
     int64_t n2[2];
     orc_comb(2, x2, w[1], n2);
-    rec[nr++] = (rec_t){key, a + n2[0], b + n2[1]};
+    if (keep_parent)
+      rec[(*nr)++] = (rec_t){key, a + n2[0], b + n2[1]};
+    else if (n2[0] != 0 || n2[1] != 0)
+      rec[(*nr)++] = (rec_t){key, n2[0], n2[1]};
 
-    /* Spawn into every off-diagonal target of the column, Re and Im channel of each, in group
-     * (xmask ascending) order, with one comb over the whole list (reading R3). */
     for (uint32_t g = 1; g < G; ++g) {
       int64_t cre, cim;
       group_coeff(T, g, key, &cre, &cim);
@@ -521,15 +539,38 @@ static int step_replica(const orc_ctx* c, uint32_t r, const table_t* T, int64_t 
     if (G > 1) orc_comb(2 * (G - 1), xs, w[0], ns);
     for (uint32_t g = 1; g < G; ++g) {
       int64_t cr = ns[2 * (g - 1)], ci = ns[2 * (g - 1) + 1];
-      if (cr != 0 || ci != 0) rec[nr++] = (rec_t){key ^ T->gx[g], cr, ci};
+      if (cr != 0 || ci != 0) rec[(*nr)++] = (rec_t){key ^ T->gx[g], cr, ci};
     }
   }
   free(xs);
   free(ns);
+  return ORC_OK;
+}
+
+/* N(s+1) of replica r.  Euler (End Matter on simulation methodology):
+ *   N(s+1) = N(s) + round(dt L(t_s) N(s)),
+ * with table A = dt L(t_s).  AB2 (same paragraph), for s >= 1:
+ *   N(s+1) = N(s) + round(3/2 dt L(t_s) N(s)) + round(-1/2 dt L(t_{s-1}) N(s-1)),
+ * with table A = 3/2 dt L(t_s) on stream 0 and table B = -1/2 dt L(t_{s-1}) on N(s-1), stream 1.
+ * Annihilation (End Matter): all records merged, summed by location, opposite signs cancel,
+ * empty locations disappear. */
+static int step_replica(const orc_ctx* c, uint32_t r, const table_t* A, int64_t qa,
+                        const table_t* B, int64_t qb, store_t* out, uint64_t* nchild) {
+  const store_t* in = &c->st[r];
+  const store_t* pv = B ? &c->prev[r] : NULL;
+  uint64_t cap = in->n * (uint64_t)A->n_groups + 1;
+  if (B) cap += pv->n * (uint64_t)B->n_groups;
+  rec_t* rec = (rec_t*)malloc(cap * sizeof(rec_t));
+  if (!rec) return ORC_ERR_NOMEM;
+  uint64_t nr = 0;
+  int rc = add_records(c, r, in, A, qa, 0u, 1, rec, &nr);
+  if (!rc && B) rc = add_records(c, r, pv, B, qb, 1u, 0, rec, &nr);
+  if (rc) {
+    free(rec);
+    return rc;
+  }
   *nchild = nr - in->n;
 
-  /* Annihilation (End Matter): merge children with the surviving parents, sum by location,
-   * opposite signs cancel, empty locations disappear. */
   qsort(rec, nr, sizeof(rec_t), cmp_rec);
   uint64_t m = 0;
   for (uint64_t i = 0; i < nr;) {
@@ -565,34 +606,49 @@ static int step_replica(const orc_ctx* c, uint32_t r, const table_t* T, int64_t 
   return ORC_OK;
 }
 
+static uint64_t diag_sum(const table_t* T) {
+  uint64_t s = 0;
+  for (uint32_t i = T->gs[0]; i < T->gs[1]; ++i)
+    s += (uint64_t)llabs(T->t[i].qre) + (uint64_t)llabs(T->t[i].qim);
+  return s;
+}
+
+/* The shifts of all replicas in Q32 for one table (factor `scale`), with the diagonal-group bound
+ * including the shift. */
+static int shifts_q32(const orc_ctx* c, const table_t* T, double scale, int64_t* qs) {
+  const uint64_t dsum = diag_sum(T);
+  for (uint32_t r = 0; r < c->R; ++r)
+    if (q32(c->dt, 1.0, c->shift[r], scale, &qs[r]) ||
+        dsum + (uint64_t)llabs(qs[r]) >= (1ull << 31))
+      return ORC_ERR_DT;
+  return ORC_OK;
+}
+
 static int one_step(orc_ctx* c, const double* s, const double* gamma, int threads) {
-  table_t T;
-  int rc = build_table(c, s, gamma, &T);
+  const int two = c->ab2 && c->have_prev;
+  table_t A, B;
+  int rc = build_table(c, s, gamma, two ? 1.5 : 1.0, &A);
   if (rc) return rc;
+  if (two) {
+    rc = build_table(c, c->w_prev, c->w_prev + c->n_h, -0.5, &B);
+    if (rc) {
+      table_free(&A);
+      return rc;
+    }
+  }
   store_t* nxt = (store_t*)calloc(c->R, sizeof(store_t));
   int* rcs = (int*)calloc(c->R, sizeof(int));
-  if (!nxt || !rcs) {
-    free(nxt);
-    free(rcs);
-    table_free(&T);
-    return ORC_ERR_NOMEM;
-  }
-  /* Death-group bound including the shift. */
-  uint64_t dsum = 0;
-  for (uint32_t i = T.gs[0]; i < T.gs[1]; ++i)
-    dsum += (uint64_t)llabs(T.t[i].qre) + (uint64_t)llabs(T.t[i].qim);
-  int64_t* qs = (int64_t*)calloc(c->R, sizeof(int64_t));
-  for (uint32_t r = 0; r < c->R && qs; ++r) {
-    if (q32(c->dt, 1.0, c->shift[r], &qs[r]) || dsum + (uint64_t)llabs(qs[r]) >= (1ull << 31))
-      rc = ORC_ERR_DT;
-  }
-  if (!qs) rc = ORC_ERR_NOMEM;
+  int64_t* qa = (int64_t*)calloc(c->R, sizeof(int64_t));
+  int64_t* qb = (int64_t*)calloc(c->R, sizeof(int64_t));
+  if (!nxt || !rcs || !qa || !qb) rc = ORC_ERR_NOMEM;
+  if (!rc) rc = shifts_q32(c, &A, two ? 1.5 : 1.0, qa);
+  if (!rc && two) rc = shifts_q32(c, &B, -0.5, qb);
   if (rc == ORC_OK) {
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads > 0 ? threads : 1)
 #endif
     for (uint32_t r = 0; r < c->R; ++r)
-      rcs[r] = step_replica(c, r, &T, qs[r], &nxt[r], &c->nchild[r]);
+      rcs[r] = step_replica(c, r, &A, qa[r], two ? &B : NULL, qb[r], &nxt[r], &c->nchild[r]);
     for (uint32_t r = 0; r < c->R; ++r)
       if (rcs[r] && !rc) rc = rcs[r];
   }
@@ -607,17 +663,29 @@ static int one_step(orc_ctx* c, const double* s, const double* gamma, int thread
         c->walker_steps += (uint64_t)llabs((int64_t)c->st[r].re[p]) +
                            (uint64_t)llabs((int64_t)c->st[r].im[p]);
       c->key_steps += c->st[r].n;
-      store_free(&c->st[r]);
+      if (c->ab2) {
+        store_free(&c->prev[r]);
+        c->prev[r] = c->st[r];
+      } else {
+        store_free(&c->st[r]);
+      }
       c->st[r] = nxt[r];
     }
+    if (c->ab2) {
+      memcpy(c->w_prev, s, c->n_h * sizeof(double));
+      memcpy(c->w_prev + c->n_h, gamma, c->n_l * sizeof(double));
+      c->have_prev = 1;
+    }
     c->step += 1;
-  } else {
+  } else if (nxt) {
     for (uint32_t r = 0; r < c->R; ++r) store_free(&nxt[r]);
   }
-  free(qs);
+  free(qa);
+  free(qb);
   free(nxt);
   free(rcs);
-  table_free(&T);
+  table_free(&A);
+  if (two) table_free(&B);
   return rc;
 }
 
@@ -642,6 +710,47 @@ int orc_step_threads(orc_ctx* c, uint32_t nsteps, const double* s, const double*
   for (uint32_t k = 0; k < nsteps; ++k) {
     int rc = one_step(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, used);
     if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+/* AB2 mode (End Matter on simulation methodology).  Switching it on or off clears N(s-1): the
+ * next step is an Euler step unless orc_set_prev supplies N(s-1) and the weights of step s-1. */
+int orc_set_integrator(orc_ctx* c, int ab2) {
+  if (ab2 != 0 && ab2 != 1) return ORC_ERR_ARG;
+  c->ab2 = ab2;
+  c->have_prev = 0;
+  for (uint32_t r = 0; r < c->R; ++r) store_free(&c->prev[r]);
+  return ORC_OK;
+}
+
+static int store_set(store_t* st, uint32_t n_qubits, const uint64_t* keys, const int32_t* re,
+                     const int32_t* im, uint64_t n);
+
+/* N(s-1) of one replica and the weights of step s-1 (s_prev[n_h], gamma_prev[n_l], shared by all
+ * replicas) for an AB2 context resumed at step s >= 1; a replica whose N(s-1) is not set has an
+ * empty one.  orc_import leaves N(s-1) alone. */
+int orc_set_prev(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+                 const int32_t* im, uint64_t n, const double* s_prev, const double* gamma_prev) {
+  if (!c->ab2 || replica >= c->R) return ORC_ERR_ARG;
+  int rc = store_set(&c->prev[replica], c->n, keys, re, im, n);
+  if (rc) return rc;
+  memcpy(c->w_prev, s_prev, c->n_h * sizeof(double));
+  memcpy(c->w_prev + c->n_h, gamma_prev, c->n_l * sizeof(double));
+  c->have_prev = 1;
+  return ORC_OK;
+}
+
+int orc_export_prev(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+                    uint64_t cap, uint64_t* n) {
+  if (!c->ab2 || !c->have_prev || replica >= c->R) return ORC_ERR_ARG;
+  const store_t* st = &c->prev[replica];
+  *n = st->n;
+  if (st->n > cap) return ORC_ERR_ARG;
+  if (st->n) {
+    memcpy(keys, st->key, st->n * sizeof(uint64_t));
+    memcpy(re, st->re, st->n * sizeof(int32_t));
+    memcpy(im, st->im, st->n * sizeof(int32_t));
   }
   return ORC_OK;
 }
@@ -712,16 +821,14 @@ int orc_export(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, 
   return ORC_OK;
 }
 
-int orc_import(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
-               const int32_t* im, uint64_t n, uint32_t step) {
-  if (replica >= c->R) return ORC_ERR_ARG;
-  const uint64_t kmask = c->n == 32 ? ~0ull : ((1ull << (2 * c->n)) - 1);
+static int store_set(store_t* st, uint32_t n_qubits, const uint64_t* keys, const int32_t* re,
+                     const int32_t* im, uint64_t n) {
+  const uint64_t kmask = n_qubits == 32 ? ~0ull : ((1ull << (2 * n_qubits)) - 1);
   for (uint64_t i = 0; i < n; ++i) {
     if (keys[i] & ~kmask) return ORC_ERR_ARG;
     if (i && keys[i] <= keys[i - 1]) return ORC_ERR_ARG;
     if (re[i] == 0 && im[i] == 0) return ORC_ERR_ARG;
   }
-  store_t* st = &c->st[replica];
   store_free(st);
   st->key = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
   st->re = (int32_t*)malloc((n ? n : 1) * sizeof(int32_t));
@@ -731,6 +838,14 @@ int orc_import(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t
   memcpy(st->re, re, n * sizeof(int32_t));
   memcpy(st->im, im, n * sizeof(int32_t));
   st->n = n;
+  return ORC_OK;
+}
+
+int orc_import(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+               const int32_t* im, uint64_t n, uint32_t step) {
+  if (replica >= c->R) return ORC_ERR_ARG;
+  int rc = store_set(&c->st[replica], c->n, keys, re, im, n);
+  if (rc) return rc;
   c->step = step;
   return ORC_OK;
 }

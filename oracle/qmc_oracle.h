@@ -63,10 +63,11 @@ uint32_t orc_n_terms(const orc_ctx* c);
 int orc_get_terms(const orc_ctx* c, uint64_t* xmask, uint64_t* zmask, double* kre, double* kim,
                   uint32_t* kind, uint32_t* index);
 
-/* The quantized, merged, grouped coefficient table for one step with weights s[n_h], gamma[n_l].
+/* The quantized, merged, grouped coefficient table for one step with weights s[n_h], gamma[n_l]:
+ * scale * dt * L(t) with scale 1 (Euler) or 3/2, -1/2 (the two AB2 terms).
  * Groups are ordered by xmask ascending; group 0 is always the diagonal (xmask 0, possibly empty).
  * gstart has n_groups+1 entries. Returns ORC_ERR_DT if the bound fails. */
-int orc_table(const orc_ctx* c, const double* s, const double* gamma,
+int orc_table(const orc_ctx* c, const double* s, const double* gamma, double scale,
               uint32_t cap_groups, uint32_t cap_terms,
               uint32_t* n_groups, uint64_t* gxmask, uint32_t* gstart,
               uint32_t* n_terms, uint64_t* tzmask, int64_t* tq /* [n][2] */);
@@ -74,12 +75,22 @@ int orc_table(const orc_ctx* c, const double* s, const double* gamma,
 /* Column `key` of dt*L(t) (unquantized, FP64), merged by target key, targets ascending. */
 int orc_column_fp(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
                   uint32_t cap, uint32_t* n, uint64_t* tkey, double* val /* [n][2] */);
-/* Column `key` of the quantized table (Q32 integers), merged by target key, targets ascending. */
-int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, uint64_t key,
-                 uint32_t cap, uint32_t* n, uint64_t* tkey, int64_t* val /* [n][2] */);
+/* Column `key` of the quantized table with factor `scale` (Q32 integers), merged by target key,
+ * targets ascending. */
+int orc_column_q(const orc_ctx* c, const double* s, const double* gamma, double scale,
+                 uint64_t key, uint32_t cap, uint32_t* n, uint64_t* tkey,
+                 int64_t* val /* [n][2] */);
 
-/* Advance every replica by nsteps Euler steps; s is [nsteps][n_h], gamma [nsteps][n_l]. */
+/* Advance every replica by nsteps steps; s is [nsteps][n_h], gamma [nsteps][n_l].  Euler by
+ * default; in AB2 mode every step after the first uses N(s-1) and the weights of step s-1. */
 int orc_step(orc_ctx* c, uint32_t nsteps, const double* s, const double* gamma);
+/* 0: Euler, 1: AB2 (End Matter on simulation methodology).  Clears N(s-1). */
+int orc_set_integrator(orc_ctx* c, int ab2);
+/* AB2: N(s-1) of one replica and the weights of step s-1 (shared by all replicas). */
+int orc_set_prev(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+                 const int32_t* im, uint64_t n, const double* s_prev, const double* gamma_prev);
+int orc_export_prev(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+                    uint64_t cap, uint64_t* n);
 /* Apply the ideal instantaneous Pauli conjugation rho -> P rho P^dagger, P = X^x Z^z. */
 int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z);
 /* Constant diagonal shift S added to the death coefficient (0 = none, the paper's setting). */

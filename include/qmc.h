@@ -121,9 +121,30 @@ int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma
  * QMC_ERR_STORE_CAP or QMC_ERR_SPAWN_CAP).  path 2: streamed only.  QMC_ERR_ARG otherwise. */
 int qmc_step_path(qmc_ctx* ctx, int32_t path);
 
+/* Time integrator of qmc_step (End Matter on simulation methodology): 0 = Euler (default),
+ * N(s+1) = N(s) + round(dt L(t_s) N(s)); 1 = AB2, for s >= 1
+ *   N(s+1) = N(s) + round(3/2 dt L(t_s) N(s)) + round(-1/2 dt L(t_{s-1}) N(s-1)),
+ * each term rounded as in the Euler step from its own table -- Q32 of scale * (dt * (w * kappa))
+ * with scale 3/2 and -1/2 -- and its own Philox stream (0 for N(s), 1 for N(s-1), whose diagonal
+ * is a record of its own rather than a change of N(s-1)).  The context keeps N(s-1) and the
+ * weights of step s-1; without them (after qmc_init, qmc_set_integrator or qmc_pulse) the next
+ * step is an Euler step.  Switching clears N(s-1).  QMC_ERR_ARG for another value. */
+int qmc_set_integrator(qmc_ctx* ctx, int32_t integrator);
+
+/* AB2: N(s-1) of one replica (same record rules as qmc_init) and the weights of step s-1
+ * (s_prev[n_h], gamma_prev[n_l], shared by all replicas), for a context resumed at step s
+ * (qmc_import) with the next step an AB2 step.  A replica whose N(s-1) is not set has an empty
+ * one.  QMC_ERR_ARG if the integrator is not AB2 or the records are invalid. */
+int qmc_set_prev(qmc_ctx* ctx, uint32_t replica, const uint64_t* keys, const int32_t* re,
+                 const int32_t* im, uint64_t n, const double* s_prev, const double* gamma_prev);
+
+/* AB2: copy one replica's N(s-1) to host arrays, as qmc_export.  QMC_ERR_ARG if there is none. */
+int qmc_export_prev(qmc_ctx* ctx, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+                    uint64_t cap, uint64_t* n);
+
 /* Ideal instantaneous Pauli pulse on every replica: rho -> P rho P^dagger with P = X^x Z^z,
  * i.e. |i><j| -> (-1)^{popc(z & i) + popc(z & j)} |i ^ x><j ^ x| (used for the staggered-XX
- * dynamical-decoupling pulses of Fig. 1(c)). */
+ * dynamical-decoupling pulses of Fig. 1(c)).  With AB2 the next step is an Euler step. */
 int qmc_pulse(qmc_ctx* ctx, uint64_t x, uint64_t z);
 
 /* Constant diagonal shift S for one replica (death coefficient L_diag + S).  The paper needs
@@ -169,7 +190,8 @@ int qmc_export(qmc_ctx* ctx, uint32_t replica, uint64_t* keys, int32_t* re, int3
                uint64_t cap, uint64_t* n);
 
 /* Replace one replica's store (same rules as qmc_init's records) and set the step counter
- * of the context to `step` (the Philox counter of the next step). */
+ * of the context to `step` (the Philox counter of the next step).  N(s-1) (AB2) is left as it
+ * is; qmc_set_prev replaces it. */
 int qmc_import(qmc_ctx* ctx, uint32_t replica, const uint64_t* keys, const int32_t* re,
                const int32_t* im, uint64_t n, uint32_t step);
 
@@ -201,13 +223,14 @@ int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
 int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches, qmc_stats* covered);
 
 /* The quantized coefficient table of one step for this configuration and model, computed on
- * the host only (no device, no context): n_groups groups (group 0 = diagonal, always present)
+ * the host only (no device, no context), for scale * dt * L(t) (scale 1 for Euler, 3/2 and -1/2
+ * for the two AB2 terms): n_groups groups (group 0 = diagonal, always present)
  * with masks gxmask[g] and term ranges gstart[g] .. gstart[g+1]-1; term t has sign mask
  * tzmask[t] and Q32 coefficient tq[t][0] + i tq[t][1].  For checking the table against an
  * independent implementation.  QMC_ERR_ARG if a capacity is too small, QMC_ERR_DT if the
  * Q32 bound fails. */
 int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double* s,
-                    const double* gamma, uint32_t cap_groups, uint32_t cap_terms,
+                    const double* gamma, double scale, uint32_t cap_groups, uint32_t cap_terms,
                     uint32_t* n_groups, uint64_t* gxmask, uint32_t* gstart, uint32_t* n_terms,
                     uint64_t* tzmask, int64_t* tq);
 

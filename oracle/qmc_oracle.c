@@ -755,7 +755,8 @@ int orc_export_prev(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t*
   return ORC_OK;
 }
 
-/* Ideal instantaneous Pauli pulse: P |i><j| P^dagger = (-1)^{popc(z&i) + popc(z&j)} |i^x><j^x|. */
+/* Ideal instantaneous Pauli pulse: P |i><j| P^dagger = (-1)^{popc(z&i) + popc(z&j)} |i^x><j^x|.
+ * With AB2 the step after a pulse is an Euler step. */
 int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z) {
   const uint32_t n = c->n;
   const uint64_t qmask = n == 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
@@ -786,6 +787,8 @@ int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z) {
     }
     free(rec);
   }
+  /* AB2 (reading: a pulse restarts the two-step formula): the next step is an Euler step. */
+  c->have_prev = 0;
   return ORC_OK;
 }
 

@@ -91,7 +91,8 @@ int orc_set_prev(orc_ctx* c, uint32_t replica, const uint64_t* keys, const int32
                  const int32_t* im, uint64_t n, const double* s_prev, const double* gamma_prev);
 int orc_export_prev(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
                     uint64_t cap, uint64_t* n);
-/* Apply the ideal instantaneous Pauli conjugation rho -> P rho P^dagger, P = X^x Z^z. */
+/* Apply the ideal instantaneous Pauli conjugation rho -> P rho P^dagger, P = X^x Z^z (with AB2,
+ * the next step is an Euler step). */
 int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z);
 /* Constant diagonal shift S added to the death coefficient (0 = none, the paper's setting). */
 int orc_set_shift(orc_ctx* c, uint32_t replica, double shift);

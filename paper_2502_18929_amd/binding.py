@@ -23,7 +23,8 @@ QMC_ERR_COUNT_OVERFLOW = -5
 QMC_ERR_HIP = -6
 QMC_ERR_STATE = -8
 
-EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path", "qmc_pulse",
+EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
+            "qmc_set_integrator", "qmc_set_prev", "qmc_export_prev", "qmc_pulse",
             "qmc_set_shift", "qmc_observe", "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
             "qmc_destroy"]
@@ -96,8 +97,11 @@ def lib():
         L.qmc_counters.argtypes = [vp, P(Stats)]
         L.qmc_profile.argtypes = [vp, ctypes.c_int32]
         L.qmc_step_path.argtypes = [vp, ctypes.c_int32]
+        L.qmc_set_integrator.argtypes = [vp, ctypes.c_int32]
+        L.qmc_set_prev.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(dbl), P(dbl)]
+        L.qmc_export_prev.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.qmc_profile_read.argtypes = [vp, P(dbl), P(u64), P(Stats)]
-        L.qmc_coeff_table.argtypes = [P(Config), P(Model), P(dbl), P(dbl), u32, u32, P(u32),
+        L.qmc_coeff_table.argtypes = [P(Config), P(Model), P(dbl), P(dbl), dbl, u32, u32, P(u32),
                                       P(u64), P(u32), P(u32), P(u64), P(ctypes.c_int64)]
         L.qmc_last_error.argtypes = [vp]
         L.qmc_last_error.restype = ctypes.c_char_p
@@ -284,6 +288,37 @@ class QMC:
         return dict(step=st.step, n_occ=st.n_occ_total, walker_steps=st.walker_steps,
                     key_steps=st.key_steps, child_steps=st.child_steps, out_steps=st.out_steps)
 
+    def set_integrator(self, integrator):
+        """Time integrator: 'euler' (default) or 'ab2' (clears N(s-1))."""
+        self._check(lib().qmc_set_integrator(self._ctx, {"euler": 0, "ab2": 1}[integrator]))
+
+    def set_prev(self, replica, keys, re, im, s_prev, gamma_prev):
+        """AB2: N(s-1) of one replica and the weights of step s-1."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        re = np.ascontiguousarray(re, dtype=np.int32)
+        im = np.ascontiguousarray(im, dtype=np.int32)
+        s = np.ascontiguousarray(s_prev if self.n_h else np.zeros(1), dtype=np.float64)
+        g = np.ascontiguousarray(gamma_prev if self.n_l else np.zeros(1), dtype=np.float64)
+        self._check(lib().qmc_set_prev(self._ctx, int(replica), _ptr(keys, ctypes.c_uint64),
+                                       _ptr(re, ctypes.c_int32), _ptr(im, ctypes.c_int32),
+                                       len(keys), _ptr(s, ctypes.c_double),
+                                       _ptr(g, ctypes.c_double)))
+
+    def export_prev(self, replica):
+        """AB2: N(s-1) of one replica (keys ascending)."""
+        n = ctypes.c_uint64()
+        rc = lib().qmc_export_prev(self._ctx, int(replica), None, None, None, 0, ctypes.byref(n))
+        if rc not in (QMC_OK, QMC_ERR_ARG):
+            self._check(rc)
+        m = n.value
+        k = np.zeros(max(m, 1), np.uint64)
+        a = np.zeros(max(m, 1), np.int32)
+        b = np.zeros(max(m, 1), np.int32)
+        self._check(lib().qmc_export_prev(self._ctx, int(replica), _ptr(k, ctypes.c_uint64),
+                                          _ptr(a, ctypes.c_int32), _ptr(b, ctypes.c_int32), m,
+                                          ctypes.byref(n)))
+        return k[:m].copy(), a[:m].copy(), b[:m].copy()
+
     def set_path(self, path):
         """Step implementation: 'auto' (default), 'fused' (persistent kernel) or 'streamed'."""
         self._check(lib().qmc_step_path(self._ctx, {"auto": 0, "fused": 1, "streamed": 2}[path]))
@@ -304,8 +339,9 @@ class QMC:
                    child_steps=st.child_steps, out_steps=st.out_steps)
         return ms.value, n.value, cov
 
-def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1):
-    """Host-only: the quantized step table the library would use (no device needed)."""
+def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1, scale=1.0):
+    """Host-only: the quantized step table the library would use (no device needed), for
+    scale * dt * L(t) (1 for Euler; 3/2 and -1/2 for the two AB2 terms)."""
     L = lib()
     hm = _monos(h)
     lm = _monos([m for op in lops for m in op])
@@ -321,7 +357,7 @@ def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1):
     gx = np.zeros(cap, np.uint64); gs = np.zeros(cap + 1, np.uint32)
     tz = np.zeros(cap, np.uint64); tq = np.zeros((cap, 2), np.int64)
     rc = L.qmc_coeff_table(ctypes.byref(cfg), ctypes.byref(model), _ptr(s, ctypes.c_double),
-                           _ptr(g, ctypes.c_double), cap, cap, ctypes.byref(ng),
+                           _ptr(g, ctypes.c_double), float(scale), cap, cap, ctypes.byref(ng),
                            _ptr(gx, ctypes.c_uint64), _ptr(gs, ctypes.c_uint32), ctypes.byref(nt),
                            _ptr(tz, ctypes.c_uint64), _ptr(tq, ctypes.c_int64))
     if rc:

@@ -65,7 +65,8 @@ struct TableHeader {
 };
 
 struct Counters {
-  uint64_t n_store[2];     // occupied keys of the store buffer 0 / 1
+  uint64_t n_store[2];     // occupied keys of the current / next store (by step parity)
+  uint64_t n_prev;         // occupied keys of N(s-1) (AB2)
   uint64_t n_child[2];     // child records of the step with the same parity
   uint64_t walker_steps;   // running sum of N^tot over the parents of every step
   uint64_t key_steps;      // running sum of occupied keys over the parents of every step
@@ -192,10 +193,12 @@ struct KeyLayout {
   }
 };
 
+// Philox block of a walker: counter (key, step, (replica << 8) | stream), key = the seed.
+// Stream 0 draws for N(s) (Euler, first AB2 term), stream 1 for N(s-1) (second AB2 term).
 __device__ __forceinline__ void walker_random(uint64_t key, uint32_t step, uint32_t replica,
-                                              uint64_t seed, uint32_t w[4]) {
-  philox4x32_10((uint32_t)key, (uint32_t)(key >> 32), step, replica << 8, (uint32_t)seed,
-                (uint32_t)(seed >> 32), w);
+                                              uint64_t seed, uint32_t stream, uint32_t w[4]) {
+  philox4x32_10((uint32_t)key, (uint32_t)(key >> 32), step, (replica << 8) | stream,
+                (uint32_t)seed, (uint32_t)(seed >> 32), w);
 }
 
 // Group coefficient c = sum_t (-1)^parity(zmask_t & key) q_t; |c_re| + |c_im| < 2^31, so every

@@ -25,6 +25,7 @@ constexpr uint32_t kMaxPauli = 256;
 constexpr uint32_t kMaxLookup = 4096;
 constexpr size_t kTableArea = 8u << 20;   // device bytes for the step tables of one chunk
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
+constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -45,8 +46,8 @@ struct QTerm {
 
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
-      obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, in_k, in_v, in_n, split, tab_off,
-      slots, done, total;
+      obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
+      tab_off, tabB_off, slots, done, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -93,19 +94,22 @@ bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
   L.status = take(L.max_tiles * 8);
   L.splits = take((L.max_tiles + 1) * 8);
   L.tab = take(kTableArea);
-  L.qshift = take((size_t)c.n_replicas * 8);
+  L.qshift = take((size_t)c.n_replicas * 2 * 8);  // first / only term, then the second AB2 term
   L.obs_out = take((size_t)c.n_replicas * (5 + 2 * kMaxPauli) * 8);
   L.obs_in = take((size_t)kMaxPauli * 16);
   L.look_keys = take((size_t)kMaxLookup * 8);
   L.look_out = take((size_t)c.n_replicas * kMaxLookup * 16);
-  L.seg_k = take((size_t)2 * P * L.segcap * 8);
-  L.seg_v = take((size_t)2 * P * L.segcap * 8);
-  L.seg_n = take((size_t)2 * P * 4);
+  L.seg_k = take((size_t)kSegBuffers * P * L.segcap * 8);
+  L.seg_v = take((size_t)kSegBuffers * P * L.segcap * 8);
+  L.seg_n = take((size_t)kSegBuffers * P * 4);
+  L.pk = take(S * 8);  // N(s-1) (AB2)
+  L.pv = take(S * 8);
   L.in_k = take((size_t)2 * P * L.incap * 8);
   L.in_v = take((size_t)2 * P * L.incap * 8);
   L.in_n = take((size_t)2 * P * 4);
   L.split = take((size_t)P * 8);
   L.tab_off = take((size_t)kMaxChunkSteps * 4);
+  L.tabB_off = take((size_t)kMaxChunkSteps * 4);
   L.slots = take((size_t)P * 4 * 8);
   L.done = take(8);
   L.total = o;
@@ -142,6 +146,9 @@ struct qmc_ctx {
   int32_t prof_class = -1;
   uint64_t epoch = 0;               // last barrier epoch used by the persistent step
   int32_t path = 0;                 // 0 automatic, 1 fused persistent kernel only, 2 streamed only
+  int32_t integrator = 0;           // 0 Euler, 1 AB2
+  bool have_prev = false;           // AB2: N(s-1) (device) and w_prev are valid
+  std::vector<double> w_prev;       // AB2: weights of step s-1 (s then gamma)
   uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
   uint32_t streamed_until = 0;      // automatic mode: steps before this one run streamed
   std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
@@ -156,8 +163,12 @@ struct qmc_ctx {
   // between it and the segment area of the persistent step (at least 4x the store capacity).
   uint64_t* sk(uint32_t) const { return at<uint64_t>(L.sk0); }
   int2* sv(uint32_t) const { return at<int2>(L.sv0); }
-  uint64_t* alt_k() const { return at<uint64_t>(L.seg_k); }
-  int2* alt_v() const { return at<int2>(L.seg_v); }
+  uint64_t* alt_k(uint32_t i = 0) const {
+    return at<uint64_t>(L.seg_k) + (size_t)i * L.cap_store;
+  }
+  int2* alt_v(uint32_t i = 0) const { return at<int2>(L.seg_v) + (size_t)i * L.cap_store; }
+  uint64_t* pk() const { return at<uint64_t>(L.pk); }  // N(s-1), AB2
+  int2* pv() const { return at<int2>(L.pv); }
   uint64_t* ck(uint32_t b) const { return at<uint64_t>(b ? L.ck1 : L.ck0); }
   int2* cv(uint32_t b) const { return at<int2>(b ? L.cv1 : L.cv0); }
   qmc::Counters* counters() const { return at<qmc::Counters>(L.counters); }
@@ -225,8 +236,11 @@ void compile_model(const qmc_model& m, uint32_t n, std::vector<SrcTerm>& out) {
   }
 }
 
-bool quantize(double dt, double w, double k, int64_t& q) {
-  const double v = std::ldexp(dt * (w * k), 32);
+// Q32 of scale * dt * w * kappa0: the product w * kappa0 first, then dt, then the integrator's
+// factor (1 for Euler; 3/2 and -1/2 for the two AB2 terms), exact scaling by 2^32, round half to
+// even.
+bool quantize(double dt, double w, double k, double scale, int64_t& q) {
+  const double v = std::ldexp(scale * (dt * (w * k)), 32);
   if (!std::isfinite(v) || std::fabs(v) >= 4611686018427387904.0) return false;
   q = (int64_t)std::llrint(v);
   return true;
@@ -242,8 +256,8 @@ struct HostTable {
   uint64_t q_off = 0, q_diag = 0;
 };
 
-int build_table(const qmc_ctx* c, const double* s, const double* g, HostTable& T,
-                std::string& why) {
+int build_table(const qmc_ctx* c, const double* s, const double* g, double scale,
+                HostTable& T, std::string& why) {
   std::vector<QTerm> q;
   q.reserve(c->terms.size());
   for (const SrcTerm& st : c->terms) {
@@ -253,7 +267,8 @@ int build_table(const qmc_ctx* c, const double* s, const double* g, HostTable& T
       return QMC_ERR_ARG;
     }
     QTerm qt{st.xmask, st.zmask, 0, 0};
-    if (!quantize(c->cfg.dt, w, st.kre, qt.qre) || !quantize(c->cfg.dt, w, st.kim, qt.qim)) {
+    if (!quantize(c->cfg.dt, w, st.kre, scale, qt.qre) ||
+        !quantize(c->cfg.dt, w, st.kim, scale, qt.qim)) {
       why = "coefficient too large for Q32";
       return QMC_ERR_DT;
     }
@@ -451,10 +466,11 @@ int upload_qshift(qmc_ctx* c, const std::vector<int64_t>& qs) {
   return QMC_OK;
 }
 
-int shifts_q32(const qmc_ctx* c, std::vector<int64_t>& qs) {
+// Per-replica Q32 shifts for a table with the integrator's factor `scale`.
+int shifts_q32(const qmc_ctx* c, double scale, std::vector<int64_t>& qs) {
   qs.resize(c->R);
   for (uint32_t r = 0; r < c->R; ++r)
-    if (!quantize(c->cfg.dt, 1.0, c->shift[r], qs[r])) return QMC_ERR_DT;
+    if (!quantize(c->cfg.dt, 1.0, c->shift[r], scale, qs[r])) return QMC_ERR_DT;
   return QMC_OK;
 }
 
@@ -543,7 +559,7 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   c->cur = 0;
   rc = upload_store(c, 0, ck, cv);
   if (!rc) {
-    std::vector<int64_t> qs(c->R, 0);
+    std::vector<int64_t> qs(2 * (size_t)c->R, 0);
     rc = upload_qshift(c, qs);
   }
   if (rc) {
@@ -569,24 +585,34 @@ void add_cover(qmc_ctx* c, const qmc::Counters& a, const qmc::Counters& b, uint3
 constexpr uint64_t kFusedKeysPerSegment = 8192;  // automatic mode: larger stores run streamed
 constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a fused overflow
 
-// Steps [step, step + nst) as one launch of the fused persistent kernel (tables already on the
-// device at dtab, offsets at tab_off).  On return kd = completed steps, reason = the kernel's stop
-// reason (0 end, 1 rebalance, 2 error), hc = the counters; the store and c->step reflect kd.
-int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& reason,
-              qmc::Counters& hc) {
+// One chunk of steps [step, step + nst): device tables at dtab (+ offsA / offsB), and whether
+// the chunk integrates with AB2 from a known N(s-1) (`two`; the tables B exist).
+struct Chunk {
+  uint8_t* dtab;
+  std::vector<uint32_t> offsA, offsB;
+  uint32_t nst;
+  bool two;
+};
+
+// Steps of the chunk as one launch of the fused persistent kernel.  On return kd = completed
+// steps, reason = the kernel's stop reason (0 end, 1 rebalance, 2 error), hc = the counters; the
+// store (and N(s-1) for AB2) and c->step reflect kd.
+int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::Counters& hc) {
   const qmc::Counters before = c->last_hc;
   uint32_t* pin_done = reinterpret_cast<uint32_t*>(c->pinned_small + 1024);
+  const uint32_t nst = ch.nst;
   PersistLaunch pl;
   pl.ck = c->sk(0);
   pl.cv = c->sv(0);
-  pl.ck_w = c->sk(0);
-  pl.cv_w = c->sv(0);
+  pl.pk_prev = ch.two ? c->pk() : nullptr;
+  pl.pv_prev = ch.two ? c->pv() : nullptr;
   pl.counters = c->counters();
   pl.cur = c->cur;
   pl.sk = c->at<uint64_t>(c->L.seg_k);
   pl.sv = c->at<int2>(c->L.seg_v);
   pl.segcap = c->L.segcap;
   pl.seg_n = c->at<uint32_t>(c->L.seg_n);
+  pl.nbuf = c->integrator == 1 ? 3u : 2u;
   pl.ik = c->at<uint64_t>(c->L.in_k);
   pl.iv = c->at<int2>(c->L.in_v);
   pl.incap = c->L.incap;
@@ -594,14 +620,16 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
   pl.split = c->at<uint64_t>(c->L.split);
   pl.split_w = c->at<uint64_t>(c->L.split);
   pl.P = c->L.P;
-  pl.tab_base = dtab;
+  pl.tab_base = ch.dtab;
   pl.tab_off = c->at<uint32_t>(c->L.tab_off);
+  pl.tabB_off = ch.two ? c->at<uint32_t>(c->L.tabB_off) : nullptr;
   pl.step0 = c->step;
   pl.nsteps = nst;
   pl.seed = c->cfg.seed;
   pl.kbits = c->kbits;
   pl.n_replicas = c->R;
   pl.qshift = c->at<int64_t>(c->L.qshift);
+  pl.qshiftB = c->at<int64_t>(c->L.qshift) + c->R;
   pl.slots = c->at<uint64_t>(c->L.slots);
   pl.epoch0 = c->epoch + 1;
   c->epoch += (uint64_t)nst + 1;  // barriers of this launch: batch start + one per step
@@ -609,6 +637,11 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
   pl.cap_inbox = c->L.cap_child;
   pl.rebal_min = 64;
   pl.done = c->at<uint32_t>(c->L.done);
+  HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), ch.offsA.data(), nst * 4,
+                           hipMemcpyHostToDevice, c->stream));
+  if (ch.two)
+    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tabB_off), ch.offsB.data(), nst * 4,
+                             hipMemcpyHostToDevice, c->stream));
   const bool prof = c->prof_class == 3;
   if (prof) {
     while (c->prof_ev.size() < 2) {
@@ -640,9 +673,14 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
     }
     kd = es - pl.step0;
   }
-  // The state after kd completed steps is in segment buffer kd & 1 (kd = 0: untouched store).
+  // N(step0 + j) is in segment buffer j mod nbuf; kd = 0 leaves the stores untouched.
   if (kd > 0) {
-    HIPCHK(c, qmcp_gather(c->stream, &pl, kd & 1u));
+    qmc::Counters* dcnt = c->counters();
+    if (c->integrator == 1)
+      HIPCHK(c, qmcp_gather(c->stream, &pl, (kd - 1) % pl.nbuf, c->pk(), c->pv(),
+                            &dcnt->n_prev));
+    HIPCHK(c, qmcp_gather(c->stream, &pl, kd % pl.nbuf, c->sk(0), c->sv(0),
+                          &dcnt->n_store[c->cur]));
     rc = read_counters(c, hc);
     if (rc) return rc;
   }
@@ -652,17 +690,23 @@ int run_fused(qmc_ctx* c, uint8_t* dtab, uint32_t nst, uint32_t& kd, uint32_t& r
   return QMC_OK;
 }
 
-// Steps [step, step + nst) as separate kernels per step: spawn (first step only), LSD radix sort
-// of the children, and the merge, which also spawns the next step's children.  The store
-// alternates between the canonical buffer and the segment area and ends in the canonical buffer.
-int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& offs, uint32_t nst,
-                 uint32_t& kd, qmc::Counters& hc) {
+// Steps of the chunk as separate kernels per step: spawn (first step only, plus the second AB2
+// term from N(s-1)), LSD radix sort of the children, and the merge, which also spawns the next
+// step's children (both AB2 terms).  The store cycles through the canonical buffer and one (two
+// for AB2) buffers of the segment area and ends in the canonical buffer; N(s-1) ends in its
+// buffer.
+int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   qmc::Counters* dcnt = c->counters();
   const qmc::Counters before = c->last_hc;
+  const uint32_t nst = ch.nst;
   const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits);
   const uint32_t step0 = c->step, cur0 = c->cur;
-  uint64_t* bk[2] = {c->sk(0), c->alt_k()};
-  int2* bv[2] = {c->sv(0), c->alt_v()};
+  const uint32_t nb = c->integrator == 1 ? 3u : 2u;
+  uint64_t* bk[3] = {c->sk(0), c->alt_k(0), c->alt_k(1)};
+  int2* bv[3] = {c->sv(0), c->alt_v(0), c->alt_v(1)};
+  const int64_t* qshA = c->at<int64_t>(c->L.qshift);
+  const int64_t* qshB = qshA + c->R;
+  const uint8_t* dtab = ch.dtab;
   HIPCHK(c, qmck_batch_begin(c->stream, dcnt, c->at<uint64_t>(c->L.status), c->L.max_tiles,
                              c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
                              2 * qmc::kMaxPasses * qmc::kRadixBins));
@@ -680,14 +724,20 @@ int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& o
   };
   uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
   HIPCHK(c, mark(0, 0, 0));
-  HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, cur0, dtab + offs[0], step0, c->cfg.seed,
-                       c->kbits, c->ck(cb), c->cv(cb), c->L.cap_child, c->L.cap_store,
-                       c->ghist(step0 & 1), passes));
+  HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab + ch.offsA[0],
+                       step0, c->cfg.seed, c->kbits, 0u, nullptr, c->ck(cb), c->cv(cb),
+                       c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
+  if (ch.two)
+    HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab + ch.offsB[0],
+                         step0, c->cfg.seed, c->kbits, 1u, qshB, c->ck(cb), c->cv(cb),
+                         c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
   HIPCHK(c, mark(0, 0, 1));
   for (uint32_t k = 0; k < nst; ++k) {
-    const uint32_t st = step0 + k, b = k & 1u, cur = cur0 ^ b;
-    const uint8_t* tab = dtab + offs[k];
-    const uint8_t* tab_next = (k + 1 < nst) ? dtab + offs[k + 1] : nullptr;
+    const uint32_t st = step0 + k, b = k % nb, cur = cur0 ^ (k & 1u);
+    const uint8_t* tab = dtab + ch.offsA[k];
+    const bool more = k + 1 < nst;
+    const uint8_t* tab_next = more ? dtab + ch.offsA[k + 1] : nullptr;
+    const uint8_t* tabB_next = more && c->integrator == 1 ? dtab + ch.offsB[k + 1] : nullptr;
     const uint32_t csel = st & 1;
     HIPCHK(c, mark(1, k, 0));
     HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
@@ -698,8 +748,8 @@ int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& o
     HIPCHK(c, mark(2, k, 0));
     HIPCHK(c, qmck_merge(c->stream, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
                          c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), tab, tab_next,
-                         c->at<int64_t>(c->L.qshift), st, c->cfg.seed, c->kbits, bk[b ^ 1],
-                         bv[b ^ 1], c->L.cap_store, c->L.cap_store + c->L.cap_child,
+                         tabB_next, qshA, qshB, st, c->cfg.seed, c->kbits, bk[(k + 1) % nb],
+                         bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
                          c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
                          passes));
     HIPCHK(c, mark(2, k, 1));
@@ -725,10 +775,20 @@ int run_streamed(qmc_ctx* c, const uint8_t* dtab, const std::vector<uint32_t>& o
     }
     kd = es - step0;
   }
+  // N(step0 + j) is in bk[j mod nb] with count n_store[cur0 ^ (j & 1)].  N(s-1) first: it may
+  // sit in the canonical buffer that N(s) then overwrites.
   const uint32_t cur = cur0 ^ (kd & 1u);
-  if (kd & 1u) {
-    HIPCHK(c, qmck_copy_store(c->stream, bk[1], bv[1], bk[0], bv[0], &dcnt->n_store[cur],
-                              c->L.cap_store));
+  if (c->integrator == 1 && kd > 0) {
+    const uint32_t j = kd - 1;
+    HIPCHK(c, qmck_copy_store(c->stream, bk[j % nb], bv[j % nb], c->pk(), c->pv(),
+                              &dcnt->n_store[cur0 ^ (j & 1u)], c->L.cap_store));
+    HIPCHK(c, hipMemcpyAsync(&dcnt->n_prev, &dcnt->n_store[cur0 ^ (j & 1u)], 8,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (kd % nb != 0)
+    HIPCHK(c, qmck_copy_store(c->stream, bk[kd % nb], bv[kd % nb], bk[0], bv[0],
+                              &dcnt->n_store[cur], c->L.cap_store));
+  if (kd > 0) {
     rc = read_counters(c, hc);
     if (rc) return rc;
   }
@@ -746,26 +806,58 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
   if (nsteps == 0) return QMC_OK;
   if ((c->n_h && !s) || (c->n_l && !gamma)) return fail(c, QMC_ERR_ARG, "missing weights");
-  std::vector<int64_t> qs;
-  if (shifts_q32(c, qs)) return fail(c, QMC_ERR_DT, "shift too large for Q32");
-  uint64_t max_qs = 0;
-  for (int64_t v : qs) max_qs = std::max(max_qs, uabs(v));
+  const bool ab2 = c->integrator == 1;
+  // AB2 without N(s-1): the first step of this call is an Euler step of its own.
+  const uint32_t euler_first = ab2 && !c->have_prev ? 1u : 0u;
+  auto wts = [&](uint32_t k, const double*& ws, const double*& wg) {
+    ws = s + (size_t)k * c->n_h;
+    wg = gamma + (size_t)k * c->n_l;
+  };
 
-  // Build and check every table of the batch before launching anything.
-  std::vector<HostTable> tabs(nsteps);
-  std::vector<size_t> tbytes(nsteps);
+  // Build and check every table of the call before launching anything: step k uses A(k) (the
+  // only table for Euler) and, for AB2, B(k) from the weights of step k - 1.
+  std::vector<HostTable> tA(nsteps), tB(ab2 ? nsteps : 0);
+  std::vector<size_t> bA(nsteps), bB(ab2 ? nsteps : 0);
+  std::vector<int64_t> qsA, qsB, qs1;
+  if (shifts_q32(c, 1.0, qs1) || (ab2 && (shifts_q32(c, 1.5, qsA) || shifts_q32(c, -0.5, qsB))))
+    return fail(c, QMC_ERR_DT, "shift too large for Q32");
+  uint64_t max_qa = 0, max_qb = 0;
+  for (uint32_t r = 0; r < c->R; ++r) {
+    max_qa = std::max(max_qa, uabs(ab2 ? qsA[r] : qs1[r]));
+    if (ab2) max_qb = std::max(max_qb, uabs(qsB[r]));
+    if (euler_first) max_qa = std::max(max_qa, uabs(qs1[r]));
+  }
   for (uint32_t k = 0; k < nsteps; ++k) {
     std::string why;
-    int rc = build_table(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, tabs[k], why);
+    const double *ws, *wg;
+    wts(k, ws, wg);
+    const bool two = ab2 && k >= euler_first;
+    int rc = build_table(c, ws, wg, two ? 1.5 : 1.0, tA[k], why);
+    if (!rc && two) {
+      const double *ps, *pg;
+      if (k > 0) {
+        wts(k - 1, ps, pg);
+      } else {
+        ps = c->w_prev.data();
+        pg = c->w_prev.data() + c->n_h;
+      }
+      rc = build_table(c, ps, pg, -0.5, tB[k], why);
+      if (!rc && tB[k].q_diag + max_qb >= (1ull << 31)) {
+        rc = QMC_ERR_DT;
+        why = "diagonal group with shift violates the Q32 bound";
+      }
+    }
     if (rc) return fail(c, rc, "step " + std::to_string(c->step + k) + ": " + why);
-    if (tabs[k].q_diag + max_qs >= (1ull << 31))
+    if (tA[k].q_diag + max_qa >= (1ull << 31))
       return fail(c, QMC_ERR_DT, "diagonal group with shift violates the Q32 bound");
-    tbytes[k] = pack_table(tabs[k], nullptr);
+    bA[k] = pack_table(tA[k], nullptr);
+    if (two) bB[k] = pack_table(tB[k], nullptr);
   }
   const uint32_t first_step = c->step;
   const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
   size_t max_tbytes = 0;
-  for (size_t b : tbytes) max_tbytes = std::max(max_tbytes, b);
+  for (size_t b : bA) max_tbytes = std::max(max_tbytes, b);
+  for (size_t b : bB) max_tbytes = std::max(max_tbytes, b);
   const bool fused_fits = max_tbytes <= kPersistTableBytes;
   if (c->path == 1 && !fused_fits)
     return fail(c, QMC_ERR_ARG, "step table larger than the fused kernel takes; use the "
@@ -773,37 +865,60 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
   uint32_t last_local_fail = 0xFFFFFFFFu;
   while (c->step < first_step + nsteps) {
     const uint32_t k0 = c->step - first_step;
+    const bool two = ab2 && k0 >= euler_first;
     const bool fused = c->path == 1 || (c->path == 0 && fused_fits &&
                                         c->step >= c->streamed_until &&
                                         c->n_occ <= fused_max_keys);
+    // Shifts of this chunk's tables.
+    {
+      std::vector<int64_t> q(2 * (size_t)c->R, 0);
+      for (uint32_t r = 0; r < c->R; ++r) {
+        q[r] = two ? qsA[r] : qs1[r];
+        if (two) q[c->R + r] = qsB[r];
+      }
+      int rc = upload_qshift(c, q);
+      if (rc) return rc;
+    }
     // One launch (fused) or one stream of launches: as many of the remaining steps as fit the
-    // table area; an automatic streamed run stops where the fused kernel may be tried again.
-    uint32_t kmax = nsteps;
+    // table area; the Euler first step of AB2 runs alone; an automatic streamed run stops where
+    // the fused kernel may be tried again.
+    uint32_t kmax = two || !ab2 ? nsteps : k0 + 1;
     if (!fused && c->path == 0 && c->step < c->streamed_until)
-      kmax = std::min<uint32_t>(nsteps, c->streamed_until - first_step);
+      kmax = std::min<uint32_t>(kmax, c->streamed_until - first_step);
+    Chunk ch;
+    ch.dtab = c->at<uint8_t>(c->L.tab);
+    ch.two = two;
     size_t bytes = 0;
     uint32_t k1 = k0;
-    std::vector<uint32_t> offs;
-    while (k1 < kmax && k1 - k0 < kMaxChunkSteps && bytes + tbytes[k1] <= kTableArea) {
-      offs.push_back((uint32_t)bytes);
-      bytes += tbytes[k1];
+    while (k1 < kmax && k1 - k0 < kMaxChunkSteps &&
+           bytes + bA[k1] + (two ? bB[k1] : 0) <= kTableArea) {
+      ch.offsA.push_back((uint32_t)bytes);
+      bytes += bA[k1];
+      if (two) {
+        ch.offsB.push_back((uint32_t)bytes);
+        bytes += bB[k1];
+      }
       ++k1;
     }
     if (k1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
-    for (uint32_t k = k0; k < k1; ++k) pack_table(tabs[k], c->pinned + offs[k - k0]);
-    uint8_t* dtab = c->at<uint8_t>(c->L.tab);
-    HIPCHK(c, hipMemcpyAsync(dtab, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
+    ch.nst = k1 - k0;
+    for (uint32_t k = k0; k < k1; ++k) {
+      pack_table(tA[k], c->pinned + ch.offsA[k - k0]);
+      if (two) pack_table(tB[k], c->pinned + ch.offsB[k - k0]);
+    }
+    HIPCHK(c, hipMemcpyAsync(ch.dtab, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
     qmc::Counters hc;
     uint32_t kd = 0, reason = 0;
-    int rc;
-    if (fused) {
-      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), offs.data(), offs.size() * 4,
-                               hipMemcpyHostToDevice, c->stream));
-      rc = run_fused(c, dtab, k1 - k0, kd, reason, hc);
-    } else {
-      rc = run_streamed(c, dtab, offs, k1 - k0, kd, hc);
-    }
+    int rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);
     if (rc) return rc;
+    if (ab2 && kd > 0) {
+      // N(s-1) is now on the device; remember the weights of step s-1.
+      const double *ws, *wg;
+      wts(k0 + kd - 1, ws, wg);
+      c->w_prev.assign(ws, ws + c->n_h);
+      c->w_prev.insert(c->w_prev.end(), wg, wg + c->n_l);
+      c->have_prev = true;
+    }
     if (hc.err) {
       const uint32_t e = hc.err;
       const std::string at = "step " + std::to_string(c->step) + ": ";
@@ -841,6 +956,15 @@ int qmc_step_path(qmc_ctx* c, int32_t path) {
   return QMC_OK;
 }
 
+int qmc_set_integrator(qmc_ctx* c, int32_t integrator) {
+  if (!c || integrator < 0 || integrator > 1) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  c->integrator = integrator;
+  c->have_prev = false;
+  c->w_prev.clear();
+  return QMC_OK;
+}
+
 int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
   if (!c) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
@@ -867,16 +991,21 @@ int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
   if (rc) return rc;
   if (hc.err & qmc::kErrOverflow)
     return fail(c, QMC_ERR_COUNT_OVERFLOW, "pulse negated INT32_MIN");
+  c->have_prev = false;  // AB2 restarts after a pulse (its next step is an Euler step)
   return QMC_OK;
 }
 
 int qmc_set_shift(qmc_ctx* c, uint32_t replica, double shift) {
   if (!c || replica >= c->R || !std::isfinite(shift)) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
-  c->shift[replica] = shift;
   std::vector<int64_t> qs;
-  if (shifts_q32(c, qs)) return fail(c, QMC_ERR_DT, "shift too large for Q32");
-  return upload_qshift(c, qs);
+  const double old = c->shift[replica];
+  c->shift[replica] = shift;
+  if (shifts_q32(c, 1.5, qs)) {  // the largest factor any table uses
+    c->shift[replica] = old;
+    return fail(c, QMC_ERR_DT, "shift too large for Q32");
+  }
+  return QMC_OK;  // uploaded with the tables of the next qmc_step
 }
 
 int qmc_observe(qmc_ctx* c, const qmc_obs_spec* spec, qmc_obs_out* out) {
@@ -1047,6 +1176,89 @@ int qmc_import(qmc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t
   return QMC_OK;
 }
 
+// N(s-1) of all replicas (AB2), sorted composite keys, from the device.
+int download_prev(qmc_ctx* c, std::vector<uint64_t>& ck, std::vector<int2>& cv) {
+  uint64_t n = 0;
+  HIPCHK(c, hipMemcpyAsync(&n, &c->counters()->n_prev, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  ck.resize(n);
+  cv.resize(n);
+  if (n) {
+    HIPCHK(c, hipMemcpyAsync(ck.data(), c->pk(), n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cv.data(), c->pv(), n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return QMC_OK;
+}
+
+int qmc_set_prev(qmc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t* re,
+                 const int32_t* im, uint64_t n, const double* s_prev, const double* gamma_prev) {
+  if (!c || replica >= c->R) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (c->integrator != 1) return fail(c, QMC_ERR_ARG, "N(s-1) is only used by AB2");
+  if ((c->n_h && !s_prev) || (c->n_l && !gamma_prev))
+    return fail(c, QMC_ERR_ARG, "missing weights of step s-1");
+  std::string why;
+  int rc = check_records(c->n, keys, re, im, n, why);
+  if (rc) return fail(c, rc, why);
+  if (n > c->cfg.store_capacity) return fail(c, QMC_ERR_ARG, "more records than store capacity");
+  std::vector<uint64_t> ck;
+  std::vector<int2> cv;
+  if (c->have_prev) {
+    rc = download_prev(c, ck, cv);
+    if (rc) return rc;
+  }
+  const uint64_t tag = c->kbits >= 64 ? 0 : (uint64_t)replica << c->kbits;
+  const uint64_t hi = c->kbits >= 64 ? ~0ull : (((uint64_t)replica + 1) << c->kbits) - 1;
+  const size_t b = (size_t)(std::lower_bound(ck.begin(), ck.end(), tag) - ck.begin());
+  const size_t e = (size_t)(std::upper_bound(ck.begin(), ck.end(), hi) - ck.begin());
+  std::vector<uint64_t> nk(ck.begin(), ck.begin() + b);
+  std::vector<int2> nv(cv.begin(), cv.begin() + b);
+  for (uint64_t i = 0; i < n; ++i) {
+    nk.push_back(tag | keys[i]);
+    nv.push_back(make_int2(re[i], im[i]));
+  }
+  nk.insert(nk.end(), ck.begin() + e, ck.end());
+  nv.insert(nv.end(), cv.begin() + e, cv.end());
+  const uint64_t m = nk.size();
+  if (m) {
+    HIPCHK(c, hipMemcpyAsync(c->pk(), nk.data(), m * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pv(), nv.data(), m * 8, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(&c->counters()->n_prev, &m, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->w_prev.assign(s_prev, s_prev + c->n_h);
+  c->w_prev.insert(c->w_prev.end(), gamma_prev, gamma_prev + c->n_l);
+  c->have_prev = true;
+  return QMC_OK;
+}
+
+int qmc_export_prev(qmc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
+                    uint64_t cap, uint64_t* n) {
+  if (!c || replica >= c->R || !n) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (c->integrator != 1 || !c->have_prev) return fail(c, QMC_ERR_ARG, "no N(s-1)");
+  std::vector<uint64_t> ck;
+  std::vector<int2> cv;
+  int rc = download_prev(c, ck, cv);
+  if (rc) return rc;
+  const uint64_t lo = c->kbits >= 64 ? 0 : (uint64_t)replica << c->kbits;
+  const uint64_t hi = c->kbits >= 64 ? ~0ull : (((uint64_t)replica + 1) << c->kbits) - 1;
+  auto b = std::lower_bound(ck.begin(), ck.end(), lo);
+  auto e = std::upper_bound(ck.begin(), ck.end(), hi);
+  const uint64_t m = (uint64_t)(e - b);
+  *n = m;
+  if (m > cap) return fail(c, QMC_ERR_ARG, "export capacity too small");
+  const uint64_t kmask = c->kbits >= 64 ? ~0ull : ((1ull << c->kbits) - 1);
+  const size_t off = (size_t)(b - ck.begin());
+  for (uint64_t i = 0; i < m; ++i) {
+    keys[i] = ck[off + i] & kmask;
+    re[i] = cv[off + i].x;
+    im[i] = cv[off + i].y;
+  }
+  return QMC_OK;
+}
+
 int qmc_counters(qmc_ctx* c, qmc_stats* out) {
   if (!c || !out) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
@@ -1080,7 +1292,7 @@ int qmc_profile_read(qmc_ctx* c, double* ms, uint64_t* launches, qmc_stats* cove
 }
 
 int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double* s,
-                    const double* gamma, uint32_t cap_groups, uint32_t cap_terms,
+                    const double* gamma, double scale, uint32_t cap_groups, uint32_t cap_terms,
                     uint32_t* n_groups, uint64_t* gxmask, uint32_t* gstart, uint32_t* n_terms,
                     uint64_t* tzmask, int64_t* tq) {
   std::string why;
@@ -1091,7 +1303,8 @@ int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double*
   tmp.n = cfg->n_qubits;
   compile_model(*model, tmp.n, tmp.terms);
   HostTable T;
-  rc = build_table(&tmp, s, gamma, T, why);
+  if (!std::isfinite(scale)) return QMC_ERR_ARG;
+  rc = build_table(&tmp, s, gamma, scale, T, why);
   if (rc) return rc;
   *n_groups = (uint32_t)T.gx.size();
   *n_terms = (uint32_t)T.t.size();

@@ -84,20 +84,40 @@ struct Emitter {
   }
 };
 
-// Children of one parent (called by every lane of a wave; `valid` lanes hold a parent).
+// Children of one parent (called by every lane of a wave; `valid` lanes hold a parent), drawn
+// from Philox stream `stream`.  With `qsh` (the per-replica Q32 shifts of this table) the
+// diagonal of the column is emitted as a record of the parent's own key too (the second AB2
+// term, whose parent is N(s-1)); without it the diagonal is left to the merge, which applies
+// it to the parent itself.
 __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, bool valid,
                                              uint64_t ck, int2 v, uint32_t step, uint64_t seed,
-                                             const KeyLayout& kl) {
+                                             const KeyLayout& kl, uint32_t stream,
+                                             const int64_t* qsh) {
   const uint32_t G = tv.h->n_groups;
-  if (G <= 1) return;
   uint32_t w[4] = {0, 0, 0, 0};
-  bool active = false;
-  if (valid) {
-    walker_random(kl.key(ck), step, kl.replica(ck), seed, w);
-    active = !comb_all_zero(uabs64(v.x) + uabs64(v.y), tv.h->q_off, w[0]);
-  }
-  if (__ballot(active) == 0) return;
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+  if (valid) walker_random(kl.key(ck), step, kl.replica(ck), seed, stream, w);
   const uint64_t key = kl.key(ck);
+  if (qsh) {
+    const int64_t qs = valid ? qsh[kl.replica(ck)] : 0;
+    const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w[1]);
+    if (__ballot(dact)) {
+      int2 d = make_int2(0, 0);
+      if (dact) {
+        int32_t dre, dim;
+        group_coeff(tv.t, 0, tv.gs[1], key, dre, dim);
+        int64_t xre, xim;
+        cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
+        uint64_t r = w[1];
+        d.x = (int32_t)comb_step(r, xre);
+        d.y = (int32_t)comb_step(r, xim);
+      }
+      em.emit((d.x | d.y) != 0, ck, d);
+    }
+  }
+  if (G <= 1) return;
+  const bool active = valid && !comb_all_zero(sab, tv.h->q_off, w[0]);
+  if (__ballot(active) == 0) return;
   uint64_t r = w[0];
   for (uint32_t g = 1; g < G; ++g) {
     int2 child = make_int2(0, 0);
@@ -114,23 +134,25 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
 }
 
 // ---------------------------------------------------------------------------------------------
-// k_spawn: children of the first step of a batch (later steps spawn inside k_merge).
+// k_spawn: children of the first step of a batch from N(s) (later steps spawn inside k_merge),
+// and with AB2 the records of the second term from N(s-1) (stream 1, diagonal included).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_spawn(
     const uint64_t* __restrict__ pk, const int2* __restrict__ pv, Counters* __restrict__ cnt,
-    uint32_t cur, const uint8_t* __restrict__ tab, uint32_t step, uint64_t seed, KeyLayout kl,
+    const uint64_t* __restrict__ count, const uint8_t* __restrict__ tab, uint32_t step,
+    uint64_t seed, KeyLayout kl, uint32_t stream, const int64_t* __restrict__ qsh,
     uint64_t* __restrict__ ck_out, int2* __restrict__ cv_out, uint64_t cap_child,
     uint32_t* __restrict__ ghist, uint32_t passes) {
   __shared__ uint64_t s_key[kWaves][kSpawnSeg];
   __shared__ int2 s_val[kWaves][kSpawnSeg];
   if (cnt->err) return;
-  const uint64_t np = cnt->n_store[cur];
+  const uint64_t np = *count;
   const TableView tv = table_view(tab);
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   Emitter em{s_key[wave], s_val[wave], kSpawnSeg, 0, cnt, step & 1u, step, ck_out, cv_out,
              cap_child, ghist, passes};
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  if (tv.h->n_groups > 1) {
+  if (tv.h->n_groups > 1 || qsh) {
     for (uint64_t wbase = (uint64_t)blockIdx.x * kBlock + wave * kWave; wbase < np;
          wbase += stride) {
       const uint64_t p = wbase + lane;
@@ -141,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
         ck = pk[p];
         v = pv[p];
       }
-      spawn_parent(em, tv, valid, ck, v, step, seed, kl);
+      spawn_parent(em, tv, valid, ck, v, step, seed, kl, stream, qsh);
     }
   }
   if (em.fill) em.flush();
@@ -472,6 +494,8 @@ struct MergeArgs {
   uint32_t epoch;
   const uint8_t* tab;        // table of step s (death)
   const uint8_t* tab_next;   // table of step s+1 (spawn), or null
+  const uint8_t* tabB_next;  // AB2: table of the second term of step s+1 (from N(s)), or null
+  const int64_t* qshiftB;    // AB2: its per-replica Q32 shifts
   const int64_t* qshift;
   uint32_t step;
   uint64_t seed;
@@ -546,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       const int64_t qs = A.qshift[rep];
       int64_t a = v.x, b = v.y;
       uint32_t w[4];
-      walker_random(kl.key(ck), A.step, rep, A.seed, w);
+      walker_random(kl.key(ck), A.step, rep, A.seed, 0u, w);
       const uint64_t sab = uabs64(a) + uabs64(b);
       wsum += sab;
       if (!comb_all_zero(sab, q_diag + uabs64(qs), w[1])) {
@@ -706,7 +730,18 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         const bool valid = p < agg;
         const uint64_t ck = valid ? s_ok[p] : 0;
         const int2 v = valid ? s_ov[p] : make_int2(0, 0);
-        spawn_parent(em, tn, valid, ck, v, A.step + 1, A.seed, kl);
+        spawn_parent(em, tn, valid, ck, v, A.step + 1, A.seed, kl, 0u, nullptr);
+      }
+      if (A.tabB_next) {
+        // second AB2 term of step s+1 from this tile's parents N(s), as loaded
+        const TableView tb = table_view(A.tabB_next);
+        for (uint32_t wb = wave * kWave; wb < pn; wb += kBlock) {
+          const uint32_t p = wb + lane;
+          const bool valid = p < pn;
+          const uint64_t ck = valid ? A.pk[pa + p] : 0;
+          const int2 v = valid ? A.pv[pa + p] : make_int2(0, 0);
+          spawn_parent(em, tb, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
+        }
       }
       if (em.fill) em.flush();
     }
@@ -923,13 +958,14 @@ int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t 
   return (int)hipGetLastError();
 }
 
-int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
-               const uint8_t* tab, uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ck,
-               int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
-               uint32_t passes) {
+int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
+               const uint64_t* count, const uint8_t* tab, uint32_t step, uint64_t seed,
+               uint32_t kbits, uint32_t stream, const int64_t* qsh, uint64_t* ck, int2* cv,
+               uint64_t cap_child, uint64_t max_parents, uint32_t* ghist, uint32_t passes) {
   uint32_t g = grid_for(max_parents, 1024);
-  hipLaunchKernelGGL(k_spawn, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, cur, tab,
-                     step, seed, key_layout(kbits), ck, cv, cap_child, ghist, passes);
+  hipLaunchKernelGGL(k_spawn, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, count,
+                     tab, step, seed, key_layout(kbits), stream, qsh, ck, cv, cap_child, ghist,
+                     passes);
   return (int)hipGetLastError();
 }
 
@@ -964,9 +1000,10 @@ int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, vo
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
                uint64_t* status, const uint8_t* tab, const uint8_t* tab_next,
-               const int64_t* qshift, uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok,
-               int2* ov, uint64_t cap_store, uint64_t max_items, uint64_t* ck_next,
-               int2* cv_next, uint64_t cap_child, uint32_t* ghist_next, uint32_t passes) {
+               const uint8_t* tabB_next, const int64_t* qshift, const int64_t* qshiftB,
+               uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok, int2* ov,
+               uint64_t cap_store, uint64_t max_items, uint64_t* ck_next, int2* cv_next,
+               uint64_t cap_child, uint32_t* ghist_next, uint32_t passes) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   hipLaunchKernelGGL(k_merge_part,
                      dim3(grid_for(((uint64_t)max_tiles + 1) * kWave, 2048)), dim3(kBlock), 0,
@@ -984,6 +1021,8 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.epoch = merge_epoch(step);
   a.tab = tab;
   a.tab_next = tab_next;
+  a.tabB_next = tabB_next;
+  a.qshiftB = qshiftB;
   a.qshift = qshift;
   a.step = step;
   a.seed = seed;

@@ -10,14 +10,15 @@ constexpr uint32_t kPersistTableBytes = 8192;
 struct PersistLaunch {
   const uint64_t* ck;   // canonical store (read at batch start)
   const int2* cv;
-  uint64_t* ck_w;       // canonical store (written by the gather)
-  int2* cv_w;
+  const uint64_t* pk_prev;  // AB2: N(step0 - 1), sorted, count in counters->n_prev; else null
+  const int2* pv_prev;
   void* counters;
   uint32_t cur;
-  uint64_t* sk;         // segments [2][P][segcap]
+  uint64_t* sk;         // segments [nbuf][P][segcap]
   int2* sv;
   uint64_t segcap;
-  uint32_t* seg_n;      // [2][P]
+  uint32_t* seg_n;      // [nbuf][P]
+  uint32_t nbuf;        // 2 (Euler) or 3 (AB2: N(s) and N(s-1) survive a failed step)
   uint64_t* ik;         // inboxes [2][P][incap]
   int2* iv;
   uint32_t incap;
@@ -26,12 +27,14 @@ struct PersistLaunch {
   uint64_t* split_w;
   uint32_t P;
   const uint8_t* tab_base;
-  const uint32_t* tab_off;  // [nsteps] byte offsets of the step tables
+  const uint32_t* tab_off;   // [nsteps] byte offsets of the step tables (first / only term)
+  const uint32_t* tabB_off;  // AB2: [nsteps] offsets of the second-term tables; else null
   uint32_t step0, nsteps;
   uint64_t seed;
   uint32_t kbits;
   uint32_t n_replicas;
-  const int64_t* qshift;
+  const int64_t* qshift;     // per-replica Q32 shifts of the first / only term
+  const int64_t* qshiftB;    // AB2: of the second term
   uint64_t* slots;      // [P][4] epoch-tagged per-workgroup barrier slots (zeroed once)
   uint64_t epoch0;      // first barrier epoch of the launch
   uint64_t cap_store;
@@ -46,5 +49,8 @@ int qmcp_max_segments(int* P);
 int qmcp_prepare(hipStream_t st, const PersistLaunch* L);
 // The cooperative launch of the persistent step kernel (after qmcp_prepare).
 int qmcp_launch(hipStream_t st, const PersistLaunch* L);
-int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t par);
+// Segment buffer `buf` (N(step0 + j) after j steps is in buffer j mod nbuf) -> the sorted store
+// (out_k, out_v) with its record count written to *out_count (device pointers).
+int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t buf, uint64_t* out_k,
+                int2* out_v, uint64_t* out_count);
 }

@@ -24,7 +24,7 @@ namespace qmc {
 constexpr int kPBlock = 512;               // threads per workgroup
 constexpr int kPWaves = kPBlock / kWave;   // 8
 constexpr int kPTile = 1024;               // parents per tile (staged in LDS)
-constexpr int kActCap = 2 * kPBlock;       // block list of active new parents
+constexpr int kActCap = kPBlock + kWave;   // block list of active new parents
 constexpr int kStage = 256;                // per-wave staging of routed records
 
 struct PersistArgs {
@@ -33,11 +33,16 @@ struct PersistArgs {
   const int2* cv;
   Counters* cnt;
   uint32_t cur;
-  // segments [2][P][segcap] and counts [2][P]
+  // AB2: N(step0 - 1), sorted (its records draw the second term of step0), or null
+  const uint64_t* pk_prev;
+  const int2* pv_prev;
+  // segments [nbuf][P][segcap] and counts [nbuf][P]; pass k reads buffer k mod nbuf and
+  // writes buffer (k + 1) mod nbuf (three buffers keep N(s) and N(s-1) while N(s+1) is written)
   uint64_t* sk;
   int2* sv;
   uint64_t segcap;
   uint32_t* seg_n;
+  uint32_t nbuf;
   // inboxes [2][P][incap] and counts [2][P]
   uint64_t* ik;
   int2* iv;
@@ -49,11 +54,13 @@ struct PersistArgs {
   // per-step tables of the batch
   const uint8_t* tab_base;
   const uint32_t* tab_off;
+  const uint32_t* tabB_off;  // AB2: tables of the second term, or null (Euler)
   uint32_t step0, nsteps;
   uint64_t seed;
   KeyLayout kl;
   uint32_t n_replicas;
-  const int64_t* qshift;
+  const int64_t* qshift;    // per-replica Q32 shifts of the first term (Euler: the only one)
+  const int64_t* qshiftB;   // AB2: of the second term
   // synchronization and reporting
   uint64_t* slots;        // [P][4] per workgroup: epoch, keys out, inbox records, error bits
   uint64_t cap_store;     // total occupied keys allowed
@@ -79,7 +86,8 @@ struct Shared {
   uint64_t red[kPWaves];
   uint64_t xch[kPWaves][4];
   uint64_t dec[4];        // reduced totals of the last barrier: keys, max segment, inbox, errors
-  uint4 tab[kPersistTableBytes / 16];  // the step table of the spawns drawn in this pass
+  uint4 tab[kPersistTableBytes / 16];   // the step table of the spawns drawn in this pass
+  uint4 tabB[kPersistTableBytes / 16];  // AB2: the table of their second term
   uint32_t err;           // error bits this workgroup raised in the current step
 };
 using LTable = TableViewT<lptr>;
@@ -531,15 +539,15 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
   }
 }
 
-// Draw Philox for new parents [o0, o1) of segment buffer (seg_k, seg_v) at step `step` and
-// route their death deltas and children.  The parents that can produce a nonzero amount are
+// Draw Philox (stream `stream`) for the records [o0, o1) of (seg_k, seg_v) at step `step` and
+// route their diagonal deltas and children under table tn with shifts qsh.  The parents that can produce a nonzero amount are
 // compacted over the whole workgroup into a list, which is processed in full 64-parent batches
 // spread over the waves (a batch costs the same whatever its lane count), so a busy key range
 // needs few batches and they run on different SIMDs.  Block-uniform control flow.
 __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router& R,
-                                        const LTable& tn, const uint64_t* seg_k,
-                                        const int2* seg_v, uint64_t o0, uint64_t o1,
-                                        uint32_t step) {
+                                        const LTable& tn, const int64_t* qsh, uint32_t stream,
+                                        const uint64_t* seg_k, const int2* seg_v, uint64_t o0,
+                                        uint64_t o1, uint32_t step) {
   const uint32_t t = threadIdx.x, wave = t / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
   const uint64_t q_diag = tn.h->q_diag, q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
@@ -556,8 +564,8 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
       ck = seg_k[i];
       v = seg_v[i];
       const uint32_t rep = kl.replica(ck);
-      qs = A.qshift[rep];
-      walker_random(kl.key(ck), step, rep, A.seed, w);
+      qs = qsh[rep];
+      walker_random(kl.key(ck), step, rep, A.seed, stream, w);
       const uint64_t sab = uabs64(v.x) + uabs64(v.y);
       act = !comb_all_zero(sab, q_diag + uabs64(qs), w[1]) || !comb_all_zero(sab, q_off, w[0]);
     }
@@ -616,15 +624,17 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
 }
 
 // Merge one segment's parents (sorted, global) with its sorted inbox (LDS), sum per key,
-// write the surviving keys to the output segment, and (if `spawn`) draw the next step from them.
+// write the surviving keys to the output segment, and (if `spawn`) draw the next step from them
+// (and, if `spawnB`, the next step's second AB2 term from the parents).
 // The parents go through LDS in tiles of kPTile; each tile takes the inbox records up to its last
 // parent (the last tile takes the rest), and the merged items of the tile are split evenly over
 // the threads by a merge-path search that never cuts a key's run.  Returns the number of keys
 // written in S.red[0] and the walker sum of the parents in S.red[1] (block-uniform).
 __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, const uint64_t* pk,
                                               const int2* pv, uint64_t np, uint32_t c, uint64_t* ok,
-                                              int2* ov, uint32_t step, bool spawn, Router R,
-                                              const LTable tn, uint32_t nstep) {
+                                              int2* ov, uint32_t step, bool spawn, bool spawnB,
+                                              Router R, const LTable tn, const LTable tnB,
+                                              uint32_t nstep) {
   const uint32_t t = threadIdx.x;
   uint64_t out_run = 0;   // block-uniform
   uint64_t wsum = 0;
@@ -722,7 +732,10 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
     out_run = o0 + agg;
     jb = je;
     __syncthreads();  // this tile's outputs are visible to the whole workgroup
-    if (spawn && o0 + agg <= A.segcap) advance(A, S, R, tn, ok, ov, o0, o0 + agg, nstep);
+    if (spawn && o0 + agg <= A.segcap)
+      advance(A, S, R, tn, A.qshift, 0u, ok, ov, o0, o0 + agg, nstep);
+    // AB2: the second term of the next step from this tile's parents N(s)
+    if (spawnB) advance(A, S, R, tnB, A.qshiftB, 1u, pk + f, pv + f, 0, pn, nstep);
     __syncthreads();
   }
   // block reduction of the walker sum
@@ -756,14 +769,21 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     const uint64_t n_can = cnt->n_store[A.cur];
     S.red[0] = lower_bound_glb(A.ck, n_can, A.split[p]);
     S.red[1] = p + 1 < P ? lower_bound_glb(A.ck, n_can, A.split[p + 1]) : n_can;
+    // and of N(step0 - 1) (AB2)
+    const uint64_t n_prev = A.pk_prev ? cnt->n_prev : 0;
+    S.red[2] = A.pk_prev ? lower_bound_glb(A.pk_prev, n_prev, A.split[p]) : 0;
+    S.red[3] = A.pk_prev && p + 1 < P ? lower_bound_glb(A.pk_prev, n_prev, A.split[p + 1])
+                                      : n_prev;
   }
   __syncthreads();
-  const uint64_t cb = S.red[0], ce = S.red[1];
+  const uint64_t cb = S.red[0], ce = S.red[1], qb = S.red[2], qe = S.red[3];
   __syncthreads();
 
   // Pass k = -1 merges the canonical slice with an empty inbox into segment buffer 0 and draws
-  // step0 from it; pass k >= 0 is step step0 + k: segment buffer k & 1 and inbox parity k & 1
-  // in, buffer and parity (k & 1) ^ 1 out.
+  // step0 from it (and, with AB2, the second term of step0 from N(step0 - 1)); pass k >= 0 is
+  // step step0 + k: segment buffer k mod nbuf and inbox parity k & 1 in, buffer (k + 1) mod nbuf
+  // and parity (k & 1) ^ 1 out, and draws step s + 1 from its outputs (first AB2 term) and its
+  // parents (second term).
   uint64_t epoch = A.epoch0 - 1;
   uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
   uint32_t reason = 0, kdone = A.nsteps;
@@ -780,10 +800,17 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     const uint64_t* ibk = A.ik + ((uint64_t)par * P + p) * A.incap;
     const int2* ibv = A.iv + ((uint64_t)par * P + p) * A.incap;
     const bool last = k + 1 == (int32_t)A.nsteps;
-    // table of the spawns drawn in this pass (step s + 1; step0 on the first pass) -> LDS
+    const uint32_t ob = (uint32_t)(k + 1) % A.nbuf, ib = (ob + A.nbuf - 1) % A.nbuf;
+    // tables of the spawns drawn in this pass (step s + 1; step0 on the first pass) -> LDS
     const uint4* tg = reinterpret_cast<const uint4*>(A.tab_base + A.tab_off[last ? k : k + 1]);
     const uint32_t tw = reinterpret_cast<const TableHeader*>(tg)->bytes / 16;
     for (uint32_t i = t; i < tw; i += kPBlock) S.tab[i] = tg[i];
+    const bool two = A.tabB_off && !last && (!first || A.pk_prev);
+    if (two) {
+      const uint4* tb = reinterpret_cast<const uint4*>(A.tab_base + A.tabB_off[k + 1]);
+      const uint32_t tbw = reinterpret_cast<const TableHeader*>(tb)->bytes / 16;
+      for (uint32_t i = t; i < tbw; i += kPBlock) S.tabB[i] = tb[i];
+    }
     for (uint32_t i = t; i < m2; i += kPBlock) {
       S.in_k[i] = i < c ? ld_agent(&ibk[i]) : ~0ull;
       S.in_v[i] = i < c ? ld_agent(&ibv[i]) : make_int2(0, 0);
@@ -792,19 +819,25 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     if (t == 0) st_agent(&A.in_n[par * P + p], 0u);  // refilled during pass k+1 (for k+2)
     if (c > 1) sort_inbox(S, m2, c, packed);  // the c real records first, then the padding
     // parents: the canonical slice, or the segment written by the previous pass
-    const uint64_t np_k = first ? ce - cb : A.seg_n[par * P + p];
-    const uint64_t* pk = first ? A.ck + cb : A.sk + ((uint64_t)par * P + p) * A.segcap;
-    const int2* pv = first ? A.cv + cb : A.sv + ((uint64_t)par * P + p) * A.segcap;
-    uint64_t* okp = A.sk + ((uint64_t)(par ^ 1u) * P + p) * A.segcap;
-    int2* ovp = A.sv + ((uint64_t)(par ^ 1u) * P + p) * A.segcap;
+    const uint64_t np_k = first ? ce - cb : A.seg_n[ib * P + p];
+    const uint64_t* pk = first ? A.ck + cb : A.sk + ((uint64_t)ib * P + p) * A.segcap;
+    const int2* pv = first ? A.cv + cb : A.sv + ((uint64_t)ib * P + p) * A.segcap;
+    uint64_t* okp = A.sk + ((uint64_t)ob * P + p) * A.segcap;
+    int2* ovp = A.sv + ((uint64_t)ob * P + p) * A.segcap;
     const uint32_t nstep = first ? A.step0 : s + 1;
     const LTable tn = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab));
+    const LTable tnB = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tabB));
     Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, nstep, &S.err,
              S.st_k[t / kWave], S.st_v[t / kWave], 0u};
-    merge_segment(A, S, pk, pv, np_k, c, okp, ovp, s, !last, R, tn, nstep);
+    merge_segment(A, S, pk, pv, np_k, c, okp, ovp, s, !last, two && !first, R, tn, tnB, nstep);
     const uint64_t nout = S.red[0], wsum = S.red[1];
+    if (two && first) {
+      // the second AB2 term of step0 from this range of N(step0 - 1)
+      advance(A, S, R, tnB, A.qshiftB, 1u, A.pk_prev + qb, A.pv_prev + qb, 0, qe - qb, nstep);
+      __syncthreads();
+    }
     if (t == 0) {
-      A.seg_n[(par ^ 1u) * P + p] = (uint32_t)(nout <= A.segcap ? nout : 0);
+      A.seg_n[ob * P + p] = (uint32_t)(nout <= A.segcap ? nout : 0);
       if (!first) {
         st_w += wsum;
         st_k += np_k;
@@ -869,20 +902,21 @@ __global__ void k_persist_prep(Counters* cnt, uint32_t* in_n, uint32_t P, uint32
   }
 }
 
-// Segments of buffer `par` -> canonical store (concatenation in segment order is sorted).
+// Segments of buffer `par` -> a sorted store (concatenation in segment order is sorted) whose
+// record count goes to *count.
 __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ sk,
                                                 const int2* __restrict__ sv,
                                                 const uint32_t* __restrict__ seg_n, uint32_t par,
                                                 uint32_t P, uint64_t segcap,
                                                 uint64_t* __restrict__ ck, int2* __restrict__ cv,
-                                                Counters* __restrict__ cnt, uint32_t cur) {
+                                                uint64_t* __restrict__ count) {
   __shared__ uint64_t s_off;
   const uint32_t p = blockIdx.x;
   if (threadIdx.x == 0) {
     uint64_t o = 0;
     for (uint32_t q = 0; q < p; ++q) o += seg_n[par * P + q];
     s_off = o;
-    if (p == P - 1) cnt->n_store[cur] = o + seg_n[par * P + p];
+    if (p == P - 1) *count = o + seg_n[par * P + p];
   }
   __syncthreads();
   const uint64_t off = s_off;
@@ -901,6 +935,11 @@ PersistArgs make_args(const PersistLaunch* L) {
   a.cv = L->cv;
   a.cnt = (Counters*)L->counters;
   a.cur = L->cur;
+  a.pk_prev = L->pk_prev;
+  a.pv_prev = L->pv_prev;
+  a.nbuf = L->nbuf;
+  a.tabB_off = L->tabB_off;
+  a.qshiftB = L->qshiftB;
   a.sk = L->sk;
   a.sv = L->sv;
   a.segcap = L->segcap;
@@ -965,9 +1004,10 @@ int qmcp_launch(hipStream_t st, const PersistLaunch* L) {
   return (int)hipGetLastError();
 }
 
-int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t par) {
-  hipLaunchKernelGGL(k_gather, dim3(L->P), dim3(256), 0, st, L->sk, L->sv, L->seg_n, par, L->P,
-                     L->segcap, L->ck_w, L->cv_w, (Counters*)L->counters, L->cur);
+int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t buf, uint64_t* out_k,
+                int2* out_v, uint64_t* out_count) {
+  hipLaunchKernelGGL(k_gather, dim3(L->P), dim3(256), 0, st, L->sk, L->sv, L->seg_n, buf, L->P,
+                     L->segcap, out_k, out_v, out_count);
   return (int)hipGetLastError();
 }
 

@@ -1,0 +1,191 @@
+"""GPU parity of the AB2 integrator (End Matter on simulation methodology) against the oracle.
+
+N(s+1) = N(s) + round(3/2 dt L(t_s) N(s)) + round(-1/2 dt L(t_{s-1}) N(s-1)), first step Euler.
+Whole per-replica stores are compared bit for bit (and N(s-1) where it matters), on both step
+paths; both sides run their own trajectories from the same initial records.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2502_18929_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+PATHS = ["fused", "streamed"]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_18929_amd import binding
+    binding.lib()
+    return binding
+
+
+def _pair(B, orc, w, store, spawn, path, R=None, seed=None):
+    R = w.n_replicas if R is None else R
+    seed = w.seed if seed is None else seed
+    g = B.QMC.from_workload(w, store_capacity=store, spawn_capacity=spawn, n_replicas=R,
+                            seed=seed)
+    g.set_path(path)
+    g.set_integrator("ab2")
+    o = orc.Oracle(w.n, R, seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im,
+                   integrator="ab2")
+    return g, o
+
+
+def _same(x, y, where):
+    for a, b in zip(x, y):
+        if not np.array_equal(a, b):
+            raise AssertionError(f"{where}: sizes {len(x[0])} / {len(y[0])}")
+
+
+def _assert_same(g, o, R, where, prev=False):
+    for r in range(R):
+        _same(g.export(r), o.export(r), f"{where} replica {r}")
+        if prev:
+            _same(g.export_prev(r), o.export_prev(r), f"{where} N(s-1) replica {r}")
+
+
+def _run_both(g, o, w, start, stop):
+    for a, b, pulses in w.segments():
+        if b <= start or a >= stop:
+            continue
+        if a >= start:
+            for (px, pz) in pulses:
+                g.pulse(px, pz)
+                o.pulse(px, pz)
+        lo, hi = max(a, start), min(b, stop)
+        g.step(w.s[lo:hi], w.gamma[lo:hi])
+        o.step(w.s[lo:hi], w.gamma[lo:hi])
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("seed", range(4))
+def test_ab2_random_models_every_step(B, orc, seed, path):
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(1, 5))
+    h, lops = W.random_model(n, rng, n_h=int(rng.integers(1, 6)), n_l=int(rng.integers(0, 4)))
+    keys, re, im = W.random_records(n, rng, int(rng.integers(1, 12)), scale=3000)
+    R = int(rng.integers(1, 5))
+    dt = 0.01
+    _say(f"AB2 random model seed={seed} n={n} R={R} keys={len(keys)} path={path}")
+    g = B.QMC(n, R, 2000 + seed, dt, h, lops, keys, re, im, store_capacity=1 << (2 * n),
+              spawn_capacity=8192)
+    g.set_path(path)
+    g.set_integrator("ab2")
+    o = orc.Oracle(n, R, 2000 + seed, dt, h, lops, keys, re, im, integrator="ab2")
+    s = rng.normal(size=(30, len(h))) * 0.5
+    gam = np.abs(rng.normal(size=(30, len(lops)))) * 0.5
+    for k in range(30):
+        g.step(s[k:k + 1], gam[k:k + 1])
+        o.step(s[k:k + 1], gam[k:k + 1])
+        _assert_same(g, o, R, f"step {k}", prev=(k % 7 == 0))
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_ab2_ghz4_full_trajectory(B, orc, path):
+    w = W.config_ghz4()
+    _say(f"AB2 {w.name}: {w.nsteps} steps, {path}")
+    g, o = _pair(B, orc, w, 256, 8192, path)
+    for k0 in range(0, w.nsteps, 25):
+        _run_both(g, o, w, k0, k0 + 25)
+        _assert_same(g, o, w.n_replicas, f"step {k0 + 25}", prev=True)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_ab2_dd_small_with_pulses(B, orc, path):
+    """DD with ideal pulses: every pulse restarts the two-step formula with an Euler step."""
+    w = W.dd(n=6, n_replicas=4, walker_target=20000, nsteps=800, seed=11)
+    _say(f"AB2 dd n=6: {w.nsteps} steps with pulses, {path}")
+    g, o = _pair(B, orc, w, 4096, 1 << 17, path)
+    for k0 in range(0, w.nsteps, 100):
+        _run_both(g, o, w, k0, k0 + 100)
+        _assert_same(g, o, w.n_replicas, f"step {k0 + 100}")
+
+
+@pytest.mark.parametrize("path", ["auto", "streamed"])
+def test_ab2_ghz20_nm_full_size(B, orc, path):
+    """n=20 non-Markovian GHZ at full size (8 replicas x 1e7 walkers), all 3000 AB2 steps,
+    every replica compared every 250 steps."""
+    w = W.config_ghz20_nm()
+    _say(f"AB2 {w.name}: full size, {path}")
+    g, o = _pair(B, orc, w, 1 << 17, 1 << 20, path)
+    for k0 in range(0, w.nsteps, 250):
+        g.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250])
+        o.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250], threads=16)
+        _assert_same(g, o, w.n_replicas, f"step {k0 + 250}")
+        _say(f"  step {k0 + 250} equal")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_ab2_resume_with_prev(B, orc, path):
+    """Export N(s) and N(s-1) at step 150, resume a new context from them: identical to an
+    uninterrupted run."""
+    w = W.config_ghz4()
+    a, _ = _pair(B, orc, w, 256, 8192, path)
+    a.step(w.s[:300], w.gamma[:300])
+    b, _ = _pair(B, orc, w, 256, 8192, path)
+    b.step(w.s[:150], w.gamma[:150])
+    c, _ = _pair(B, orc, w, 256, 8192, path)
+    for r in range(w.n_replicas):
+        c.import_(r, *b.export(r), step=150)
+        c.set_prev(r, *b.export_prev(r), w.s[149], w.gamma[149])
+    c.step(w.s[150:300], w.gamma[150:300])
+    for r in range(w.n_replicas):
+        _same(a.export(r), c.export(r), f"replica {r}")
+        _same(a.export_prev(r), c.export_prev(r), f"N(s-1) replica {r}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_ab2_spawn_capacity_error_rolls_back(B, orc, path):
+    """A capacity error mid-batch leaves N(s) and N(s-1) of the last good step; resuming from
+    them with enough capacity gives the uninterrupted trajectory."""
+    w = W.config_ghz4()
+    g, _ = _pair(B, orc, w, 256, 24, path)
+    with pytest.raises(B.QMCError) as e:
+        g.step(w.s[:120], w.gamma[:120])
+    assert e.value.code == B.QMC_ERR_SPAWN_CAP
+    st = g.counters()["step"]
+    _say(f"spawn capacity error at step {st}")
+    assert st >= 1
+    cur = [g.export(r) for r in range(w.n_replicas)]
+    prev = [g.export_prev(r) for r in range(w.n_replicas)]
+    big, _ = _pair(B, orc, w, 256, 8192, path)
+    for r in range(w.n_replicas):
+        big.import_(r, *cur[r], step=st)
+        big.set_prev(r, *prev[r], w.s[st - 1], w.gamma[st - 1])
+    big.step(w.s[st:130], w.gamma[st:130])
+    ref, _ = _pair(B, orc, w, 256, 8192, path)
+    ref.step(w.s[:130], w.gamma[:130])
+    for r in range(w.n_replicas):
+        _same(big.export(r), ref.export(r), f"replica {r}")
+
+
+def test_ab2_auto_path_falls_back_to_streamed(B, orc):
+    """Every key of n=8 occupied under 66 column groups: the fused kernel's key ranges overflow
+    and the automatic path runs the AB2 steps streamed."""
+    rng = np.random.default_rng(21)
+    n, R = 8, 2
+    h, lops = W.random_model(n, rng, n_h=24, n_l=4)
+    keys = np.arange(1 << (2 * n), dtype=np.uint64)
+    re = rng.integers(-3000, 3000, size=len(keys)).astype(np.int32)
+    im = rng.integers(-3000, 3000, size=len(keys)).astype(np.int32)
+    re[(re == 0) & (im == 0)] = 1
+    s = rng.normal(size=(3, len(h)))
+    gam = np.abs(rng.normal(size=(3, len(lops))))
+    g = B.QMC(n, R, 5, 0.01, h, lops, keys, re, im, store_capacity=1 << 17,
+              spawn_capacity=1 << 24)
+    g.set_integrator("ab2")
+    o = orc.Oracle(n, R, 5, 0.01, h, lops, keys, re, im, integrator="ab2")
+    g.step(s, gam)
+    o.step(s, gam, threads=8)
+    _assert_same(g, o, R, "after 3 steps", prev=True)

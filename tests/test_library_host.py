@@ -31,15 +31,17 @@ def _tables_equal(a, b):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("scale", [1.0, 1.5, -0.5])
 @pytest.mark.parametrize("cfg", ["ghz4", "dd12", "ghz20_nm"])
-def test_coeff_tables_match_oracle_on_configs(orc, cfg):
+def test_coeff_tables_match_oracle_on_configs(orc, cfg, scale):
+    """Euler tables (scale 1) and the two AB2 tables (3/2, -1/2), bit for bit."""
     w = W.CONFIGS[cfg]()
     o = orc.Oracle(w.n, 1, 1, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
     idx = sorted(set([0, 1, w.nsteps // 3, w.nsteps // 2, w.nsteps - 1] +
                      list(range(0, w.nsteps, max(1, w.nsteps // 25)))))
     for k in idx:
-        a = binding.coeff_table(w.n, w.dt, w.h, w.lops, w.s[k], w.gamma[k])
-        b = o.table(w.s[k], w.gamma[k])
+        a = binding.coeff_table(w.n, w.dt, w.h, w.lops, w.s[k], w.gamma[k], scale=scale)
+        b = o.table(w.s[k], w.gamma[k], scale=scale)
         _tables_equal(a, b)
 
 

@@ -70,13 +70,13 @@ def profiled_traffic(kind, workload):
     return float(b.group(1))
 
 
-def cpu_baseline(w, budget_s=20.0):
+def cpu_baseline(w, integrator="euler", budget_s=20.0):
     """The CPU oracle, untuned, on the host cores over the first steps of the same workload
     (about budget_s seconds of work); reports walker-steps/s."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     o = oracle.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
-                      w.init_im)
+                      w.init_im, integrator=integrator)
     t0 = time.perf_counter()
     done, used = 0, 1
     chunk = 50
@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="ghz20_nm", choices=["ghz20_nm", "dd12", "ghz4"])
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "streamed"])
+    ap.add_argument("--integrator", default="euler", choices=["euler", "ab2"],
+                    help="time integrator (End Matter on simulation methodology)")
     ap.add_argument("--roofline-kernel", default=None, choices=list(KERNEL_NAMES),
                     help="kernel class timed for the roofline (default: the workload's "
                          "dominant kernel)")
@@ -127,12 +129,14 @@ def main():
     torch.cuda.set_device(0)
     g = binding.QMC.from_workload(w, store_capacity=store_cap, spawn_capacity=spawn_cap)
     g.set_path(args.path)
+    g.set_integrator(args.integrator)
     init = [g.export(r) for r in range(w.n_replicas)]
 
     # warmup: W steps from the initial state, then restore the initial state (untimed)
     g.run_workload(w, 0, Wm)
     for r in range(w.n_replicas):
         g.import_(r, *init[r], step=0)
+    g.set_integrator(args.integrator)  # forget the warmup's N(s-1): the run starts at step 0
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib << 18  # float32 elements
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -179,6 +183,7 @@ def main():
                         f"walkers, dt={w.dt}, {w.nsteps} steps",
             "n_qubits": w.n, "replicas": w.n_replicas, "walker_target": w.walker_target,
             "dt": w.dt, "steps_timed": K, "step_path": args.path,
+            "integrator": args.integrator,
             "parallelism": "1 GPU, replicas batched in one store",
         },
         "key_steps_per_s": key_steps / elapsed,
@@ -194,7 +199,7 @@ def main():
                   "trace_mean": float(obs["trace"].mean())},
     }
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(w)
+        res["cpu_baseline"] = cpu_baseline(w, args.integrator)
     g.close()
     print(json.dumps(res), flush=True)
 

@@ -20,6 +20,7 @@ constexpr int kMergeSlack = kMaxGroups + 1;  // a key's run of children is at mo
 constexpr int kMergeCap = kMergeTile + kMergeSlack + 8;
 constexpr int kSpawnSeg = 512;       // per-wave LDS staging of child records in k_spawn
 constexpr int kMergeSpawnSeg = 256;  // the same inside the merge (aliases the child tile)
+constexpr int kMergeActive = kBlock + kWave;  // merge queue of active outputs: < 64 + one chunk
 constexpr int kRadixBits = 11;       // digit width of the onesweep passes
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 6;        // ceil(64 / 11)

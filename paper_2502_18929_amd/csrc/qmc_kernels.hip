@@ -133,6 +133,32 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
   }
 }
 
+// Children of up to 64 active parents (lane < n holds one; w0 is its spawn comb word, drawn when
+// the parent was queued), every lane of the wave calling.
+__device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, const uint64_t* ak,
+                                            const int2* av, const uint32_t* aw, uint32_t n,
+                                            const KeyLayout& kl) {
+  const uint32_t lane = __lane_id();
+  const bool act = lane < n;
+  const uint64_t ck = act ? ak[lane] : 0;
+  const int2 v = act ? av[lane] : make_int2(0, 0);
+  uint64_t r = act ? aw[lane] : 0;
+  const uint64_t key = kl.key(ck);
+  const uint32_t G = tv.h->n_groups;
+  for (uint32_t g = 1; g < G; ++g) {
+    int2 child = make_int2(0, 0);
+    if (act) {
+      int32_t cre, cim;
+      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      child.x = (int32_t)comb_step(r, xre);
+      child.y = (int32_t)comb_step(r, xim);
+    }
+    em.emit((child.x | child.y) != 0, ck ^ tv.gx[g], child);
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // k_spawn: children of the first step of a batch from N(s) (later steps spawn inside k_merge),
 // and with AB2 the records of the second term from N(s-1) (stream 1, diagonal included).
@@ -523,6 +549,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base;
   __shared__ uint64_t s_ws[kWaves];
+  // Outputs that can spawn in step s+1, queued across tiles and spawned in full 64-lane batches
+  // (a batch costs the same whatever its lane count, and sparse columns leave most lanes idle).
+  __shared__ uint64_t s_ak[kMergeActive];
+  __shared__ int2 s_av[kMergeActive];
+  __shared__ uint32_t s_aw[kMergeActive];
   static_assert(kWaves * kMergeSpawnSeg <= CAP, "spawn staging must fit the child tile");
 
   Counters* cnt = A.cnt;
@@ -540,6 +571,42 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   const uint64_t q_diag = tv.h->q_diag;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
+  uint32_t nl = 0;  // queued active outputs (block-uniform)
+  // Spawns the first nb * 64 queued outputs (at most nl) with the staging of the child tile,
+  // then moves the rest to the front of the queue.  Block-uniform; ends with the queue stable.
+  auto drain = [&](uint32_t nb) __attribute__((always_inline)) {
+    if (nb > 0) {
+      const TableView tn = table_view(A.tab_next);
+      Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
+                 cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child, A.ghist_next,
+                 A.passes};
+      for (uint32_t b = wave; b < nb; b += kWaves) {
+        const uint32_t b0 = b * kWave;
+        spawn_batch(em, tn, s_ak + b0, s_av + b0, s_aw + b0,
+                    nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl);
+      }
+      if (em.fill) em.flush();
+    }
+    const uint32_t done = nb * kWave < nl ? nb * kWave : nl;
+    const uint32_t rest = nl - done;
+    __syncthreads();
+    uint64_t rk = 0;
+    int2 rv = make_int2(0, 0);
+    uint32_t rw = 0;
+    if (threadIdx.x < rest) {
+      rk = s_ak[done + threadIdx.x];
+      rv = s_av[done + threadIdx.x];
+      rw = s_aw[done + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x < rest) {
+      s_ak[threadIdx.x] = rk;
+      s_av[threadIdx.x] = rv;
+      s_aw[threadIdx.x] = rw;
+    }
+    nl = rest;
+    __syncthreads();
+  };
 
   while (true) {
     if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->tile_counter, 1u);
@@ -719,22 +786,49 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     }
     __syncthreads();
 
-    // Children of step s+1 from the outputs of this tile (the staging aliases the child tile).
+    // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
+    // that can spawn go to the queue; full batches are spawned when it fills.
     if (A.tab_next) {
       const TableView tn = table_view(A.tab_next);
-      Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
-                 cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child, A.ghist_next,
-                 A.passes};
-      for (uint32_t wb = wave * kWave; wb < agg; wb += kBlock) {
-        const uint32_t p = wb + lane;
-        const bool valid = p < agg;
-        const uint64_t ck = valid ? s_ok[p] : 0;
-        const int2 v = valid ? s_ov[p] : make_int2(0, 0);
-        spawn_parent(em, tn, valid, ck, v, A.step + 1, A.seed, kl, 0u, nullptr);
+      const uint64_t q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
+      for (uint32_t base = 0; base < agg; base += kBlock) {
+        const uint32_t p = base + threadIdx.x;
+        bool act = false;
+        uint64_t ck = 0;
+        int2 v = make_int2(0, 0);
+        uint32_t w[4] = {0, 0, 0, 0};
+        if (p < agg) {
+          ck = s_ok[p];
+          v = s_ov[p];
+          walker_random(kl.key(ck), A.step + 1, kl.replica(ck), A.seed, 0u, w);
+          act = !comb_all_zero(uabs64(v.x) + uabs64(v.y), q_off, w[0]);
+        }
+        const uint64_t m = __ballot(act);
+        if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
+          const uint32_t c2 = s_scan[x];
+          off += x < wave ? c2 : 0u;
+          tot += c2;
+        }
+        __syncthreads();
+        if (nl + tot > (uint32_t)kMergeActive) drain(nl / kWave);
+        if (act) {
+          const uint32_t at = nl + off + mbcnt64(m);
+          s_ak[at] = ck;
+          s_av[at] = v;
+          s_aw[at] = w[0];
+        }
+        nl += tot;
+        __syncthreads();
       }
       if (A.tabB_next) {
         // second AB2 term of step s+1 from this tile's parents N(s), as loaded
         const TableView tb = table_view(A.tabB_next);
+        Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg,
+                   0, cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child,
+                   A.ghist_next, A.passes};
         for (uint32_t wb = wave * kWave; wb < pn; wb += kBlock) {
           const uint32_t p = wb + lane;
           const bool valid = p < pn;
@@ -742,11 +836,13 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           const int2 v = valid ? A.pv[pa + p] : make_int2(0, 0);
           spawn_parent(em, tb, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
         }
+        if (em.fill) em.flush();
       }
-      if (em.fill) em.flush();
     }
     __syncthreads();
   }
+  // the rest of the queue (block-uniform: every thread left the tile loop together)
+  if (A.tab_next && nl > 0) drain((nl + kWave - 1) / kWave);
 }
 
 // ---------------------------------------------------------------------------------------------

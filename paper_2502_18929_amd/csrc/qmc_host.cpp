@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/qmc.h"
@@ -25,6 +26,7 @@ constexpr uint32_t kMaxPauli = 256;
 constexpr uint32_t kMaxLookup = 4096;
 constexpr size_t kTableArea = 8u << 20;   // device bytes for the step tables of one chunk
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
+constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -234,15 +236,24 @@ void compile_model(const qmc_model& m, uint32_t n, std::vector<SrcTerm>& out) {
       }
     }
   }
+  // Terms of equal (xmask, zmask) adjacent, diagonal first: a step table then merges runs by
+  // integer addition (order-free) without sorting again.
+  std::stable_sort(out.begin(), out.end(), [](const SrcTerm& a, const SrcTerm& b) {
+    return a.xmask != b.xmask ? a.xmask < b.xmask : a.zmask < b.zmask;
+  });
 }
 
 // Q32 of scale * dt * w * kappa0: the product w * kappa0 first, then dt, then the integrator's
 // factor (1 for Euler; 3/2 and -1/2 for the two AB2 terms), exact scaling by 2^32, round half to
 // even.
 bool quantize(double dt, double w, double k, double scale, int64_t& q) {
-  const double v = std::ldexp(scale * (dt * (w * k)), 32);
-  if (!std::isfinite(v) || std::fabs(v) >= 4611686018427387904.0) return false;
-  q = (int64_t)std::llrint(v);
+  // multiplying by 2^32 is exact (as ldexp); |v| < 2^51 rounds half to even by adding and
+  // subtracting 1.5 * 2^52 in the default rounding mode, larger values go through llrint
+  const double v = scale * (dt * (w * k)) * 4294967296.0;
+  if (!(std::fabs(v) < 4611686018427387904.0)) return false;  // also NaN and infinities
+  constexpr double kMagic = 6755399441055744.0;
+  q = std::fabs(v) < 2251799813685248.0 ? (int64_t)((v + kMagic) - kMagic)
+                                         : (int64_t)std::llrint(v);
   return true;
 }
 
@@ -258,32 +269,28 @@ struct HostTable {
 
 int build_table(const qmc_ctx* c, const double* s, const double* g, double scale,
                 HostTable& T, std::string& why) {
-  std::vector<QTerm> q;
-  q.reserve(c->terms.size());
-  for (const SrcTerm& st : c->terms) {
-    const double w = st.weight_kind == 0 ? s[st.weight_index] : g[st.weight_index];
-    if (!std::isfinite(w)) {
-      why = "non-finite weight";
-      return QMC_ERR_ARG;
-    }
-    QTerm qt{st.xmask, st.zmask, 0, 0};
-    if (!quantize(c->cfg.dt, w, st.kre, scale, qt.qre) ||
-        !quantize(c->cfg.dt, w, st.kim, scale, qt.qim)) {
-      why = "coefficient too large for Q32";
-      return QMC_ERR_DT;
-    }
-    q.push_back(qt);
-  }
-  std::sort(q.begin(), q.end(), [](const QTerm& a, const QTerm& b) {
-    return a.xmask != b.xmask ? a.xmask < b.xmask : a.zmask < b.zmask;
-  });
+  // c->terms is sorted by (xmask, zmask): each run of equal terms is one merged Q32 term.
+  const std::vector<SrcTerm>& src = c->terms;
   T.t.clear();
-  for (size_t i = 0; i < q.size();) {
-    QTerm acc = q[i];
-    size_t j = i + 1;
-    for (; j < q.size() && q[j].xmask == acc.xmask && q[j].zmask == acc.zmask; ++j) {
-      acc.qre += q[j].qre;
-      acc.qim += q[j].qim;
+  T.t.reserve(src.size());
+  for (size_t i = 0; i < src.size();) {
+    QTerm acc{src[i].xmask, src[i].zmask, 0, 0};
+    size_t j = i;
+    for (; j < src.size() && src[j].xmask == acc.xmask && src[j].zmask == acc.zmask; ++j) {
+      const SrcTerm& st = src[j];
+      const double w = st.weight_kind == 0 ? s[st.weight_index] : g[st.weight_index];
+      if (!std::isfinite(w)) {
+        why = "non-finite weight";
+        return QMC_ERR_ARG;
+      }
+      int64_t qre, qim;
+      if (!quantize(c->cfg.dt, w, st.kre, scale, qre) ||
+          !quantize(c->cfg.dt, w, st.kim, scale, qim)) {
+        why = "coefficient too large for Q32";
+        return QMC_ERR_DT;
+      }
+      acc.qre += qre;
+      acc.qim += qim;
     }
     if (acc.qre != 0 || acc.qim != 0) T.t.push_back(acc);
     i = j;
@@ -725,7 +732,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
   HIPCHK(c, mark(0, 0, 0));
   HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab + ch.offsA[0],
-                       step0, c->cfg.seed, c->kbits, 0u, nullptr, c->ck(cb), c->cv(cb),
+                       step0, c->cfg.seed, c->kbits, 0u, qshA, c->ck(cb), c->cv(cb),
                        c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
   if (ch.two)
     HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab + ch.offsB[0],
@@ -734,7 +741,6 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   HIPCHK(c, mark(0, 0, 1));
   for (uint32_t k = 0; k < nst; ++k) {
     const uint32_t st = step0 + k, b = k % nb, cur = cur0 ^ (k & 1u);
-    const uint8_t* tab = dtab + ch.offsA[k];
     const bool more = k + 1 < nst;
     const uint8_t* tab_next = more ? dtab + ch.offsA[k + 1] : nullptr;
     const uint8_t* tabB_next = more && c->integrator == 1 ? dtab + ch.offsB[k + 1] : nullptr;
@@ -747,7 +753,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     const uint32_t cf = cb ^ (passes & 1);  // sorted children
     HIPCHK(c, mark(2, k, 0));
     HIPCHK(c, qmck_merge(c->stream, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
-                         c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), tab, tab_next,
+                         c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), tab_next,
                          tabB_next, qshA, qshB, st, c->cfg.seed, c->kbits, bk[(k + 1) % nb],
                          bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
                          c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
@@ -827,31 +833,66 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     if (ab2) max_qb = std::max(max_qb, uabs(qsB[r]));
     if (euler_first) max_qa = std::max(max_qa, uabs(qs1[r]));
   }
-  for (uint32_t k = 0; k < nsteps; ++k) {
-    std::string why;
-    const double *ws, *wg;
-    wts(k, ws, wg);
-    const bool two = ab2 && k >= euler_first;
-    int rc = build_table(c, ws, wg, two ? 1.5 : 1.0, tA[k], why);
-    if (!rc && two) {
-      const double *ps, *pg;
-      if (k > 0) {
-        wts(k - 1, ps, pg);
-      } else {
-        ps = c->w_prev.data();
-        pg = c->w_prev.data() + c->n_h;
+  // Steps [k0, k1): returns the first failing step (with its code and message) or k1.
+  auto build_range = [&](uint32_t k0, uint32_t k1, int& rc_out, std::string& why) -> uint32_t {
+    for (uint32_t k = k0; k < k1; ++k) {
+      const double *ws, *wg;
+      wts(k, ws, wg);
+      const bool two = ab2 && k >= euler_first;
+      int rc = build_table(c, ws, wg, two ? 1.5 : 1.0, tA[k], why);
+      if (!rc && two) {
+        const double *ps, *pg;
+        if (k > 0) {
+          wts(k - 1, ps, pg);
+        } else {
+          ps = c->w_prev.data();
+          pg = c->w_prev.data() + c->n_h;
+        }
+        rc = build_table(c, ps, pg, -0.5, tB[k], why);
+        if (!rc && tB[k].q_diag + max_qb >= (1ull << 31)) {
+          rc = QMC_ERR_DT;
+          why = "diagonal group with shift violates the Q32 bound";
+        }
       }
-      rc = build_table(c, ps, pg, -0.5, tB[k], why);
-      if (!rc && tB[k].q_diag + max_qb >= (1ull << 31)) {
+      if (!rc && tA[k].q_diag + max_qa >= (1ull << 31)) {
         rc = QMC_ERR_DT;
         why = "diagonal group with shift violates the Q32 bound";
       }
+      if (rc) {
+        rc_out = rc;
+        return k;
+      }
+      bA[k] = pack_table(tA[k], nullptr);
+      if (two) bB[k] = pack_table(tB[k], nullptr);
     }
-    if (rc) return fail(c, rc, "step " + std::to_string(c->step + k) + ": " + why);
-    if (tA[k].q_diag + max_qa >= (1ull << 31))
-      return fail(c, QMC_ERR_DT, "diagonal group with shift violates the Q32 bound");
-    bA[k] = pack_table(tA[k], nullptr);
-    if (two) bB[k] = pack_table(tB[k], nullptr);
+    return k1;
+  };
+  {
+    // Long calls build on a few host threads (tables are independent); the first failing
+    // step in step order is reported either way.
+    const uint32_t nth = nsteps >= 512 ? std::min<uint32_t>(kTableThreads, nsteps / 256) : 1u;
+    std::vector<uint32_t> bad(nth, nsteps);
+    std::vector<int> code(nth, QMC_OK);
+    std::vector<std::string> msg(nth);
+    auto part = [&](uint32_t i) {
+      const uint32_t a = (uint32_t)((uint64_t)nsteps * i / nth);
+      const uint32_t b = (uint32_t)((uint64_t)nsteps * (i + 1) / nth);
+      const uint32_t f = build_range(a, b, code[i], msg[i]);
+      if (f < b) bad[i] = f;
+    };
+    std::vector<std::thread> pool;
+    for (uint32_t i = 1; i < nth; ++i) {
+      try {
+        pool.emplace_back(part, i);
+      } catch (...) {  // no thread available: build that part here
+        part(i);
+      }
+    }
+    part(0);
+    for (std::thread& th : pool) th.join();
+    for (uint32_t i = 0; i < nth; ++i)
+      if (bad[i] < nsteps)
+        return fail(c, code[i], "step " + std::to_string(c->step + bad[i]) + ": " + msg[i]);
   }
   const uint32_t first_step = c->step;
   const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
@@ -863,6 +904,8 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     return fail(c, QMC_ERR_ARG, "step table larger than the fused kernel takes; use the "
                                 "automatic or streamed path");
   uint32_t last_local_fail = 0xFFFFFFFFu;
+  uint32_t win1 = 0;  // steps [.., win1) of this call have their tables in the table area
+  std::vector<uint32_t> offA(nsteps, 0), offB(ab2 ? nsteps : 0, 0);
   while (c->step < first_step + nsteps) {
     const uint32_t k0 = c->step - first_step;
     const bool two = ab2 && k0 >= euler_first;
@@ -885,28 +928,36 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     uint32_t kmax = two || !ab2 ? nsteps : k0 + 1;
     if (!fused && c->path == 0 && c->step < c->streamed_until)
       kmax = std::min<uint32_t>(kmax, c->streamed_until - first_step);
+    if (k0 >= win1) {
+      // Pack and upload the tables of as many steps from k0 on as fit the table area; launches
+      // that resume after a rebalance reuse them.
+      size_t bytes = 0;
+      win1 = k0;
+      while (win1 < nsteps) {
+        const bool tw = ab2 && win1 >= euler_first;
+        const size_t need = bA[win1] + (tw ? bB[win1] : 0);
+        if (bytes + need > kTableArea) break;
+        offA[win1] = (uint32_t)bytes;
+        pack_table(tA[win1], c->pinned + bytes);
+        bytes += bA[win1];
+        if (tw) {
+          offB[win1] = (uint32_t)bytes;
+          pack_table(tB[win1], c->pinned + bytes);
+          bytes += bB[win1];
+        }
+        ++win1;
+      }
+      if (win1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
+      HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab), c->pinned, bytes,
+                               hipMemcpyHostToDevice, c->stream));
+    }
     Chunk ch;
     ch.dtab = c->at<uint8_t>(c->L.tab);
     ch.two = two;
-    size_t bytes = 0;
-    uint32_t k1 = k0;
-    while (k1 < kmax && k1 - k0 < kMaxChunkSteps &&
-           bytes + bA[k1] + (two ? bB[k1] : 0) <= kTableArea) {
-      ch.offsA.push_back((uint32_t)bytes);
-      bytes += bA[k1];
-      if (two) {
-        ch.offsB.push_back((uint32_t)bytes);
-        bytes += bB[k1];
-      }
-      ++k1;
-    }
-    if (k1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
+    const uint32_t k1 = std::min<uint32_t>(std::min<uint32_t>(kmax, win1), k0 + kMaxChunkSteps);
     ch.nst = k1 - k0;
-    for (uint32_t k = k0; k < k1; ++k) {
-      pack_table(tA[k], c->pinned + ch.offsA[k - k0]);
-      if (two) pack_table(tB[k], c->pinned + ch.offsB[k - k0]);
-    }
-    HIPCHK(c, hipMemcpyAsync(ch.dtab, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
+    ch.offsA.assign(offA.begin() + k0, offA.begin() + k1);
+    if (two) ch.offsB.assign(offB.begin() + k0, offB.begin() + k1);
     qmc::Counters hc;
     uint32_t kd = 0, reason = 0;
     int rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);

@@ -9,8 +9,9 @@ uint32_t qmck_sort_passes(uint32_t key_bits);
 int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t n_status,
                      uint64_t* sort_status, uint64_t n_sort_status, uint32_t* ghist,
                      uint32_t n_ghist);
-// Children of step `step` from the n = *count records (pk, pv), Philox stream `stream`; with
-// qsh (per-replica Q32 shifts) the diagonal of each column is emitted as a record as well.
+// Records of step `step` from the n = *count parents (pk, pv), Philox stream `stream`: the death
+// delta of each parent (diagonal of its column plus the per-replica Q32 shift qsh) and its
+// children.
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
                const uint64_t* count, const uint8_t* tab, uint32_t step, uint64_t seed,
                uint32_t kbits, uint32_t stream, const int64_t* qsh, uint64_t* ck, int2* cv,
@@ -22,11 +23,11 @@ int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, vo
               uint32_t step, uint32_t src, uint64_t max_items);
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, const uint8_t* tab, const uint8_t* tab_next,
-               const uint8_t* tabB_next, const int64_t* qshift, const int64_t* qshiftB,
-               uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok, int2* ov,
-               uint64_t cap_store, uint64_t max_items, uint64_t* ck_next, int2* cv_next,
-               uint64_t cap_child, uint32_t* ghist_next, uint32_t passes);
+               uint64_t* status, const uint8_t* tab_next, const uint8_t* tabB_next,
+               const int64_t* qshift, const int64_t* qshiftB, uint32_t step, uint64_t seed,
+               uint32_t kbits, uint64_t* ok, int2* ov, uint64_t cap_store, uint64_t max_items,
+               uint64_t* ck_next, int2* cv_next, uint64_t cap_child, uint32_t* ghist_next,
+               uint32_t passes);
 int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t cur, uint32_t n,
                uint64_t x, uint64_t z, uint64_t* ck, int2* cv, uint32_t csel,
                uint64_t max_parents);

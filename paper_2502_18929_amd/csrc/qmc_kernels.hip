@@ -1,15 +1,16 @@
 // qmc_kernels.hip -- HIP kernels of one population-dynamics time step (gfx950, wave64).
 //
 // Step s (End Matter, spawn and annihilation; Euler solver):
-//   children(s)      spawned from N(s): key ^ mask, comb-rounded dt L N, unsorted, with the
-//                    radix digit histograms of every pass accumulated while they are written
-//   k_onesweep x P   single-pass LSD radix sort of the children by composite key: per tile,
+//   records(s)       from N(s): the death/cloning delta of each parent (diagonal of its
+//                    column, the parent's own key) and its children (key ^ mask), comb-rounded
+//                    dt L N, unsorted, with the radix digit histograms of every pass
+//                    accumulated while they are written
+//   k_onesweep x P   single-pass LSD radix sort of the records by composite key: per tile,
 //                    wave-local stable ranking in LDS, decoupled look-back per digit, scatter
-//   k_merge_part     merge-path split points of (parents, sorted children), moved to run ends
-//   k_merge          death/cloning of each parent (diagonal of the column, applied to N(s)),
-//                    merge with the children, int64 segmented sum per key, drop (0, 0),
+//   k_merge_part     merge-path split points of (parents, sorted records), moved to run ends
+//   k_merge          merge of parents and records, int64 segmented sum per key, drop (0, 0),
 //                    decoupled look-back for the compacted output offset -> N(s+1); then the
-//                    children of step s+1 are spawned from the outputs still in LDS
+//                    records of step s+1 are made from the outputs still in LDS
 // The first step of a batch spawns with k_spawn.  Plus k_pulse (ideal Pauli conjugation),
 // k_observe / k_lookup (estimator numerators) and small utility kernels.  Every kernel reads its
 // problem sizes from device memory, so a batch of steps is enqueued without host sync.
@@ -84,11 +85,10 @@ struct Emitter {
   }
 };
 
-// Children of one parent (called by every lane of a wave; `valid` lanes hold a parent), drawn
-// from Philox stream `stream`.  With `qsh` (the per-replica Q32 shifts of this table) the
-// diagonal of the column is emitted as a record of the parent's own key too (the second AB2
-// term, whose parent is N(s-1)); without it the diagonal is left to the merge, which applies
-// it to the parent itself.
+// Death/cloning record and children of one parent (called by every lane of a wave; `valid` lanes
+// hold a parent), drawn from Philox stream `stream`; `qsh` holds the per-replica Q32 shifts of
+// this table.  The death delta is a record of the parent's own key, summed into N(s+1) by the
+// merge like the children.
 __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, bool valid,
                                              uint64_t ck, int2 v, uint32_t step, uint64_t seed,
                                              const KeyLayout& kl, uint32_t stream,
@@ -98,7 +98,7 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
   const uint64_t sab = uabs64(v.x) + uabs64(v.y);
   if (valid) walker_random(kl.key(ck), step, kl.replica(ck), seed, stream, w);
   const uint64_t key = kl.key(ck);
-  if (qsh) {
+  {
     const int64_t qs = valid ? qsh[kl.replica(ck)] : 0;
     const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w[1]);
     if (__ballot(dact)) {
@@ -133,18 +133,41 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
   }
 }
 
-// Children of up to 64 active parents (lane < n holds one; w0 is its spawn comb word, drawn when
-// the parent was queued), every lane of the wave calling.
-__device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, const uint64_t* ak,
-                                            const int2* av, const uint32_t* aw, uint32_t n,
-                                            const KeyLayout& kl) {
+// Death/cloning record and children of up to 64 queued parents (lane < n holds one; (w0, w1) are
+// its spawn and death comb words, drawn when it was queued), every lane of the wave calling.  The
+// death delta of step s+1 is a record of the parent's own key, summed into N(s+2) by the next
+// merge like the children.
+__device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, const int64_t* qsh,
+                                            const uint64_t* ak, const int2* av, const uint2* aw,
+                                            uint32_t n, const KeyLayout& kl) {
   const uint32_t lane = __lane_id();
-  const bool act = lane < n;
-  const uint64_t ck = act ? ak[lane] : 0;
-  const int2 v = act ? av[lane] : make_int2(0, 0);
-  uint64_t r = act ? aw[lane] : 0;
+  const bool valid = lane < n;
+  const uint64_t ck = valid ? ak[lane] : 0;
+  const int2 v = valid ? av[lane] : make_int2(0, 0);
+  const uint2 w = valid ? aw[lane] : make_uint2(0, 0);
   const uint64_t key = kl.key(ck);
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+  {
+    const int64_t qs = valid ? qsh[kl.replica(ck)] : 0;
+    const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w.y);
+    if (__ballot(dact)) {
+      int2 d = make_int2(0, 0);
+      if (dact) {
+        int32_t dre, dim;
+        group_coeff(tv.t, 0, tv.gs[1], key, dre, dim);
+        int64_t xre, xim;
+        cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
+        uint64_t r = w.y;
+        d.x = (int32_t)comb_step(r, xre);
+        d.y = (int32_t)comb_step(r, xim);
+      }
+      em.emit((d.x | d.y) != 0, ck, d);
+    }
+  }
   const uint32_t G = tv.h->n_groups;
+  const bool act = valid && G > 1 && !comb_all_zero(sab, tv.h->q_off, w.x);
+  if (__ballot(act) == 0) return;
+  uint64_t r = w.x;
   for (uint32_t g = 1; g < G; ++g) {
     int2 child = make_int2(0, 0);
     if (act) {
@@ -160,8 +183,8 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, co
 }
 
 // ---------------------------------------------------------------------------------------------
-// k_spawn: children of the first step of a batch from N(s) (later steps spawn inside k_merge),
-// and with AB2 the records of the second term from N(s-1) (stream 1, diagonal included).
+// k_spawn: death records and children of the first step of a batch from N(s) (later steps spawn
+// inside k_merge), and with AB2 the records of the second term from N(s-1) (stream 1).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_spawn(
     const uint64_t* __restrict__ pk, const int2* __restrict__ pv, Counters* __restrict__ cnt,
@@ -178,19 +201,17 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
   Emitter em{s_key[wave], s_val[wave], kSpawnSeg, 0, cnt, step & 1u, step, ck_out, cv_out,
              cap_child, ghist, passes};
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  if (tv.h->n_groups > 1 || qsh) {
-    for (uint64_t wbase = (uint64_t)blockIdx.x * kBlock + wave * kWave; wbase < np;
-         wbase += stride) {
-      const uint64_t p = wbase + lane;
-      const bool valid = p < np;
-      uint64_t ck = 0;
-      int2 v = make_int2(0, 0);
-      if (valid) {
-        ck = pk[p];
-        v = pv[p];
-      }
-      spawn_parent(em, tv, valid, ck, v, step, seed, kl, stream, qsh);
+  for (uint64_t wbase = (uint64_t)blockIdx.x * kBlock + wave * kWave; wbase < np;
+       wbase += stride) {
+    const uint64_t p = wbase + lane;
+    const bool valid = p < np;
+    uint64_t ck = 0;
+    int2 v = make_int2(0, 0);
+    if (valid) {
+      ck = pk[p];
+      v = pv[p];
     }
+    spawn_parent(em, tv, valid, ck, v, step, seed, kl, stream, qsh);
   }
   if (em.fill) em.flush();
 }
@@ -518,11 +539,10 @@ struct MergeArgs {
   const uint2* splits;
   uint64_t* status;
   uint32_t epoch;
-  const uint8_t* tab;        // table of step s (death)
-  const uint8_t* tab_next;   // table of step s+1 (spawn), or null
+  const uint8_t* tab_next;   // table of step s+1 (death and spawn), or null
   const uint8_t* tabB_next;  // AB2: table of the second term of step s+1 (from N(s)), or null
   const int64_t* qshiftB;    // AB2: its per-replica Q32 shifts
-  const int64_t* qshift;
+  const int64_t* qshift;    // per-replica Q32 shifts of tab_next
   uint32_t step;
   uint64_t seed;
   KeyLayout kl;
@@ -553,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   // (a batch costs the same whatever its lane count, and sparse columns leave most lanes idle).
   __shared__ uint64_t s_ak[kMergeActive];
   __shared__ int2 s_av[kMergeActive];
-  __shared__ uint32_t s_aw[kMergeActive];
+  __shared__ uint2 s_aw[kMergeActive];
   static_assert(kWaves * kMergeSpawnSeg <= CAP, "spawn staging must fit the child tile");
 
   Counters* cnt = A.cnt;
@@ -566,9 +586,6 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_store[A.cur ^ 1] = 0;
     return;
   }
-  const TableView tv = table_view(A.tab);
-  const uint32_t d_end = tv.h->n_groups > 0 ? tv.gs[1] : 0u;
-  const uint64_t q_diag = tv.h->q_diag;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
   uint32_t nl = 0;  // queued active outputs (block-uniform)
@@ -582,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
                  A.passes};
       for (uint32_t b = wave; b < nb; b += kWaves) {
         const uint32_t b0 = b * kWave;
-        spawn_batch(em, tn, s_ak + b0, s_av + b0, s_aw + b0,
+        spawn_batch(em, tn, A.qshift, s_ak + b0, s_av + b0, s_aw + b0,
                     nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl);
       }
       if (em.fill) em.flush();
@@ -592,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __syncthreads();
     uint64_t rk = 0;
     int2 rv = make_int2(0, 0);
-    uint32_t rw = 0;
+    uint2 rw = make_uint2(0, 0);
     if (threadIdx.x < rest) {
       rk = s_ak[done + threadIdx.x];
       rv = s_av[done + threadIdx.x];
@@ -628,30 +645,15 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     const uint32_t pa = s0.x, pn = s1.x - s0.x;
     const uint32_t ca = s0.y, cn = s1.y - s0.y;
 
-    // Parents with their death/cloning update (diagonal of the column, applied to N(s)).
+    // Parents (their death/cloning delta of this step arrived as a record among the children).
     uint64_t wsum = 0;
     for (uint32_t x = threadIdx.x; x < pn; x += kBlock) {
       const uint64_t ck = A.pk[pa + x];
       const int2 v = A.pv[pa + x];
-      const uint32_t rep = kl.replica(ck);
-      const int64_t qs = A.qshift[rep];
-      int64_t a = v.x, b = v.y;
-      uint32_t w[4];
-      walker_random(kl.key(ck), A.step, rep, A.seed, 0u, w);
-      const uint64_t sab = uabs64(a) + uabs64(b);
-      wsum += sab;
-      if (!comb_all_zero(sab, q_diag + uabs64(qs), w[1])) {
-        int32_t dre, dim;
-        group_coeff(tv.t, 0, d_end, kl.key(ck), dre, dim);
-        int64_t xre, xim;
-        cmul_q32(a, b, dre + (int32_t)qs, dim, xre, xim);
-        uint64_t r = w[1];
-        a += comb_step(r, xre);
-        b += comb_step(r, xim);
-      }
+      wsum += uabs64(v.x) + uabs64(v.y);
       s_pk[x] = ck;
-      s_pre[x] = a;
-      s_pim[x] = b;
+      s_pre[x] = v.x;
+      s_pim[x] = v.y;
     }
     for (uint32_t x = threadIdx.x; x < cn; x += kBlock) {
       s_ck[x] = A.ckeys[ca + x];
@@ -712,21 +714,114 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       atomicMin(&cnt->err_step, A.step);
     }
 
-    // Block exclusive scan of counts.
-    s_scan[threadIdx.x] = count;
-    __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {
-      const uint32_t v = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s_scan[threadIdx.x] += v;
-      __syncthreads();
+    // Block exclusive scan of the counts: inclusive scan within each wave, then wave totals.
+    uint32_t incl = count;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t x = __shfl_up(incl, o);
+      if (lane >= (uint32_t)o) incl += x;
     }
-    const uint32_t excl = s_scan[threadIdx.x] - count;
-    const uint32_t agg = s_scan[kBlock - 1];
-
-    // Decoupled look-back for the tile's output offset (wave 0, 64 predecessors per round).
+    if (lane == kWave - 1) s_scan[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, agg = 0;
+    for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
+      const uint32_t v = s_scan[x];
+      wpre += x < wave ? v : 0u;
+      agg += v;
+    }
+    const uint32_t excl = wpre + incl - count;
+    // The tile's aggregate is published now; its look-back for the output offset waits until
+    // after the LDS work below, by when the predecessors have usually published theirs.
     if (threadIdx.x == 0)
       atomic_store_agent(&A.status[tile], lb_pack(A.epoch, tile == 0 ? 2 : 1, agg));
+
+    // Pass 2: the annihilated, compacted records of the tile, into LDS.
+    {
+      uint32_t i = i0, j = j0;
+      uint32_t o = excl;
+      while (i < i1 || j < j1) {
+        uint64_t k;
+        int64_t re = 0, im = 0;
+        if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
+          k = s_pk[i];
+          re = s_pre[i];
+          im = s_pim[i];
+          ++i;
+        } else {
+          k = s_ck[j];
+        }
+        while (j < j1 && s_ck[j] == k) {
+          re += s_cv[j].x;
+          im += s_cv[j].y;
+          ++j;
+        }
+        if (re != 0 || im != 0) {
+          s_ok[o] = k;
+          s_ov[o] = make_int2((int32_t)re, (int32_t)im);
+          ++o;
+        }
+      }
+    }
+    __syncthreads();
+
+    // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
+    // that can spawn go to the queue; full batches are spawned when it fills.
+    if (A.tab_next) {
+      const TableView tn = table_view(A.tab_next);
+      const uint64_t q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
+      const uint64_t q_diag = tn.h->q_diag;
+      for (uint32_t base = 0; base < agg; base += kBlock) {
+        const uint32_t p = base + threadIdx.x;
+        bool act = false;
+        uint64_t ck = 0;
+        int2 v = make_int2(0, 0);
+        uint32_t w[4] = {0, 0, 0, 0};
+        if (p < agg) {
+          ck = s_ok[p];
+          v = s_ov[p];
+          const uint32_t rep = kl.replica(ck);
+          walker_random(kl.key(ck), A.step + 1, rep, A.seed, 0u, w);
+          const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+          act = !comb_all_zero(sab, q_off, w[0]) ||
+                !comb_all_zero(sab, q_diag + uabs64(A.qshift[rep]), w[1]);
+        }
+        const uint64_t m = __ballot(act);
+        if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
+          const uint32_t c2 = s_scan[x];
+          off += x < wave ? c2 : 0u;
+          tot += c2;
+        }
+        __syncthreads();
+        if (nl + tot > (uint32_t)kMergeActive) drain(nl / kWave);
+        if (act) {
+          const uint32_t at = nl + off + mbcnt64(m);
+          s_ak[at] = ck;
+          s_av[at] = v;
+          s_aw[at] = make_uint2(w[0], w[1]);
+        }
+        nl += tot;
+        __syncthreads();
+      }
+      if (A.tabB_next) {
+        // second AB2 term of step s+1 from this tile's parents N(s), as loaded
+        const TableView tb = table_view(A.tabB_next);
+        Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg,
+                   0, cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child,
+                   A.ghist_next, A.passes};
+        for (uint32_t wb = wave * kWave; wb < pn; wb += kBlock) {
+          const uint32_t p = wb + lane;
+          const bool valid = p < pn;
+          const uint64_t ck = valid ? A.pk[pa + p] : 0;
+          const int2 v = valid ? A.pv[pa + p] : make_int2(0, 0);
+          spawn_parent(em, tb, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
+        }
+        if (em.fill) em.flush();
+      }
+    }
+
+    // Decoupled look-back for the tile's output offset (wave 0, 64 predecessors per round).
     if (wave == 0) {
       uint64_t prefix = 0;
       bool ok = true;
@@ -750,93 +845,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       }
     }
     __syncthreads();
+    // the tile's records to the new store, coalesced
     const uint64_t gbase = s_base;
-
-    // Pass 2: the annihilated, compacted records, to global memory and to LDS.
-    {
-      uint32_t i = i0, j = j0;
-      uint32_t o = excl;
-      while (i < i1 || j < j1) {
-        uint64_t k;
-        int64_t re = 0, im = 0;
-        if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
-          k = s_pk[i];
-          re = s_pre[i];
-          im = s_pim[i];
-          ++i;
-        } else {
-          k = s_ck[j];
-        }
-        while (j < j1 && s_ck[j] == k) {
-          re += s_cv[j].x;
-          im += s_cv[j].y;
-          ++j;
-        }
-        if (re != 0 || im != 0) {
-          const int2 v = make_int2((int32_t)re, (int32_t)im);
-          if (gbase + o < A.cap_store) {
-            A.ok[gbase + o] = k;
-            A.ov[gbase + o] = v;
-          }
-          s_ok[o] = k;
-          s_ov[o] = v;
-          ++o;
-        }
-      }
-    }
-    __syncthreads();
-
-    // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
-    // that can spawn go to the queue; full batches are spawned when it fills.
-    if (A.tab_next) {
-      const TableView tn = table_view(A.tab_next);
-      const uint64_t q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
-      for (uint32_t base = 0; base < agg; base += kBlock) {
-        const uint32_t p = base + threadIdx.x;
-        bool act = false;
-        uint64_t ck = 0;
-        int2 v = make_int2(0, 0);
-        uint32_t w[4] = {0, 0, 0, 0};
-        if (p < agg) {
-          ck = s_ok[p];
-          v = s_ov[p];
-          walker_random(kl.key(ck), A.step + 1, kl.replica(ck), A.seed, 0u, w);
-          act = !comb_all_zero(uabs64(v.x) + uabs64(v.y), q_off, w[0]);
-        }
-        const uint64_t m = __ballot(act);
-        if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t off = 0, tot = 0;
-        for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
-          const uint32_t c2 = s_scan[x];
-          off += x < wave ? c2 : 0u;
-          tot += c2;
-        }
-        __syncthreads();
-        if (nl + tot > (uint32_t)kMergeActive) drain(nl / kWave);
-        if (act) {
-          const uint32_t at = nl + off + mbcnt64(m);
-          s_ak[at] = ck;
-          s_av[at] = v;
-          s_aw[at] = w[0];
-        }
-        nl += tot;
-        __syncthreads();
-      }
-      if (A.tabB_next) {
-        // second AB2 term of step s+1 from this tile's parents N(s), as loaded
-        const TableView tb = table_view(A.tabB_next);
-        Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg,
-                   0, cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child,
-                   A.ghist_next, A.passes};
-        for (uint32_t wb = wave * kWave; wb < pn; wb += kBlock) {
-          const uint32_t p = wb + lane;
-          const bool valid = p < pn;
-          const uint64_t ck = valid ? A.pk[pa + p] : 0;
-          const int2 v = valid ? A.pv[pa + p] : make_int2(0, 0);
-          spawn_parent(em, tb, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
-        }
-        if (em.fill) em.flush();
+    for (uint32_t x = threadIdx.x; x < agg; x += kBlock) {
+      if (gbase + x < A.cap_store) {
+        A.ok[gbase + x] = s_ok[x];
+        A.ov[gbase + x] = s_ov[x];
       }
     }
     __syncthreads();
@@ -1095,11 +1109,11 @@ int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, vo
 
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, const uint8_t* tab, const uint8_t* tab_next,
-               const uint8_t* tabB_next, const int64_t* qshift, const int64_t* qshiftB,
-               uint32_t step, uint64_t seed, uint32_t kbits, uint64_t* ok, int2* ov,
-               uint64_t cap_store, uint64_t max_items, uint64_t* ck_next, int2* cv_next,
-               uint64_t cap_child, uint32_t* ghist_next, uint32_t passes) {
+               uint64_t* status, const uint8_t* tab_next, const uint8_t* tabB_next,
+               const int64_t* qshift, const int64_t* qshiftB, uint32_t step, uint64_t seed,
+               uint32_t kbits, uint64_t* ok, int2* ov, uint64_t cap_store, uint64_t max_items,
+               uint64_t* ck_next, int2* cv_next, uint64_t cap_child, uint32_t* ghist_next,
+               uint32_t passes) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   hipLaunchKernelGGL(k_merge_part,
                      dim3(grid_for(((uint64_t)max_tiles + 1) * kWave, 2048)), dim3(kBlock), 0,
@@ -1115,7 +1129,6 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.splits = splits;
   a.status = status;
   a.epoch = merge_epoch(step);
-  a.tab = tab;
   a.tab_next = tab_next;
   a.tabB_next = tabB_next;
   a.qshiftB = qshiftB;

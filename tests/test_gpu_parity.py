@@ -385,3 +385,28 @@ def test_dt_error_leaves_state(B, orc):
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
     assert g.counters()["step"] == 10
+
+
+@pytest.mark.parametrize("bad, code", [(1, "DT"), (1537, "DT"), (2999, "ARG")])
+def test_long_call_table_error_names_first_step(B, orc, bad, code):
+    """A 3000-step call builds its tables on several host threads: the first bad step is
+    reported (by step number) and nothing runs."""
+    w = W.config_ghz4()
+    g = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    g.step(w.s[:10], w.gamma[:10])
+    before = g.export(0)
+    s = np.tile(w.s[10:11], (3000, 1))
+    gam = np.tile(w.gamma[10:11], (3000, 1))
+    if code == "DT":
+        s[bad] *= 1e4
+        s[2990] *= 1e4  # a later bad step is not the one reported
+    else:
+        gam[bad, 0] = np.nan
+    with pytest.raises(B.QMCError) as e:
+        g.step(s, gam)
+    assert e.value.code == getattr(B, "QMC_ERR_" + code)
+    assert f"step {10 + bad}:" in str(e.value)
+    after = g.export(0)
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert g.counters()["step"] == 10

@@ -66,6 +66,27 @@ def test_coeff_tables_match_oracle_random(orc, seed):
     _tables_equal(a, b)
 
 
+def test_quantization_ties_round_half_even(orc):
+    """Coefficients landing exactly halfway between Q32 steps round half to even, both below
+    2^51 and above it (a pair of huge terms on one mask whose rounded sum is small)."""
+    n = 3
+    dt = 2.0 ** -33  # dt * c * 2^32 = c / 2: odd integers c give exact ties
+    h = [(x, z, float(2 * (4 * x + z) + 1) * (-1) ** z) for x in range(1, 4) for z in range(4)]
+    h += [(0, 1, 2.0 ** 52 + 1), (0, 1, -(2.0 ** 52 + 3)), (0, 2, 2.0 ** 53 + 2.0),
+          (0, 2, -(2.0 ** 53) - 6.0)]
+    s = np.ones(len(h))
+    o = orc.Oracle(n, 1, 1, dt, h, [], [0], [1], [0])
+    b = o.table(s, np.zeros(0))
+    a = binding.coeff_table(n, dt, h, [], s, np.zeros(0))
+    _tables_equal(a, b)
+    d0, d1 = int(a["gstart"][0]), int(a["gstart"][1])  # the diagonal group
+    q = dict(zip(a["zmask"][d0:d1].tolist(), a["q"][d0:d1].tolist()))
+    # -i h gives Im = -Re(h): ties -(2^51 + 1/2) -> -2^51, 2^51 + 3/2 -> 2^51 + 2, and above
+    # 2^52 (spacing 1) the halves -(2^52 + 1) and 2^52 + 3 are already integers
+    assert q[1][1] == -(2 ** 51) + (2 ** 51 + 2)
+    assert q[2][1] == -(2 ** 52 + 1) + (2 ** 52 + 3)
+
+
 def test_dt_bound_rejected_like_oracle(orc):
     w = W.config_ghz4()
     with pytest.raises(binding.QMCError) as e:

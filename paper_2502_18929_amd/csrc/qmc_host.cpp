@@ -24,7 +24,7 @@ namespace {
 
 constexpr uint32_t kMaxPauli = 256;
 constexpr uint32_t kMaxLookup = 4096;
-constexpr size_t kTableArea = 8u << 20;   // device bytes for the step tables of one chunk
+constexpr size_t kTableArea = 32u << 20;  // device bytes for the step tables of one window
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
@@ -140,7 +140,7 @@ struct qmc_ctx {
   uint32_t cur = 0;
   std::vector<double> shift;
   std::vector<int64_t> nd0_re;
-  uint8_t* pinned = nullptr;     // table staging, kTableArea bytes
+  uint8_t* pinned = nullptr;     // table staging: kTableArea bytes, then the window offsets
   uint8_t* pinned_small = nullptr;  // counters and estimator staging
   size_t pinned_small_bytes = 0;
   std::string err;
@@ -328,13 +328,13 @@ int build_table(const qmc_ctx* c, const double* s, const double* g, double scale
 size_t pack_table(const HostTable& T, uint8_t* dst) {
   // device layout: every group's terms padded with zero terms to a nonzero multiple of kTermPad
   const uint32_t G = (uint32_t)T.gx.size();
-  std::vector<uint32_t> gs(G + 1, 0);
-  for (uint32_t g = 0; g < G; ++g) {
+  auto padded = [&](uint32_t g) -> uint32_t {
     const uint32_t len = T.gs[g + 1] - T.gs[g];
-    const uint32_t blocks = len == 0 ? 1u : (len + qmc::kTermPad - 1) / qmc::kTermPad;
-    gs[g + 1] = gs[g] + blocks * qmc::kTermPad;
-  }
-  const uint32_t NT = gs[G];
+    return len == 0 ? (uint32_t)qmc::kTermPad
+                    : (len + qmc::kTermPad - 1) / qmc::kTermPad * qmc::kTermPad;
+  };
+  uint32_t NT = 0;
+  for (uint32_t g = 0; g < G; ++g) NT += padded(g);
   qmc::TableHeader h{};
   h.n_groups = G;
   h.n_terms = NT;
@@ -348,15 +348,20 @@ size_t pack_table(const HostTable& T, uint8_t* dst) {
   std::memset(dst, 0, h.bytes);
   std::memcpy(dst, &h, sizeof(h));
   std::memcpy(dst + h.gx_off, T.gx.data(), 8 * G);
-  std::memcpy(dst + h.gs_off, gs.data(), 4 * (G + 1));
+  uint32_t* gs = reinterpret_cast<uint32_t*>(dst + h.gs_off);
   qmc::Term* tt = reinterpret_cast<qmc::Term*>(dst + h.t_off);
-  for (uint32_t g = 0; g < G; ++g)
+  uint32_t at = 0;
+  for (uint32_t g = 0; g < G; ++g) {
+    gs[g] = at;
     for (uint32_t i = T.gs[g]; i < T.gs[g + 1]; ++i) {
-      qmc::Term& o = tt[gs[g] + (i - T.gs[g])];
+      qmc::Term& o = tt[at + (i - T.gs[g])];
       o.zmask = T.t[i].zmask;
       o.qre = (int32_t)T.t[i].qre;
       o.qim = (int32_t)T.t[i].qim;
     }
+    at += padded(g);
+  }
+  gs[G] = at;
   return h.bytes;
 }
 
@@ -538,7 +543,8 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
     if (ket == bra) nd += re[i];
   }
   c->nd0_re.assign(c->R, nd);
-  hipError_t e = hipHostMalloc((void**)&c->pinned, kTableArea, hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&c->pinned, kTableArea + (size_t)kMaxChunkSteps * 8,
+                               hipHostMallocDefault);
   c->pinned_small_bytes = std::max<size_t>(1 << 16, (size_t)c->R * kMaxLookup * 16 + 4096);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->pinned_small, c->pinned_small_bytes, hipHostMallocDefault);
@@ -595,8 +601,10 @@ constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a 
 // One chunk of steps [step, step + nst): device tables at dtab (+ offsA / offsB), and whether
 // the chunk integrates with AB2 from a known N(s-1) (`two`; the tables B exist).
 struct Chunk {
-  uint8_t* dtab;
-  std::vector<uint32_t> offsA, offsB;
+  uint8_t* dtab;                 // the device table area
+  const uint32_t* offsA;         // table offsets of the chunk's steps (host copy)
+  const uint32_t* offsB;         // AB2: second-term table offsets, or null
+  uint32_t first;                // index of the chunk's first step in the device offset arrays
   uint32_t nst;
   bool two;
 };
@@ -628,8 +636,8 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.split_w = c->at<uint64_t>(c->L.split);
   pl.P = c->L.P;
   pl.tab_base = ch.dtab;
-  pl.tab_off = c->at<uint32_t>(c->L.tab_off);
-  pl.tabB_off = ch.two ? c->at<uint32_t>(c->L.tabB_off) : nullptr;
+  pl.tab_off = c->at<uint32_t>(c->L.tab_off) + ch.first;
+  pl.tabB_off = ch.two ? c->at<uint32_t>(c->L.tabB_off) + ch.first : nullptr;
   pl.step0 = c->step;
   pl.nsteps = nst;
   pl.seed = c->cfg.seed;
@@ -644,11 +652,6 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.cap_inbox = c->L.cap_child;
   pl.rebal_min = 64;
   pl.done = c->at<uint32_t>(c->L.done);
-  HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), ch.offsA.data(), nst * 4,
-                           hipMemcpyHostToDevice, c->stream));
-  if (ch.two)
-    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tabB_off), ch.offsB.data(), nst * 4,
-                             hipMemcpyHostToDevice, c->stream));
   const bool prof = c->prof_class == 3;
   if (prof) {
     while (c->prof_ev.size() < 2) {
@@ -672,7 +675,9 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   }
   kd = pin_done[0];
   reason = pin_done[1];
+  bool sized = true;  // the kernel wrote the sizes of the stores gathered below
   if (reason == 2 || hc.err) {
+    sized = false;
     const uint32_t es = hc.err_step;
     if (es < pl.step0 || es > pl.step0 + pl.nsteps) {
       c->broken = true;
@@ -688,8 +693,10 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
                             &dcnt->n_prev));
     HIPCHK(c, qmcp_gather(c->stream, &pl, kd % pl.nbuf, c->sk(0), c->sv(0),
                           &dcnt->n_store[c->cur]));
-    rc = read_counters(c, hc);
-    if (rc) return rc;
+    if (!sized) {
+      rc = read_counters(c, hc);
+      if (rc) return rc;
+    }
   }
   c->step = pl.step0 + kd;
   c->n_occ = hc.n_store[c->cur];
@@ -822,8 +829,6 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
 
   // Build and check every table of the call before launching anything: step k uses A(k) (the
   // only table for Euler) and, for AB2, B(k) from the weights of step k - 1.
-  std::vector<HostTable> tA(nsteps), tB(ab2 ? nsteps : 0);
-  std::vector<size_t> bA(nsteps), bB(ab2 ? nsteps : 0);
   std::vector<int64_t> qsA, qsB, qs1;
   if (shifts_q32(c, 1.0, qs1) || (ab2 && (shifts_q32(c, 1.5, qsA) || shifts_q32(c, -0.5, qsB))))
     return fail(c, QMC_ERR_DT, "shift too large for Q32");
@@ -833,52 +838,104 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     if (ab2) max_qb = std::max(max_qb, uabs(qsB[r]));
     if (euler_first) max_qa = std::max(max_qa, uabs(qs1[r]));
   }
-  // Steps [k0, k1): returns the first failing step (with its code and message) or k1.
-  auto build_range = [&](uint32_t k0, uint32_t k1, int& rc_out, std::string& why) -> uint32_t {
-    for (uint32_t k = k0; k < k1; ++k) {
-      const double *ws, *wg;
-      wts(k, ws, wg);
-      const bool two = ab2 && k >= euler_first;
-      int rc = build_table(c, ws, wg, two ? 1.5 : 1.0, tA[k], why);
-      if (!rc && two) {
-        const double *ps, *pg;
-        if (k > 0) {
-          wts(k - 1, ps, pg);
-        } else {
-          ps = c->w_prev.data();
-          pg = c->w_prev.data() + c->n_h;
-        }
-        rc = build_table(c, ps, pg, -0.5, tB[k], why);
-        if (!rc && tB[k].q_diag + max_qb >= (1ull << 31)) {
-          rc = QMC_ERR_DT;
-          why = "diagonal group with shift violates the Q32 bound";
-        }
+  // Tables of step k into (TA, TB); QMC_OK or the error with its message.
+  auto build_step = [&](uint32_t k, HostTable& TA, HostTable& TB, std::string& why) -> int {
+    const double *ws, *wg;
+    wts(k, ws, wg);
+    const bool two = ab2 && k >= euler_first;
+    int rc = build_table(c, ws, wg, two ? 1.5 : 1.0, TA, why);
+    if (!rc && two) {
+      const double *ps, *pg;
+      if (k > 0) {
+        wts(k - 1, ps, pg);
+      } else {
+        ps = c->w_prev.data();
+        pg = c->w_prev.data() + c->n_h;
       }
-      if (!rc && tA[k].q_diag + max_qa >= (1ull << 31)) {
+      rc = build_table(c, ps, pg, -0.5, TB, why);
+      if (!rc && TB.q_diag + max_qb >= (1ull << 31)) {
         rc = QMC_ERR_DT;
         why = "diagonal group with shift violates the Q32 bound";
       }
-      if (rc) {
-        rc_out = rc;
-        return k;
-      }
-      bA[k] = pack_table(tA[k], nullptr);
-      if (two) bB[k] = pack_table(tB[k], nullptr);
     }
-    return k1;
+    if (!rc && TA.q_diag + max_qa >= (1ull << 31)) {
+      rc = QMC_ERR_DT;
+      why = "diagonal group with shift violates the Q32 bound";
+    }
+    return rc;
+  };
+  // Table windows: steps [win0, win1) of this call have their packed tables in the device table
+  // area (at the same offsets as in the pinned staging area) and their offsets in tab_off /
+  // tabB_off; every launch of those steps reuses them.
+  const uint32_t wmax = std::min<uint32_t>(nsteps, kMaxChunkSteps);
+  std::vector<uint32_t> offA(wmax, 0), offB(ab2 ? wmax : 0, 0);
+  uint32_t win0 = 0, win1 = 0;
+  size_t max_tbytes = 0;
+  auto upload_window = [&](const std::vector<std::pair<size_t, size_t>>& spans) -> int {
+    for (const auto& sp : spans)
+      if (sp.second)
+        HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab) + sp.first, c->pinned + sp.first,
+                                 sp.second, hipMemcpyHostToDevice, c->stream));
+    uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
+    const uint32_t nw = win1 - win0;
+    std::memcpy(po, offA.data(), (size_t)nw * 4);
+    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), po, (size_t)nw * 4,
+                             hipMemcpyHostToDevice, c->stream));
+    if (ab2) {
+      std::memcpy(po + kMaxChunkSteps, offB.data(), (size_t)nw * 4);
+      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tabB_off), po + kMaxChunkSteps,
+                               (size_t)nw * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    return QMC_OK;
   };
   {
-    // Long calls build on a few host threads (tables are independent); the first failing
-    // step in step order is reported either way.
+    // Long calls build on a few host threads (tables are independent), each packing its run of
+    // steps into its own slice of the staging area while it fits (the first window); every
+    // step is checked, and the first failing step in step order is reported.
     const uint32_t nth = nsteps >= 512 ? std::min<uint32_t>(kTableThreads, nsteps / 256) : 1u;
-    std::vector<uint32_t> bad(nth, nsteps);
-    std::vector<int> code(nth, QMC_OK);
-    std::vector<std::string> msg(nth);
+    struct Part {
+      uint32_t a, b, stored, bad;
+      size_t base, used;
+      size_t max_bytes;
+      int code;
+      std::string why;
+    };
+    std::vector<Part> parts(nth);
+    for (uint32_t i = 0; i < nth; ++i) {
+      Part& q = parts[i];
+      q.a = (uint32_t)((uint64_t)nsteps * i / nth);
+      q.b = (uint32_t)((uint64_t)nsteps * (i + 1) / nth);
+      q.stored = q.a;
+      q.bad = nsteps;
+      q.base = kTableArea / nth * i;
+      q.used = q.max_bytes = 0;
+      q.code = QMC_OK;
+    }
     auto part = [&](uint32_t i) {
-      const uint32_t a = (uint32_t)((uint64_t)nsteps * i / nth);
-      const uint32_t b = (uint32_t)((uint64_t)nsteps * (i + 1) / nth);
-      const uint32_t f = build_range(a, b, code[i], msg[i]);
-      if (f < b) bad[i] = f;
+      Part& q = parts[i];
+      const size_t cap = kTableArea / nth;
+      HostTable TA, TB;
+      for (uint32_t k = q.a; k < q.b; ++k) {
+        q.code = build_step(k, TA, TB, q.why);
+        if (q.code) {
+          q.bad = k;
+          return;
+        }
+        const bool two = ab2 && k >= euler_first;
+        const size_t sa = pack_table(TA, nullptr), sb = two ? pack_table(TB, nullptr) : 0;
+        q.max_bytes = std::max(q.max_bytes, std::max(sa, sb));
+        if (q.stored == k && k < wmax && q.used + sa + sb <= cap) {
+          offA[k] = (uint32_t)(q.base + q.used);
+          pack_table(TA, c->pinned + q.base + q.used);
+          q.used += sa;
+          if (two) {
+            offB[k] = (uint32_t)(q.base + q.used);
+            pack_table(TB, c->pinned + q.base + q.used);
+            q.used += sb;
+          }
+          q.stored = k + 1;
+        }
+      }
     };
     std::vector<std::thread> pool;
     for (uint32_t i = 1; i < nth; ++i) {
@@ -890,30 +947,38 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     }
     part(0);
     for (std::thread& th : pool) th.join();
-    for (uint32_t i = 0; i < nth; ++i)
-      if (bad[i] < nsteps)
-        return fail(c, code[i], "step " + std::to_string(c->step + bad[i]) + ": " + msg[i]);
+    for (const Part& q : parts)
+      if (q.code) return fail(c, q.code, "step " + std::to_string(c->step + q.bad) + ": " + q.why);
+    // the first window: every step up to the first part that could not store all of its steps
+    std::vector<std::pair<size_t, size_t>> spans;
+    win1 = 0;
+    for (const Part& q : parts) {
+      max_tbytes = std::max(max_tbytes, q.max_bytes);
+      if (win1 == q.a) {
+        spans.emplace_back(q.base, q.used);
+        win1 = q.stored;
+      }
+    }
+    if (win1 == 0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
+    int rc = upload_window(spans);
+    if (rc) return rc;
   }
   const uint32_t first_step = c->step;
   const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
-  size_t max_tbytes = 0;
-  for (size_t b : bA) max_tbytes = std::max(max_tbytes, b);
-  for (size_t b : bB) max_tbytes = std::max(max_tbytes, b);
   const bool fused_fits = max_tbytes <= kPersistTableBytes;
   if (c->path == 1 && !fused_fits)
     return fail(c, QMC_ERR_ARG, "step table larger than the fused kernel takes; use the "
                                 "automatic or streamed path");
   uint32_t last_local_fail = 0xFFFFFFFFu;
-  uint32_t win1 = 0;  // steps [.., win1) of this call have their tables in the table area
-  std::vector<uint32_t> offA(nsteps, 0), offB(ab2 ? nsteps : 0, 0);
+  int32_t shift_mode = -1;  // shifts on the device: 0 single Euler term, 1 both AB2 terms
   while (c->step < first_step + nsteps) {
     const uint32_t k0 = c->step - first_step;
     const bool two = ab2 && k0 >= euler_first;
     const bool fused = c->path == 1 || (c->path == 0 && fused_fits &&
                                         c->step >= c->streamed_until &&
                                         c->n_occ <= fused_max_keys);
-    // Shifts of this chunk's tables.
-    {
+    if (shift_mode != (int32_t)two) {
+      // shifts of this chunk's tables
       std::vector<int64_t> q(2 * (size_t)c->R, 0);
       for (uint32_t r = 0; r < c->R; ++r) {
         q[r] = two ? qsA[r] : qs1[r];
@@ -921,43 +986,47 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
       }
       int rc = upload_qshift(c, q);
       if (rc) return rc;
+      shift_mode = (int32_t)two;
     }
-    // One launch (fused) or one stream of launches: as many of the remaining steps as fit the
-    // table area; the Euler first step of AB2 runs alone; an automatic streamed run stops where
-    // the fused kernel may be tried again.
+    // One launch (fused) or one stream of launches: the remaining steps of the table window;
+    // the Euler first step of AB2 runs alone; an automatic streamed run stops where the fused
+    // kernel may be tried again.
     uint32_t kmax = two || !ab2 ? nsteps : k0 + 1;
     if (!fused && c->path == 0 && c->step < c->streamed_until)
       kmax = std::min<uint32_t>(kmax, c->streamed_until - first_step);
     if (k0 >= win1) {
-      // Pack and upload the tables of as many steps from k0 on as fit the table area; launches
-      // that resume after a rebalance reuse them.
+      // the next window (calls longer than the first one): packed here, one step after another
+      win0 = win1 = k0;
       size_t bytes = 0;
-      win1 = k0;
-      while (win1 < nsteps) {
+      HostTable TA, TB;
+      std::string why;
+      while (win1 < nsteps && win1 - win0 < kMaxChunkSteps) {
+        if (build_step(win1, TA, TB, why)) return fail(c, QMC_ERR_STATE, "table changed: " + why);
         const bool tw = ab2 && win1 >= euler_first;
-        const size_t need = bA[win1] + (tw ? bB[win1] : 0);
-        if (bytes + need > kTableArea) break;
-        offA[win1] = (uint32_t)bytes;
-        pack_table(tA[win1], c->pinned + bytes);
-        bytes += bA[win1];
+        const size_t sa = pack_table(TA, nullptr), sb = tw ? pack_table(TB, nullptr) : 0;
+        if (bytes + sa + sb > kTableArea) break;
+        offA[win1 - win0] = (uint32_t)bytes;
+        pack_table(TA, c->pinned + bytes);
+        bytes += sa;
         if (tw) {
-          offB[win1] = (uint32_t)bytes;
-          pack_table(tB[win1], c->pinned + bytes);
-          bytes += bB[win1];
+          offB[win1 - win0] = (uint32_t)bytes;
+          pack_table(TB, c->pinned + bytes);
+          bytes += sb;
         }
         ++win1;
       }
       if (win1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
-      HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab), c->pinned, bytes,
-                               hipMemcpyHostToDevice, c->stream));
+      int rc = upload_window({{0, bytes}});
+      if (rc) return rc;
     }
     Chunk ch;
     ch.dtab = c->at<uint8_t>(c->L.tab);
     ch.two = two;
-    const uint32_t k1 = std::min<uint32_t>(std::min<uint32_t>(kmax, win1), k0 + kMaxChunkSteps);
+    const uint32_t k1 = std::min<uint32_t>(kmax, win1);
     ch.nst = k1 - k0;
-    ch.offsA.assign(offA.begin() + k0, offA.begin() + k1);
-    if (two) ch.offsB.assign(offB.begin() + k0, offB.begin() + k1);
+    ch.first = k0 - win0;
+    ch.offsA = offA.data() + ch.first;
+    ch.offsB = two ? offB.data() + ch.first : nullptr;
     qmc::Counters hc;
     uint32_t kd = 0, reason = 0;
     int rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);

@@ -787,6 +787,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   uint64_t epoch = A.epoch0 - 1;
   uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
   uint32_t reason = 0, kdone = A.nsteps;
+  uint64_t tot_last = 0, tot_prev = 0;  // keys of the last two passes' outputs
   for (int32_t k = -1; k < (int32_t)A.nsteps; ++k) {
     const bool first = k < 0;
     const uint32_t s = first ? A.step0 : A.step0 + (uint32_t)k;
@@ -853,6 +854,8 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     }
     // every workgroup reads the same reduced totals and takes the same decision
     const uint64_t tot = S.dec[0], mx = S.dec[1], nin = S.dec[2], ebits = S.dec[3];
+    tot_prev = tot_last;
+    tot_last = tot;
     const bool cap_store = tot > A.cap_store, cap_in = nin > A.cap_inbox;
     if (ebits || cap_store || cap_in) {
       if (p == 0 && t == 0) {
@@ -877,6 +880,11 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     if (p == 0) {
       A.done[0] = kdone;
       A.done[1] = reason;
+      if (reason != 2 && kdone > 0) {
+        // sizes of the stores the host gathers: N(step0 + kdone), and N(step0 + kdone - 1)
+        cnt->n_store[A.cur] = tot_last;
+        if (A.nbuf == 3) cnt->n_prev = tot_prev;
+      }
     }
   }
 }

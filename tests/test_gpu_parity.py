@@ -387,6 +387,48 @@ def test_dt_error_leaves_state(B, orc):
     assert g.counters()["step"] == 10
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_call_longer_than_one_table_window(B, orc, path):
+    """8500 steps in one call: the tables come in two windows (at most 8000 steps each)."""
+    rng = np.random.default_rng(77)
+    n = 2
+    h, lops = W.random_model(n, rng, n_h=3, n_l=2)
+    keys, re, im = W.random_records(n, rng, 5, scale=2000)
+    N = 8500
+    s = np.cos(np.arange(N) / 300.0)[:, None] * np.ones((1, len(h)))
+    gam = np.abs(np.sin(np.arange(N) / 500.0))[:, None] * np.ones((1, len(lops)))
+    _say(f"8500-step call, {path}")
+    g = B.QMC(n, 2, 31, 0.002, h, lops, keys, re, im, store_capacity=64, spawn_capacity=4096)
+    g.set_path(path)
+    o = orc.Oracle(n, 2, 31, 0.002, h, lops, keys, re, im)
+    g.step(s, gam)
+    o.step(s, gam)
+    for r in range(2):
+        for x, y in zip(g.export(r), o.export(r)):
+            assert np.array_equal(x, y), f"replica {r}"
+
+
+def test_tables_larger_than_a_staging_slice(B, orc):
+    """Every Pauli monomial of n=5 in H (about 2000 terms, 34 KB per table): the host threads'
+    staging slices cannot hold all their steps, so the call runs over several table windows."""
+    rng = np.random.default_rng(5)
+    n = 5
+    h = [(x, z, (1j if bin(x & z).count("1") & 1 else 1) * 0.005 * rng.normal())
+         for x in range(32) for z in range(32)]
+    lops = [[(1 << q, 0, 0.3)] for q in range(n)]
+    N = 1024
+    s = np.ones((N, len(h))) * (1 + 0.1 * np.sin(np.arange(N) / 50))[:, None]
+    gam = np.ones((N, len(lops))) * 0.05
+    keys, re, im = W.random_records(n, rng, 8, scale=20)
+    _say("dense tables, 1024 steps, streamed")
+    g = B.QMC(n, 1, 9, 0.001, h, lops, keys, re, im, store_capacity=1024, spawn_capacity=1 << 16)
+    o = orc.Oracle(n, 1, 9, 0.001, h, lops, keys, re, im)
+    g.step(s, gam)
+    o.step(s, gam)
+    for x, y in zip(g.export(0), o.export(0)):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("bad, code", [(1, "DT"), (1537, "DT"), (2999, "ARG")])
 def test_long_call_table_error_names_first_step(B, orc, bad, code):
     """A 3000-step call builds its tables on several host threads: the first bad step is

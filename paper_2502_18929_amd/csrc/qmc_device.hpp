@@ -224,6 +224,26 @@ __device__ __forceinline__ void group_coeff(TP t, uint32_t b, uint32_t e, uint64
   cim = im;
 }
 
+// The same sum over the terms [b, e) (a multiple of kTermPad, possibly empty) of one group: a
+// slice of its terms.
+template <typename TP>
+__device__ __forceinline__ void group_coeff_part(TP t, uint32_t b, uint32_t e, uint64_t key,
+                                                 int32_t& cre, int32_t& cim) {
+  int32_t re = 0, im = 0;
+  for (uint32_t i = b; i < e; i += kTermPad) {
+#pragma unroll
+    for (int u = 0; u < kTermPad; ++u) {
+      const uint64_t zm = t[i + u].zmask;
+      const int32_t qre = t[i + u].qre, qim = t[i + u].qim;
+      const int32_t s = -(int32_t)parity64(zm & key);  // 0 or -1
+      re += (qre ^ s) - s;
+      im += (qim ^ s) - s;
+    }
+  }
+  cre = re;
+  cim = im;
+}
+
 __device__ __forceinline__ void cmul_q32(int64_t a, int64_t b, int32_t cre, int32_t cim,
                                          int64_t& xre, int64_t& xim) {
   xre = a * (int64_t)cre - b * (int64_t)cim;

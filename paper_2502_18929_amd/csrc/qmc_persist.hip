@@ -539,6 +539,93 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
   }
 }
 
+// Death deltas and children of the whole active list [0, nl) when it holds at most kPWaves / 2
+// batches of 64 parents, with J = kPWaves / batches waves on each batch: wave j of a batch takes
+// the j-th slice of the diagonal group's terms and of the off-diagonal groups.  The partial
+// diagonal coefficients are summed over the slices (integer sums, exact), and the comb of slice
+// j starts where the comb over all earlier groups would stand: the uniform plus their amounts,
+// mod 2^32 (the remainder after any run of comb steps is that sum mod 2^32), so every record
+// equals the one the single-wave comb in group order gives.  Block-uniform; uses the parent tile
+// area of LDS for the partial sums.
+__device__ __forceinline__ void process_wide(const PersistArgs& A, Shared& S, Router& R,
+                                             const LTable& tn, uint32_t nl) {
+  static_assert(sizeof(S.pa_v) >= kPBlock * sizeof(int2), "partial coefficients");
+  static_assert(sizeof(S.pa_k) >= kPBlock * sizeof(uint32_t), "partial comb amounts");
+  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
+  const uint32_t nb = (nl + kWave - 1) / kWave;
+  const uint32_t J = kPWaves / nb;
+  const uint32_t b = wave / J, j = wave % J;
+  const bool mine = b < nb;  // wave-uniform
+  int2* dpart = S.pa_v;
+  uint32_t* cpart = reinterpret_cast<uint32_t*>(S.pa_k);
+  const uint32_t i = b * kWave + lane;
+  const bool valid = mine && i < nl;
+  const uint64_t ck = valid ? S.act_k[i] : 0;
+  const int2 v = valid ? S.act_v[i] : make_int2(0, 0);
+  const uint2 w = valid ? S.act_w[i] : make_uint2(0, 0);
+  const int64_t qs = valid ? S.act_s[i] : 0;
+  const uint64_t key = A.kl.key(ck);
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+  const uint32_t G = tn.h->n_groups;
+  const bool dact = valid && !comb_all_zero(sab, tn.h->q_diag + uabs64(qs), w.y);
+  const bool act = valid && G > 1 && !comb_all_zero(sab, tn.h->q_off, w.x);
+  const uint32_t nd = tn.gs[1] / kTermPad;
+  const uint32_t d0 = nd * j / J * kTermPad, d1 = nd * (j + 1) / J * kTermPad;
+  const uint32_t g0 = 1 + (G - 1) * j / J, g1 = 1 + (G - 1) * (j + 1) / J;
+  int32_t pre = 0, pim = 0;
+  if (__ballot(dact) && dact) group_coeff_part(tn.t, d0, d1, key, pre, pim);
+  uint32_t amt = 0;
+  if (__ballot(act) && act) {
+    for (uint32_t g = g0; g < g1; ++g) {
+      int32_t cre, cim;
+      group_coeff(tn.t, tn.gs[g], tn.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      amt += (uint32_t)uabs64(xre) + (uint32_t)uabs64(xim);
+    }
+  }
+  if (mine) {
+    dpart[wave * kWave + lane] = make_int2(pre, pim);
+    cpart[wave * kWave + lane] = amt;
+  }
+  __syncthreads();
+  if (mine && j == 0 && __ballot(dact)) {
+    int2 d = make_int2(0, 0);
+    if (dact) {
+      int32_t dre = 0, dim = 0;
+      for (uint32_t jj = 0; jj < J; ++jj) {
+        const int2 pp = dpart[(b * J + jj) * kWave + lane];
+        dre += pp.x;
+        dim += pp.y;
+      }
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
+      uint64_t r = w.y;
+      d.x = (int32_t)comb_step(r, xre);
+      d.y = (int32_t)comb_step(r, xim);
+    }
+    R.emit((d.x | d.y) != 0, ck, d);
+  }
+  if (mine && __ballot(act)) {
+    uint32_t r0 = w.x;
+    for (uint32_t jj = 0; jj < j; ++jj) r0 += cpart[(b * J + jj) * kWave + lane];
+    uint64_t r = r0;
+    for (uint32_t g = g0; g < g1; ++g) {
+      int2 child = make_int2(0, 0);
+      if (act) {
+        int32_t cre, cim;
+        group_coeff(tn.t, tn.gs[g], tn.gs[g + 1], key, cre, cim);
+        int64_t xre, xim;
+        cmul_q32(v.x, v.y, cre, cim, xre, xim);
+        child.x = (int32_t)comb_step(r, xre);
+        child.y = (int32_t)comb_step(r, xim);
+      }
+      R.emit((child.x | child.y) != 0, ck ^ tn.gx[g], child);
+    }
+  }
+  __syncthreads();
+}
+
 // Draw Philox (stream `stream`) for the records [o0, o1) of (seg_k, seg_v) at step `step` and
 // route their diagonal deltas and children under table tn with shifts qsh.  The parents that can produce a nonzero amount are
 // compacted over the whole workgroup into a list, which is processed in full 64-parent batches
@@ -592,9 +679,14 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
     if (end || nl >= (uint32_t)kPBlock) {
       // full batches now (all of them at the end), the rest moves to the front of the list
       const uint32_t nb = end ? (nl + kWave - 1) / kWave : nl / kWave;
-      for (uint32_t b = wave; b < nb; b += kPWaves) {
-        const uint32_t b0 = b * kWave;
-        process_active(A, S, R, tn, b0, nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave);
+      if (end && nb <= (uint32_t)kPWaves / 2) {
+        if (nb > 0) process_wide(A, S, R, tn, nl);  // few batches: several waves on each
+      } else {
+        for (uint32_t b = wave; b < nb; b += kPWaves) {
+          const uint32_t b0 = b * kWave;
+          process_active(A, S, R, tn, b0,
+                         nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave);
+        }
       }
       const uint32_t done = nb * kWave < nl ? nb * kWave : nl;
       const uint32_t rest = nl - done;

@@ -95,7 +95,7 @@ bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
   L.sort_status = take(L.n_sort_status * 8);
   L.status = take(L.max_tiles * 8);
   L.splits = take((L.max_tiles + 1) * 8);
-  L.tab = take(kTableArea);
+  L.tab = take(kTableArea + kPersistTableBytes);  // slack: the fused kernel reads 8 KB
   L.qshift = take((size_t)c.n_replicas * 2 * 8);  // first / only term, then the second AB2 term
   L.obs_out = take((size_t)c.n_replicas * (5 + 2 * kMaxPauli) * 8);
   L.obs_in = take((size_t)kMaxPauli * 16);
@@ -112,7 +112,7 @@ bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
   L.split = take((size_t)P * 8);
   L.tab_off = take((size_t)kMaxChunkSteps * 4);
   L.tabB_off = take((size_t)kMaxChunkSteps * 4);
-  L.slots = take((size_t)P * 4 * 8);
+  L.slots = take((size_t)2 * P * 4 * 8);
   L.done = take(8);
   L.total = o;
   return true;
@@ -555,7 +555,7 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   // zero counters, then the initial store (replica tag in the high bits)
   e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
   if (e == hipSuccess)
-    e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)c->L.P * 4 * 8, c->stream);
+    e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)2 * c->L.P * 4 * 8, c->stream);
   if (e != hipSuccess) {
     qmc_destroy(c);
     return QMC_ERR_HIP;

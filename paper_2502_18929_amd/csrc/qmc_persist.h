@@ -35,7 +35,7 @@ struct PersistLaunch {
   uint32_t n_replicas;
   const int64_t* qshift;     // per-replica Q32 shifts of the first / only term
   const int64_t* qshiftB;    // AB2: of the second term
-  uint64_t* slots;      // [P][4] epoch-tagged per-workgroup barrier slots (zeroed once)
+  uint64_t* slots;      // [2][P][4] epoch-tagged per-workgroup barrier slots (zeroed once)
   uint64_t epoch0;      // first barrier epoch of the launch
   uint64_t cap_store;
   uint64_t cap_inbox;

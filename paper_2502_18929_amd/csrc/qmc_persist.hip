@@ -62,7 +62,8 @@ struct PersistArgs {
   const int64_t* qshift;    // per-replica Q32 shifts of the first term (Euler: the only one)
   const int64_t* qshiftB;   // AB2: of the second term
   // synchronization and reporting
-  uint64_t* slots;        // [P][4] per workgroup: epoch, keys out, inbox records, error bits
+  uint64_t* slots;        // [2][P][4] barrier slots by epoch parity: keys out, inbox records,
+                          // error bits, each tagged with the epoch
   uint64_t cap_store;     // total occupied keys allowed
   uint64_t cap_inbox;     // total inbox records allowed per step
   uint32_t rebal_min;     // stop to rebalance when the largest range exceeds 1.25 x mean + this
@@ -137,44 +138,49 @@ __device__ __forceinline__ void raise_err(Counters* cnt, uint32_t* my_err, uint3
 }
 
 // Grid-wide barrier with reduction over the co-resident workgroups of a cooperative launch.
-// Each workgroup publishes (epoch, keys out, inbox records, error bits) in its own slot and then
-// reads every slot itself (one thread per slot) until all carry this epoch, reducing the values
+// Each workgroup publishes (keys out, inbox records, error bits) in its own slot and then reads
+// every slot itself (one thread per slot) until all carry this epoch, reducing the values
 // locally: two memory round trips, no master workgroup, identical totals everywhere (S.dec).
-// All cross-workgroup writes before the barrier are agent-scope atomics, so publishing only waits
-// for their completion.  Waits are bounded: on expiry the totals carry kErrLookback and false is
-// returned.
+// Every slot word carries the low 32 bits of the epoch above its 32-bit value, so a word is
+// valid on its own and the three are published without ordering waits; slots alternate between
+// two buffers by epoch parity, so a workgroup that has passed this barrier and publishes the
+// next one never overwrites a slot another workgroup may still be reading.  All cross-workgroup
+// writes before the barrier are agent-scope atomics, so publishing only waits for their
+// completion.  Waits are bounded: on expiry the totals carry kErrLookback and false is returned.
 __device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint64_t epoch,
                                           uint64_t nout, uint64_t nin) {
   const uint32_t t = threadIdx.x, p = blockIdx.x, P = A.P;
   wait_mem();
   __syncthreads();
+  const uint64_t tag = (epoch & 0xFFFFFFFFull) << 32;
+  uint64_t* const buf = A.slots + (epoch & 1u) * 4 * (uint64_t)P;
   if (t == 0) {
-    uint64_t* sl = A.slots + 4 * (uint64_t)p;
-    st_agent(&sl[1], nout);
-    st_agent(&sl[2], nin);
-    st_agent(&sl[3], (uint64_t)S.err);
-    wait_mem();
-    st_agent(&sl[0], epoch);
+    uint64_t* sl = buf + 4 * (uint64_t)p;
+    st_agent(&sl[0], tag | (nout < 0xFFFFFFFFull ? nout : 0xFFFFFFFFull));
+    st_agent(&sl[1], tag | (nin < 0xFFFFFFFFull ? nin : 0xFFFFFFFFull));
+    st_agent(&sl[2], tag | (uint64_t)S.err);
   }
   uint64_t tot = 0, mx = 0, nn = 0, er = 0;
   for (uint32_t q = t; q < P; q += kPBlock) {
-    const uint64_t* sl = A.slots + 4 * (uint64_t)q;
+    const uint64_t* sl = buf + 4 * (uint64_t)q;
     uint32_t spins = 0;
-    while (ld_agent(&sl[0]) < epoch) {
+    uint64_t v0, v1, v2;
+    while (true) {
+      v0 = ld_agent(&sl[0]);
+      v1 = ld_agent(&sl[1]);
+      v2 = ld_agent(&sl[2]);
+      if (((v0 ^ tag) | (v1 ^ tag) | (v2 ^ tag)) >> 32 == 0) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 24)) {
         er |= kErrLookback;
         break;
       }
     }
-    wait_mem();
-    const uint64_t v1 = ld_agent(&sl[1]);
-    const uint64_t v2 = ld_agent(&sl[2]);
-    const uint64_t v3 = ld_agent(&sl[3]);
-    tot += v1;
-    mx = v1 > mx ? v1 : mx;
-    nn += v2;
-    er |= v3;
+    v0 &= 0xFFFFFFFFull;
+    tot += v0;
+    mx = v0 > mx ? v0 : mx;
+    nn += v1 & 0xFFFFFFFFull;
+    er |= v2 & 0xFFFFFFFFull;
   }
   for (int o = 32; o > 0; o >>= 1) {
     tot += __shfl_xor(tot, o);
@@ -880,31 +886,51 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
   uint32_t reason = 0, kdone = A.nsteps;
   uint64_t tot_last = 0, tot_prev = 0;  // keys of the last two passes' outputs
+  static_assert(kPersistTableBytes / 16 == kPBlock, "one table word per thread");
+  // table offsets of the current pass, loaded one pass ahead; the table of pass k is the one of
+  // step s + 1 (step0 on the first pass, step s itself on the last, which spawns nothing)
+  auto tab_index = [&](int32_t kk) -> uint32_t {
+    return kk + 1 == (int32_t)A.nsteps ? (uint32_t)kk : (uint32_t)(kk + 1);
+  };
+  uint32_t offA = A.tab_off[tab_index(-1)];
+  uint32_t offB = A.tabB_off && A.nsteps > 0 ? A.tabB_off[0] : 0u;
+  uint64_t np_next = 0;  // keys this workgroup wrote in the previous pass
   for (int32_t k = -1; k < (int32_t)A.nsteps; ++k) {
     const bool first = k < 0;
     const uint32_t s = first ? A.step0 : A.step0 + (uint32_t)k;
     const uint32_t par = (uint32_t)k & 1u;  // 1 for the first pass
-    // inbox of this step -> LDS, sorted (empty on the first pass: zeroed before the launch)
+    const bool last = k + 1 == (int32_t)A.nsteps;
+    const uint32_t ob = (uint32_t)(k + 1) % A.nbuf, ib = (ob + A.nbuf - 1) % A.nbuf;
+    const bool two = A.tabB_off && !last && (!first || A.pk_prev);
+    // One round of independent loads: the inbox count with the first kPBlock inbox records
+    // (read before the count is known; the ones past it are dropped), the step tables (a whole
+    // table area per thread block: the device area has that much slack past its end) and the
+    // table offsets of the next pass.
+    const uint64_t* ibk = A.ik + ((uint64_t)par * P + p) * A.incap;
+    const int2* ibv = A.iv + ((uint64_t)par * P + p) * A.incap;
     const uint32_t c_raw = ld_agent(&A.in_n[par * P + p]);
+    uint64_t k0 = 0;
+    int2 v0 = make_int2(0, 0);
+    if (t < A.incap) {
+      k0 = ld_agent(&ibk[t]);
+      v0 = ld_agent(&ibv[t]);
+    }
+    S.tab[t] = reinterpret_cast<const uint4*>(A.tab_base + offA)[t];
+    if (two) S.tabB[t] = reinterpret_cast<const uint4*>(A.tab_base + offB)[t];
+    if (k + 1 < (int32_t)A.nsteps) {
+      offA = A.tab_off[tab_index(k + 1)];
+      if (A.tabB_off && k + 2 < (int32_t)A.nsteps) offB = A.tabB_off[k + 2];
+    }
+    // inbox of this step -> LDS, sorted (empty on the first pass: zeroed before the launch)
     const uint32_t c = c_raw < A.incap ? c_raw : A.incap;
     if (t == 0 && c_raw > A.incap) raise_err(cnt, &S.err, kErrInbox, s);
     uint32_t m2 = 1;
     while (m2 < c) m2 <<= 1;
-    const uint64_t* ibk = A.ik + ((uint64_t)par * P + p) * A.incap;
-    const int2* ibv = A.iv + ((uint64_t)par * P + p) * A.incap;
-    const bool last = k + 1 == (int32_t)A.nsteps;
-    const uint32_t ob = (uint32_t)(k + 1) % A.nbuf, ib = (ob + A.nbuf - 1) % A.nbuf;
-    // tables of the spawns drawn in this pass (step s + 1; step0 on the first pass) -> LDS
-    const uint4* tg = reinterpret_cast<const uint4*>(A.tab_base + A.tab_off[last ? k : k + 1]);
-    const uint32_t tw = reinterpret_cast<const TableHeader*>(tg)->bytes / 16;
-    for (uint32_t i = t; i < tw; i += kPBlock) S.tab[i] = tg[i];
-    const bool two = A.tabB_off && !last && (!first || A.pk_prev);
-    if (two) {
-      const uint4* tb = reinterpret_cast<const uint4*>(A.tab_base + A.tabB_off[k + 1]);
-      const uint32_t tbw = reinterpret_cast<const TableHeader*>(tb)->bytes / 16;
-      for (uint32_t i = t; i < tbw; i += kPBlock) S.tabB[i] = tb[i];
+    if (t < m2) {
+      S.in_k[t] = t < c ? k0 : ~0ull;
+      S.in_v[t] = t < c ? v0 : make_int2(0, 0);
     }
-    for (uint32_t i = t; i < m2; i += kPBlock) {
+    for (uint32_t i = t + kPBlock; i < m2; i += kPBlock) {
       S.in_k[i] = i < c ? ld_agent(&ibk[i]) : ~0ull;
       S.in_v[i] = i < c ? ld_agent(&ibv[i]) : make_int2(0, 0);
     }
@@ -912,7 +938,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     if (t == 0) st_agent(&A.in_n[par * P + p], 0u);  // refilled during pass k+1 (for k+2)
     if (c > 1) sort_inbox(S, m2, c, packed);  // the c real records first, then the padding
     // parents: the canonical slice, or the segment written by the previous pass
-    const uint64_t np_k = first ? ce - cb : A.seg_n[ib * P + p];
+    const uint64_t np_k = first ? ce - cb : np_next;
     const uint64_t* pk = first ? A.ck + cb : A.sk + ((uint64_t)ib * P + p) * A.segcap;
     const int2* pv = first ? A.cv + cb : A.sv + ((uint64_t)ib * P + p) * A.segcap;
     uint64_t* okp = A.sk + ((uint64_t)ob * P + p) * A.segcap;
@@ -929,8 +955,9 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       advance(A, S, R, tnB, A.qshiftB, 1u, A.pk_prev + qb, A.pv_prev + qb, 0, qe - qb, nstep);
       __syncthreads();
     }
+    np_next = nout <= A.segcap ? nout : 0;
     if (t == 0) {
-      A.seg_n[ob * P + p] = (uint32_t)(nout <= A.segcap ? nout : 0);
+      A.seg_n[ob * P + p] = (uint32_t)np_next;
       if (!first) {
         st_w += wsum;
         st_k += np_k;

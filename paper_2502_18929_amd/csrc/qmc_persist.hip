@@ -426,10 +426,12 @@ struct Router {
       val[c] = has[c] ? sv[i] : make_int2(0, 0);
       q[c] = 0;
     }
-    // destination: the largest p with split[p] <= key (split[0] == 0)
+    // destination: the largest p with split[p] <= key (split[0] == 0); chunks past the fill
+    // are skipped (wave-uniform)
     for (uint32_t st = pbits ? 1u << (pbits - 1) : 0u; st > 0; st >>= 1) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
+        if ((uint32_t)c * kWave >= fill) break;
         const uint32_t cand = q[c] + st;
         if (cand < P && split[cand] <= key[c]) q[c] = cand;
       }
@@ -442,6 +444,8 @@ struct Router {
     uint32_t rank[NC], pidx[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      rank[c] = pidx[c] = 0;
+      if ((uint32_t)c * kWave >= fill) continue;
       uint64_t peers = __ballot(has[c]);
       for (uint32_t b = 0; b < pbits; ++b) {
         const uint64_t bm = __ballot((q[c] >> b) & 1u);

@@ -294,9 +294,11 @@ __device__ __forceinline__ void run_split(const KA& A, uint32_t na, const KB& B,
     const uint64_t c = B(j - 1);
     if (i == 0 || c > last) last = c;
   }
-  // Only children can continue the run (a parent equal to `last` would precede it).
-  uint32_t lo = j, hi = nb;
-  if (hi - lo > (uint32_t)kMergeSlack) hi = lo + kMergeSlack;
+  // Only children can continue the run (a parent equal to `last` would precede it); most
+  // splits do not fall inside a run, which the first probe settles.
+  if (j >= nb || B(j) > last) return;
+  uint32_t lo = j + 1, hi = nb;
+  if (hi - j > (uint32_t)kMergeSlack) hi = j + kMergeSlack;
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
     if (B(mid) <= last)

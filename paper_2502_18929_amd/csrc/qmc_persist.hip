@@ -78,6 +78,7 @@ struct Shared {
   uint64_t pa_k[kPTile];
   int2 pa_v[kPTile];
   uint32_t scan[kPBlock];
+  uint32_t xsplit[kPBlock];  // merge-path split of each thread: parent index | inbox index << 16
   uint64_t act_k[kActCap];   // active new parents: key, value, comb words (w0, w1), shift
   int2 act_v[kActCap];
   uint2 act_w[kActCap];
@@ -273,6 +274,19 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t k, bool desc) {
 // Wider keys take a bitonic network on the records in LDS.
 __device__ __forceinline__ void sort_inbox(Shared& S, uint32_t m, uint32_t c, bool packed) {
   const uint32_t t = threadIdx.x, wave = t / kWave, lane = __lane_id();
+  if (packed && c <= (uint32_t)kWave) {
+    // one chunk: wave 0 sorts it in registers and puts the records in place
+    if (wave == 0) {
+      const uint64_t wd = wave_sort64(lane < c ? (S.in_k[lane] << 12) | lane : ~0ull, false);
+      const int2 v = lane < c ? S.in_v[wd & 0xFFFu] : make_int2(0, 0);
+      if (lane < c) {
+        S.in_k[lane] = wd >> 12;
+        S.in_v[lane] = v;
+      }
+    }
+    __syncthreads();
+    return;
+  }
   if (packed && c <= 2u * kPBlock) {
     const uint32_t nch = (c + kWave - 1) / kWave;  // <= 16 chunks of 64 words in S.pa_k
     for (uint32_t ch = wave; ch < nch; ch += kPWaves) {
@@ -763,13 +777,18 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
     auto KB = [&](uint32_t x) { return ck[x]; };
     const uint32_t tot = pn + cn;
     const uint32_t per = (tot + kPBlock - 1) / kPBlock;
-    uint32_t d0 = t * per, d1 = d0 + per;
+    uint32_t d0 = t * per;
     if (d0 > tot) d0 = tot;
-    if (d1 > tot) d1 = tot;
+    // this thread's end is the next thread's start (one search per thread)
     uint32_t i0, j0, i1, j1;
     run_split(KA, pn, KB, cn, d0, i0, j0);
-    run_split(KA, pn, KB, cn, d1, i1, j1);
-    if (t == kPBlock - 1) {
+    S.xsplit[t] = i0 | (j0 << 16);
+    __syncthreads();
+    if (t + 1 < (uint32_t)kPBlock) {
+      const uint32_t nx = S.xsplit[t + 1];
+      i1 = nx & 0xFFFFu;
+      j1 = nx >> 16;
+    } else {
       i1 = pn;
       j1 = cn;
     }

@@ -76,6 +76,7 @@ def lib():
                                        P(ctypes.c_int)]
         L.orc_pulse.argtypes = [ctypes.c_void_p, u64, u64]
         L.orc_set_shift.argtypes = [ctypes.c_void_p, u32, dbl]
+        L.orc_set_initiator.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.orc_counters.argtypes = [ctypes.c_void_p, P(u64), P(u64), P(u64), P(u64)]
         L.orc_counters.restype = None
         L.orc_get_step.argtypes = [ctypes.c_void_p]
@@ -245,6 +246,11 @@ class Oracle:
 
     def set_shift(self, replica, shift):
         _check(lib().orc_set_shift(self._ctx, int(replica), float(shift)), "set_shift")
+
+    def set_initiator(self, min_walkers):
+        """Initiator approximation (End Matter on simulation methodology, reading R17): parents
+        with |re| + |im| < min_walkers spawn only onto keys occupied in N(s); 0 = off."""
+        _check(lib().orc_set_initiator(self._ctx, int(min_walkers)), "set_initiator")
 
     def counters(self):
         w, k, ch, mx = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

@@ -22,6 +22,13 @@
  *      s_m(t_s) and gamma_k(t_s) per step.
  *  R6  No population control by default (the Liouvillian is trace preserving, so the paper uses
  *      none); an optional constant diagonal shift S per replica enters death as L_diag + S.
+ *  R17 Initiator approximation (End Matter on simulation methodology, last paragraph): a parent
+ *      is an initiator when its population |re| + |im| is at least a threshold (the caller's
+ *      xi * N^diag, rounded up to whole walkers); every record a non-initiator spawns onto a key
+ *      that is not occupied in N(s) is discarded.  "Occupied" means present in N(s), the vector
+ *      being advanced, before annihilation; the rule covers the second AB2 term too (parents
+ *      from N(s-1), targets checked against N(s)); death on the parent's own key in N(s) is
+ *      never discarded.  Threshold 0 = off.
  *
  * Floating point: the only FP64 arithmetic is the coefficient quantization, done in a fixed
  * operation order (compile with -ffp-contract=off).  Everything the walkers touch is integer.
@@ -115,6 +122,10 @@ struct orc_ctx {
   store_t* prev;         /* [R] */
   double* w_prev;        /* [n_h + n_l] */
   int have_prev;         /* N(s-1) and w_prev are valid (false at step 0: Euler first step) */
+  /* Initiator approximation (End Matter on simulation methodology, last paragraph): a parent
+   * whose population |re| + |im| is below init_min is not an initiator, and the records it
+   * spawns onto keys absent from N(s) are discarded.  0 = off (every parent spawns). */
+  uint64_t init_min;
 };
 
 /* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
@@ -499,9 +510,23 @@ static int cmp_rec(const void* a, const void* b) {
  *    when nonzero (the second AB2 term adds to N(s+1), it does not carry N(s-1) over);
  *  - off-diagonal (spawn, reading R3): every group in table order, Re then Im, one comb with w0,
  *    a record (key ^ xmask, n_re, n_im) when nonzero. */
+static int occupied(const store_t* st, uint64_t key) {
+  uint64_t lo = 0, hi = st->n;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (st->key[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < st->n && st->key[lo] == key;
+}
+
+/* `occ` is N(s), the vector being advanced: with the initiator approximation a record from a
+ * non-initiator parent survives only on a key occupied there. */
 static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const table_t* T,
-                       int64_t qs_re, uint32_t stream, int keep_parent, rec_t* rec,
-                       uint64_t* nr) {
+                       int64_t qs_re, uint32_t stream, int keep_parent, const store_t* occ,
+                       rec_t* rec, uint64_t* nr) {
   const uint32_t G = T->n_groups;
   int64_t* xs = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
   int64_t* ns = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
@@ -518,6 +543,8 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
     const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step, (r << 8) | stream};
     uint32_t w[4];
     orc_philox4x32_10(ctr, pkey, w);
+    const int initiator =
+        c->init_min == 0 || (uint64_t)(llabs(a) + llabs(b)) >= c->init_min;
 
     int64_t dre, dim;
     group_coeff(T, 0, key, &dre, &dim);
@@ -527,7 +554,7 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
     orc_comb(2, x2, w[1], n2);
     if (keep_parent)
       rec[(*nr)++] = (rec_t){key, a + n2[0], b + n2[1]};
-    else if (n2[0] != 0 || n2[1] != 0)
+    else if ((n2[0] != 0 || n2[1] != 0) && (initiator || occupied(occ, key)))
       rec[(*nr)++] = (rec_t){key, n2[0], n2[1]};
 
     for (uint32_t g = 1; g < G; ++g) {
@@ -539,7 +566,9 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
     if (G > 1) orc_comb(2 * (G - 1), xs, w[0], ns);
     for (uint32_t g = 1; g < G; ++g) {
       int64_t cr = ns[2 * (g - 1)], ci = ns[2 * (g - 1) + 1];
-      if (cr != 0 || ci != 0) rec[(*nr)++] = (rec_t){key ^ T->gx[g], cr, ci};
+      const uint64_t target = key ^ T->gx[g];
+      if ((cr != 0 || ci != 0) && (initiator || occupied(occ, target)))
+        rec[(*nr)++] = (rec_t){target, cr, ci};
     }
   }
   free(xs);
@@ -563,8 +592,8 @@ static int step_replica(const orc_ctx* c, uint32_t r, const table_t* A, int64_t 
   rec_t* rec = (rec_t*)malloc(cap * sizeof(rec_t));
   if (!rec) return ORC_ERR_NOMEM;
   uint64_t nr = 0;
-  int rc = add_records(c, r, in, A, qa, 0u, 1, rec, &nr);
-  if (!rc && B) rc = add_records(c, r, pv, B, qb, 1u, 0, rec, &nr);
+  int rc = add_records(c, r, in, A, qa, 0u, 1, in, rec, &nr);
+  if (!rc && B) rc = add_records(c, r, pv, B, qb, 1u, 0, in, rec, &nr);
   if (rc) {
     free(rec);
     return rc;
@@ -789,6 +818,11 @@ int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z) {
   }
   /* AB2 (reading: a pulse restarts the two-step formula): the next step is an Euler step. */
   c->have_prev = 0;
+  return ORC_OK;
+}
+
+int orc_set_initiator(orc_ctx* c, uint64_t min_walkers) {
+  c->init_min = min_walkers;
   return ORC_OK;
 }
 

@@ -96,6 +96,9 @@ int orc_export_prev(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t*
 int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z);
 /* Constant diagonal shift S added to the death coefficient (0 = none, the paper's setting). */
 int orc_set_shift(orc_ctx* c, uint32_t replica, double shift);
+/* Initiator approximation (End Matter on simulation methodology): parents with |re| + |im| below
+ * min_walkers spawn only onto keys occupied in N(s) (reading R17).  0 = off. */
+int orc_set_initiator(orc_ctx* c, uint64_t min_walkers);
 
 uint32_t orc_get_step(const orc_ctx* c);
 /* Sums over all steps so far and all replicas of the parents' N^tot, of their occupied keys and

@@ -551,3 +551,139 @@ def test_ab2_dense_map_is_second_order(orc):
     e1, e2 = err(1, dense.ab2_map), err(2, dense.ab2_map)
     assert e1 < 0.2 * e_euler, (e1, e_euler)
     assert 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+# --- Initiator approximation (End Matter on simulation methodology, reading R17) -------------
+
+def _dense_vec(o, r, D2):
+    k, a, b = o.export(r)
+    v = np.zeros(D2, dtype=np.int64), np.zeros(D2, dtype=np.int64)
+    v[0][k.astype(np.int64)] = a
+    v[1][k.astype(np.int64)] = b
+    return v
+
+
+def _mixed_records(n, rng, count, T):
+    """Sorted unique keys, about half of them with populations below the threshold T and the
+    others at or above it."""
+    keys, re, im = W.random_records(n, rng, count, scale=T // 4)
+    big = rng.random(len(keys)) < 0.5
+    big[0], big[-1] = True, False
+    re = np.where(big, np.sign(re + 0.5).astype(np.int32) * (T + rng.integers(0, 2 * T, len(keys))),
+                  re).astype(np.int32)
+    # populations exactly at the threshold and one walker below it
+    re[1], im[1] = T // 2, -(T - T // 2)
+    re[2], im[2] = -(T - 1), 0
+    return keys, re, im
+
+
+def _one_step(orc, n, R, seed, dt, h, lops, s, g, cur, prev=None, T=0, integ="euler"):
+    keys, re, im = cur
+    o = orc.Oracle(n, R, seed, dt, h, lops, keys, re, im, integrator=integ)
+    for r in range(R):
+        o.import_(r, keys, re, im, step=11)
+        if prev is not None:
+            o.set_prev(r, *prev[:3], prev[3], prev[4])
+    o.set_initiator(T)
+    o.step(s[None, :], g[None, :])
+    return o
+
+
+def _restrict(rec, T):
+    keys, re, im = rec
+    keep = (np.abs(re.astype(np.int64)) + np.abs(im.astype(np.int64))) >= T
+    return keys[keep], re[keep], im[keep]
+
+
+@pytest.mark.parametrize("T", [0, 1])
+def test_initiator_threshold_zero_or_one_is_the_plain_step(orc, T):
+    """Threshold 0 (off) or 1 (every nonzero parent is an initiator): the plain trajectory."""
+    rng = np.random.default_rng(61)
+    n = 3
+    h, lops = W.random_model(n, rng, n_h=5, n_l=3)
+    keys, re, im = W.random_records(n, rng, 9, scale=200)
+    s = rng.normal(size=(40, len(h)))
+    g = np.abs(rng.normal(size=(40, len(lops))))
+    a = orc.Oracle(n, 3, 5, 0.02, h, lops, keys, re, im)
+    b = orc.Oracle(n, 3, 5, 0.02, h, lops, keys, re, im)
+    b.set_initiator(T)
+    a.step(s, g)
+    b.step(s, g)
+    for r in range(3):
+        for x, y in zip(a.export(r), b.export(r)):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_initiator_step_decomposes_into_plain_steps(orc, seed):
+    """One Euler step with threshold T equals, on keys occupied in N(s), the plain step of N(s),
+    and on every other key the plain step of N(s) restricted to its initiators (Philox is keyed
+    on the walker's key, so the draws are the same in all three runs)."""
+    rng = np.random.default_rng(300 + seed)
+    n = 3
+    D2 = 1 << (2 * n)
+    h, lops = W.random_model(n, rng, n_h=6, n_l=3, max_l_terms=2)
+    T = 60
+    cur = _mixed_records(n, rng, 14, T)
+    s = rng.normal(size=len(h))
+    g = np.abs(rng.normal(size=len(lops)))
+    R = 4
+    a = _one_step(orc, n, R, 17, 0.01, h, lops, s, g, cur, T=T)
+    b = _one_step(orc, n, R, 17, 0.01, h, lops, s, g, cur)
+    c = _one_step(orc, n, R, 17, 0.01, h, lops, s, g, _restrict(cur, T))
+    occ = np.zeros(D2, dtype=bool)
+    occ[cur[0].astype(np.int64)] = True
+    assert 0 < (_restrict(cur, T)[0].size) < cur[0].size
+    for r in range(R):
+        va, vb, vc = _dense_vec(a, r, D2), _dense_vec(b, r, D2), _dense_vec(c, r, D2)
+        for p in range(2):
+            assert np.array_equal(va[p][occ], vb[p][occ])
+            assert np.array_equal(va[p][~occ], vc[p][~occ])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_initiator_ab2_step_decomposes_into_plain_steps(orc, seed):
+    """The same decomposition for an AB2 step: the second term's parents come from N(s-1) and
+    are initiators by their own population there; targets are checked against N(s)."""
+    rng = np.random.default_rng(400 + seed)
+    n = 3
+    D2 = 1 << (2 * n)
+    h, lops = W.random_model(n, rng, n_h=6, n_l=3)
+    T = 60
+    cur = _mixed_records(n, rng, 12, T)
+    prv = _mixed_records(n, rng, 12, T)
+    s1, s0 = rng.normal(size=len(h)), rng.normal(size=len(h))
+    g1, g0 = np.abs(rng.normal(size=len(lops))), np.abs(rng.normal(size=len(lops)))
+    R = 3
+    kw = dict(integ="ab2")
+    a = _one_step(orc, n, R, 23, 0.01, h, lops, s1, g1, cur, prev=(*prv, s0, g0), T=T, **kw)
+    b = _one_step(orc, n, R, 23, 0.01, h, lops, s1, g1, cur, prev=(*prv, s0, g0), **kw)
+    c = _one_step(orc, n, R, 23, 0.01, h, lops, s1, g1, _restrict(cur, T),
+                  prev=(*_restrict(prv, T), s0, g0), **kw)
+    occ = np.zeros(D2, dtype=bool)
+    occ[cur[0].astype(np.int64)] = True
+    for r in range(R):
+        va, vb, vc = _dense_vec(a, r, D2), _dense_vec(b, r, D2), _dense_vec(c, r, D2)
+        for p in range(2):
+            assert np.array_equal(va[p][occ], vb[p][occ])
+            assert np.array_equal(va[p][~occ], vc[p][~occ])
+
+
+def test_initiator_without_initiators_never_grows_the_support(orc):
+    """With a threshold above every population, no record reaches a new key: the occupied set
+    of N(s+1) is a subset of that of N(s), step after step."""
+    rng = np.random.default_rng(71)
+    n = 3
+    h, lops = W.random_model(n, rng, n_h=6, n_l=3)
+    keys, re, im = W.random_records(n, rng, 10, scale=300)
+    o = orc.Oracle(n, 2, 3, 0.01, h, lops, keys, re, im)
+    o.set_initiator(1 << 40)
+    s = rng.normal(size=(30, len(h)))
+    g = np.abs(rng.normal(size=(30, len(lops))))
+    prev = [set(o.export(r)[0].tolist()) for r in range(2)]
+    for k in range(30):
+        o.step(s[k:k + 1], g[k:k + 1])
+        for r in range(2):
+            now = set(o.export(r)[0].tolist())
+            assert now <= prev[r]
+            prev[r] = now

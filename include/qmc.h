@@ -151,6 +151,16 @@ int qmc_pulse(qmc_ctx* ctx, uint64_t x, uint64_t z);
  * none (the Liouvillian is trace preserving); S != 0 biases the estimator. */
 int qmc_set_shift(qmc_ctx* ctx, uint32_t replica, double shift);
 
+/* Initiator approximation (End Matter on simulation methodology, last paragraph): from the next
+ * step on, a parent whose population |re| + |im| is below min_walkers (the caller's
+ * xi * N^diag rounded up to whole walkers) is not an initiator, and every record it spawns onto
+ * a key that is not occupied in N(s) is discarded; death on its own key always counts.  With
+ * AB2 the second term's parents are judged by their population in N(s-1), their targets
+ * against N(s).  0 turns it off (the default: the plain step).  The rule is applied where the
+ * records are merged: a routed record's key carries one flag bit below the composite key.
+ * Errors: QMC_ERR_ARG when 2n + replica bits leave no bit for the flag (2n + bits > 63). */
+int qmc_set_initiator(qmc_ctx* ctx, uint64_t min_walkers);
+
 typedef struct {
   uint32_t n_pauli;          /* observables P = X^px Z^pz: sum_i (-1)^popc(pz&i) N_{i,i^px} */
   const uint64_t* px;

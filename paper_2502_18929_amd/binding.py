@@ -25,7 +25,7 @@ QMC_ERR_STATE = -8
 
 EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_set_integrator", "qmc_set_prev", "qmc_export_prev", "qmc_pulse",
-            "qmc_set_shift", "qmc_observe", "qmc_export", "qmc_import", "qmc_counters",
+            "qmc_set_shift", "qmc_set_initiator", "qmc_observe", "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
             "qmc_destroy"]
 
@@ -91,6 +91,7 @@ def lib():
         L.qmc_step.argtypes = [vp, u32, P(dbl), P(dbl)]
         L.qmc_pulse.argtypes = [vp, u64, u64]
         L.qmc_set_shift.argtypes = [vp, u32, dbl]
+        L.qmc_set_initiator.argtypes = [vp, ctypes.c_uint64]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
         L.qmc_export.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.qmc_import.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, u32]
@@ -232,6 +233,11 @@ class QMC:
     def set_shift(self, replica, shift):
         self._check(lib().qmc_set_shift(self._ctx, int(replica), float(shift)))
 
+    def set_initiator(self, min_walkers):
+        """Initiator approximation: parents with |re| + |im| < min_walkers spawn only onto keys
+        occupied in N(s); 0 = off.  initiator_threshold(xi, n_diag) gives ceil(xi * N^diag)."""
+        self._check(lib().qmc_set_initiator(self._ctx, int(min_walkers)))
+
     def observe(self, pauli=(), psi=(), want_eps=False):
         R = self.R
         npl = len(pauli)
@@ -338,6 +344,16 @@ class QMC:
         cov = dict(steps=st.step, walker_steps=st.walker_steps, key_steps=st.key_steps,
                    child_steps=st.child_steps, out_steps=st.out_steps)
         return ms.value, n.value, cov
+
+def initiator_threshold(xi, n_diag):
+    """The initiator threshold in whole walkers for a fraction xi of N^diag (rounded up, exact
+    for the decimal fractions used in practice: xi * N^diag computed in integer arithmetic when
+    xi is given as a Fraction or a decimal string)."""
+    from fractions import Fraction
+    x = Fraction(str(xi)) if not isinstance(xi, Fraction) else xi
+    v = x * int(n_diag)
+    return int(-(-v.numerator // v.denominator))
+
 
 def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1, scale=1.0):
     """Host-only: the quantized step table the library would use (no device needed), for

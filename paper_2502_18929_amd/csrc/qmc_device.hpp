@@ -186,11 +186,26 @@ __device__ __forceinline__ TableViewT<Ptr> table_view(const uint8_t* tab) {
 }
 
 struct KeyLayout {
-  uint32_t kbits;   // 2n
-  uint64_t kmask;   // (1 << 2n) - 1
+  uint32_t kbits;     // 2n
+  uint64_t kmask;     // (1 << 2n) - 1
+  // Initiator approximation (End Matter on simulation methodology): with it on (ish = 1) a
+  // routed record's key is (composite key << 1) | flag, flag = its parent is not an initiator
+  // (population below init_min); a flagged record only lands on a key that has a parent.
+  uint32_t ish;       // 0 or 1
+  uint64_t init_min;  // initiator threshold in walkers (0 with ish = 0)
   __device__ __forceinline__ uint64_t key(uint64_t ck) const { return ck & kmask; }
   __device__ __forceinline__ uint32_t replica(uint64_t ck) const {
     return kbits >= 64 ? 0u : (uint32_t)(ck >> kbits);
+  }
+  // routed-record key of composite key ck spawned by a parent of population sab
+  __device__ __forceinline__ uint64_t rkey(uint64_t ck, uint64_t sab) const {
+    return (ck << ish) | (sab < init_min ? 1ull : 0ull);
+  }
+  // composite key of a routed record
+  __device__ __forceinline__ uint64_t ckey(uint64_t rk) const { return rk >> ish; }
+  // whether a routed record counts on a key with / without a parent
+  __device__ __forceinline__ bool keep(uint64_t rk, bool has_parent) const {
+    return has_parent || (rk & 1ull & (uint64_t)ish) == 0;
   }
 };
 

@@ -149,6 +149,7 @@ struct qmc_ctx {
   uint64_t epoch = 0;               // last barrier epoch used by the persistent step
   int32_t path = 0;                 // 0 automatic, 1 fused persistent kernel only, 2 streamed only
   int32_t integrator = 0;           // 0 Euler, 1 AB2
+  uint64_t init_min = 0;            // initiator threshold in walkers (0 = off)
   bool have_prev = false;           // AB2: N(s-1) (device) and w_prev are valid
   std::vector<double> w_prev;       // AB2: weights of step s-1 (s then gamma)
   uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
@@ -642,6 +643,7 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.nsteps = nst;
   pl.seed = c->cfg.seed;
   pl.kbits = c->kbits;
+  pl.init_min = c->init_min;
   pl.n_replicas = c->R;
   pl.qshift = c->at<int64_t>(c->L.qshift);
   pl.qshiftB = c->at<int64_t>(c->L.qshift) + c->R;
@@ -713,7 +715,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   qmc::Counters* dcnt = c->counters();
   const qmc::Counters before = c->last_hc;
   const uint32_t nst = ch.nst;
-  const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits);
+  const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits + (c->init_min ? 1u : 0u));
   const uint32_t step0 = c->step, cur0 = c->cur;
   const uint32_t nb = c->integrator == 1 ? 3u : 2u;
   uint64_t* bk[3] = {c->sk(0), c->alt_k(0), c->alt_k(1)};
@@ -739,11 +741,12 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
   HIPCHK(c, mark(0, 0, 0));
   HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab + ch.offsA[0],
-                       step0, c->cfg.seed, c->kbits, 0u, qshA, c->ck(cb), c->cv(cb),
+                       step0, c->cfg.seed, c->kbits, c->init_min, 0u, qshA, c->ck(cb), c->cv(cb),
                        c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
   if (ch.two)
     HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab + ch.offsB[0],
-                         step0, c->cfg.seed, c->kbits, 1u, qshB, c->ck(cb), c->cv(cb),
+                         step0, c->cfg.seed, c->kbits, c->init_min, 1u, qshB, c->ck(cb),
+                         c->cv(cb),
                          c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
   HIPCHK(c, mark(0, 0, 1));
   for (uint32_t k = 0; k < nst; ++k) {
@@ -761,7 +764,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     HIPCHK(c, mark(2, k, 0));
     HIPCHK(c, qmck_merge(c->stream, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
                          c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), tab_next,
-                         tabB_next, qshA, qshB, st, c->cfg.seed, c->kbits, bk[(k + 1) % nb],
+                         tabB_next, qshA, qshB, st, c->cfg.seed, c->kbits, c->init_min,
+                         bk[(k + 1) % nb],
                          bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
                          c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
                          passes));
@@ -1112,6 +1116,15 @@ int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
   if (hc.err & qmc::kErrOverflow)
     return fail(c, QMC_ERR_COUNT_OVERFLOW, "pulse negated INT32_MIN");
   c->have_prev = false;  // AB2 restarts after a pulse (its next step is an Euler step)
+  return QMC_OK;
+}
+
+int qmc_set_initiator(qmc_ctx* c, uint64_t min_walkers) {
+  if (!c) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (min_walkers > 0 && c->kbits + c->rbits + 1 > 64)
+    return fail(c, QMC_ERR_ARG, "no key bit left for the initiator flag");
+  c->init_min = min_walkers;
   return QMC_OK;
 }
 

@@ -11,11 +11,13 @@ int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t 
                      uint32_t n_ghist);
 // Records of step `step` from the n = *count parents (pk, pv), Philox stream `stream`: the death
 // delta of each parent (diagonal of its column plus the per-replica Q32 shift qsh) and its
-// children.
+// children.  init_min > 0: initiator approximation, record keys carry the non-initiator flag
+// below the composite key.
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
                const uint64_t* count, const uint8_t* tab, uint32_t step, uint64_t seed,
-               uint32_t kbits, uint32_t stream, const int64_t* qsh, uint64_t* ck, int2* cv,
-               uint64_t cap_child, uint64_t max_parents, uint32_t* ghist, uint32_t passes);
+               uint32_t kbits, uint64_t init_min, uint32_t stream, const int64_t* qsh,
+               uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
+               uint32_t passes);
 int qmck_digit_hist(hipStream_t st, const uint64_t* keys, void* counters, uint32_t nsel,
                     uint32_t passes, uint32_t* ghist, uint64_t max_items);
 int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
@@ -25,9 +27,9 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
                uint64_t* status, const uint8_t* tab_next, const uint8_t* tabB_next,
                const int64_t* qshift, const int64_t* qshiftB, uint32_t step, uint64_t seed,
-               uint32_t kbits, uint64_t* ok, int2* ov, uint64_t cap_store, uint64_t max_items,
-               uint64_t* ck_next, int2* cv_next, uint64_t cap_child, uint32_t* ghist_next,
-               uint32_t passes);
+               uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
+               uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
+               uint32_t* ghist_next, uint32_t passes);
 int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t cur, uint32_t n,
                uint64_t x, uint64_t z, uint64_t* ck, int2* cv, uint32_t csel,
                uint64_t max_parents);

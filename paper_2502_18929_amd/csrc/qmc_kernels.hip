@@ -112,7 +112,7 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
         d.x = (int32_t)comb_step(r, xre);
         d.y = (int32_t)comb_step(r, xim);
       }
-      em.emit((d.x | d.y) != 0, ck, d);
+      em.emit((d.x | d.y) != 0, kl.rkey(ck, sab), d);
     }
   }
   if (G <= 1) return;
@@ -129,7 +129,7 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
       child.x = (int32_t)comb_step(r, xre);
       child.y = (int32_t)comb_step(r, xim);
     }
-    em.emit((child.x | child.y) != 0, ck ^ tv.gx[g], child);
+    em.emit((child.x | child.y) != 0, kl.rkey(ck ^ tv.gx[g], sab), child);
   }
 }
 
@@ -161,7 +161,7 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, co
         d.x = (int32_t)comb_step(r, xre);
         d.y = (int32_t)comb_step(r, xim);
       }
-      em.emit((d.x | d.y) != 0, ck, d);
+      em.emit((d.x | d.y) != 0, kl.rkey(ck, sab), d);
     }
   }
   const uint32_t G = tv.h->n_groups;
@@ -178,7 +178,7 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, co
       child.x = (int32_t)comb_step(r, xre);
       child.y = (int32_t)comb_step(r, xim);
     }
-    em.emit((child.x | child.y) != 0, ck ^ tv.gx[g], child);
+    em.emit((child.x | child.y) != 0, kl.rkey(ck ^ tv.gx[g], sab), child);
   }
 }
 
@@ -485,7 +485,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
                                                        Counters* __restrict__ cnt, uint32_t cur,
                                                        uint32_t csel, uint2* __restrict__ splits,
                                                        uint32_t max_tiles,
-                                                       uint32_t* __restrict__ ghist_next) {
+                                                       uint32_t* __restrict__ ghist_next,
+                                                       uint32_t ish) {
   if (cnt->err) return;
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   // The next step's child counter, sort tickets and digit histograms were last used two steps
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
   const uint32_t ntiles = (total + kMergeTile - 1) / kMergeTile;
   const uint32_t lane = __lane_id();
   auto A = [&](uint32_t x) { return pk[x]; };
-  auto B = [&](uint32_t x) { return ckeys[x]; };
+  auto B = [&](uint32_t x) { return ckeys[x] >> ish; };  // composite key of a routed record
   for (uint32_t t = gt / kWave; t <= ntiles && t <= max_tiles; t += gridDim.x * kWaves) {
     uint32_t d = t * kMergeTile;
     if (d > total) d = total;
@@ -671,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
 
     // Per-thread ranges of the local merge, cut only at run ends.
     auto KA = [&](uint32_t x) { return s_pk[x]; };
-    auto KB = [&](uint32_t x) { return s_ck[x]; };
+    auto KB = [&](uint32_t x) { return kl.ckey(s_ck[x]); };
     const uint32_t tot = pn + cn;
     uint32_t d0 = threadIdx.x * kMergeIpt, d1 = d0 + kMergeIpt;
     if (d0 > tot) d0 = tot;
@@ -692,17 +693,21 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       while (i < i1 || j < j1) {
         uint64_t k;
         int64_t re = 0, im = 0;
-        if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
+        bool hp = false;
+        if (j >= j1 || (i < i1 && s_pk[i] <= kl.ckey(s_ck[j]))) {
           k = s_pk[i];
           re = s_pre[i];
           im = s_pim[i];
+          hp = true;
           ++i;
         } else {
-          k = s_ck[j];
+          k = kl.ckey(s_ck[j]);
         }
-        while (j < j1 && s_ck[j] == k) {
-          re += s_cv[j].x;
-          im += s_cv[j].y;
+        while (j < j1 && kl.ckey(s_ck[j]) == k) {
+          if (kl.keep(s_ck[j], hp)) {
+            re += s_cv[j].x;
+            im += s_cv[j].y;
+          }
           ++j;
         }
         if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
@@ -741,17 +746,21 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       while (i < i1 || j < j1) {
         uint64_t k;
         int64_t re = 0, im = 0;
-        if (j >= j1 || (i < i1 && s_pk[i] <= s_ck[j])) {
+        bool hp = false;
+        if (j >= j1 || (i < i1 && s_pk[i] <= kl.ckey(s_ck[j]))) {
           k = s_pk[i];
           re = s_pre[i];
           im = s_pim[i];
+          hp = true;
           ++i;
         } else {
-          k = s_ck[j];
+          k = kl.ckey(s_ck[j]);
         }
-        while (j < j1 && s_ck[j] == k) {
-          re += s_cv[j].x;
-          im += s_cv[j].y;
+        while (j < j1 && kl.ckey(s_ck[j]) == k) {
+          if (kl.keep(s_ck[j], hp)) {
+            re += s_cv[j].x;
+            im += s_cv[j].y;
+          }
           ++j;
         }
         if (re != 0 || im != 0) {
@@ -1044,8 +1053,10 @@ static inline uint32_t grid_for(uint64_t n, uint32_t cap_blocks) {
   return (uint32_t)g;
 }
 
-static inline KeyLayout key_layout(uint32_t kbits) {
-  return KeyLayout{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1)};
+// init_min > 0 turns the initiator approximation on (one flag bit below each routed key).
+static inline KeyLayout key_layout(uint32_t kbits, uint64_t init_min = 0) {
+  return KeyLayout{kbits, kbits >= 64 ? ~0ull : ((1ull << kbits) - 1), init_min ? 1u : 0u,
+                   init_min};
 }
 
 }  // namespace qmc
@@ -1070,12 +1081,13 @@ int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t 
 
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
                const uint64_t* count, const uint8_t* tab, uint32_t step, uint64_t seed,
-               uint32_t kbits, uint32_t stream, const int64_t* qsh, uint64_t* ck, int2* cv,
-               uint64_t cap_child, uint64_t max_parents, uint32_t* ghist, uint32_t passes) {
+               uint32_t kbits, uint64_t init_min, uint32_t stream, const int64_t* qsh,
+               uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
+               uint32_t passes) {
   uint32_t g = grid_for(max_parents, 1024);
   hipLaunchKernelGGL(k_spawn, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, count,
-                     tab, step, seed, key_layout(kbits), stream, qsh, ck, cv, cap_child, ghist,
-                     passes);
+                     tab, step, seed, key_layout(kbits, init_min), stream, qsh, ck, cv, cap_child,
+                     ghist, passes);
   return (int)hipGetLastError();
 }
 
@@ -1111,13 +1123,15 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
                uint64_t* status, const uint8_t* tab_next, const uint8_t* tabB_next,
                const int64_t* qshift, const int64_t* qshiftB, uint32_t step, uint64_t seed,
-               uint32_t kbits, uint64_t* ok, int2* ov, uint64_t cap_store, uint64_t max_items,
-               uint64_t* ck_next, int2* cv_next, uint64_t cap_child, uint32_t* ghist_next,
-               uint32_t passes) {
+               uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
+               uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
+               uint32_t* ghist_next, uint32_t passes) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
+  const KeyLayout kl = key_layout(kbits, init_min);
   hipLaunchKernelGGL(k_merge_part,
                      dim3(grid_for(((uint64_t)max_tiles + 1) * kWave, 2048)), dim3(kBlock), 0,
-                     st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next);
+                     st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next,
+                     kl.ish);
   MergeArgs a;
   a.pk = pk;
   a.pv = pv;
@@ -1135,7 +1149,7 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.qshift = qshift;
   a.step = step;
   a.seed = seed;
-  a.kl = key_layout(kbits);
+  a.kl = kl;
   a.ok = ok;
   a.ov = ov;
   a.cap_store = cap_store;

@@ -32,6 +32,7 @@ struct PersistLaunch {
   uint32_t step0, nsteps;
   uint64_t seed;
   uint32_t kbits;
+  uint64_t init_min;    // initiator threshold in walkers (0 = off)
   uint32_t n_replicas;
   const int64_t* qshift;     // per-replica Q32 shifts of the first / only term
   const int64_t* qshiftB;    // AB2: of the second term

@@ -418,6 +418,7 @@ struct Router {
   uint32_t par;            // inbox parity of the destination step
   uint32_t step;           // destination step (for error reports)
   uint32_t* my_err;        // this workgroup's error word (LDS)
+  uint32_t ish;            // initiator flag bit below each routed key (0 or 1)
   uint64_t* sk;            // this wave's LDS staging
   int2* sv;
   uint32_t fill;           // wave-uniform
@@ -447,7 +448,7 @@ struct Router {
       for (int c = 0; c < NC; ++c) {
         if ((uint32_t)c * kWave >= fill) break;
         const uint32_t cand = q[c] + st;
-        if (cand < P && split[cand] <= key[c]) q[c] = cand;
+        if (cand < P && split[cand] <= (key[c] >> ish)) q[c] = cand;
       }
     }
     wave_lds_fence();  // the staging area becomes the table of distinct destinations
@@ -537,7 +538,7 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
         d.x = (int32_t)comb_step(r, xre);
         d.y = (int32_t)comb_step(r, xim);
       }
-      R.emit((d.x | d.y) != 0, ck, d);
+      R.emit((d.x | d.y) != 0, A.kl.rkey(ck, sab), d);
     }
   }
   // Children into every off-diagonal target, one comb over all groups (Re, Im) in order.
@@ -558,7 +559,7 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
       child.x = (int32_t)comb_step(r, xre);
       child.y = (int32_t)comb_step(r, xim);
     }
-    R.emit((child.x | child.y) != 0, ck ^ gxm, child);
+    R.emit((child.x | child.y) != 0, A.kl.rkey(ck ^ gxm, sab), child);
     gb = ge;
   }
 }
@@ -628,7 +629,7 @@ __device__ __forceinline__ void process_wide(const PersistArgs& A, Shared& S, Ro
       d.x = (int32_t)comb_step(r, xre);
       d.y = (int32_t)comb_step(r, xim);
     }
-    R.emit((d.x | d.y) != 0, ck, d);
+    R.emit((d.x | d.y) != 0, A.kl.rkey(ck, sab), d);
   }
   if (mine && __ballot(act)) {
     uint32_t r0 = w.x;
@@ -644,7 +645,7 @@ __device__ __forceinline__ void process_wide(const PersistArgs& A, Shared& S, Ro
         child.x = (int32_t)comb_step(r, xre);
         child.y = (int32_t)comb_step(r, xim);
       }
-      R.emit((child.x | child.y) != 0, ck ^ tn.gx[g], child);
+      R.emit((child.x | child.y) != 0, A.kl.rkey(ck ^ tn.gx[g], sab), child);
     }
   }
   __syncthreads();
@@ -768,13 +769,14 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
     __syncthreads();
     // inbox window of this tile: records up to its last parent, or all the rest on the last tile
     const bool last_tile = tt + 1 == ntile;
-    const uint32_t je = last_tile ? c : upper_bound_lds(S.in_k, c, S.pa_k[pn - 1]);
+    const uint32_t je =
+        last_tile ? c : upper_bound_lds(S.in_k, c, (S.pa_k[pn - 1] << A.kl.ish) | A.kl.ish);
     const uint32_t cn = je - jb;
     const uint64_t* ck = S.in_k + jb;
     const int2* cv = S.in_v + jb;
     // this thread's share of the tile's merged items
     auto KA = [&](uint32_t x) { return S.pa_k[x]; };
-    auto KB = [&](uint32_t x) { return ck[x]; };
+    auto KB = [&](uint32_t x) { return A.kl.ckey(ck[x]); };
     const uint32_t tot = pn + cn;
     const uint32_t per = (tot + kPBlock - 1) / kPBlock;
     uint32_t d0 = t * per;
@@ -797,17 +799,21 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
       while (i < i1 || j < j1) {
         uint64_t key;
         int64_t re = 0, im = 0;
-        if (j >= j1 || (i < i1 && S.pa_k[i] <= ck[j])) {
+        bool hp = false;
+        if (j >= j1 || (i < i1 && S.pa_k[i] <= A.kl.ckey(ck[j]))) {
           key = S.pa_k[i];
           re = S.pa_v[i].x;
           im = S.pa_v[i].y;
+          hp = true;
           ++i;
         } else {
-          key = ck[j];
+          key = A.kl.ckey(ck[j]);
         }
-        while (j < j1 && ck[j] == key) {
-          re += cv[j].x;
-          im += cv[j].y;
+        while (j < j1 && A.kl.ckey(ck[j]) == key) {
+          if (A.kl.keep(ck[j], hp)) {
+            re += cv[j].x;
+            im += cv[j].y;
+          }
           ++j;
         }
         out(key, re, im);
@@ -882,7 +888,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   // composite keys below 2^52: the inbox sort can pack a 12-bit record index under the key
   uint32_t rbits = 0;
   while ((1ull << rbits) < (uint64_t)A.n_replicas) ++rbits;
-  const bool packed = A.kl.kbits + rbits <= 52;
+  const bool packed = A.kl.kbits + rbits + A.kl.ish <= 52;
   for (uint32_t i = t; i < P; i += kPBlock) S.split[i] = A.split[i];
   if (t == 0) {
     S.err = 0;
@@ -970,7 +976,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     const LTable tn = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab));
     const LTable tnB = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tabB));
     Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, nstep, &S.err,
-             S.st_k[t / kWave], S.st_v[t / kWave], 0u};
+             A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u};
     merge_segment(A, S, pk, pv, np_k, c, okp, ovp, s, !last, two && !first, R, tn, tnB, nstep);
     const uint64_t nout = S.red[0], wsum = S.red[1];
     if (two && first) {
@@ -1105,7 +1111,8 @@ PersistArgs make_args(const PersistLaunch* L) {
   a.step0 = L->step0;
   a.nsteps = L->nsteps;
   a.seed = L->seed;
-  a.kl = KeyLayout{L->kbits, L->kbits >= 64 ? ~0ull : ((1ull << L->kbits) - 1)};
+  a.kl = KeyLayout{L->kbits, L->kbits >= 64 ? ~0ull : ((1ull << L->kbits) - 1),
+                   L->init_min ? 1u : 0u, L->init_min};
   a.n_replicas = L->n_replicas;
   a.qshift = L->qshift;
   a.slots = L->slots;

@@ -128,7 +128,9 @@ int qmc_step_path(qmc_ctx* ctx, int32_t path);
  * with scale 3/2 and -1/2 -- and its own Philox stream (0 for N(s), 1 for N(s-1), whose diagonal
  * is a record of its own rather than a change of N(s-1)).  The context keeps N(s-1) and the
  * weights of step s-1; without them (after qmc_init, qmc_set_integrator or qmc_pulse) the next
- * step is an Euler step.  Switching clears N(s-1).  QMC_ERR_ARG for another value. */
+ * step is an Euler step.  Switching clears N(s-1).  QMC_ERR_ARG for another value.  An AB2
+ * step whose two tables have more than 257 column groups between them is refused by qmc_step
+ * with QMC_ERR_ARG (a key's records from both tables must stay within one merge run). */
 int qmc_set_integrator(qmc_ctx* ctx, int32_t integrator);
 
 /* AB2: N(s-1) of one replica (same record rules as qmc_init) and the weights of step s-1

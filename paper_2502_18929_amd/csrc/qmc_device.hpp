@@ -27,6 +27,7 @@ constexpr int kMaxPasses = 6;        // ceil(64 / 11)
 constexpr int kSortIpt = 16;         // records per thread of a sort tile
 constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
+constexpr int kMergeBlocks = 768;    // k_merge: three workgroups per CU (about 51 KB of LDS each)
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
 constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)
 constexpr int kTermPad = 4;          // terms per group are a multiple of this in a packed table

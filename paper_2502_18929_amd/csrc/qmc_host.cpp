@@ -861,6 +861,12 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
         rc = QMC_ERR_DT;
         why = "diagonal group with shift violates the Q32 bound";
       }
+      // A key receives at most one record per group of each table; the merges keep a key's
+      // records together only up to kMergeSlack + 1 of them.
+      if (!rc && TA.gx.size() + TB.gx.size() > (size_t)qmc::kMergeSlack + 1) {
+        rc = QMC_ERR_ARG;
+        why = "the two AB2 tables have more than 257 column groups between them";
+      }
     }
     if (!rc && TA.q_diag + max_qa >= (1ull << 31)) {
       rc = QMC_ERR_DT;

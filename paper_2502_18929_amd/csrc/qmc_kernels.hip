@@ -559,14 +559,12 @@ struct MergeArgs {
 
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   constexpr int CAP = kMergeCap;
-  __shared__ uint64_t s_pk[CAP];
-  __shared__ int64_t s_pre[CAP];
-  __shared__ int64_t s_pim[CAP];
+  __shared__ uint64_t s_pk[CAP];   // parents of the tile; then its annihilated records
+  __shared__ int2 s_pv[CAP];
   __shared__ uint64_t s_ck[CAP];   // children of the tile; later the spawn staging
   __shared__ int2 s_cv[CAP];
-  __shared__ uint64_t s_ok[CAP];   // annihilated outputs of the tile
-  __shared__ int2 s_ov[CAP];
   __shared__ uint32_t s_scan[kBlock];
+  __shared__ uint32_t s_xsplit[kBlock];  // merge-path split of each thread: parent | child << 16
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base;
   __shared__ uint64_t s_ws[kWaves];
@@ -653,8 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       const int2 v = A.pv[pa + x];
       wsum += uabs64(v.x) + uabs64(v.y);
       s_pk[x] = ck;
-      s_pre[x] = v.x;
-      s_pim[x] = v.y;
+      s_pv[x] = v;
     }
     for (uint32_t x = threadIdx.x; x < cn; x += kBlock) {
       s_ck[x] = A.ckeys[ca + x];
@@ -674,20 +671,29 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     auto KA = [&](uint32_t x) { return s_pk[x]; };
     auto KB = [&](uint32_t x) { return kl.ckey(s_ck[x]); };
     const uint32_t tot = pn + cn;
-    uint32_t d0 = threadIdx.x * kMergeIpt, d1 = d0 + kMergeIpt;
+    uint32_t d0 = threadIdx.x * kMergeIpt;
     if (d0 > tot) d0 = tot;
-    if (d1 > tot) d1 = tot;
+    // this thread's end is the next thread's start (one search per thread)
     uint32_t i0, j0, i1, j1;
     run_split(KA, pn, KB, cn, d0, i0, j0);
-    run_split(KA, pn, KB, cn, d1, i1, j1);
-    if (threadIdx.x == kBlock - 1) {
+    s_xsplit[threadIdx.x] = i0 | (j0 << 16);
+    __syncthreads();
+    if (threadIdx.x + 1 < (uint32_t)kBlock) {
+      const uint32_t nx = s_xsplit[threadIdx.x + 1];
+      i1 = nx & 0xFFFFu;
+      j1 = nx >> 16;
+    } else {
       i1 = pn;
       j1 = cn;
     }
 
-    // Pass 1: count nonzero outputs.
+    // One pass: the annihilated records of this thread's range, held in registers.  A range is
+    // kMergeIpt merged items moved to run ends, and only the run of its last key can extend it,
+    // so it holds at most kMergeIpt distinct keys.
+    uint64_t rk[kMergeIpt];
+    int2 rv[kMergeIpt];
     uint32_t count = 0;
-    bool overflow = false;
+    bool overflow = false, too_many = false;
     {
       uint32_t i = i0, j = j0;
       while (i < i1 || j < j1) {
@@ -696,8 +702,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         bool hp = false;
         if (j >= j1 || (i < i1 && s_pk[i] <= kl.ckey(s_ck[j]))) {
           k = s_pk[i];
-          re = s_pre[i];
-          im = s_pim[i];
+          re = s_pv[i].x;
+          im = s_pv[i].y;
           hp = true;
           ++i;
         } else {
@@ -711,11 +717,26 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           ++j;
         }
         if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
-        count += (re != 0 || im != 0) ? 1u : 0u;
+        if (re != 0 || im != 0) {
+#pragma unroll
+          for (int u = 0; u < kMergeIpt; ++u)
+            if ((uint32_t)u == count) {
+              rk[u] = k;
+              rv[u] = make_int2((int32_t)re, (int32_t)im);
+            }
+          if (count < (uint32_t)kMergeIpt)
+            ++count;
+          else
+            too_many = true;
+        }
       }
     }
     if (overflow) {
       atomicOr(&cnt->err, kErrOverflow);
+      atomicMin(&cnt->err_step, A.step);
+    }
+    if (too_many) {  // cannot happen (see above); refuse rather than drop a record
+      atomicOr(&cnt->err, kErrLookback);
       atomicMin(&cnt->err_step, A.step);
     }
 
@@ -739,37 +760,14 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     if (threadIdx.x == 0)
       atomic_store_agent(&A.status[tile], lb_pack(A.epoch, tile == 0 ? 2 : 1, agg));
 
-    // Pass 2: the annihilated, compacted records of the tile, into LDS.
-    {
-      uint32_t i = i0, j = j0;
-      uint32_t o = excl;
-      while (i < i1 || j < j1) {
-        uint64_t k;
-        int64_t re = 0, im = 0;
-        bool hp = false;
-        if (j >= j1 || (i < i1 && s_pk[i] <= kl.ckey(s_ck[j]))) {
-          k = s_pk[i];
-          re = s_pre[i];
-          im = s_pim[i];
-          hp = true;
-          ++i;
-        } else {
-          k = kl.ckey(s_ck[j]);
-        }
-        while (j < j1 && kl.ckey(s_ck[j]) == k) {
-          if (kl.keep(s_ck[j], hp)) {
-            re += s_cv[j].x;
-            im += s_cv[j].y;
-          }
-          ++j;
-        }
-        if (re != 0 || im != 0) {
-          s_ok[o] = k;
-          s_ov[o] = make_int2((int32_t)re, (int32_t)im);
-          ++o;
-        }
+    // The tile's annihilated records, compacted into the parent area of LDS (every thread has
+    // finished reading the tile: the scan above synchronized the block).
+#pragma unroll
+    for (int u = 0; u < kMergeIpt; ++u)
+      if ((uint32_t)u < count) {
+        s_pk[excl + u] = rk[u];
+        s_pv[excl + u] = rv[u];
       }
-    }
     __syncthreads();
 
     // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
@@ -785,8 +783,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         int2 v = make_int2(0, 0);
         uint32_t w[4] = {0, 0, 0, 0};
         if (p < agg) {
-          ck = s_ok[p];
-          v = s_ov[p];
+          ck = s_pk[p];
+          v = s_pv[p];
           const uint32_t rep = kl.replica(ck);
           walker_random(kl.key(ck), A.step + 1, rep, A.seed, 0u, w);
           const uint64_t sab = uabs64(v.x) + uabs64(v.y);
@@ -858,8 +856,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     const uint64_t gbase = s_base;
     for (uint32_t x = threadIdx.x; x < agg; x += kBlock) {
       if (gbase + x < A.cap_store) {
-        A.ok[gbase + x] = s_ok[x];
-        A.ov[gbase + x] = s_ov[x];
+        A.ok[gbase + x] = s_pk[x];
+        A.ov[gbase + x] = s_pv[x];
       }
     }
     __syncthreads();
@@ -1158,8 +1156,8 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.cap_child = cap_child;
   a.ghist_next = ghist_next;
   a.passes = passes;
-  const uint32_t g = max_tiles < (uint32_t)kPersistBlocks ? (max_tiles ? max_tiles : 1)
-                                                          : (uint32_t)kPersistBlocks;
+  const uint32_t g = max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
+                                                        : (uint32_t)kMergeBlocks;
   hipLaunchKernelGGL(k_merge, dim3(g), dim3(kBlock), 0, st, a);
   return (int)hipGetLastError();
 }

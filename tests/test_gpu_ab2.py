@@ -189,3 +189,21 @@ def test_ab2_auto_path_falls_back_to_streamed(B, orc):
     g.step(s, gam)
     o.step(s, gam, threads=8)
     _assert_same(g, o, R, "after 3 steps", prev=True)
+
+
+def test_ab2_refuses_tables_with_too_many_groups(B):
+    """n = 7 with every single-qubit X and Y monomial on both sides gives 2 x 128 - 1 column
+    groups per table: an AB2 step with two such tables is refused before anything runs, and
+    the state is unchanged; the Euler step alone is accepted."""
+    n = 7
+    h = [(x, 0, 0.01) for x in range(1, 1 << n)]
+    g = B.QMC(n, 1, 3, 0.001, h, [], [0], [100], [0], store_capacity=1 << 10,
+              spawn_capacity=1 << 16)
+    g.set_integrator("ab2")
+    s = np.ones((3, len(h)))
+    with pytest.raises(B.QMCError) as e:
+        g.step(s, np.zeros((3, 0)))
+    assert e.value.code == B.QMC_ERR_ARG
+    assert g.counters()["step"] == 0
+    g.step(s[:1], np.zeros((1, 0)))  # the Euler first step alone is fine
+    assert g.counters()["step"] == 1

@@ -103,3 +103,12 @@ def test_invalid_configuration_rejected():
         binding.coeff_table(33, 0.01, [], [], [], [])
     with pytest.raises(binding.QMCError):
         binding.coeff_table(2, 0.01, [(4, 0, 1.0)], [], [1.0], [])   # mask outside n bits
+
+
+def test_initiator_threshold_rounds_up_exactly():
+    """ceil(xi * N^diag) in exact rational arithmetic (0.001 * 1e7 is 10000, not 10001)."""
+    assert binding.initiator_threshold("0.001", 10_000_000) == 10_000
+    assert binding.initiator_threshold(0.001, 1_000_000) == 1_000
+    assert binding.initiator_threshold("0.001", 10_001) == 11
+    assert binding.initiator_threshold("0.1", 3) == 1
+    assert binding.initiator_threshold(0, 10 ** 9) == 0

@@ -77,6 +77,7 @@ def lib():
         L.orc_pulse.argtypes = [ctypes.c_void_p, u64, u64]
         L.orc_set_shift.argtypes = [ctypes.c_void_p, u32, dbl]
         L.orc_set_initiator.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        L.orc_set_replica_base.argtypes = [ctypes.c_void_p, u32]
         L.orc_counters.argtypes = [ctypes.c_void_p, P(u64), P(u64), P(u64), P(u64)]
         L.orc_counters.restype = None
         L.orc_get_step.argtypes = [ctypes.c_void_p]
@@ -246,6 +247,11 @@ class Oracle:
 
     def set_shift(self, replica, shift):
         _check(lib().orc_set_shift(self._ctx, int(replica), float(shift)), "set_shift")
+
+    def set_replica_base(self, base):
+        """Philox stream ids base .. base + R - 1 for this context's replicas (one circuit of a
+        batch of circuits)."""
+        _check(lib().orc_set_replica_base(self._ctx, int(base)), "set_replica_base")
 
     def set_initiator(self, min_walkers):
         """Initiator approximation (End Matter on simulation methodology, reading R17): parents

@@ -126,6 +126,9 @@ struct orc_ctx {
    * whose population |re| + |im| is below init_min is not an initiator, and the records it
    * spawns onto keys absent from N(s) are discarded.  0 = off (every parent spawns). */
   uint64_t init_min;
+  /* Philox stream id of replica r is replica_base + r: a context that holds one circuit of a
+   * batch draws what the batch draws for that circuit's replicas. */
+  uint32_t replica_base;
 };
 
 /* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
@@ -540,7 +543,8 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
     const uint64_t key = in->key[p];
     const int64_t a = in->re[p], b = in->im[p];
     /* Philox counter: the walker's key, the step, and (replica << 8) | stream. */
-    const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step, (r << 8) | stream};
+    const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step,
+                             ((c->replica_base + r) << 8) | stream};
     uint32_t w[4];
     orc_philox4x32_10(ctr, pkey, w);
     const int initiator =
@@ -818,6 +822,12 @@ int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z) {
   }
   /* AB2 (reading: a pulse restarts the two-step formula): the next step is an Euler step. */
   c->have_prev = 0;
+  return ORC_OK;
+}
+
+int orc_set_replica_base(orc_ctx* c, uint32_t base) {
+  if ((uint64_t)base + c->R > (1u << 24)) return ORC_ERR_ARG;
+  c->replica_base = base;
   return ORC_OK;
 }
 

@@ -99,6 +99,10 @@ int orc_set_shift(orc_ctx* c, uint32_t replica, double shift);
 /* Initiator approximation (End Matter on simulation methodology): parents with |re| + |im| below
  * min_walkers spawn only onto keys occupied in N(s) (reading R17).  0 = off. */
 int orc_set_initiator(orc_ctx* c, uint64_t min_walkers);
+/* Replica r draws Philox with stream id base + r (the counter's last word is
+ * ((base + r) << 8) | stream): a context holding one circuit of a batch of circuits uses the ids
+ * the batch gives that circuit's replicas.  Default 0. */
+int orc_set_replica_base(orc_ctx* c, uint32_t base);
 
 uint32_t orc_get_step(const orc_ctx* c);
 /* Sums over all steps so far and all replicas of the parents' N^tot, of their occupied keys and

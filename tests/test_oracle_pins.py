@@ -687,3 +687,25 @@ def test_initiator_without_initiators_never_grows_the_support(orc):
             now = set(o.export(r)[0].tolist())
             assert now <= prev[r]
             prev[r] = now
+
+
+def test_replica_base_selects_the_replicas_of_a_larger_context(orc):
+    """Replicas r of a context with stream base b follow replicas b + r of a context with more
+    replicas (the draws are keyed on the stream id, not on the context)."""
+    rng = np.random.default_rng(81)
+    n = 3
+    h, lops = W.random_model(n, rng, n_h=5, n_l=2)
+    keys, re, im = W.random_records(n, rng, 6, scale=300)
+    s = rng.normal(size=(25, len(h)))
+    g = np.abs(rng.normal(size=(25, len(lops))))
+    big = orc.Oracle(n, 7, 9, 0.01, h, lops, keys, re, im)
+    small = orc.Oracle(n, 2, 9, 0.01, h, lops, keys, re, im)
+    small.set_replica_base(5)
+    big.step(s, g)
+    small.step(s, g)
+    for r in range(2):
+        for x, y in zip(small.export(r), big.export(5 + r)):
+            assert np.array_equal(x, y)
+    other = orc.Oracle(n, 2, 9, 0.01, h, lops, keys, re, im)
+    other.step(s, g)
+    assert not all(np.array_equal(x, y) for x, y in zip(other.export(0), small.export(0)))

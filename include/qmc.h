@@ -104,6 +104,25 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
              const int32_t* re, const int32_t* im, uint64_t n0, void* d_workspace,
              size_t ws_bytes, void* hip_stream, qmc_ctx** out);
 
+/* A batch of circuits in one context (the spec batched step): n_circuits models on the
+ * same n qubits (a smaller circuit leaves the extra qubits idle: its masks and keys use only its
+ * own qubits), each with its own initial records (keys[c], re[c], im[c], n0[c], as qmc_init)
+ * and cfg->n_replicas replicas.  Replica r of circuit c is store segment s = c * n_replicas + r:
+ * its composite key is (s << 2n) | key, its Philox stream id is s, and every call that takes a
+ * replica index (qmc_export, qmc_import, qmc_set_shift, qmc_observe's output rows) takes s.
+ * Capacities are per segment.  qmc_step takes the weights of all circuits side by side:
+ * s[nsteps][sum_c n_h(c)], gamma[nsteps][sum_c n_l(c)], circuit c's after those of circuits
+ * 0..c-1.  One step advances every circuit with its own table; on the fused path every key
+ * range holds one circuit's keys.  The AB2 integrator and the initiator approximation run one
+ * circuit per context (QMC_ERR_ARG otherwise).  1 <= n_circuits <= 512 and at most the number
+ * of co-resident workgroups of the fused step (256 on MI355X); QMC_ERR_ARG otherwise. */
+int qmc_workspace_bytes_batch(const qmc_config* cfg, uint32_t n_circuits,
+                              const qmc_model* models, size_t* bytes);
+int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* models,
+                   const uint64_t* const* keys, const int32_t* const* re,
+                   const int32_t* const* im, const uint64_t* n0, void* d_workspace,
+                   size_t ws_bytes, void* hip_stream, qmc_ctx** out);
+
 /* Advance every replica by nsteps Euler steps (End Matter, spawn and annihilation steps,
  * Euler solver).  s is [nsteps][n_h] and gamma is [nsteps][n_l], row k holding the weights at
  * the left end t = (step0 + k) * dt of step k.  Tables are quantized and bound-checked on the
@@ -148,6 +167,8 @@ int qmc_export_prev(qmc_ctx* ctx, uint32_t replica, uint64_t* keys, int32_t* re,
  * i.e. |i><j| -> (-1)^{popc(z & i) + popc(z & j)} |i ^ x><j ^ x| (used for the staggered-XX
  * dynamical-decoupling pulses of Fig. 1(c)).  With AB2 the next step is an Euler step. */
 int qmc_pulse(qmc_ctx* ctx, uint64_t x, uint64_t z);
+/* The same for a batch: circuit c takes P = X^x[c] Z^z[c] (arrays of n_circuits entries). */
+int qmc_pulse_batch(qmc_ctx* ctx, const uint64_t* x, const uint64_t* z);
 
 /* Constant diagonal shift S for one replica (death coefficient L_diag + S).  The paper needs
  * none (the Liouvillian is trace preserving); S != 0 biases the estimator. */

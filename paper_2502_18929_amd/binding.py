@@ -27,7 +27,7 @@ EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_set_integrator", "qmc_set_prev", "qmc_export_prev", "qmc_pulse",
             "qmc_set_shift", "qmc_set_initiator", "qmc_observe", "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
-            "qmc_destroy"]
+            "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch"]
 
 
 class Monomial(ctypes.Structure):
@@ -90,6 +90,10 @@ def lib():
                                ctypes.c_size_t, vp, P(vp)]
         L.qmc_step.argtypes = [vp, u32, P(dbl), P(dbl)]
         L.qmc_pulse.argtypes = [vp, u64, u64]
+        L.qmc_pulse_batch.argtypes = [vp, P(u64), P(u64)]
+        L.qmc_workspace_bytes_batch.argtypes = [P(Config), u32, P(Model), P(ctypes.c_size_t)]
+        L.qmc_init_batch.argtypes = [P(Config), u32, P(Model), P(P(u64)), P(P(i32)), P(P(i32)),
+                                     P(u64), vp, ctypes.c_size_t, vp, P(vp)]
         L.qmc_set_shift.argtypes = [vp, u32, dbl]
         L.qmc_set_initiator.argtypes = [vp, ctypes.c_uint64]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
@@ -131,28 +135,62 @@ def _monos(lst):
 
 
 class QMC:
-    """One libqmc context: R replicas of one model, advanced on one HIP stream."""
+    """One libqmc context: R replicas of one model (or of each model of a batch of circuits,
+    see ``QMC.batch``), advanced on one HIP stream."""
 
     def __init__(self, n, n_replicas, seed, dt, h, lops, keys, re, im, store_capacity,
                  spawn_capacity, walker_target=0, stream=None):
+        self._setup(n, n_replicas, seed, dt, [(h, lops, keys, re, im)], store_capacity,
+                    spawn_capacity, walker_target, stream)
+
+    @classmethod
+    def batch(cls, n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity,
+              stream=None):
+        """A batch of circuits on n qubits: circuits = [(h, lops, keys, re, im), ...] (a
+        smaller circuit uses only its low qubits).  Replica r of circuit c is segment
+        c * n_replicas + r for export/import/observe/set_shift; step() takes the weights of all
+        circuits side by side (circuit 0's columns first)."""
+        self = cls.__new__(cls)
+        self._setup(n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity, 0, stream)
+        return self
+
+    def _setup(self, n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity,
+               walker_target, stream):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libqmc needs a HIP device; none is visible")
         L = lib()
-        self.n, self.R, self.n_h, self.n_l = int(n), int(n_replicas), len(h), len(lops)
-        self._h = _monos(h)
-        self._l = _monos([m for op in lops for m in op])
-        off = np.zeros(len(lops) + 1, dtype=np.uint32)
-        for k, op in enumerate(lops):
-            off[k + 1] = off[k] + len(op)
-        self._off = off
-        self._cfg = Config(self.n, self.R, int(seed), float(dt), int(walker_target),
+        C = len(circuits)
+        self.n, self.C, self.Rc = int(n), C, int(n_replicas)
+        self.R = C * self.Rc
+        self.n_h = sum(len(c[0]) for c in circuits)
+        self.n_l = sum(len(c[1]) for c in circuits)
+        self._keep = []
+        models = (Model * C)()
+        keys_p = (P64 * C)()
+        re_p = (ctypes.POINTER(ctypes.c_int32) * C)()
+        im_p = (ctypes.POINTER(ctypes.c_int32) * C)()
+        n0 = np.zeros(C, dtype=np.uint64)
+        for ci, (h, lops, keys, re, im) in enumerate(circuits):
+            hm = _monos(h)
+            lm = _monos([m for op in lops for m in op])
+            off = np.zeros(len(lops) + 1, dtype=np.uint32)
+            for kk, op in enumerate(lops):
+                off[kk + 1] = off[kk] + len(op)
+            keys = np.ascontiguousarray(keys, dtype=np.uint64)
+            re = np.ascontiguousarray(re, dtype=np.int32)
+            im = np.ascontiguousarray(im, dtype=np.int32)
+            self._keep += [hm, lm, off, keys, re, im]
+            models[ci] = Model(len(h), hm, len(lops), _ptr(off, ctypes.c_uint32), lm)
+            keys_p[ci] = _ptr(keys, ctypes.c_uint64)
+            re_p[ci] = _ptr(re, ctypes.c_int32)
+            im_p[ci] = _ptr(im, ctypes.c_int32)
+            n0[ci] = len(keys)
+        self._models, self._n0 = models, n0
+        self._cfg = Config(self.n, self.Rc, int(seed), float(dt), int(walker_target),
                            int(store_capacity), int(spawn_capacity))
-        self._model = Model(self.n_h, self._h, self.n_l, _ptr(self._off, ctypes.c_uint32),
-                            self._l)
         nb = ctypes.c_size_t()
-        rc = L.qmc_workspace_bytes(ctypes.byref(self._cfg), ctypes.byref(self._model),
-                                   ctypes.byref(nb))
+        rc = L.qmc_workspace_bytes_batch(ctypes.byref(self._cfg), C, models, ctypes.byref(nb))
         if rc:
             raise QMCError(rc, "invalid configuration")
         self.ws_bytes = nb.value
@@ -162,15 +200,11 @@ class QMC:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        keys = np.ascontiguousarray(keys, dtype=np.uint64)
-        re = np.ascontiguousarray(re, dtype=np.int32)
-        im = np.ascontiguousarray(im, dtype=np.int32)
         self._ctx = ctypes.c_void_p()
-        rc = L.qmc_init(ctypes.byref(self._cfg), ctypes.byref(self._model),
-                        _ptr(keys, ctypes.c_uint64), _ptr(re, ctypes.c_int32),
-                        _ptr(im, ctypes.c_int32), len(keys), ctypes.c_void_p(aligned),
-                        self.ws_bytes, ctypes.c_void_p(stream.cuda_stream),
-                        ctypes.byref(self._ctx))
+        rc = L.qmc_init_batch(ctypes.byref(self._cfg), C, models, keys_p, re_p, im_p,
+                              _ptr(n0, ctypes.c_uint64), ctypes.c_void_p(aligned),
+                              self.ws_bytes, ctypes.c_void_p(stream.cuda_stream),
+                              ctypes.byref(self._ctx))
         if rc:
             raise QMCError(rc, "qmc_init failed")
 
@@ -229,6 +263,14 @@ class QMC:
 
     def pulse(self, x, z):
         self._check(lib().qmc_pulse(self._ctx, int(x), int(z)))
+
+    def pulse_batch(self, xs, zs):
+        """Circuit c of a batch takes the Pauli X^xs[c] Z^zs[c]."""
+        x = np.ascontiguousarray(xs, dtype=np.uint64)
+        z = np.ascontiguousarray(zs, dtype=np.uint64)
+        assert len(x) == self.C and len(z) == self.C
+        self._check(lib().qmc_pulse_batch(self._ctx, _ptr(x, ctypes.c_uint64),
+                                          _ptr(z, ctypes.c_uint64)))
 
     def set_shift(self, replica, shift):
         self._check(lib().qmc_set_shift(self._ctx, int(replica), float(shift)))

@@ -29,6 +29,7 @@ constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
 constexpr int kMergeBlocks = 768;    // k_merge: three workgroups per CU (about 51 KB of LDS each)
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
+constexpr int kMaxCircuits = kMaxSegments;  // circuits of one batch (each needs a key range)
 constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)
 constexpr int kTermPad = 4;          // terms per group are a multiple of this in a packed table
 
@@ -185,6 +186,19 @@ __device__ __forceinline__ TableViewT<Ptr> table_view(const uint8_t* tab) {
   v.t = (Ptr<Term>)(b + v.h->t_off);
   return v;
 }
+
+// The step tables of one step for a batch of circuits: circuit c's table starts at base + off[c];
+// segment s of the store (composite key >> 2n: replica rep of circuit c is s = c * rep_per + r)
+// takes its circuit's table.  One circuit (the usual case) has a single table for all replicas.
+struct TabSet {
+  const uint8_t* base;
+  const uint32_t* off;  // [circuits] offsets for this step, or null: no table
+  uint32_t rep_per;     // replicas per circuit
+  __device__ __forceinline__ bool valid() const { return off != nullptr; }
+  __device__ __forceinline__ const uint8_t* of_segment(uint32_t seg) const {
+    return base + off[seg / rep_per];
+  }
+};
 
 struct KeyLayout {
   uint32_t kbits;     // 2n

@@ -49,7 +49,7 @@ struct QTerm {
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
-      tab_off, tabB_off, slots, done, total;
+      tab_off, tabB_off, slots, done, pulse, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -64,7 +64,8 @@ uint32_t replica_bits(uint32_t R) {
   return b;
 }
 
-bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
+// c.n_replicas counts store segments (circuits x replicas per circuit).
+bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout& L) {
   const uint64_t S = c.store_capacity * (uint64_t)c.n_replicas;
   const uint64_t C = c.spawn_capacity * (uint64_t)c.n_replicas;
   if (S == 0 || C == 0 || S >= (1ull << 31) || C >= (1ull << 31) || P == 0) return false;
@@ -110,10 +111,11 @@ bool compute_layout(const qmc_config& c, uint32_t P, Layout& L) {
   L.in_v = take((size_t)2 * P * L.incap * 8);
   L.in_n = take((size_t)2 * P * 4);
   L.split = take((size_t)P * 8);
-  L.tab_off = take((size_t)kMaxChunkSteps * 4);
+  L.tab_off = take((size_t)kMaxChunkSteps * 4 * n_circuits);
   L.tabB_off = take((size_t)kMaxChunkSteps * 4);
   L.slots = take((size_t)2 * P * 4 * 8);
   L.done = take(8);
+  L.pulse = take((size_t)n_circuits * 16);
   L.total = o;
   return true;
 }
@@ -130,9 +132,12 @@ int persist_segments(uint32_t* P) {
 
 struct qmc_ctx {
   qmc_config cfg{};
+  // R = store segments = circuits x replicas per circuit (one circuit: R = the replicas)
   uint32_t n = 0, R = 0, kbits = 0, rbits = 0;
-  uint32_t n_h = 0, n_l = 0;
-  std::vector<SrcTerm> terms;
+  uint32_t C = 1, Rc = 0;           // circuits of a batch, replicas per circuit
+  uint32_t n_h = 0, n_l = 0;        // weights per step, all circuits together
+  std::vector<std::vector<SrcTerm>> terms;  // per circuit
+  std::vector<uint32_t> wh_off, wl_off;      // a circuit's first weight in a step's s / gamma
   Layout L{};
   uint8_t* ws = nullptr;
   hipStream_t stream = nullptr;
@@ -268,10 +273,9 @@ struct HostTable {
   uint64_t q_off = 0, q_diag = 0;
 };
 
-int build_table(const qmc_ctx* c, const double* s, const double* g, double scale,
-                HostTable& T, std::string& why) {
-  // c->terms is sorted by (xmask, zmask): each run of equal terms is one merged Q32 term.
-  const std::vector<SrcTerm>& src = c->terms;
+int build_table(const std::vector<SrcTerm>& src, double dt, const double* s, const double* g,
+                double scale, HostTable& T, std::string& why) {
+  // src is sorted by (xmask, zmask): each run of equal terms is one merged Q32 term.
   T.t.clear();
   T.t.reserve(src.size());
   for (size_t i = 0; i < src.size();) {
@@ -285,8 +289,7 @@ int build_table(const qmc_ctx* c, const double* s, const double* g, double scale
         return QMC_ERR_ARG;
       }
       int64_t qre, qim;
-      if (!quantize(c->cfg.dt, w, st.kre, scale, qre) ||
-          !quantize(c->cfg.dt, w, st.kim, scale, qim)) {
+      if (!quantize(dt, w, st.kre, scale, qre) || !quantize(dt, w, st.kim, scale, qim)) {
         why = "coefficient too large for Q32";
         return QMC_ERR_DT;
       }
@@ -425,7 +428,7 @@ int validate(const qmc_config* cfg, const qmc_model* m, std::string& why) {
       return QMC_ERR_ARG;
     }
   Layout L;
-  if (!compute_layout(*cfg, 1, L)) {
+  if (!compute_layout(*cfg, 1, 1, L)) {
     why = "capacities must be nonzero and R*(store+spawn) < 2^31";
     return QMC_ERR_ARG;
   }
@@ -491,69 +494,122 @@ int shifts_q32(const qmc_ctx* c, double scale, std::vector<int64_t>& qs) {
 
 extern "C" {
 
-int qmc_workspace_bytes(const qmc_config* cfg, const qmc_model* model, size_t* bytes) {
+namespace {
+
+// The configuration of the store: n_replicas counts segments (circuits x replicas per circuit).
+qmc_config segment_config(const qmc_config* cfg, uint32_t n_circuits) {
+  qmc_config s = *cfg;
+  s.n_replicas = cfg->n_replicas * n_circuits;
+  return s;
+}
+
+int validate_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* models,
+                   std::string& why) {
+  if (!cfg || !models || n_circuits < 1 || n_circuits > (uint32_t)qmc::kMaxCircuits) {
+    why = "1..512 circuits with a model each";
+    return QMC_ERR_ARG;
+  }
+  if ((uint64_t)cfg->n_replicas * n_circuits >= (1u << 24)) {
+    why = "circuits x replicas must stay below 2^24";
+    return QMC_ERR_ARG;
+  }
+  const qmc_config s = segment_config(cfg, n_circuits);
+  for (uint32_t ci = 0; ci < n_circuits; ++ci) {
+    int rc = validate(&s, &models[ci], why);
+    if (rc) {
+      why = "circuit " + std::to_string(ci) + ": " + why;
+      return rc;
+    }
+  }
+  return QMC_OK;
+}
+
+}  // namespace
+
+int qmc_workspace_bytes_batch(const qmc_config* cfg, uint32_t n_circuits,
+                              const qmc_model* models, size_t* bytes) {
   std::string why;
-  int rc = validate(cfg, model, why);
+  int rc = validate_batch(cfg, n_circuits, models, why);
   if (rc) return rc;
   uint32_t P = 0;
   rc = persist_segments(&P);
   if (rc) return rc;
   Layout L;
-  compute_layout(*cfg, P, L);
+  compute_layout(segment_config(cfg, n_circuits), P, n_circuits, L);
   if (bytes) *bytes = L.total;
   return QMC_OK;
 }
 
-int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys,
-             const int32_t* re, const int32_t* im, uint64_t n0, void* d_workspace,
-             size_t ws_bytes, void* hip_stream, qmc_ctx** out) {
-  static thread_local std::string g_why;
+int qmc_workspace_bytes(const qmc_config* cfg, const qmc_model* model, size_t* bytes) {
+  return qmc_workspace_bytes_batch(cfg, 1, model, bytes);
+}
+
+int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* models,
+                   const uint64_t* const* keys, const int32_t* const* re,
+                   const int32_t* const* im, const uint64_t* n0, void* d_workspace,
+                   size_t ws_bytes, void* hip_stream, qmc_ctx** out) {
   if (!out) return QMC_ERR_ARG;
   *out = nullptr;
   std::string why;
-  int rc = validate(cfg, model, why);
-  if (!rc) rc = check_records(cfg->n_qubits, keys, re, im, n0, why);
+  int rc = validate_batch(cfg, n_circuits, models, why);
   if (rc) return rc;
-  if (n0 > cfg->store_capacity) return QMC_ERR_ARG;
+  if (!keys || !re || !im || !n0) return QMC_ERR_ARG;
+  for (uint32_t ci = 0; ci < n_circuits; ++ci) {
+    rc = check_records(cfg->n_qubits, keys[ci], re[ci], im[ci], n0[ci], why);
+    if (rc) return rc;
+    if (n0[ci] > cfg->store_capacity) return QMC_ERR_ARG;
+  }
+  uint32_t P = 0;
+  if (persist_segments(&P)) return QMC_ERR_HIP;
+  if (n_circuits > P) return QMC_ERR_ARG;  // every circuit needs a key range of its own
   qmc_ctx* c = new qmc_ctx();
-  c->cfg = *cfg;
+  c->cfg = segment_config(cfg, n_circuits);
   c->n = cfg->n_qubits;
-  c->R = cfg->n_replicas;
+  c->C = n_circuits;
+  c->Rc = cfg->n_replicas;
+  c->R = c->C * c->Rc;
   c->kbits = 2 * c->n;
   c->rbits = replica_bits(c->R);
-  c->n_h = model->n_h;
-  c->n_l = model->n_l;
-  uint32_t P = 0;
-  if (persist_segments(&P)) {
-    delete c;
-    return QMC_ERR_HIP;
+  c->n_h = c->n_l = 0;
+  c->terms.resize(c->C);
+  for (uint32_t ci = 0; ci < c->C; ++ci) {
+    c->wh_off.push_back(c->n_h);
+    c->wl_off.push_back(c->n_l);
+    c->n_h += models[ci].n_h;
+    c->n_l += models[ci].n_l;
+    compile_model(models[ci], c->n, c->terms[ci]);
   }
-  compute_layout(*cfg, P, c->L);
+  compute_layout(c->cfg, P, c->C, c->L);
   if (!d_workspace || ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) {
     delete c;
     return QMC_ERR_ARG;
   }
   c->ws = (uint8_t*)d_workspace;
   c->stream = (hipStream_t)hip_stream;
-  compile_model(*model, c->n, c->terms);
   c->shift.assign(c->R, 0.0);
-  int64_t nd = 0;
-  for (uint64_t i = 0; i < n0; ++i) {
-    const uint64_t ket = keys[i] & ((c->n >= 32) ? 0xFFFFFFFFull : ((1ull << c->n) - 1));
-    const uint64_t bra = c->n >= 32 ? keys[i] >> 32 : keys[i] >> c->n;
-    if (ket == bra) nd += re[i];
+  c->nd0_re.assign(c->R, 0);
+  for (uint32_t ci = 0; ci < c->C; ++ci) {
+    int64_t nd = 0;
+    for (uint64_t i = 0; i < n0[ci]; ++i) {
+      const uint64_t kk = keys[ci][i];
+      const uint64_t ket = kk & ((c->n >= 32) ? 0xFFFFFFFFull : ((1ull << c->n) - 1));
+      const uint64_t bra = c->n >= 32 ? kk >> 32 : kk >> c->n;
+      if (ket == bra) nd += re[ci][i];
+    }
+    for (uint32_t r = 0; r < c->Rc; ++r) c->nd0_re[(size_t)ci * c->Rc + r] = nd;
   }
-  c->nd0_re.assign(c->R, nd);
-  hipError_t e = hipHostMalloc((void**)&c->pinned, kTableArea + (size_t)kMaxChunkSteps * 8,
+  hipError_t e = hipHostMalloc((void**)&c->pinned,
+                               kTableArea + (size_t)kMaxChunkSteps * 4 * (c->C + 1),
                                hipHostMallocDefault);
   c->pinned_small_bytes = std::max<size_t>(1 << 16, (size_t)c->R * kMaxLookup * 16 + 4096);
+  c->pinned_small_bytes = std::max<size_t>(c->pinned_small_bytes, (size_t)c->C * 16 + 4096);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->pinned_small, c->pinned_small_bytes, hipHostMallocDefault);
   if (e != hipSuccess) {
     qmc_destroy(c);
     return QMC_ERR_HIP;
   }
-  // zero counters, then the initial store (replica tag in the high bits)
+  // zero counters, then the initial store (segment tag in the high bits)
   e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
   if (e == hipSuccess)
     e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)2 * c->L.P * 4 * 8, c->stream);
@@ -563,12 +619,13 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
   }
   std::vector<uint64_t> ck;
   std::vector<int2> cv;
-  ck.reserve(n0 * c->R);
-  cv.reserve(n0 * c->R);
-  for (uint32_t r = 0; r < c->R; ++r)
-    for (uint64_t i = 0; i < n0; ++i) {
-      ck.push_back((c->kbits >= 64 ? 0 : ((uint64_t)r << c->kbits)) | keys[i]);
-      cv.push_back(make_int2(re[i], im[i]));
+  for (uint32_t ci = 0; ci < c->C; ++ci)
+    for (uint32_t r = 0; r < c->Rc; ++r) {
+      const uint64_t seg = (uint64_t)ci * c->Rc + r;
+      for (uint64_t i = 0; i < n0[ci]; ++i) {
+        ck.push_back((c->kbits >= 64 ? 0 : (seg << c->kbits)) | keys[ci][i]);
+        cv.push_back(make_int2(re[ci][i], im[ci][i]));
+      }
     }
   c->cur = 0;
   rc = upload_store(c, 0, ck, cv);
@@ -577,12 +634,18 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
     rc = upload_qshift(c, qs);
   }
   if (rc) {
-    g_why = c->err;
     qmc_destroy(c);
     return rc;
   }
   *out = c;
   return QMC_OK;
+}
+
+int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys,
+             const int32_t* re, const int32_t* im, uint64_t n0, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, qmc_ctx** out) {
+  return qmc_init_batch(cfg, 1, model, &keys, &re, &im, &n0, d_workspace, ws_bytes, hip_stream,
+                        out);
 }
 
 namespace {
@@ -603,8 +666,6 @@ constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a 
 // the chunk integrates with AB2 from a known N(s-1) (`two`; the tables B exist).
 struct Chunk {
   uint8_t* dtab;                 // the device table area
-  const uint32_t* offsA;         // table offsets of the chunk's steps (host copy)
-  const uint32_t* offsB;         // AB2: second-term table offsets, or null
   uint32_t first;                // index of the chunk's first step in the device offset arrays
   uint32_t nst;
   bool two;
@@ -637,8 +698,10 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.split_w = c->at<uint64_t>(c->L.split);
   pl.P = c->L.P;
   pl.tab_base = ch.dtab;
-  pl.tab_off = c->at<uint32_t>(c->L.tab_off) + ch.first;
+  pl.tab_off = c->at<uint32_t>(c->L.tab_off) + (size_t)ch.first * c->C;
   pl.tabB_off = ch.two ? c->at<uint32_t>(c->L.tabB_off) + ch.first : nullptr;
+  pl.n_circuits = c->C;
+  pl.rep_per = c->Rc;
   pl.step0 = c->step;
   pl.nsteps = nst;
   pl.seed = c->cfg.seed;
@@ -740,11 +803,14 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   };
   uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
   HIPCHK(c, mark(0, 0, 0));
-  HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab + ch.offsA[0],
+  // device table offsets of step k of the chunk: [circuit] (A), and the AB2 B term
+  const uint32_t* dA = c->at<uint32_t>(c->L.tab_off) + (size_t)ch.first * c->C;
+  const uint32_t* dB = c->at<uint32_t>(c->L.tabB_off) + ch.first;
+  HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab, dA, c->Rc,
                        step0, c->cfg.seed, c->kbits, c->init_min, 0u, qshA, c->ck(cb), c->cv(cb),
                        c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
   if (ch.two)
-    HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab + ch.offsB[0],
+    HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab, dB, c->Rc,
                          step0, c->cfg.seed, c->kbits, c->init_min, 1u, qshB, c->ck(cb),
                          c->cv(cb),
                          c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
@@ -752,8 +818,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   for (uint32_t k = 0; k < nst; ++k) {
     const uint32_t st = step0 + k, b = k % nb, cur = cur0 ^ (k & 1u);
     const bool more = k + 1 < nst;
-    const uint8_t* tab_next = more ? dtab + ch.offsA[k + 1] : nullptr;
-    const uint8_t* tabB_next = more && c->integrator == 1 ? dtab + ch.offsB[k + 1] : nullptr;
+    const uint32_t* toff_next = more ? dA + (size_t)(k + 1) * c->C : nullptr;
+    const uint32_t* toffB_next = more && c->integrator == 1 ? dB + (k + 1) : nullptr;
     const uint32_t csel = st & 1;
     HIPCHK(c, mark(1, k, 0));
     HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
@@ -763,8 +829,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     const uint32_t cf = cb ^ (passes & 1);  // sorted children
     HIPCHK(c, mark(2, k, 0));
     HIPCHK(c, qmck_merge(c->stream, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
-                         c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), tab_next,
-                         tabB_next, qshA, qshB, st, c->cfg.seed, c->kbits, c->init_min,
+                         c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), dtab,
+                         toff_next, toffB_next, c->Rc, qshA, qshB, st, c->cfg.seed, c->kbits, c->init_min,
                          bk[(k + 1) % nb],
                          bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
                          c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
@@ -842,12 +908,17 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     if (ab2) max_qb = std::max(max_qb, uabs(qsB[r]));
     if (euler_first) max_qa = std::max(max_qa, uabs(qs1[r]));
   }
-  // Tables of step k into (TA, TB); QMC_OK or the error with its message.
-  auto build_step = [&](uint32_t k, HostTable& TA, HostTable& TB, std::string& why) -> int {
+  // Tables of step k of circuit ci into (TA, TB); QMC_OK or the error with its message.  (AB2
+  // runs with one circuit only.)
+  const uint32_t NC = c->C;
+  auto build_step = [&](uint32_t k, uint32_t ci, HostTable& TA, HostTable& TB,
+                        std::string& why) -> int {
     const double *ws, *wg;
     wts(k, ws, wg);
+    ws += c->wh_off[ci];
+    wg += c->wl_off[ci];
     const bool two = ab2 && k >= euler_first;
-    int rc = build_table(c, ws, wg, two ? 1.5 : 1.0, TA, why);
+    int rc = build_table(c->terms[ci], c->cfg.dt, ws, wg, two ? 1.5 : 1.0, TA, why);
     if (!rc && two) {
       const double *ps, *pg;
       if (k > 0) {
@@ -856,7 +927,7 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
         ps = c->w_prev.data();
         pg = c->w_prev.data() + c->n_h;
       }
-      rc = build_table(c, ps, pg, -0.5, TB, why);
+      rc = build_table(c->terms[ci], c->cfg.dt, ps, pg, -0.5, TB, why);
       if (!rc && TB.q_diag + max_qb >= (1ull << 31)) {
         rc = QMC_ERR_DT;
         why = "diagonal group with shift violates the Q32 bound";
@@ -874,11 +945,11 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     }
     return rc;
   };
-  // Table windows: steps [win0, win1) of this call have their packed tables in the device table
-  // area (at the same offsets as in the pinned staging area) and their offsets in tab_off /
-  // tabB_off; every launch of those steps reuses them.
+  // Table windows: steps [win0, win1) of this call have their packed tables (all circuits) in
+  // the device table area, at the same offsets as in the pinned staging area, and their offsets
+  // in tab_off ([step][circuit]) / tabB_off; every launch of those steps reuses them.
   const uint32_t wmax = std::min<uint32_t>(nsteps, kMaxChunkSteps);
-  std::vector<uint32_t> offA(wmax, 0), offB(ab2 ? wmax : 0, 0);
+  std::vector<uint32_t> offA((size_t)wmax * NC, 0), offB(ab2 ? wmax : 0, 0);
   uint32_t win0 = 0, win1 = 0;
   size_t max_tbytes = 0;
   auto upload_window = [&](const std::vector<std::pair<size_t, size_t>>& spans) -> int {
@@ -887,16 +958,35 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
         HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab) + sp.first, c->pinned + sp.first,
                                  sp.second, hipMemcpyHostToDevice, c->stream));
     uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
-    const uint32_t nw = win1 - win0;
-    std::memcpy(po, offA.data(), (size_t)nw * 4);
-    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), po, (size_t)nw * 4,
-                             hipMemcpyHostToDevice, c->stream));
+    const size_t nw = (size_t)(win1 - win0) * NC;
+    std::memcpy(po, offA.data(), nw * 4);
+    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), po, nw * 4, hipMemcpyHostToDevice,
+                             c->stream));
     if (ab2) {
-      std::memcpy(po + kMaxChunkSteps, offB.data(), (size_t)nw * 4);
-      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tabB_off), po + kMaxChunkSteps,
-                               (size_t)nw * 4, hipMemcpyHostToDevice, c->stream));
+      uint32_t* pb = po + (size_t)kMaxChunkSteps * NC;
+      std::memcpy(pb, offB.data(), (size_t)(win1 - win0) * 4);
+      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tabB_off), pb, (size_t)(win1 - win0) * 4,
+                               hipMemcpyHostToDevice, c->stream));
     }
     return QMC_OK;
+  };
+  // Packs the tables of step k (all circuits, both AB2 terms) at `bytes` of the staging area
+  // when they fit under `cap`; returns false otherwise.
+  auto pack_step = [&](uint32_t k, uint32_t slot, std::vector<HostTable>& TA, HostTable& TB,
+                       size_t base, size_t& used, size_t cap) -> bool {
+    const bool two = ab2 && k >= euler_first;
+    size_t need = two ? pack_table(TB, nullptr) : 0;
+    for (uint32_t ci = 0; ci < NC; ++ci) need += pack_table(TA[ci], nullptr);
+    if (used + need > cap) return false;
+    for (uint32_t ci = 0; ci < NC; ++ci) {
+      offA[(size_t)slot * NC + ci] = (uint32_t)(base + used);
+      used += pack_table(TA[ci], c->pinned + base + used);
+    }
+    if (two) {
+      offB[slot] = (uint32_t)(base + used);
+      used += pack_table(TB, c->pinned + base + used);
+    }
+    return true;
   };
   {
     // Long calls build on a few host threads (tables are independent), each packing its run of
@@ -911,40 +1001,33 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
       std::string why;
     };
     std::vector<Part> parts(nth);
+    const size_t slice = (kTableArea / nth) & ~(size_t)255;  // slices stay 256-byte aligned
     for (uint32_t i = 0; i < nth; ++i) {
       Part& q = parts[i];
       q.a = (uint32_t)((uint64_t)nsteps * i / nth);
       q.b = (uint32_t)((uint64_t)nsteps * (i + 1) / nth);
       q.stored = q.a;
       q.bad = nsteps;
-      q.base = kTableArea / nth * i;
+      q.base = slice * i;
       q.used = q.max_bytes = 0;
       q.code = QMC_OK;
     }
     auto part = [&](uint32_t i) {
       Part& q = parts[i];
-      const size_t cap = kTableArea / nth;
-      HostTable TA, TB;
+      std::vector<HostTable> TA(NC);
+      HostTable TB;
       for (uint32_t k = q.a; k < q.b; ++k) {
-        q.code = build_step(k, TA, TB, q.why);
-        if (q.code) {
-          q.bad = k;
-          return;
-        }
-        const bool two = ab2 && k >= euler_first;
-        const size_t sa = pack_table(TA, nullptr), sb = two ? pack_table(TB, nullptr) : 0;
-        q.max_bytes = std::max(q.max_bytes, std::max(sa, sb));
-        if (q.stored == k && k < wmax && q.used + sa + sb <= cap) {
-          offA[k] = (uint32_t)(q.base + q.used);
-          pack_table(TA, c->pinned + q.base + q.used);
-          q.used += sa;
-          if (two) {
-            offB[k] = (uint32_t)(q.base + q.used);
-            pack_table(TB, c->pinned + q.base + q.used);
-            q.used += sb;
+        for (uint32_t ci = 0; ci < NC; ++ci) {
+          q.code = build_step(k, ci, TA[ci], TB, q.why);
+          if (q.code) {
+            q.bad = k;
+            return;
           }
-          q.stored = k + 1;
+          q.max_bytes = std::max(q.max_bytes, pack_table(TA[ci], nullptr));
         }
+        if (ab2 && k >= euler_first) q.max_bytes = std::max(q.max_bytes, pack_table(TB, nullptr));
+        if (q.stored == k && k < wmax && pack_step(k, k, TA, TB, q.base, q.used, slice))
+          q.stored = k + 1;
       }
     };
     std::vector<std::thread> pool;
@@ -969,7 +1052,7 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
         win1 = q.stored;
       }
     }
-    if (win1 == 0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
+    if (win1 == 0) return fail(c, QMC_ERR_ARG, "step tables larger than the table area");
     int rc = upload_window(spans);
     if (rc) return rc;
   }
@@ -1008,24 +1091,17 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
       // the next window (calls longer than the first one): packed here, one step after another
       win0 = win1 = k0;
       size_t bytes = 0;
-      HostTable TA, TB;
+      std::vector<HostTable> TA(NC);
+      HostTable TB;
       std::string why;
       while (win1 < nsteps && win1 - win0 < kMaxChunkSteps) {
-        if (build_step(win1, TA, TB, why)) return fail(c, QMC_ERR_STATE, "table changed: " + why);
-        const bool tw = ab2 && win1 >= euler_first;
-        const size_t sa = pack_table(TA, nullptr), sb = tw ? pack_table(TB, nullptr) : 0;
-        if (bytes + sa + sb > kTableArea) break;
-        offA[win1 - win0] = (uint32_t)bytes;
-        pack_table(TA, c->pinned + bytes);
-        bytes += sa;
-        if (tw) {
-          offB[win1 - win0] = (uint32_t)bytes;
-          pack_table(TB, c->pinned + bytes);
-          bytes += sb;
-        }
+        for (uint32_t ci = 0; ci < NC; ++ci)
+          if (build_step(win1, ci, TA[ci], TB, why))
+            return fail(c, QMC_ERR_STATE, "table changed: " + why);
+        if (!pack_step(win1, win1 - win0, TA, TB, 0, bytes, kTableArea)) break;
         ++win1;
       }
-      if (win1 == k0) return fail(c, QMC_ERR_ARG, "step table larger than the table area");
+      if (win1 == k0) return fail(c, QMC_ERR_ARG, "step tables larger than the table area");
       int rc = upload_window({{0, bytes}});
       if (rc) return rc;
     }
@@ -1035,8 +1111,6 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
     const uint32_t k1 = std::min<uint32_t>(kmax, win1);
     ch.nst = k1 - k0;
     ch.first = k0 - win0;
-    ch.offsA = offA.data() + ch.first;
-    ch.offsB = two ? offB.data() + ch.first : nullptr;
     qmc::Counters hc;
     uint32_t kd = 0, reason = 0;
     int rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);
@@ -1088,6 +1162,7 @@ int qmc_step_path(qmc_ctx* c, int32_t path) {
 
 int qmc_set_integrator(qmc_ctx* c, int32_t integrator) {
   if (!c || integrator < 0 || integrator > 1) return QMC_ERR_ARG;
+  if (integrator == 1 && c->C > 1) return fail(c, QMC_ERR_ARG, "AB2 runs one circuit per context");
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
   c->integrator = integrator;
   c->have_prev = false;
@@ -1095,18 +1170,28 @@ int qmc_set_integrator(qmc_ctx* c, int32_t integrator) {
   return QMC_OK;
 }
 
-int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
-  if (!c) return QMC_ERR_ARG;
+int qmc_pulse_batch(qmc_ctx* c, const uint64_t* x, const uint64_t* z) {
+  if (!c || !x || !z) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
   const uint64_t qmask = c->n >= 32 ? 0xFFFFFFFFull : ((1ull << c->n) - 1);
-  if ((x | z) & ~qmask) return fail(c, QMC_ERR_ARG, "pulse mask outside n bits");
+  bool any_x = false;
+  uint64_t* pin = reinterpret_cast<uint64_t*>(c->pinned_small);
+  for (uint32_t ci = 0; ci < c->C; ++ci) {
+    if ((x[ci] | z[ci]) & ~qmask) return fail(c, QMC_ERR_ARG, "pulse mask outside n bits");
+    any_x = any_x || x[ci] != 0;
+    pin[2 * ci] = x[ci];
+    pin[2 * ci + 1] = z[ci];
+  }
   qmc::Counters* dcnt = c->counters();
+  HIPCHK(c, hipMemcpyAsync(c->at<uint64_t>(c->L.pulse), pin, (size_t)c->C * 16,
+                           hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, qmck_batch_begin(c->stream, dcnt, nullptr, 0,
                              c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
                              2 * qmc::kMaxPasses * qmc::kRadixBins));
-  HIPCHK(c, qmck_pulse(c->stream, c->sk(c->cur), c->sv(c->cur), dcnt, c->cur, c->n, x, z,
-                       c->ck(0), c->cv(0), 0, c->L.cap_store));
-  if (x != 0) {
+  HIPCHK(c, qmck_pulse(c->stream, c->sk(c->cur), c->sv(c->cur), dcnt, c->cur, c->n, c->kbits,
+                       c->Rc, c->at<uint64_t>(c->L.pulse), any_x ? 1 : 0, c->ck(0), c->cv(0), 0,
+                       c->L.cap_store));
+  if (any_x) {
     const uint32_t passes = qmck_sort_passes(c->kbits + c->rbits);
     HIPCHK(c, qmck_digit_hist(c->stream, c->ck(0), dcnt, 0, passes, c->ghist(0), c->L.cap_store));
     HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, 0, passes,
@@ -1117,7 +1202,7 @@ int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
                               &dcnt->n_child[0], c->L.cap_store));
   }
   qmc::Counters hc;
-  int rc = read_counters(c, hc);
+  int rc = read_counters(c, hc);  // also keeps the pinned masks alive until the copy is done
   if (rc) return rc;
   if (hc.err & qmc::kErrOverflow)
     return fail(c, QMC_ERR_COUNT_OVERFLOW, "pulse negated INT32_MIN");
@@ -1125,9 +1210,17 @@ int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
   return QMC_OK;
 }
 
+int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
+  if (!c) return QMC_ERR_ARG;
+  std::vector<uint64_t> xs(c->C, x), zs(c->C, z);
+  return qmc_pulse_batch(c, xs.data(), zs.data());
+}
+
 int qmc_set_initiator(qmc_ctx* c, uint64_t min_walkers) {
   if (!c) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (min_walkers > 0 && c->C > 1)
+    return fail(c, QMC_ERR_ARG, "the initiator approximation runs one circuit per context");
   if (min_walkers > 0 && c->kbits + c->rbits + 1 > 64)
     return fail(c, QMC_ERR_ARG, "no key bit left for the initiator flag");
   c->init_min = min_walkers;
@@ -1437,13 +1530,11 @@ int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double*
   std::string why;
   int rc = validate(cfg, model, why);
   if (rc) return rc;
-  qmc_ctx tmp;
-  tmp.cfg = *cfg;
-  tmp.n = cfg->n_qubits;
-  compile_model(*model, tmp.n, tmp.terms);
+  std::vector<SrcTerm> terms;
+  compile_model(*model, cfg->n_qubits, terms);
   HostTable T;
   if (!std::isfinite(scale)) return QMC_ERR_ARG;
-  rc = build_table(&tmp, s, gamma, scale, T, why);
+  rc = build_table(terms, cfg->dt, s, gamma, scale, T, why);
   if (rc) return rc;
   *n_groups = (uint32_t)T.gx.size();
   *n_terms = (uint32_t)T.t.size();

@@ -13,8 +13,10 @@ int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t 
 // delta of each parent (diagonal of its column plus the per-replica Q32 shift qsh) and its
 // children.  init_min > 0: initiator approximation, record keys carry the non-initiator flag
 // below the composite key.
+// The tables are tab_base + tab_off[c] for circuit c (rep_per replicas per circuit).
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
-               const uint64_t* count, const uint8_t* tab, uint32_t step, uint64_t seed,
+               const uint64_t* count, const uint8_t* tab_base, const uint32_t* tab_off,
+               uint32_t rep_per, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint32_t stream, const int64_t* qsh,
                uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
                uint32_t passes);
@@ -25,14 +27,17 @@ int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, vo
               uint32_t step, uint32_t src, uint64_t max_items);
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, const uint8_t* tab_next, const uint8_t* tabB_next,
-               const int64_t* qshift, const int64_t* qshiftB, uint32_t step, uint64_t seed,
+               uint64_t* status, const uint8_t* tab_base, const uint32_t* toff_next,
+               const uint32_t* toffB_next, uint32_t rep_per, const int64_t* qshift,
+               const int64_t* qshiftB, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
                uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
                uint32_t* ghist_next, uint32_t passes);
+// Ideal Pauli pulse: circuit c of the store (rep_per replicas each) takes X^x Z^z with
+// (x, z) = (pxz[2c], pxz[2c+1]) (device); with any_x the records go to (ck, cv) for a re-sort.
 int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t cur, uint32_t n,
-               uint64_t x, uint64_t z, uint64_t* ck, int2* cv, uint32_t csel,
-               uint64_t max_parents);
+               uint32_t kbits, uint32_t rep_per, const uint64_t* pxz, int any_x, uint64_t* ck,
+               int2* cv, uint32_t csel, uint64_t max_parents);
 // Copies *count records (a device counter) from (ki, vi) to (ko, vo).
 int qmck_copy_store(hipStream_t st, const uint64_t* ki, const int2* vi, uint64_t* ko, int2* vo,
                     const uint64_t* count, uint64_t max_items);

@@ -85,22 +85,20 @@ struct Emitter {
   }
 };
 
-// Death/cloning record and children of one parent (called by every lane of a wave; `valid` lanes
-// hold a parent), drawn from Philox stream `stream`; `qsh` holds the per-replica Q32 shifts of
-// this table.  The death delta is a record of the parent's own key, summed into N(s+1) by the
-// merge like the children.
-__device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, bool valid,
-                                             uint64_t ck, int2 v, uint32_t step, uint64_t seed,
-                                             const KeyLayout& kl, uint32_t stream,
-                                             const int64_t* qsh) {
-  const uint32_t G = tv.h->n_groups;
-  uint32_t w[4] = {0, 0, 0, 0};
-  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-  if (valid) walker_random(kl.key(ck), step, kl.replica(ck), seed, stream, w);
+// Death/cloning record and children of one parent per lane, every lane of the wave calling
+// (`valid` lanes hold a parent; (w0, w1) its spawn and death comb words).  The lane's table is its
+// circuit's (tv); tables of different circuits may have different group counts, so the group
+// loop runs to the largest count in the wave.  The death delta is a record of the parent's own
+// key, summed into the next store by the merge like the children; qsh holds the per-segment Q32
+// shifts of the table.
+__device__ __forceinline__ void spawn_records(Emitter& em, const TableView& tv, bool valid,
+                                              uint64_t ck, int2 v, uint32_t w0, uint32_t w1,
+                                              const KeyLayout& kl, const int64_t* qsh) {
   const uint64_t key = kl.key(ck);
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
   {
     const int64_t qs = valid ? qsh[kl.replica(ck)] : 0;
-    const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w[1]);
+    const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w1);
     if (__ballot(dact)) {
       int2 d = make_int2(0, 0);
       if (dact) {
@@ -108,36 +106,46 @@ __device__ __forceinline__ void spawn_parent(Emitter& em, const TableView& tv, b
         group_coeff(tv.t, 0, tv.gs[1], key, dre, dim);
         int64_t xre, xim;
         cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
-        uint64_t r = w[1];
+        uint64_t r = w1;
         d.x = (int32_t)comb_step(r, xre);
         d.y = (int32_t)comb_step(r, xim);
       }
       em.emit((d.x | d.y) != 0, kl.rkey(ck, sab), d);
     }
   }
-  if (G <= 1) return;
-  const bool active = valid && !comb_all_zero(sab, tv.h->q_off, w[0]);
-  if (__ballot(active) == 0) return;
-  uint64_t r = w[0];
-  for (uint32_t g = 1; g < G; ++g) {
+  const uint32_t G = valid ? tv.h->n_groups : 0u;
+  const bool act = valid && G > 1 && !comb_all_zero(sab, tv.h->q_off, w0);
+  uint64_t r = w0;
+  for (uint32_t g = 1; __ballot(act && g < G) != 0; ++g) {
     int2 child = make_int2(0, 0);
-    if (active) {
+    uint64_t target = ck;
+    if (act && g < G) {
       int32_t cre, cim;
       group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
       int64_t xre, xim;
       cmul_q32(v.x, v.y, cre, cim, xre, xim);
       child.x = (int32_t)comb_step(r, xre);
       child.y = (int32_t)comb_step(r, xim);
+      target = ck ^ tv.gx[g];
     }
-    em.emit((child.x | child.y) != 0, kl.rkey(ck ^ tv.gx[g], sab), child);
+    em.emit((child.x | child.y) != 0, kl.rkey(target, sab), child);
   }
 }
 
-// Death/cloning record and children of up to 64 queued parents (lane < n holds one; (w0, w1) are
-// its spawn and death comb words, drawn when it was queued), every lane of the wave calling.  The
-// death delta of step s+1 is a record of the parent's own key, summed into N(s+2) by the next
-// merge like the children.
-__device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, const int64_t* qsh,
+// Records of one parent per lane drawn from Philox stream `stream` at step `step`.
+__device__ __forceinline__ void spawn_parent(Emitter& em, const TabSet& ts, bool valid,
+                                             uint64_t ck, int2 v, uint32_t step, uint64_t seed,
+                                             const KeyLayout& kl, uint32_t stream,
+                                             const int64_t* qsh) {
+  uint32_t w[4] = {0, 0, 0, 0};
+  if (valid) walker_random(kl.key(ck), step, kl.replica(ck), seed, stream, w);
+  const TableView tv = table_view(ts.of_segment(valid ? kl.replica(ck) : 0u));
+  spawn_records(em, tv, valid, ck, v, w[0], w[1], kl, qsh);
+}
+
+// Records of up to 64 queued parents (lane < n holds one, with the comb words drawn when it was
+// queued).
+__device__ __forceinline__ void spawn_batch(Emitter& em, const TabSet& ts, const int64_t* qsh,
                                             const uint64_t* ak, const int2* av, const uint2* aw,
                                             uint32_t n, const KeyLayout& kl) {
   const uint32_t lane = __lane_id();
@@ -145,41 +153,8 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, co
   const uint64_t ck = valid ? ak[lane] : 0;
   const int2 v = valid ? av[lane] : make_int2(0, 0);
   const uint2 w = valid ? aw[lane] : make_uint2(0, 0);
-  const uint64_t key = kl.key(ck);
-  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-  {
-    const int64_t qs = valid ? qsh[kl.replica(ck)] : 0;
-    const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w.y);
-    if (__ballot(dact)) {
-      int2 d = make_int2(0, 0);
-      if (dact) {
-        int32_t dre, dim;
-        group_coeff(tv.t, 0, tv.gs[1], key, dre, dim);
-        int64_t xre, xim;
-        cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
-        uint64_t r = w.y;
-        d.x = (int32_t)comb_step(r, xre);
-        d.y = (int32_t)comb_step(r, xim);
-      }
-      em.emit((d.x | d.y) != 0, kl.rkey(ck, sab), d);
-    }
-  }
-  const uint32_t G = tv.h->n_groups;
-  const bool act = valid && G > 1 && !comb_all_zero(sab, tv.h->q_off, w.x);
-  if (__ballot(act) == 0) return;
-  uint64_t r = w.x;
-  for (uint32_t g = 1; g < G; ++g) {
-    int2 child = make_int2(0, 0);
-    if (act) {
-      int32_t cre, cim;
-      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
-      int64_t xre, xim;
-      cmul_q32(v.x, v.y, cre, cim, xre, xim);
-      child.x = (int32_t)comb_step(r, xre);
-      child.y = (int32_t)comb_step(r, xim);
-    }
-    em.emit((child.x | child.y) != 0, kl.rkey(ck ^ tv.gx[g], sab), child);
-  }
+  const TableView tv = table_view(ts.of_segment(valid ? kl.replica(ck) : 0u));
+  spawn_records(em, tv, valid, ck, v, w.x, w.y, kl, qsh);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -188,7 +163,7 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TableView& tv, co
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_spawn(
     const uint64_t* __restrict__ pk, const int2* __restrict__ pv, Counters* __restrict__ cnt,
-    const uint64_t* __restrict__ count, const uint8_t* __restrict__ tab, uint32_t step,
+    const uint64_t* __restrict__ count, TabSet ts, uint32_t step,
     uint64_t seed, KeyLayout kl, uint32_t stream, const int64_t* __restrict__ qsh,
     uint64_t* __restrict__ ck_out, int2* __restrict__ cv_out, uint64_t cap_child,
     uint32_t* __restrict__ ghist, uint32_t passes) {
@@ -196,7 +171,6 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
   __shared__ int2 s_val[kWaves][kSpawnSeg];
   if (cnt->err) return;
   const uint64_t np = *count;
-  const TableView tv = table_view(tab);
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   Emitter em{s_key[wave], s_val[wave], kSpawnSeg, 0, cnt, step & 1u, step, ck_out, cv_out,
              cap_child, ghist, passes};
@@ -211,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
       ck = pk[p];
       v = pv[p];
     }
-    spawn_parent(em, tv, valid, ck, v, step, seed, kl, stream, qsh);
+    spawn_parent(em, ts, valid, ck, v, step, seed, kl, stream, qsh);
   }
   if (em.fill) em.flush();
 }
@@ -540,8 +514,8 @@ struct MergeArgs {
   const uint2* splits;
   uint64_t* status;
   uint32_t epoch;
-  const uint8_t* tab_next;   // table of step s+1 (death and spawn), or null
-  const uint8_t* tabB_next;  // AB2: table of the second term of step s+1 (from N(s)), or null
+  TabSet tab_next;           // tables of step s+1 (death and spawn), or none
+  TabSet tabB_next;          // AB2: tables of the second term of step s+1 (from N(s)), or none
   const int64_t* qshiftB;    // AB2: its per-replica Q32 shifts
   const int64_t* qshift;    // per-replica Q32 shifts of tab_next
   uint32_t step;
@@ -592,13 +566,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   // then moves the rest to the front of the queue.  Block-uniform; ends with the queue stable.
   auto drain = [&](uint32_t nb) __attribute__((always_inline)) {
     if (nb > 0) {
-      const TableView tn = table_view(A.tab_next);
       Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
                  cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child, A.ghist_next,
                  A.passes};
       for (uint32_t b = wave; b < nb; b += kWaves) {
         const uint32_t b0 = b * kWave;
-        spawn_batch(em, tn, A.qshift, s_ak + b0, s_av + b0, s_aw + b0,
+        spawn_batch(em, A.tab_next, A.qshift, s_ak + b0, s_av + b0, s_aw + b0,
                     nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl);
       }
       if (em.fill) em.flush();
@@ -772,10 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
 
     // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
     // that can spawn go to the queue; full batches are spawned when it fills.
-    if (A.tab_next) {
-      const TableView tn = table_view(A.tab_next);
-      const uint64_t q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
-      const uint64_t q_diag = tn.h->q_diag;
+    if (A.tab_next.valid()) {
       for (uint32_t base = 0; base < agg; base += kBlock) {
         const uint32_t p = base + threadIdx.x;
         bool act = false;
@@ -788,8 +758,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           const uint32_t rep = kl.replica(ck);
           walker_random(kl.key(ck), A.step + 1, rep, A.seed, 0u, w);
           const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+          const TableView tn = table_view(A.tab_next.of_segment(rep));
+          const uint64_t q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
           act = !comb_all_zero(sab, q_off, w[0]) ||
-                !comb_all_zero(sab, q_diag + uabs64(A.qshift[rep]), w[1]);
+                !comb_all_zero(sab, tn.h->q_diag + uabs64(A.qshift[rep]), w[1]);
         }
         const uint64_t m = __ballot(act);
         if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);
@@ -811,9 +783,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         nl += tot;
         __syncthreads();
       }
-      if (A.tabB_next) {
+      if (A.tabB_next.valid()) {
         // second AB2 term of step s+1 from this tile's parents N(s), as loaded
-        const TableView tb = table_view(A.tabB_next);
         Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg,
                    0, cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child,
                    A.ghist_next, A.passes};
@@ -822,7 +793,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           const bool valid = p < pn;
           const uint64_t ck = valid ? A.pk[pa + p] : 0;
           const int2 v = valid ? A.pv[pa + p] : make_int2(0, 0);
-          spawn_parent(em, tb, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
+          spawn_parent(em, A.tabB_next, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
         }
         if (em.fill) em.flush();
       }
@@ -863,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __syncthreads();
   }
   // the rest of the queue (block-uniform: every thread left the tile loop together)
-  if (A.tab_next && nl > 0) drain((nl + kWave - 1) / kWave);
+  if (A.tab_next.valid() && nl > 0) drain((nl + kWave - 1) / kWave);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -892,16 +863,19 @@ __global__ void k_batch_begin(Counters* cnt, uint64_t* status, uint64_t n_status
 // pulse with x != 0 (sorted afterwards).
 __global__ __launch_bounds__(kBlock) void k_pulse(uint64_t* __restrict__ pk, int2* __restrict__ pv,
                                                   Counters* __restrict__ cnt, uint32_t cur,
-                                                  uint32_t n, uint64_t x, uint64_t z,
+                                                  uint32_t n, KeyLayout kl, uint32_t rep_per,
+                                                  const uint64_t* __restrict__ pxz, bool any_x,
                                                   uint64_t* __restrict__ ck_out,
                                                   int2* __restrict__ cv_out, uint32_t csel) {
   const uint64_t np = cnt->n_store[cur];
   const uint64_t qm = n >= 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
-  const uint64_t kx = (x << n) | x;
   for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < np;
        p += (uint64_t)gridDim.x * kBlock) {
     const uint64_t ck = pk[p];
     int2 v = pv[p];
+    // the Pauli of this record's circuit
+    const uint32_t c = kl.replica(ck) / rep_per;
+    const uint64_t x = pxz[2 * c], z = pxz[2 * c + 1];
     const uint64_t i = ck & qm, j = (ck >> n) & qm;
     const bool neg = ((__popcll(z & i) + __popcll(z & j)) & 1) != 0;
     if (neg) {
@@ -909,14 +883,14 @@ __global__ __launch_bounds__(kBlock) void k_pulse(uint64_t* __restrict__ pk, int
       v.x = -v.x;
       v.y = -v.y;
     }
-    if (x == 0) {
+    if (!any_x) {
       pv[p] = v;
     } else {
-      ck_out[p] = ck ^ kx;
+      ck_out[p] = ck ^ ((x << n) | x);
       cv_out[p] = v;
     }
   }
-  if (x != 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt->n_child[csel] = np;
+  if (any_x && blockIdx.x == 0 && threadIdx.x == 0) cnt->n_child[csel] = np;
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_store(const uint64_t* __restrict__ ki,
@@ -1078,13 +1052,14 @@ int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t 
 }
 
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
-               const uint64_t* count, const uint8_t* tab, uint32_t step, uint64_t seed,
+               const uint64_t* count, const uint8_t* tab_base, const uint32_t* tab_off,
+               uint32_t rep_per, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint32_t stream, const int64_t* qsh,
                uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
                uint32_t passes) {
   uint32_t g = grid_for(max_parents, 1024);
   hipLaunchKernelGGL(k_spawn, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, count,
-                     tab, step, seed, key_layout(kbits, init_min), stream, qsh, ck, cv, cap_child,
+                     TabSet{tab_base, tab_off, rep_per}, step, seed, key_layout(kbits, init_min), stream, qsh, ck, cv, cap_child,
                      ghist, passes);
   return (int)hipGetLastError();
 }
@@ -1119,8 +1094,9 @@ int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, vo
 
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, const uint8_t* tab_next, const uint8_t* tabB_next,
-               const int64_t* qshift, const int64_t* qshiftB, uint32_t step, uint64_t seed,
+               uint64_t* status, const uint8_t* tab_base, const uint32_t* toff_next,
+               const uint32_t* toffB_next, uint32_t rep_per, const int64_t* qshift,
+               const int64_t* qshiftB, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
                uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
                uint32_t* ghist_next, uint32_t passes) {
@@ -1141,8 +1117,8 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.splits = splits;
   a.status = status;
   a.epoch = merge_epoch(step);
-  a.tab_next = tab_next;
-  a.tabB_next = tabB_next;
+  a.tab_next = TabSet{tab_base, toff_next, rep_per};
+  a.tabB_next = TabSet{tab_base, toffB_next, rep_per};
   a.qshiftB = qshiftB;
   a.qshift = qshift;
   a.step = step;
@@ -1163,11 +1139,11 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
 }
 
 int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t cur, uint32_t n,
-               uint64_t x, uint64_t z, uint64_t* ck, int2* cv, uint32_t csel,
-               uint64_t max_parents) {
+               uint32_t kbits, uint32_t rep_per, const uint64_t* pxz, int any_x, uint64_t* ck,
+               int2* cv, uint32_t csel, uint64_t max_parents) {
   uint32_t g = grid_for(max_parents, 8192);
   hipLaunchKernelGGL(k_pulse, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, cur, n,
-                     x, z, ck, cv, csel);
+                     key_layout(kbits), rep_per, pxz, any_x != 0, ck, cv, csel);
   return (int)hipGetLastError();
 }
 

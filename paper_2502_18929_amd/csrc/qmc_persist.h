@@ -33,6 +33,8 @@ struct PersistLaunch {
   uint64_t seed;
   uint32_t kbits;
   uint64_t init_min;    // initiator threshold in walkers (0 = off)
+  uint32_t n_circuits;  // circuits of the batch: tab_off holds n_circuits offsets per step
+  uint32_t rep_per;     // replicas per circuit (segments = n_circuits * rep_per)
   uint32_t n_replicas;
   const int64_t* qshift;     // per-replica Q32 shifts of the first / only term
   const int64_t* qshiftB;    // AB2: of the second term

@@ -51,10 +51,12 @@ struct PersistArgs {
   // key ranges: split[p] <= key < split[p+1]
   const uint64_t* split;
   uint32_t P;
-  // per-step tables of the batch
+  // per-step tables of the batch: step k of circuit c at tab_base + tab_off[k * n_circuits + c]
   const uint8_t* tab_base;
   const uint32_t* tab_off;
-  const uint32_t* tabB_off;  // AB2: tables of the second term, or null (Euler)
+  const uint32_t* tabB_off;  // AB2 (one circuit): tables of the second term, or null (Euler)
+  uint32_t n_circuits;
+  uint32_t rep_per;          // replicas per circuit
   uint32_t step0, nsteps;
   uint64_t seed;
   KeyLayout kl;
@@ -66,7 +68,8 @@ struct PersistArgs {
                           // error bits, each tagged with the epoch
   uint64_t cap_store;     // total occupied keys allowed
   uint64_t cap_inbox;     // total inbox records allowed per step
-  uint32_t rebal_min;     // stop to rebalance when the largest range exceeds 1.25 x mean + this
+  uint32_t rebal_min;     // stop to rebalance when the largest range exceeds 1.25 x the larger
+                          // of the mean and the launch's first largest range, + this
   uint64_t epoch0;        // first barrier epoch of this launch (epochs only grow)
   uint32_t* done;         // [0] steps completed, [1] stop reason (0 end, 1 rebalance, 2 error)
 };
@@ -915,13 +918,16 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
   uint32_t reason = 0, kdone = A.nsteps;
   uint64_t tot_last = 0, tot_prev = 0;  // keys of the last two passes' outputs
+  uint64_t mx_ref = 0;  // largest key range right after the split (circuit-aligned ranges)
   static_assert(kPersistTableBytes / 16 == kPBlock, "one table word per thread");
   // table offsets of the current pass, loaded one pass ahead; the table of pass k is the one of
   // step s + 1 (step0 on the first pass, step s itself on the last, which spawns nothing)
   auto tab_index = [&](int32_t kk) -> uint32_t {
     return kk + 1 == (int32_t)A.nsteps ? (uint32_t)kk : (uint32_t)(kk + 1);
   };
-  uint32_t offA = A.tab_off[tab_index(-1)];
+  // this workgroup's circuit (its key range lies within one circuit)
+  const uint32_t circ = A.kl.replica(S.split[p]) / A.rep_per;
+  uint32_t offA = A.tab_off[tab_index(-1) * A.n_circuits + circ];
   uint32_t offB = A.tabB_off && A.nsteps > 0 ? A.tabB_off[0] : 0u;
   uint64_t np_next = 0;  // keys this workgroup wrote in the previous pass
   for (int32_t k = -1; k < (int32_t)A.nsteps; ++k) {
@@ -947,7 +953,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     S.tab[t] = reinterpret_cast<const uint4*>(A.tab_base + offA)[t];
     if (two) S.tabB[t] = reinterpret_cast<const uint4*>(A.tab_base + offB)[t];
     if (k + 1 < (int32_t)A.nsteps) {
-      offA = A.tab_off[tab_index(k + 1)];
+      offA = A.tab_off[tab_index(k + 1) * A.n_circuits + circ];
       if (A.tabB_off && k + 2 < (int32_t)A.nsteps) offB = A.tabB_off[k + 2];
     }
     // inbox of this step -> LDS, sorted (empty on the first pass: zeroed before the launch)
@@ -1014,7 +1020,9 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       kdone = first ? 0u : (uint32_t)k;  // refined by the host from err_step
       break;
     }
-    if (!first && !last && mx > tot / P + tot / (4 * P) + A.rebal_min) {
+    if (first) mx_ref = mx;
+    const uint64_t ref = tot / P > mx_ref ? tot / P : mx_ref;
+    if (!first && !last && mx > ref + ref / 4 + A.rebal_min) {
       reason = 1;
       kdone = (uint32_t)k + 1;
       break;
@@ -1037,13 +1045,54 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   }
 }
 
-// Splitters: split[0] = 0, split[p] = key at index p*n/P of the canonical store.
+// Splitters, aligned to circuits (a key range then needs one circuit's table): the first
+// workgroup of circuit c starts at its lowest composite key (c * rep_per) << kbits, circuit c gets
+// 1 + floor((P - C) * n_c / n) workgroups (the rest to the largest circuit) and its other splits
+// sit at even positions of its keys.  One circuit: split[p] = the key at index p * n / P.
+// One workgroup of kPBlock threads.
 __global__ void k_splitters(const uint64_t* __restrict__ ck, const Counters* __restrict__ cnt,
-                            uint32_t cur, uint32_t P, uint64_t* __restrict__ split) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
+                            uint32_t cur, uint32_t P, uint32_t C, uint32_t rep_per,
+                            uint32_t kbits, uint64_t* __restrict__ split) {
+  __shared__ uint64_t s_off[kMaxCircuits + 1];
+  __shared__ uint32_t s_first[kMaxCircuits + 1];
+  const uint32_t t = threadIdx.x;
   const uint64_t n = cnt->n_store[cur];
-  split[p] = (p == 0 || n == 0) ? 0ull : ck[((uint64_t)p * n) / P];
+  auto base_key = [&](uint32_t c) -> uint64_t {
+    return kbits >= 64 ? 0ull : ((uint64_t)c * rep_per) << kbits;
+  };
+  for (uint32_t c = t; c <= C; c += blockDim.x)
+    s_off[c] = c == C ? n : (c == 0 ? 0 : lower_bound_glb(ck, n, base_key(c)));
+  __syncthreads();
+  if (t == 0) {
+    uint32_t used = 0, big = 0;
+    uint64_t bign = 0;
+    for (uint32_t c = 0; c < C; ++c) {
+      const uint64_t nc = s_off[c + 1] - s_off[c];
+      s_first[c] = used;
+      used += 1 + (n ? (uint32_t)(((uint64_t)(P - C) * nc) / n) : 0u);
+      if (c == 0 || nc > bign) {
+        big = c;
+        bign = nc;
+      }
+    }
+    const uint32_t extra = P - used;
+    for (uint32_t c = big + 1; c < C; ++c) s_first[c] += extra;
+    s_first[C] = P;
+  }
+  __syncthreads();
+  for (uint32_t p = t; p < P; p += blockDim.x) {
+    uint32_t lo = 0, hi = C;  // the circuit c with s_first[c] <= p < s_first[c + 1]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_first[mid] <= p)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t c = lo, j = p - s_first[c], a = s_first[c + 1] - s_first[c];
+    const uint64_t nc = s_off[c + 1] - s_off[c];
+    split[p] = (j == 0 || nc == 0) ? base_key(c) : ck[s_off[c] + (j * nc) / a];
+  }
 }
 
 // Batch prologue: empty inboxes of the first step, error flags reset.
@@ -1095,6 +1144,8 @@ PersistArgs make_args(const PersistLaunch* L) {
   a.pv_prev = L->pv_prev;
   a.nbuf = L->nbuf;
   a.tabB_off = L->tabB_off;
+  a.n_circuits = L->n_circuits;
+  a.rep_per = L->rep_per;
   a.qshiftB = L->qshiftB;
   a.sk = L->sk;
   a.sv = L->sv;
@@ -1147,8 +1198,9 @@ int qmcp_max_segments(int* P) {
 int qmcp_prepare(hipStream_t st, const PersistLaunch* L) {
   hipLaunchKernelGGL(k_persist_prep, dim3(1), dim3(256), 0, st, (Counters*)L->counters, L->in_n,
                      L->P, L->done);
-  hipLaunchKernelGGL(k_splitters, dim3((L->P + 255) / 256), dim3(256), 0, st, L->ck,
-                     (const Counters*)L->counters, L->cur, L->P, L->split_w);
+  hipLaunchKernelGGL(k_splitters, dim3(1), dim3(kPBlock), 0, st, L->ck,
+                     (const Counters*)L->counters, L->cur, L->P, L->n_circuits, L->rep_per,
+                     L->kbits, L->split_w);
   return (int)hipGetLastError();
 }
 

@@ -203,6 +203,85 @@ def config_ghz20_nm():
                gamma_damp=0.002, deph_cos=(0.02, 0.5), name="ghz20_nm")
 
 
+@dataclass
+class BatchWorkload:
+    """Many circuits advanced together (one context, one step launch).  Every circuit is a
+    Workload on its own n_c <= n qubits; in the batch it lives on n qubits with the extra ones
+    idle (its masks and keys only touch its own qubits).  Replica r of circuit c is segment
+    c * n_replicas + r."""
+    name: str
+    n: int
+    n_replicas: int
+    seed: int
+    dt: float
+    nsteps: int
+    circuits: list
+
+    def weights(self, a, b):
+        """Weights of steps [a, b) of all circuits side by side (circuit order)."""
+        s = np.concatenate([w.s[a:b] for w in self.circuits], axis=1)
+        g = np.concatenate([w.gamma[a:b] for w in self.circuits], axis=1)
+        return s, g
+
+    def segments(self):
+        """[(start, stop, masks)]: runs of steps between pulse steps of any circuit; masks is
+        None or (xs, zs), the Pauli of every circuit before the run (0, 0 = none)."""
+        steps = set()
+        for w in self.circuits:
+            steps |= {k for k in w.pulses if 0 < k < self.nsteps}
+        cuts = sorted(steps | {0, self.nsteps})
+        out = []
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            xs = np.zeros(len(self.circuits), dtype=np.uint64)
+            zs = np.zeros(len(self.circuits), dtype=np.uint64)
+            any_p = False
+            for c, w in enumerate(self.circuits):
+                for (px, pz) in w.pulses.get(a, []):
+                    xs[c] ^= np.uint64(px)
+                    zs[c] ^= np.uint64(pz)
+                    any_p = True
+            out.append((a, b, (xs, zs) if any_p else None))
+        return out
+
+
+def batch(n_circuits=64, n_lo=6, n_hi=16, n_replicas=4, nsteps=1000, dt=0.005, seed=5,
+          w_lo=1e4, w_hi=1e6, rate_lo=0.001, rate_hi=0.02, name=None):
+    """Batched circuits of uneven size: n_c ~ U{n_lo..n_hi}, each a DD-crosstalk or a GHZ
+    circuit (as dd / ghz above) with rates ~ U[rate_lo, rate_hi] and a walker target
+    log-uniform in [w_lo, w_hi], drawn from numpy PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    circuits = []
+    units = int(math.ceil(nsteps * dt - 1e-9))
+    for c in range(n_circuits):
+        nc = int(rng.integers(n_lo, n_hi + 1))
+        kind = "dd" if rng.random() < 0.5 else "ghz"
+        g1, g2 = (float(x) for x in rng.uniform(rate_lo, rate_hi, size=2))
+        wt = int(round(math.exp(rng.uniform(math.log(w_lo), math.log(w_hi)))))
+        if kind == "dd":
+            w = dd(n=nc, n_replicas=n_replicas, walker_target=wt, dt=dt, nsteps=nsteps,
+                   seed=seed, gamma_deph=g1, gamma_damp=g2, disorder_seed=seed * 1000 + c)
+        else:
+            w = ghz(n=nc, n_replicas=n_replicas, walker_target=wt, dt=dt,
+                    n_gates=max(1, min(nc, units)), seed=seed, gamma_deph=g1, gamma_damp=g2)
+            w = w.truncated(nsteps) if w.nsteps > nsteps else w
+            if w.nsteps < nsteps:  # idle after the last gate, the noise going on
+                extra = nsteps - w.nsteps
+                w.s = np.concatenate([w.s, np.zeros((extra, w.n_h))])
+                w.gamma = np.concatenate([w.gamma, np.repeat(w.gamma[-1:], extra, axis=0)])
+                w.nsteps = nsteps
+        w.name = f"{kind}_n{nc}_c{c}"
+        circuits.append(w)
+    n = max(w.n for w in circuits)
+    return BatchWorkload(name=name or f"batch{n_circuits}", n=n, n_replicas=n_replicas,
+                         seed=seed, dt=dt, nsteps=nsteps, circuits=circuits)
+
+
+def config_batch64():
+    """64 circuits, n ~ U{6..16}, DD or GHZ, rates U[0.001, 0.02], walker targets log-uniform
+    in 1e4..1e6, 4 replicas each, dt = 0.005, 1000 steps (the batched configuration)."""
+    return batch(name="batch64")
+
+
 CONFIGS = {"ghz4": config_ghz4, "dd12": config_dd12, "ghz20_nm": config_ghz20_nm}
 
 

@@ -25,8 +25,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {"fused": "k_persist", "sort": "k_onesweep", "merge": "k_merge"}
 # the dominant kernel of each workload on the automatic path (with the initiator approximation
 # the dd12 store stays small enough for the fused kernel throughout)
-DOMINANT = {"ghz20_nm": "fused", "dd12": "merge", "ghz4": "fused"}
-DOMINANT_INITIATOR = {"ghz20_nm": "fused", "dd12": "fused", "ghz4": "fused"}
+DOMINANT = {"ghz20_nm": "fused", "dd12": "merge", "ghz4": "fused", "batch64": "merge"}
+DOMINANT_INITIATOR = {"ghz20_nm": "fused", "dd12": "fused", "ghz4": "fused", "batch64": "fused"}
 KERNEL_SOURCES = ["paper_2502_18929_amd/csrc/qmc_persist.hip",
                   "paper_2502_18929_amd/csrc/qmc_kernels.hip",
                   "paper_2502_18929_amd/csrc/qmc_device.hpp"]
@@ -102,7 +102,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the whole trajectory of the workload)")
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="ghz20_nm", choices=["ghz20_nm", "dd12", "ghz4"])
+    ap.add_argument("--workload", default="ghz20_nm",
+                    choices=["ghz20_nm", "dd12", "ghz4", "batch64"])
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "streamed"])
     ap.add_argument("--integrator", default="euler", choices=["euler", "ab2"],
                     help="time integrator (End Matter on simulation methodology)")
@@ -128,6 +129,8 @@ def main():
     import torch
     from paper_2502_18929_amd import binding, workloads as W
 
+    if args.workload == "batch64":
+        return main_batch(args, kind)
     w = W.CONFIGS[args.workload]()
     K = w.nsteps if args.steps is None else min(args.steps, w.nsteps)
     Wm = min(args.warmup, w.nsteps)
@@ -212,6 +215,101 @@ def main():
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w, args.integrator, init_min)
+    g.close()
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline_batch(bw, budget_s=20.0):
+    """The CPU oracle, circuit by circuit (each with its replicas' stream ids), over the first
+    steps of the batch, about budget_s seconds; walker-steps/s over all circuits."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    R = bw.n_replicas
+    orcs = []
+    for c, w in enumerate(bw.circuits):
+        o = oracle.Oracle(bw.n, R, bw.seed, bw.dt, w.h, w.lops, w.init_keys, w.init_re,
+                          w.init_im)
+        o.set_replica_base(c * R)
+        orcs.append(o)
+    t0 = time.perf_counter()
+    done, used = 0, 1
+    for a, b, masks in bw.segments():
+        for lo in range(a, b, 20):
+            if time.perf_counter() - t0 >= budget_s:
+                break
+            hi = min(lo + 20, b)
+            if lo == a and masks is not None:
+                for c, o in enumerate(orcs):
+                    if masks[0][c] or masks[1][c]:
+                        o.pulse(int(masks[0][c]), int(masks[1][c]))
+            for o, w in zip(orcs, bw.circuits):
+                used = max(used, o.step(w.s[lo:hi], w.gamma[lo:hi], threads=threads))
+            done = hi
+    dt = time.perf_counter() - t0
+    ws = sum(o.counters()["walker_steps"] for o in orcs)
+    ks = sum(o.counters()["key_steps"] for o in orcs)
+    return {"value": ws / dt, "unit": "walker-steps/s", "cores": used, "kind": "oracle",
+            "sample": f"steps 0..{done} of {bw.nsteps} of {bw.name} (all {len(orcs)} circuits x "
+                      f"{R} replicas), {dt:.1f} s, OpenMP across each circuit's replicas",
+            "key_steps_per_s": ks / dt}
+
+
+def main_batch(args, kind):
+    """The batched configuration: 64 circuits of uneven size in one context and one step."""
+    import torch
+    from paper_2502_18929_amd import binding, workloads as W
+    bw = W.config_batch64()
+    K = bw.nsteps if args.steps is None else min(args.steps, bw.nsteps)
+    Wm = min(args.warmup, bw.nsteps)
+    torch.cuda.set_device(0)
+    circuits = [(w.h, w.lops, w.init_keys, w.init_re, w.init_im) for w in bw.circuits]
+    g = binding.QMC.batch(bw.n, bw.n_replicas, bw.seed, bw.dt, circuits,
+                          store_capacity=1 << 18, spawn_capacity=1 << 18)
+    g.set_path(args.path)
+    init = [g.export(r) for r in range(g.R)]
+    g.run_batch_workload(bw, 0, Wm)
+    for r in range(g.R):
+        g.import_(r, *init[r], step=0)
+    torch.cuda.synchronize()
+    st0 = g.counters()
+    g.profile(kind)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run_batch_workload(bw, 0, K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = g.counters()
+    prof_ms, prof_n, cov = g.profile_read()
+    g.profile(None)
+    elapsed = t1 - t0
+    walker_steps = st1["walker_steps"] - st0["walker_steps"]
+    abytes = algorithmic_bytes(kind, cov)
+    per_launch = abytes / prof_n if prof_n else None
+    avg_ms = prof_ms / prof_n if prof_n else None
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
+    obs = g.observe()
+    res = {
+        "metric": "walker-steps/sec on 1 GPU (batched circuits)",
+        "value": walker_steps / elapsed, "unit": "walker-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"{bw.name}: {len(bw.circuits)} circuits, n = "
+                               f"{min(w.n for w in bw.circuits)}..{max(w.n for w in bw.circuits)}"
+                               f" (DD or GHZ), {bw.n_replicas} replicas each, walker targets "
+                               f"1e4..1e6, dt={bw.dt}, {bw.nsteps} steps",
+                   "circuits": len(bw.circuits), "replicas": bw.n_replicas, "dt": bw.dt,
+                   "steps_timed": K, "step_path": args.path,
+                   "parallelism": "1 GPU, all circuits and replicas in one store"},
+        "key_steps_per_s": (st1["key_steps"] - st0["key_steps"]) / elapsed,
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[kind], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(kind, bw.name), "avg_launch_ms": avg_ms,
+                     "launches": prof_n, "steps_covered": cov["steps"],
+                     "algorithmic_bytes_per_launch": per_launch},
+        "final": {"n_occ_total": st1["n_occ"], "trace_mean": float(obs["trace"].mean())},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_batch(bw)
     g.close()
     print(json.dumps(res), flush=True)
 

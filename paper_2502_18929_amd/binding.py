@@ -261,6 +261,18 @@ class QMC:
             for (px, pz) in w.pulses.get(w.nsteps, []):
                 self.pulse(px, pz)
 
+    def run_batch_workload(self, bw, start=0, stop=None):
+        """Advance a batch context through steps [start, stop) of a BatchWorkload, applying the
+        circuits' pulses."""
+        stop = bw.nsteps if stop is None else stop
+        for a, b, masks in bw.segments():
+            if b <= start or a >= stop:
+                continue
+            if a >= start and masks is not None:
+                self.pulse_batch(*masks)
+            lo, hi = max(a, start), min(b, stop)
+            self.step(*bw.weights(lo, hi))
+
     def pulse(self, x, z):
         self._check(lib().qmc_pulse(self._ctx, int(x), int(z)))
 

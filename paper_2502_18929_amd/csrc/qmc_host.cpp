@@ -1356,23 +1356,31 @@ int qmc_export(qmc_ctx* c, uint32_t replica, uint64_t* keys, int32_t* re, int32_
                uint64_t cap, uint64_t* n) {
   if (!c || replica >= c->R || !n) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
-  std::vector<uint64_t> ck;
-  std::vector<int2> cv;
-  int rc = download_store(c, ck, cv);
-  if (rc) return rc;
+  // the replica's index range, found on the device, then only its records come over
   const uint64_t lo = c->kbits >= 64 ? 0 : (uint64_t)replica << c->kbits;
   const uint64_t hi = c->kbits >= 64 ? ~0ull : (((uint64_t)replica + 1) << c->kbits) - 1;
-  auto b = std::lower_bound(ck.begin(), ck.end(), lo);
-  auto e = std::upper_bound(ck.begin(), ck.end(), hi);
-  const uint64_t m = (uint64_t)(e - b);
+  uint64_t* dr = c->at<uint64_t>(c->L.look_out);  // scratch: two words
+  HIPCHK(c, qmck_key_range(c->stream, c->sk(c->cur), &c->counters()->n_store[c->cur], lo, hi,
+                           dr));
+  uint64_t* pr = reinterpret_cast<uint64_t*>(c->pinned_small);
+  HIPCHK(c, hipMemcpyAsync(pr, dr, 16, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const uint64_t b = pr[0], m = pr[1] - pr[0];
   *n = m;
   if (m > cap) return fail(c, QMC_ERR_ARG, "export capacity too small");
+  if (m == 0) return QMC_OK;
+  std::vector<uint64_t> ck(m);
+  std::vector<int2> cv(m);
+  HIPCHK(c, hipMemcpyAsync(ck.data(), c->sk(c->cur) + b, m * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(cv.data(), c->sv(c->cur) + b, m * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   const uint64_t kmask = c->kbits >= 64 ? ~0ull : ((1ull << c->kbits) - 1);
-  const size_t off = (size_t)(b - ck.begin());
   for (uint64_t i = 0; i < m; ++i) {
-    keys[i] = ck[off + i] & kmask;
-    re[i] = cv[off + i].x;
-    im[i] = cv[off + i].y;
+    keys[i] = ck[i] & kmask;
+    re[i] = cv[i].x;
+    im[i] = cv[i].y;
   }
   return QMC_OK;
 }

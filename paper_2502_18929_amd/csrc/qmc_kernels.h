@@ -33,6 +33,9 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
                uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
                uint32_t* ghist_next, uint32_t passes);
+// out[0..1] (device) = the index range of the sorted keys[0, *count) within [lo, hi].
+int qmck_key_range(hipStream_t st, const uint64_t* keys, const uint64_t* count, uint64_t lo,
+                   uint64_t hi, uint64_t* out);
 // Ideal Pauli pulse: circuit c of the store (rep_per replicas each) takes X^x Z^z with
 // (x, z) = (pxz[2c], pxz[2c+1]) (device); with any_x the records go to (ck, cv) for a re-sort.
 int qmck_pulse(hipStream_t st, uint64_t* pk, int2* pv, void* counters, uint32_t cur, uint32_t n,

@@ -893,6 +893,32 @@ __global__ __launch_bounds__(kBlock) void k_pulse(uint64_t* __restrict__ pk, int
   if (any_x && blockIdx.x == 0 && threadIdx.x == 0) cnt->n_child[csel] = np;
 }
 
+// [out[0], out[1]) = the records of the sorted keys[0, *count) with lo <= key <= hi (one
+// thread: two binary searches).
+__global__ void k_key_range(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ count,
+                            uint64_t lo, uint64_t hi, uint64_t* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const uint64_t n = *count;
+  uint64_t a = 0, b = n;
+  while (a < b) {
+    const uint64_t m = a + (b - a) / 2;
+    if (keys[m] < lo)
+      a = m + 1;
+    else
+      b = m;
+  }
+  uint64_t c = a, d = n;
+  while (c < d) {
+    const uint64_t m = c + (d - c) / 2;
+    if (keys[m] <= hi)
+      c = m + 1;
+    else
+      d = m;
+  }
+  out[0] = a;
+  out[1] = c;
+}
+
 __global__ __launch_bounds__(kBlock) void k_copy_store(const uint64_t* __restrict__ ki,
                                                        const int2* __restrict__ vi,
                                                        uint64_t* __restrict__ ko,
@@ -1135,6 +1161,12 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   const uint32_t g = max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
                                                         : (uint32_t)kMergeBlocks;
   hipLaunchKernelGGL(k_merge, dim3(g), dim3(kBlock), 0, st, a);
+  return (int)hipGetLastError();
+}
+
+int qmck_key_range(hipStream_t st, const uint64_t* keys, const uint64_t* count, uint64_t lo,
+                   uint64_t hi, uint64_t* out) {
+  hipLaunchKernelGGL(k_key_range, dim3(1), dim3(64), 0, st, keys, count, lo, hi, out);
   return (int)hipGetLastError();
 }
 

@@ -231,7 +231,9 @@ int qmc_import(qmc_ctx* ctx, uint32_t replica, const uint64_t* keys, const int32
 /* Counters of a context: the step counter, the occupied keys of all replicas now, and running
  * sums since qmc_init over the parents of every step of N^tot (walker_steps), occupied keys
  * (key_steps), child records (child_steps) and annihilated output keys (out_steps).  The sums
- * give the walker-steps/s and key-steps/s rates and the algorithmic bytes of the kernels. */
+ * give the walker-steps/s and key-steps/s rates and the algorithmic bytes of the kernels.
+ * `rebalances` counts the times the fused kernel re-cut its key ranges to even out a grown
+ * population, inside one launch or by stopping for a new one (no effect on the results). */
 typedef struct {
   uint32_t step;
   uint64_t n_occ_total;
@@ -239,6 +241,7 @@ typedef struct {
   uint64_t key_steps;
   uint64_t child_steps;
   uint64_t out_steps;
+  uint64_t rebalances;
 } qmc_stats;
 
 int qmc_counters(qmc_ctx* ctx, qmc_stats* out);

@@ -45,7 +45,8 @@ class Config(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_uint32), ("n_occ_total", ctypes.c_uint64),
                 ("walker_steps", ctypes.c_uint64), ("key_steps", ctypes.c_uint64),
-                ("child_steps", ctypes.c_uint64), ("out_steps", ctypes.c_uint64)]
+                ("child_steps", ctypes.c_uint64), ("out_steps", ctypes.c_uint64),
+                ("rebalances", ctypes.c_uint64)]
 
 
 class Model(ctypes.Structure):
@@ -346,7 +347,8 @@ class QMC:
         st = Stats()
         self._check(lib().qmc_counters(self._ctx, ctypes.byref(st)))
         return dict(step=st.step, n_occ=st.n_occ_total, walker_steps=st.walker_steps,
-                    key_steps=st.key_steps, child_steps=st.child_steps, out_steps=st.out_steps)
+                    key_steps=st.key_steps, child_steps=st.child_steps, out_steps=st.out_steps,
+                    rebalances=st.rebalances)
 
     def set_integrator(self, integrator):
         """Time integrator: 'euler' (default) or 'ab2' (clears N(s-1))."""

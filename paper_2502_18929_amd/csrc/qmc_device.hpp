@@ -78,7 +78,7 @@ struct Counters {
   uint32_t err;
   uint32_t err_step;
   uint32_t tile_counter;   // merge tile ticket
-  uint32_t pad;
+  uint32_t resplits;       // key ranges re-cut inside the fused kernel (running sum)
   uint32_t sort_ticket[2][kMaxPasses + 2];  // onesweep tile tickets per step parity and pass
 };
 

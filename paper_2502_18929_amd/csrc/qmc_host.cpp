@@ -162,6 +162,7 @@ struct qmc_ctx {
   std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
   double prof_ms = 0.0;
   uint64_t prof_launches = 0;
+  uint64_t relaunches = 0;  // fused launches that stopped to re-cut the key ranges
   qmc_stats prof_cover{};            // counter deltas of the steps run by the timed class
   qmc::Counters last_hc{};           // counters at the last device read
 
@@ -657,10 +658,12 @@ void add_cover(qmc_ctx* c, const qmc::Counters& a, const qmc::Counters& b, uint3
   c->prof_cover.key_steps += b.key_steps - a.key_steps;
   c->prof_cover.child_steps += b.child_steps - a.child_steps;
   c->prof_cover.out_steps += b.out_steps - a.out_steps;
+  c->prof_cover.rebalances += b.resplits - a.resplits;
 }
 
 constexpr uint64_t kFusedKeysPerSegment = 8192;  // automatic mode: larger stores run streamed
 constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a fused overflow
+constexpr uint32_t kKernelResplits = 64;          // re-splits the fused kernel does by itself
 
 // One chunk of steps [step, step + nst): device tables at dtab (+ offsA / offsB), and whether
 // the chunk integrates with AB2 from a known N(s-1) (`two`; the tables B exist).
@@ -711,8 +714,10 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.qshift = c->at<int64_t>(c->L.qshift);
   pl.qshiftB = c->at<int64_t>(c->L.qshift) + c->R;
   pl.slots = c->at<uint64_t>(c->L.slots);
+  pl.max_rebal = c->integrator == 0 && c->C == 1 ? kKernelResplits : 0u;
   pl.epoch0 = c->epoch + 1;
-  c->epoch += (uint64_t)nst + 1;  // barriers of this launch: batch start + one per step
+  // barriers of this launch: batch start, one per step, two per re-split
+  c->epoch += (uint64_t)nst + 1 + 2ull * pl.max_rebal;
   pl.cap_store = c->L.cap_store;
   pl.cap_inbox = c->L.cap_child;
   pl.rebal_min = 64;
@@ -740,6 +745,10 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   }
   kd = pin_done[0];
   reason = pin_done[1];
+  if (reason == 1) {
+    c->relaunches += 1;
+    if (prof) c->prof_cover.rebalances += 1;
+  }
   bool sized = true;  // the kernel wrote the sizes of the stores gathered below
   if (reason == 2 || hc.err) {
     sized = false;
@@ -1511,6 +1520,7 @@ int qmc_counters(qmc_ctx* c, qmc_stats* out) {
   out->key_steps = hc.key_steps;
   out->child_steps = hc.child_steps;
   out->out_steps = hc.out_steps;
+  out->rebalances = hc.resplits + c->relaunches;
   return QMC_OK;
 }
 

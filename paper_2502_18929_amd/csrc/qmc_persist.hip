@@ -28,9 +28,12 @@ constexpr int kActCap = kPBlock + kWave;   // block list of active new parents
 constexpr int kStage = 256;                // per-wave staging of routed records
 
 struct PersistArgs {
-  // canonical store: sorted records of all replicas (read by the first pass)
+  // canonical store: sorted records of all replicas (read by the first pass; a re-split in
+  // the kernel writes it through ckw / cvw, the same arrays)
   const uint64_t* ck;
   const int2* cv;
+  uint64_t* ckw;
+  int2* cvw;
   Counters* cnt;
   uint32_t cur;
   // AB2: N(step0 - 1), sorted (its records draw the second term of step0), or null
@@ -68,6 +71,7 @@ struct PersistArgs {
                           // error bits, each tagged with the epoch
   uint64_t cap_store;     // total occupied keys allowed
   uint64_t cap_inbox;     // total inbox records allowed per step
+  uint32_t max_rebal;     // re-splits the kernel may do itself (one circuit, Euler), then it stops
   uint32_t rebal_min;     // stop to rebalance when the largest range exceeds 1.25 x the larger
                           // of the mean and the launch's first largest range, + this
   uint64_t epoch0;        // first barrier epoch of this launch (epochs only grow)
@@ -91,6 +95,7 @@ struct Shared {
   uint64_t red[kPWaves];
   uint64_t xch[kPWaves][4];
   uint64_t dec[4];        // reduced totals of the last barrier: keys, max segment, inbox, errors
+  uint32_t nouts[kMaxSegments];  // keys out of every workgroup at the last barrier
   uint4 tab[kPersistTableBytes / 16];   // the step table of the spawns drawn in this pass
   uint4 tabB[kPersistTableBytes / 16];  // AB2: the table of their second term
   uint32_t err;           // error bits this workgroup raised in the current step
@@ -181,6 +186,7 @@ __device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint6
       }
     }
     v0 &= 0xFFFFFFFFull;
+    S.nouts[q] = (uint32_t)v0;
     tot += v0;
     mx = v0 > mx ? v0 : mx;
     nn += v1 & 0xFFFFFFFFull;
@@ -754,7 +760,7 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
                                               const int2* pv, uint64_t np, uint32_t c, uint64_t* ok,
                                               int2* ov, uint32_t step, bool spawn, bool spawnB,
                                               Router R, const LTable tn, const LTable tnB,
-                                              uint32_t nstep) {
+                                              uint32_t nstep, bool coherent = false) {
   const uint32_t t = threadIdx.x;
   uint64_t out_run = 0;   // block-uniform
   uint64_t wsum = 0;
@@ -764,8 +770,9 @@ __device__ __forceinline__ void merge_segment(const PersistArgs& A, Shared& S, c
     const uint64_t f = tt * kPTile;
     const uint32_t pn = np > f ? (uint32_t)((np - f) < (uint64_t)kPTile ? (np - f) : kPTile) : 0u;
     for (uint32_t i = t; i < pn; i += kPBlock) {
-      S.pa_k[i] = pk[f + i];
-      const int2 v = pv[f + i];
+      // parents written by other workgroups in this launch (a re-split store) bypass the caches
+      S.pa_k[i] = coherent ? ld_agent(&pk[f + i]) : pk[f + i];
+      const int2 v = coherent ? ld_agent(&pv[f + i]) : pv[f + i];
       S.pa_v[i] = v;
       wsum += uabs64(v.x) + uabs64(v.y);
     }
@@ -919,6 +926,8 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   uint32_t reason = 0, kdone = A.nsteps;
   uint64_t tot_last = 0, tot_prev = 0;  // keys of the last two passes' outputs
   uint64_t mx_ref = 0;  // largest key range right after the split (circuit-aligned ranges)
+  const uint32_t rebal_max = A.nbuf == 2 && A.n_circuits == 1 ? A.max_rebal : 0u;
+  uint32_t rebal_left = rebal_max;
   static_assert(kPersistTableBytes / 16 == kPBlock, "one table word per thread");
   // table offsets of the current pass, loaded one pass ahead; the table of pass k is the one of
   // step s + 1 (step0 on the first pass, step s itself on the last, which spawns nothing)
@@ -1023,9 +1032,69 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     if (first) mx_ref = mx;
     const uint64_t ref = tot / P > mx_ref ? tot / P : mx_ref;
     if (!first && !last && mx > ref + ref / 4 + A.rebal_min) {
-      reason = 1;
-      kdone = (uint32_t)k + 1;
-      break;
+      if (rebal_left == 0) {
+        reason = 1;
+        kdone = (uint32_t)k + 1;
+        break;
+      }
+      // Re-split in the kernel (one circuit, Euler): N(s+1) of every range goes to the
+      // canonical store at its prefix, the records already routed for step s+1 are dropped,
+      // the ranges are re-cut at even positions, and step s+1 is drawn again from the new
+      // slices into the same segment buffer and inbox parity; pass k + 1 then runs as usual.
+      // The draws are keyed on the walkers, so the records are the same; only their owners
+      // change.
+      --rebal_left;
+      {
+        uint32_t mine = t < p ? S.nouts[t] : 0u;
+        for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+        if (__lane_id() == 0) S.scan[t / kWave] = mine;
+        __syncthreads();
+        uint64_t prefix = 0;
+        for (int w = 0; w < kPWaves; ++w) prefix += S.scan[w];
+        const uint64_t* sk_o = A.sk + ((uint64_t)ob * P + p) * A.segcap;
+        const int2* sv_o = A.sv + ((uint64_t)ob * P + p) * A.segcap;
+        for (uint64_t i = t; i < nout; i += kPBlock) {
+          st_agent(&A.ckw[prefix + i], sk_o[i]);
+          st_agent(&A.cvw[prefix + i], sv_o[i]);
+        }
+        if (t == 0) st_agent(&A.in_n[(par ^ 1u) * P + p], 0u);
+      }
+      ++epoch;
+      if (!grid_sync(S, A, epoch, 0, 0)) {
+        reason = 2;
+        kdone = (uint32_t)k + 1;
+        break;
+      }
+      for (uint32_t q = t; q < P; q += kPBlock)
+        S.split[q] = q == 0 ? 0ull : ld_agent(&A.ckw[((uint64_t)q * tot) / P]);
+      __syncthreads();
+      const uint64_t rb = p == 0 ? 0 : ((uint64_t)p * tot) / P;
+      const uint64_t re = p + 1 < P ? ((uint64_t)(p + 1) * tot) / P : tot;
+      {
+        uint64_t* okp = A.sk + ((uint64_t)ob * P + p) * A.segcap;
+        int2* ovp = A.sv + ((uint64_t)ob * P + p) * A.segcap;
+        const LTable tn = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab));
+        Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, s + 1, &S.err,
+                 A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u};
+        merge_segment(A, S, A.ckw + rb, A.cvw + rb, re - rb, 0, okp, ovp, s + 1, true, false, R,
+                      tn, tn, s + 1, true);
+      }
+      const uint64_t nout2 = S.red[0];
+      np_next = nout2 <= A.segcap ? nout2 : 0;
+      if (t == 0) A.seg_n[ob * P + p] = (uint32_t)np_next;
+      ++epoch;
+      if (!grid_sync(S, A, epoch, nout2, 0)) {
+        reason = 2;
+        kdone = (uint32_t)k + 1;
+        break;
+      }
+      if (S.dec[3]) {
+        reason = 2;
+        kdone = (uint32_t)k + 1;
+        break;
+      }
+      mx_ref = S.dec[1];
+      tot_last = S.dec[0];
     }
   }
   if (t == 0) {
@@ -1036,6 +1105,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     if (p == 0) {
       A.done[0] = kdone;
       A.done[1] = reason;
+      atomicAdd(&cnt->resplits, rebal_max - rebal_left);
       if (reason != 2 && kdone > 0) {
         // sizes of the stores the host gathers: N(step0 + kdone), and N(step0 + kdone - 1)
         cnt->n_store[A.cur] = tot_last;
@@ -1138,6 +1208,8 @@ PersistArgs make_args(const PersistLaunch* L) {
   PersistArgs a;
   a.ck = L->ck;
   a.cv = L->cv;
+  a.ckw = L->ck;
+  a.cvw = L->cv;
   a.cnt = (Counters*)L->counters;
   a.cur = L->cur;
   a.pk_prev = L->pk_prev;
@@ -1171,6 +1243,7 @@ PersistArgs make_args(const PersistLaunch* L) {
   a.cap_store = L->cap_store;
   a.cap_inbox = L->cap_inbox;
   a.rebal_min = L->rebal_min;
+  a.max_rebal = L->max_rebal;
   a.done = L->done;
   return a;
 }

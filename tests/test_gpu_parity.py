@@ -166,6 +166,10 @@ def test_ghz20_nm_full_size(B, orc, path):
         o.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250], threads=16)
         _assert_same(g, o, w.n_replicas, f"step {k0 + 250}")
         _say(f"  step {k0 + 250} equal ({time.time() - t0:.1f}s)")
+    # the growing population made the fused kernel re-cut its key ranges (inside its launches)
+    reb = g.counters()["rebalances"]
+    _say(f"  key-range re-cuts: {reb}")
+    assert (reb > 0) == (path == "auto")
 
 
 @pytest.mark.parametrize("path", PATHS)

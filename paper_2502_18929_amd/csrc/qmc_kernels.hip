@@ -597,6 +597,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __syncthreads();
   };
 
+  // bounds of the next step's table for the segment of the last output seen (outputs are
+  // sorted by segment, so they change rarely)
+  uint32_t h_seg = ~0u;
+  uint64_t h_qoff = 0, h_qdiag = 0;
   while (true) {
     if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->tile_counter, 1u);
     __syncthreads();
@@ -756,12 +760,16 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           ck = s_pk[p];
           v = s_pv[p];
           const uint32_t rep = kl.replica(ck);
+          if (rep != h_seg) {
+            const TableHeader* h =
+                reinterpret_cast<const TableHeader*>(A.tab_next.of_segment(rep));
+            h_qoff = h->n_groups > 1 ? h->q_off : 0;
+            h_qdiag = h->q_diag + uabs64(A.qshift[rep]);
+            h_seg = rep;
+          }
           walker_random(kl.key(ck), A.step + 1, rep, A.seed, 0u, w);
           const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-          const TableView tn = table_view(A.tab_next.of_segment(rep));
-          const uint64_t q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
-          act = !comb_all_zero(sab, q_off, w[0]) ||
-                !comb_all_zero(sab, tn.h->q_diag + uabs64(A.qshift[rep]), w[1]);
+          act = !comb_all_zero(sab, h_qoff, w[0]) || !comb_all_zero(sab, h_qdiag, w[1]);
         }
         const uint64_t m = __ballot(act);
         if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);

@@ -78,6 +78,12 @@ def lib():
         L.orc_set_shift.argtypes = [ctypes.c_void_p, u32, dbl]
         L.orc_set_initiator.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.orc_set_replica_base.argtypes = [ctypes.c_void_p, u32]
+        i8p = P(ctypes.c_int8)
+        L.orc_set_proposal.argtypes = [ctypes.c_void_p, u32, u32, i8p, P(ctypes.c_int32), i8p,
+                                       P(ctypes.c_int32), u32]
+        L.orc_mlp_scores.argtypes = [ctypes.c_void_p, u64, P(ctypes.c_int32)]
+        L.orc_proposal_thresholds.argtypes = [u32, P(u64), P(u64)]
+        L.orc_proposal_draw.argtypes = [u32, P(i64), P(u64), u32, u32, u32, P(u32), P(i64)]
         L.orc_counters.argtypes = [ctypes.c_void_p, P(u64), P(u64), P(u64), P(u64)]
         L.orc_counters.restype = None
         L.orc_get_step.argtypes = [ctypes.c_void_p]
@@ -95,6 +101,30 @@ def lib():
                                   P(u64), P(u64), P(i64), P(i64), P(i64), P(u64)]
         _lib = L
     return _lib
+
+
+MLP_IN, MLP_HIDDEN, MLP_OUT = 64, 32, 64
+
+
+def proposal_thresholds(W):
+    """Thresholds P (sum 2^32, each >= 1) from the nonnegative integer weights W (reading R18)."""
+    W = np.ascontiguousarray(W, dtype=np.uint64)
+    P = np.zeros(len(W), dtype=np.uint64)
+    _check(lib().orc_proposal_thresholds(len(W), _p(W, ctypes.c_uint64), _p(P, ctypes.c_uint64)),
+           "proposal_thresholds")
+    return P
+
+
+def proposal_draw(x, P, K, u, j):
+    """One proposal draw (reading R18): (channel, signed walkers) for uniforms u (32 bits) and
+    j < K."""
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    P = np.ascontiguousarray(P, dtype=np.uint64)
+    ch, n = ctypes.c_uint32(), ctypes.c_int64()
+    _check(lib().orc_proposal_draw(len(x), _p(x, ctypes.c_int64), _p(P, ctypes.c_uint64), int(K),
+                                   int(u), int(j), ctypes.byref(ch), ctypes.byref(n)),
+           "proposal_draw")
+    return int(ch.value), int(n.value)
 
 
 def philox4x32_10(ctr, key):
@@ -257,6 +287,35 @@ class Oracle:
         """Initiator approximation (End Matter on simulation methodology, reading R17): parents
         with |re| + |im| < min_walkers spawn only onto keys occupied in N(s); 0 = off."""
         _check(lib().orc_set_initiator(self._ctx, int(min_walkers)), "set_initiator")
+
+    def set_integrator(self, integrator):
+        """'euler' or 'ab2' (clears N(s-1))."""
+        _check(lib().orc_set_integrator(self._ctx, {"euler": 0, "ab2": 1}[integrator]),
+               "integrator")
+
+    def set_proposal(self, kind, k=1, mlp=None):
+        """Spawn proposal (reading R18): kind 'comb' (default), 'uniform', 'heatbath' or 'mlp'
+        with k samples per parent; mlp = (w1 int8 [32, 64], b1 int32 [32], w2 int8 [64, 32],
+        b2 int32 [64], s1)."""
+        kinds = {"comb": 0, "uniform": 1, "heatbath": 2, "mlp": 3}
+        kd = kinds[kind]
+        args = [None, None, None, None, 0]
+        if kd == 3:
+            w1, b1, w2, b2, s1 = mlp
+            self._mlp = (np.ascontiguousarray(w1, dtype=np.int8),
+                         np.ascontiguousarray(b1, dtype=np.int32),
+                         np.ascontiguousarray(w2, dtype=np.int8),
+                         np.ascontiguousarray(b2, dtype=np.int32))
+            assert self._mlp[0].shape == (MLP_HIDDEN, MLP_IN)
+            assert self._mlp[2].shape == (MLP_OUT, MLP_HIDDEN)
+            args = [_p(self._mlp[0], ctypes.c_int8), _p(self._mlp[1], ctypes.c_int32),
+                    _p(self._mlp[2], ctypes.c_int8), _p(self._mlp[3], ctypes.c_int32), int(s1)]
+        _check(lib().orc_set_proposal(self._ctx, kd, int(k) if kd else 0, *args), "set_proposal")
+
+    def mlp_scores(self, key):
+        out = np.zeros(MLP_OUT, dtype=np.int32)
+        _check(lib().orc_mlp_scores(self._ctx, int(key), _p(out, ctypes.c_int32)), "mlp_scores")
+        return out
 
     def counters(self):
         w, k, ch, mx = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

@@ -29,6 +29,19 @@
  *      being advanced, before annihilation; the rule covers the second AB2 term too (parents
  *      from N(s-1), targets checked against N(s)); death on the parent's own key in N(s) is
  *      never discarded.  Threshold 0 = off.
+ *  R18 Spawn proposals (the End Matter's multinomial over the (target, Re/Im) channels of a
+ *      column, with importance weights so that any proposal keeps the stated expectation):
+ *      instead of the comb over every channel, a parent draws K (a power of two) channels
+ *      ch = (group g >= 1, Re or Im) with probabilities P_ch / 2^32 and puts
+ *      round(x_ch / (K P_ch)) walkers on each, x_ch being the channel's Q32 amount (the same
+ *      integer the comb rounds).  The rounding is exact: the offset of the uniform inside its
+ *      channel interval is uniform on [0, P_ch), and with K sub-draws it gives a uniform on
+ *      [0, K P_ch).  The thresholds P_ch come from nonnegative integer weights W_ch: a floor
+ *      F = floor(2^32 / (16 nch)) each, the rest shared in proportion to W_ch (all W = 0 counts
+ *      as all W = 1), the rounding remainder to the last channel.  Weights: uniform (1 each),
+ *      heat-bath (|x_ch|, scaled below 2^24: the paper's |L|-proportional choice for this
+ *      parent) or the scores of a small int8 MLP of the key bits (one score per group, both
+ *      components).  Death keeps its comb.  Euler only, no initiator; 0 = the plain comb.
  *
  * Floating point: the only FP64 arithmetic is the coefficient quantization, done in a fixed
  * operation order (compile with -ffp-contract=off).  Everything the walkers touch is integer.
@@ -129,6 +142,14 @@ struct orc_ctx {
   /* Philox stream id of replica r is replica_base + r: a context that holds one circuit of a
    * batch draws what the batch draws for that circuit's replicas. */
   uint32_t replica_base;
+  /* Spawn proposal (reading R18): kind 0 = the comb, 1 uniform, 2 heat-bath, 3 MLP scores;
+   * prop_k samples per parent; the MLP's int8 weights, int32 biases and hidden shift. */
+  uint32_t prop_kind, prop_k;
+  int8_t mlp_w1[ORC_MLP_HIDDEN][ORC_MLP_IN];
+  int32_t mlp_b1[ORC_MLP_HIDDEN];
+  int8_t mlp_w2[ORC_MLP_OUT][ORC_MLP_HIDDEN];
+  int32_t mlp_b2[ORC_MLP_OUT];
+  uint32_t mlp_s1;
 };
 
 /* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
@@ -525,6 +546,117 @@ static int occupied(const store_t* st, uint64_t key) {
   return lo < st->n && st->key[lo] == key;
 }
 
+/* ---- spawn proposals (reading R18) ---------------------------------------------------------- */
+
+/* Scores of the groups 1..ORC_MLP_OUT for one key: input b is +1 where bit b of the key is set,
+ * -1 where it is clear (b < 2n), 0 past 2n; hidden h_j = min(127, max(0, a_j) >> s1) with
+ * a_j = sum_b w1[j][b] in_b + b1[j]; score_g = sum_j w2[g][j] h_j + b2[g] (int32, exact). */
+static void mlp_scores(const orc_ctx* c, uint64_t key, int32_t* score) {
+  int32_t h[ORC_MLP_HIDDEN];
+  for (int j = 0; j < ORC_MLP_HIDDEN; ++j) {
+    int32_t a = c->mlp_b1[j];
+    for (uint32_t b = 0; b < 2 * c->n && b < ORC_MLP_IN; ++b)
+      a += ((key >> b) & 1u) ? c->mlp_w1[j][b] : -(int32_t)c->mlp_w1[j][b];
+    int32_t v = a > 0 ? (a >> c->mlp_s1) : 0;
+    h[j] = v > 127 ? 127 : v;
+  }
+  for (int g = 0; g < ORC_MLP_OUT; ++g) {
+    int32_t o = c->mlp_b2[g];
+    for (int j = 0; j < ORC_MLP_HIDDEN; ++j) o += (int32_t)c->mlp_w2[g][j] * h[j];
+    score[g] = o;
+  }
+}
+
+int orc_mlp_scores(const orc_ctx* c, uint64_t key, int32_t* score) {
+  if (!c || !score) return ORC_ERR_ARG;
+  mlp_scores(c, key, score);
+  return ORC_OK;
+}
+
+/* Thresholds P[0..nch) (sum exactly 2^32, each >= 1) from weights W (each < 2^32). */
+int orc_proposal_thresholds(uint32_t nch, const uint64_t* W, uint64_t* P) {
+  if (nch == 0 || nch > 2 * 255 || !W || !P) return ORC_ERR_ARG;
+  const uint64_t T = 1ull << 32;
+  const uint64_t F = T / (16ull * nch), M = T - (uint64_t)nch * F;
+  uint64_t S = 0;
+  for (uint32_t i = 0; i < nch; ++i) {
+    if (W[i] >= T) return ORC_ERR_ARG;
+    S += W[i];
+  }
+  uint64_t used = 0;
+  for (uint32_t i = 0; i + 1 < nch; ++i) {
+    const uint64_t w = S ? W[i] : 1, tot = S ? S : nch;
+    P[i] = F + (w * M) / tot;
+    used += P[i];
+  }
+  P[nch - 1] = T - used;
+  return ORC_OK;
+}
+
+/* One proposal draw: the channel whose interval [C_ch, C_ch + P_ch) holds u, o = u - C_ch, and
+ * n = floor(|x| / (K P)) + [j P + o < |x| mod (K P)] with the sign of x_ch; j < K. */
+int orc_proposal_draw(uint32_t nch, const int64_t* x, const uint64_t* P, uint32_t K, uint32_t u,
+                      uint32_t j, uint32_t* ch_out, int64_t* n_out) {
+  if (nch == 0 || !x || !P || K == 0 || (K & (K - 1)) || j >= K) return ORC_ERR_ARG;
+  uint64_t C = 0;
+  uint32_t ch = 0;
+  while (ch + 1 < nch && (uint64_t)u >= C + P[ch]) C += P[ch++];
+  const uint64_t o = (uint64_t)u - C, D = (uint64_t)K * P[ch], U = (uint64_t)j * P[ch] + o;
+  const uint64_t a = x[ch] < 0 ? (uint64_t)(-x[ch]) : (uint64_t)x[ch];
+  const uint64_t m = a / D + (U < a % D ? 1u : 0u);
+  *ch_out = ch;
+  *n_out = x[ch] < 0 ? -(int64_t)m : (int64_t)m;
+  return ORC_OK;
+}
+
+static uint32_t bitlen64(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzll(v) : 0u; }
+
+/* The proposal records of one parent (key, a + ib): xs[2(g-1) + comp] are its channel amounts. */
+static int proposal_records(const orc_ctx* c, uint32_t r, const table_t* T, uint64_t key,
+                            const int64_t* xs, uint64_t* W, uint64_t* P, rec_t* rec,
+                            uint64_t* nr) {
+  const uint32_t G = T->n_groups, nch = 2 * (G - 1);
+  if (c->prop_kind == 1) {
+    for (uint32_t i = 0; i < nch; ++i) W[i] = 1;
+  } else if (c->prop_kind == 2) {
+    uint64_t mx = 0;
+    for (uint32_t i = 0; i < nch; ++i) {
+      const uint64_t a = xs[i] < 0 ? (uint64_t)(-xs[i]) : (uint64_t)xs[i];
+      if (a > mx) mx = a;
+    }
+    const uint32_t sh = bitlen64(mx) > 24 ? bitlen64(mx) - 24 : 0;
+    for (uint32_t i = 0; i < nch; ++i)
+      W[i] = (xs[i] < 0 ? (uint64_t)(-xs[i]) : (uint64_t)xs[i]) >> sh;
+  } else {
+    int32_t score[ORC_MLP_OUT];
+    mlp_scores(c, key, score);
+    for (uint32_t g = 1; g < G; ++g) {
+      const int32_t v = g - 1 < ORC_MLP_OUT ? score[g - 1] : 0;
+      const uint64_t w = v <= 0 ? 0 : (v > (1 << 24) ? (1u << 24) : (uint64_t)v);
+      W[2 * (g - 1)] = W[2 * (g - 1) + 1] = w;
+    }
+  }
+  int rc = orc_proposal_thresholds(nch, W, P);
+  if (rc) return rc;
+  const uint32_t pkey[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+  for (uint32_t k = 0; k < c->prop_k; ++k) {
+    /* sample k: Philox stream 0x40 + k of this walker and step */
+    const uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), c->step,
+                             ((c->replica_base + r) << 8) | (0x40u + k)};
+    uint32_t q[4];
+    orc_philox4x32_10(ctr, pkey, q);
+    uint32_t ch;
+    int64_t m;
+    orc_proposal_draw(nch, xs, P, c->prop_k, q[0], q[1] & (c->prop_k - 1), &ch, &m);
+    if (m > INT32_MAX || m < -(int64_t)INT32_MAX) return ORC_ERR_COUNT_OVERFLOW;
+    if (m != 0) {
+      const uint32_t g = 1 + ch / 2;
+      rec[(*nr)++] = (rec_t){key ^ T->gx[g], (ch & 1) ? 0 : m, (ch & 1) ? m : 0};
+    }
+  }
+  return ORC_OK;
+}
+
 /* `occ` is N(s), the vector being advanced: with the initiator approximation a record from a
  * non-initiator parent survives only on a key occupied there. */
 static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const table_t* T,
@@ -533,11 +665,14 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
   const uint32_t G = T->n_groups;
   int64_t* xs = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
   int64_t* ns = (int64_t*)malloc(2 * (size_t)(G ? G : 1) * sizeof(int64_t));
-  if (!xs || !ns) {
+  uint64_t* pw = (uint64_t*)malloc(4 * (size_t)(G ? G : 1) * sizeof(uint64_t));
+  if (!xs || !ns || !pw) {
     free(xs);
     free(ns);
+    free(pw);
     return ORC_ERR_NOMEM;
   }
+  int rc = ORC_OK;
   const uint32_t pkey[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
   for (uint64_t p = 0; p < in->n; ++p) {
     const uint64_t key = in->key[p];
@@ -567,6 +702,11 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
       xs[2 * (g - 1)] = a * cre - b * cim;
       xs[2 * (g - 1) + 1] = a * cim + b * cre;
     }
+    if (c->prop_kind != 0) {
+      if (G > 1) rc = proposal_records(c, r, T, key, xs, pw, pw + 2 * G, rec, nr);
+      if (rc) break;
+      continue;
+    }
     if (G > 1) orc_comb(2 * (G - 1), xs, w[0], ns);
     for (uint32_t g = 1; g < G; ++g) {
       int64_t cr = ns[2 * (g - 1)], ci = ns[2 * (g - 1) + 1];
@@ -577,7 +717,8 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
   }
   free(xs);
   free(ns);
-  return ORC_OK;
+  free(pw);
+  return rc;
 }
 
 /* N(s+1) of replica r.  Euler (End Matter on simulation methodology):
@@ -591,7 +732,8 @@ static int step_replica(const orc_ctx* c, uint32_t r, const table_t* A, int64_t 
                         const table_t* B, int64_t qb, store_t* out, uint64_t* nchild) {
   const store_t* in = &c->st[r];
   const store_t* pv = B ? &c->prev[r] : NULL;
-  uint64_t cap = in->n * (uint64_t)A->n_groups + 1;
+  uint64_t per = A->n_groups > c->prop_k + 1 ? A->n_groups : c->prop_k + 1;
+  uint64_t cap = in->n * per + 1;
   if (B) cap += pv->n * (uint64_t)B->n_groups;
   rec_t* rec = (rec_t*)malloc(cap * sizeof(rec_t));
   if (!rec) return ORC_ERR_NOMEM;
@@ -751,6 +893,7 @@ int orc_step_threads(orc_ctx* c, uint32_t nsteps, const double* s, const double*
  * next step is an Euler step unless orc_set_prev supplies N(s-1) and the weights of step s-1. */
 int orc_set_integrator(orc_ctx* c, int ab2) {
   if (ab2 != 0 && ab2 != 1) return ORC_ERR_ARG;
+  if (ab2 && c->prop_kind) return ORC_ERR_ARG;
   c->ab2 = ab2;
   c->have_prev = 0;
   for (uint32_t r = 0; r < c->R; ++r) store_free(&c->prev[r]);
@@ -832,7 +975,25 @@ int orc_set_replica_base(orc_ctx* c, uint32_t base) {
 }
 
 int orc_set_initiator(orc_ctx* c, uint64_t min_walkers) {
+  if (min_walkers && c->prop_kind) return ORC_ERR_ARG;
   c->init_min = min_walkers;
+  return ORC_OK;
+}
+
+int orc_set_proposal(orc_ctx* c, uint32_t kind, uint32_t k, const int8_t* w1, const int32_t* b1,
+                     const int8_t* w2, const int32_t* b2, uint32_t s1) {
+  if (kind > 3) return ORC_ERR_ARG;
+  if (kind && (k == 0 || k > 64 || (k & (k - 1)) || c->ab2 || c->init_min)) return ORC_ERR_ARG;
+  if (kind == 3 && (!w1 || !b1 || !w2 || !b2 || s1 > 30)) return ORC_ERR_ARG;
+  c->prop_kind = kind;
+  c->prop_k = kind ? k : 0;
+  if (kind == 3) {
+    memcpy(c->mlp_w1, w1, sizeof(c->mlp_w1));
+    memcpy(c->mlp_b1, b1, sizeof(c->mlp_b1));
+    memcpy(c->mlp_w2, w2, sizeof(c->mlp_w2));
+    memcpy(c->mlp_b2, b2, sizeof(c->mlp_b2));
+    c->mlp_s1 = s1;
+  }
   return ORC_OK;
 }
 

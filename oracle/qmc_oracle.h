@@ -30,6 +30,11 @@ typedef struct { uint64_t x, z; double re, im; } orc_monomial;
 
 typedef struct orc_ctx orc_ctx;
 
+/* Spawn-proposal MLP sizes (reading R18): key-bit inputs, hidden units, group scores. */
+#define ORC_MLP_IN 64
+#define ORC_MLP_HIDDEN 32
+#define ORC_MLP_OUT 64
+
 enum {
   ORC_OK = 0,
   ORC_ERR_ARG = -1,
@@ -103,6 +108,18 @@ int orc_set_initiator(orc_ctx* c, uint64_t min_walkers);
  * ((base + r) << 8) | stream): a context holding one circuit of a batch of circuits uses the ids
  * the batch gives that circuit's replicas.  Default 0. */
 int orc_set_replica_base(orc_ctx* c, uint32_t base);
+/* Spawn proposal (reading R18): kind 0 = the comb (default), 1 uniform, 2 heat-bath, 3 MLP
+ * scores; k samples per parent (a power of two, <= 64); the MLP (kind 3) has int8 weights
+ * w1[ORC_MLP_HIDDEN][ORC_MLP_IN], int32 b1[ORC_MLP_HIDDEN], int8 w2[ORC_MLP_OUT][ORC_MLP_HIDDEN],
+ * int32 b2[ORC_MLP_OUT] and hidden shift s1 (copied).  Euler without initiators only. */
+int orc_set_proposal(orc_ctx* c, uint32_t kind, uint32_t k, const int8_t* w1, const int32_t* b1,
+                     const int8_t* w2, const int32_t* b2, uint32_t s1);
+/* The MLP scores of groups 1..ORC_MLP_OUT for one key (the context's weights). */
+int orc_mlp_scores(const orc_ctx* c, uint64_t key, int32_t* score);
+/* Proposal thresholds (sum 2^32, each >= 1) from nch weights, and one draw from them. */
+int orc_proposal_thresholds(uint32_t nch, const uint64_t* W, uint64_t* P);
+int orc_proposal_draw(uint32_t nch, const int64_t* x, const uint64_t* P, uint32_t K, uint32_t u,
+                      uint32_t j, uint32_t* ch, int64_t* n);
 
 uint32_t orc_get_step(const orc_ctx* c);
 /* Sums over all steps so far and all replicas of the parents' N^tot, of their occupied keys and

@@ -305,6 +305,16 @@ def random_model(n, rng, n_h=4, n_l=2, max_l_terms=2):
     return h, lops
 
 
+def random_mlp(rng, hidden_shift=5, scale=40):
+    """Seeded weights of the spawn-proposal MLP (shapes of the C ABI: w1 int8 [32, 64], b1 int32
+    [32], w2 int8 [64, 32], b2 int32 [64], hidden shift): random inputs, not trained ones."""
+    w1 = rng.integers(-scale, scale + 1, size=(32, 64)).astype(np.int8)
+    b1 = rng.integers(-200, 800, size=32).astype(np.int32)
+    w2 = rng.integers(-scale, scale + 1, size=(64, 32)).astype(np.int8)
+    b2 = rng.integers(-2000, 4000, size=64).astype(np.int32)
+    return w1, b1, w2, b2, int(hidden_shift)
+
+
 def random_records(n, rng, count, scale=50):
     """Sorted unique keys over 2n bits with nonzero Gaussian-integer populations."""
     K = 1 << (2 * n)

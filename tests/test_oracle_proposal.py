@@ -1,0 +1,208 @@
+"""Pins of the oracle's spawn proposals (reading R18: the End Matter's multinomial over the
+(target, Re/Im) channels of a column, with importance weights).
+
+What fixes them independently of the oracle: the partition property of the thresholds, the
+channel lookup as numpy's searchsorted, the exact conditional expectation of the rounding by
+enumerating every (offset, sub-draw) pair of small channel intervals, the MLP as numpy integer
+matrix products, the diagonal-only special case (no channel, so the plain step), and the
+unbiasedness identity E[N(s+1)] = (I + dt L_q) N(s) as a z-test over many replicas.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2502_18929_amd import workloads as W
+
+KINDS = ["uniform", "heatbath", "mlp"]
+
+
+# ---- thresholds ------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(8))
+def test_thresholds_partition_the_unit_interval(orc, seed):
+    rng = np.random.default_rng(900 + seed)
+    nch = int(rng.integers(1, 510))
+    kind = seed % 4
+    if kind == 0:
+        Wt = rng.integers(0, 1 << 24, size=nch)
+    elif kind == 1:
+        Wt = np.zeros(nch, dtype=np.int64)            # all zero: uniform
+    elif kind == 2:
+        Wt = np.where(rng.random(nch) < 0.9, 0, rng.integers(1, 1 << 31, size=nch))
+    else:
+        Wt = np.full(nch, (1 << 32) - 1, dtype=np.int64)
+    P = orc.proposal_thresholds(Wt).astype(object)
+    assert sum(P) == 1 << 32
+    F = (1 << 32) // (16 * nch)
+    assert all(p >= F >= 1 for p in P)
+    # larger weight, larger threshold (the last channel takes the remainder on top)
+    order = np.argsort(Wt[:-1], kind="stable")
+    Pm = [P[i] for i in order]
+    assert all(a <= b for a, b in zip(Pm, Pm[1:]))
+    if kind == 1:
+        assert len(set(P[:-1])) <= 1
+
+
+def test_thresholds_refuse_bad_input(orc):
+    with pytest.raises(orc.OracleError):
+        orc.proposal_thresholds([])
+    with pytest.raises(orc.OracleError):
+        orc.proposal_thresholds([1 << 32, 1])
+
+
+# ---- one draw --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_draw_channel_is_the_searchsorted_interval(orc, seed):
+    rng = np.random.default_rng(910 + seed)
+    nch = int(rng.integers(2, 60))
+    P = orc.proposal_thresholds(rng.integers(0, 1 << 20, size=nch))
+    cum = np.cumsum(P.astype(np.uint64))
+    x = rng.integers(-(1 << 40), 1 << 40, size=nch)
+    for u in list(rng.integers(0, 1 << 32, size=300)) + [0, (1 << 32) - 1] + list(cum[:-1]):
+        ch, _ = orc.proposal_draw(x, P, 1, int(u), 0)
+        assert ch == int(np.searchsorted(cum, np.uint64(u), side="right"))
+
+
+@pytest.mark.parametrize("K", [1, 2, 8])
+@pytest.mark.parametrize("x", [0, 1, 6, 7, -13, 123456789012, -(1 << 61) - 5])
+def test_draw_conditional_expectation_is_exact(orc, K, x):
+    """Small channel intervals enumerated whole: the sum of the draws over every offset o and
+    sub-draw j of a channel equals x (so E[n | channel] = x / (K P) exactly)."""
+    P = np.array([3, 5, 1, (1 << 32) - 9], dtype=np.uint64)
+    xs = np.array([x, -x, 2 * x + 1, 0], dtype=np.int64)
+    start = 0
+    for ch_want in range(3):
+        tot = 0
+        for o in range(int(P[ch_want])):
+            for j in range(K):
+                ch, n = orc.proposal_draw(xs, P, K, start + o, j)
+                assert ch == ch_want
+                assert n == 0 or (n > 0) == (xs[ch] > 0)
+                tot += n
+        assert Fraction(tot) == Fraction(int(xs[ch_want]))
+        start += int(P[ch_want])
+
+
+def test_draw_refuses_bad_sub_draws(orc):
+    P = orc.proposal_thresholds([1, 1])
+    with pytest.raises(orc.OracleError):
+        orc.proposal_draw([1, 1], P, 3, 0, 0)      # K not a power of two
+    with pytest.raises(orc.OracleError):
+        orc.proposal_draw([1, 1], P, 4, 0, 4)      # j >= K
+
+
+# ---- the MLP ---------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 5, 12, 20, 32])
+def test_mlp_scores_are_the_integer_network(orc, n):
+    rng = np.random.default_rng(930 + n)
+    h, lops = W.random_model(min(n, 3), rng)
+    keys, re, im = W.random_records(min(n, 3), rng, 3)
+    o = orc.Oracle(n, 1, 1, 0.01, [], [], keys, re, im)
+    w1, b1, w2, b2, s1 = W.random_mlp(rng)
+    o.set_proposal("mlp", 1, (w1, b1, w2, b2, s1))
+    for _ in range(20):
+        key = int(rng.integers(0, 1 << min(2 * n, 63)))
+        bits = np.array([((key >> b) & 1) if b < 2 * n else 0 for b in range(64)], dtype=np.int64)
+        x = np.where(np.arange(64) < 2 * n, 2 * bits - 1, 0)
+        a = w1.astype(np.int64) @ x + b1
+        hid = np.minimum(np.where(a > 0, a, 0) >> s1, 127)
+        want = w2.astype(np.int64) @ hid + b2
+        assert np.array_equal(o.mlp_scores(key), want)
+
+
+# ---- the step --------------------------------------------------------------------------------
+
+def _store(o, r):
+    k, a, b = o.export(r)
+    return k.tolist(), a.tolist(), b.tolist()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_diagonal_only_model_is_the_plain_step(orc, kind):
+    """Pure dephasing has no off-diagonal channel: a proposal changes nothing."""
+    rng = np.random.default_rng(940)
+    n = 2
+    lops = [[(0, 1 << q, 1.0 + 0j)] for q in range(n)]
+    keys, re, im = W.random_records(n, rng, 10, scale=500)
+    gam = np.full((3, n), 0.7)
+    a = orc.Oracle(n, 3, 5, 0.05, [], lops, keys, re, im)
+    b = orc.Oracle(n, 3, 5, 0.05, [], lops, keys, re, im)
+    b.set_proposal(kind, 4, W.random_mlp(rng) if kind == "mlp" else None)
+    a.step(np.zeros((3, 0)), gam)
+    b.step(np.zeros((3, 0)), gam)
+    for r in range(3):
+        assert _store(a, r) == _store(b, r)
+
+
+def test_proposal_refuses_ab2_and_initiators(orc):
+    rng = np.random.default_rng(941)
+    h, lops = W.random_model(2, rng)
+    keys, re, im = W.random_records(2, rng, 4)
+    o = orc.Oracle(2, 1, 1, 0.01, h, lops, keys, re, im)
+    with pytest.raises(orc.OracleError):
+        o.set_proposal("uniform", 3)
+    o.set_proposal("uniform", 2)
+    with pytest.raises(orc.OracleError):
+        o.set_integrator("ab2")
+    with pytest.raises(orc.OracleError):
+        o.set_initiator(5)
+    o.set_proposal("comb")
+    o.set_initiator(5)
+    with pytest.raises(orc.OracleError):
+        o.set_proposal("heatbath", 1)
+
+
+def _q_matrix(o, n, s, gamma):
+    D2 = 1 << (2 * n)
+    M = np.zeros((D2, D2), dtype=object)
+    for key in range(D2):
+        tk, v = o.column_q(s, gamma, key)
+        for t, (a, b) in zip(tk, v):
+            M[int(t), key] = (int(a), int(b))
+    return M
+
+
+@pytest.mark.parametrize("kind,K", [("uniform", 1), ("uniform", 4), ("heatbath", 2),
+                                    ("mlp", 1), ("mlp", 8)])
+def test_one_step_unbiased(orc, kind, K):
+    """Mean of many one-step samples (replicas draw independent streams) vs the exact
+    (I + dt L_q) N: every component within 5 standard errors."""
+    rng = np.random.default_rng(950)
+    n = 2
+    h, lops = W.random_model(n, rng, n_h=4, n_l=2)
+    s = rng.normal(size=len(h))
+    gamma = np.abs(rng.normal(size=len(lops)))
+    dt = 0.05
+    keys, re, im = W.random_records(n, rng, 6, scale=40)
+    R = 6000
+    o = orc.Oracle(n, R, 777, dt, h, lops, keys, re, im)
+    o.set_proposal(kind, K, W.random_mlp(rng) if kind == "mlp" else None)
+    o.step(s[None, :], gamma[None, :])
+    D2 = 1 << (2 * n)
+    samples = np.zeros((R, D2), dtype=complex)
+    for r in range(R):
+        k, a, b = o.export(r)
+        samples[r, k.astype(np.int64)] = a + 1j * b
+    Q = _q_matrix(o, n, s, gamma)
+    N0 = np.zeros(D2, dtype=complex)
+    N0[keys.astype(np.int64)] = re + 1j * im
+    expect = N0.copy()
+    for key in range(D2):
+        if N0[key] == 0:
+            continue
+        a, b = int(N0[key].real), int(N0[key].imag)
+        for t in range(D2):
+            if Q[t, key] != 0:
+                cr, ci = Q[t, key]
+                expect[t] += complex(a * cr - b * ci, a * ci + b * cr) / 2.0 ** 32
+    mean = samples.mean(axis=0)
+    for part in (np.real, np.imag):
+        sd = part(samples).std(axis=0, ddof=1)
+        diff = part(mean) - part(expect)
+        z = np.where(sd > 0, diff / np.maximum(sd, 1e-300) * math.sqrt(R), 0.0)
+        assert np.all(np.abs(z) < 5.0), z
+        assert np.all(np.abs(diff[sd == 0]) < 1e-9)

@@ -39,8 +39,9 @@
  *      [0, K P_ch).  The thresholds P_ch come from nonnegative integer weights W_ch: a floor
  *      F = floor(2^32 / (16 nch)) each, the rest shared in proportion to W_ch (all W = 0 counts
  *      as all W = 1), the rounding remainder to the last channel.  Weights: uniform (1 each),
- *      heat-bath (|x_ch|, scaled below 2^24: the paper's |L|-proportional choice for this
- *      parent) or the scores of a small int8 MLP of the key bits (one score per group, both
+ *      heat-bath (|x_ch| >> sh, sh = max(0, bitlen(|a| + |b|) + bitlen(q_off) - 24) with q_off
+ *      the sum of the off-diagonal |q| of the table, so W < 2^24: the paper's |L|-proportional
+ *      choice for this parent) or the scores of a small int8 MLP of the key bits (one score per group, both
  *      components).  Death keeps its comb.  Euler only, no initiator; 0 = the plain comb.
  *
  * Floating point: the only FP64 arithmetic is the coefficient quantization, done in a fixed
@@ -613,18 +614,18 @@ static uint32_t bitlen64(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzl
 
 /* The proposal records of one parent (key, a + ib): xs[2(g-1) + comp] are its channel amounts. */
 static int proposal_records(const orc_ctx* c, uint32_t r, const table_t* T, uint64_t key,
-                            const int64_t* xs, uint64_t* W, uint64_t* P, rec_t* rec,
-                            uint64_t* nr) {
+                            uint64_t sab, const int64_t* xs, uint64_t* W, uint64_t* P,
+                            rec_t* rec, uint64_t* nr) {
   const uint32_t G = T->n_groups, nch = 2 * (G - 1);
   if (c->prop_kind == 1) {
     for (uint32_t i = 0; i < nch; ++i) W[i] = 1;
   } else if (c->prop_kind == 2) {
-    uint64_t mx = 0;
-    for (uint32_t i = 0; i < nch; ++i) {
-      const uint64_t a = xs[i] < 0 ? (uint64_t)(-xs[i]) : (uint64_t)xs[i];
-      if (a > mx) mx = a;
-    }
-    const uint32_t sh = bitlen64(mx) > 24 ? bitlen64(mx) - 24 : 0;
+    /* |x_ch| <= sab * q_off < 2^(bitlen(sab) + bitlen(q_off)): shifted below 2^24 */
+    uint64_t q_off = 0;
+    for (uint32_t i = T->gs[1]; i < T->gs[G]; ++i)
+      q_off += (uint64_t)llabs(T->t[i].qre) + (uint64_t)llabs(T->t[i].qim);
+    const uint32_t bl = bitlen64(sab) + bitlen64(q_off);
+    const uint32_t sh = bl > 24 ? bl - 24 : 0;
     for (uint32_t i = 0; i < nch; ++i)
       W[i] = (xs[i] < 0 ? (uint64_t)(-xs[i]) : (uint64_t)xs[i]) >> sh;
   } else {
@@ -703,7 +704,9 @@ static int add_records(const orc_ctx* c, uint32_t r, const store_t* in, const ta
       xs[2 * (g - 1) + 1] = a * cim + b * cre;
     }
     if (c->prop_kind != 0) {
-      if (G > 1) rc = proposal_records(c, r, T, key, xs, pw, pw + 2 * G, rec, nr);
+      if (G > 1)
+        rc = proposal_records(c, r, T, key, (uint64_t)(llabs(a) + llabs(b)), xs, pw, pw + 2 * G,
+                              rec, nr);
       if (rc) break;
       continue;
     }

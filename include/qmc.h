@@ -184,6 +184,27 @@ int qmc_set_shift(qmc_ctx* ctx, uint32_t replica, double shift);
  * Errors: QMC_ERR_ARG when 2n + replica bits leave no bit for the flag (2n + bits > 63). */
 int qmc_set_initiator(qmc_ctx* ctx, uint64_t min_walkers);
 
+/* Spawn proposal (End Matter, spawn step: the multinomial over a column's (target, Re/Im)
+ * channels, with importance weights so the expectation stays dt L N).  kind 0 = the plain comb
+ * over every channel (default); otherwise each parent draws `samples` channels (a power of two,
+ * 1..64) with fixed-point probabilities P_ch / 2^32 and puts round(x_ch / (samples P_ch)) walkers
+ * on each, x_ch being the channel's Q32 amount, rounded exactly from the offset of the uniform
+ * inside the channel's interval.  P_ch: a floor of 2^32 / (16 nch) each, the rest in proportion to
+ * weights W_ch -- kind 1 uniform (W = 1), kind 2 heat-bath (|x_ch| scaled below 2^24), kind 3 the
+ * scores of an int8 MLP of the key bits: input b = +1 / -1 where bit b of the key (2n bits) is
+ * set / clear, 0 up to 64; hidden h_j = min(127, max(0, b1[j] + w1[j] . input) >> hidden_shift),
+ * 32 units; score_g = b2[g-1] + w2[g-1] . h for groups g = 1..64 (W = min(2^24, max(0, score))
+ * for both components, 0 past 64).  w1 int8 [32][64], b1 int32 [32], w2 int8 [64][32], b2 int32
+ * [64], row-major host arrays, copied (kind 3 only; NULL otherwise).  Death keeps its comb.
+ * Sample k of a parent draws Philox stream 0x40 + k.  Runs on the streamed path (the automatic
+ * path switches to it; a fused-only context refuses the step).  Errors: QMC_ERR_ARG for a bad
+ * kind, sample count or shift, with AB2, the initiator approximation or several circuits, and
+ * at qmc_step when samples x (column groups - 1) + 1 exceeds 256 for a step's table;
+ * QMC_ERR_COUNT_OVERFLOW when one drawn record exceeds the int32 range. */
+int qmc_set_proposal(qmc_ctx* ctx, int32_t kind, uint32_t samples, const int8_t* w1,
+                     const int32_t* b1, const int8_t* w2, const int32_t* b2,
+                     uint32_t hidden_shift);
+
 typedef struct {
   uint32_t n_pauli;          /* observables P = X^px Z^pz: sum_i (-1)^popc(pz&i) N_{i,i^px} */
   const uint64_t* px;

@@ -25,7 +25,8 @@ QMC_ERR_STATE = -8
 
 EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_set_integrator", "qmc_set_prev", "qmc_export_prev", "qmc_pulse",
-            "qmc_set_shift", "qmc_set_initiator", "qmc_observe", "qmc_export", "qmc_import", "qmc_counters",
+            "qmc_set_shift", "qmc_set_initiator", "qmc_set_proposal", "qmc_observe",
+            "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
             "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch"]
 
@@ -97,6 +98,8 @@ def lib():
                                      P(u64), vp, ctypes.c_size_t, vp, P(vp)]
         L.qmc_set_shift.argtypes = [vp, u32, dbl]
         L.qmc_set_initiator.argtypes = [vp, ctypes.c_uint64]
+        i8p = P(ctypes.c_int8)
+        L.qmc_set_proposal.argtypes = [vp, i32, u32, i8p, P(i32), i8p, P(i32), u32]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
         L.qmc_export.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.qmc_import.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, u32]
@@ -292,6 +295,27 @@ class QMC:
         """Initiator approximation: parents with |re| + |im| < min_walkers spawn only onto keys
         occupied in N(s); 0 = off.  initiator_threshold(xi, n_diag) gives ceil(xi * N^diag)."""
         self._check(lib().qmc_set_initiator(self._ctx, int(min_walkers)))
+
+    PROPOSALS = {"comb": 0, "uniform": 1, "heatbath": 2, "mlp": 3}
+
+    def set_proposal(self, kind, samples=1, mlp=None):
+        """Spawn proposal: 'comb' (the plain step), 'uniform', 'heatbath' or 'mlp' with `samples`
+        channel draws per parent; mlp = (w1 int8 [32, 64], b1 int32 [32], w2 int8 [64, 32],
+        b2 int32 [64], hidden_shift)."""
+        kd = self.PROPOSALS[kind]
+        if kd == 3:
+            w1, b1, w2, b2, s1 = mlp
+            arrs = [np.ascontiguousarray(w1, dtype=np.int8), np.ascontiguousarray(b1, dtype=np.int32),
+                    np.ascontiguousarray(w2, dtype=np.int8), np.ascontiguousarray(b2, dtype=np.int32)]
+            if arrs[0].shape != (32, 64) or arrs[1].shape != (32,) or arrs[2].shape != (64, 32) \
+                    or arrs[3].shape != (64,):
+                raise ValueError("MLP shapes: w1 [32, 64], b1 [32], w2 [64, 32], b2 [64]")
+            self._check(lib().qmc_set_proposal(
+                self._ctx, kd, int(samples), _ptr(arrs[0], ctypes.c_int8), _ptr(arrs[1], ctypes.c_int32),
+                _ptr(arrs[2], ctypes.c_int8), _ptr(arrs[3], ctypes.c_int32), int(s1)))
+        else:
+            self._check(lib().qmc_set_proposal(self._ctx, kd, int(samples) if kd else 0, None, None,
+                                               None, None, 0))
 
     def observe(self, pauli=(), psi=(), want_eps=False):
         R = self.R

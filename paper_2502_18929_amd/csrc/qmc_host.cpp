@@ -25,6 +25,11 @@ namespace {
 constexpr uint32_t kMaxPauli = 256;
 constexpr uint32_t kMaxLookup = 4096;
 constexpr size_t kTableArea = 32u << 20;  // device bytes for the step tables of one window
+// spawn-proposal MLP weights on the device: w1 int8 [hidden][in], b1 int32, w2 int8 [out][hidden],
+// b2 int32 (each part a multiple of 8 bytes, so the int8 rows stay 8-byte aligned)
+constexpr size_t kMlpW1 = (size_t)kPropHidden * kPropIn, kMlpB1 = (size_t)kPropHidden * 4,
+                 kMlpW2 = (size_t)kPropOut * kPropHidden, kMlpB2 = (size_t)kPropOut * 4;
+constexpr size_t kMlpBytes = kMlpW1 + kMlpB1 + kMlpW2 + kMlpB2;
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
@@ -49,7 +54,7 @@ struct QTerm {
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
-      tab_off, tabB_off, slots, done, pulse, total;
+      tab_off, tabB_off, slots, done, pulse, mlp, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -116,6 +121,7 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.slots = take((size_t)2 * P * 4 * 8);
   L.done = take(8);
   L.pulse = take((size_t)n_circuits * 16);
+  L.mlp = take(kMlpBytes);
   L.total = o;
   return true;
 }
@@ -155,6 +161,7 @@ struct qmc_ctx {
   int32_t path = 0;                 // 0 automatic, 1 fused persistent kernel only, 2 streamed only
   int32_t integrator = 0;           // 0 Euler, 1 AB2
   uint64_t init_min = 0;            // initiator threshold in walkers (0 = off)
+  QmcProposal prop{};               // spawn proposal (kind 0: the comb); weights on the device
   bool have_prev = false;           // AB2: N(s-1) (device) and w_prev are valid
   std::vector<double> w_prev;       // AB2: weights of step s-1 (s then gamma)
   uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
@@ -817,12 +824,12 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   const uint32_t* dB = c->at<uint32_t>(c->L.tabB_off) + ch.first;
   HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab, dA, c->Rc,
                        step0, c->cfg.seed, c->kbits, c->init_min, 0u, qshA, c->ck(cb), c->cv(cb),
-                       c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
+                       c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes, &c->prop));
   if (ch.two)
     HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab, dB, c->Rc,
                          step0, c->cfg.seed, c->kbits, c->init_min, 1u, qshB, c->ck(cb),
                          c->cv(cb),
-                         c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes));
+                         c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes, nullptr));
   HIPCHK(c, mark(0, 0, 1));
   for (uint32_t k = 0; k < nst; ++k) {
     const uint32_t st = step0 + k, b = k % nb, cur = cur0 ^ (k & 1u);
@@ -843,7 +850,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
                          bk[(k + 1) % nb],
                          bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
                          c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
-                         passes));
+                         passes, &c->prop));
     HIPCHK(c, mark(2, k, 1));
     cb = cf ^ 1;
   }
@@ -947,6 +954,13 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
         rc = QMC_ERR_ARG;
         why = "the two AB2 tables have more than 257 column groups between them";
       }
+    }
+    // A proposal puts up to k records of one parent on one key: every key's records from one
+    // table must stay within the merge's run bound.
+    if (!rc && c->prop.kind &&
+        (uint64_t)c->prop.k * (TA.gx.size() - 1) + 1 > (uint64_t)qmc::kMergeSlack) {
+      rc = QMC_ERR_ARG;
+      why = "proposal samples times column groups exceed the merge's run bound (256)";
     }
     if (!rc && TA.q_diag + max_qa >= (1ull << 31)) {
       rc = QMC_ERR_DT;
@@ -1071,12 +1085,14 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
   if (c->path == 1 && !fused_fits)
     return fail(c, QMC_ERR_ARG, "step table larger than the fused kernel takes; use the "
                                 "automatic or streamed path");
+  if (c->path == 1 && c->prop.kind)
+    return fail(c, QMC_ERR_ARG, "spawn proposals run on the streamed path");
   uint32_t last_local_fail = 0xFFFFFFFFu;
   int32_t shift_mode = -1;  // shifts on the device: 0 single Euler term, 1 both AB2 terms
   while (c->step < first_step + nsteps) {
     const uint32_t k0 = c->step - first_step;
     const bool two = ab2 && k0 >= euler_first;
-    const bool fused = c->path == 1 || (c->path == 0 && fused_fits &&
+    const bool fused = c->path == 1 || (c->path == 0 && fused_fits && !c->prop.kind &&
                                         c->step >= c->streamed_until &&
                                         c->n_occ <= fused_max_keys);
     if (shift_mode != (int32_t)two) {
@@ -1172,6 +1188,8 @@ int qmc_step_path(qmc_ctx* c, int32_t path) {
 int qmc_set_integrator(qmc_ctx* c, int32_t integrator) {
   if (!c || integrator < 0 || integrator > 1) return QMC_ERR_ARG;
   if (integrator == 1 && c->C > 1) return fail(c, QMC_ERR_ARG, "AB2 runs one circuit per context");
+  if (integrator == 1 && c->prop.kind)
+    return fail(c, QMC_ERR_ARG, "AB2 runs without spawn proposals");
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
   c->integrator = integrator;
   c->have_prev = false;
@@ -1225,9 +1243,49 @@ int qmc_pulse(qmc_ctx* c, uint64_t x, uint64_t z) {
   return qmc_pulse_batch(c, xs.data(), zs.data());
 }
 
+int qmc_set_proposal(qmc_ctx* c, int32_t kind, uint32_t samples, const int8_t* w1,
+                     const int32_t* b1, const int8_t* w2, const int32_t* b2,
+                     uint32_t hidden_shift) {
+  if (!c || kind < 0 || kind > 3) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (kind == 0) {
+    c->prop = QmcProposal{};
+    return QMC_OK;
+  }
+  if (samples == 0 || samples > 64 || (samples & (samples - 1)))
+    return fail(c, QMC_ERR_ARG, "proposal samples must be a power of two from 1 to 64");
+  if (c->integrator != 0 || c->init_min != 0 || c->C != 1)
+    return fail(c, QMC_ERR_ARG, "spawn proposals run with Euler, one circuit, no initiators");
+  if (2 * c->n > (uint32_t)kPropIn) return fail(c, QMC_ERR_ARG, "key wider than the MLP input");
+  QmcProposal p{};
+  p.kind = (uint32_t)kind;
+  p.k = samples;
+  p.nbits = 2 * c->n;
+  if (kind == 3) {
+    if (!w1 || !b1 || !w2 || !b2 || hidden_shift > 30)
+      return fail(c, QMC_ERR_ARG, "the MLP proposal needs its weights and a shift <= 30");
+    uint8_t* d = c->at<uint8_t>(c->L.mlp);
+    HIPCHK(c, hipMemcpyAsync(d, w1, kMlpW1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + kMlpW1, b1, kMlpB1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + kMlpW1 + kMlpB1, w2, kMlpW2, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + kMlpW1 + kMlpB1 + kMlpW2, b2, kMlpB2, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the caller's arrays may go away
+    p.s1 = hidden_shift;
+    p.w1 = reinterpret_cast<const int8_t*>(d);
+    p.b1 = reinterpret_cast<const int32_t*>(d + kMlpW1);
+    p.w2 = reinterpret_cast<const int8_t*>(d + kMlpW1 + kMlpB1);
+    p.b2 = reinterpret_cast<const int32_t*>(d + kMlpW1 + kMlpB1 + kMlpW2);
+  }
+  c->prop = p;
+  return QMC_OK;
+}
+
 int qmc_set_initiator(qmc_ctx* c, uint64_t min_walkers) {
   if (!c) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (min_walkers > 0 && c->prop.kind)
+    return fail(c, QMC_ERR_ARG, "the initiator approximation runs without spawn proposals");
   if (min_walkers > 0 && c->C > 1)
     return fail(c, QMC_ERR_ARG, "the initiator approximation runs one circuit per context");
   if (min_walkers > 0 && c->kbits + c->rbits + 1 > 64)

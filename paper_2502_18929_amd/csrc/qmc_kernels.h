@@ -4,6 +4,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Spawn proposal (End Matter, spawn step: the multinomial over a column's (target, Re/Im)
+// channels, importance weighted): kind 0 = the comb (no proposal), 1 uniform, 2 heat-bath, 3 the
+// int8 MLP scores of the key bits; k samples per parent (a power of two); MLP sizes
+// kPropIn x kPropHidden x kPropOut, weights in device memory (w1 [hidden][in], w2 [out][hidden]).
+constexpr int kPropIn = 64, kPropHidden = 32, kPropOut = 64;
+struct QmcProposal {
+  uint32_t kind;
+  uint32_t k;
+  uint32_t nbits;   // key bits fed to the MLP (2n)
+  uint32_t s1;      // hidden-layer shift
+  const int8_t* w1;
+  const int32_t* b1;
+  const int8_t* w2;
+  const int32_t* b2;
+};
+
 extern "C" {
 uint32_t qmck_sort_passes(uint32_t key_bits);
 int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t n_status,
@@ -19,7 +35,7 @@ int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counter
                uint32_t rep_per, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint32_t stream, const int64_t* qsh,
                uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
-               uint32_t passes);
+               uint32_t passes, const QmcProposal* prop);
 int qmck_digit_hist(hipStream_t st, const uint64_t* keys, void* counters, uint32_t nsel,
                     uint32_t passes, uint32_t* ghist, uint64_t max_items);
 int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
@@ -32,7 +48,7 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                const int64_t* qshiftB, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
                uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
-               uint32_t* ghist_next, uint32_t passes);
+               uint32_t* ghist_next, uint32_t passes, const QmcProposal* prop);
 // out[0..1] (device) = the index range of the sorted keys[0, *count) within [lo, hi].
 int qmck_key_range(hipStream_t st, const uint64_t* keys, const uint64_t* count, uint64_t lo,
                    uint64_t hi, uint64_t* out);

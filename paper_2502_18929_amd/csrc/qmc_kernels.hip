@@ -83,7 +83,183 @@ struct Emitter {
     fill += (uint32_t)__popcll(m);
     if (fill > seg - kWave) flush();
   }
+
+  // A record of this step does not fit int32.
+  __device__ __forceinline__ void overflow() {
+    atomicOr(&cnt->err, kErrOverflow);
+    atomicMin(&cnt->err_step, step);
+  }
 };
+
+typedef int32_t v16i32 __attribute__((ext_vector_type(16)));
+
+// Hidden layer of the proposal MLP for the 64 keys of a wave (lane l holds key l; every lane
+// calls): h[l][j] = min(127, max(0, a) >> s1), a = b1[j] + sum_b w1[j][b] x_b, with x_b = +1 where
+// bit b of the key is set and -1 where it is clear for b < nbits, 0 past.  Two int8 MFMA products
+// (32 keys x 16 inputs by 16 inputs x 32 units, four input blocks each) accumulate in int32;
+// lane l of an MFMA holds unit l % 32 of keys 8 (i / 4) + 4 (l / 32) + i % 4 in its i-th
+// accumulator.  The units go to hid[key][unit] (LDS, 64 x 32 bytes).
+__device__ __forceinline__ void mlp_hidden(const QmcProposal& pr, uint64_t key, uint8_t* hid) {
+  const uint32_t lane = __lane_id(), col = lane & 31u, half = lane >> 5;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    const uint64_t kr = __shfl(key, rb * 32 + (int)col);  // key of A-operand row col
+    v16i32 acc = {};
+#pragma unroll
+    for (int kb = 0; kb < kPropIn / 16; ++kb) {
+      const uint32_t b0 = kb * 16 + half * 8;
+      uint64_t a = 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t b = b0 + e;
+        const uint64_t f = b < pr.nbits ? (((kr >> b) & 1u) ? 0x01ull : 0xFFull) : 0ull;
+        a |= f << (8 * e);
+      }
+      const uint64_t w = *reinterpret_cast<const uint64_t*>(pr.w1 + col * kPropIn + b0);
+      acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)a, (long)w, acc, 0, 0, 0);
+    }
+    const int32_t bias = pr.b1[col];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t row = 8 * (i / 4) + 4 * half + (i % 4);
+      const int32_t v = acc[i] + bias;
+      int32_t h = v > 0 ? (v >> pr.s1) : 0;
+      h = h > 127 ? 127 : h;
+      hid[(rb * 32 + row) * kPropHidden + col] = (uint8_t)h;
+    }
+  }
+  wave_lds_fence();
+}
+
+__device__ __forceinline__ uint32_t bitlen64(uint64_t v) {
+  return v ? 64u - (uint32_t)__clzll(v) : 0u;
+}
+
+// Off-diagonal records of one parent per lane under a spawn proposal (End Matter, spawn step:
+// the multinomial over the column's (target, Re/Im) channels, with importance weights); every
+// lane of the wave calls.  Channel ch = 2 (g - 1) + comp of group g >= 1; thresholds P_ch sum to
+// 2^32: a floor F = floor(2^32 / (16 nch)) each, the rest M shared in proportion to the weights
+// W_ch (all zero: as all one), the remainder to the last channel.  Sample k draws Philox stream
+// 0x40 + k: u = word 0 picks the channel whose interval [C, C + P) holds it, j = word 1 mod K, and
+// the channel's Q32 amount x gives floor(|x| / (K P)) walkers plus one where j P + (u - C) <
+// |x| mod (K P), with the sign of x -- a uniform on [0, K P), so the rounding is exact.
+// Weights: uniform 1; heat-bath |x_ch| >> sh, sh = max(0, bitlen(|a| + |b|) + bitlen(q_off) - 24);
+// MLP min(2^24, max(0, score_g)) for both components, score_g = b2[g-1] + w2[g-1] . h (0 past
+// kPropOut groups).
+__device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv, bool valid,
+                                               uint64_t ck, int2 v, const KeyLayout& kl,
+                                               const QmcProposal& pr, uint32_t step,
+                                               uint64_t seed, uint8_t* hid) {
+  const uint32_t lane = __lane_id();
+  const uint64_t key = kl.key(ck);
+  if (pr.kind == 3) mlp_hidden(pr, key, hid);
+  const uint32_t G = valid ? tv.h->n_groups : 0u;
+  const bool act = valid && G > 1;
+  if (__ballot(act) == 0) return;
+  uint32_t hw[kPropHidden / 4];
+#pragma unroll
+  for (int q = 0; q < kPropHidden / 4; ++q)
+    hw[q] = pr.kind == 3 ? reinterpret_cast<const uint32_t*>(hid + lane * kPropHidden)[q] : 0u;
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+  const uint32_t nch = act ? 2 * (G - 1) : 2u;
+  const uint64_t T32 = 1ull << 32, F = T32 / (16ull * nch), M = T32 - (uint64_t)nch * F;
+  uint32_t sh = 0;
+  if (pr.kind == 2) {
+    const uint32_t bl = bitlen64(sab) + bitlen64(tv.h->q_off);
+    sh = bl > 24 ? bl - 24 : 0u;
+  }
+  auto weights = [&](uint32_t g, uint64_t& wr, uint64_t& wi) __attribute__((always_inline)) {
+    if (pr.kind == 2) {
+      int32_t cre, cim;
+      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      wr = uabs64(xre) >> sh;
+      wi = uabs64(xim) >> sh;
+    } else {
+      int32_t sc = 0;
+      if (g - 1 < (uint32_t)kPropOut) {
+        const uint32_t* w2r = reinterpret_cast<const uint32_t*>(pr.w2 + (g - 1) * kPropHidden);
+        sc = pr.b2[g - 1];
+#pragma unroll
+        for (int q = 0; q < kPropHidden / 4; ++q)
+          sc = __builtin_amdgcn_sdot4((int)hw[q], (int)w2r[q], sc, false);
+      }
+      const uint64_t w = sc <= 0 ? 0ull : (sc > (1 << 24) ? (1ull << 24) : (uint64_t)sc);
+      wr = wi = w;
+    }
+  };
+  uint64_t S = 0;
+  if (pr.kind >= 2 && act)
+    for (uint32_t g = 1; g < G; ++g) {
+      uint64_t wr, wi;
+      weights(g, wr, wi);
+      S += wr + wi;
+    }
+  const uint64_t St = S ? S : nch;
+  const uint32_t rep = kl.replica(ck);
+  for (uint32_t k = 0; k < pr.k; ++k) {
+    uint32_t q[4] = {0, 0, 0, 0};
+    if (act) walker_random(key, step, rep, seed, 0x40u + k, q);
+    const uint64_t u = q[0];
+    uint32_t ch = 0;
+    uint64_t C = 0, P = 1;
+    if (act) {
+      if (pr.kind == 1) {
+        const uint64_t P0 = F + M / nch;
+        ch = (uint32_t)(u / P0);
+        if (ch > nch - 1) ch = nch - 1;
+        C = (uint64_t)ch * P0;
+        P = ch + 1 < nch ? P0 : T32 - C;
+      } else {
+        bool found = false;
+        for (uint32_t g = 1; g < G && !found; ++g) {
+          uint64_t wr, wi;
+          weights(g, wr, wi);
+          for (uint32_t comp = 0; comp < 2 && !found; ++comp) {
+            const uint32_t c2 = 2 * (g - 1) + comp;
+            if (c2 + 1 == nch) {
+              ch = c2;
+              P = T32 - C;
+              found = true;
+            } else {
+              const uint64_t w = S ? (comp ? wi : wr) : 1ull;
+              const uint64_t p = F + (w * M) / St;
+              if (u < C + p) {
+                ch = c2;
+                P = p;
+                found = true;
+              } else {
+                C += p;
+              }
+            }
+          }
+        }
+      }
+    }
+    const uint32_t g = act ? 1 + ch / 2 : 1u;
+    int2 rec = make_int2(0, 0);
+    bool over = false;
+    if (act) {
+      int32_t cre, cim;
+      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      const int64_t x = (ch & 1u) ? xim : xre;
+      const uint64_t a = uabs64(x), D = (uint64_t)pr.k * P;
+      const uint64_t U = (uint64_t)(q[1] & (pr.k - 1)) * P + (u - C);
+      const uint64_t m = a / D + (U < a % D ? 1u : 0u);
+      if (m > 0x7FFFFFFFull) {
+        over = true;
+      } else {
+        const int32_t n = x < 0 ? -(int32_t)m : (int32_t)m;
+        rec = (ch & 1u) ? make_int2(0, n) : make_int2(n, 0);
+      }
+    }
+    if (over) em.overflow();
+    em.emit((rec.x | rec.y) != 0, kl.rkey(ck ^ (act ? tv.gx[g] : 0ull), sab), rec);
+  }
+}
 
 // Death/cloning record and children of one parent per lane, every lane of the wave calling
 // (`valid` lanes hold a parent; (w0, w1) its spawn and death comb words).  The lane's table is its
@@ -91,9 +267,12 @@ struct Emitter {
 // loop runs to the largest count in the wave.  The death delta is a record of the parent's own
 // key, summed into the next store by the merge like the children; qsh holds the per-segment Q32
 // shifts of the table.
+template <bool kProp>
 __device__ __forceinline__ void spawn_records(Emitter& em, const TableView& tv, bool valid,
                                               uint64_t ck, int2 v, uint32_t w0, uint32_t w1,
-                                              const KeyLayout& kl, const int64_t* qsh) {
+                                              const KeyLayout& kl, const int64_t* qsh,
+                                              const QmcProposal& pr, uint32_t step,
+                                              uint64_t seed, uint8_t* hid) {
   const uint64_t key = kl.key(ck);
   const uint64_t sab = uabs64(v.x) + uabs64(v.y);
   {
@@ -112,6 +291,10 @@ __device__ __forceinline__ void spawn_records(Emitter& em, const TableView& tv, 
       }
       em.emit((d.x | d.y) != 0, kl.rkey(ck, sab), d);
     }
+  }
+  if constexpr (kProp) {
+    spawn_proposal(em, tv, valid, ck, v, kl, pr, step, seed, hid);
+    return;
   }
   const uint32_t G = valid ? tv.h->n_groups : 0u;
   const bool act = valid && G > 1 && !comb_all_zero(sab, tv.h->q_off, w0);
@@ -133,42 +316,49 @@ __device__ __forceinline__ void spawn_records(Emitter& em, const TableView& tv, 
 }
 
 // Records of one parent per lane drawn from Philox stream `stream` at step `step`.
+template <bool kProp = false>
 __device__ __forceinline__ void spawn_parent(Emitter& em, const TabSet& ts, bool valid,
                                              uint64_t ck, int2 v, uint32_t step, uint64_t seed,
                                              const KeyLayout& kl, uint32_t stream,
-                                             const int64_t* qsh) {
+                                             const int64_t* qsh, const QmcProposal& pr = {},
+                                             uint8_t* hid = nullptr) {
   uint32_t w[4] = {0, 0, 0, 0};
   if (valid) walker_random(kl.key(ck), step, kl.replica(ck), seed, stream, w);
   const TableView tv = table_view(ts.of_segment(valid ? kl.replica(ck) : 0u));
-  spawn_records(em, tv, valid, ck, v, w[0], w[1], kl, qsh);
+  spawn_records<kProp>(em, tv, valid, ck, v, w[0], w[1], kl, qsh, pr, step, seed, hid);
 }
 
 // Records of up to 64 queued parents (lane < n holds one, with the comb words drawn when it was
 // queued).
+template <bool kProp>
 __device__ __forceinline__ void spawn_batch(Emitter& em, const TabSet& ts, const int64_t* qsh,
                                             const uint64_t* ak, const int2* av, const uint2* aw,
-                                            uint32_t n, const KeyLayout& kl) {
+                                            uint32_t n, const KeyLayout& kl,
+                                            const QmcProposal& pr, uint32_t step, uint64_t seed,
+                                            uint8_t* hid) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < n;
   const uint64_t ck = valid ? ak[lane] : 0;
   const int2 v = valid ? av[lane] : make_int2(0, 0);
   const uint2 w = valid ? aw[lane] : make_uint2(0, 0);
   const TableView tv = table_view(ts.of_segment(valid ? kl.replica(ck) : 0u));
-  spawn_records(em, tv, valid, ck, v, w.x, w.y, kl, qsh);
+  spawn_records<kProp>(em, tv, valid, ck, v, w.x, w.y, kl, qsh, pr, step, seed, hid);
 }
 
 // ---------------------------------------------------------------------------------------------
 // k_spawn: death records and children of the first step of a batch from N(s) (later steps spawn
 // inside k_merge), and with AB2 the records of the second term from N(s-1) (stream 1).
 // ---------------------------------------------------------------------------------------------
+template <bool kProp>
 __global__ __launch_bounds__(kBlock) void k_spawn(
     const uint64_t* __restrict__ pk, const int2* __restrict__ pv, Counters* __restrict__ cnt,
     const uint64_t* __restrict__ count, TabSet ts, uint32_t step,
     uint64_t seed, KeyLayout kl, uint32_t stream, const int64_t* __restrict__ qsh,
     uint64_t* __restrict__ ck_out, int2* __restrict__ cv_out, uint64_t cap_child,
-    uint32_t* __restrict__ ghist, uint32_t passes) {
+    uint32_t* __restrict__ ghist, uint32_t passes, QmcProposal pr) {
   __shared__ uint64_t s_key[kWaves][kSpawnSeg];
   __shared__ int2 s_val[kWaves][kSpawnSeg];
+  __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? kWave * kPropHidden : 4];
   if (cnt->err) return;
   const uint64_t np = *count;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
@@ -185,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
       ck = pk[p];
       v = pv[p];
     }
-    spawn_parent(em, ts, valid, ck, v, step, seed, kl, stream, qsh);
+    spawn_parent<kProp>(em, ts, valid, ck, v, step, seed, kl, stream, qsh, pr,
+                        s_hid[kProp ? wave : 0]);
   }
   if (em.fill) em.flush();
 }
@@ -529,10 +720,13 @@ struct MergeArgs {
   uint64_t cap_child;
   uint32_t* ghist_next;
   uint32_t passes;
+  QmcProposal prop;          // spawn proposal of step s+1 (kind 0: the comb)
 };
 
+template <bool kProp>
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   constexpr int CAP = kMergeCap;
+  __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? kWave * kPropHidden : 4];
   __shared__ uint64_t s_pk[CAP];   // parents of the tile; then its annihilated records
   __shared__ int2 s_pv[CAP];
   __shared__ uint64_t s_ck[CAP];   // children of the tile; later the spawn staging
@@ -571,8 +765,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
                  A.passes};
       for (uint32_t b = wave; b < nb; b += kWaves) {
         const uint32_t b0 = b * kWave;
-        spawn_batch(em, A.tab_next, A.qshift, s_ak + b0, s_av + b0, s_aw + b0,
-                    nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl);
+        spawn_batch<kProp>(em, A.tab_next, A.qshift, s_ak + b0, s_av + b0, s_aw + b0,
+                           nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl, A.prop,
+                           A.step + 1, A.seed, s_hid[kProp ? wave : 0]);
       }
       if (em.fill) em.flush();
     }
@@ -769,7 +964,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           }
           walker_random(kl.key(ck), A.step + 1, rep, A.seed, 0u, w);
           const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-          act = !comb_all_zero(sab, h_qoff, w[0]) || !comb_all_zero(sab, h_qdiag, w[1]);
+          // a proposal draws for every parent of a column with off-diagonal groups
+          act = (kProp ? h_qoff != 0 : !comb_all_zero(sab, h_qoff, w[0])) ||
+                !comb_all_zero(sab, h_qdiag, w[1]);
         }
         const uint64_t m = __ballot(act);
         if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);
@@ -1090,11 +1287,19 @@ int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counter
                uint32_t rep_per, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint32_t stream, const int64_t* qsh,
                uint64_t* ck, int2* cv, uint64_t cap_child, uint64_t max_parents, uint32_t* ghist,
-               uint32_t passes) {
+               uint32_t passes, const QmcProposal* prop) {
   uint32_t g = grid_for(max_parents, 1024);
-  hipLaunchKernelGGL(k_spawn, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters, count,
-                     TabSet{tab_base, tab_off, rep_per}, step, seed, key_layout(kbits, init_min), stream, qsh, ck, cv, cap_child,
-                     ghist, passes);
+  const QmcProposal pr = prop ? *prop : QmcProposal{};
+  if (pr.kind)
+    hipLaunchKernelGGL(k_spawn<true>, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters,
+                       count, TabSet{tab_base, tab_off, rep_per}, step, seed,
+                       key_layout(kbits, init_min), stream, qsh, ck, cv, cap_child, ghist, passes,
+                       pr);
+  else
+    hipLaunchKernelGGL(k_spawn<false>, dim3(g), dim3(kBlock), 0, st, pk, pv, (Counters*)counters,
+                       count, TabSet{tab_base, tab_off, rep_per}, step, seed,
+                       key_layout(kbits, init_min), stream, qsh, ck, cv, cap_child, ghist, passes,
+                       pr);
   return (int)hipGetLastError();
 }
 
@@ -1133,7 +1338,7 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                const int64_t* qshiftB, uint32_t step, uint64_t seed,
                uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
                uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
-               uint32_t* ghist_next, uint32_t passes) {
+               uint32_t* ghist_next, uint32_t passes, const QmcProposal* prop) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   const KeyLayout kl = key_layout(kbits, init_min);
   hipLaunchKernelGGL(k_merge_part,
@@ -1166,9 +1371,13 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.cap_child = cap_child;
   a.ghist_next = ghist_next;
   a.passes = passes;
+  a.prop = prop ? *prop : QmcProposal{};
   const uint32_t g = max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
                                                         : (uint32_t)kMergeBlocks;
-  hipLaunchKernelGGL(k_merge, dim3(g), dim3(kBlock), 0, st, a);
+  if (a.prop.kind)
+    hipLaunchKernelGGL(k_merge<true>, dim3(g), dim3(kBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_merge<false>, dim3(g), dim3(kBlock), 0, st, a);
   return (int)hipGetLastError();
 }
 

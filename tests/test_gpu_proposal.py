@@ -1,0 +1,171 @@
+"""GPU parity of the spawn proposals (uniform, heat-bath, int8 MLP scores): the HIP streamed step
+through the C ABI against the CPU oracle, bit for bit, on seeded synthetic inputs.  Both sides
+run their own trajectories from the same initial records and the same MLP weights."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2502_18929_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_18929_amd import binding
+    binding.lib()
+    return binding
+
+
+def _assert_same(g, o, R, where=""):
+    for r in range(R):
+        gk, ga, gb = g.export(r)
+        ok, oa, ob = o.export(r)
+        if not (np.array_equal(gk, ok) and np.array_equal(ga, oa) and np.array_equal(gb, ob)):
+            n = min(len(gk), len(ok))
+            bad = np.nonzero((gk[:n] != ok[:n]) | (ga[:n] != oa[:n]) | (gb[:n] != ob[:n]))[0]
+            first = int(bad[0]) if len(bad) else n
+            raise AssertionError(f"{where} replica {r}: sizes gpu {len(gk)} oracle {len(ok)}, "
+                                 f"first difference at {first}")
+
+
+def _pair(B, orc, n, R, seed, dt, h, lops, keys, re, im, kind, K, mlp, store, spawn):
+    g = B.QMC(n, R, seed, dt, h, lops, keys, re, im, store_capacity=store, spawn_capacity=spawn)
+    g.set_path("streamed")
+    g.set_proposal(kind, K, mlp)
+    o = orc.Oracle(n, R, seed, dt, h, lops, keys, re, im)
+    o.set_proposal(kind, K, mlp)
+    return g, o
+
+
+CASES = [(kind, K) for kind in ["uniform", "heatbath", "mlp"] for K in (1, 4)]
+
+
+@pytest.mark.parametrize("kind,K", CASES)
+@pytest.mark.parametrize("seed", range(3))
+def test_random_models_every_step(B, orc, kind, K, seed):
+    rng = np.random.default_rng(1300 + seed)
+    n = int(rng.integers(1, 5))
+    h, lops = W.random_model(n, rng, n_h=int(rng.integers(1, 6)), n_l=int(rng.integers(0, 4)))
+    R = int(rng.integers(1, 4))
+    keys, re, im = W.random_records(n, rng, int(rng.integers(1, 12)), scale=300)
+    steps = 6
+    s = rng.normal(size=(steps, len(h)))
+    gam = np.abs(rng.normal(size=(steps, len(lops))))
+    mlp = W.random_mlp(rng) if kind == "mlp" else None
+    _say(f"proposal {kind} K={K} seed {seed}: n={n} R={R} {len(keys)} keys")
+    g, o = _pair(B, orc, n, R, 40 + seed, 0.01, h, lops, keys, re, im, kind, K, mlp,
+                 1 << 12, 1 << 14)
+    for k in range(3):       # one step per call: the spawn kernel
+        g.step(s[k:k + 1], gam[k:k + 1])
+        o.step(s[k:k + 1], gam[k:k + 1])
+        _assert_same(g, o, R, f"step {k}")
+    g.step(s[3:], gam[3:])   # three steps in one call: spawns inside the merge
+    o.step(s[3:], gam[3:])
+    _assert_same(g, o, R, "after the batch")
+
+
+@pytest.mark.parametrize("kind,K", [("uniform", 2), ("heatbath", 2), ("mlp", 2), ("mlp", 4)])
+def test_many_tiles_and_ragged(B, orc, kind, K):
+    """n=7 register, every key of two replicas occupied with uneven populations: the merge runs
+    over many tiles with a ragged tail and drains full and partial batches of parents."""
+    rng = np.random.default_rng(1400 + K)
+    n, R = 7, 2
+    h, lops = W.random_model(n, rng, n_h=8, n_l=3)
+    keys = np.arange(1 << (2 * n), dtype=np.uint64)[::3]
+    re = rng.integers(-40, 40, size=len(keys)).astype(np.int32)
+    im = rng.integers(-40, 40, size=len(keys)).astype(np.int32)
+    re[(re == 0) & (im == 0)] = 3
+    steps = 5
+    s = rng.normal(size=(steps, len(h))) * 0.3
+    gam = np.abs(rng.normal(size=(steps, len(lops)))) * 0.3
+    mlp = W.random_mlp(rng) if kind == "mlp" else None
+    _say(f"proposal {kind} K={K}: n={n}, {len(keys)} keys x {R} replicas")
+    g, o = _pair(B, orc, n, R, 9, 0.01, h, lops, keys, re, im, kind, K, mlp, 1 << 15, 1 << 20)
+    g.step(s, gam)
+    o.step(s, gam, threads=2)
+    _assert_same(g, o, R, f"{kind} K={K} after {steps} steps")
+
+
+def test_ghz20_nm_mlp_first_steps(B, orc):
+    """The n=20 GHZ workload (40 key bits into the MLP) for 200 steps with the MLP proposal."""
+    w = W.config_ghz20_nm()
+    rng = np.random.default_rng(1500)
+    mlp = W.random_mlp(rng)
+    R = 2
+    _say("ghz20_nm with the MLP proposal, 2 replicas, 200 steps")
+    g = B.QMC.from_workload(w, store_capacity=1 << 17, spawn_capacity=1 << 19, n_replicas=R)
+    g.set_proposal("mlp", 2, mlp)
+    o = orc.Oracle(w.n, R, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    o.set_proposal("mlp", 2, mlp)
+    for k0 in (0, 100):
+        g.step(w.s[k0:k0 + 100], w.gamma[k0:k0 + 100])
+        o.step(w.s[k0:k0 + 100], w.gamma[k0:k0 + 100], threads=2)
+        _assert_same(g, o, R, f"step {k0 + 100}")
+
+
+def test_overflowing_record_is_reported_like_the_oracle(B, orc):
+    """X on each of 8 qubits (16 column groups, 32 channels) and one parent of 2^31 - 1 walkers:
+    a uniform draw onto an imaginary channel carries about 2^32.7 walkers.  With this seed the
+    oracle stops at step 2; the GPU must stop there too, keeping N(2)."""
+    n = 8
+    h = [(1 << q, 0, 20.0) for q in range(n)]
+    keys = np.array([0], dtype=np.uint64)
+    re = np.array([2 ** 31 - 1], dtype=np.int32)
+    im = np.array([0], dtype=np.int32)
+    s = np.ones((4, n))
+    gam = np.zeros((4, 0))
+    g, o = _pair(B, orc, n, 1, 3, 0.005, h, [], keys, re, im, "uniform", 1, None, 1 << 10,
+                 1 << 12)
+    with pytest.raises(orc.OracleError) as eo:
+        o.step(s, gam)
+    assert eo.value.code == -5 and o.step_index == 2
+    with pytest.raises(B.QMCError) as eg:
+        g.step(s, gam)
+    assert eg.value.code == B.QMC_ERR_COUNT_OVERFLOW
+    assert g.counters()["step"] == 2
+    _assert_same(g, o, 1, "stopped at step 2")
+
+
+def _raw(B, g, kind, K, s1=0):
+    g._check(B.lib().qmc_set_proposal(g._ctx, kind, K, None, None, None, None, s1))
+
+
+def test_refusals(B, orc):
+    rng = np.random.default_rng(1600)
+    h, lops = W.random_model(2, rng)
+    keys, re, im = W.random_records(2, rng, 4)
+    g = B.QMC(2, 1, 1, 0.01, h, lops, keys, re, im, store_capacity=64, spawn_capacity=256)
+    for kind, K in [(1, 0), (1, 3), (1, 128), (4, 1), (3, 1)]:   # (3, 1): MLP without weights
+        with pytest.raises(B.QMCError) as e:
+            _raw(B, g, kind, K)
+        assert e.value.code == B.QMC_ERR_ARG
+    g.set_proposal("uniform", 2)
+    with pytest.raises(B.QMCError):
+        g.set_integrator("ab2")
+    with pytest.raises(B.QMCError):
+        g.set_initiator(10)
+    g.set_path("fused")
+    with pytest.raises(B.QMCError) as e:
+        g.step(np.zeros((1, len(h))), np.zeros((1, len(lops))))
+    assert e.value.code == B.QMC_ERR_ARG
+    g.set_path("auto")
+    g.step(np.zeros((1, len(h))), np.zeros((1, len(lops))))   # the automatic path streams
+    # samples x groups beyond the merge's run bound: dd12 has 60 off-diagonal groups
+    w = W.config_dd12()
+    d = B.QMC.from_workload(w, store_capacity=1 << 12, spawn_capacity=1 << 14, n_replicas=1)
+    d.set_proposal("uniform", 8)
+    with pytest.raises(B.QMCError) as e:
+        d.step(w.s[:1], w.gamma[:1])
+    assert e.value.code == B.QMC_ERR_ARG
+    d.set_proposal("uniform", 4)
+    d.step(w.s[:1], w.gamma[:1])

@@ -72,14 +72,17 @@ def profiled_traffic(kind, workload):
     return float(b.group(1))
 
 
-def cpu_baseline(w, integrator="euler", init_min=0, budget_s=20.0):
+def cpu_baseline(w, integrator="euler", init_min=0, budget_s=20.0, proposal=None):
     """The CPU oracle, untuned, on the host cores over the first steps of the same workload
-    (about budget_s seconds of work); reports walker-steps/s."""
+    (about budget_s seconds of work); reports walker-steps/s.  proposal = (kind, samples, mlp)
+    or None (the comb)."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     o = oracle.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
                       w.init_im, integrator=integrator)
     o.set_initiator(init_min)
+    if proposal:
+        o.set_proposal(*proposal)
     t0 = time.perf_counter()
     done, used = 0, 1
     chunk = 50
@@ -116,6 +119,11 @@ def main():
     ap.add_argument("--initiator-xi", default=None,
                     help="initiator approximation with threshold xi * N^diag (End Matter on "
                          "simulation methodology; the paper uses 0.001); default: the plain step")
+    ap.add_argument("--proposal", default="comb", choices=["comb", "uniform", "heatbath", "mlp"],
+                    help="spawn proposal (End Matter spawn step, importance weighted); mlp is "
+                         "trained first on statistics of an untimed plain run")
+    ap.add_argument("--proposal-samples", type=int, default=4,
+                    help="channel draws per parent under a proposal (a power of two)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -123,8 +131,8 @@ def main():
               "(replicas and key-space shards would each map to one GPU).", file=sys.stderr)
         sys.exit(2)
     dominant = DOMINANT_INITIATOR if args.initiator_xi else DOMINANT
-    kind = args.roofline_kernel or ("merge" if args.path == "streamed"
-                                    else dominant[args.workload])
+    kind = args.roofline_kernel or ("merge" if args.path == "streamed" or
+                                    args.proposal != "comb" else dominant[args.workload])
 
     import torch
     from paper_2502_18929_amd import binding, workloads as W
@@ -144,6 +152,18 @@ def main():
                 if args.initiator_xi else 0)
     g.set_initiator(init_min)
     init = [g.export(r) for r in range(w.n_replicas)]
+    prop, train_corr = None, None
+    if args.proposal != "comb":
+        mlp = None
+        if args.proposal == "mlp":
+            # statistics of the method's own plain run (untimed), then back to the initial state
+            from paper_2502_18929_amd import proposal as PR
+            at = list(range(w.nsteps // 16, w.nsteps, w.nsteps // 16))
+            mlp, train_corr = PR.train(g, w, at[-1], at)
+            for r in range(w.n_replicas):
+                g.import_(r, *init[r], step=0)
+        prop = (args.proposal, args.proposal_samples, mlp)
+        g.set_proposal(*prop)
 
     # warmup: W steps from the initial state, then restore the initial state (untimed)
     g.run_workload(w, 0, Wm)
@@ -211,10 +231,14 @@ def main():
         },
         "final": {"n_occ_total": st1["n_occ"],
                   "fidelity_mean": float(obs["fidelity"][:, 0].mean()),
+                  "fidelity_std_replicas": float(obs["fidelity"][:, 0].std(ddof=1)),
                   "trace_mean": float(obs["trace"].mean())},
     }
+    if prop:
+        res["config"]["proposal"] = {"kind": prop[0], "samples": prop[1],
+                                     "mlp_train_corr": train_corr}
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(w, args.integrator, init_min)
+        res["cpu_baseline"] = cpu_baseline(w, args.integrator, init_min, proposal=prop)
     g.close()
     print(json.dumps(res), flush=True)
 

@@ -667,13 +667,24 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
   const uint32_t nc = (uint32_t)cnt->n_child[csel];
   const uint32_t total = np + nc;
   const uint32_t ntiles = (total + kMergeTile - 1) / kMergeTile;
-  const uint32_t lane = __lane_id();
   auto A = [&](uint32_t x) { return pk[x]; };
   auto B = [&](uint32_t x) { return ckeys[x] >> ish; };  // composite key of a routed record
-  for (uint32_t t = gt / kWave; t <= ntiles && t <= max_tiles; t += gridDim.x * kWaves) {
+  // One thread per tile boundary: a binary search on the merge path (the upper levels of the
+  // searches are shared by neighbouring boundaries and stay in the caches), then the boundary
+  // moves past the records that continue the run of the last key before it.
+  for (uint32_t t = gt; t <= ntiles && t <= max_tiles; t += gridDim.x * kBlock) {
     uint32_t d = t * kMergeTile;
     if (d > total) d = total;
-    const uint32_t i = merge_path_wave(A, np, B, nc, d);
+    // i = the number of parents among the first d merged items (parents first on equal keys)
+    uint32_t lo = d > nc ? d - nc : 0u, hi = d < np ? d : np;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (A(mid) <= B(d - 1 - mid))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const uint32_t i = lo;
     uint32_t j = d - i;
     if (d > 0 && d < total) {
       uint64_t last = 0;
@@ -682,16 +693,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
         const uint64_t c = B(j - 1);
         if (i == 0 || c > last) last = c;
       }
-      // children continuing the run of `last` (at most one per column group)
-      for (int r = 0; r < (kMergeSlack + kWave - 1) / kWave; ++r) {
-        const uint32_t q = j + lane;
-        const uint64_t m = __ballot(q < nc && B(q) <= last);
-        const uint32_t c = (uint32_t)__popcll(m);
-        j += c;
-        if (c < (uint32_t)kWave) break;
-      }
+      // records continuing the run of `last` (at most kMergeSlack of them)
+      const uint32_t jmax = nc - j < (uint32_t)kMergeSlack ? nc : j + (uint32_t)kMergeSlack;
+      while (j < jmax && B(j) <= last) ++j;
     }
-    if (lane == 0) splits[t] = make_uint2(i, j);
+    splits[t] = make_uint2(i, j);
   }
 }
 
@@ -1342,7 +1348,7 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   const KeyLayout kl = key_layout(kbits, init_min);
   hipLaunchKernelGGL(k_merge_part,
-                     dim3(grid_for(((uint64_t)max_tiles + 1) * kWave, 2048)), dim3(kBlock), 0,
+                     dim3(grid_for((uint64_t)max_tiles + 1, 2048)), dim3(kBlock), 0,
                      st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next,
                      kl.ish);
   MergeArgs a;

@@ -27,6 +27,7 @@ constexpr int kMaxPasses = 6;        // ceil(64 / 11)
 constexpr int kSortIpt = 16;         // records per thread of a sort tile
 constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
+constexpr int kMergeTicketCounters = 8;  // k_merge tile tickets: counter b mod 8 serves block b
 constexpr int kMergeBlocks = 768;    // k_merge: three workgroups per CU (about 51 KB of LDS each)
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
 constexpr int kMaxCircuits = kMaxSegments;  // circuits of one batch (each needs a key range)
@@ -77,9 +78,10 @@ struct Counters {
   uint64_t out_steps;      // running sum of annihilated output keys of every step
   uint32_t err;
   uint32_t err_step;
-  uint32_t tile_counter;   // merge tile ticket
+  uint32_t tile_counter;   // (unused)
   uint32_t resplits;       // key ranges re-cut inside the fused kernel (running sum)
   uint32_t sort_ticket[2][kMaxPasses + 2];  // onesweep tile tickets per step parity and pass
+  uint32_t merge_ticket[kMergeTicketCounters][32];  // merge tile tickets, one 128-byte line each
 };
 
 // Epoch tags of the look-back status words (never 0, distinct within a batch of <= 8000 steps).

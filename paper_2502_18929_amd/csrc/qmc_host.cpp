@@ -686,7 +686,12 @@ struct Chunk {
 // store (and N(s-1) for AB2) and c->step reflect kd.
 int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::Counters& hc) {
   const qmc::Counters before = c->last_hc;
-  uint32_t* pin_done = reinterpret_cast<uint32_t*>(c->pinned_small + 1024);
+  // the kernel's done flags go to pinned memory past the counters, which read_counters copies
+  // to the start of the same buffer
+  constexpr size_t kPinDone = (sizeof(qmc::Counters) + 255) / 256 * 256;
+  static_assert(kPinDone >= sizeof(qmc::Counters) && kPinDone + 8 <= (1u << 16),
+                "done flags must not overlap the counters in the pinned staging buffer");
+  uint32_t* pin_done = reinterpret_cast<uint32_t*>(c->pinned_small + kPinDone);
   const uint32_t nst = ch.nst;
   PersistLaunch pl;
   pl.ck = c->sk(0);

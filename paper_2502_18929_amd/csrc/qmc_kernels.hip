@@ -658,8 +658,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
   // ago; this step's merge, which spawns the next step's children, runs after this kernel.
   for (uint32_t i = gt; i < (uint32_t)(kMaxPasses * kRadixBins); i += gridDim.x * kBlock)
     ghist_next[i] = 0;
+  if (gt < (uint32_t)kMergeTicketCounters) cnt->merge_ticket[gt][0] = 0;
   if (gt == 0) {
-    cnt->tile_counter = 0;
     cnt->n_child[csel ^ 1] = 0;
     for (int p = 0; p < kMaxPasses + 2; ++p) cnt->sort_ticket[csel ^ 1][p] = 0;
   }
@@ -802,8 +802,14 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   // sorted by segment, so they change rarely)
   uint32_t h_seg = ~0u;
   uint64_t h_qoff = 0, h_qdiag = 0;
+  // Tile tickets from C counters (a single contended counter serializes the grid): block b
+  // takes tiles b mod C, b mod C + C, ... in order, so every tile is taken by a running block and
+  // the smallest unfinished tile is always being processed (its look-back cannot stall).
+  const uint32_t nctr = gridDim.x < (uint32_t)kMergeTicketCounters ? gridDim.x
+                                                                    : (uint32_t)kMergeTicketCounters;
+  const uint32_t my_ctr = blockIdx.x % nctr;
   while (true) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->tile_counter, 1u);
+    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->merge_ticket[my_ctr][0], 1u) * nctr + my_ctr;
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) break;

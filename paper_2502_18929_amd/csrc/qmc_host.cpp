@@ -726,7 +726,7 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.qshift = c->at<int64_t>(c->L.qshift);
   pl.qshiftB = c->at<int64_t>(c->L.qshift) + c->R;
   pl.slots = c->at<uint64_t>(c->L.slots);
-  pl.max_rebal = c->integrator == 0 && c->C == 1 ? kKernelResplits : 0u;
+  pl.max_rebal = c->C == 1 ? kKernelResplits : 0u;
   pl.epoch0 = c->epoch + 1;
   // barriers of this launch: batch start, one per step, two per re-split
   c->epoch += (uint64_t)nst + 1 + 2ull * pl.max_rebal;

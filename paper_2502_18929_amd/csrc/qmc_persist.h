@@ -10,8 +10,8 @@ constexpr uint32_t kPersistTableBytes = 8192;
 struct PersistLaunch {
   uint64_t* ck;         // canonical store (read at batch start, rewritten by a re-split)
   int2* cv;
-  const uint64_t* pk_prev;  // AB2: N(step0 - 1), sorted, count in counters->n_prev; else null
-  const int2* pv_prev;
+  uint64_t* pk_prev;    // AB2: N(step0 - 1), sorted, count in counters->n_prev; else null
+  int2* pv_prev;        // (a re-split in the kernel rewrites it with N(s))
   void* counters;
   uint32_t cur;
   uint64_t* sk;         // segments [nbuf][P][segcap]
@@ -43,7 +43,7 @@ struct PersistLaunch {
   uint64_t cap_store;
   uint64_t cap_inbox;
   uint32_t rebal_min;
-  uint32_t max_rebal;   // re-splits done inside one launch (one circuit, Euler); 0: stop instead
+  uint32_t max_rebal;   // re-splits done inside one launch (one circuit); 0: stop instead
   uint32_t* done;       // [2]
 };
 

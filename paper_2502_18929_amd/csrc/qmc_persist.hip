@@ -39,6 +39,8 @@ struct PersistArgs {
   // AB2: N(step0 - 1), sorted (its records draw the second term of step0), or null
   const uint64_t* pk_prev;
   const int2* pv_prev;
+  uint64_t* pkw;          // the same array, rewritten by an AB2 re-split in the kernel (N(s))
+  int2* pvw;
   // segments [nbuf][P][segcap] and counts [nbuf][P]; pass k reads buffer k mod nbuf and
   // writes buffer (k + 1) mod nbuf (three buffers keep N(s) and N(s-1) while N(s+1) is written)
   uint64_t* sk;
@@ -71,7 +73,7 @@ struct PersistArgs {
                           // error bits, each tagged with the epoch
   uint64_t cap_store;     // total occupied keys allowed
   uint64_t cap_inbox;     // total inbox records allowed per step
-  uint32_t max_rebal;     // re-splits the kernel may do itself (one circuit, Euler), then it stops
+  uint32_t max_rebal;     // re-splits the kernel may do itself (one circuit), then it stops
   uint32_t rebal_min;     // stop to rebalance when the largest range exceeds 1.25 x the larger
                           // of the mean and the launch's first largest range, + this
   uint64_t epoch0;        // first barrier epoch of this launch (epochs only grow)
@@ -95,7 +97,7 @@ struct Shared {
   uint64_t red[kPWaves];
   uint64_t xch[kPWaves][4];
   uint64_t dec[4];        // reduced totals of the last barrier: keys, max segment, inbox, errors
-  uint32_t nouts[kMaxSegments];  // keys out of every workgroup at the last barrier
+  uint32_t nouts[2][kMaxSegments];  // keys out of every workgroup, by barrier epoch parity
   uint4 tab[kPersistTableBytes / 16];   // the step table of the spawns drawn in this pass
   uint4 tabB[kPersistTableBytes / 16];  // AB2: the table of their second term
   uint32_t err;           // error bits this workgroup raised in the current step
@@ -186,7 +188,7 @@ __device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint6
       }
     }
     v0 &= 0xFFFFFFFFull;
-    S.nouts[q] = (uint32_t)v0;
+    S.nouts[epoch & 1u][q] = (uint32_t)v0;
     tot += v0;
     mx = v0 > mx ? v0 : mx;
     nn += v1 & 0xFFFFFFFFull;
@@ -236,11 +238,12 @@ __device__ __forceinline__ uint32_t upper_bound_lds(const uint64_t* a, uint32_t 
   return lo;
 }
 
-__device__ __forceinline__ uint64_t lower_bound_glb(const uint64_t* a, uint64_t n, uint64_t v) {
+__device__ __forceinline__ uint64_t lower_bound_glb(const uint64_t* a, uint64_t n, uint64_t v,
+                                                   bool coherent = false) {
   uint64_t lo = 0, hi = n;
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
-    if (a[mid] < v)
+    if ((coherent ? ld_agent(&a[mid]) : a[mid]) < v)
       lo = mid + 1;
     else
       hi = mid;
@@ -668,7 +671,8 @@ __device__ __forceinline__ void process_wide(const PersistArgs& A, Shared& S, Ro
 __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router& R,
                                         const LTable& tn, const int64_t* qsh, uint32_t stream,
                                         const uint64_t* seg_k, const int2* seg_v, uint64_t o0,
-                                        uint64_t o1, uint32_t step) {
+                                        uint64_t o1, uint32_t step,
+                                        bool coherent = false) {
   const uint32_t t = threadIdx.x, wave = t / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
   const uint64_t q_diag = tn.h->q_diag, q_off = tn.h->n_groups > 1 ? tn.h->q_off : 0;
@@ -682,8 +686,8 @@ __device__ __forceinline__ void advance(const PersistArgs& A, Shared& S, Router&
     uint32_t w[4] = {0, 0, 0, 0};
     int64_t qs = 0;
     if (valid) {
-      ck = seg_k[i];
-      v = seg_v[i];
+      ck = coherent ? ld_agent(&seg_k[i]) : seg_k[i];
+      v = coherent ? ld_agent(&seg_v[i]) : seg_v[i];
       const uint32_t rep = kl.replica(ck);
       qs = qsh[rep];
       walker_random(kl.key(ck), step, rep, A.seed, stream, w);
@@ -926,7 +930,8 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   uint32_t reason = 0, kdone = A.nsteps;
   uint64_t tot_last = 0, tot_prev = 0;  // keys of the last two passes' outputs
   uint64_t mx_ref = 0;  // largest key range right after the split (circuit-aligned ranges)
-  const uint32_t rebal_max = A.nbuf == 2 && A.n_circuits == 1 ? A.max_rebal : 0u;
+  const uint32_t rebal_max =
+      A.n_circuits == 1 && (A.nbuf == 2 || A.pkw != nullptr) ? A.max_rebal : 0u;
   uint32_t rebal_left = rebal_max;
   static_assert(kPersistTableBytes / 16 == kPBlock, "one table word per thread");
   // table offsets of the current pass, loaded one pass ahead; the table of pass k is the one of
@@ -1037,25 +1042,43 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         kdone = (uint32_t)k + 1;
         break;
       }
-      // Re-split in the kernel (one circuit, Euler): N(s+1) of every range goes to the
-      // canonical store at its prefix, the records already routed for step s+1 are dropped,
-      // the ranges are re-cut at even positions, and step s+1 is drawn again from the new
-      // slices into the same segment buffer and inbox parity; pass k + 1 then runs as usual.
-      // The draws are keyed on the walkers, so the records are the same; only their owners
-      // change.
+      // Re-split in the kernel (one circuit): N(s+1) of every range goes to the canonical
+      // store at its prefix (with AB2 also N(s), this pass's parents, to the N(s-1) array, which
+      // only the first pass reads), the records already routed for step s+1 are dropped, the
+      // ranges are re-cut at even positions of N(s+1), and step s+1 is drawn again from the new
+      // slices (with AB2 its second term from each range's slice of N(s)) into the same segment
+      // buffer and inbox parity; pass k + 1 then runs as usual.  The draws are keyed on the
+      // walkers, so the records are the same; only their owners change.
       --rebal_left;
+      const bool two_rs = A.nbuf == 3 && two;
       {
-        uint32_t mine = t < p ? S.nouts[t] : 0u;
-        for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
-        if (__lane_id() == 0) S.scan[t / kWave] = mine;
-        __syncthreads();
-        uint64_t prefix = 0;
-        for (int w = 0; w < kPWaves; ++w) prefix += S.scan[w];
+        // exclusive prefix over the workgroups of the counts of barrier parity `par_b`
+        auto prefix_of = [&](uint32_t par_b) -> uint64_t {
+          uint32_t mine = t < p ? S.nouts[par_b][t] : 0u;
+          for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+          __syncthreads();
+          if (__lane_id() == 0) S.scan[t / kWave] = mine;
+          __syncthreads();
+          uint64_t pre = 0;
+          for (int w = 0; w < kPWaves; ++w) pre += S.scan[w];
+          return pre;
+        };
+        const uint64_t prefix = prefix_of(epoch & 1u);
         const uint64_t* sk_o = A.sk + ((uint64_t)ob * P + p) * A.segcap;
         const int2* sv_o = A.sv + ((uint64_t)ob * P + p) * A.segcap;
         for (uint64_t i = t; i < nout; i += kPBlock) {
           st_agent(&A.ckw[prefix + i], sk_o[i]);
           st_agent(&A.cvw[prefix + i], sv_o[i]);
+        }
+        if (two_rs) {
+          // N(s): this pass's parents, counted at the previous barrier
+          const uint64_t prefix_s = prefix_of((epoch - 1) & 1u);
+          const uint64_t* sk_i = A.sk + ((uint64_t)ib * P + p) * A.segcap;
+          const int2* sv_i = A.sv + ((uint64_t)ib * P + p) * A.segcap;
+          for (uint64_t i = t; i < np_k; i += kPBlock) {
+            st_agent(&A.pkw[prefix_s + i], sk_i[i]);
+            st_agent(&A.pvw[prefix_s + i], sv_i[i]);
+          }
         }
         if (t == 0) st_agent(&A.in_n[(par ^ 1u) * P + p], 0u);
       }
@@ -1068,6 +1091,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       for (uint32_t q = t; q < P; q += kPBlock)
         S.split[q] = q == 0 ? 0ull : ld_agent(&A.ckw[((uint64_t)q * tot) / P]);
       __syncthreads();
+      uint64_t nout2 = 0;
       const uint64_t rb = p == 0 ? 0 : ((uint64_t)p * tot) / P;
       const uint64_t re = p + 1 < P ? ((uint64_t)(p + 1) * tot) / P : tot;
       {
@@ -1078,8 +1102,22 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
                  A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u};
         merge_segment(A, S, A.ckw + rb, A.cvw + rb, re - rb, 0, okp, ovp, s + 1, true, false, R,
                       tn, tn, s + 1, true);
+        nout2 = S.red[0];
+        if (two_rs) {
+          // the second AB2 term of step s+1 from this range's slice of N(s) (tot_prev keys)
+          if (t == 0) {
+            S.red[2] = p == 0 ? 0 : lower_bound_glb(A.pkw, tot_prev, S.split[p], true);
+            S.red[3] = p + 1 < P ? lower_bound_glb(A.pkw, tot_prev, S.split[p + 1], true)
+                                 : tot_prev;
+          }
+          __syncthreads();
+          const uint64_t sb = S.red[2], se = S.red[3];
+          __syncthreads();
+          const LTable tnB = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tabB));
+          advance(A, S, R, tnB, A.qshiftB, 1u, A.pkw + sb, A.pvw + sb, 0, se - sb, s + 1, true);
+          __syncthreads();
+        }
       }
-      const uint64_t nout2 = S.red[0];
       np_next = nout2 <= A.segcap ? nout2 : 0;
       if (t == 0) A.seg_n[ob * P + p] = (uint32_t)np_next;
       ++epoch;
@@ -1214,6 +1252,8 @@ PersistArgs make_args(const PersistLaunch* L) {
   a.cur = L->cur;
   a.pk_prev = L->pk_prev;
   a.pv_prev = L->pv_prev;
+  a.pkw = L->pk_prev;
+  a.pvw = L->pv_prev;
   a.nbuf = L->nbuf;
   a.tabB_off = L->tabB_off;
   a.n_circuits = L->n_circuits;

@@ -119,11 +119,21 @@ def test_ab2_ghz20_nm_full_size(B, orc, path):
     w = W.config_ghz20_nm()
     _say(f"AB2 {w.name}: full size, {path}")
     g, o = _pair(B, orc, w, 1 << 17, 1 << 20, path)
+    g.profile("fused")
     for k0 in range(0, w.nsteps, 250):
         g.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250])
         o.step(w.s[k0:k0 + 250], w.gamma[k0:k0 + 250], threads=16)
         _assert_same(g, o, w.n_replicas, f"step {k0 + 250}")
         _say(f"  step {k0 + 250} equal")
+    _, launches, _ = g.profile_read()
+    reb = g.counters()["rebalances"]
+    _say(f"  fused launches {launches}, key-range re-cuts {reb}")
+    if path == "auto":
+        # the re-cuts happen inside the launches: one per call (the first call also runs the
+        # Euler first step on its own)
+        assert reb > 0 and launches <= w.nsteps // 250 + 1
+    else:
+        assert reb == 0 and launches == 0
 
 
 @pytest.mark.parametrize("path", PATHS)

@@ -198,45 +198,9 @@ __device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv,
     }
   const uint64_t St = S ? S : nch;
   const uint32_t rep = kl.replica(ck);
-  for (uint32_t k = 0; k < pr.k; ++k) {
-    uint32_t q[4] = {0, 0, 0, 0};
-    if (act) walker_random(key, step, rep, seed, 0x40u + k, q);
-    const uint64_t u = q[0];
-    uint32_t ch = 0;
-    uint64_t C = 0, P = 1;
-    if (act) {
-      if (pr.kind == 1) {
-        const uint64_t P0 = F + M / nch;
-        ch = (uint32_t)(u / P0);
-        if (ch > nch - 1) ch = nch - 1;
-        C = (uint64_t)ch * P0;
-        P = ch + 1 < nch ? P0 : T32 - C;
-      } else {
-        bool found = false;
-        for (uint32_t g = 1; g < G && !found; ++g) {
-          uint64_t wr, wi;
-          weights(g, wr, wi);
-          for (uint32_t comp = 0; comp < 2 && !found; ++comp) {
-            const uint32_t c2 = 2 * (g - 1) + comp;
-            if (c2 + 1 == nch) {
-              ch = c2;
-              P = T32 - C;
-              found = true;
-            } else {
-              const uint64_t w = S ? (comp ? wi : wr) : 1ull;
-              const uint64_t p = F + (w * M) / St;
-              if (u < C + p) {
-                ch = c2;
-                P = p;
-                found = true;
-              } else {
-                C += p;
-              }
-            }
-          }
-        }
-      }
-    }
+  // The draws of one sample: channel ch with interval [C, C + P) holding u, and its record.
+  auto emit_draw = [&](uint32_t ch, uint64_t C, uint64_t P, uint64_t u, uint32_t j)
+      __attribute__((always_inline)) {
     const uint32_t g = act ? 1 + ch / 2 : 1u;
     int2 rec = make_int2(0, 0);
     bool over = false;
@@ -247,7 +211,7 @@ __device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv,
       cmul_q32(v.x, v.y, cre, cim, xre, xim);
       const int64_t x = (ch & 1u) ? xim : xre;
       const uint64_t a = uabs64(x), D = (uint64_t)pr.k * P;
-      const uint64_t U = (uint64_t)(q[1] & (pr.k - 1)) * P + (u - C);
+      const uint64_t U = (uint64_t)(j & (pr.k - 1)) * P + (u - C);
       const uint64_t m = a / D + (U < a % D ? 1u : 0u);
       if (m > 0x7FFFFFFFull) {
         over = true;
@@ -258,6 +222,62 @@ __device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv,
     }
     if (over) em.overflow();
     em.emit((rec.x | rec.y) != 0, kl.rkey(ck ^ (act ? tv.gx[g] : 0ull), sab), rec);
+  };
+  if (pr.kind == 1) {
+    const uint64_t P0 = F + M / nch;
+    for (uint32_t k = 0; k < pr.k; ++k) {
+      uint32_t q[4] = {0, 0, 0, 0};
+      if (act) walker_random(key, step, rep, seed, 0x40u + k, q);
+      uint32_t ch = (uint32_t)((uint64_t)q[0] / P0);
+      if (ch > nch - 1) ch = nch - 1;
+      const uint64_t C = (uint64_t)ch * P0;
+      emit_draw(ch, C, ch + 1 < nch ? P0 : T32 - C, q[0], q[1]);
+    }
+    return;
+  }
+  // Weighted proposals: the samples in blocks of kSamp, each block's channels found in one scan
+  // over the groups (the thresholds are recomputed from the weights on the way).
+  constexpr int kSamp = 8;
+  for (uint32_t k0 = 0; k0 < pr.k; k0 += kSamp) {
+    uint32_t su[kSamp], sj[kSamp], sch[kSamp];
+    uint64_t sC[kSamp], sP[kSamp];
+    bool sf[kSamp];
+#pragma unroll
+    for (int b = 0; b < kSamp; ++b) {
+      uint32_t q[4] = {0, 0, 0, 0};
+      if (act && k0 + b < pr.k) walker_random(key, step, rep, seed, 0x40u + k0 + b, q);
+      su[b] = q[0];
+      sj[b] = q[1];
+      sch[b] = 0;
+      sC[b] = 0;
+      sP[b] = 1;
+      sf[b] = !(act && k0 + b < pr.k);
+    }
+    if (act) {
+      uint64_t C = 0;
+      for (uint32_t g = 1; g < G; ++g) {
+        uint64_t wr, wi;
+        weights(g, wr, wi);
+#pragma unroll
+        for (uint32_t comp = 0; comp < 2; ++comp) {
+          const uint32_t c2 = 2 * (g - 1) + comp;
+          const uint64_t w = S ? (comp ? wi : wr) : 1ull;
+          const uint64_t p = c2 + 1 == nch ? T32 - C : F + (w * M) / St;
+#pragma unroll
+          for (int b = 0; b < kSamp; ++b)
+            if (!sf[b] && (uint64_t)su[b] < C + p) {
+              sch[b] = c2;
+              sC[b] = C;
+              sP[b] = p;
+              sf[b] = true;
+            }
+          C += p;
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kSamp; ++b)
+      if (k0 + b < pr.k) emit_draw(sch[b], sC[b], sP[b], su[b], sj[b]);
   }
 }
 

@@ -152,6 +152,9 @@ def main():
                 if args.initiator_xi else 0)
     g.set_initiator(init_min)
     init = [g.export(r) for r in range(w.n_replicas)]
+    # the sort tile of the streamed path, autotuned where that path carries the run
+    sort_tile = g.tune_sort(0 if (args.path == "streamed" or args.proposal != "comb" or
+                                  DOMINANT[args.workload] != "fused") else 16)
     prop, train_corr = None, None
     if args.proposal != "comb":
         mlp = None
@@ -220,6 +223,7 @@ def main():
             "initiator": ({"xi": args.initiator_xi, "min_walkers": init_min}
                           if init_min else None),
             "parallelism": "1 GPU, replicas batched in one store",
+            "sort_tile_records_per_thread": sort_tile,
         },
         "key_steps_per_s": key_steps / elapsed,
         "roofline": {
@@ -291,6 +295,7 @@ def main_batch(args, kind):
                           store_capacity=1 << 18, spawn_capacity=1 << 18)
     g.set_path(args.path)
     init = [g.export(r) for r in range(g.R)]
+    sort_tile = g.tune_sort(0)   # the streamed path carries most of this run
     g.run_batch_workload(bw, 0, Wm)
     for r in range(g.R):
         g.import_(r, *init[r], step=0)
@@ -323,7 +328,8 @@ def main_batch(args, kind):
                                f"1e4..1e6, dt={bw.dt}, {bw.nsteps} steps",
                    "circuits": len(bw.circuits), "replicas": bw.n_replicas, "dt": bw.dt,
                    "steps_timed": K, "step_path": args.path,
-                   "parallelism": "1 GPU, all circuits and replicas in one store"},
+                   "parallelism": "1 GPU, all circuits and replicas in one store",
+                   "sort_tile_records_per_thread": sort_tile},
         "key_steps_per_s": (st1["key_steps"] - st0["key_steps"]) / elapsed,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[kind], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -205,6 +205,16 @@ int qmc_set_proposal(qmc_ctx* ctx, int32_t kind, uint32_t samples, const int8_t*
                      const int32_t* b1, const int8_t* w2, const int32_t* b2,
                      uint32_t hidden_shift);
 
+/* Tile size of the streamed path's radix sort of child records (records per thread of a
+ * 256-thread tile: 8, 12, 16 or 24; 16 by default).  records_per_thread = 0 autotunes: every size
+ * is timed three times on synthetic records of this context's composite-key width and spawn
+ * capacity (at most 4M records) in the child buffers, and the fastest is kept; nonzero sets it.
+ * The sorted order, and so every result, is the same for every size.  *chosen (may be NULL)
+ * receives the size in use.  Call between steps (the child buffers are scratch then).  Errors:
+ * QMC_ERR_ARG for an unsupported size; QMC_ERR_HIP if a timing run fails (the context is then
+ * unusable). */
+int qmc_tune_sort(qmc_ctx* ctx, uint32_t records_per_thread, uint32_t* chosen);
+
 typedef struct {
   uint32_t n_pauli;          /* observables P = X^px Z^pz: sum_i (-1)^popc(pz&i) N_{i,i^px} */
   const uint64_t* px;

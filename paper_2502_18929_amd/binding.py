@@ -25,7 +25,7 @@ QMC_ERR_STATE = -8
 
 EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_set_integrator", "qmc_set_prev", "qmc_export_prev", "qmc_pulse",
-            "qmc_set_shift", "qmc_set_initiator", "qmc_set_proposal", "qmc_observe",
+            "qmc_set_shift", "qmc_set_initiator", "qmc_set_proposal", "qmc_tune_sort", "qmc_observe",
             "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
             "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch"]
@@ -100,6 +100,7 @@ def lib():
         L.qmc_set_initiator.argtypes = [vp, ctypes.c_uint64]
         i8p = P(ctypes.c_int8)
         L.qmc_set_proposal.argtypes = [vp, i32, u32, i8p, P(i32), i8p, P(i32), u32]
+        L.qmc_tune_sort.argtypes = [vp, u32, P(u32)]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
         L.qmc_export.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.qmc_import.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, u32]
@@ -295,6 +296,13 @@ class QMC:
         """Initiator approximation: parents with |re| + |im| < min_walkers spawn only onto keys
         occupied in N(s); 0 = off.  initiator_threshold(xi, n_diag) gives ceil(xi * N^diag)."""
         self._check(lib().qmc_set_initiator(self._ctx, int(min_walkers)))
+
+    def tune_sort(self, records_per_thread=0):
+        """Sort tile size of the streamed path: 0 autotunes (times 8, 12, 16, 24 records per
+        thread and keeps the fastest), else sets it.  Returns the size in use."""
+        out = ctypes.c_uint32()
+        self._check(lib().qmc_tune_sort(self._ctx, int(records_per_thread), ctypes.byref(out)))
+        return int(out.value)
 
     PROPOSALS = {"comb": 0, "uniform": 1, "heatbath": 2, "mlp": 3}
 

@@ -30,6 +30,9 @@ constexpr size_t kTableArea = 32u << 20;  // device bytes for the step tables of
 constexpr size_t kMlpW1 = (size_t)kPropHidden * kPropIn, kMlpB1 = (size_t)kPropHidden * 4,
                  kMlpW2 = (size_t)kPropOut * kPropHidden, kMlpB2 = (size_t)kPropOut * 4;
 constexpr size_t kMlpBytes = kMlpW1 + kMlpB1 + kMlpW2 + kMlpB2;
+// sort tiles: kBlock x (8, 12, 16 or 24) records; 16 unless qmc_tune_sort picks another
+constexpr uint64_t kSortTileMin = (uint64_t)qmc::kBlock * 8;
+constexpr uint32_t kSortIpts[] = {8, 12, 16, 24};
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
@@ -79,7 +82,8 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   // the child buffers hold one step's children, or the whole store when a pulse with x != 0
   // re-sorts it
   L.cap_sort = std::max(S, C);
-  L.n_sort_status = ((L.cap_sort + qmc::kSortTile - 1) / qmc::kSortTile) * qmc::kRadixBins;
+  // look-back status words of the sort, (tile, digit), for the smallest tile it can use
+  L.n_sort_status = ((L.cap_sort + kSortTileMin - 1) / kSortTileMin) * qmc::kRadixBins;
   L.max_tiles = (S + C + qmc::kMergeTile - 1) / qmc::kMergeTile;
   L.P = P;
   L.segcap = std::max<uint64_t>(4096, (2 * S + P - 1) / P);
@@ -162,6 +166,7 @@ struct qmc_ctx {
   int32_t integrator = 0;           // 0 Euler, 1 AB2
   uint64_t init_min = 0;            // initiator threshold in walkers (0 = off)
   QmcProposal prop{};               // spawn proposal (kind 0: the comb); weights on the device
+  uint32_t sort_ipt = 16;           // records per thread of a sort tile
   bool have_prev = false;           // AB2: N(s-1) (device) and w_prev are valid
   std::vector<double> w_prev;       // AB2: weights of step s-1 (s then gamma)
   uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
@@ -845,7 +850,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     HIPCHK(c, mark(1, k, 0));
     HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
                         c->ghist(csel), c->at<uint64_t>(c->L.sort_status), st, cb,
-                        c->L.cap_child));
+                        c->L.cap_child, c->sort_ipt));
     HIPCHK(c, mark(1, k, 1));
     const uint32_t cf = cb ^ (passes & 1);  // sorted children
     HIPCHK(c, mark(2, k, 0));
@@ -1228,7 +1233,7 @@ int qmc_pulse_batch(qmc_ctx* c, const uint64_t* x, const uint64_t* z) {
     HIPCHK(c, qmck_digit_hist(c->stream, c->ck(0), dcnt, 0, passes, c->ghist(0), c->L.cap_store));
     HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, 0, passes,
                         c->ghist(0), c->at<uint64_t>(c->L.sort_status), c->step, 0,
-                        c->L.cap_sort));
+                        c->L.cap_sort, c->sort_ipt));
     const uint32_t out = passes & 1;
     HIPCHK(c, qmck_copy_store(c->stream, c->ck(out), c->cv(out), c->sk(c->cur), c->sv(c->cur),
                               &dcnt->n_child[0], c->L.cap_store));
@@ -1283,6 +1288,85 @@ int qmc_set_proposal(qmc_ctx* c, int32_t kind, uint32_t samples, const int8_t* w
     p.b2 = reinterpret_cast<const int32_t*>(d + kMlpW1 + kMlpB1 + kMlpW2);
   }
   c->prop = p;
+  return QMC_OK;
+}
+
+int qmc_tune_sort(qmc_ctx* c, uint32_t records_per_thread, uint32_t* chosen) {
+  if (!c) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (records_per_thread != 0) {
+    if (!qmck_sort_tile_ok(records_per_thread))
+      return fail(c, QMC_ERR_ARG, "sort tiles take 8, 12, 16 or 24 records per thread");
+    c->sort_ipt = records_per_thread;
+    if (chosen) *chosen = c->sort_ipt;
+    return QMC_OK;
+  }
+  // Autotune: time every tile size on synthetic records of this context's key width and spawn
+  // capacity (at most 4M records) in the child buffers, which hold nothing between calls, and
+  // keep the fastest.  The sorted order does not depend on the tile size.
+  qmc::Counters* dcnt = c->counters();
+  const uint64_t n = std::min<uint64_t>(c->L.cap_child, 1ull << 22);
+  const uint32_t bits = c->kbits + c->rbits + (c->init_min ? 1u : 0u);
+  const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
+  const uint32_t passes = qmck_sort_passes(bits);
+  uint64_t* pin_n = reinterpret_cast<uint64_t*>(c->pinned_small + 2048);
+  *pin_n = n;
+  hipEvent_t ev[2];
+  HIPCHK(c, hipEventCreate(&ev[0]));
+  HIPCHK(c, hipEventCreate(&ev[1]));
+  uint32_t best = c->sort_ipt;
+  float best_ms = 0.f;
+  int rc = QMC_OK;
+  for (uint32_t ipt : kSortIpts) {
+    float fastest = 0.f;
+    for (int rep = 0; rep < 3 && rc == QMC_OK; ++rep) {
+      hipError_t e = (hipError_t)qmck_batch_begin(
+          c->stream, dcnt, nullptr, 0, c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status,
+          c->ghist(0), 2 * qmc::kMaxPasses * qmc::kRadixBins);
+      if (e == hipSuccess)
+        e = (hipError_t)qmck_fill_sort_probe(c->stream, c->ck(0), c->cv(0), n, mask, 77 + rep);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&dcnt->n_child[0], pin_n, 8, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = (hipError_t)qmck_digit_hist(c->stream, c->ck(0), dcnt, 0, passes, c->ghist(0), n);
+      if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+      if (e == hipSuccess)
+        e = (hipError_t)qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, 0,
+                                  passes, c->ghist(0), c->at<uint64_t>(c->L.sort_status), c->step,
+                                  0, n, ipt);
+      if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e != hipSuccess) {
+        c->broken = true;
+        rc = fail(c, QMC_ERR_HIP, std::string("sort tuning: ") + hipGetErrorString(e));
+        break;
+      }
+      if (rep == 0 || ms < fastest) fastest = ms;
+    }
+    if (rc) break;
+    if (best_ms == 0.f || fastest < best_ms) {
+      best_ms = fastest;
+      best = ipt;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc) return rc;
+  qmc::Counters hc;
+  rc = read_counters(c, hc);
+  if (rc) return rc;
+  if (hc.err) {
+    c->broken = true;
+    return fail(c, QMC_ERR_HIP, "sort tuning raised a device error");
+  }
+  // leave the counters as a step expects them
+  HIPCHK(c, qmck_batch_begin(c->stream, dcnt, nullptr, 0, c->at<uint64_t>(c->L.sort_status),
+                             c->L.n_sort_status, c->ghist(0),
+                             2 * qmc::kMaxPasses * qmc::kRadixBins));
+  c->sort_ipt = best;
+  if (chosen) *chosen = best;
   return QMC_OK;
 }
 

@@ -40,7 +40,12 @@ int qmck_digit_hist(hipStream_t st, const uint64_t* keys, void* counters, uint32
                     uint32_t passes, uint32_t* ghist, uint64_t max_items);
 int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
               uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint64_t* sort_status,
-              uint32_t step, uint32_t src, uint64_t max_items);
+              uint32_t step, uint32_t src, uint64_t max_items, uint32_t ipt);
+// Records per thread of a sort tile that qmck_sort supports (8, 12, 16, 24): nonzero if ok.
+int qmck_sort_tile_ok(uint32_t ipt);
+// n synthetic records (keys masked to `mask`, values (1, 0)) for timing the sort.
+int qmck_fill_sort_probe(hipStream_t st, uint64_t* k, int2* v, uint64_t n, uint64_t mask,
+                         uint64_t salt);
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
                uint64_t* status, const uint8_t* tab_base, const uint32_t* toff_next,

@@ -424,8 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_digit_hist(const uint64_t* __restric
 }
 
 // ---------------------------------------------------------------------------------------------
-// k_onesweep: one LSD radix pass.  Tiles of kSortTile records are taken in order from a ticket
-// counter; wave w of a block ranks records [w*1024, (w+1)*1024) of the tile stably in LDS; the
+// k_onesweep: one LSD radix pass.  Tiles of kBlock * IPT records are taken in order from a ticket
+// counter; wave w of a block ranks records [w*64*IPT, (w+1)*64*IPT) of the tile stably in LDS; the
 // tile's per-digit counts are published and the exclusive prefix over earlier tiles is found by
 // decoupled look-back (Merrill & Garland), one status word per (tile, digit).
 // ---------------------------------------------------------------------------------------------
@@ -501,12 +501,14 @@ __device__ uint32_t merge_path_wave(const KA& A, uint32_t na, const KB& B, uint3
   return lo + (uint32_t)__popcll(__ballot(t));
 }
 
+template <int IPT>
 __global__ __launch_bounds__(kBlock) void k_onesweep(
     const uint64_t* __restrict__ kin, const int2* __restrict__ vin, uint64_t* __restrict__ kout,
     int2* __restrict__ vout, Counters* __restrict__ cnt, uint32_t nsel, uint32_t pass,
     const uint32_t* __restrict__ ghist, uint64_t* __restrict__ status, uint32_t epoch,
     uint32_t step) {
   constexpr int DPT = kRadixBins / kBlock;  // digits per thread
+  constexpr int TILE = kBlock * IPT;        // records per tile
   __shared__ uint32_t s_gbase[kRadixBins];
   __shared__ uint32_t s_wcnt[kWaves][kRadixBins];
   __shared__ uint32_t s_pref[kRadixBins];
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
   __shared__ uint32_t s_tile;
   if (cnt->err) return;
   const uint64_t n = cnt->n_child[nsel];
-  const uint32_t ntiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  const uint32_t ntiles = (uint32_t)((n + TILE - 1) / TILE);
   const uint32_t shift = pass * kRadixBits;
   const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = __lane_id();
   const uint32_t* gh = ghist + pass * kRadixBins;
@@ -559,12 +561,12 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) break;
-    const uint64_t tbase = (uint64_t)tile * kSortTile + (uint64_t)wave * (kSortIpt * kWave);
-    uint64_t key[kSortIpt];
-    int2 val[kSortIpt];
-    uint32_t rk[kSortIpt];
+    const uint64_t tbase = (uint64_t)tile * TILE + (uint64_t)wave * (IPT * kWave);
+    uint64_t key[IPT];
+    int2 val[IPT];
+    uint32_t rk[IPT];
 #pragma unroll
-    for (int k = 0; k < kSortIpt; ++k) {
+    for (int k = 0; k < IPT; ++k) {
       const uint64_t i = tbase + (uint64_t)k * kWave + lane;
       const bool v = i < n;
       key[k] = v ? kin[i] : 0;
@@ -641,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
     for (int i = 0; i < DPT; ++i) s_pref[tid * DPT + i] = s_gbase[tid * DPT + i] + pref[i];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kSortIpt; ++k) {
+    for (int k = 0; k < IPT; ++k) {
       const uint64_t i = tbase + (uint64_t)k * kWave + lane;
       if (i < n) {
         const uint32_t d = digit_of(key[k], shift);
@@ -1345,21 +1347,72 @@ int qmck_digit_hist(hipStream_t st, const uint64_t* keys, void* counters, uint32
 
 // Sorts n_child[nsel] records found in buffer pair `src` (0/1 of (k0,v0)/(k1,v1)); the result
 // lands in pair src ^ (passes & 1).
-int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
-              uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint64_t* sort_status,
-              uint32_t step, uint32_t src, uint64_t max_items) {
-  uint64_t* kb[2] = {k0, k1};
-  int2* vb[2] = {v0, v1};
-  const uint64_t max_tiles = (max_items + kSortTile - 1) / kSortTile;
+int qmck_sort_tile_ok(uint32_t ipt) {
+  return ipt == 8 || ipt == 12 || ipt == 16 || ipt == 24;
+}
+
+extern "C++" template <int IPT>
+static void sort_passes(hipStream_t st, uint64_t* const* kb, int2* const* vb, void* counters,
+                        uint32_t nsel, uint32_t passes, const uint32_t* ghist,
+                        uint64_t* sort_status, uint32_t step, uint32_t src, uint64_t max_items) {
+  const uint64_t tile = (uint64_t)kBlock * IPT;
+  const uint64_t max_tiles = (max_items + tile - 1) / tile;
   const uint32_t g = (uint32_t)(max_tiles < (uint64_t)kPersistBlocks ? (max_tiles ? max_tiles : 1)
                                                                        : kPersistBlocks);
   uint32_t s = src;
   for (uint32_t p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_onesweep, dim3(g), dim3(kBlock), 0, st, kb[s], vb[s], kb[s ^ 1],
+    hipLaunchKernelGGL(k_onesweep<IPT>, dim3(g), dim3(kBlock), 0, st, kb[s], vb[s], kb[s ^ 1],
                        vb[s ^ 1], (Counters*)counters, nsel, p, ghist, sort_status,
                        sort_epoch(step, p), step);
     s ^= 1;
   }
+}
+
+int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
+              uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint64_t* sort_status,
+              uint32_t step, uint32_t src, uint64_t max_items, uint32_t ipt) {
+  uint64_t* kb[2] = {k0, k1};
+  int2* vb[2] = {v0, v1};
+  switch (ipt) {
+    case 8:
+      sort_passes<8>(st, kb, vb, counters, nsel, passes, ghist, sort_status, step, src, max_items);
+      break;
+    case 12:
+      sort_passes<12>(st, kb, vb, counters, nsel, passes, ghist, sort_status, step, src,
+                      max_items);
+      break;
+    case 24:
+      sort_passes<24>(st, kb, vb, counters, nsel, passes, ghist, sort_status, step, src,
+                      max_items);
+      break;
+    default:
+      sort_passes<16>(st, kb, vb, counters, nsel, passes, ghist, sort_status, step, src,
+                      max_items);
+      break;
+  }
+  return (int)hipGetLastError();
+}
+
+// Synthetic records for timing the sort: keys from a 64-bit mix of the index (the splitmix64
+// finalizer), masked to the composite-key bits, value (1, 0).
+__global__ __launch_bounds__(kBlock) void k_fill_sort_probe(uint64_t* __restrict__ k,
+                                                            int2* __restrict__ v, uint64_t n,
+                                                            uint64_t mask, uint64_t salt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock) {
+    uint64_t z = (i + salt) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    k[i] = z & mask;
+    v[i] = make_int2(1, 0);
+  }
+}
+
+int qmck_fill_sort_probe(hipStream_t st, uint64_t* k, int2* v, uint64_t n, uint64_t mask,
+                         uint64_t salt) {
+  hipLaunchKernelGGL(k_fill_sort_probe, dim3(grid_for(n, 2048)), dim3(kBlock), 0, st, k, v, n,
+                     mask, salt);
   return (int)hipGetLastError();
 }
 

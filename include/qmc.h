@@ -215,6 +215,13 @@ int qmc_set_proposal(qmc_ctx* ctx, int32_t kind, uint32_t samples, const int8_t*
  * unusable). */
 int qmc_tune_sort(qmc_ctx* ctx, uint32_t records_per_thread, uint32_t* chosen);
 
+/* Streamed chunks as HIP graphs: with on = 1 every chunk of streamed steps (spawn, and per step
+ * the sort passes, merge split points and merge) is captured from the context's stream into a
+ * graph; the executable graph of the previous chunk is updated with it when the launches are
+ * the same (only arguments changed), else a new one is instantiated; then it is launched.  The
+ * results are identical; profiling (qmc_profile) runs the chunks eagerly.  Default 0. */
+int qmc_use_graphs(qmc_ctx* ctx, int32_t on);
+
 typedef struct {
   uint32_t n_pauli;          /* observables P = X^px Z^pz: sum_i (-1)^popc(pz&i) N_{i,i^px} */
   const uint64_t* px;

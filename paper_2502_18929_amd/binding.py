@@ -25,7 +25,8 @@ QMC_ERR_STATE = -8
 
 EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_set_integrator", "qmc_set_prev", "qmc_export_prev", "qmc_pulse",
-            "qmc_set_shift", "qmc_set_initiator", "qmc_set_proposal", "qmc_tune_sort", "qmc_observe",
+            "qmc_set_shift", "qmc_set_initiator", "qmc_set_proposal", "qmc_tune_sort",
+            "qmc_use_graphs", "qmc_observe",
             "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
             "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch"]
@@ -101,6 +102,7 @@ def lib():
         i8p = P(ctypes.c_int8)
         L.qmc_set_proposal.argtypes = [vp, i32, u32, i8p, P(i32), i8p, P(i32), u32]
         L.qmc_tune_sort.argtypes = [vp, u32, P(u32)]
+        L.qmc_use_graphs.argtypes = [vp, i32]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
         L.qmc_export.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.qmc_import.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, u32]
@@ -296,6 +298,10 @@ class QMC:
         """Initiator approximation: parents with |re| + |im| < min_walkers spawn only onto keys
         occupied in N(s); 0 = off.  initiator_threshold(xi, n_diag) gives ceil(xi * N^diag)."""
         self._check(lib().qmc_set_initiator(self._ctx, int(min_walkers)))
+
+    def use_graphs(self, on=True):
+        """Capture each chunk of streamed steps into a HIP graph and replay it."""
+        self._check(lib().qmc_use_graphs(self._ctx, 1 if on else 0))
 
     def tune_sort(self, records_per_thread=0):
         """Sort tile size of the streamed path: 0 autotunes (times 8, 12, 16, 24 records per

@@ -167,6 +167,9 @@ struct qmc_ctx {
   uint64_t init_min = 0;            // initiator threshold in walkers (0 = off)
   QmcProposal prop{};               // spawn proposal (kind 0: the comb); weights on the device
   uint32_t sort_ipt = 16;           // records per thread of a sort tile
+  bool use_graph = false;           // streamed chunks captured into a HIP graph and replayed
+  hipGraphExec_t gexec = nullptr;   // the executable graph of the last captured chunk
+  hipStream_t gstream = nullptr;    // the stream chunks are captured from (default priority)
   bool have_prev = false;           // AB2: N(s-1) (device) and w_prev are valid
   std::vector<double> w_prev;       // AB2: weights of step s-1 (s then gamma)
   uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
@@ -812,9 +815,6 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   const int64_t* qshA = c->at<int64_t>(c->L.qshift);
   const int64_t* qshB = qshA + c->R;
   const uint8_t* dtab = ch.dtab;
-  HIPCHK(c, qmck_batch_begin(c->stream, dcnt, c->at<uint64_t>(c->L.status), c->L.max_tiles,
-                             c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
-                             2 * qmc::kMaxPasses * qmc::kRadixBins));
   const uint32_t nev = 2 * nst;
   if (c->prof_class >= 0 && c->prof_class <= 2) {
     while (c->prof_ev.size() < nev) {
@@ -823,46 +823,96 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
       c->prof_ev.push_back(ev);
     }
   }
-  auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
-    if (c->prof_class != cls) return hipSuccess;
-    return hipEventRecord(c->prof_ev[2 * k + which], c->stream);
+  // Every launch of the chunk, in stream order; with graphs on they are captured instead.
+  auto enqueue = [&](hipStream_t st_q) -> hipError_t {
+#define ENQ(x)                                   \
+  do {                                           \
+    const hipError_t e_ = (hipError_t)(x);       \
+    if (e_ != hipSuccess) return e_;             \
+  } while (0)
+    ENQ(qmck_batch_begin(st_q, dcnt, c->at<uint64_t>(c->L.status), c->L.max_tiles,
+                               c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
+                               2 * qmc::kMaxPasses * qmc::kRadixBins));
+    auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
+      if (c->prof_class != cls) return hipSuccess;
+      return hipEventRecord(c->prof_ev[2 * k + which], st_q);
+    };
+    uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
+    ENQ(mark(0, 0, 0));
+    // device table offsets of step k of the chunk: [circuit] (A), and the AB2 B term
+    const uint32_t* dA = c->at<uint32_t>(c->L.tab_off) + (size_t)ch.first * c->C;
+    const uint32_t* dB = c->at<uint32_t>(c->L.tabB_off) + ch.first;
+    ENQ(qmck_spawn(st_q, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab, dA, c->Rc,
+                         step0, c->cfg.seed, c->kbits, c->init_min, 0u, qshA, c->ck(cb), c->cv(cb),
+                         c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes, &c->prop));
+    if (ch.two)
+      ENQ(qmck_spawn(st_q, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab, dB, c->Rc,
+                           step0, c->cfg.seed, c->kbits, c->init_min, 1u, qshB, c->ck(cb),
+                           c->cv(cb),
+                           c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes, nullptr));
+    ENQ(mark(0, 0, 1));
+    for (uint32_t k = 0; k < nst; ++k) {
+      const uint32_t st = step0 + k, b = k % nb, cur = cur0 ^ (k & 1u);
+      const bool more = k + 1 < nst;
+      const uint32_t* toff_next = more ? dA + (size_t)(k + 1) * c->C : nullptr;
+      const uint32_t* toffB_next = more && c->integrator == 1 ? dB + (k + 1) : nullptr;
+      const uint32_t csel = st & 1;
+      ENQ(mark(1, k, 0));
+      ENQ(qmck_sort(st_q, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
+                          c->ghist(csel), c->at<uint64_t>(c->L.sort_status), st, cb,
+                          c->L.cap_child, c->sort_ipt));
+      ENQ(mark(1, k, 1));
+      const uint32_t cf = cb ^ (passes & 1);  // sorted children
+      ENQ(mark(2, k, 0));
+      ENQ(qmck_merge(st_q, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
+                           c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), dtab,
+                           toff_next, toffB_next, c->Rc, qshA, qshB, st, c->cfg.seed, c->kbits, c->init_min,
+                           bk[(k + 1) % nb],
+                           bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
+                           c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
+                           passes, &c->prop));
+      ENQ(mark(2, k, 1));
+      cb = cf ^ 1;
+    }
+#undef ENQ
+    return hipSuccess;
   };
-  uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
-  HIPCHK(c, mark(0, 0, 0));
-  // device table offsets of step k of the chunk: [circuit] (A), and the AB2 B term
-  const uint32_t* dA = c->at<uint32_t>(c->L.tab_off) + (size_t)ch.first * c->C;
-  const uint32_t* dB = c->at<uint32_t>(c->L.tabB_off) + ch.first;
-  HIPCHK(c, qmck_spawn(c->stream, bk[0], bv[0], dcnt, &dcnt->n_store[cur0], dtab, dA, c->Rc,
-                       step0, c->cfg.seed, c->kbits, c->init_min, 0u, qshA, c->ck(cb), c->cv(cb),
-                       c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes, &c->prop));
-  if (ch.two)
-    HIPCHK(c, qmck_spawn(c->stream, c->pk(), c->pv(), dcnt, &dcnt->n_prev, dtab, dB, c->Rc,
-                         step0, c->cfg.seed, c->kbits, c->init_min, 1u, qshB, c->ck(cb),
-                         c->cv(cb),
-                         c->L.cap_child, c->L.cap_store, c->ghist(step0 & 1), passes, nullptr));
-  HIPCHK(c, mark(0, 0, 1));
-  for (uint32_t k = 0; k < nst; ++k) {
-    const uint32_t st = step0 + k, b = k % nb, cur = cur0 ^ (k & 1u);
-    const bool more = k + 1 < nst;
-    const uint32_t* toff_next = more ? dA + (size_t)(k + 1) * c->C : nullptr;
-    const uint32_t* toffB_next = more && c->integrator == 1 ? dB + (k + 1) : nullptr;
-    const uint32_t csel = st & 1;
-    HIPCHK(c, mark(1, k, 0));
-    HIPCHK(c, qmck_sort(c->stream, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
-                        c->ghist(csel), c->at<uint64_t>(c->L.sort_status), st, cb,
-                        c->L.cap_child, c->sort_ipt));
-    HIPCHK(c, mark(1, k, 1));
-    const uint32_t cf = cb ^ (passes & 1);  // sorted children
-    HIPCHK(c, mark(2, k, 0));
-    HIPCHK(c, qmck_merge(c->stream, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
-                         c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), dtab,
-                         toff_next, toffB_next, c->Rc, qshA, qshB, st, c->cfg.seed, c->kbits, c->init_min,
-                         bk[(k + 1) % nb],
-                         bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
-                         c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
-                         passes, &c->prop));
-    HIPCHK(c, mark(2, k, 1));
-    cb = cf ^ 1;
+  const bool graph = c->use_graph && c->prof_class < 0;
+  if (!graph) {
+    HIPCHK(c, enqueue(c->stream));
+  } else {
+    // Capture the chunk on a stream of its own (the context's stream may be the null stream,
+    // which cannot be captured), update the executable graph of the previous chunk with it (same
+    // launches, new arguments) or instantiate a new one, and launch it on the context's stream.
+    if (!c->gstream) HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
+    const hipError_t eq = enqueue(c->gstream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->gstream, &g);
+    if (eq != hipSuccess || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      c->broken = true;
+      return fail(c, QMC_ERR_HIP, std::string("graph capture: ") +
+                                      hipGetErrorString(eq != hipSuccess ? eq : ec));
+    }
+    if (c->gexec) {
+      hipGraphNode_t bad = nullptr;
+      hipGraphExecUpdateResult res;
+      if (hipGraphExecUpdate(c->gexec, g, &bad, &res) != hipSuccess ||
+          res != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+      }
+    }
+    hipError_t el = hipSuccess;
+    if (!c->gexec) el = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (el == hipSuccess) el = hipGraphLaunch(c->gexec, c->stream);
+    if (el != hipSuccess) {
+      c->broken = true;
+      return fail(c, QMC_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(el));
+    }
   }
   int rc = read_counters(c, hc);
   if (rc) return rc;
@@ -1288,6 +1338,13 @@ int qmc_set_proposal(qmc_ctx* c, int32_t kind, uint32_t samples, const int8_t* w
     p.b2 = reinterpret_cast<const int32_t*>(d + kMlpW1 + kMlpB1 + kMlpW2);
   }
   c->prop = p;
+  return QMC_OK;
+}
+
+int qmc_use_graphs(qmc_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  c->use_graph = on != 0;
   return QMC_OK;
 }
 
@@ -1727,6 +1784,8 @@ void qmc_destroy(qmc_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->pinned_small) (void)hipHostFree(c->pinned_small);
   delete c;
 }

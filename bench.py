@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--proposal-samples", type=int, default=4,
                     help="channel draws per parent under a proposal (a power of two)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--progress", type=int, default=0,
+                    help="print a line to stderr after every this many timed steps (runs the "
+                         "timed region in calls of that many steps; 0: one call)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -185,7 +188,12 @@ def main():
     g.profile(kind)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.run_workload(w, 0, K)
+    if args.progress > 0:
+        for a in range(0, K, args.progress):
+            g.run_workload(w, a, min(a + args.progress, K))
+            print(f"timed steps {a}..{min(a + args.progress, K)}", file=sys.stderr, flush=True)
+    else:
+        g.run_workload(w, 0, K)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = g.counters()

@@ -131,3 +131,48 @@ def test_batch_refuses_ab2_and_initiator(B):
     with pytest.raises(B.QMCError) as e:
         g.set_initiator(10)
     assert e.value.code == B.QMC_ERR_ARG
+
+
+def test_batch64_full_size_sampled_circuits(B, orc):
+    """The batched configuration at full size (64 circuits, 1000 steps, automatic path, sort tile
+    autotuned: the launch configuration of the benchmark): the four circuits with the smallest
+    walker targets, whose oracles finish in seconds, equal their oracles at steps 500 and 1000;
+    every other circuit's store is checked to be sorted, unique and free of empty records."""
+    bw = W.config_batch64()
+    R = bw.n_replicas
+    circuits = [(w.h, w.lops, w.init_keys, w.init_re, w.init_im) for w in bw.circuits]
+    _say(f"{bw.name}: n={bw.n}, {len(circuits)} circuits, {bw.nsteps} steps, automatic path")
+    g = B.QMC.batch(bw.n, R, bw.seed, bw.dt, circuits, store_capacity=1 << 18,
+                    spawn_capacity=1 << 18)
+    g.tune_sort(0)
+    pick = sorted(range(len(bw.circuits)),
+                  key=lambda c: (bw.circuits[c].walker_target, bw.circuits[c].n))[:4]
+    orcs = {}
+    for c in pick:
+        h, lops, keys, re, im = circuits[c]
+        o = orc.Oracle(bw.n, R, bw.seed, bw.dt, h, lops, keys, re, im)
+        o.set_replica_base(c * R)
+        orcs[c] = o
+    checkpoints = {500, bw.nsteps}
+    for a, b, masks in bw.segments():
+        cuts = sorted({a, b} | {x for x in checkpoints if a < x < b})
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            if lo == a and masks is not None:
+                g.pulse_batch(*masks)
+                for c, o in orcs.items():
+                    if masks[0][c] or masks[1][c]:
+                        o.pulse(int(masks[0][c]), int(masks[1][c]))
+            s, gam = bw.weights(lo, hi)
+            g.step(s, gam)
+            for c, o in orcs.items():
+                o.step(bw.circuits[c].s[lo:hi], bw.circuits[c].gamma[lo:hi])
+            if hi in checkpoints:
+                for c, o in orcs.items():
+                    for r in range(R):
+                        for x, y in zip(g.export(c * R + r), o.export(r)):
+                            assert np.array_equal(x, y), f"step {hi}: circuit {c} replica {r}"
+                _say(f"  step {hi}: circuits {pick} equal their oracles")
+    for seg in range(len(circuits) * R):
+        k, a, b = g.export(seg)
+        assert np.all(np.diff(k.astype(np.int64)) > 0) if len(k) > 1 else True
+        assert not np.any((a == 0) & (b == 0))

@@ -456,3 +456,28 @@ def test_long_call_table_error_names_first_step(B, orc, bad, code):
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
     assert g.counters()["step"] == 10
+
+
+def test_dd12_full_size_paths_agree(B):
+    """dd12 at full size, all 4000 steps (up to 121M keys), in the benchmark's launch
+    configuration (automatic path: fused while the store is small, then streamed with the
+    autotuned sort tile) against the streamed path alone with the default tile: every replica
+    identical, stores sorted, unique and free of empty records.  (The oracle follows dd12 over
+    its first 600 steps above; at 121M keys it would take hours.)"""
+    w = W.config_dd12()
+    _say(f"{w.name}: full size, {w.nsteps} steps, automatic vs streamed")
+    stores = []
+    for path, tune in [("auto", 0), ("streamed", 16)]:
+        g = B.QMC.from_workload(w, store_capacity=1 << 24, spawn_capacity=1 << 21)
+        g.set_path(path)
+        g.tune_sort(tune)
+        g.run_workload(w, 0, w.nsteps)
+        stores.append([g.export(r) for r in range(w.n_replicas)])
+        _say(f"  {path}: {g.counters()['n_occ']} keys at the end")
+        g.close()
+    for r in range(w.n_replicas):
+        ka, aa, ba = stores[0][r]
+        kb, ab, bb = stores[1][r]
+        assert np.array_equal(ka, kb) and np.array_equal(aa, ab) and np.array_equal(ba, bb), r
+        assert np.all(ka[1:] > ka[:-1])
+        assert not np.any((aa == 0) & (ba == 0))

@@ -850,28 +850,29 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     const uint32_t pa = s0.x, pn = s1.x - s0.x;
     const uint32_t ca = s0.y, cn = s1.y - s0.y;
 
-    // Parents (their death/cloning delta of this step arrived as a record among the children).
-    uint64_t wsum = 0;
-    for (uint32_t x = threadIdx.x; x < pn; x += kBlock) {
-      const uint64_t ck = A.pk[pa + x];
-      const int2 v = A.pv[pa + x];
-      wsum += uabs64(v.x) + uabs64(v.y);
-      s_pk[x] = ck;
-      s_pv[x] = v;
+    // Parents (their death/cloning delta of this step arrived as a record among the children)
+    // and the tile's records go straight from global memory to LDS (LDS-direct dword loads: a
+    // wave instruction moves 256 contiguous bytes, and no registers hold the data, so every load
+    // of the tile is in flight at once).
+    {
+      auto to_lds = [&](const void* src, void* dst, uint32_t ndw) __attribute__((always_inline)) {
+        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+        for (uint32_t c = wave; c * kWave < ndw; c += kWaves) {
+          const uint32_t x = c * kWave + lane;
+          if (x < ndw) __builtin_amdgcn_global_load_lds(s32 + x, d32 + c * kWave, 4, 0, 0);
+        }
+      };
+      to_lds(A.pk + pa, s_pk, 2 * pn);
+      to_lds(A.pv + pa, s_pv, 2 * pn);
+      to_lds(A.ckeys + ca, s_ck, 2 * cn);
+      to_lds(A.cvals + ca, s_cv, 2 * cn);
+      __builtin_amdgcn_s_waitcnt(0);
     }
-    for (uint32_t x = threadIdx.x; x < cn; x += kBlock) {
-      s_ck[x] = A.ckeys[ca + x];
-      s_cv[x] = A.cvals[ca + x];
-    }
-    for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
-    if (lane == 0) s_ws[wave] = wsum;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t t = 0;
-      for (int w = 0; w < kWaves; ++w) t += s_ws[w];
-      atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)t);
+    if (threadIdx.x == 0)
       atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)pn);
-    }
+    uint64_t wsum = 0;  // walker sum of the parents this thread's merge range holds
 
     // Per-thread ranges of the local merge, cut only at run ends.
     auto KA = [&](uint32_t x) { return s_pk[x]; };
@@ -910,6 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
           k = s_pk[i];
           re = s_pv[i].x;
           im = s_pv[i].y;
+          wsum += uabs64(re) + uabs64(im);
           hp = true;
           ++i;
         } else {
@@ -953,7 +955,14 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       if (lane >= (uint32_t)o) incl += x;
     }
     if (lane == kWave - 1) s_scan[wave] = incl;
+    for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+    if (lane == 0) s_ws[wave] = wsum;
     __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+      for (int w = 0; w < kWaves; ++w) t += s_ws[w];
+      atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)t);
+    }
     uint32_t wpre = 0, agg = 0;
     for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
       const uint32_t v = s_scan[x];

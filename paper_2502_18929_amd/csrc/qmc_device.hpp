@@ -29,6 +29,7 @@ constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
 constexpr int kMergeTicketCounters = 8;  // k_merge tile tickets: counter b mod 8 serves block b
 constexpr int kMergeBlocks = 768;    // k_merge: three workgroups per CU (about 51 KB of LDS each)
+constexpr int kMergeOnlyBlocks = 1536;  // a merge that does not spawn: six per CU (about 23 KB)
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
 constexpr int kMaxCircuits = kMaxSegments;  // circuits of one batch (each needs a key range)
 constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)

@@ -751,14 +751,19 @@ struct MergeArgs {
   QmcProposal prop;          // spawn proposal of step s+1 (kind 0: the comb)
 };
 
-template <bool kProp>
+// kSpawn: the merge also draws the records of step s+1 from its outputs (kProp: under a spawn
+// proposal); without it the kernel only merges (fewer registers and LDS per workgroup).
+template <bool kProp, bool kSpawn>
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   constexpr int CAP = kMergeCap;
+  constexpr int QCAP = kSpawn ? kMergeActive : 1;
   __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? kWave * kPropHidden : 4];
   __shared__ uint64_t s_pk[CAP];   // parents of the tile; then its annihilated records
   __shared__ int2 s_pv[CAP];
-  __shared__ uint64_t s_ck[CAP];   // children of the tile; later the spawn staging
-  __shared__ int2 s_cv[CAP];
+  // children of the tile (a merge that spawns also stages the next step's records here; one
+  // that does not keeps the children behind the parents in s_pk / s_pv)
+  __shared__ uint64_t s_ck_arr[kSpawn ? CAP : 1];
+  __shared__ int2 s_cv_arr[kSpawn ? CAP : 1];
   __shared__ uint32_t s_scan[kBlock];
   __shared__ uint32_t s_xsplit[kBlock];  // merge-path split of each thread: parent | child << 16
   __shared__ uint32_t s_tile;
@@ -766,9 +771,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   __shared__ uint64_t s_ws[kWaves];
   // Outputs that can spawn in step s+1, queued across tiles and spawned in full 64-lane batches
   // (a batch costs the same whatever its lane count, and sparse columns leave most lanes idle).
-  __shared__ uint64_t s_ak[kMergeActive];
-  __shared__ int2 s_av[kMergeActive];
-  __shared__ uint2 s_aw[kMergeActive];
+  __shared__ uint64_t s_ak[QCAP];
+  __shared__ int2 s_av[QCAP];
+  __shared__ uint2 s_aw[QCAP];
   static_assert(kWaves * kMergeSpawnSeg <= CAP, "spawn staging must fit the child tile");
 
   Counters* cnt = A.cnt;
@@ -788,7 +793,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   // then moves the rest to the front of the queue.  Block-uniform; ends with the queue stable.
   auto drain = [&](uint32_t nb) __attribute__((always_inline)) {
     if (nb > 0) {
-      Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
+      Emitter em{s_ck_arr + wave * kMergeSpawnSeg, s_cv_arr + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
                  cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child, A.ghist_next,
                  A.passes};
       for (uint32_t b = wave; b < nb; b += kWaves) {
@@ -849,6 +854,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     }
     const uint32_t pa = s0.x, pn = s1.x - s0.x;
     const uint32_t ca = s0.y, cn = s1.y - s0.y;
+    uint64_t* const s_ck = kSpawn ? s_ck_arr : s_pk + pn;
+    int2* const s_cv = kSpawn ? s_cv_arr : s_pv + pn;
 
     // Parents (their death/cloning delta of this step arrived as a record among the children)
     // and the tile's records go straight from global memory to LDS (LDS-direct dword loads: a
@@ -987,7 +994,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
 
     // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
     // that can spawn go to the queue; full batches are spawned when it fills.
-    if (A.tab_next.valid()) {
+    if (kSpawn && A.tab_next.valid()) {
       for (uint32_t base = 0; base < agg; base += kBlock) {
         const uint32_t p = base + threadIdx.x;
         bool act = false;
@@ -1033,7 +1040,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       }
       if (A.tabB_next.valid()) {
         // second AB2 term of step s+1 from this tile's parents N(s), as loaded
-        Emitter em{s_ck + wave * kMergeSpawnSeg, s_cv + wave * kMergeSpawnSeg, kMergeSpawnSeg,
+        Emitter em{s_ck_arr + wave * kMergeSpawnSeg, s_cv_arr + wave * kMergeSpawnSeg,
+                   kMergeSpawnSeg,
                    0, cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child,
                    A.ghist_next, A.passes};
         for (uint32_t wb = wave * kWave; wb < pn; wb += kBlock) {
@@ -1082,7 +1090,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     __syncthreads();
   }
   // the rest of the queue (block-uniform: every thread left the tile loop together)
-  if (A.tab_next.valid() && nl > 0) drain((nl + kWave - 1) / kWave);
+  if (kSpawn && A.tab_next.valid() && nl > 0) drain((nl + kWave - 1) / kWave);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1468,10 +1476,15 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.prop = prop ? *prop : QmcProposal{};
   const uint32_t g = max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
                                                         : (uint32_t)kMergeBlocks;
-  if (a.prop.kind)
-    hipLaunchKernelGGL(k_merge<true>, dim3(g), dim3(kBlock), 0, st, a);
+  if (toff_next == nullptr && toffB_next == nullptr)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_merge<false, false>),
+                       dim3(max_tiles < (uint32_t)kMergeOnlyBlocks ? (max_tiles ? max_tiles : 1)
+                                                                   : (uint32_t)kMergeOnlyBlocks),
+                       dim3(kBlock), 0, st, a);
+  else if (a.prop.kind)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_merge<true, true>), dim3(g), dim3(kBlock), 0, st, a);
   else
-    hipLaunchKernelGGL(k_merge<false>, dim3(g), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_merge<false, true>), dim3(g), dim3(kBlock), 0, st, a);
   return (int)hipGetLastError();
 }
 

@@ -234,6 +234,7 @@ def main():
             "sort_tile_records_per_thread": sort_tile,
         },
         "key_steps_per_s": key_steps / elapsed,
+        "rebalances": st1["rebalances"] - st0["rebalances"],
         "roofline": {
             "bound": "hbm", "kernel": KERNEL_NAMES[kind],
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -736,8 +736,8 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.slots = c->at<uint64_t>(c->L.slots);
   pl.max_rebal = c->C == 1 ? kKernelResplits : 0u;
   pl.epoch0 = c->epoch + 1;
-  // barriers of this launch: batch start, one per step, two per re-split
-  c->epoch += (uint64_t)nst + 1 + 2ull * pl.max_rebal;
+  // barriers of this launch: batch start, one per step, three per re-split
+  c->epoch += (uint64_t)nst + 1 + 3ull * pl.max_rebal;
   pl.cap_store = c->L.cap_store;
   pl.cap_inbox = c->L.cap_child;
   pl.rebal_min = 64;

@@ -55,6 +55,7 @@ struct PersistArgs {
   uint32_t* in_n;
   // key ranges: split[p] <= key < split[p+1]
   const uint64_t* split;
+  uint64_t* splitw;       // the same array, rewritten by a re-split in the kernel
   uint32_t P;
   // per-step tables of the batch: step k of circuit c at tab_base + tab_off[k * n_circuits + c]
   const uint8_t* tab_base;
@@ -224,6 +225,14 @@ __device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint6
   }
   __syncthreads();
   return (S.dec[3] & kErrLookback) == 0;
+}
+
+// Off-diagonal bound and group count of the step table held in LDS.
+__device__ __forceinline__ uint64_t tn_qoff(const Shared& S) {
+  return reinterpret_cast<const TableHeader*>(S.tab)->q_off;
+}
+__device__ __forceinline__ uint32_t tn_groups(const Shared& S) {
+  return reinterpret_cast<const TableHeader*>(S.tab)->n_groups;
 }
 
 __device__ __forceinline__ uint32_t upper_bound_lds(const uint64_t* a, uint32_t n, uint64_t v) {
@@ -1045,10 +1054,11 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       // Re-split in the kernel (one circuit): N(s+1) of every range goes to the canonical
       // store at its prefix (with AB2 also N(s), this pass's parents, to the N(s-1) array, which
       // only the first pass reads), the records already routed for step s+1 are dropped, the
-      // ranges are re-cut at even positions of N(s+1), and step s+1 is drawn again from the new
-      // slices (with AB2 its second term from each range's slice of N(s)) into the same segment
-      // buffer and inbox parity; pass k + 1 then runs as usual.  The draws are keyed on the
-      // walkers, so the records are the same; only their owners change.
+      // ranges are re-cut at even positions of the estimated cost of N(s+1) (below), and step
+      // s+1 is drawn again from the new slices (with AB2 its second term from each range's slice
+      // of N(s)) into the same segment buffer and inbox parity; pass k + 1 then runs as usual.
+      // The draws are keyed on the walkers, so the records are the same; only their owners
+      // change.
       --rebal_left;
       const bool two_rs = A.nbuf == 3 && two;
       {
@@ -1082,6 +1092,86 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         }
         if (t == 0) st_agent(&A.in_n[(par ^ 1u) * P + p], 0u);
       }
+      // The new ranges hold equal estimated cost rather than equal key counts.  A key costs
+      // 4 + 3 min(e, G - 1): e = (|a| + |b|) q_off / 2^32 is its expected number of spawned
+      // walkers in step s+1, and it routes at most one record per off-diagonal group (a key
+      // takes ~29 ns, a routed record ~21 ns).  Each workgroup publishes the cost of its N(s+1);
+      // the boundaries r W / P (W the total) that fall in its slice it places at the key whose
+      // running cost crosses them; then every workgroup reads the new splitters.
+      const uint64_t wq_off = tn_qoff(S);
+      const uint32_t wcap = tn_groups(S) > 1 ? tn_groups(S) - 1 : 0u;
+      const uint64_t* wsk = A.sk + ((uint64_t)ob * P + p) * A.segcap;
+      const int2* wsv = A.sv + ((uint64_t)ob * P + p) * A.segcap;
+      auto key_cost = [&](uint64_t i) -> uint32_t {
+        const int2 v = wsv[i];
+        const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+        const uint64_t hi = __umul64hi(sab, wq_off), lo = sab * wq_off;
+        const uint64_t e = hi != 0 ? ~0ull : (lo >> 32);
+        return 4u + 3u * (uint32_t)(e < wcap ? e : wcap);
+      };
+      uint64_t wmine = 0;
+      for (uint64_t i = t; i < nout; i += kPBlock) wmine += key_cost(i);
+      for (int o = 32; o > 0; o >>= 1) wmine += __shfl_xor(wmine, o);
+      __syncthreads();
+      if (__lane_id() == 0) S.red[t / kWave] = wmine;
+      __syncthreads();
+      wmine = 0;
+      for (int w = 0; w < kPWaves; ++w) wmine += S.red[w];
+      __syncthreads();
+      ++epoch;
+      if (!grid_sync(S, A, epoch, wmine, 0)) {
+        reason = 2;
+        kdone = (uint32_t)k + 1;
+        break;
+      }
+      {
+        const uint64_t wtot = S.dec[0];
+        uint32_t mine = t < p ? S.nouts[epoch & 1u][t] : 0u;
+        for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+        __syncthreads();
+        if (__lane_id() == 0) S.scan[t / kWave] = mine;
+        __syncthreads();
+        uint64_t wpre = 0;  // cost of the slices before this one
+        for (int w = 0; w < kPWaves; ++w) wpre += S.scan[w];
+        // thread t places boundary t (0 < t < P) at cost t W / P if it falls in this slice
+        const uint64_t bnd = t < P ? ((uint64_t)t * wtot) / P : 0;
+        const bool own = t > 0 && t < P && bnd >= wpre && bnd < wpre + wmine;
+        uint64_t carry = wpre;  // running cost before the current chunk
+        for (uint64_t c0 = 0; c0 < nout; c0 += kPBlock) {
+          // inclusive scan of this chunk's key costs
+          const uint32_t wi = c0 + t < nout ? key_cost(c0 + t) : 0u;
+          uint32_t incl = wi;
+          for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t x = __shfl_up(incl, o);
+            if (__lane_id() >= (uint32_t)o) incl += x;
+          }
+          __syncthreads();
+          if (__lane_id() == kWave - 1) S.scan[t / kWave] = incl;
+          __syncthreads();
+          uint32_t wbefore = 0, ctot = 0;
+          for (int w = 0; w < kPWaves; ++w) {
+            wbefore += w < (int)(t / kWave) ? S.scan[w] : 0u;
+            ctot += S.scan[w];
+          }
+          S.xsplit[t] = wbefore + incl;
+          __syncthreads();
+          if (own && bnd >= carry && bnd < carry + ctot) {
+            // the first key of the chunk whose inclusive running cost exceeds the boundary
+            const uint32_t tgt = (uint32_t)(bnd - carry);
+            uint32_t lo = 0, hi = kPBlock - 1;
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (S.xsplit[mid] > tgt)
+                hi = mid;
+              else
+                lo = mid + 1;
+            }
+            st_agent(&A.splitw[t], wsk[c0 + lo]);
+          }
+          carry += ctot;
+          __syncthreads();
+        }
+      }
       ++epoch;
       if (!grid_sync(S, A, epoch, 0, 0)) {
         reason = 2;
@@ -1089,11 +1179,16 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         break;
       }
       for (uint32_t q = t; q < P; q += kPBlock)
-        S.split[q] = q == 0 ? 0ull : ld_agent(&A.ckw[((uint64_t)q * tot) / P]);
+        S.split[q] = q == 0 ? 0ull : ld_agent(&A.splitw[q]);
       __syncthreads();
       uint64_t nout2 = 0;
-      const uint64_t rb = p == 0 ? 0 : ((uint64_t)p * tot) / P;
-      const uint64_t re = p + 1 < P ? ((uint64_t)(p + 1) * tot) / P : tot;
+      if (t == 0) {
+        S.red[2] = p == 0 ? 0 : lower_bound_glb(A.ckw, tot, S.split[p], true);
+        S.red[3] = p + 1 < P ? lower_bound_glb(A.ckw, tot, S.split[p + 1], true) : tot;
+      }
+      __syncthreads();
+      const uint64_t rb = S.red[2], re = S.red[3];
+      __syncthreads();
       {
         uint64_t* okp = A.sk + ((uint64_t)ob * P + p) * A.segcap;
         int2* ovp = A.sv + ((uint64_t)ob * P + p) * A.segcap;
@@ -1284,6 +1379,7 @@ PersistArgs make_args(const PersistLaunch* L) {
   a.cap_inbox = L->cap_inbox;
   a.rebal_min = L->rebal_min;
   a.max_rebal = L->max_rebal;
+  a.splitw = L->split_w;
   a.done = L->done;
   return a;
 }

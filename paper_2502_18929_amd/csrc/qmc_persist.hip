@@ -177,7 +177,14 @@ __device__ __forceinline__ bool grid_sync(Shared& S, const PersistArgs& A, uint6
     const uint64_t* sl = buf + 4 * (uint64_t)q;
     uint32_t spins = 0;
     uint64_t v0, v1, v2;
-    while (true) {
+    // the workgroup's own slot: the values it has just published (the last workgroup to arrive
+    // then needs no round trip through the coherence point for its own store)
+    if (q == p) {
+      v0 = tag | (nout < 0xFFFFFFFFull ? nout : 0xFFFFFFFFull);
+      v1 = tag | (nin < 0xFFFFFFFFull ? nin : 0xFFFFFFFFull);
+      v2 = tag | (uint64_t)S.err;
+    }
+    while (q != p) {
       v0 = ld_agent(&sl[0]);
       v1 = ld_agent(&sl[1]);
       v2 = ld_agent(&sl[2]);

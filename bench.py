@@ -49,6 +49,39 @@ def algorithmic_bytes(kind, cov):
     return 32 * ch
 
 
+ERROR_BAR = 0.01  # target half-width of the 95 % confidence interval of the final estimators
+
+
+def error_bar(obs, w, elapsed, seed=0, boot=2000):
+    """95 % bootstrap confidence interval over the replicas (the paper's error bars, End Matter on
+    simulation methodology; percentile interval of the mean of resampled replicas) of the final
+    fidelity and of every Pauli observable of the workload, and the wall time to the error bar
+    ERROR_BAR: the measured run when its widest interval is within it, else the run scaled by
+    the replicas the target needs, (h / ERROR_BAR)^2 times as many (replicas are batched in one
+    store, so the time grows with them)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    series = {"fidelity": obs["fidelity"][:, 0]}
+    for i, (label, _, _, ph) in enumerate(w.pauli_obs):
+        v = obs["pauli_val"][:, i, 0] + 1j * obs["pauli_val"][:, i, 1]
+        series[label] = (complex(ph) * v).real
+    R = len(series["fidelity"])
+    if R < 2:
+        return None
+    idx = rng.integers(0, R, size=(boot, R))
+    half = {}
+    for k, v in series.items():
+        lo, hi = np.percentile(v[idx].mean(axis=1), [2.5, 97.5])
+        half[k] = float(hi - lo) / 2
+    hmax = max(half.values())
+    reached = hmax <= ERROR_BAR
+    return {"target_ci95_halfwidth": ERROR_BAR, "replicas": R,
+            "ci95_halfwidth_fidelity": half["fidelity"], "ci95_halfwidth_max": hmax,
+            "widest": max(half, key=half.get), "reached": reached,
+            "wall_s": elapsed if reached else elapsed * (hmax / ERROR_BAR) ** 2,
+            "basis": "measured run" if reached else "extrapolated: replicas x (h / target)^2"}
+
+
 def sources_digest():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -124,11 +157,16 @@ def main():
                          "trained first on statistics of an untimed plain run")
     ap.add_argument("--proposal-samples", type=int, default=4,
                     help="channel draws per parent under a proposal (a power of two)")
+    ap.add_argument("--pulse-width", type=float, default=None,
+                    help="dd12 with square pulses of this width (steps of dt / 10 inside them) "
+                         "instead of ideal instantaneous ones")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--progress", type=int, default=0,
                     help="print a line to stderr after every this many timed steps (runs the "
                          "timed region in calls of that many steps; 0: one call)")
     args = ap.parse_args()
+    if args.pulse_width is not None and (args.workload != "dd12" or args.integrator != "euler"):
+        ap.error("--pulse-width applies to dd12 with the Euler step (AB2 needs a uniform step)")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(replicas and key-space shards would each map to one GPU).", file=sys.stderr)
@@ -142,7 +180,8 @@ def main():
 
     if args.workload == "batch64":
         return main_batch(args, kind)
-    w = W.CONFIGS[args.workload]()
+    w = (W.CONFIGS[args.workload]() if args.pulse_width is None else
+         W.config_dd12(pulse_width=args.pulse_width))
     K = w.nsteps if args.steps is None else min(args.steps, w.nsteps)
     Wm = min(args.warmup, w.nsteps)
     caps = {"ghz20_nm": (1 << 17, 1 << 19), "dd12": (1 << 24, 1 << 21), "ghz4": (256, 4096)}
@@ -226,7 +265,7 @@ def main():
             "workload": f"{w.name}: n={w.n}, {w.n_replicas} replicas x {w.walker_target:g} "
                         f"walkers, dt={w.dt}, {w.nsteps} steps",
             "n_qubits": w.n, "replicas": w.n_replicas, "walker_target": w.walker_target,
-            "dt": w.dt, "steps_timed": K, "step_path": args.path,
+            "dt": w.dt, "steps_timed": K, "step_path": args.path, "notes": w.notes,
             "integrator": args.integrator,
             "initiator": ({"xi": args.initiator_xi, "min_walkers": init_min}
                           if init_min else None),
@@ -245,7 +284,8 @@ def main():
         "final": {"n_occ_total": st1["n_occ"],
                   "fidelity_mean": float(obs["fidelity"][:, 0].mean()),
                   "fidelity_std_replicas": float(obs["fidelity"][:, 0].std(ddof=1)),
-                  "trace_mean": float(obs["trace"].mean())},
+                  "trace_mean": float(obs["trace"].mean()),
+                  "error_bar": error_bar(obs, w, elapsed)},
     }
     if prop:
         res["config"]["proposal"] = {"kind": prop[0], "samples": prop[1],

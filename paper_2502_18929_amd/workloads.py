@@ -47,6 +47,7 @@ class Workload:
     psi: list = field(default_factory=list)        # sparse |psi>: [(index, amplitude)]
     frame: str = "Z"
     notes: str = ""
+    step_dt: np.ndarray | None = None  # physical time step of every step (None: dt throughout)
 
     @property
     def n_h(self):
@@ -74,6 +75,8 @@ class Workload:
         w.s = self.s[:nsteps].copy()
         w.gamma = self.gamma[:nsteps].copy()
         w.pulses = {k: v for k, v in self.pulses.items() if k <= nsteps}
+        if self.step_dt is not None:
+            w.step_dt = self.step_dt[:nsteps].copy()
         if n_replicas is not None:
             w.n_replicas = n_replicas
         if walker_target is not None:
@@ -143,9 +146,16 @@ def _to_x_frame(mono):
 
 
 def dd(n=12, n_replicas=16, walker_target=1_000_000, dt=0.005, nsteps=4000, seed=2,
-       j_scale=0.02, gamma_deph=0.005, gamma_damp=0.002, tau=1.0, disorder_seed=2):
-    """Staggered-XX dynamical decoupling of |+>^n on a ring with ZZ crosstalk, in the X frame,
-    with ideal instantaneous X pulses.  J_q = j_scale * U[0.5, 1.5] from numpy PCG64."""
+       j_scale=0.02, gamma_deph=0.005, gamma_damp=0.002, tau=1.0, disorder_seed=2,
+       pulse_width=None, substeps=10, name=None):
+    """Staggered-XX dynamical decoupling of |+>^n on a ring with ZZ crosstalk, in the X frame.
+    J_q = j_scale * U[0.5, 1.5] from numpy PCG64.  The X pulses on the even qubits at tau/2 + k tau
+    and on the odd ones at (k + 1) tau are ideal and instantaneous, or, with pulse_width w, square
+    pulses a X_q with a = pi / (2 w) (a pi rotation) over [t_p - w/2, t_p + w/2), integrated with
+    `substeps` steps of dt / substeps inside the windows (nsteps counts steps of dt before the
+    pulses are sub-stepped; a pulse at the end of the run is completed past it).  A step of
+    dt / m is a step of dt with every weight and rate divided by m (L is linear in them), so the
+    context keeps one dt; step_dt holds each step's physical time step."""
     rng = np.random.Generator(np.random.PCG64(disorder_seed))
     J = j_scale * rng.uniform(0.5, 1.5, size=n)
     h_z = []
@@ -174,13 +184,56 @@ def dd(n=12, n_replicas=16, walker_target=1_000_000, dt=0.005, nsteps=4000, seed
         pulses.setdefault(k, []).append((0, odd))
     # merge pulses at the same step into one Pauli (they commute)
     pulses = {k: [(0, sum(z for _, z in v))] for k, v in pulses.items()}
+    step_dt = None
+    notes = "X frame, ideal pulses"
+    if pulse_width is not None:
+        hw = int(round(pulse_width / (2.0 * dt)))
+        assert hw >= 1 and abs(2 * hw * dt - pulse_width) < 1e-12, \
+            "the pulse width must be an even number of steps"
+        assert 2 * hw <= per_tau // 2, "pulse windows must not overlap"
+        assert substeps >= 1
+        amp = math.pi / (2.0 * pulse_width)
+        n_j = len(h)
+        h = h + [_to_x_frame((_bit(q), 0, 1.0)) for q in range(n)]  # physical X_q
+        # physical qubits pulsed during step k; a pulse centred on the last instant (the ideal
+        # pulse after the final step) is completed, so the run ends half a window later
+        active = np.zeros(nsteps + hw, dtype=np.int64)
+        for k, v in pulses.items():
+            for _, z in v:  # the X-frame Z mask of an ideal pulse is its physical X mask
+                active[max(0, k - hw):k + hw] |= z
+        rows_s, rows_g, sdt = [], [], []
+        for k in range(nsteps + hw):
+            if k >= nsteps and active[k] == 0:
+                break
+            kk = min(k, nsteps - 1)
+            srow = np.zeros(n_j + n)
+            srow[:n_j] = s[kk]
+            if active[k] == 0:
+                rows_s.append(srow)
+                rows_g.append(gamma[kk])
+                sdt.append(dt)
+                continue
+            for q in range(n):
+                if (int(active[k]) >> q) & 1:
+                    srow[n_j + q] = amp
+            for _ in range(substeps):
+                rows_s.append(srow / substeps)
+                rows_g.append(gamma[kk] / substeps)
+                sdt.append(dt / substeps)
+        s = np.array(rows_s)
+        gamma = np.array(rows_g)
+        step_dt = np.array(sdt)
+        nsteps = len(sdt)
+        pulses = {}
+        notes = (f"X frame, square pulses of width {pulse_width} (amplitude {amp:.4g}), "
+                 f"steps of dt/{substeps} inside them")
     keys, re, im = _single_key_init(walker_target)
     # <Z_q> in the physical frame is <X_q> in the X frame.
     pauli_obs = [(f"Z{q}", _bit(q), 0, 1.0) for q in range(n)]
-    return Workload(name=f"dd_n{n}", n=n, n_replicas=n_replicas, seed=seed, dt=dt, nsteps=nsteps,
+    return Workload(name=name or f"dd_n{n}", n=n, n_replicas=n_replicas, seed=seed, dt=dt, nsteps=nsteps,
                     walker_target=walker_target, h=h, lops=lops, s=s, gamma=gamma,
                     init_keys=keys, init_re=re, init_im=im, pulses=pulses, pauli_obs=pauli_obs,
-                    psi=[(0, 1.0)], frame="X", notes="X frame, ideal pulses")
+                    psi=[(0, 1.0)], frame="X", notes=notes, step_dt=step_dt)
 
 
 # ---- the three single-GPU configurations ----------------------------------------------------
@@ -190,9 +243,11 @@ def config_ghz4():
     return ghz(n=4, n_replicas=4, walker_target=10_000, dt=0.01, seed=1, name="ghz4")
 
 
-def config_dd12():
-    """n=12 staggered-XX DD with ZZ crosstalk, dt=0.005, 4000 steps, 16 replicas x 1e6."""
-    return dd(n=12, n_replicas=16, walker_target=1_000_000, dt=0.005, nsteps=4000, seed=2)
+def config_dd12(pulse_width=None):
+    """n=12 staggered-XX DD with ZZ crosstalk, dt=0.005, 4000 steps, 16 replicas x 1e6; ideal
+    pulses, or square pulses of that width with steps of dt / 10 inside them."""
+    return dd(n=12, n_replicas=16, walker_target=1_000_000, dt=0.005, nsteps=4000, seed=2,
+              pulse_width=pulse_width, name="dd12" if pulse_width is None else "dd12_finite")
 
 
 def config_ghz20_nm():

@@ -1,0 +1,122 @@
+"""The finite-pulse option of the DD workload, pinned on dense linear algebra: square pulses
+a X_q of width w with a w = pi / 2, integrated with steps of dt / m inside the windows, where a
+step of dt / m is the step of dt with every weight and rate divided by m (the Liouvillian of
+eq. (2) is linear in them)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import dense
+from paper_2502_18929_amd import workloads as W
+
+
+def _zq(n, r, q):
+    # physical Z_q is X_q in the X frame of the DD workload
+    return float(np.trace(dense.pauli(n, 1 << q, 0) @ r).real)
+
+
+def _plus(n):
+    r = np.zeros((2 ** n, 2 ** n), complex)
+    r[0, 0] = 1.0
+    return dense.vec(r)
+
+
+def _random_rho(n, rng):
+    a = rng.standard_normal((2 ** n, 2 ** n)) + 1j * rng.standard_normal((2 ** n, 2 ** n))
+    r = a @ a.conj().T
+    return dense.vec(r / np.trace(r))
+
+
+def test_step_times_cover_the_run():
+    w = W.dd(n=4, nsteps=400, pulse_width=0.05, substeps=10)
+    # 4 windows of 10 steps of dt become 100 sub-steps each; the last (at the end of the run)
+    # is completed past it: 5 more steps of dt, as 50 sub-steps
+    assert w.nsteps == 400 - 3 * 10 - 5 + 4 * 100
+    assert w.step_dt.sum() == pytest.approx(400 * 0.005 + 5 * 0.005, abs=1e-12)
+    assert w.pulses == {} and w.s.shape == (w.nsteps, 2 * 4) and w.gamma.shape == (w.nsteps, 8)
+
+
+@pytest.mark.parametrize("m", [1, 3, 10])
+def test_window_steps_integrate_the_physical_generator(m):
+    # the sub-steps of the first window (even qubits, centred at tau / 2) together propagate
+    # exactly as the physical generator over the window's duration w: crosstalk weights 1, pulse
+    # amplitude pi / (2 w) on the even qubits, the unscaled rates
+    n, w_, dt = 3, 0.05, 0.005
+    w = W.dd(n=n, nsteps=400, pulse_width=w_, substeps=m)
+    n_j = len(w.h) - n
+    inside = np.nonzero(w.s[:, n_j:].any(axis=1))[0]
+    first = inside[: int(round(w_ / dt)) * m]
+    assert np.all(np.diff(first) == 1) and first[0] == int(round((0.5 - w_ / 2) / dt))
+    model = dense.DenseModel(n, w.h, w.lops)
+    U = np.eye(4 ** n, dtype=complex)
+    for k in first:
+        U = sla.expm(w.dt * model.L(w.s[k], w.gamma[k])) @ U
+    s_phys = np.zeros(len(w.h))
+    s_phys[:n_j] = 1.0
+    s_phys[n_j::2] = math.pi / (2 * w_)  # qubits 0, 2
+    g_phys = np.array([0.005] * n + [0.002] * n)
+    assert np.abs(U - sla.expm(w_ * model.L(s_phys, g_phys))).max() < 1e-10
+
+
+@pytest.mark.parametrize("m", [1, 4])
+def test_windows_are_the_ideal_pulses(m):
+    # without crosstalk and noise the exact propagation through the finite pulses is the product
+    # of the ideal ones (X conjugations of the even / odd qubits), window by window
+    n, rng = 3, np.random.default_rng(2 + m)
+    kw = dict(n=n, nsteps=400, j_scale=0.0, gamma_deph=0.0, gamma_damp=0.0)
+    wf = W.dd(pulse_width=0.05, substeps=m, **kw)
+    wi = W.dd(**kw)
+    v0 = _random_rho(n, rng)
+    vf = dense.expm_piecewise(dense.DenseModel(n, wf.h, wf.lops), wf.s, wf.gamma, wf.dt, v0)
+    pul = {k: [dense.pulse_superop(n, x, z) for x, z in v] for k, v in wi.pulses.items()}
+    vi = dense.euler_map(dense.DenseModel(n, wi.h, wi.lops), wi.s, wi.gamma, wi.dt, v0, pulses=pul)
+    assert len(wi.pulses) == 4
+    assert np.abs(vf - vi).max() < 1e-10
+
+
+def test_finite_width_effect_within_its_bound():
+    # each window differs from its ideal pulse (centred in it) by at most 2 w ||L_rest||, with
+    # L_rest the crosstalk and noise part (trace norm; ||L_rest|| <= 2 ||H_rest|| + 2 sum gamma
+    # ||L_k||^2), so |delta <Z_q>| <= sum over windows of 2 w ||L_rest||
+    n, w_ = 3, 0.05
+    wf = W.dd(n=n, nsteps=400, pulse_width=w_, substeps=10)
+    wi = W.dd(n=n, nsteps=400)
+    v0 = _plus(n)
+    rf = dense.unvec(dense.expm_piecewise(dense.DenseModel(n, wf.h, wf.lops), wf.s, wf.gamma,
+                                          wf.dt, v0), n)
+    pul = {k: [dense.pulse_superop(n, x, z) for x, z in v] for k, v in wi.pulses.items()}
+    # exact between the ideal pulses: constant generator, one exponential per run of steps
+    mi = dense.DenseModel(n, wi.h, wi.lops)
+    E = sla.expm(wi.dt * mi.L(wi.s[0], wi.gamma[0]))
+    v = np.array(v0)
+    for k in range(wi.nsteps):
+        for P in pul.get(k, []):
+            v = P @ v
+        v = E @ v
+    for P in pul.get(wi.nsteps, []):
+        v = P @ v
+    ri = dense.unvec(v, n)
+    h_rest = sum(abs(c) for _, _, c in wi.h)
+    l_rest = 2 * h_rest + 2 * (n * 0.005 + n * 0.002)  # ||Z|| = ||sigma^-|| = 1
+    bound = 4 * 2 * w_ * l_rest
+    diff = max(abs(_zq(n, rf, q) - _zq(n, ri, q)) for q in range(n))
+    assert diff <= bound
+    assert diff > 0  # the width has an effect
+
+
+def test_substep_euler_converges_first_order():
+    # the Euler map against the exact propagation of the same piecewise-constant model: the error
+    # comes from inside the windows and halves with the sub-step
+    n = 3
+    errs = []
+    for m in (10, 20, 40):
+        w = W.dd(n=n, nsteps=400, pulse_width=0.05, substeps=m)
+        model = dense.DenseModel(n, w.h, w.lops)
+        v0 = _plus(n)
+        re_ = dense.unvec(dense.euler_map(model, w.s, w.gamma, w.dt, v0), n)
+        rx = dense.unvec(dense.expm_piecewise(model, w.s, w.gamma, w.dt, v0), n)
+        errs.append(max(abs(_zq(n, re_, q) - _zq(n, rx, q)) for q in range(n)))
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+    assert errs[0] < 1e-3

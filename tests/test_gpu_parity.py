@@ -139,6 +139,19 @@ def test_dd_small_with_pulses(B, orc, path):
         _assert_same(g, o, w.n_replicas, f"step {k0 + 100}")
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_dd_small_finite_pulses(B, orc, path):
+    """DD with square pulses of width 0.05 integrated with steps of dt / 10 inside them (weights
+    and rates divided by 10 there): three pulse windows, the last completed past the run."""
+    w = W.dd(n=6, n_replicas=4, walker_target=20000, nsteps=300, seed=12, pulse_width=0.05,
+             substeps=10)
+    _say(f"dd n=6: {w.nsteps} steps with finite pulses, {path}")
+    g, o = _pair(B, orc, w, store=4096, spawn=1 << 16, path=path)
+    for k0 in range(0, w.nsteps, 150):
+        _run_both(g, o, w, k0, min(k0 + 150, w.nsteps))
+        _assert_same(g, o, w.n_replicas, f"step {min(k0 + 150, w.nsteps)}")
+
+
 def test_general_pauli_pulse_resorts(B, orc):
     rng = np.random.default_rng(4)
     n = 5

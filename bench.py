@@ -158,8 +158,10 @@ def main():
     ap.add_argument("--proposal-samples", type=int, default=4,
                     help="channel draws per parent under a proposal (a power of two)")
     ap.add_argument("--pulse-width", type=float, default=None,
-                    help="dd12 with square pulses of this width (steps of dt / 10 inside them) "
-                         "instead of ideal instantaneous ones")
+                    help="dd12 with square pulses of this width instead of ideal instantaneous "
+                         "ones")
+    ap.add_argument("--pulse-substeps", type=int, default=10,
+                    help="steps per dt inside finite pulse windows")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--progress", type=int, default=0,
                     help="print a line to stderr after every this many timed steps (runs the "
@@ -181,7 +183,7 @@ def main():
     if args.workload == "batch64":
         return main_batch(args, kind)
     w = (W.CONFIGS[args.workload]() if args.pulse_width is None else
-         W.config_dd12(pulse_width=args.pulse_width))
+         W.config_dd12(pulse_width=args.pulse_width, substeps=args.pulse_substeps))
     K = w.nsteps if args.steps is None else min(args.steps, w.nsteps)
     Wm = min(args.warmup, w.nsteps)
     caps = {"ghz20_nm": (1 << 17, 1 << 19), "dd12": (1 << 24, 1 << 21), "ghz4": (256, 4096)}

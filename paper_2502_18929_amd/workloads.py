@@ -243,11 +243,12 @@ def config_ghz4():
     return ghz(n=4, n_replicas=4, walker_target=10_000, dt=0.01, seed=1, name="ghz4")
 
 
-def config_dd12(pulse_width=None):
+def config_dd12(pulse_width=None, substeps=10):
     """n=12 staggered-XX DD with ZZ crosstalk, dt=0.005, 4000 steps, 16 replicas x 1e6; ideal
-    pulses, or square pulses of that width with steps of dt / 10 inside them."""
+    pulses, or square pulses of that width with steps of dt / substeps inside them."""
     return dd(n=12, n_replicas=16, walker_target=1_000_000, dt=0.005, nsteps=4000, seed=2,
-              pulse_width=pulse_width, name="dd12" if pulse_width is None else "dd12_finite")
+              pulse_width=pulse_width, substeps=substeps,
+              name="dd12" if pulse_width is None else "dd12_finite")
 
 
 def config_ghz20_nm():

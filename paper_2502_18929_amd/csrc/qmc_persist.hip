@@ -1069,15 +1069,17 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       --rebal_left;
       const bool two_rs = A.nbuf == 3 && two;
       {
-        // exclusive prefix over the workgroups of the counts of barrier parity `par_b`
+        // exclusive prefix over the workgroups of the counts of barrier parity `par_b` (64-bit:
+        // the counts of all workgroups together may pass 2^32)
         auto prefix_of = [&](uint32_t par_b) -> uint64_t {
-          uint32_t mine = t < p ? S.nouts[par_b][t] : 0u;
+          uint64_t mine = t < p ? S.nouts[par_b][t] : 0u;
           for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
           __syncthreads();
-          if (__lane_id() == 0) S.scan[t / kWave] = mine;
+          if (__lane_id() == 0) S.red[t / kWave] = mine;
           __syncthreads();
           uint64_t pre = 0;
-          for (int w = 0; w < kPWaves; ++w) pre += S.scan[w];
+          for (int w = 0; w < kPWaves; ++w) pre += S.red[w];
+          __syncthreads();
           return pre;
         };
         const uint64_t prefix = prefix_of(epoch & 1u);
@@ -1124,6 +1126,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       __syncthreads();
       wmine = 0;
       for (int w = 0; w < kPWaves; ++w) wmine += S.red[w];
+      wmine = wmine < 0xFFFFFFFFull ? wmine : 0xFFFFFFFFull;  // as the barrier publishes it
       __syncthreads();
       ++epoch;
       if (!grid_sync(S, A, epoch, wmine, 0)) {
@@ -1133,13 +1136,14 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       }
       {
         const uint64_t wtot = S.dec[0];
-        uint32_t mine = t < p ? S.nouts[epoch & 1u][t] : 0u;
+        // cost of the slices before this one (64-bit: the total may pass 2^32)
+        uint64_t mine = t < p ? S.nouts[epoch & 1u][t] : 0u;
         for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
         __syncthreads();
-        if (__lane_id() == 0) S.scan[t / kWave] = mine;
+        if (__lane_id() == 0) S.red[t / kWave] = mine;
         __syncthreads();
-        uint64_t wpre = 0;  // cost of the slices before this one
-        for (int w = 0; w < kPWaves; ++w) wpre += S.scan[w];
+        uint64_t wpre = 0;
+        for (int w = 0; w < kPWaves; ++w) wpre += S.red[w];
         // thread t places boundary t (0 < t < P) at cost t W / P if it falls in this slice
         const uint64_t bnd = t < P ? ((uint64_t)t * wtot) / P : 0;
         const bool own = t > 0 && t < P && bnd >= wpre && bnd < wpre + wmine;

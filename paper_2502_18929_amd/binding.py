@@ -145,6 +145,8 @@ class QMC:
     """One libqmc context: R replicas of one model (or of each model of a batch of circuits,
     see ``QMC.batch``), advanced on one HIP stream."""
 
+    _integrator = "euler"  # the context's default time integrator
+
     def __init__(self, n, n_replicas, seed, dt, h, lops, keys, re, im, store_capacity,
                  spawn_capacity, walker_target=0, stream=None):
         self._setup(n, n_replicas, seed, dt, [(h, lops, keys, re, im)], store_capacity,
@@ -254,8 +256,15 @@ class QMC:
                                    _ptr(g, ctypes.c_double)))
 
     def run_workload(self, w, start=0, stop=None):
-        """Advance through steps [start, stop) of a workload, applying its ideal pulses."""
+        """Advance through steps [start, stop) of a workload, applying its ideal pulses.  A
+        workload whose steps differ in length (finite pulses sub-stepped) needs the Euler step:
+        AB2's weights 3/2 and -1/2 assume a uniform step."""
         stop = w.nsteps if stop is None else stop
+        sdt = getattr(w, "step_dt", None)
+        if (self._integrator == "ab2" and sdt is not None and
+                not np.all(sdt[start:stop] == sdt[start])):
+            raise QMCError(QMC_ERR_ARG, "AB2 needs a uniform step; this workload sub-steps "
+                                        "its pulses (use the Euler step)")
         for a, b, pulses in w.segments():
             if b <= start or a >= stop:
                 continue
@@ -391,6 +400,7 @@ class QMC:
     def set_integrator(self, integrator):
         """Time integrator: 'euler' (default) or 'ab2' (clears N(s-1))."""
         self._check(lib().qmc_set_integrator(self._ctx, {"euler": 0, "ab2": 1}[integrator]))
+        self._integrator = integrator
 
     def set_prev(self, replica, keys, re, im, s_prev, gamma_prev):
         """AB2: N(s-1) of one replica and the weights of step s-1."""

@@ -120,3 +120,13 @@ def test_substep_euler_converges_first_order():
         errs.append(max(abs(_zq(n, re_, q) - _zq(n, rx, q)) for q in range(n)))
     assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
     assert errs[0] < 1e-3
+
+
+def test_ab2_refuses_sub_stepped_pulses():
+    # the binding refuses AB2 on a workload whose steps differ in length, before any GPU call
+    from paper_2502_18929_amd import binding
+    w = W.dd(n=3, nsteps=200, pulse_width=0.05, substeps=10)
+    q = binding.QMC.__new__(binding.QMC)
+    q._integrator = "ab2"
+    with pytest.raises(binding.QMCError, match="uniform step"):
+        q.run_workload(w)

@@ -162,6 +162,9 @@ def main():
                          "ones")
     ap.add_argument("--pulse-substeps", type=int, default=10,
                     help="steps per dt inside finite pulse windows")
+    ap.add_argument("--sequential-steps", type=int, default=0,
+                    help="batch64: also time its first this many steps circuit by circuit, one "
+                         "context each, against the batched step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--progress", type=int, default=0,
                     help="print a line to stderr after every this many timed steps (runs the "
@@ -333,6 +336,37 @@ def cpu_baseline_batch(bw, budget_s=20.0):
             "key_steps_per_s": ks / dt}
 
 
+def batch_vs_sequential(bw, S, path):
+    """The first S steps of the batch twice: batched (all circuits in one context) and circuit by
+    circuit (one context each, run one after another), wall times between device
+    synchronizations.  The batched step equals each circuit's own step bit for bit (tested), so
+    the statistics are the same and the time ratio is what batching gains."""
+    import torch
+    from paper_2502_18929_amd import binding
+    circuits = [(w.h, w.lops, w.init_keys, w.init_re, w.init_im) for w in bw.circuits]
+    g = binding.QMC.batch(bw.n, bw.n_replicas, bw.seed, bw.dt, circuits,
+                          store_capacity=1 << 18, spawn_capacity=1 << 18)
+    g.set_path(path)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run_batch_workload(bw, 0, S)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    g.close()
+    t_seq = 0.0
+    for w in bw.circuits:
+        q = binding.QMC.from_workload(w, store_capacity=1 << 21, spawn_capacity=1 << 21)
+        q.set_path(path)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q.run_workload(w, 0, S)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        q.close()
+    return {"steps": S, "circuits": len(bw.circuits), "batched_s": t_batch,
+            "sequential_s": t_seq, "speedup": t_seq / t_batch}
+
+
 def main_batch(args, kind):
     """The batched configuration: 64 circuits of uneven size in one context and one step."""
     import torch
@@ -389,6 +423,9 @@ def main_batch(args, kind):
                      "algorithmic_bytes_per_launch": per_launch},
         "final": {"n_occ_total": st1["n_occ"], "trace_mean": float(obs["trace"].mean())},
     }
+    if args.sequential_steps > 0:
+        res["batched_vs_sequential"] = batch_vs_sequential(bw, min(args.sequential_steps, K),
+                                                           args.path)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_batch(bw)
     g.close()

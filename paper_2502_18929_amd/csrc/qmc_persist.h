@@ -23,8 +23,9 @@ struct PersistLaunch {
   int2* iv;
   uint32_t incap;
   uint32_t* in_n;       // [2][P]
-  const uint64_t* split;
-  uint64_t* split_w;
+  const uint64_t* split;  // [P] first composite key of each workgroup's range
+  uint64_t* split_w;      // the same array, written by the preparation kernel and by the
+                          // cost-weighted re-splits inside the fused kernel
   uint32_t P;
   const uint8_t* tab_base;
   const uint32_t* tab_off;   // [nsteps] byte offsets of the step tables (first / only term)

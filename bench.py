@@ -27,26 +27,38 @@ KERNEL_NAMES = {"fused": "k_persist", "sort": "k_onesweep", "merge": "k_merge"}
 # the dd12 store stays small enough for the fused kernel throughout)
 DOMINANT = {"ghz20_nm": "fused", "dd12": "merge", "ghz4": "fused", "batch64": "merge"}
 DOMINANT_INITIATOR = {"ghz20_nm": "fused", "dd12": "fused", "ghz4": "fused", "batch64": "fused"}
+# every source whose change can alter a kernel's launches or traffic (the host sets the launch
+# configuration), so committed counter numbers are dropped as soon as one of them changes
 KERNEL_SOURCES = ["paper_2502_18929_amd/csrc/qmc_persist.hip",
                   "paper_2502_18929_amd/csrc/qmc_kernels.hip",
-                  "paper_2502_18929_amd/csrc/qmc_device.hpp"]
+                  "paper_2502_18929_amd/csrc/qmc_device.hpp",
+                  "paper_2502_18929_amd/csrc/qmc_persist.h",
+                  "paper_2502_18929_amd/csrc/qmc_kernels.h",
+                  "paper_2502_18929_amd/csrc/qmc_host.cpp"]
+
+
+def step_bytes(cov):
+    """Algorithmic bytes of whole steps (counter sums `cov` over those steps; 16 B per record:
+    u64 key, i32 re, i32 im): read every parent to spawn (16 N_occ), write its diagonal
+    (death/cloning) update back (8 N_occ), write and read every off-diagonal child
+    (2 x 16 N_sp), read every parent again to annihilate (16 N_occ) and write every surviving key
+    (16 N_occ'): 16 (2.5 N_occ + 2 N_sp + N_occ')."""
+    return 16 * (2.5 * cov["key_steps"] + 2 * cov["spawn_steps"] + cov["out_steps"])
 
 
 def algorithmic_bytes(kind, cov):
-    """Bytes the method must move in the steps a kernel class ran (counter sums `cov` of those
-    steps; 16 B per record: u64 key, i32 re, i32 im).
-    fused (one launch = whole steps): read each parent, write each surviving key, and each
-      routed record (child or death delta) once written by its sender and once read by its
-      owner: 16 (N_p + N_out + 2 N_c);
-    merge: read parents and sorted children, write the new store (the children of the next step,
-      which the streamed merge also writes, are not counted); sort: every child record in and
-      out once."""
-    keys, ch, out = cov["key_steps"], cov["child_steps"], cov["out_steps"]
+    """Algorithmic bytes of the steps a kernel class ran.
+    fused: the kernel runs whole steps, so all of step_bytes;
+    merge: its annihilation share alone, parents and children read and the store written,
+      16 (N_occ + N_sp + N_occ') (the draws of the next step, which it also makes, are left out:
+      a lower bound);
+    sort: every child read and written once, 32 N_sp."""
+    keys, sp, out = cov["key_steps"], cov["spawn_steps"], cov["out_steps"]
     if kind == "fused":
-        return 16 * (keys + out + 2 * ch)
+        return step_bytes(cov)
     if kind == "merge":
-        return 16 * (keys + ch + out)
-    return 32 * ch
+        return 16 * (keys + sp + out)
+    return 32 * sp
 
 
 ERROR_BAR = 0.01  # target half-width of the 95 % confidence interval of the final estimators
@@ -90,46 +102,139 @@ def sources_digest():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kind, workload):
+def profiled_traffic(kind, workload, steps_per_launch):
     """HBM bytes per launch of the kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when there is no
-    summary for this kernel and workload or the kernel sources changed since it was taken."""
+    summary for this kernel and workload, when its launches covered another number of steps than
+    the ones timed here, or when the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kind]}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"sources_digest:\s*([0-9a-f]+)", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or m.group(1) != sources_digest():
+    c = re.search(r"steps_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or not c or m.group(1) != sources_digest():
+        return None
+    if steps_per_launch is None or abs(float(c.group(1)) - steps_per_launch) > 1e-9:
         return None
     return float(b.group(1))
 
 
-def cpu_baseline(w, integrator="euler", init_min=0, budget_s=20.0, proposal=None):
-    """The CPU oracle, untuned, on the host cores over the first steps of the same workload
-    (about budget_s seconds of work); reports walker-steps/s.  proposal = (kind, samples, mlp)
-    or None (the comb)."""
+def host_description():
+    """Host cores and CPU model of the machine the CPU baseline runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(w, K, integrator="euler", init_min=0, budget_s=10.0, proposal=None):
+    """The CPU oracle, untuned, on the host cores over the same steps [0, K) that the GPU timed,
+    from the same initial state: the window is run again from the start until about budget_s
+    seconds of work are done, or cut at budget_s when one pass takes longer.  Reports
+    walker-steps/s over everything it ran.  proposal = (kind, samples, mlp) or None (the comb)."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
-    o = oracle.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
-                      w.init_im, integrator=integrator)
-    o.set_initiator(init_min)
-    if proposal:
-        o.set_proposal(*proposal)
     t0 = time.perf_counter()
-    done, used = 0, 1
+    ws = ks = 0
+    passes, done, used = 0, 0, 1
     chunk = 50
-    while done < w.nsteps and time.perf_counter() - t0 < budget_s:
-        stop = min(done + chunk, w.nsteps)
-        used = o.step(w.s[done:stop], w.gamma[done:stop], threads=threads)
-        done = stop
+    while time.perf_counter() - t0 < budget_s:
+        o = oracle.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
+                          w.init_im, integrator=integrator)
+        o.set_initiator(init_min)
+        if proposal:
+            o.set_proposal(*proposal)
+        done = 0
+        for a, b, pulses in w.segments():
+            if a >= K or time.perf_counter() - t0 >= budget_s:
+                break
+            for (px, pz) in pulses:
+                o.pulse(px, pz)
+            for lo in range(a, min(b, K), chunk):
+                if time.perf_counter() - t0 >= budget_s:
+                    break
+                hi = min(lo + chunk, b, K)
+                used = o.step(w.s[lo:hi], w.gamma[lo:hi], threads=threads)
+                done = hi
+        c = o.counters()
+        ws += c["walker_steps"]
+        ks += c["key_steps"]
+        o.close()
+        if done < K:
+            break
+        passes += 1
     dt = time.perf_counter() - t0
-    c = o.counters()
-    return {"value": c["walker_steps"] / dt, "unit": "walker-steps/s", "cores": used,
-            "kind": "oracle",
-            "sample": f"steps 0..{done} of {w.nsteps} of {w.name} (all {w.n_replicas} replicas), "
-                      f"{dt:.1f} s, OpenMP across replicas",
-            "key_steps_per_s": c["key_steps"] / dt}
+    partial = done if done < K else 0
+    if partial == 0:
+        what = f"{passes} pass(es) over steps 0..{K}"
+    elif passes == 0:
+        what = f"steps 0..{partial} of the timed window 0..{K}"
+    else:
+        what = f"{passes} pass(es) over steps 0..{K} and steps 0..{partial} of one more"
+    return {"value": ws / dt, "unit": "walker-steps/s", "cores": used, "kind": "oracle",
+            "sample": f"{what} of {w.name} (all {w.n_replicas} replicas, the GPU's timed "
+                      f"window), {dt:.1f} s, OpenMP across replicas",
+            "key_steps_per_s": ks / dt, "host": host_description()}
+
+
+def roofline(kind, workload, prof_ms, prof_n, cov):
+    """The roofline object of the timed kernel class: algorithmic bytes per launch over the
+    average launch duration (HIP events on the context stream around exactly those launches),
+    against the HBM peak; the whole-step bytes of the same steps beside it."""
+    abytes = algorithmic_bytes(kind, cov)
+    per_launch = abytes / prof_n if prof_n else None
+    avg_ms = prof_ms / prof_n if prof_n else None
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
+    spl = cov["steps"] / prof_n if prof_n else None
+    return {"bound": "hbm", "kernel": KERNEL_NAMES[kind], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(kind, workload, spl), "avg_launch_ms": avg_ms,
+            "launches": prof_n, "steps_covered": cov["steps"], "steps_per_launch": spl,
+            "algorithmic_bytes_per_launch": per_launch,
+            "step_bytes_per_launch": step_bytes(cov) / prof_n if prof_n else None,
+            "counts": {k: cov[k] for k in ("key_steps", "spawn_steps", "child_steps",
+                                           "out_steps")}}
+
+
+EXACT_PATH = os.path.join(ROOT, "tests", "golden", "ghz4_exact.json")
+
+
+def vs_exact(obs, w, integrator):
+    """Replica means of the final estimators against the dense solutions of the same model
+    (stored by tests/golden/make_exact.py): the dense map of the integrator used, which is the
+    exact expectation of the stochastic step (z-score over the replicas), and the exact
+    propagation (the integrator's time-step bias beside the statistical error)."""
+    import numpy as np
+    if not os.path.exists(EXACT_PATH):
+        return None
+    ref = json.load(open(EXACT_PATH))
+    if ref.get("workload") != w.name or ref.get("nsteps") != w.nsteps:
+        return None
+    series = {"fidelity": obs["fidelity"][:, 0], "trace": obs["trace"]}
+    for i, (label, _, _, ph) in enumerate(w.pauli_obs):
+        v = obs["pauli_val"][:, i, 0] + 1j * obs["pauli_val"][:, i, 1]
+        series[label] = (complex(ph) * v).real
+    mp = "ab2_map" if integrator == "ab2" else "euler_map"
+    out = {}
+    for k, v in series.items():
+        mean = float(np.mean(v))
+        se = float(np.std(v, ddof=1) / np.sqrt(len(v))) if len(v) > 1 else float("nan")
+        m, ex = ref[mp][k], ref["expm"][k]
+        out[k] = {"mean": mean, "se": se, mp: m, "expm": ex,
+                  "z_vs_map": (mean - m) / se if se > 0 else None,
+                  "dev_vs_expm": mean - ex, "map_bias_vs_expm": m - ex}
+    zs = [abs(o["z_vs_map"]) for o in out.values() if o["z_vs_map"] is not None]
+    return {"reference": mp, "max_abs_z_vs_map": max(zs) if zs else None,
+            "max_abs_dev_vs_expm": max(abs(o["dev_vs_expm"]) for o in out.values()),
+            "observables": out}
 
 
 def main():
@@ -248,10 +353,7 @@ def main():
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
     key_steps = st1["key_steps"] - st0["key_steps"]
     value = walker_steps / elapsed
-    abytes = algorithmic_bytes(kind, cov)
-    per_launch = abytes / prof_n if prof_n else None
-    avg_ms = prof_ms / prof_n if prof_n else None
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
+    roof = roofline(kind, w.name, prof_ms, prof_n, cov)
     obs = g.observe(pauli=[(x, z) for _, x, z, _ in w.pauli_obs], psi=w.psi)
     res = {
         "metric": "walker-steps/sec on 1 GPU at n=20; wall time to fixed error bar vs exact",
@@ -279,31 +381,30 @@ def main():
         },
         "key_steps_per_s": key_steps / elapsed,
         "rebalances": st1["rebalances"] - st0["rebalances"],
-        "roofline": {
-            "bound": "hbm", "kernel": KERNEL_NAMES[kind],
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(kind, w.name),
-            "avg_launch_ms": avg_ms, "launches": prof_n, "steps_covered": cov["steps"],
-            "algorithmic_bytes_per_launch": per_launch,
-        },
-        "final": {"n_occ_total": st1["n_occ"],
+        "roofline": roof,
+        "final": {"n_occ_total": st1["n_occ"], "t": K * w.dt,
                   "fidelity_mean": float(obs["fidelity"][:, 0].mean()),
                   "fidelity_std_replicas": float(obs["fidelity"][:, 0].std(ddof=1)),
                   "trace_mean": float(obs["trace"].mean()),
-                  "error_bar": error_bar(obs, w, elapsed)},
+                  "error_bar": (error_bar(obs, w, elapsed) if K == w.nsteps else None),
+                  "error_bar_note": (None if K == w.nsteps else
+                                     f"the timed window ends at step {K} of {w.nsteps}: the "
+                                     "error bar is taken at the end of the trajectory only")},
     }
+    if w.n <= 5 and K == w.nsteps:
+        res["vs_exact"] = vs_exact(obs, w, args.integrator)
     if prop:
         res["config"]["proposal"] = {"kind": prop[0], "samples": prop[1],
                                      "mlp_train_corr": train_corr}
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(w, args.integrator, init_min, proposal=prop)
+        res["cpu_baseline"] = cpu_baseline(w, K, args.integrator, init_min, proposal=prop)
     g.close()
     print(json.dumps(res), flush=True)
 
 
-def cpu_baseline_batch(bw, budget_s=20.0):
-    """The CPU oracle, circuit by circuit (each with its replicas' stream ids), over the first
-    steps of the batch, about budget_s seconds; walker-steps/s over all circuits."""
+def cpu_baseline_batch(bw, K, budget_s=20.0):
+    """The CPU oracle, circuit by circuit (each with its replicas' stream ids), over the steps
+    [0, K) the GPU timed, cut at about budget_s seconds; walker-steps/s over all circuits."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     R = bw.n_replicas
@@ -316,10 +417,12 @@ def cpu_baseline_batch(bw, budget_s=20.0):
     t0 = time.perf_counter()
     done, used = 0, 1
     for a, b, masks in bw.segments():
-        for lo in range(a, b, 20):
+        if a >= K:
+            break
+        for lo in range(a, min(b, K), 20):
             if time.perf_counter() - t0 >= budget_s:
                 break
-            hi = min(lo + 20, b)
+            hi = min(lo + 20, b, K)
             if lo == a and masks is not None:
                 for c, o in enumerate(orcs):
                     if masks[0][c] or masks[1][c]:
@@ -331,9 +434,10 @@ def cpu_baseline_batch(bw, budget_s=20.0):
     ws = sum(o.counters()["walker_steps"] for o in orcs)
     ks = sum(o.counters()["key_steps"] for o in orcs)
     return {"value": ws / dt, "unit": "walker-steps/s", "cores": used, "kind": "oracle",
-            "sample": f"steps 0..{done} of {bw.nsteps} of {bw.name} (all {len(orcs)} circuits x "
-                      f"{R} replicas), {dt:.1f} s, OpenMP across each circuit's replicas",
-            "key_steps_per_s": ks / dt}
+            "sample": f"steps 0..{done} of the timed window 0..{K} of {bw.name} (all "
+                      f"{len(orcs)} circuits x {R} replicas), {dt:.1f} s, OpenMP across each "
+                      f"circuit's replicas",
+            "key_steps_per_s": ks / dt, "host": host_description()}
 
 
 def batch_vs_sequential(bw, S, path):
@@ -397,10 +501,7 @@ def main_batch(args, kind):
     g.profile(None)
     elapsed = t1 - t0
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
-    abytes = algorithmic_bytes(kind, cov)
-    per_launch = abytes / prof_n if prof_n else None
-    avg_ms = prof_ms / prof_n if prof_n else None
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
+    roof = roofline(kind, bw.name, prof_ms, prof_n, cov)
     obs = g.observe()
     res = {
         "metric": "walker-steps/sec on 1 GPU (batched circuits)",
@@ -416,18 +517,14 @@ def main_batch(args, kind):
                    "parallelism": "1 GPU, all circuits and replicas in one store",
                    "sort_tile_records_per_thread": sort_tile},
         "key_steps_per_s": (st1["key_steps"] - st0["key_steps"]) / elapsed,
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[kind], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(kind, bw.name), "avg_launch_ms": avg_ms,
-                     "launches": prof_n, "steps_covered": cov["steps"],
-                     "algorithmic_bytes_per_launch": per_launch},
+        "roofline": roof,
         "final": {"n_occ_total": st1["n_occ"], "trace_mean": float(obs["trace"].mean())},
     }
     if args.sequential_steps > 0:
         res["batched_vs_sequential"] = batch_vs_sequential(bw, min(args.sequential_steps, K),
                                                            args.path)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline_batch(bw)
+        res["cpu_baseline"] = cpu_baseline_batch(bw, K)
     g.close()
     print(json.dumps(res), flush=True)
 

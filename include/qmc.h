@@ -268,8 +268,11 @@ int qmc_import(qmc_ctx* ctx, uint32_t replica, const uint64_t* keys, const int32
 
 /* Counters of a context: the step counter, the occupied keys of all replicas now, and running
  * sums since qmc_init over the parents of every step of N^tot (walker_steps), occupied keys
- * (key_steps), child records (child_steps) and annihilated output keys (out_steps).  The sums
- * give the walker-steps/s and key-steps/s rates and the algorithmic bytes of the kernels.
+ * (key_steps), routed records (child_steps: the nonzero death/cloning deltas, which travel as
+ * records of the parent's own key, and the children), annihilated output keys (out_steps) and
+ * off-diagonal children alone (spawn_steps, the spawned walkers' records of the End Matter spawn
+ * step).  The sums give the walker-steps/s and key-steps/s rates and the algorithmic bytes of
+ * the kernels.
  * `rebalances` counts the times the fused kernel re-cut its key ranges to even out a grown
  * population, inside one launch or by stopping for a new one (no effect on the results). */
 typedef struct {
@@ -280,6 +283,7 @@ typedef struct {
   uint64_t child_steps;
   uint64_t out_steps;
   uint64_t rebalances;
+  uint64_t spawn_steps;
 } qmc_stats;
 
 int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
@@ -292,7 +296,7 @@ int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
  * and, in `covered` (may be NULL), the counter sums (walker_steps, key_steps, child_steps,
  * out_steps, and in `step` the number of steps) of exactly the steps that the timed launches
  * ran -- for classes 1, 2 and 3; zeros for class 0, which runs for the first step of a batch
- * only.  The algorithmic bytes of the timed kernels follow from these sums. */
+ * only (spawn_steps likewise).  The algorithmic bytes of the timed kernels follow from these sums. */
 int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
 int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches, qmc_stats* covered);
 

@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_uint32), ("n_occ_total", ctypes.c_uint64),
                 ("walker_steps", ctypes.c_uint64), ("key_steps", ctypes.c_uint64),
                 ("child_steps", ctypes.c_uint64), ("out_steps", ctypes.c_uint64),
-                ("rebalances", ctypes.c_uint64)]
+                ("rebalances", ctypes.c_uint64), ("spawn_steps", ctypes.c_uint64)]
 
 
 class Model(ctypes.Structure):
@@ -395,7 +395,7 @@ class QMC:
         self._check(lib().qmc_counters(self._ctx, ctypes.byref(st)))
         return dict(step=st.step, n_occ=st.n_occ_total, walker_steps=st.walker_steps,
                     key_steps=st.key_steps, child_steps=st.child_steps, out_steps=st.out_steps,
-                    rebalances=st.rebalances)
+                    rebalances=st.rebalances, spawn_steps=st.spawn_steps)
 
     def set_integrator(self, integrator):
         """Time integrator: 'euler' (default) or 'ab2' (clears N(s-1))."""
@@ -446,7 +446,8 @@ class QMC:
         self._check(lib().qmc_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n),
                                            ctypes.byref(st)))
         cov = dict(steps=st.step, walker_steps=st.walker_steps, key_steps=st.key_steps,
-                   child_steps=st.child_steps, out_steps=st.out_steps)
+                   child_steps=st.child_steps, out_steps=st.out_steps,
+                   spawn_steps=st.spawn_steps)
         return ms.value, n.value, cov
 
 def initiator_threshold(xi, n_diag):

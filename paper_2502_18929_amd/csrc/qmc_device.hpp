@@ -77,6 +77,8 @@ struct Counters {
   uint64_t key_steps;      // running sum of occupied keys over the parents of every step
   uint64_t child_steps;    // running sum of child records of every step
   uint64_t out_steps;      // running sum of annihilated output keys of every step
+  uint64_t death_steps;    // running sum of nonzero diagonal (death/cloning) records of every
+                           // step; child_steps - death_steps are the off-diagonal children
   uint32_t err;
   uint32_t err_step;
   uint32_t tile_counter;   // (unused)

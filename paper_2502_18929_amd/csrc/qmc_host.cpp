@@ -155,6 +155,7 @@ struct qmc_ctx {
   uint32_t cur = 0;
   std::vector<double> shift;
   std::vector<int64_t> nd0_re;
+  std::vector<int64_t> qshift_dev;  // the Q32 shifts last uploaded to the device (both terms)
   uint8_t* pinned = nullptr;     // table staging: kTableArea bytes, then the window offsets
   uint8_t* pinned_small = nullptr;  // counters and estimator staging
   size_t pinned_small_bytes = 0;
@@ -491,10 +492,13 @@ int read_counters(qmc_ctx* c, qmc::Counters& out) {
 }
 
 int upload_qshift(qmc_ctx* c, const std::vector<int64_t>& qs) {
+  if (qs == c->qshift_dev) return QMC_OK;  // the device already holds these shifts
+  c->qshift_dev.clear();
   std::memcpy(c->pinned_small, qs.data(), qs.size() * 8);
   HIPCHK(c, hipMemcpyAsync(c->at<int64_t>(c->L.qshift), c->pinned_small, qs.size() * 8,
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->qshift_dev = qs;
   return QMC_OK;
 }
 
@@ -629,6 +633,17 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
   e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
   if (e == hipSuccess)
     e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)2 * c->L.P * 4 * 8, c->stream);
+  // One copy each way between the pinned staging and the table area, of a size the runtime
+  // hands to its DMA engines: their first use in a process costs several milliseconds, which
+  // belongs to set-up rather than to the first qmc_step that uploads a window of tables.
+  constexpr size_t kWarmCopy = 1u << 20;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->at<uint8_t>(c->L.tab), c->pinned, kWarmCopy, hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->pinned, c->at<uint8_t>(c->L.tab), kWarmCopy, hipMemcpyDeviceToHost,
+                       c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     qmc_destroy(c);
     return QMC_ERR_HIP;
@@ -673,6 +688,8 @@ void add_cover(qmc_ctx* c, const qmc::Counters& a, const qmc::Counters& b, uint3
   c->prof_cover.key_steps += b.key_steps - a.key_steps;
   c->prof_cover.child_steps += b.child_steps - a.child_steps;
   c->prof_cover.out_steps += b.out_steps - a.out_steps;
+  c->prof_cover.spawn_steps +=
+      (b.child_steps - b.death_steps) - (a.child_steps - a.death_steps);
   c->prof_cover.rebalances += b.resplits - a.resplits;
 }
 
@@ -1724,6 +1741,7 @@ int qmc_counters(qmc_ctx* c, qmc_stats* out) {
   out->key_steps = hc.key_steps;
   out->child_steps = hc.child_steps;
   out->out_steps = hc.out_steps;
+  out->spawn_steps = hc.child_steps - hc.death_steps;
   out->rebalances = hc.resplits + c->relaunches;
   return QMC_OK;
 }

@@ -35,13 +35,17 @@ struct Emitter {
   uint64_t cap;
   uint32_t* ghist;      // [passes][kRadixBins]
   uint32_t passes;
+  uint32_t ndiag = 0;   // wave-uniform: staged records that are diagonal (death) records
 
   __device__ void flush() {
     const uint32_t lane = __lane_id();
     wave_lds_fence();
     uint64_t base = 0;
-    if (lane == 0)
+    if (lane == 0) {
       base = atomicAdd((unsigned long long*)&cnt->n_child[nsel], (unsigned long long)fill);
+      if (ndiag) atomicAdd((unsigned long long*)&cnt->death_steps, (unsigned long long)ndiag);
+    }
+    ndiag = 0;
     base = __shfl(base, 0);
     const bool ok = base + fill <= cap;
     if (!ok && lane == 0) {
@@ -82,6 +86,12 @@ struct Emitter {
     }
     fill += (uint32_t)__popcll(m);
     if (fill > seg - kWave) flush();
+  }
+
+  // The same for a parent's diagonal (death/cloning) record, counted apart from the children.
+  __device__ __forceinline__ void emit_diag(bool has, uint64_t key, int2 val) {
+    ndiag += (uint32_t)__popcll(__ballot(has));
+    emit(has, key, val);
   }
 
   // A record of this step does not fit int32.
@@ -309,7 +319,7 @@ __device__ __forceinline__ void spawn_records(Emitter& em, const TableView& tv, 
         d.x = (int32_t)comb_step(r, xre);
         d.y = (int32_t)comb_step(r, xim);
       }
-      em.emit((d.x | d.y) != 0, kl.rkey(ck, sab), d);
+      em.emit_diag((d.x | d.y) != 0, kl.rkey(ck, sab), d);
     }
   }
   if constexpr (kProp) {

@@ -102,6 +102,7 @@ struct Shared {
   uint4 tab[kPersistTableBytes / 16];   // the step table of the spawns drawn in this pass
   uint4 tabB[kPersistTableBytes / 16];  // AB2: the table of their second term
   uint32_t err;           // error bits this workgroup raised in the current step
+  uint32_t ndiag;         // diagonal records this workgroup routed in the current pass
 };
 using LTable = TableViewT<lptr>;
 
@@ -450,6 +451,7 @@ struct Router {
   uint64_t* sk;            // this wave's LDS staging
   int2* sv;
   uint32_t fill;           // wave-uniform
+  uint32_t* ndiag;         // LDS count of the diagonal (death/cloning) records routed this pass
 
   __device__ __forceinline__ void flush() {
     if (fill == 0) return;
@@ -539,6 +541,13 @@ struct Router {
     fill += (uint32_t)__popcll(m);
     if (fill > kStage - kWave) flush();
   }
+
+  // The same for a parent's diagonal (death/cloning) record, counted apart from the children.
+  __device__ __forceinline__ void emit_diag(bool has, uint64_t key, int2 val) {
+    const uint64_t m = __ballot(has);
+    if (m != 0 && __lane_id() == 0) atomicAdd(ndiag, (uint32_t)__popcll(m));
+    emit(has, key, val);
+  }
 };
 
 // Death delta and children of the n <= 64 active parents at list offset b (one per lane).
@@ -566,7 +575,7 @@ __device__ __forceinline__ void process_active(const PersistArgs& A, Shared& S, 
         d.x = (int32_t)comb_step(r, xre);
         d.y = (int32_t)comb_step(r, xim);
       }
-      R.emit((d.x | d.y) != 0, A.kl.rkey(ck, sab), d);
+      R.emit_diag((d.x | d.y) != 0, A.kl.rkey(ck, sab), d);
     }
   }
   // Children into every off-diagonal target, one comb over all groups (Re, Im) in order.
@@ -657,7 +666,7 @@ __device__ __forceinline__ void process_wide(const PersistArgs& A, Shared& S, Ro
       d.x = (int32_t)comb_step(r, xre);
       d.y = (int32_t)comb_step(r, xim);
     }
-    R.emit((d.x | d.y) != 0, A.kl.rkey(ck, sab), d);
+    R.emit_diag((d.x | d.y) != 0, A.kl.rkey(ck, sab), d);
   }
   if (mine && __ballot(act)) {
     uint32_t r0 = w.x;
@@ -943,6 +952,8 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   // parents (second term).
   uint64_t epoch = A.epoch0 - 1;
   uint64_t st_w = 0, st_k = 0, st_c = 0, st_o = 0;  // statistics of this workgroup (thread 0)
+  uint64_t st_d = 0;     // diagonal records among the routed records of the steps run
+  uint32_t pend_d = 0;   // diagonal records routed by the last pass (consumed by the next one)
   uint32_t reason = 0, kdone = A.nsteps;
   uint64_t tot_last = 0, tot_prev = 0;  // keys of the last two passes' outputs
   uint64_t mx_ref = 0;  // largest key range right after the split (circuit-aligned ranges)
@@ -963,6 +974,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
   for (int32_t k = -1; k < (int32_t)A.nsteps; ++k) {
     const bool first = k < 0;
     const uint32_t s = first ? A.step0 : A.step0 + (uint32_t)k;
+    if (t == 0) S.ndiag = 0;  // counted by this pass's router (after the inbox barrier below)
     const uint32_t par = (uint32_t)k & 1u;  // 1 for the first pass
     const bool last = k + 1 == (int32_t)A.nsteps;
     const uint32_t ob = (uint32_t)(k + 1) % A.nbuf, ib = (ob + A.nbuf - 1) % A.nbuf;
@@ -1012,7 +1024,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     const LTable tn = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab));
     const LTable tnB = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tabB));
     Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, nstep, &S.err,
-             A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u};
+             A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u, &S.ndiag};
     merge_segment(A, S, pk, pv, np_k, c, okp, ovp, s, !last, two && !first, R, tn, tnB, nstep);
     const uint64_t nout = S.red[0], wsum = S.red[1];
     if (two && first) {
@@ -1028,7 +1040,9 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         st_k += np_k;
         st_c += c;
         st_o += nout;
+        st_d += pend_d;
       }
+      pend_d = S.ndiag;
     }
     ++epoch;
     if (!grid_sync(S, A, epoch, nout, c)) {
@@ -1196,6 +1210,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
       if (t == 0) {
         S.red[2] = p == 0 ? 0 : lower_bound_glb(A.ckw, tot, S.split[p], true);
         S.red[3] = p + 1 < P ? lower_bound_glb(A.ckw, tot, S.split[p + 1], true) : tot;
+        S.ndiag = 0;  // the records of step s+1 are drawn again
       }
       __syncthreads();
       const uint64_t rb = S.red[2], re = S.red[3];
@@ -1205,7 +1220,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         int2* ovp = A.sv + ((uint64_t)ob * P + p) * A.segcap;
         const LTable tn = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab));
         Router R{A.in_n, A.ik, A.iv, A.incap, cnt, S.split, P, pbits, par ^ 1u, s + 1, &S.err,
-                 A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u};
+                 A.kl.ish, S.st_k[t / kWave], S.st_v[t / kWave], 0u, &S.ndiag};
         merge_segment(A, S, A.ckw + rb, A.cvw + rb, re - rb, 0, okp, ovp, s + 1, true, false, R,
                       tn, tn, s + 1, true);
         nout2 = S.red[0];
@@ -1225,7 +1240,10 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
         }
       }
       np_next = nout2 <= A.segcap ? nout2 : 0;
-      if (t == 0) A.seg_n[ob * P + p] = (uint32_t)np_next;
+      if (t == 0) {
+        A.seg_n[ob * P + p] = (uint32_t)np_next;
+        pend_d = S.ndiag;
+      }
       ++epoch;
       if (!grid_sync(S, A, epoch, nout2, 0)) {
         reason = 2;
@@ -1246,6 +1264,7 @@ __global__ __launch_bounds__(kPBlock) void k_persist(PersistArgs A) {
     atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)st_k);
     atomicAdd((unsigned long long*)&cnt->child_steps, (unsigned long long)st_c);
     atomicAdd((unsigned long long*)&cnt->out_steps, (unsigned long long)st_o);
+    atomicAdd((unsigned long long*)&cnt->death_steps, (unsigned long long)st_d);
     if (p == 0) {
       A.done[0] = kdone;
       A.done[1] = reason;

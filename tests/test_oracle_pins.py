@@ -278,6 +278,63 @@ def test_death_only_closed_form(orc):
         assert abs(mean.imag - f * im[c]) < 5 * sdi + 1
 
 
+def _ab2_scalar(h, steps):
+    """Closed form of the AB2 recurrence y_{s+1} = y_s + h (3/2 y_s - 1/2 y_{s-1}) with the Euler
+    first step y_1 = (1 + h) y_0, y_0 = 1: y_s = c1 r1^s + c2 r2^s, r1, r2 the roots of
+    r^2 - (1 + 3h/2) r + h/2 = 0."""
+    b, c = 1 + 1.5 * h, 0.5 * h
+    disc = math.sqrt(b * b - 4 * c)
+    r1, r2 = (b + disc) / 2, (b - disc) / 2
+    c2 = (r1 - (1 + h)) / (r1 - r2)
+    c1 = 1 - c2
+    return c1 * r1 ** steps + c2 * r2 ** steps
+
+
+@pytest.mark.parametrize("integrator", ["euler", "ab2"])
+@pytest.mark.parametrize("S", [1.5, -1.0])
+def test_shift_closed_form(orc, integrator, S):
+    """A constant shift S adds S to the diagonal (death/cloning) coefficient of every key.  With
+    pure dephasing on one qubit (L_diag = 0 on |i><i|, -2 gamma on |0><1| and |1><0|, no
+    spawning) every key evolves alone: E[N(s)] = y_s N(0) with y_s = (1 + dt (L_diag + S))^s for
+    Euler and the closed form of the AB2 recurrence (both terms carrying the shift) for AB2, in
+    Re and Im alike.  A shift at half strength, of the wrong sign, on Im instead of Re, or left
+    out of the second AB2 term misses these values by tens of standard errors."""
+    n, g, dt, steps = 1, 0.5, 0.02, 30
+    lops = [[(0, 1, 1.0)]]
+    keys = np.array([0, 1, 2, 3], dtype=np.uint64)     # |0><0|, |1><0|, |0><1|, |1><1|
+    re = np.array([1000, 800, 700, 900], dtype=np.int32)
+    im = np.array([0, 300, -400, 0], dtype=np.int32)
+    ldiag = np.array([0.0, -2 * g, -2 * g, 0.0])
+    R = 400
+    o = orc.Oracle(n, R, 11, dt, [], lops, keys, re, im, integrator=integrator)
+    for r in range(R):
+        o.set_shift(r, S)
+    o.step(np.zeros((steps, 0)), np.full((steps, 1), g))
+    vals = np.zeros((R, 4), dtype=complex)
+    for r in range(R):
+        k, a, b = o.export(r)
+        d = dict(zip(k.tolist(), (a + 1j * b).tolist()))
+        vals[r] = [d.get(int(x), 0) for x in keys]
+    for c in range(4):
+        h = dt * (ldiag[c] + S)
+        y = (1 + h) ** steps if integrator == "euler" else _ab2_scalar(h, steps)
+        mean = vals[:, c].mean()
+        se_re = vals[:, c].real.std(ddof=1) / math.sqrt(R)
+        se_im = vals[:, c].imag.std(ddof=1) / math.sqrt(R)
+        assert abs(mean.real - y * re[c]) < 5 * se_re + 1, (c, mean, y * re[c], se_re)
+        assert abs(mean.imag - y * im[c]) < 5 * se_im + 1, (c, mean, y * im[c], se_im)
+
+
+def test_ab2_scalar_closed_form_is_the_recurrence():
+    """The AB2 closed form used above equals the recurrence it solves."""
+    for h in (0.03, -0.05, 0.01):
+        y = [1.0, 1 + h]
+        for _ in range(40):
+            y.append(y[-1] + h * (1.5 * y[-1] - 0.5 * y[-2]))
+        for s_ in (0, 1, 7, 40):
+            assert _ab2_scalar(h, s_) == pytest.approx(y[s_], rel=1e-12)
+
+
 def _run_oracle_obs(orc, w, R):
     o = orc.Oracle(w.n, R, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
     obs = [(x, z) for _, x, z, _ in w.pauli_obs]
@@ -323,6 +380,12 @@ def test_multi_step_matches_dense_euler_map(orc):
         mean = per.mean(axis=0)
         se = per.std(axis=0, ddof=1) / math.sqrt(R)
         assert np.all(np.abs(mean - exact) < 5 * se + 1e-4), (cp, mean, exact, se)
+    # against the physical solution (exact propagation of the piecewise-constant circuit): within
+    # the statistical error plus the Euler map's own time-step bias, which is large at dt = 0.01
+    ex = _ghz4_dense_obs(w, dense.expm_piecewise(dm, w.s, w.gamma, w.dt, dense.vec(rho0)), psi)
+    bias = np.abs(np.array(exact) - np.array(ex))
+    assert bias.max() > 0.05                      # Euler's O(dt) bias: 0.10 in <Z_3>
+    assert np.all(np.abs(mean - ex) < 5 * se + bias + 1e-4), (mean, ex, bias, se)
 
 
 def test_replica_average_is_hermitian(orc):
@@ -554,6 +617,12 @@ def test_ab2_multi_step_matches_dense_ab2_map(orc):
         mean = per.mean(axis=0)
         se = per.std(axis=0, ddof=1) / math.sqrt(R)
         assert np.all(np.abs(mean - exact) < 5 * se + 1e-4), (cp, mean, exact, se)
+    # against the physical solution: within the statistical error plus the AB2 map's own
+    # time-step bias, an order of magnitude below Euler's at dt = 0.01
+    ex = _ghz4_dense_obs(w, dense.expm_piecewise(dm, w.s, w.gamma, w.dt, dense.vec(rho0)), psi)
+    bias = np.abs(np.array(exact) - np.array(ex))
+    assert bias.max() < 0.01
+    assert np.all(np.abs(mean - ex) < 5 * se + bias + 1e-4), (mean, ex, bias, se)
 
 
 def test_ab2_dense_map_is_second_order(orc):

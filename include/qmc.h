@@ -255,6 +255,33 @@ typedef struct {
 /* Estimators of the current state (any NULL output pointer is skipped). */
 int qmc_observe(qmc_ctx* ctx, const qmc_obs_spec* spec, qmc_obs_out* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the estimators of qmc_observe on a store the caller holds in device
+ * memory, with no context and no allocation of any kind.  d_keys are n composite keys
+ * (replica << 2 n_qubits) | key, sorted ascending and unique, and d_vals the n (re, im) int32
+ * pairs beside them (2n int32), both device pointers owned by the caller (a context's store, or
+ * any copy of one); nd0_re is a host array of Re N^diag(0) per replica, which normalizes the FP64
+ * outputs (it may be NULL when no FP64 output is asked for).  spec and out are as for
+ * qmc_observe, with the same values.  Every scratch word -- staged inputs, accumulators,
+ * lookups, outputs before their copy back -- lives in one device array of
+ * QMC_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device, held until the process
+ * ends; its address is taken on the first call on each device.  Each GPU has one such array
+ * which every call on it shares: calls that overlap on one GPU race, so callers on one GPU must
+ * serialize them (the array keeps the last call's contents; each call clears what it
+ * accumulates).  Limits: n_replicas <= QMC_NOALLOC_MAX_REPLICAS, n_pauli <=
+ * QMC_NOALLOC_MAX_PAULI, n_psi <= QMC_NOALLOC_MAX_PSI and n_psi^2 x n_replicas <=
+ * QMC_NOALLOC_MAX_LOOKUPS; beyond them QMC_ERR_ARG, as for a mask outside n bits or a missing
+ * pointer.  Enqueued on hip_stream (NULL = the default stream), which is synchronized before the
+ * call returns.  QMC_ERR_HIP if a launch or copy fails. */
+#define QMC_NOALLOC_MAX_REPLICAS 256
+#define QMC_NOALLOC_MAX_PAULI 64
+#define QMC_NOALLOC_MAX_PSI 32
+#define QMC_NOALLOC_MAX_LOOKUPS 32768
+#define QMC_NOALLOC_SCRATCH_BYTES 1360128
+int qmc_observe_noalloc(uint32_t n_qubits, uint32_t n_replicas, const uint64_t* d_keys,
+                        const int32_t* d_vals, uint64_t n, const int64_t* nd0_re,
+                        const qmc_obs_spec* spec, qmc_obs_out* out, void* hip_stream);
+
 /* Copy one replica's store to host arrays (keys ascending).  *n receives the size; if it
  * exceeds cap nothing is copied and QMC_ERR_ARG is returned. */
 int qmc_export(qmc_ctx* ctx, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,

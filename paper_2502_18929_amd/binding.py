@@ -29,7 +29,8 @@ EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_use_graphs", "qmc_observe",
             "qmc_export", "qmc_import", "qmc_counters",
             "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
-            "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch"]
+            "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch",
+            "qmc_observe_noalloc"]
 
 
 class Monomial(ctypes.Structure):
@@ -119,6 +120,8 @@ def lib():
         L.qmc_last_error.restype = ctypes.c_char_p
         L.qmc_destroy.argtypes = [vp]
         L.qmc_destroy.restype = None
+        L.qmc_observe_noalloc.argtypes = [u32, u32, vp, vp, u64, P(ctypes.c_int64), P(ObsSpec),
+                                          P(ObsOut), vp]
         _lib = L
     return _lib
 
@@ -341,31 +344,9 @@ class QMC:
                                                None, None, 0))
 
     def observe(self, pauli=(), psi=(), want_eps=False):
-        R = self.R
-        npl = len(pauli)
-        px = np.ascontiguousarray([p[0] for p in pauli] or [0], dtype=np.uint64)
-        pz = np.ascontiguousarray([p[1] for p in pauli] or [0], dtype=np.uint64)
-        pidx = np.ascontiguousarray([p[0] for p in psi] or [0], dtype=np.uint64)
-        pre = np.ascontiguousarray([complex(p[1]).real for p in psi] or [0.0])
-        pim = np.ascontiguousarray([complex(p[1]).imag for p in psi] or [0.0])
-        spec = ObsSpec(npl, _ptr(px, ctypes.c_uint64), _ptr(pz, ctypes.c_uint64), len(psi),
-                       _ptr(pidx, ctypes.c_uint64), _ptr(pre, ctypes.c_double),
-                       _ptr(pim, ctypes.c_double), 1 if want_eps else 0)
-        o = dict(n_occ=np.zeros(R, np.uint64), n_tot=np.zeros(R, np.uint64),
-                 ndiag=np.zeros((R, 2), np.int64), pauli=np.zeros((R, max(npl, 1), 2), np.int64),
-                 eps2=np.zeros((R, 2), np.uint64), trace=np.zeros(R), theta=np.zeros(R),
-                 pauli_val=np.zeros((R, max(npl, 1), 2)), fidelity=np.zeros((R, 2)),
-                 eps=np.zeros(R))
-        out = ObsOut(_ptr(o["n_occ"], ctypes.c_uint64), _ptr(o["n_tot"], ctypes.c_uint64),
-                     _ptr(o["ndiag"], ctypes.c_int64), _ptr(o["pauli"], ctypes.c_int64),
-                     _ptr(o["eps2"], ctypes.c_uint64), _ptr(o["trace"], ctypes.c_double),
-                     _ptr(o["theta"], ctypes.c_double), _ptr(o["pauli_val"], ctypes.c_double),
-                     _ptr(o["fidelity"], ctypes.c_double), _ptr(o["eps"], ctypes.c_double))
+        spec, o, out, keep = _obs_args(self.R, pauli, psi, want_eps)
         self._check(lib().qmc_observe(self._ctx, ctypes.byref(spec), ctypes.byref(out)))
-        o["pauli"] = o["pauli"][:, :npl]
-        o["pauli_val"] = o["pauli_val"][:, :npl]
-        o["eps2_int"] = [int(a) + (int(b) << 64) for a, b in o["eps2"]]
-        return o
+        return _obs_result(o, len(pauli))
 
     def export(self, replica):
         n = ctypes.c_uint64()
@@ -449,6 +430,67 @@ class QMC:
                    child_steps=st.child_steps, out_steps=st.out_steps,
                    spawn_steps=st.spawn_steps)
         return ms.value, n.value, cov
+
+def _obs_args(R, pauli, psi, want_eps):
+    """The qmc_obs_spec and the output arrays of an estimator call over R replicas (the arrays
+    are returned too, so they outlive the call)."""
+    npl = len(pauli)
+    px = np.ascontiguousarray([p[0] for p in pauli] or [0], dtype=np.uint64)
+    pz = np.ascontiguousarray([p[1] for p in pauli] or [0], dtype=np.uint64)
+    pidx = np.ascontiguousarray([p[0] for p in psi] or [0], dtype=np.uint64)
+    pre = np.ascontiguousarray([complex(p[1]).real for p in psi] or [0.0])
+    pim = np.ascontiguousarray([complex(p[1]).imag for p in psi] or [0.0])
+    spec = ObsSpec(npl, _ptr(px, ctypes.c_uint64), _ptr(pz, ctypes.c_uint64), len(psi),
+                   _ptr(pidx, ctypes.c_uint64), _ptr(pre, ctypes.c_double),
+                   _ptr(pim, ctypes.c_double), 1 if want_eps else 0)
+    o = dict(n_occ=np.zeros(R, np.uint64), n_tot=np.zeros(R, np.uint64),
+             ndiag=np.zeros((R, 2), np.int64), pauli=np.zeros((R, max(npl, 1), 2), np.int64),
+             eps2=np.zeros((R, 2), np.uint64), trace=np.zeros(R), theta=np.zeros(R),
+             pauli_val=np.zeros((R, max(npl, 1), 2)), fidelity=np.zeros((R, 2)),
+             eps=np.zeros(R))
+    out = ObsOut(_ptr(o["n_occ"], ctypes.c_uint64), _ptr(o["n_tot"], ctypes.c_uint64),
+                 _ptr(o["ndiag"], ctypes.c_int64), _ptr(o["pauli"], ctypes.c_int64),
+                 _ptr(o["eps2"], ctypes.c_uint64), _ptr(o["trace"], ctypes.c_double),
+                 _ptr(o["theta"], ctypes.c_double), _ptr(o["pauli_val"], ctypes.c_double),
+                 _ptr(o["fidelity"], ctypes.c_double), _ptr(o["eps"], ctypes.c_double))
+    return spec, o, out, (px, pz, pidx, pre, pim)
+
+
+def _obs_result(o, npl):
+    o["pauli"] = o["pauli"][:, :npl]
+    o["pauli_val"] = o["pauli_val"][:, :npl]
+    o["eps2_int"] = [int(a) + (int(b) << 64) for a, b in o["eps2"]]
+    return o
+
+
+def observe_noalloc(n, n_replicas, keys, vals, nd0_re, pauli=(), psi=(), want_eps=False,
+                    stream=None):
+    """qmc_observe_noalloc: the estimators of a sorted store held in device memory, with no
+    context and no allocation in the library.  keys: a device tensor of the composite keys
+    (replica << 2n | key, ascending; int64 or uint64 storage), vals: a device int32 tensor of
+    [len(keys), 2] (re, im); nd0_re: Re N^diag(0) per replica.  Returns what QMC.observe does."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libqmc needs a HIP device; none is visible")
+    m = int(keys.numel())
+    if vals.dtype != torch.int32 or tuple(vals.shape) != (m, 2) or not vals.is_contiguous():
+        raise ValueError("vals must be a contiguous int32 tensor of shape [len(keys), 2]")
+    if keys.element_size() != 8 or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous 64-bit tensor")
+    nd0 = np.ascontiguousarray(nd0_re, dtype=np.int64)
+    if nd0.shape != (int(n_replicas),):
+        raise ValueError("nd0_re needs one value per replica")
+    spec, o, out, keep = _obs_args(int(n_replicas), pauli, psi, want_eps)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib().qmc_observe_noalloc(int(n), int(n_replicas), ctypes.c_void_p(keys.data_ptr()),
+                                   ctypes.c_void_p(vals.data_ptr()), m,
+                                   _ptr(nd0, ctypes.c_int64), ctypes.byref(spec),
+                                   ctypes.byref(out), ctypes.c_void_p(stream.cuda_stream))
+    if rc:
+        raise QMCError(rc, "qmc_observe_noalloc failed")
+    return _obs_result(o, len(pauli))
+
 
 def initiator_threshold(xi, n_diag):
     """The initiator threshold in whole walkers for a fraction xi of N^diag (rounded up, exact

@@ -71,4 +71,8 @@ int qmck_observe(hipStream_t st, const uint64_t* pk, const int2* pv, void* count
                  uint64_t max_per_replica);
 int qmck_lookup(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters, uint32_t cur,
                 uint32_t kbits, const uint64_t* keys, uint32_t nk, uint32_t nrep, int64_t* out);
+// out[r] (device, nrep + 1 words) = first record of replica r of the sorted store whose size is
+// n_store[0] of the Counters image at `counters`; out[nrep] = that size.
+int qmck_replica_bounds(hipStream_t st, const uint64_t* keys, const void* counters,
+                        uint32_t kbits, uint32_t nrep, uint64_t* out);
 }

@@ -1288,6 +1288,21 @@ __global__ __launch_bounds__(kBlock) void k_observe(const uint64_t* __restrict__
   }
 }
 
+// out[r] = the first record of replica r in the sorted composite keys[0, *count), r < nrep, and
+// out[nrep] = *count (one binary search per thread).
+__global__ void k_replica_bounds(const uint64_t* __restrict__ keys,
+                                 const uint64_t* __restrict__ count, uint32_t kbits,
+                                 uint32_t nrep, uint64_t* __restrict__ out) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n = *count;
+  if (r > nrep) return;
+  if (r == nrep || (r > 0 && kbits >= 64)) {
+    out[r] = n;
+    return;
+  }
+  out[r] = r == 0 ? 0 : lower_bound64(keys, n, (uint64_t)r << kbits);
+}
+
 // Values at given keys of every replica: out[(rep * nk + k) * 2 + {0,1}].
 __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t* __restrict__ pk,
                                                    const int2* __restrict__ pv,
@@ -1529,6 +1544,14 @@ int qmck_observe(hipStream_t st, const uint64_t* pk, const int2* pv, void* count
                      out_stride * sizeof(unsigned long long), st, pk, pv,
                      (const Counters*)counters, cur, n, key_layout(kbits), n_pauli, pxz, want_eps,
                      out, out_stride);
+  return (int)hipGetLastError();
+}
+
+int qmck_replica_bounds(hipStream_t st, const uint64_t* keys, const void* counters,
+                        uint32_t kbits, uint32_t nrep, uint64_t* out) {
+  const uint32_t g = (nrep + 1 + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_replica_bounds, dim3(g), dim3(kBlock), 0, st, keys,
+                     &((const Counters*)counters)->n_store[0], kbits, nrep, out);
   return (int)hipGetLastError();
 }
 

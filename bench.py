@@ -529,5 +529,17 @@ def main_batch(args, kind):
     print(json.dumps(res), flush=True)
 
 
+def release_device():
+    """Everything this process holds on the device is given back before the interpreter exits:
+    contexts are closed by then, so only torch's cached blocks remain."""
+    import gc
+    import torch
+    gc.collect()
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+
 if __name__ == "__main__":
     main()
+    release_device()

@@ -241,6 +241,7 @@ class QMC:
         if getattr(self, "_ctx", None):
             lib().qmc_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+        self._ws = None  # the device workspace goes back to torch's allocator now
 
     def __del__(self):
         try:

@@ -76,6 +76,18 @@ typedef struct {
   uint64_t walker_target;   /* N^diag of the eq. (3) paragraph; only used for reporting */
   uint64_t store_capacity;  /* occupied keys per replica the store can hold */
   uint64_t spawn_capacity;  /* child records per replica per step */
+  /* Population control (FCIQMC background paragraph; the update rule of Booth, Thom & Alavi,
+   * J. Chem. Phys. 131, 054106 (2009)).  shift_mode 0 (default): the shift of each replica is
+   * the constant of qmc_set_shift (0 unless set; the paper needs none, the Liouvillian being
+   * trace preserving).  shift_mode 1: after every step whose index is a multiple of
+   * shift_period (A >= 1), a replica whose N^tot has reached shift_target takes its N^tot as
+   * the reference (the first time) or updates its shift, S <- S - shift_zeta / (A dt) *
+   * ln(N^tot(s) / N^tot(s - A)) (FP64, natural logarithm; an empty replica keeps S).  The shift
+   * adds to the death coefficient (L_diag + S) and biases the estimators.  Euler only. */
+  uint32_t shift_mode;
+  double shift_zeta;        /* damping zeta >= 0 */
+  uint32_t shift_period;    /* A */
+  uint64_t shift_target;    /* N^tot at which a replica's shift starts to vary */
 } qmc_config;
 
 /* H(t) = sum_m s_m(t) h[m] with real weights s_m(t) given per step; L_k = sum of the monomials
@@ -145,7 +157,8 @@ int qmc_step_path(qmc_ctx* ctx, int32_t path);
  *   N(s+1) = N(s) + round(3/2 dt L(t_s) N(s)) + round(-1/2 dt L(t_{s-1}) N(s-1)),
  * each term rounded as in the Euler step from its own table -- Q32 of scale * (dt * (w * kappa))
  * with scale 3/2 and -1/2 -- and its own Philox stream (0 for N(s), 1 for N(s-1), whose diagonal
- * is a record of its own rather than a change of N(s-1)).  The context keeps N(s-1) and the
+ * is a record of its own rather than a change of N(s-1)).  Refused (QMC_ERR_ARG) with the
+ * variable shift.  The context keeps N(s-1) and the
  * weights of step s-1; without them (after qmc_init, qmc_set_integrator or qmc_pulse) the next
  * step is an Euler step.  Switching clears N(s-1).  QMC_ERR_ARG for another value.  An AB2
  * step whose two tables have more than 257 column groups between them is refused by qmc_step
@@ -170,8 +183,9 @@ int qmc_pulse(qmc_ctx* ctx, uint64_t x, uint64_t z);
 /* The same for a batch: circuit c takes P = X^x[c] Z^z[c] (arrays of n_circuits entries). */
 int qmc_pulse_batch(qmc_ctx* ctx, const uint64_t* x, const uint64_t* z);
 
-/* Constant diagonal shift S for one replica (death coefficient L_diag + S).  The paper needs
- * none (the Liouvillian is trace preserving); S != 0 biases the estimator. */
+/* Diagonal shift S of one replica (death coefficient L_diag + S): the constant value, or the
+ * current value of a variable shift (shift_mode 1), which later updates start from.  The paper
+ * needs none (the Liouvillian is trace preserving); S != 0 biases the estimator. */
 int qmc_set_shift(qmc_ctx* ctx, uint32_t replica, double shift);
 
 /* Initiator approximation (End Matter on simulation methodology, last paragraph): from the next
@@ -250,6 +264,8 @@ typedef struct {
   double* pauli_val;         /* [R][n_pauli][2] */
   double* fidelity;          /* [R][2] (Re, Im) */
   double* eps;               /* [R] */
+  double* shift;             /* [R] the shift S now: nonzero means biased estimators (not
+                                written by qmc_observe_noalloc, which has no context) */
 } qmc_obs_out;
 
 /* Estimators of the current state (any NULL output pointer is skipped). */

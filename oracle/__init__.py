@@ -76,6 +76,9 @@ def lib():
                                        P(ctypes.c_int)]
         L.orc_pulse.argtypes = [ctypes.c_void_p, u64, u64]
         L.orc_set_shift.argtypes = [ctypes.c_void_p, u32, dbl]
+        L.orc_get_shift.argtypes = [ctypes.c_void_p, u32]
+        L.orc_get_shift.restype = dbl
+        L.orc_set_shift_control.argtypes = [ctypes.c_void_p, ctypes.c_int, dbl, u32, u64]
         L.orc_set_initiator.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.orc_set_replica_base.argtypes = [ctypes.c_void_p, u32]
         i8p = P(ctypes.c_int8)
@@ -277,6 +280,14 @@ class Oracle:
 
     def set_shift(self, replica, shift):
         _check(lib().orc_set_shift(self._ctx, int(replica), float(shift)), "set_shift")
+
+    def shift(self, replica):
+        return lib().orc_get_shift(self._ctx, int(replica))
+
+    def set_shift_control(self, mode, zeta=0.0, period=1, target=0):
+        """Variable shift (FCIQMC background paragraph; Booth et al. 2009): mode 1 = on."""
+        _check(lib().orc_set_shift_control(self._ctx, int(mode), float(zeta), int(period),
+                                           int(target)), "set_shift_control")
 
     def set_replica_base(self, base):
         """Philox stream ids base .. base + R - 1 for this context's replicas (one circuit of a

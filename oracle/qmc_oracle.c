@@ -146,6 +146,17 @@ struct orc_ctx {
   /* Spawn proposal (reading R18): kind 0 = the comb, 1 uniform, 2 heat-bath, 3 MLP scores;
    * prop_k samples per parent; the MLP's int8 weights, int32 biases and hidden shift. */
   uint32_t prop_kind, prop_k;
+  /* Variable shift (population control of the FCIQMC background paragraph, the update rule of
+   * Booth, Thom & Alavi 2009): mode 1 turns it on.  At every step s that is a multiple of
+   * shift_period = A, a replica whose N^tot has reached shift_target starts to follow
+   * S <- S - zeta / (A dt) * ln(N^tot(s) / N^tot(s - A)); shift_on marks the replicas that have
+   * started, shift_ref holds their N^tot at the last update. */
+  int shift_mode;
+  double shift_zeta;
+  uint32_t shift_period;
+  uint64_t shift_target;
+  uint8_t* shift_on;     /* [R] */
+  uint64_t* shift_ref;   /* [R] */
   int8_t mlp_w1[ORC_MLP_HIDDEN][ORC_MLP_IN];
   int32_t mlp_b1[ORC_MLP_HIDDEN];
   int8_t mlp_w2[ORC_MLP_OUT][ORC_MLP_HIDDEN];
@@ -242,10 +253,13 @@ int orc_create(uint32_t n_qubits, uint32_t n_replicas, uint64_t seed, double dt,
   }
   c->st = (store_t*)calloc(n_replicas, sizeof(store_t));
   c->shift = (double*)calloc(n_replicas, sizeof(double));
+  c->shift_on = (uint8_t*)calloc(n_replicas, 1);
+  c->shift_ref = (uint64_t*)calloc(n_replicas, sizeof(uint64_t));
   c->nchild = (uint64_t*)calloc(n_replicas, sizeof(uint64_t));
   c->prev = (store_t*)calloc(n_replicas, sizeof(store_t));
   c->w_prev = (double*)calloc((size_t)n_h + n_l + 1, sizeof(double));
-  if (!c->st || !c->shift || !c->nchild || !c->prev || !c->w_prev) {
+  if (!c->st || !c->shift || !c->shift_on || !c->shift_ref || !c->nchild || !c->prev ||
+      !c->w_prev) {
     orc_destroy(c);
     return ORC_ERR_NOMEM;
   }
@@ -279,6 +293,8 @@ void orc_destroy(orc_ctx* c) {
   free(c->prev);
   free(c->w_prev);
   free(c->shift);
+  free(c->shift_on);
+  free(c->shift_ref);
   free(c->nchild);
   free(c->terms);
   free(c);
@@ -867,10 +883,53 @@ static int one_step(orc_ctx* c, const double* s, const double* gamma, int thread
   return rc;
 }
 
+/* N^tot = sum |re| + |im| of one replica (eq. (3) paragraph). */
+static uint64_t ntot_of(const store_t* st) {
+  uint64_t t = 0;
+  for (uint64_t p = 0; p < st->n; ++p)
+    t += (uint64_t)llabs((int64_t)st->re[p]) + (uint64_t)llabs((int64_t)st->im[p]);
+  return t;
+}
+
+/* The variable-shift update after a step (see shift_mode): at steps that are multiples of the
+ * period, a replica that has reached the target starts (its N^tot becomes the reference), and
+ * a started one takes S <- S - zeta / (A dt) * ln(N^tot / reference) and a new reference.  An
+ * empty replica, or one whose reference is zero, keeps its shift. */
+static void shift_update(orc_ctx* c) {
+  if (c->shift_mode != 1 || c->step % c->shift_period != 0) return;
+  for (uint32_t r = 0; r < c->R; ++r) {
+    const uint64_t nt = ntot_of(&c->st[r]);
+    if (!c->shift_on[r]) {
+      if (nt >= c->shift_target) {
+        c->shift_on[r] = 1;
+        c->shift_ref[r] = nt;
+      }
+      continue;
+    }
+    if (nt > 0 && c->shift_ref[r] > 0)
+      c->shift[r] = c->shift[r] - (c->shift_zeta / ((double)c->shift_period * c->dt)) *
+                                      log((double)nt / (double)c->shift_ref[r]);
+    c->shift_ref[r] = nt;
+  }
+}
+
+int orc_set_shift_control(orc_ctx* c, int mode, double zeta, uint32_t period, uint64_t target) {
+  if (mode != 0 && mode != 1) return ORC_ERR_ARG;
+  if (mode == 1 && (period == 0 || !isfinite(zeta) || zeta < 0.0 || c->ab2)) return ORC_ERR_ARG;
+  c->shift_mode = mode;
+  c->shift_zeta = zeta;
+  c->shift_period = period ? period : 1;
+  c->shift_target = target;
+  memset(c->shift_on, 0, c->R);
+  memset(c->shift_ref, 0, c->R * sizeof(uint64_t));
+  return ORC_OK;
+}
+
 int orc_step(orc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) {
   for (uint32_t k = 0; k < nsteps; ++k) {
     int rc = one_step(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, 1);
     if (rc) return rc;
+    shift_update(c);
   }
   return ORC_OK;
 }
@@ -888,6 +947,7 @@ int orc_step_threads(orc_ctx* c, uint32_t nsteps, const double* s, const double*
   for (uint32_t k = 0; k < nsteps; ++k) {
     int rc = one_step(c, s + (size_t)k * c->n_h, gamma + (size_t)k * c->n_l, used);
     if (rc) return rc;
+    shift_update(c);
   }
   return ORC_OK;
 }
@@ -896,6 +956,7 @@ int orc_step_threads(orc_ctx* c, uint32_t nsteps, const double* s, const double*
  * next step is an Euler step unless orc_set_prev supplies N(s-1) and the weights of step s-1. */
 int orc_set_integrator(orc_ctx* c, int ab2) {
   if (ab2 != 0 && ab2 != 1) return ORC_ERR_ARG;
+  if (ab2 && c->shift_mode) return ORC_ERR_ARG;  /* the variable shift runs with Euler */
   if (ab2 && c->prop_kind) return ORC_ERR_ARG;
   c->ab2 = ab2;
   c->have_prev = 0;
@@ -1007,6 +1068,10 @@ int orc_set_shift(orc_ctx* c, uint32_t replica, double shift) {
 }
 
 uint32_t orc_get_step(const orc_ctx* c) { return c->step; }
+
+double orc_get_shift(const orc_ctx* c, uint32_t replica) {
+  return replica < c->R ? c->shift[replica] : 0.0;
+}
 
 void orc_counters(const orc_ctx* c, uint64_t* walker_steps, uint64_t* key_steps,
                   uint64_t* child_steps, uint64_t* max_children) {

@@ -101,6 +101,14 @@ int orc_export_prev(const orc_ctx* c, uint32_t replica, uint64_t* keys, int32_t*
 int orc_pulse(orc_ctx* c, uint64_t x, uint64_t z);
 /* Constant diagonal shift S added to the death coefficient (0 = none, the paper's setting). */
 int orc_set_shift(orc_ctx* c, uint32_t replica, double shift);
+/* The shift of one replica now. */
+double orc_get_shift(const orc_ctx* c, uint32_t replica);
+/* Variable shift (population control of the FCIQMC background paragraph; update rule of Booth,
+ * Thom & Alavi 2009): mode 1 = on.  After every step whose index is a multiple of `period`
+ * (A), a replica whose N^tot has reached `target` starts to follow
+ * S <- S - zeta / (A dt) * ln(N^tot(s) / N^tot(s - A)).  Biased (the Liouvillian needs no shift);
+ * Euler only.  Switching resets which replicas have started. */
+int orc_set_shift_control(orc_ctx* c, int mode, double zeta, uint32_t period, uint64_t target);
 /* Initiator approximation (End Matter on simulation methodology): parents with |re| + |im| below
  * min_walkers spawn only onto keys occupied in N(s) (reading R17).  0 = off. */
 int orc_set_initiator(orc_ctx* c, uint64_t min_walkers);

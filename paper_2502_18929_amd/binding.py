@@ -42,7 +42,9 @@ class Config(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("n_replicas", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("dt", ctypes.c_double),
                 ("walker_target", ctypes.c_uint64), ("store_capacity", ctypes.c_uint64),
-                ("spawn_capacity", ctypes.c_uint64)]
+                ("spawn_capacity", ctypes.c_uint64), ("shift_mode", ctypes.c_uint32),
+                ("shift_zeta", ctypes.c_double), ("shift_period", ctypes.c_uint32),
+                ("shift_target", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -73,7 +75,8 @@ PD = ctypes.POINTER(ctypes.c_double)
 
 class ObsOut(ctypes.Structure):
     _fields_ = [("n_occ", P64), ("n_tot", P64), ("ndiag", PI64), ("pauli", PI64), ("eps2", P64),
-                ("trace", PD), ("theta", PD), ("pauli_val", PD), ("fidelity", PD), ("eps", PD)]
+                ("trace", PD), ("theta", PD), ("pauli_val", PD), ("fidelity", PD), ("eps", PD),
+                ("shift", PD)]
 
 
 _lib = None
@@ -151,23 +154,26 @@ class QMC:
     _integrator = "euler"  # the context's default time integrator
 
     def __init__(self, n, n_replicas, seed, dt, h, lops, keys, re, im, store_capacity,
-                 spawn_capacity, walker_target=0, stream=None):
+                 spawn_capacity, walker_target=0, stream=None, shift=None):
+        """shift = None (constant shift, 0 unless set_shift) or a dict of the variable-shift
+        control: {"zeta": ..., "period": A, "target": N^tot at which it starts}."""
         self._setup(n, n_replicas, seed, dt, [(h, lops, keys, re, im)], store_capacity,
-                    spawn_capacity, walker_target, stream)
+                    spawn_capacity, walker_target, stream, shift)
 
     @classmethod
     def batch(cls, n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity,
-              stream=None):
+              stream=None, shift=None):
         """A batch of circuits on n qubits: circuits = [(h, lops, keys, re, im), ...] (a
         smaller circuit uses only its low qubits).  Replica r of circuit c is segment
         c * n_replicas + r for export/import/observe/set_shift; step() takes the weights of all
         circuits side by side (circuit 0's columns first)."""
         self = cls.__new__(cls)
-        self._setup(n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity, 0, stream)
+        self._setup(n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity, 0, stream,
+                    shift)
         return self
 
     def _setup(self, n, n_replicas, seed, dt, circuits, store_capacity, spawn_capacity,
-               walker_target, stream):
+               walker_target, stream, shift=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libqmc needs a HIP device; none is visible")
@@ -199,8 +205,11 @@ class QMC:
             im_p[ci] = _ptr(im, ctypes.c_int32)
             n0[ci] = len(keys)
         self._models, self._n0 = models, n0
+        sh = shift or {}
         self._cfg = Config(self.n, self.Rc, int(seed), float(dt), int(walker_target),
-                           int(store_capacity), int(spawn_capacity))
+                           int(store_capacity), int(spawn_capacity), 1 if shift else 0,
+                           float(sh.get("zeta", 0.0)), int(sh.get("period", 1)),
+                           int(sh.get("target", 0)))
         nb = ctypes.c_size_t()
         rc = L.qmc_workspace_bytes_batch(ctypes.byref(self._cfg), C, models, ctypes.byref(nb))
         if rc:
@@ -222,7 +231,7 @@ class QMC:
 
     @classmethod
     def from_workload(cls, w, store_capacity=None, spawn_capacity=None, n_replicas=None,
-                      seed=None):
+                      seed=None, shift=None):
         R = w.n_replicas if n_replicas is None else n_replicas
         if store_capacity is None:
             store_capacity = min(1 << (2 * w.n), 1 << 20)
@@ -230,7 +239,7 @@ class QMC:
             spawn_capacity = store_capacity
         return cls(w.n, R, w.seed if seed is None else seed, w.dt, w.h, w.lops, w.init_keys,
                    w.init_re, w.init_im, store_capacity, spawn_capacity,
-                   walker_target=w.walker_target)
+                   walker_target=w.walker_target, shift=shift)
 
     def _check(self, rc):
         if rc:
@@ -448,16 +457,19 @@ def _obs_args(R, pauli, psi, want_eps):
              ndiag=np.zeros((R, 2), np.int64), pauli=np.zeros((R, max(npl, 1), 2), np.int64),
              eps2=np.zeros((R, 2), np.uint64), trace=np.zeros(R), theta=np.zeros(R),
              pauli_val=np.zeros((R, max(npl, 1), 2)), fidelity=np.zeros((R, 2)),
-             eps=np.zeros(R))
+             eps=np.zeros(R), shift=np.zeros(R))
     out = ObsOut(_ptr(o["n_occ"], ctypes.c_uint64), _ptr(o["n_tot"], ctypes.c_uint64),
                  _ptr(o["ndiag"], ctypes.c_int64), _ptr(o["pauli"], ctypes.c_int64),
                  _ptr(o["eps2"], ctypes.c_uint64), _ptr(o["trace"], ctypes.c_double),
                  _ptr(o["theta"], ctypes.c_double), _ptr(o["pauli_val"], ctypes.c_double),
-                 _ptr(o["fidelity"], ctypes.c_double), _ptr(o["eps"], ctypes.c_double))
+                 _ptr(o["fidelity"], ctypes.c_double), _ptr(o["eps"], ctypes.c_double),
+                 _ptr(o["shift"], ctypes.c_double))
     return spec, o, out, (px, pz, pidx, pre, pim)
 
 
 def _obs_result(o, npl):
+    # a nonzero shift (constant or variable population control) biases the estimators
+    o["biased"] = bool(np.any(o["shift"] != 0))
     o["pauli"] = o["pauli"][:, :npl]
     o["pauli_val"] = o["pauli_val"][:, :npl]
     o["eps2_int"] = [int(a) + (int(b) << 64) for a, b in o["eps2"]]
@@ -512,7 +524,7 @@ def coeff_table(n, dt, h, lops, s, gamma, n_replicas=1, scale=1.0):
     off = np.zeros(len(lops) + 1, dtype=np.uint32)
     for k, op in enumerate(lops):
         off[k + 1] = off[k] + len(op)
-    cfg = Config(int(n), int(n_replicas), 0, float(dt), 0, 1, 1)
+    cfg = Config(int(n), int(n_replicas), 0, float(dt), 0, 1, 1, 0, 0.0, 1, 0)
     model = Model(len(h), hm, len(lops), _ptr(off, ctypes.c_uint32), lm)
     s = np.ascontiguousarray(s if len(h) else np.zeros(1), dtype=np.float64)
     g = np.ascontiguousarray(gamma if len(lops) else np.zeros(1), dtype=np.float64)

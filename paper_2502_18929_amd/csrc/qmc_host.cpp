@@ -156,6 +156,8 @@ struct qmc_ctx {
   std::vector<double> shift;
   std::vector<int64_t> nd0_re;
   std::vector<int64_t> qshift_dev;  // the Q32 shifts last uploaded to the device (both terms)
+  std::vector<uint8_t> shift_on;     // variable shift: the replica has reached shift_target
+  std::vector<uint64_t> shift_ref;   // variable shift: N^tot at the last update
   uint8_t* pinned = nullptr;     // table staging: kTableArea bytes, then the window offsets
   uint8_t* pinned_small = nullptr;  // counters and estimator staging
   size_t pinned_small_bytes = 0;
@@ -424,6 +426,12 @@ int validate(const qmc_config* cfg, const qmc_model* m, std::string& why) {
     why = "dt must be positive and finite";
     return QMC_ERR_ARG;
   }
+  if (cfg->shift_mode > 1 ||
+      (cfg->shift_mode == 1 && (cfg->shift_period == 0 || !std::isfinite(cfg->shift_zeta) ||
+                                cfg->shift_zeta < 0.0))) {
+    why = "shift_mode 0 or 1; a variable shift needs shift_period >= 1 and shift_zeta >= 0";
+    return QMC_ERR_ARG;
+  }
   const uint64_t qmask = cfg->n_qubits >= 32 ? 0xFFFFFFFFull : ((1ull << cfg->n_qubits) - 1);
   for (uint32_t i = 0; i < m->n_h; ++i)
     if ((m->h[i].x | m->h[i].z) & ~qmask) {
@@ -607,6 +615,8 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
   c->ws = (uint8_t*)d_workspace;
   c->stream = (hipStream_t)hip_stream;
   c->shift.assign(c->R, 0.0);
+  c->shift_on.assign(c->R, 0);
+  c->shift_ref.assign(c->R, 0);
   c->nd0_re.assign(c->R, 0);
   for (uint32_t ci = 0; ci < c->C; ++ci) {
     int64_t nd = 0;
@@ -977,11 +987,79 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
 
 }  // namespace
 
+namespace {
+
+// Per-replica N^tot of the current store (the eq. (3) estimator pass with no observables),
+// exact integers, synchronizing the stream.
+int replica_ntot(qmc_ctx* c, std::vector<uint64_t>& nt) {
+  const uint32_t R = c->R, stride = 5;
+  unsigned long long* dout = c->at<unsigned long long>(c->L.obs_out);
+  HIPCHK(c, hipMemsetAsync(dout, 0, (size_t)R * stride * 8, c->stream));
+  HIPCHK(c, qmck_observe(c->stream, c->sk(c->cur), c->sv(c->cur), c->counters(), c->cur, c->n,
+                         c->kbits, R, 0, c->at<uint64_t>(c->L.obs_in), 0, dout, stride,
+                         c->cfg.store_capacity));
+  std::vector<unsigned long long> acc((size_t)R * stride);
+  HIPCHK(c, hipMemcpyAsync(acc.data(), dout, acc.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  nt.resize(R);
+  for (uint32_t r = 0; r < R; ++r) nt[r] = acc[(size_t)r * stride];
+  return QMC_OK;
+}
+
+// The variable-shift update after the step that brought the counter to a multiple of the
+// period (qmc_config): a replica that reaches the target takes its N^tot as the reference, a
+// started one updates S from ln(N^tot / reference) and takes a new reference.  The shifts are
+// checked against the Q32 bound when the next step's tables are built.
+int shift_update(qmc_ctx* c) {
+  std::vector<uint64_t> nt;
+  int rc = replica_ntot(c, nt);
+  if (rc) return rc;
+  const double rate = c->cfg.shift_zeta / ((double)c->cfg.shift_period * c->cfg.dt);
+  for (uint32_t r = 0; r < c->R; ++r) {
+    if (!c->shift_on[r]) {
+      if (nt[r] >= c->cfg.shift_target) {
+        c->shift_on[r] = 1;
+        c->shift_ref[r] = nt[r];
+      }
+      continue;
+    }
+    if (nt[r] > 0 && c->shift_ref[r] > 0)
+      c->shift[r] = c->shift[r] - rate * std::log((double)nt[r] / (double)c->shift_ref[r]);
+    c->shift_ref[r] = nt[r];
+  }
+  return QMC_OK;
+}
+
+int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma);
+
+}  // namespace
+
 int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) {
   if (!c) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
   if (nsteps == 0) return QMC_OK;
   if ((c->n_h && !s) || (c->n_l && !gamma)) return fail(c, QMC_ERR_ARG, "missing weights");
+  if (c->cfg.shift_mode != 1) return step_impl(c, nsteps, s, gamma);
+  // Variable shift: runs of steps up to the next multiple of the period, each followed by the
+  // shift update.
+  const uint32_t A = c->cfg.shift_period;
+  uint32_t done = 0;
+  while (done < nsteps) {
+    const uint32_t k = std::min<uint32_t>(nsteps - done, A - c->step % A);
+    int rc = step_impl(c, k, s + (size_t)done * c->n_h, gamma + (size_t)done * c->n_l);
+    if (rc) return rc;
+    done += k;
+    if (c->step % A == 0) {
+      rc = shift_update(c);
+      if (rc) return rc;
+    }
+  }
+  return QMC_OK;
+}
+
+namespace {
+
+int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) {
   const bool ab2 = c->integrator == 1;
   // AB2 without N(s-1): the first step of this call is an Euler step of its own.
   const uint32_t euler_first = ab2 && !c->have_prev ? 1u : 0u;
@@ -1255,6 +1333,8 @@ int qmc_step(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma) 
   return QMC_OK;
 }
 
+}  // namespace
+
 int qmc_step_path(qmc_ctx* c, int32_t path) {
   if (!c || path < 0 || path > 2) return QMC_ERR_ARG;
   c->path = path;
@@ -1264,6 +1344,8 @@ int qmc_step_path(qmc_ctx* c, int32_t path) {
 
 int qmc_set_integrator(qmc_ctx* c, int32_t integrator) {
   if (!c || integrator < 0 || integrator > 1) return QMC_ERR_ARG;
+  if (integrator == 1 && c->cfg.shift_mode == 1)
+    return fail(c, QMC_ERR_ARG, "the variable shift runs with the Euler step");
   if (integrator == 1 && c->C > 1) return fail(c, QMC_ERR_ARG, "AB2 runs one circuit per context");
   if (integrator == 1 && c->prop.kind)
     return fail(c, QMC_ERR_ARG, "AB2 runs without spawn proposals");
@@ -1536,6 +1618,7 @@ int qmc_observe(qmc_ctx* c, const qmc_obs_spec* spec, qmc_obs_out* out) {
     const double nd0 = (double)c->nd0_re[r];
     if (out->n_occ) out->n_occ[r] = bounds[r + 1] - bounds[r];
     if (out->n_tot) out->n_tot[r] = a[0];
+    if (out->shift) out->shift[r] = c->shift[r];
     const int64_t dre = (int64_t)a[1], dim = (int64_t)a[2];
     if (out->ndiag) {
       out->ndiag[2 * r] = dre;

@@ -335,6 +335,93 @@ def test_ab2_scalar_closed_form_is_the_recurrence():
             assert _ab2_scalar(h, s_) == pytest.approx(y[s_], rel=1e-12)
 
 
+def _ntot(o, r):
+    k, a, b = o.export(r)
+    return int(np.abs(a.astype(np.int64)).sum() + np.abs(b.astype(np.int64)).sum())
+
+
+def test_variable_shift_converges_to_minus_the_diagonal(orc):
+    """Variable shift (FCIQMC background paragraph; Booth et al. 2009) on a death-only column:
+    one qubit under pure dephasing (L_diag = -2 gamma = -1 on |1><0|).  The update every A steps,
+    S <- S - zeta/(A dt) ln(N(s)/N(s-A)), drives S to -L_diag = 1 and N^tot to a plateau; both
+    follow the deterministic map S' = S - (zeta/dt) ln(1 + dt (L_diag + S)),
+    N' = N (1 + dt (L_diag + S))^A that the rule gives for the expected populations (one key:
+    the comb moves it by less than a walker per step), after a first period that only takes the
+    reference."""
+    n, g, dt, A, zeta, periods, R = 1, 0.5, 0.01, 10, 0.3, 40, 16
+    o = orc.Oracle(n, R, 21, dt, [], [[(0, 1, 1.0)]], [1], [100000], [0])
+    o.set_shift_control(1, zeta, A, 0)
+    o.step(np.zeros((A * periods, 0)), np.full((A * periods, 1), g))
+    S, N = 0.0, 100000.0
+    for k in range(periods):
+        f = 1 + dt * (-2 * g + S)
+        N *= f ** A
+        if k > 0:  # the first multiple of A only takes the reference (target 0 reached)
+            S = S - (zeta / (A * dt)) * (A * math.log(f))
+    shifts = np.array([o.shift(r) for r in range(R)])
+    ntots = np.array([_ntot(o, r) for r in range(R)])
+    assert abs(S - 1.0) < 1e-4                         # the map's fixed point
+    assert np.all(np.abs(shifts - S) < 0.02), shifts
+    assert abs(shifts.mean() - S) < 0.005
+    assert abs(ntots.mean() / N - 1) < 1e-3, (ntots.mean(), N)
+
+
+def test_variable_shift_waits_for_the_target_then_updates_once_per_period(orc):
+    """A growing population (diagonal key, L_diag = 0, constant shift 2 until the variable shift
+    starts): N^tot first reaches the target 5000 at step 90 (1000 x 1.02^s, the comb moving a
+    single key by less than a walker per step), so S stays exactly 2 through step 99 and the
+    first update, at step 100, gives S = 2 - zeta/(A dt) ln(N(100)/N(90))."""
+    n, dt, A, zeta = 1, 0.01, 10, 0.5
+    o = orc.Oracle(n, 1, 3, dt, [], [[(0, 1, 1.0)]], [0], [1000], [0])
+    o.set_shift(0, 2.0)
+    o.set_shift_control(1, zeta, A, 5000)
+    step = lambda k: o.step(np.zeros((k, 0)), np.full((k, 1), 0.3))  # dephasing: 0 on |0><0|
+    step(80)
+    n80 = _ntot(o, 0)
+    assert n80 < 5000 and abs(n80 - 1000 * 1.02 ** 80) < 80 and o.shift(0) == 2.0
+    step(10)
+    n90 = _ntot(o, 0)
+    assert n90 >= 5000 and o.shift(0) == 2.0           # started: reference taken, no update
+    step(9)
+    assert o.shift(0) == 2.0
+    step(1)
+    n100 = _ntot(o, 0)
+    expect = 2.0 - zeta / (A * dt) * math.log(n100 / n90)
+    assert o.shift(0) == pytest.approx(expect, abs=1e-12)
+    assert o.shift(0) == pytest.approx(2.0 - zeta * 10 * math.log(1.02) / (A * dt), abs=2e-3)
+
+
+def test_variable_shift_with_zero_damping_is_the_constant_shift(orc):
+    """zeta = 0 leaves S at its set value: the trajectory equals the constant-shift one."""
+    w = W.config_ghz4()
+    a = orc.Oracle(w.n, 2, 5, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    b = orc.Oracle(w.n, 2, 5, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    for o in (a, b):
+        o.set_shift(1, 0.25)
+    b.set_shift_control(1, 0.0, 7, 0)
+    a.step(w.s[:120], w.gamma[:120])
+    b.step(w.s[:120], w.gamma[:120])
+    for r in range(2):
+        for x, y in zip(a.export(r), b.export(r)):
+            assert np.array_equal(x, y)
+    assert b.shift(1) == 0.25
+
+
+def test_variable_shift_refuses_ab2_and_bad_settings(orc):
+    w = W.config_ghz4()
+    o = orc.Oracle(w.n, 1, 5, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    for bad in [(2, 0.1, 1, 0), (1, -0.1, 1, 0), (1, 0.1, 0, 0), (1, float("nan"), 5, 0)]:
+        with pytest.raises(orc.OracleError):
+            o.set_shift_control(*bad)
+    o.set_shift_control(1, 0.1, 5, 0)
+    with pytest.raises(orc.OracleError):
+        o.set_integrator("ab2")
+    o.set_shift_control(0)
+    o.set_integrator("ab2")
+    with pytest.raises(orc.OracleError):
+        o.set_shift_control(1, 0.1, 5, 0)
+
+
 def _run_oracle_obs(orc, w, R):
     o = orc.Oracle(w.n, R, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
     obs = [(x, z) for _, x, z, _ in w.pauli_obs]

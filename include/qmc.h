@@ -293,7 +293,7 @@ int qmc_observe(qmc_ctx* ctx, const qmc_obs_spec* spec, qmc_obs_out* out);
 #define QMC_NOALLOC_MAX_PAULI 64
 #define QMC_NOALLOC_MAX_PSI 32
 #define QMC_NOALLOC_MAX_LOOKUPS 32768
-#define QMC_NOALLOC_SCRATCH_BYTES 1360128
+#define QMC_NOALLOC_SCRATCH_BYTES 1359104
 int qmc_observe_noalloc(uint32_t n_qubits, uint32_t n_replicas, const uint64_t* d_keys,
                         const int32_t* d_vals, uint64_t n, const int64_t* nd0_re,
                         const qmc_obs_spec* spec, qmc_obs_out* out, void* hip_stream);
@@ -332,14 +332,15 @@ typedef struct {
 int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
 
 /* Live timing of one kernel class with HIP events recorded on the context's stream around
- * every launch of that class in qmc_step: kernel_class 0 = streamed spawn, 1 = streamed child
- * sort (all radix passes), 2 = streamed merge (partition + annihilation + next spawn), 3 = one
- * launch of the fused persistent kernel (a batch of whole steps), -1 = off.  qmc_profile resets
- * the totals.  qmc_profile_read returns the summed milliseconds, the number of timed launches
- * and, in `covered` (may be NULL), the counter sums (walker_steps, key_steps, child_steps,
- * out_steps, and in `step` the number of steps) of exactly the steps that the timed launches
- * ran -- for classes 1, 2 and 3; zeros for class 0, which runs for the first step of a batch
- * only (spawn_steps likewise).  The algorithmic bytes of the timed kernels follow from these sums. */
+ * every launch of that class in qmc_step: kernel_class 0 = streamed draws (the records of each
+ * step from its parents: death/cloning and children), 1 = streamed record sort (all radix
+ * passes), 2 = streamed annihilation (tile split points, tile output counts and offsets, and the
+ * merge), 3 = one launch of the fused persistent kernel (a batch of whole steps), -1 = off.
+ * qmc_profile resets the totals.  qmc_profile_read returns the summed milliseconds, the number of
+ * timed launches and, in `covered` (may be NULL), the counter sums (walker_steps, key_steps,
+ * child_steps, out_steps, spawn_steps, and in `step` the number of steps) of exactly the steps
+ * that the timed launches ran -- for classes 1, 2 and 3; zeros for class 0.  The algorithmic
+ * bytes of the timed kernels follow from these sums. */
 int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
 int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches, qmc_stats* covered);
 

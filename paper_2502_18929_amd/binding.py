@@ -425,8 +425,8 @@ class QMC:
         self._check(lib().qmc_step_path(self._ctx, {"auto": 0, "fused": 1, "streamed": 2}[path]))
 
     def profile(self, kernel_class):
-        """Time one kernel class with HIP events: 'spawn', 'sort', 'merge' (streamed path),
-        'fused' (one persistent launch) or None."""
+        """Time one kernel class with HIP events: 'spawn' (the draws of each step's records),
+        'sort', 'merge' (streamed path), 'fused' (one persistent launch) or None."""
         cls = {None: -1, "spawn": 0, "sort": 1, "merge": 2, "fused": 3}[kernel_class]
         self._check(lib().qmc_profile(self._ctx, cls))
 

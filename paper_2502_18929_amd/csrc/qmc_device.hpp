@@ -18,18 +18,17 @@ constexpr int kMergeIpt = 4;         // merged items per thread
 constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kMergeSlack = kMaxGroups + 1;  // a key's run of children is at most one per group
 constexpr int kMergeCap = kMergeTile + kMergeSlack + 8;
-constexpr int kSpawnSeg = 512;       // per-wave LDS staging of child records in k_spawn
-constexpr int kMergeSpawnSeg = 256;  // the same inside the merge (aliases the child tile)
-constexpr int kMergeActive = kBlock + kWave;  // merge queue of active outputs: < 64 + one chunk
+constexpr int kSpawnSeg = 256;       // per-wave LDS staging of child records in k_spawn
+constexpr int kSpawnRound = 1024;    // parents k_spawn loads at once
+constexpr int kMergeActive = kBlock + kWave;  // spawn queue of active parents: < 64 + one chunk
+constexpr int kMergeQueue = 2 * kBlock;  // merge's queue of next-step parents (flushed when full)
 constexpr int kRadixBits = 11;       // digit width of the onesweep passes
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 6;        // ceil(64 / 11)
 constexpr int kSortIpt = 16;         // records per thread of a sort tile
 constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
-constexpr int kMergeTicketCounters = 8;  // k_merge tile tickets: counter b mod 8 serves block b
-constexpr int kMergeBlocks = 768;    // k_merge: three workgroups per CU (about 51 KB of LDS each)
-constexpr int kMergeOnlyBlocks = 1536;  // a merge that does not spawn: six per CU (about 23 KB)
+constexpr int kMergeBlocks = 1536;   // k_merge: six workgroups per CU (about 23 KB of LDS each)
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
 constexpr int kMaxCircuits = kMaxSegments;  // circuits of one batch (each needs a key range)
 constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)
@@ -79,16 +78,15 @@ struct Counters {
   uint64_t out_steps;      // running sum of annihilated output keys of every step
   uint64_t death_steps;    // running sum of nonzero diagonal (death/cloning) records of every
                            // step; child_steps - death_steps are the off-diagonal children
+  uint64_t n_active;       // parents of the next step queued by the merge (their combs can fire)
   uint32_t err;
   uint32_t err_step;
   uint32_t tile_counter;   // (unused)
   uint32_t resplits;       // key ranges re-cut inside the fused kernel (running sum)
   uint32_t sort_ticket[2][kMaxPasses + 2];  // onesweep tile tickets per step parity and pass
-  uint32_t merge_ticket[kMergeTicketCounters][32];  // merge tile tickets, one 128-byte line each
 };
 
 // Epoch tags of the look-back status words (never 0, distinct within a batch of <= 8000 steps).
-__host__ __device__ inline uint32_t merge_epoch(uint32_t step) { return 1u + step % 65535u; }
 __host__ __device__ inline uint32_t sort_epoch(uint32_t step, uint32_t pass) {
   return 1u + (step * 8u + pass) % 65535u;
 }
@@ -135,8 +133,13 @@ __device__ __forceinline__ int64_t comb_step(uint64_t& r, int64_t x) {
 // comb started at U is zero: the comb only emits when its running sum crosses 2^32.
 __device__ __forceinline__ bool comb_all_zero(uint64_t s, uint64_t q, uint32_t U) {
   if (q == 0 || s == 0) return true;
-  if (__umul64hi(s, q) != 0) return false;
-  const uint64_t p = s * q;
+  uint64_t p;
+  if (((s | q) >> 32) == 0) {
+    p = (uint64_t)(uint32_t)s * (uint32_t)q;  // the usual case: one 32 x 32 -> 64 product
+  } else {
+    if (__umul64hi(s, q) != 0) return false;
+    p = s * q;
+  }
   return p < (1ull << 32) - (uint64_t)U;
 }
 

@@ -103,7 +103,9 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.cv1 = take(L.cap_sort * 8);
   L.ghist = take((size_t)2 * qmc::kMaxPasses * qmc::kRadixBins * 4);
   L.sort_status = take(L.n_sort_status * 8);
-  L.status = take(L.max_tiles * 8);
+  // merge tile counts and offsets (max_tiles words), the count blocks' sums and offsets (one
+  // block per 256 tiles, plus the total), then the tiles' int32 count adjustments
+  L.status = take((L.max_tiles + (L.max_tiles + 255) / 256 + 1) * 8 + (L.max_tiles + 1) * 4);
   L.splits = take((L.max_tiles + 1) * 8);
   L.tab = take(kTableArea + kPersistTableBytes);  // slack: the fused kernel reads 8 KB
   L.qshift = take((size_t)c.n_replicas * 2 * 8);  // first / only term, then the second AB2 term
@@ -857,9 +859,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     const hipError_t e_ = (hipError_t)(x);       \
     if (e_ != hipSuccess) return e_;             \
   } while (0)
-    ENQ(qmck_batch_begin(st_q, dcnt, c->at<uint64_t>(c->L.status), c->L.max_tiles,
-                               c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
-                               2 * qmc::kMaxPasses * qmc::kRadixBins));
+    ENQ(qmck_batch_begin(st_q, dcnt, nullptr, 0, c->at<uint64_t>(c->L.sort_status),
+                         c->L.n_sort_status, c->ghist(0), 2 * qmc::kMaxPasses * qmc::kRadixBins));
     auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
       if (c->prof_class != cls) return hipSuccess;
       return hipEventRecord(c->prof_ev[2 * k + which], st_q);
@@ -890,16 +891,40 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
                           c->L.cap_child, c->sort_ipt));
       ENQ(mark(1, k, 1));
       const uint32_t cf = cb ^ (passes & 1);  // sorted children
+      // With the Euler step and the comb, the merge also queues the records of N(st + 1) whose
+      // combs can fire in step st + 1 (in the store buffer AB2 would use), and step st + 1 is
+      // drawn from them alone; otherwise it is drawn from the whole of N(st + 1).
+      const bool queue = more && nb == 2 && c->prop.kind == 0;
       ENQ(mark(2, k, 0));
       ENQ(qmck_merge(st_q, bk[b], bv[b], c->ck(cf), c->cv(cf), dcnt, cur, csel,
-                           c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), dtab,
-                           toff_next, toffB_next, c->Rc, qshA, qshB, st, c->cfg.seed, c->kbits, c->init_min,
-                           bk[(k + 1) % nb],
-                           bv[(k + 1) % nb], c->L.cap_store, c->L.cap_store + c->L.cap_child,
-                           c->ck(cf ^ 1), c->cv(cf ^ 1), c->L.cap_child, c->ghist(csel ^ 1),
-                           passes, &c->prop));
+                     c->at<uint2>(c->L.splits), c->at<uint64_t>(c->L.status), st, c->kbits,
+                     c->init_min, bk[(k + 1) % nb], bv[(k + 1) % nb], c->L.cap_store,
+                     c->L.cap_store + c->L.cap_child, c->ghist(csel ^ 1), dtab,
+                     queue ? toff_next : nullptr, c->Rc, qshA, c->cfg.seed, c->alt_k(1),
+                     c->alt_v(1)));
       ENQ(mark(2, k, 1));
       cb = cf ^ 1;
+      if (more) {
+        // the records of step st + 1 into the other child buffers: from N(st + 1) (or its queued
+        // records), and with AB2 the second term from N(st), this step's parents
+        ENQ(mark(0, k + 1, 0));
+        if (queue)
+          ENQ(qmck_spawn(st_q, c->alt_k(1), c->alt_v(1), dcnt, &dcnt->n_active, dtab, toff_next,
+                         c->Rc, st + 1, c->cfg.seed, c->kbits, c->init_min, 0u, qshA, c->ck(cb),
+                         c->cv(cb), c->L.cap_child, c->L.cap_store, c->ghist(csel ^ 1), passes,
+                         &c->prop));
+        else
+          ENQ(qmck_spawn(st_q, bk[(k + 1) % nb], bv[(k + 1) % nb], dcnt,
+                         &dcnt->n_store[cur ^ 1u], dtab, toff_next, c->Rc, st + 1, c->cfg.seed,
+                         c->kbits, c->init_min, 0u, qshA, c->ck(cb), c->cv(cb), c->L.cap_child,
+                         c->L.cap_store, c->ghist(csel ^ 1), passes, &c->prop));
+        if (toffB_next)
+          ENQ(qmck_spawn(st_q, bk[b], bv[b], dcnt, &dcnt->n_store[cur], dtab, toffB_next, c->Rc,
+                         st + 1, c->cfg.seed, c->kbits, c->init_min, 1u, qshB, c->ck(cb),
+                         c->cv(cb), c->L.cap_child, c->L.cap_store, c->ghist(csel ^ 1), passes,
+                         nullptr));
+        ENQ(mark(0, k + 1, 1));
+      }
     }
 #undef ENQ
     return hipSuccess;
@@ -944,8 +969,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   int rc = read_counters(c, hc);
   if (rc) return rc;
   if (c->prof_class >= 0 && c->prof_class <= 2) {
-    const uint32_t kend = c->prof_class == 0 ? 1 : nst;  // the spawn kernel runs once
-    for (uint32_t k = 0; k < kend; ++k) {
+    for (uint32_t k = 0; k < nst; ++k) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
       c->prof_ms += ms;

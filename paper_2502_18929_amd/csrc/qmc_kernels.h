@@ -27,7 +27,7 @@ int qmck_batch_begin(hipStream_t st, void* counters, uint64_t* status, uint64_t 
                      uint32_t n_ghist);
 // Records of step `step` from the n = *count parents (pk, pv), Philox stream `stream`: the death
 // delta of each parent (diagonal of its column plus the per-replica Q32 shift qsh) and its
-// children.  init_min > 0: initiator approximation, record keys carry the non-initiator flag
+// children, appended at n_child[step & 1] with the digit histograms of their sort in ghist.  init_min > 0: initiator approximation, record keys carry the non-initiator flag
 // below the composite key.
 // The tables are tab_base + tab_off[c] for circuit c (rep_per replicas per circuit).
 int qmck_spawn(hipStream_t st, const uint64_t* pk, const int2* pv, void* counters,
@@ -46,14 +46,22 @@ int qmck_sort_tile_ok(uint32_t ipt);
 // n synthetic records (keys masked to `mask`, values (1, 0)) for timing the sort.
 int qmck_fill_sort_probe(hipStream_t st, uint64_t* k, int2* v, uint64_t n, uint64_t mask,
                          uint64_t salt);
+// Annihilation of step `step`: the parents (pk, pv) (n_store[cur]) merged with the sorted
+// records (ck, cv) (n_child[csel]) into the new store (ok, ov), whose size goes to
+// n_store[cur ^ 1]: tile split points (splits, max tiles + 1), tile output counts and offsets
+// (tile_off: max tiles words, max tiles / 256 + 1 words of block offsets, then max tiles + 1
+// int32 count adjustments), then the tiles.  Also clears the next step's record counter
+// and digit histograms (ghist_next), which the records of step + 1 (qmck_spawn) fill.  With
+// toff_next (the tables of step + 1 for circuit c at tab_base + toff_next[c], shifts qshift),
+// every new store record whose comb can fire in step + 1 (Philox stream 0) is appended to
+// (act_k, act_v) (room for cap_store records; their number in Counters::n_active), the parents
+// a qmck_spawn of step + 1 draws from.
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, const uint8_t* tab_base, const uint32_t* toff_next,
-               const uint32_t* toffB_next, uint32_t rep_per, const int64_t* qshift,
-               const int64_t* qshiftB, uint32_t step, uint64_t seed,
-               uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
-               uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
-               uint32_t* ghist_next, uint32_t passes, const QmcProposal* prop);
+               uint64_t* tile_off, uint32_t step, uint32_t kbits, uint64_t init_min, uint64_t* ok,
+               int2* ov, uint64_t cap_store, uint64_t max_items, uint32_t* ghist_next,
+               const uint8_t* tab_base, const uint32_t* toff_next, uint32_t rep_per,
+               const int64_t* qshift, uint64_t seed, uint64_t* act_k, int2* act_v);
 // out[0..1] (device) = the index range of the sorted keys[0, *count) within [lo, hi].
 int qmck_key_range(hipStream_t st, const uint64_t* keys, const uint64_t* count, uint64_t lo,
                    uint64_t hi, uint64_t* out);

@@ -35,17 +35,15 @@ struct Emitter {
   uint64_t cap;
   uint32_t* ghist;      // [passes][kRadixBins]
   uint32_t passes;
-  uint32_t ndiag = 0;   // wave-uniform: staged records that are diagonal (death) records
+  uint32_t ndiag = 0;   // wave-uniform: diagonal (death) records emitted so far (the owner adds
+                        // them to cnt->death_steps once, when it is done)
 
   __device__ void flush() {
     const uint32_t lane = __lane_id();
     wave_lds_fence();
     uint64_t base = 0;
-    if (lane == 0) {
+    if (lane == 0)
       base = atomicAdd((unsigned long long*)&cnt->n_child[nsel], (unsigned long long)fill);
-      if (ndiag) atomicAdd((unsigned long long*)&cnt->death_steps, (unsigned long long)ndiag);
-    }
-    ndiag = 0;
     base = __shfl(base, 0);
     const bool ok = base + fill <= cap;
     if (!ok && lane == 0) {
@@ -376,8 +374,12 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TabSet& ts, const
 }
 
 // ---------------------------------------------------------------------------------------------
-// k_spawn: death records and children of the first step of a batch from N(s) (later steps spawn
-// inside k_merge), and with AB2 the records of the second term from N(s-1) (stream 1).
+// k_spawn: the records of step `step` from the n = *count parents (pk, pv) and Philox stream
+// `stream` (0: N(s), the Euler step and the first AB2 term; 1: N(s-1), the second AB2 term):
+// the death/cloning record of every parent whose diagonal comb fires and its children.  One
+// Philox draw per parent decides whether any of its combs can fire ((|a|+|b|) sum|q| + U >=
+// 2^32); only those parents are queued (compacted over the workgroup) and processed in full
+// 64-parent batches, so the group loop runs for parents that emit (most do not at small dt).
 // ---------------------------------------------------------------------------------------------
 template <bool kProp>
 __global__ __launch_bounds__(kBlock) void k_spawn(
@@ -389,26 +391,117 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
   __shared__ uint64_t s_key[kWaves][kSpawnSeg];
   __shared__ int2 s_val[kWaves][kSpawnSeg];
   __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? kWave * kPropHidden : 4];
+  __shared__ uint64_t s_ak[kMergeActive];  // queued parents: key, value, comb words
+  __shared__ int2 s_av[kMergeActive];
+  __shared__ uint2 s_aw[kMergeActive];
+  __shared__ uint32_t s_cnt[kWaves];
+  __shared__ uint64_t s_pk[kSpawnRound];   // the parents of one round, loaded all at once
+  __shared__ int2 s_pv[kSpawnRound];
   if (cnt->err) return;
   const uint64_t np = *count;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   Emitter em{s_key[wave], s_val[wave], kSpawnSeg, 0, cnt, step & 1u, step, ck_out, cv_out,
              cap_child, ghist, passes};
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t wbase = (uint64_t)blockIdx.x * kBlock + wave * kWave; wbase < np;
-       wbase += stride) {
-    const uint64_t p = wbase + lane;
-    const bool valid = p < np;
-    uint64_t ck = 0;
-    int2 v = make_int2(0, 0);
-    if (valid) {
-      ck = pk[p];
-      v = pv[p];
+  uint32_t nl = 0;  // queued parents (block-uniform)
+  // Records of the first nb * 64 queued parents (at most nl), the rest moved to the front.
+  auto drain = [&](uint32_t nb) __attribute__((always_inline)) {
+    for (uint32_t b = wave; b < nb; b += kWaves) {
+      const uint32_t b0 = b * kWave;
+      spawn_batch<kProp>(em, ts, qsh, s_ak + b0, s_av + b0, s_aw + b0,
+                         nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl, pr, step,
+                         seed, s_hid[kProp ? wave : 0]);
     }
-    spawn_parent<kProp>(em, ts, valid, ck, v, step, seed, kl, stream, qsh, pr,
-                        s_hid[kProp ? wave : 0]);
+    const uint32_t done = nb * kWave < nl ? nb * kWave : nl;
+    const uint32_t rest = nl - done;
+    __syncthreads();
+    uint64_t rk = 0;
+    int2 rv = make_int2(0, 0);
+    uint2 rw = make_uint2(0, 0);
+    if (threadIdx.x < rest) {
+      rk = s_ak[done + threadIdx.x];
+      rv = s_av[done + threadIdx.x];
+      rw = s_aw[done + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x < rest) {
+      s_ak[threadIdx.x] = rk;
+      s_av[threadIdx.x] = rv;
+      s_aw[threadIdx.x] = rw;
+    }
+    nl = rest;
+    __syncthreads();
+  };
+  // table bounds of the segment of the last parent seen (parents are sorted by segment)
+  uint32_t h_seg = ~0u;
+  uint64_t h_qoff = 0, h_qdiag = 0;
+  // Rounds of kSpawnRound parents: all of a round's loads in flight at once (LDS-direct dword
+  // loads, no registers), then kBlock parents at a time from LDS.
+  const uint64_t stride = (uint64_t)gridDim.x * kSpawnRound;
+  for (uint64_t rbase = (uint64_t)blockIdx.x * kSpawnRound; rbase < np; rbase += stride) {
+    const uint32_t rn = (uint32_t)(np - rbase < (uint64_t)kSpawnRound ? np - rbase
+                                                                      : (uint64_t)kSpawnRound);
+    {
+      const uint32_t* ks = reinterpret_cast<const uint32_t*>(pk + rbase);
+      const uint32_t* vs = reinterpret_cast<const uint32_t*>(pv + rbase);
+      uint32_t* kd = reinterpret_cast<uint32_t*>(s_pk);
+      uint32_t* vd = reinterpret_cast<uint32_t*>(s_pv);
+      for (uint32_t c = wave; c * kWave < 2 * rn; c += kWaves) {
+        const uint32_t x = c * kWave + lane;
+        if (x < 2 * rn) {
+          __builtin_amdgcn_global_load_lds(ks + x, kd + c * kWave, 4, 0, 0);
+          __builtin_amdgcn_global_load_lds(vs + x, vd + c * kWave, 4, 0, 0);
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+    for (uint32_t sub = 0; sub < rn; sub += kBlock) {
+      const uint32_t p = sub + threadIdx.x;
+      bool act = false;
+      uint64_t ck = 0;
+      int2 v = make_int2(0, 0);
+      uint32_t w[4] = {0, 0, 0, 0};
+      if (p < rn) {
+        ck = s_pk[p];
+        v = s_pv[p];
+        const uint32_t rep = kl.replica(ck);
+        if (rep != h_seg) {
+          const TableHeader* h = reinterpret_cast<const TableHeader*>(ts.of_segment(rep));
+          h_qoff = h->n_groups > 1 ? h->q_off : 0;
+          h_qdiag = h->q_diag + uabs64(qsh[rep]);
+          h_seg = rep;
+        }
+        walker_random(kl.key(ck), step, rep, seed, stream, w);
+        const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+        // a proposal draws for every parent of a column with off-diagonal groups
+        act = (kProp ? h_qoff != 0 : !comb_all_zero(sab, h_qoff, w[0])) ||
+              !comb_all_zero(sab, h_qdiag, w[1]);
+      }
+      const uint64_t m = __ballot(act);
+      if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t off = 0, tot = 0;
+      for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
+        const uint32_t c = s_cnt[x];
+        off += x < wave ? c : 0u;
+        tot += c;
+      }
+      __syncthreads();
+      if (nl + tot > (uint32_t)kMergeActive) drain(nl / kWave);
+      if (act) {
+        const uint32_t at = nl + off + mbcnt64(m);
+        s_ak[at] = ck;
+        s_av[at] = v;
+        s_aw[at] = make_uint2(w[0], w[1]);
+      }
+      nl += tot;
+      __syncthreads();
+    }
   }
+  if (nl > 0) drain((nl + kWave - 1) / kWave);
   if (em.fill) em.flush();
+  if (lane == 0 && em.ndiag)
+    atomicAdd((unsigned long long*)&cnt->death_steps, (unsigned long long)em.ndiag);
 }
 
 // Digit histograms of n_child[nsel] records (used where records did not come from a spawn).
@@ -449,41 +542,6 @@ __device__ __forceinline__ uint64_t lb_value(uint64_t s) { return s & ((1ull << 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
-}
-
-// Exclusive prefix of `tile` by decoupled look-back, executed by all 64 lanes of one wave: each
-// round reads 64 predecessors at once, and stops at the nearest one with an inclusive prefix.
-// Returns false if a predecessor did not publish within the spin limit.
-__device__ bool lookback_wave(const uint64_t* status, uint32_t tile, uint32_t epoch,
-                              uint64_t& prefix) {
-  const uint32_t lane = __lane_id();
-  const uint32_t ep = epoch & 0xFFFFu;
-  prefix = 0;
-  int64_t hi = (int64_t)tile - 1;
-  uint32_t spins = 0;
-  while (hi >= 0) {
-    const int64_t j = hi - (int64_t)lane;
-    uint64_t s = 0;
-    bool ready = true, inc = true;
-    if (j >= 0) {
-      s = atomic_load_agent(&status[j]);
-      ready = lb_epoch(s) == ep && lb_flag(s) != 0;
-      inc = ready && lb_flag(s) == 2;
-    }
-    const uint64_t inc_m = __ballot(inc);
-    const uint64_t wait_m = __ballot(!ready);
-    const uint32_t first = inc_m ? (uint32_t)__ffsll((unsigned long long)inc_m) - 1 : 64u;
-    const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-    if (wait_m & need) {
-      if (++spins > (1u << 22)) return false;
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    prefix += wave_sum64((lane <= first && j >= 0) ? lb_value(s) : 0);
-    if (first < 64) break;
-    hi -= 64;
-  }
-  return true;
 }
 
 // Merge-path split for diagonal d computed by one wave with 64-ary search (few dependent
@@ -683,16 +741,17 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
                                                        uint32_t csel, uint2* __restrict__ splits,
                                                        uint32_t max_tiles,
                                                        uint32_t* __restrict__ ghist_next,
-                                                       uint32_t ish) {
+                                                       uint32_t ish,
+                                                       int32_t* __restrict__ tdelta) {
   if (cnt->err) return;
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   // The next step's child counter, sort tickets and digit histograms were last used two steps
   // ago; this step's merge, which spawns the next step's children, runs after this kernel.
   for (uint32_t i = gt; i < (uint32_t)(kMaxPasses * kRadixBins); i += gridDim.x * kBlock)
     ghist_next[i] = 0;
-  if (gt < (uint32_t)kMergeTicketCounters) cnt->merge_ticket[gt][0] = 0;
   if (gt == 0) {
     cnt->n_child[csel ^ 1] = 0;
+    cnt->n_active = 0;
     for (int p = 0; p < kMaxPasses + 2; ++p) cnt->sort_ticket[csel ^ 1][p] = 0;
   }
   const uint32_t np = (uint32_t)cnt->n_store[cur];
@@ -730,6 +789,155 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
       while (j < jmax && B(j) <= last) ++j;
     }
     splits[t] = make_uint2(i, j);
+    tdelta[t] = 0;
+  }
+}
+
+// Output count of every merge tile, from its records alone: each of the tile's parents survives
+// unless its records annihilate it, so the count is the parents, plus the record keys without a
+// parent whose sum is nonzero, minus the parents whose sum with their records is zero.
+// k_merge_delta: one thread per record; the one at the start of a key's run finds the run's tile
+// (split points) and the key's parent among the tile's parents (a key's parent and its records
+// always fall in one tile), sums the run, and adds +1 / -1 to tdelta[tile] (cleared by
+// k_merge_part).  k_merge_count: one thread per tile, count = parents + delta, and an exclusive
+// scan over the 256 tiles of each block: tinfo[tile] = (count << 32) | first output counted from
+// the block's first, bsum[b] = the block's outputs (k_merge_scan turns them into offsets).
+__global__ __launch_bounds__(kBlock) void k_merge_delta(const uint64_t* __restrict__ pk,
+                                                        const int2* __restrict__ pv,
+                                                        const uint64_t* __restrict__ ckeys,
+                                                        const int2* __restrict__ cvals,
+                                                        const Counters* __restrict__ cnt,
+                                                        uint32_t cur, uint32_t csel,
+                                                        const uint2* __restrict__ splits,
+                                                        int32_t* __restrict__ tdelta,
+                                                        KeyLayout kl) {
+  if (cnt->err) return;
+  const uint32_t np = (uint32_t)cnt->n_store[cur];
+  const uint32_t nc = (uint32_t)cnt->n_child[csel];
+  const uint32_t ntiles = (np + nc + kMergeTile - 1) / kMergeTile;
+  for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nc; j += gridDim.x * kBlock) {
+    const uint64_t k = kl.ckey(ckeys[j]);
+    if (j > 0 && kl.ckey(ckeys[j - 1]) == k) continue;  // not the start of its run
+    // the tile: the last t with splits[t].y <= j
+    uint32_t lo = 0, hi = ntiles;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (splits[mid].y <= j)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const uint32_t tile = lo;
+    if (tile >= ntiles) continue;  // inconsistent split points: k_merge reports them
+    const uint32_t p0 = splits[tile].x, p1 = splits[tile + 1].x;
+    uint32_t a = p0, b = p1 < np ? p1 : np;
+    while (a < b) {
+      const uint32_t mid = (a + b) >> 1;
+      if (pk[mid] < k)
+        a = mid + 1;
+      else
+        b = mid;
+    }
+    const bool hp = a < p1 && a < np && pk[a] == k;
+    int64_t re = 0, im = 0;
+    if (hp) {
+      const int2 v = pv[a];
+      re = v.x;
+      im = v.y;
+    }
+    for (uint32_t q = j; q < nc; ++q) {
+      const uint64_t rk = ckeys[q];
+      if (kl.ckey(rk) != k) break;
+      if (kl.keep(rk, hp)) {
+        const int2 v = cvals[q];
+        re += v.x;
+        im += v.y;
+      }
+    }
+    const bool nz = re != 0 || im != 0;
+    if (!hp && nz) atomicAdd(&tdelta[tile], 1);
+    if (hp && !nz) atomicAdd(&tdelta[tile], -1);
+  }
+}
+
+constexpr int kCountTiles = kBlock;  // tiles per block of k_merge_count
+__global__ __launch_bounds__(kBlock) void k_merge_count(const Counters* __restrict__ cnt,
+                                                        uint32_t cur, uint32_t csel,
+                                                        const uint2* __restrict__ splits,
+                                                        const int32_t* __restrict__ tdelta,
+                                                        uint64_t* __restrict__ tinfo,
+                                                        uint64_t* __restrict__ bsum) {
+  __shared__ uint32_t s_w[kWaves];
+  if (cnt->err) return;
+  const uint32_t np = (uint32_t)cnt->n_store[cur];
+  const uint32_t nc = (uint32_t)cnt->n_child[csel];
+  const uint32_t ntiles = (np + nc + kMergeTile - 1) / kMergeTile;
+  if (blockIdx.x * kCountTiles >= ntiles) return;  // block-uniform
+  const uint32_t tile = blockIdx.x * kCountTiles + threadIdx.x;
+  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
+  uint32_t count = 0;
+  if (tile < ntiles) {
+    const uint2 s0 = splits[tile], s1 = splits[tile + 1];
+    if (s1.x >= s0.x && s1.y >= s0.y && s1.x <= np && s1.y <= nc)  // else k_merge reports it
+      count = (uint32_t)((int32_t)(s1.x - s0.x) + tdelta[tile]);
+  }
+  uint32_t incl = count;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t x = __shfl_up(incl, o);
+    if (lane >= (uint32_t)o) incl += x;
+  }
+  if (lane == kWave - 1) s_w[wave] = incl;
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (uint32_t x = 0; x < wave; ++x) wpre += s_w[x];
+  if (tile < ntiles) tinfo[tile] = ((uint64_t)count << 32) | (wpre + incl - count);
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = wpre + incl;
+}
+
+// Exclusive prefix of the block sums of k_merge_count, in place (bsum[b] becomes the first output
+// of block b's tiles; bsum[nblocks] the new store size), and the step's counters.  One
+// workgroup.
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void k_merge_scan(uint64_t* __restrict__ bsum,
+                                                           Counters* __restrict__ cnt,
+                                                           uint32_t cur, uint32_t csel,
+                                                           uint64_t cap_store, uint32_t step) {
+  __shared__ uint64_t s_part[kScanBlock];
+  if (cnt->err) return;
+  const uint32_t np = (uint32_t)cnt->n_store[cur];
+  const uint32_t nc = (uint32_t)cnt->n_child[csel];
+  const uint32_t ntiles = (np + nc + kMergeTile - 1) / kMergeTile;
+  const uint32_t nb = (ntiles + kCountTiles - 1) / kCountTiles;
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (nb + kScanBlock - 1) / kScanBlock;
+  const uint32_t b = t * per < nb ? t * per : nb;
+  const uint32_t e = b + per < nb ? b + per : nb;
+  uint64_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += bsum[i];
+  s_part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < kScanBlock; o <<= 1) {  // inclusive scan of the thread sums
+    const uint64_t x = t >= (uint32_t)o ? s_part[t - o] : 0;
+    __syncthreads();
+    s_part[t] += x;
+    __syncthreads();
+  }
+  uint64_t run = s_part[t] - sum;
+  for (uint32_t i = b; i < e; ++i) {
+    const uint64_t c = bsum[i];
+    bsum[i] = run;
+    run += c;
+  }
+  if (t == kScanBlock - 1) {
+    const uint64_t total = s_part[t];
+    bsum[nb] = total;
+    cnt->n_store[cur ^ 1] = total;
+    cnt->child_steps += nc;
+    cnt->out_steps += total;
+    if (total > cap_store) {
+      atomicOr(&cnt->err, kErrStoreCap);
+      atomicMin(&cnt->err_step, step);
+    }
   }
 }
 
@@ -741,154 +949,131 @@ struct MergeArgs {
   Counters* cnt;
   uint32_t cur, csel;
   const uint2* splits;
-  uint64_t* status;
-  uint32_t epoch;
-  TabSet tab_next;           // tables of step s+1 (death and spawn), or none
-  TabSet tabB_next;          // AB2: tables of the second term of step s+1 (from N(s)), or none
-  const int64_t* qshiftB;    // AB2: its per-replica Q32 shifts
-  const int64_t* qshift;    // per-replica Q32 shifts of tab_next
+  const uint64_t* tinfo;     // per tile: (outputs << 32) | first output within its count block
+  const uint64_t* boff;      // first output of every count block (k_merge_scan)
   uint32_t step;
-  uint64_t seed;
   KeyLayout kl;
   uint64_t* ok;
   int2* ov;
   uint64_t cap_store;
-  uint64_t* ck_next;         // children of step s+1
-  int2* cv_next;
-  uint64_t cap_child;
-  uint32_t* ghist_next;
-  uint32_t passes;
-  QmcProposal prop;          // spawn proposal of step s+1 (kind 0: the comb)
+  // With tab_next valid: every output whose comb can fire in step s+1 under these tables (Philox
+  // stream 0, shifts qshift) is appended to (act_k, act_v) (cnt->n_active of them, at most
+  // cap_store), the parents from which k_spawn draws that step's records.
+  TabSet tab_next;
+  const int64_t* qshift;
+  uint64_t seed;
+  uint64_t* act_k;
+  int2* act_v;
 };
 
-// kSpawn: the merge also draws the records of step s+1 from its outputs (kProp: under a spawn
-// proposal); without it the kernel only merges (fewer registers and LDS per workgroup).
-template <bool kProp, bool kSpawn>
+// Annihilation: every tile's parents and sorted records go to LDS together (LDS-direct loads:
+// a wave instruction moves 256 contiguous bytes and no registers hold the data, so all of a
+// tile's loads are in flight at once), are merged with int64 sums per key, and the nonzero sums
+// are written to the new store at the tile's offset.  The tiles are independent (their offsets
+// come from k_merge_count and k_merge_scan): block b takes tiles b, b + G, b + 2G, ...  As soon as
+// a tile's merge has read its LDS data, the loads of the block's next tile are issued, so they
+// are in flight while this tile's records are written and its next-step draws are made.
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   constexpr int CAP = kMergeCap;
-  constexpr int QCAP = kSpawn ? kMergeActive : 1;
-  __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? kWave * kPropHidden : 4];
-  __shared__ uint64_t s_pk[CAP];   // parents of the tile; then its annihilated records
+  __shared__ uint64_t s_pk[CAP];   // parents, then the tile's records behind them
   __shared__ int2 s_pv[CAP];
-  // children of the tile (a merge that spawns also stages the next step's records here; one
-  // that does not keeps the children behind the parents in s_pk / s_pv)
-  __shared__ uint64_t s_ck_arr[kSpawn ? CAP : 1];
-  __shared__ int2 s_cv_arr[kSpawn ? CAP : 1];
   __shared__ uint32_t s_scan[kBlock];
   __shared__ uint32_t s_xsplit[kBlock];  // merge-path split of each thread: parent | child << 16
-  __shared__ uint32_t s_tile;
-  __shared__ uint64_t s_base;
   __shared__ uint64_t s_ws[kWaves];
-  // Outputs that can spawn in step s+1, queued across tiles and spawned in full 64-lane batches
-  // (a batch costs the same whatever its lane count, and sparse columns leave most lanes idle).
-  __shared__ uint64_t s_ak[QCAP];
-  __shared__ int2 s_av[QCAP];
-  __shared__ uint2 s_aw[QCAP];
-  static_assert(kWaves * kMergeSpawnSeg <= CAP, "spawn staging must fit the child tile");
+  __shared__ uint64_t s_qk[kMergeQueue];  // outputs that can fire in step s+1, not yet appended
+  __shared__ int2 s_qv[kMergeQueue];
+  __shared__ uint64_t s_qbase;
 
   Counters* cnt = A.cnt;
   if (cnt->err) return;
   const uint32_t np = (uint32_t)cnt->n_store[A.cur];
   const uint32_t nc = (uint32_t)cnt->n_child[A.csel];
-  const uint32_t total = np + nc;
-  const uint32_t ntiles = (total + kMergeTile - 1) / kMergeTile;
-  if (ntiles == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_store[A.cur ^ 1] = 0;
-    return;
-  }
+  const uint32_t ntiles = (np + nc + kMergeTile - 1) / kMergeTile;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
-  uint32_t nl = 0;  // queued active outputs (block-uniform)
-  // Spawns the first nb * 64 queued outputs (at most nl) with the staging of the child tile,
-  // then moves the rest to the front of the queue.  Block-uniform; ends with the queue stable.
-  auto drain = [&](uint32_t nb) __attribute__((always_inline)) {
-    if (nb > 0) {
-      Emitter em{s_ck_arr + wave * kMergeSpawnSeg, s_cv_arr + wave * kMergeSpawnSeg, kMergeSpawnSeg, 0,
-                 cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child, A.ghist_next,
-                 A.passes};
-      for (uint32_t b = wave; b < nb; b += kWaves) {
-        const uint32_t b0 = b * kWave;
-        spawn_batch<kProp>(em, A.tab_next, A.qshift, s_ak + b0, s_av + b0, s_aw + b0,
-                           nl - b0 < (uint32_t)kWave ? nl - b0 : (uint32_t)kWave, kl, A.prop,
-                           A.step + 1, A.seed, s_hid[kProp ? wave : 0]);
+  uint64_t st_keys = 0, st_w = 0;  // parents and their walkers (thread 0), added once at the end
+  const bool draw = A.tab_next.valid();
+  uint32_t nq = 0;  // queued outputs (block-uniform)
+  // Appends the queue to the list of step s+1's parents (one atomic per flush).
+  auto flush_queue = [&]() __attribute__((always_inline)) {
+    if (threadIdx.x == 0)
+      s_qbase = atomicAdd((unsigned long long*)&cnt->n_active, (unsigned long long)nq);
+    __syncthreads();
+    const uint64_t qb = s_qbase;
+    for (uint32_t i = threadIdx.x; i < nq; i += kBlock)
+      if (qb + i < A.cap_store) {
+        A.act_k[qb + i] = s_qk[i];
+        A.act_v[qb + i] = s_qv[i];
       }
-      if (em.fill) em.flush();
-    }
-    const uint32_t done = nb * kWave < nl ? nb * kWave : nl;
-    const uint32_t rest = nl - done;
     __syncthreads();
-    uint64_t rk = 0;
-    int2 rv = make_int2(0, 0);
-    uint2 rw = make_uint2(0, 0);
-    if (threadIdx.x < rest) {
-      rk = s_ak[done + threadIdx.x];
-      rv = s_av[done + threadIdx.x];
-      rw = s_aw[done + threadIdx.x];
-    }
-    __syncthreads();
-    if (threadIdx.x < rest) {
-      s_ak[threadIdx.x] = rk;
-      s_av[threadIdx.x] = rv;
-      s_aw[threadIdx.x] = rw;
-    }
-    nl = rest;
-    __syncthreads();
+    nq = 0;
   };
-
-  // bounds of the next step's table for the segment of the last output seen (outputs are
-  // sorted by segment, so they change rarely)
+  // table bounds of the segment of the last output seen (outputs are sorted by segment)
   uint32_t h_seg = ~0u;
   uint64_t h_qoff = 0, h_qdiag = 0;
-  // Tile tickets from C counters (a single contended counter serializes the grid): block b
-  // takes tiles b mod C, b mod C + C, ... in order, so every tile is taken by a running block and
-  // the smallest unfinished tile is always being processed (its look-back cannot stall).
-  const uint32_t nctr = gridDim.x < (uint32_t)kMergeTicketCounters ? gridDim.x
-                                                                    : (uint32_t)kMergeTicketCounters;
-  const uint32_t my_ctr = blockIdx.x % nctr;
-  while (true) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&cnt->merge_ticket[my_ctr][0], 1u) * nctr + my_ctr;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= ntiles) break;
-    const uint2 s0 = A.splits[tile], s1 = A.splits[tile + 1];
+  // A tile's parents [pa, pa + pn) and records [ca, ca + cn) from its split points; false if they
+  // are inconsistent (cannot happen for runs shorter than the slack; reported, never loaded).
+  auto geometry = [&](uint2 s0, uint2 s1, uint32_t& pa, uint32_t& pn, uint32_t& ca,
+                      uint32_t& cn) __attribute__((always_inline)) -> bool {
     if (s1.x < s0.x || s1.y < s0.y || (s1.x - s0.x) + (s1.y - s0.y) > (uint32_t)CAP ||
-        s1.x > np || s1.y > nc) {
-      // cannot happen for runs shorter than the slack; refuse rather than overrun LDS
-      if (threadIdx.x == 0) {
-        atomicOr(&cnt->err, kErrLookback);
-        atomicMin(&cnt->err_step, A.step);
-        atomic_store_agent(&A.status[tile], lb_pack(A.epoch, 2, 0));
+        s1.x > np || s1.y > nc)
+      return false;
+    pa = s0.x;
+    pn = s1.x - s0.x;
+    ca = s0.y;
+    cn = s1.y - s0.y;
+    return true;
+  };
+  auto issue = [&](uint32_t pa, uint32_t pn, uint32_t ca, uint32_t cn)
+      __attribute__((always_inline)) {
+    auto to_lds = [&](const void* src, void* dst, uint32_t ndw) __attribute__((always_inline)) {
+      const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+      uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+      for (uint32_t c = wave; c * kWave < ndw; c += kWaves) {
+        const uint32_t x = c * kWave + lane;
+        if (x < ndw) __builtin_amdgcn_global_load_lds(s32 + x, d32 + c * kWave, 4, 0, 0);
       }
-      __syncthreads();
+    };
+    to_lds(A.pk + pa, s_pk, 2 * pn);
+    to_lds(A.pv + pa, s_pv, 2 * pn);
+    to_lds(A.ckeys + ca, s_pk + pn, 2 * cn);
+    to_lds(A.cvals + ca, s_pv + pn, 2 * cn);
+  };
+  auto report = [&]() __attribute__((always_inline)) {
+    if (threadIdx.x == 0) {
+      atomicOr(&cnt->err, kErrLookback);
+      atomicMin(&cnt->err_step, A.step);
+    }
+  };
+
+  uint32_t pa = 0, pn = 0, ca = 0, cn = 0;
+  bool ok = false;
+  if (blockIdx.x < ntiles) {
+    ok = geometry(A.splits[blockIdx.x], A.splits[blockIdx.x + 1], pa, pn, ca, cn);
+    if (ok) issue(pa, pn, ca, cn);
+  }
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t next = tile + gridDim.x;
+    const uint64_t ti = A.tinfo[tile];
+    const uint64_t gbase = A.boff[tile / kCountTiles] + (uint32_t)ti, nout = ti >> 32;
+    uint2 n0 = make_uint2(0, 0), n1 = make_uint2(0, 0);
+    if (next < ntiles) {
+      n0 = A.splits[next];
+      n1 = A.splits[next + 1];
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this tile's LDS data (and the loads above)
+    __syncthreads();
+    uint32_t npa = 0, npn = 0, nca = 0, ncn = 0;
+    const bool nok = next < ntiles && geometry(n0, n1, npa, npn, nca, ncn);
+    if (!ok) {
+      report();
+      if (nok) issue(npa, npn, nca, ncn);
+      pa = npa, pn = npn, ca = nca, cn = ncn, ok = nok;
       continue;
     }
-    const uint32_t pa = s0.x, pn = s1.x - s0.x;
-    const uint32_t ca = s0.y, cn = s1.y - s0.y;
-    uint64_t* const s_ck = kSpawn ? s_ck_arr : s_pk + pn;
-    int2* const s_cv = kSpawn ? s_cv_arr : s_pv + pn;
-
-    // Parents (their death/cloning delta of this step arrived as a record among the children)
-    // and the tile's records go straight from global memory to LDS (LDS-direct dword loads: a
-    // wave instruction moves 256 contiguous bytes, and no registers hold the data, so every load
-    // of the tile is in flight at once).
-    {
-      auto to_lds = [&](const void* src, void* dst, uint32_t ndw) __attribute__((always_inline)) {
-        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
-        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
-        for (uint32_t c = wave; c * kWave < ndw; c += kWaves) {
-          const uint32_t x = c * kWave + lane;
-          if (x < ndw) __builtin_amdgcn_global_load_lds(s32 + x, d32 + c * kWave, 4, 0, 0);
-        }
-      };
-      to_lds(A.pk + pa, s_pk, 2 * pn);
-      to_lds(A.pv + pa, s_pv, 2 * pn);
-      to_lds(A.ckeys + ca, s_ck, 2 * cn);
-      to_lds(A.cvals + ca, s_cv, 2 * cn);
-      __builtin_amdgcn_s_waitcnt(0);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-      atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)pn);
+    const uint64_t* const s_ck = s_pk + pn;
+    const int2* const s_cv = s_pv + pn;
+    if (threadIdx.x == 0) st_keys += pn;
     uint64_t wsum = 0;  // walker sum of the parents this thread's merge range holds
 
     // Per-thread ranges of the local merge, cut only at run ends.
@@ -964,7 +1149,6 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       atomicOr(&cnt->err, kErrLookback);
       atomicMin(&cnt->err_step, A.step);
     }
-
     // Block exclusive scan of the counts: inclusive scan within each wave, then wave totals.
     uint32_t incl = count;
     for (int o = 1; o < kWave; o <<= 1) {
@@ -974,12 +1158,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     if (lane == kWave - 1) s_scan[wave] = incl;
     for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
     if (lane == 0) s_ws[wave] = wsum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t t = 0;
-      for (int w = 0; w < kWaves; ++w) t += s_ws[w];
-      atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)t);
-    }
+    __syncthreads();  // also: every thread has finished reading the tile's LDS data
+    // the next tile's loads, in flight during the rest of this one
+    if (nok) issue(npa, npn, nca, ncn);
+    if (threadIdx.x == 0)
+      for (int w = 0; w < kWaves; ++w) st_w += s_ws[w];
     uint32_t wpre = 0, agg = 0;
     for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
       const uint32_t v = s_scan[x];
@@ -987,34 +1170,26 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       agg += v;
     }
     const uint32_t excl = wpre + incl - count;
-    // The tile's aggregate is published now; its look-back for the output offset waits until
-    // after the LDS work below, by when the predecessors have usually published theirs.
-    if (threadIdx.x == 0)
-      atomic_store_agent(&A.status[tile], lb_pack(A.epoch, tile == 0 ? 2 : 1, agg));
-
-    // The tile's annihilated records, compacted into the parent area of LDS (every thread has
-    // finished reading the tile: the scan above synchronized the block).
+    // The tile's records to the new store at its offset (the count pass must agree with the
+    // merge; a disagreement is an internal error, reported rather than written); with the next
+    // step's tables, Philox once per record and the ones whose combs can fire are queued.
+    uint32_t nact = 0;
+    bool act[kMergeIpt];
+    if (agg != nout) {
+      report();
+      count = 0;
+    }
 #pragma unroll
-    for (int u = 0; u < kMergeIpt; ++u)
+    for (int u = 0; u < kMergeIpt; ++u) {
+      act[u] = false;
       if ((uint32_t)u < count) {
-        s_pk[excl + u] = rk[u];
-        s_pv[excl + u] = rv[u];
-      }
-    __syncthreads();
-
-    // Children of step s+1 from the outputs of this tile: Philox once per output, the ones
-    // that can spawn go to the queue; full batches are spawned when it fills.
-    if (kSpawn && A.tab_next.valid()) {
-      for (uint32_t base = 0; base < agg; base += kBlock) {
-        const uint32_t p = base + threadIdx.x;
-        bool act = false;
-        uint64_t ck = 0;
-        int2 v = make_int2(0, 0);
-        uint32_t w[4] = {0, 0, 0, 0};
-        if (p < agg) {
-          ck = s_pk[p];
-          v = s_pv[p];
-          const uint32_t rep = kl.replica(ck);
+        const uint64_t o = gbase + excl + u;
+        if (o < A.cap_store) {
+          A.ok[o] = rk[u];
+          A.ov[o] = rv[u];
+        }
+        if (draw) {
+          const uint32_t rep = kl.replica(rk[u]);
           if (rep != h_seg) {
             const TableHeader* h =
                 reinterpret_cast<const TableHeader*>(A.tab_next.of_segment(rep));
@@ -1022,85 +1197,69 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
             h_qdiag = h->q_diag + uabs64(A.qshift[rep]);
             h_seg = rep;
           }
-          walker_random(kl.key(ck), A.step + 1, rep, A.seed, 0u, w);
-          const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-          // a proposal draws for every parent of a column with off-diagonal groups
-          act = (kProp ? h_qoff != 0 : !comb_all_zero(sab, h_qoff, w[0])) ||
-                !comb_all_zero(sab, h_qdiag, w[1]);
-        }
-        const uint64_t m = __ballot(act);
-        if (lane == 0) s_scan[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t off = 0, tot = 0;
-        for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
-          const uint32_t c2 = s_scan[x];
-          off += x < wave ? c2 : 0u;
-          tot += c2;
-        }
-        __syncthreads();
-        if (nl + tot > (uint32_t)kMergeActive) drain(nl / kWave);
-        if (act) {
-          const uint32_t at = nl + off + mbcnt64(m);
-          s_ak[at] = ck;
-          s_av[at] = v;
-          s_aw[at] = make_uint2(w[0], w[1]);
-        }
-        nl += tot;
-        __syncthreads();
-      }
-      if (A.tabB_next.valid()) {
-        // second AB2 term of step s+1 from this tile's parents N(s), as loaded
-        Emitter em{s_ck_arr + wave * kMergeSpawnSeg, s_cv_arr + wave * kMergeSpawnSeg,
-                   kMergeSpawnSeg,
-                   0, cnt, A.csel ^ 1u, A.step + 1, A.ck_next, A.cv_next, A.cap_child,
-                   A.ghist_next, A.passes};
-        for (uint32_t wb = wave * kWave; wb < pn; wb += kBlock) {
-          const uint32_t p = wb + lane;
-          const bool valid = p < pn;
-          const uint64_t ck = valid ? A.pk[pa + p] : 0;
-          const int2 v = valid ? A.pv[pa + p] : make_int2(0, 0);
-          spawn_parent(em, A.tabB_next, valid, ck, v, A.step + 1, A.seed, kl, 1u, A.qshiftB);
-        }
-        if (em.fill) em.flush();
-      }
-    }
-
-    // Decoupled look-back for the tile's output offset (wave 0, 64 predecessors per round).
-    if (wave == 0) {
-      uint64_t prefix = 0;
-      bool ok = true;
-      if (tile > 0) ok = lookback_wave(A.status, tile, A.epoch, prefix);
-      if (lane == 0) {
-        if (!ok) {
-          atomicOr(&cnt->err, kErrLookback);
-          atomicMin(&cnt->err_step, A.step);
-        }
-        if (tile > 0) atomic_store_agent(&A.status[tile], lb_pack(A.epoch, 2, prefix + agg));
-        s_base = prefix;
-        if (tile == ntiles - 1) {
-          cnt->n_store[A.cur ^ 1] = prefix + agg;
-          atomicAdd((unsigned long long*)&cnt->child_steps, (unsigned long long)nc);
-          atomicAdd((unsigned long long*)&cnt->out_steps, (unsigned long long)(prefix + agg));
-          if (prefix + agg > A.cap_store) {
-            atomicOr(&cnt->err, kErrStoreCap);
-            atomicMin(&cnt->err_step, A.step);
-          }
+          uint32_t w[4];
+          walker_random(kl.key(rk[u]), A.step + 1, rep, A.seed, 0u, w);
+          const uint64_t sab = uabs64(rv[u].x) + uabs64(rv[u].y);
+          act[u] = !comb_all_zero(sab, h_qoff, w[0]) || !comb_all_zero(sab, h_qdiag, w[1]);
+          nact += act[u] ? 1u : 0u;
         }
       }
     }
-    __syncthreads();
-    // the tile's records to the new store, coalesced
-    const uint64_t gbase = s_base;
-    for (uint32_t x = threadIdx.x; x < agg; x += kBlock) {
-      if (gbase + x < A.cap_store) {
-        A.ok[gbase + x] = s_pk[x];
-        A.ov[gbase + x] = s_pv[x];
+    if (draw) {
+      // block exclusive scan of the queued counts, then the records into the queue (or, when
+      // more than it holds, straight into the list)
+      uint32_t ai = nact;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t x = __shfl_up(ai, o);
+        if (lane >= (uint32_t)o) ai += x;
+      }
+      __syncthreads();  // s_scan is free again
+      if (lane == kWave - 1) s_scan[wave] = ai;
+      __syncthreads();
+      uint32_t apre = 0, atot = 0;
+      for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
+        const uint32_t v = s_scan[x];
+        apre += x < wave ? v : 0u;
+        atot += v;
+      }
+      if (atot > 0) {
+        if (nq + atot > (uint32_t)kMergeQueue) flush_queue();
+        uint32_t at = apre + ai - nact;
+        if (atot > (uint32_t)kMergeQueue) {
+          if (threadIdx.x == 0)
+            s_qbase = atomicAdd((unsigned long long*)&cnt->n_active, (unsigned long long)atot);
+          __syncthreads();
+          const uint64_t qb = s_qbase;
+#pragma unroll
+          for (int u = 0; u < kMergeIpt; ++u)
+            if (act[u]) {
+              if (qb + at < A.cap_store) {
+                A.act_k[qb + at] = rk[u];
+                A.act_v[qb + at] = rv[u];
+              }
+              ++at;
+            }
+          __syncthreads();
+        } else {
+#pragma unroll
+          for (int u = 0; u < kMergeIpt; ++u)
+            if (act[u]) {
+              s_qk[nq + at] = rk[u];
+              s_qv[nq + at] = rv[u];
+              ++at;
+            }
+          nq += atot;
+        }
       }
     }
-    __syncthreads();
+    pa = npa, pn = npn, ca = nca, cn = ncn, ok = nok;
   }
-  // the rest of the queue (block-uniform: every thread left the tile loop together)
-  if (kSpawn && A.tab_next.valid() && nl > 0) drain((nl + kWave - 1) / kWave);
+  __syncthreads();
+  if (draw && nq > 0) flush_queue();
+  if (threadIdx.x == 0) {
+    if (st_keys) atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)st_keys);
+    if (st_w) atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)st_w);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1460,18 +1619,25 @@ int qmck_fill_sort_probe(hipStream_t st, uint64_t* k, int2* v, uint64_t n, uint6
 
 int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_t* ck,
                const int2* cv, void* counters, uint32_t cur, uint32_t csel, uint2* splits,
-               uint64_t* status, const uint8_t* tab_base, const uint32_t* toff_next,
-               const uint32_t* toffB_next, uint32_t rep_per, const int64_t* qshift,
-               const int64_t* qshiftB, uint32_t step, uint64_t seed,
-               uint32_t kbits, uint64_t init_min, uint64_t* ok, int2* ov, uint64_t cap_store,
-               uint64_t max_items, uint64_t* ck_next, int2* cv_next, uint64_t cap_child,
-               uint32_t* ghist_next, uint32_t passes, const QmcProposal* prop) {
+               uint64_t* tile_off, uint32_t step, uint32_t kbits, uint64_t init_min, uint64_t* ok,
+               int2* ov, uint64_t cap_store, uint64_t max_items, uint32_t* ghist_next,
+               const uint8_t* tab_base, const uint32_t* toff_next, uint32_t rep_per,
+               const int64_t* qshift, uint64_t seed, uint64_t* act_k, int2* act_v) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   const KeyLayout kl = key_layout(kbits, init_min);
+  const uint32_t nblk = (max_tiles + kCountTiles - 1) / kCountTiles;
+  uint64_t* bsum = tile_off + max_tiles;  // count blocks' sums, then offsets (nblk + 1 words)
+  int32_t* tdelta = reinterpret_cast<int32_t*>(bsum + nblk + 1);  // max_tiles + 1 words
   hipLaunchKernelGGL(k_merge_part,
                      dim3(grid_for((uint64_t)max_tiles + 1, 2048)), dim3(kBlock), 0,
                      st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next,
-                     kl.ish);
+                     kl.ish, tdelta);
+  hipLaunchKernelGGL(k_merge_delta, dim3(grid_for(max_items, 2048)), dim3(kBlock), 0, st, pk,
+                     pv, ck, cv, (const Counters*)counters, cur, csel, splits, tdelta, kl);
+  hipLaunchKernelGGL(k_merge_count, dim3(nblk ? nblk : 1), dim3(kBlock), 0, st,
+                     (const Counters*)counters, cur, csel, splits, tdelta, tile_off, bsum);
+  hipLaunchKernelGGL(k_merge_scan, dim3(1), dim3(kScanBlock), 0, st, bsum, (Counters*)counters,
+                     cur, csel, cap_store, step);
   MergeArgs a;
   a.pk = pk;
   a.pv = pv;
@@ -1481,35 +1647,22 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.cur = cur;
   a.csel = csel;
   a.splits = splits;
-  a.status = status;
-  a.epoch = merge_epoch(step);
-  a.tab_next = TabSet{tab_base, toff_next, rep_per};
-  a.tabB_next = TabSet{tab_base, toffB_next, rep_per};
-  a.qshiftB = qshiftB;
-  a.qshift = qshift;
+  a.tinfo = tile_off;
+  a.boff = bsum;
   a.step = step;
-  a.seed = seed;
   a.kl = kl;
   a.ok = ok;
   a.ov = ov;
   a.cap_store = cap_store;
-  a.ck_next = ck_next;
-  a.cv_next = cv_next;
-  a.cap_child = cap_child;
-  a.ghist_next = ghist_next;
-  a.passes = passes;
-  a.prop = prop ? *prop : QmcProposal{};
-  const uint32_t g = max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
-                                                        : (uint32_t)kMergeBlocks;
-  if (toff_next == nullptr && toffB_next == nullptr)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_merge<false, false>),
-                       dim3(max_tiles < (uint32_t)kMergeOnlyBlocks ? (max_tiles ? max_tiles : 1)
-                                                                   : (uint32_t)kMergeOnlyBlocks),
-                       dim3(kBlock), 0, st, a);
-  else if (a.prop.kind)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_merge<true, true>), dim3(g), dim3(kBlock), 0, st, a);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_merge<false, true>), dim3(g), dim3(kBlock), 0, st, a);
+  a.tab_next = TabSet{tab_base, toff_next, rep_per};
+  a.qshift = qshift;
+  a.seed = seed;
+  a.act_k = act_k;
+  a.act_v = act_v;
+  hipLaunchKernelGGL(k_merge,
+                     dim3(max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
+                                                             : (uint32_t)kMergeBlocks),
+                     dim3(kBlock), 0, st, a);
   return (int)hipGetLastError();
 }
 

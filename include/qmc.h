@@ -148,9 +148,24 @@ int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma
  * one grid barrier per step, every key range owned by one workgroup) while the store holds at
  * most 8192 keys per co-resident workgroup and no key range overflows its segment or its
  * per-step inbox, otherwise the streamed kernels (spawn, radix sort of the children, merge)
- * for the next 256 steps.  path 1: fused only (an overflowing key range is reported as
- * QMC_ERR_STORE_CAP or QMC_ERR_SPAWN_CAP).  path 2: streamed only.  QMC_ERR_ARG otherwise. */
+ * for the next 256 steps; and before both, while every replica (store segment) has at most
+ * qmc_small_limit occupied keys, the Euler step with the comb runs LDS-resident: one workgroup
+ * per segment holds it and takes batches of up to 128 steps with no grid-wide synchronization
+ * (a segment that outgrows the limit, or whose step would need more than 1024 records on
+ * unoccupied keys or exceed a capacity, hands the step over to the fused kernel for the rest of
+ * the trajectory, until the next qmc_import, qmc_step_path or qmc_small_limit).  path 1: fused
+ * only (an overflowing key range is reported as QMC_ERR_STORE_CAP or QMC_ERR_SPAWN_CAP).
+ * path 2: streamed only.  path 3: LDS-resident only, up to 1024 keys per segment
+ * (QMC_ERR_STORE_CAP when a segment does not fit; QMC_ERR_ARG with AB2, a spawn proposal, step
+ * tables above 8 KB or more segments than co-resident workgroups).  QMC_ERR_ARG otherwise. */
 int qmc_step_path(qmc_ctx* ctx, int32_t path);
+
+/* Keys per replica up to which the automatic path takes the LDS-resident step (default 256;
+ * 0 = never; at most QMC_SMALL_MAX_KEYS, else QMC_ERR_ARG).  One workgroup then carries a whole
+ * replica, so the limit trades the fused kernel's per-step grid synchronization against the
+ * work of one workgroup; it changes no result. */
+#define QMC_SMALL_MAX_KEYS 1024
+int qmc_small_limit(qmc_ctx* ctx, uint32_t keys);
 
 /* Time integrator of qmc_step (End Matter on simulation methodology): 0 = Euler (default),
  * N(s+1) = N(s) + round(dt L(t_s) N(s)); 1 = AB2, for s >= 1
@@ -335,14 +350,20 @@ int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
  * every launch of that class in qmc_step: kernel_class 0 = streamed draws (the records of each
  * step from its parents: death/cloning and children), 1 = streamed record sort (all radix
  * passes), 2 = streamed annihilation (tile split points, tile output counts and offsets, and the
- * merge), 3 = one launch of the fused persistent kernel (a batch of whole steps), -1 = off.
+ * merge), 3 = one launch of the fused persistent kernel (a batch of whole steps), 4 = one
+ * launch of the LDS-resident step (a batch of whole steps), -1 = off.
  * qmc_profile resets the totals.  qmc_profile_read returns the summed milliseconds, the number of
  * timed launches and, in `covered` (may be NULL), the counter sums (walker_steps, key_steps,
  * child_steps, out_steps, spawn_steps, and in `step` the number of steps) of exactly the steps
- * that the timed launches ran -- for classes 1, 2 and 3; zeros for class 0.  The algorithmic
- * bytes of the timed kernels follow from these sums. */
+ * that the timed launches ran -- for classes 1 to 4; zeros for class 0.  The algorithmic
+ * bytes of the timed kernels follow from these sums.  The two whole-step classes are timed
+ * together: with class 3 or 4 selected, launches of both are timed, each into its own totals,
+ * which qmc_profile_read_class returns for any class (zeros for a class not timed);
+ * QMC_ERR_ARG for a class outside 0..4. */
 int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
 int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches, qmc_stats* covered);
+int qmc_profile_read_class(qmc_ctx* ctx, int32_t kernel_class, double* ms, uint64_t* launches,
+                           qmc_stats* covered);
 
 /* The quantized coefficient table of one step for this configuration and model, computed on
  * the host only (no device, no context), for scale * dt * L(t) (scale 1 for Euler, 3/2 and -1/2

@@ -28,9 +28,10 @@ EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_set_shift", "qmc_set_initiator", "qmc_set_proposal", "qmc_tune_sort",
             "qmc_use_graphs", "qmc_observe",
             "qmc_export", "qmc_import", "qmc_counters",
-            "qmc_profile", "qmc_profile_read", "qmc_coeff_table", "qmc_last_error",
+            "qmc_profile", "qmc_profile_read", "qmc_profile_read_class", "qmc_coeff_table",
+            "qmc_last_error",
             "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch",
-            "qmc_observe_noalloc"]
+            "qmc_observe_noalloc", "qmc_small_limit"]
 
 
 class Monomial(ctypes.Structure):
@@ -113,10 +114,12 @@ def lib():
         L.qmc_counters.argtypes = [vp, P(Stats)]
         L.qmc_profile.argtypes = [vp, ctypes.c_int32]
         L.qmc_step_path.argtypes = [vp, ctypes.c_int32]
+        L.qmc_small_limit.argtypes = [vp, u32]
         L.qmc_set_integrator.argtypes = [vp, ctypes.c_int32]
         L.qmc_set_prev.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(dbl), P(dbl)]
         L.qmc_export_prev.argtypes = [vp, u32, P(u64), P(i32), P(i32), u64, P(u64)]
         L.qmc_profile_read.argtypes = [vp, P(dbl), P(u64), P(Stats)]
+        L.qmc_profile_read_class.argtypes = [vp, ctypes.c_int32, P(dbl), P(u64), P(Stats)]
         L.qmc_coeff_table.argtypes = [P(Config), P(Model), P(dbl), P(dbl), dbl, u32, u32, P(u32),
                                       P(u64), P(u32), P(u32), P(u64), P(ctypes.c_int64)]
         L.qmc_last_error.argtypes = [vp]
@@ -421,25 +424,41 @@ class QMC:
         return k[:m].copy(), a[:m].copy(), b[:m].copy()
 
     def set_path(self, path):
-        """Step implementation: 'auto' (default), 'fused' (persistent kernel) or 'streamed'."""
-        self._check(lib().qmc_step_path(self._ctx, {"auto": 0, "fused": 1, "streamed": 2}[path]))
+        """Step implementation: 'auto' (default), 'fused' (persistent kernel), 'streamed' or
+        'small' (the LDS-resident step, while every replica fits)."""
+        self._check(lib().qmc_step_path(self._ctx, {"auto": 0, "fused": 1, "streamed": 2,
+                                                    "small": 3}[path]))
+
+    def small_limit(self, keys):
+        """Keys per replica up to which the automatic path takes the LDS-resident step (0: never;
+        at most 1024)."""
+        self._check(lib().qmc_small_limit(self._ctx, int(keys)))
+
+    _PROF_CLASSES = {None: -1, "spawn": 0, "sort": 1, "merge": 2, "fused": 3, "small": 4}
 
     def profile(self, kernel_class):
         """Time one kernel class with HIP events: 'spawn' (the draws of each step's records),
-        'sort', 'merge' (streamed path), 'fused' (one persistent launch) or None."""
-        cls = {None: -1, "spawn": 0, "sort": 1, "merge": 2, "fused": 3}[kernel_class]
-        self._check(lib().qmc_profile(self._ctx, cls))
+        'sort', 'merge' (streamed path), 'fused' (one persistent launch), 'small' (one
+        LDS-resident launch) or None.  'fused' and 'small' are timed together, each into its
+        own totals (profile_read(kind))."""
+        self._check(lib().qmc_profile(self._ctx, self._PROF_CLASSES[kernel_class]))
 
-    def profile_read(self):
-        """(milliseconds, launches, covered): the timed launches of the profiled class and the
-        counter sums of the steps they ran (see qmc_profile_read)."""
+    def profile_read(self, kernel_class=None):
+        """(milliseconds, launches, covered): the timed launches of the profiled class (or of
+        `kernel_class`) and the counter sums of the steps they ran (see qmc_profile_read)."""
         ms, n, st = ctypes.c_double(), ctypes.c_uint64(), Stats()
-        self._check(lib().qmc_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n),
-                                           ctypes.byref(st)))
+        if kernel_class is None:
+            self._check(lib().qmc_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n),
+                                               ctypes.byref(st)))
+        else:
+            self._check(lib().qmc_profile_read_class(self._ctx, self._PROF_CLASSES[kernel_class],
+                                                     ctypes.byref(ms), ctypes.byref(n),
+                                                     ctypes.byref(st)))
         cov = dict(steps=st.step, walker_steps=st.walker_steps, key_steps=st.key_steps,
                    child_steps=st.child_steps, out_steps=st.out_steps,
                    spawn_steps=st.spawn_steps)
         return ms.value, n.value, cov
+
 
 def _obs_args(R, pauli, psi, want_eps):
     """The qmc_obs_spec and the output arrays of an estimator call over R replicas (the arrays

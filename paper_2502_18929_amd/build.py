@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["qmc_kernels.hip", "qmc_persist.hip", "qmc_noalloc.hip", "qmc_host.cpp"]
+SOURCES = ["qmc_kernels.hip", "qmc_persist.hip", "qmc_small.hip", "qmc_noalloc.hip",
+           "qmc_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",  # host quantization must match the oracle's FP64 operation order

@@ -19,6 +19,7 @@
 #include "qmc_device.hpp"
 #include "qmc_kernels.h"
 #include "qmc_persist.h"
+#include "qmc_small.h"
 
 namespace {
 
@@ -36,6 +37,10 @@ constexpr uint32_t kSortIpts[] = {8, 12, 16, 24};
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
+constexpr int kProfClasses = 5;            // kernel classes qmc_profile times
+constexpr uint32_t kSmallAutoKeys = 256;   // default of qmc_small_limit
+// batches of the LDS-resident step in one chain (a window of steps)
+constexpr uint32_t kSmallBatches = (kMaxChunkSteps + kSmallBatch - 1) / kSmallBatch;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -57,7 +62,7 @@ struct QTerm {
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
-      tab_off, tabB_off, slots, done, pulse, mlp, total;
+      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -128,6 +133,8 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.done = take(8);
   L.pulse = take((size_t)n_circuits * 16);
   L.mlp = take(kMlpBytes);
+  L.small_fail = take(8);
+  L.small_stats = take((size_t)kSmallBatches * c.n_replicas * kSmallStats * 8);
   L.total = o;
   return true;
 }
@@ -179,11 +186,17 @@ struct qmc_ctx {
   std::vector<double> w_prev;       // AB2: weights of step s-1 (s then gamma)
   uint64_t n_occ = 0;               // occupied keys (all replicas) after the last device sync
   uint32_t streamed_until = 0;      // automatic mode: steps before this one run streamed
+  bool small_off = false;           // automatic mode: a replica outgrew the LDS-resident step
+  uint32_t small_limit = kSmallAutoKeys;  // automatic mode: keys per replica it runs up to
+  uint32_t small_epoch = 0;         // epoch of the last LDS-resident chain
   std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
-  double prof_ms = 0.0;
-  uint64_t prof_launches = 0;
+  // per kernel class: summed milliseconds and launches of the timed launches
+  double prof_ms[kProfClasses] = {};
+  uint64_t prof_launches[kProfClasses] = {};
   uint64_t relaunches = 0;  // fused launches that stopped to re-cut the key ranges
-  qmc_stats prof_cover{};            // counter deltas of the steps run by the timed class
+  qmc_stats prof_cover[kProfClasses] = {};  // counter deltas of the steps each class ran
+  // the whole-step classes (3 fused, 4 LDS-resident) are timed together
+  bool prof_whole() const { return prof_class == 3 || prof_class == 4; }
   qmc::Counters last_hc{};           // counters at the last device read
 
   template <class T>
@@ -645,6 +658,8 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
   e = hipMemsetAsync(c->counters(), 0, sizeof(qmc::Counters), c->stream);
   if (e == hipSuccess)
     e = hipMemsetAsync(c->at<uint64_t>(c->L.slots), 0, (size_t)2 * c->L.P * 4 * 8, c->stream);
+  if (e == hipSuccess)  // the LDS-resident step's stop word: no epoch yet
+    e = hipMemsetAsync(c->at<uint64_t>(c->L.small_fail), 0, 8, c->stream);
   // One copy each way between the pinned staging and the table area, of a size the runtime
   // hands to its DMA engines: their first use in a process costs several milliseconds, which
   // belongs to set-up rather than to the first qmc_step that uploads a window of tables.
@@ -693,16 +708,17 @@ int qmc_init(const qmc_config* cfg, const qmc_model* model, const uint64_t* keys
 
 namespace {
 
-// Adds the running-sum deltas between two counter reads to the timed class's coverage.
-void add_cover(qmc_ctx* c, const qmc::Counters& a, const qmc::Counters& b, uint32_t steps) {
-  c->prof_cover.step += steps;
-  c->prof_cover.walker_steps += b.walker_steps - a.walker_steps;
-  c->prof_cover.key_steps += b.key_steps - a.key_steps;
-  c->prof_cover.child_steps += b.child_steps - a.child_steps;
-  c->prof_cover.out_steps += b.out_steps - a.out_steps;
-  c->prof_cover.spawn_steps +=
-      (b.child_steps - b.death_steps) - (a.child_steps - a.death_steps);
-  c->prof_cover.rebalances += b.resplits - a.resplits;
+// Adds the running-sum deltas between two counter reads to a kernel class's coverage.
+void add_cover(qmc_ctx* c, int cls, const qmc::Counters& a, const qmc::Counters& b,
+               uint32_t steps) {
+  qmc_stats& v = c->prof_cover[cls];
+  v.step += steps;
+  v.walker_steps += b.walker_steps - a.walker_steps;
+  v.key_steps += b.key_steps - a.key_steps;
+  v.child_steps += b.child_steps - a.child_steps;
+  v.out_steps += b.out_steps - a.out_steps;
+  v.spawn_steps += (b.child_steps - b.death_steps) - (a.child_steps - a.death_steps);
+  v.rebalances += b.resplits - a.resplits;
 }
 
 constexpr uint64_t kFusedKeysPerSegment = 8192;  // automatic mode: larger stores run streamed
@@ -771,7 +787,7 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.cap_inbox = c->L.cap_child;
   pl.rebal_min = 64;
   pl.done = c->at<uint32_t>(c->L.done);
-  const bool prof = c->prof_class == 3;
+  const bool prof = c->prof_whole();
   if (prof) {
     while (c->prof_ev.size() < 2) {
       hipEvent_t ev;
@@ -789,14 +805,14 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   if (prof) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]));
-    c->prof_ms += ms;
-    c->prof_launches += 1;
+    c->prof_ms[3] += ms;
+    c->prof_launches[3] += 1;
   }
   kd = pin_done[0];
   reason = pin_done[1];
   if (reason == 1) {
     c->relaunches += 1;
-    if (prof) c->prof_cover.rebalances += 1;
+    if (prof) c->prof_cover[3].rebalances += 1;
   }
   bool sized = true;  // the kernel wrote the sizes of the stores gathered below
   if (reason == 2 || hc.err) {
@@ -823,7 +839,148 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   }
   c->step = pl.step0 + kd;
   c->n_occ = hc.n_store[c->cur];
-  if (prof) add_cover(c, before, hc, kd);
+  if (prof) add_cover(c, 3, before, hc, kd);
+  return QMC_OK;
+}
+
+// Steps of the chunk with the LDS-resident step, one workgroup per store segment (Euler, the
+// comb).  A segment that outgrows what the step holds stops the launch at the first such step F;
+// the steps before F are then run again from the unchanged canonical store (the results are the
+// same) and the automatic mode leaves the small step for this trajectory.  On return kd =
+// completed steps (0 if not even the first step fits) and the store reflects them.
+int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
+  const qmc::Counters before = c->last_hc;
+  const uint32_t step0 = c->step, nst = ch.nst;
+  const uint64_t segcap = c->L.segcap, P = c->L.P;
+  uint64_t* seg_k = c->at<uint64_t>(c->L.seg_k);
+  int2* seg_v = c->at<int2>(c->L.seg_v);
+  uint32_t* seg_n = c->at<uint32_t>(c->L.seg_n);
+  unsigned long long* dstop = c->at<unsigned long long>(c->L.small_fail);
+  uint64_t* dstats = c->at<uint64_t>(c->L.small_stats);
+  const uint64_t rows = (uint64_t)c->R;  // statistics rows of one batch
+  qmc::Counters* dcnt = c->counters();
+  SmallLaunch sl{};
+  sl.counters = dcnt;
+  sl.cur = c->cur;
+  sl.segcap = segcap;
+  sl.tab_base = ch.dtab;
+  sl.n_circuits = c->C;
+  sl.rep_per = c->Rc;
+  sl.n_segments = c->R;
+  sl.seed = c->cfg.seed;
+  sl.kbits = c->kbits;
+  sl.init_min = c->init_min;
+  sl.qshift = c->at<int64_t>(c->L.qshift);
+  sl.cap_store = std::min<uint64_t>(c->cfg.store_capacity,
+                                    c->path == 3 ? (uint64_t)kSmallCap : c->small_limit);
+  sl.cap_spawn = c->cfg.spawn_capacity;
+  sl.stop = dstop;
+  // batch j of a chain: steps [first + j B, ...), from the canonical store (j = 0) or from
+  // segment buffer (j - 1) & 1, into segment buffer j & 1, statistics into row block j
+  auto batch = [&](uint32_t j, uint32_t first, uint32_t steps) {
+    const uint32_t ib = (j + 1) & 1, ob = j & 1;
+    sl.ck = j == 0 ? c->sk(0) : nullptr;
+    sl.cv = j == 0 ? c->sv(0) : nullptr;
+    sl.ik = seg_k + ib * P * segcap;
+    sl.iv = seg_v + ib * P * segcap;
+    sl.in_n = seg_n + ib * P;
+    sl.ok = seg_k + ob * P * segcap;
+    sl.ov = seg_v + ob * P * segcap;
+    sl.out_n = seg_n + ob * P;
+    sl.tab_off = c->at<uint32_t>(c->L.tab_off) + (size_t)(ch.first + first) * c->C;
+    sl.step0 = step0 + first;
+    sl.nsteps = steps;
+    sl.stats = dstats + (size_t)j * rows * kSmallStats;
+    return qmcs_launch(c->stream, &sl);
+  };
+  // the segments batch jd - 1 wrote into the canonical store and the statistics of batches
+  // [0, jd) into the counters; gated on the stop word of `epoch` when stop is given
+  auto finish = [&](uint32_t jd, const unsigned long long* stop, uint32_t epoch) -> int {
+    const uint32_t ob = (jd - 1) & 1;
+    HIPCHK(c, qmcs_gather(c->stream, seg_k + ob * P * segcap, seg_v + ob * P * segcap,
+                          seg_n + ob * P, segcap, c->R, c->sk(0), c->sv(0),
+                          &dcnt->n_store[c->cur], stop, epoch));
+    HIPCHK(c, qmcs_commit(c->stream, dcnt, dstats, (uint32_t)(jd * rows), stop, epoch));
+    return 0;
+  };
+  const bool prof = c->prof_whole();
+  if (prof) {
+    while (c->prof_ev.size() < 2) {
+      hipEvent_t ev;
+      HIPCHK(c, hipEventCreate(&ev));
+      c->prof_ev.push_back(ev);
+    }
+  }
+  uint64_t* pin_stop = reinterpret_cast<uint64_t*>(c->pinned_small + 4096);
+  // One chain over steps [first, first + steps) with its gated gather and commit, then one
+  // synchronization (with the counters); jd = the batches whose results are committed, stop =
+  // the first step not taken, or ~0.
+  auto run_chain = [&](uint32_t first, uint32_t steps, uint32_t& jd, uint32_t& stop) -> int {
+    const uint32_t nb = (steps + kSmallBatch - 1) / kSmallBatch;
+    const uint32_t epoch = ++c->small_epoch;
+    sl.epoch = epoch;
+    if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[0], c->stream));
+    for (uint32_t j = 0; j < nb; ++j) {
+      const uint32_t a = j * kSmallBatch;
+      HIPCHK(c, batch(j, first + a, std::min(kSmallBatch, steps - a)));
+    }
+    if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[1], c->stream));
+    int rc = finish(nb, dstop, epoch);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(pin_stop, dstop, 8, hipMemcpyDeviceToHost, c->stream));
+    rc = read_counters(c, hc);  // synchronizes the stream
+    if (rc) return rc;
+    if (prof) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]));
+      c->prof_ms[4] += ms;
+      c->prof_launches[4] += nb;
+    }
+    const uint64_t w = *pin_stop;
+    if ((uint32_t)(w >> 32) != epoch) {
+      jd = nb;
+      stop = 0xFFFFFFFFu;
+      return 0;
+    }
+    stop = 0xFFFFFFFFu - (uint32_t)w;
+    const uint32_t s0 = step0 + first;
+    if (stop < s0 || stop >= s0 + steps) {
+      c->broken = true;
+      return fail(c, QMC_ERR_HIP, "small step: stop outside the chain");
+    }
+    jd = (stop - s0) / kSmallBatch;  // complete batches, not committed yet
+    if (jd > 0) {
+      rc = finish(jd, nullptr, 0);
+      if (rc) return rc;
+    }
+    return 0;
+  };
+  kd = 0;
+  uint32_t jd = 0, stop = 0;
+  int rc = run_chain(0, nst, jd, stop);
+  if (rc) return rc;
+  kd = std::min<uint32_t>(jd * kSmallBatch, nst);
+  if (stop != 0xFFFFFFFFu) {
+    c->small_off = true;
+    const uint32_t rest = stop - step0 - kd;  // steps of the stopped batch that every replica took
+    if (rest > 0) {
+      uint32_t jd2 = 0, stop2 = 0;
+      rc = run_chain(kd, rest, jd2, stop2);
+      if (rc) return rc;
+      if (stop2 != 0xFFFFFFFFu) {
+        c->broken = true;
+        return fail(c, QMC_ERR_HIP, "small step: inconsistent stop");
+      }
+      kd += rest;
+    } else if (jd > 0) {
+      rc = read_counters(c, hc);  // the committed batches
+      if (rc) return rc;
+    }
+  }
+  if (kd == 0) return QMC_OK;  // not even the first step fits: nothing ran
+  c->step = step0 + kd;
+  c->n_occ = hc.n_store[c->cur];
+  if (prof) add_cover(c, 4, before, hc, kd);
   return QMC_OK;
 }
 
@@ -972,8 +1129,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     for (uint32_t k = 0; k < nst; ++k) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
-      c->prof_ms += ms;
-      c->prof_launches += 1;
+      c->prof_ms[c->prof_class] += ms;
+      c->prof_launches[c->prof_class] += 1;
     }
   }
   kd = nst;
@@ -1005,7 +1162,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   c->cur = cur;
   c->step = step0 + kd;
   c->n_occ = hc.n_store[cur];
-  if (c->prof_class == 1 || c->prof_class == 2) add_cover(c, before, hc, kd);
+  if (c->prof_class == 1 || c->prof_class == 2) add_cover(c, c->prof_class, before, hc, kd);
   return QMC_OK;
 }
 
@@ -1266,6 +1423,9 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
                                 "automatic or streamed path");
   if (c->path == 1 && c->prop.kind)
     return fail(c, QMC_ERR_ARG, "spawn proposals run on the streamed path");
+  if (c->path == 3 && (ab2 || c->prop.kind || !fused_fits || c->R > c->L.P))
+    return fail(c, QMC_ERR_ARG, "the LDS-resident step runs the Euler step and the comb with "
+                                "step tables of at most 8 KB, one workgroup per segment");
   uint32_t last_local_fail = 0xFFFFFFFFu;
   int32_t shift_mode = -1;  // shifts on the device: 0 single Euler term, 1 both AB2 terms
   while (c->step < first_step + nsteps) {
@@ -1274,6 +1434,11 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     const bool fused = c->path == 1 || (c->path == 0 && fused_fits && !c->prop.kind &&
                                         c->step >= c->streamed_until &&
                                         c->n_occ <= fused_max_keys);
+    // the LDS-resident step: Euler, the comb, tables the fused kernel takes, every segment
+    // small (tried while the whole store could fit; a segment that does not fit stops it)
+    const bool small = c->path == 3 ||
+                       (c->path == 0 && fused && !ab2 && !c->small_off && c->R <= c->L.P &&
+                        c->small_limit > 0 && c->n_occ <= (uint64_t)c->R * c->small_limit);
     if (shift_mode != (int32_t)two) {
       // shifts of this chunk's tables
       std::vector<int64_t> q(2 * (size_t)c->R, 0);
@@ -1317,6 +1482,17 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     ch.first = k0 - win0;
     qmc::Counters hc;
     uint32_t kd = 0, reason = 0;
+    if (small) {
+      int rc = run_small(c, ch, kd, hc);
+      if (rc) return rc;
+      if (kd == 0) {
+        if (c->path == 3)
+          return fail(c, QMC_ERR_STORE_CAP, "step " + std::to_string(c->step) +
+                                                ": a replica outgrows the LDS-resident step");
+        continue;  // the automatic mode takes this step with the fused kernel
+      }
+      continue;
+    }
     int rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);
     if (rc) return rc;
     if (ab2 && kd > 0) {
@@ -1360,9 +1536,17 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
 }  // namespace
 
 int qmc_step_path(qmc_ctx* c, int32_t path) {
-  if (!c || path < 0 || path > 2) return QMC_ERR_ARG;
+  if (!c || path < 0 || path > 3) return QMC_ERR_ARG;
   c->path = path;
   c->streamed_until = 0;
+  c->small_off = false;
+  return QMC_OK;
+}
+
+int qmc_small_limit(qmc_ctx* c, uint32_t keys) {
+  if (!c || keys > (uint32_t)kSmallCap) return QMC_ERR_ARG;
+  c->small_limit = keys;
+  c->small_off = false;
   return QMC_OK;
 }
 
@@ -1750,6 +1934,7 @@ int qmc_import(qmc_ctx* c, uint32_t replica, const uint64_t* keys, const int32_t
   rc = upload_store(c, c->cur, nk, nv);
   if (rc) return rc;
   c->step = step;
+  c->small_off = false;  // a new state: the LDS-resident step may fit again
   return QMC_OK;
 }
 
@@ -1854,20 +2039,34 @@ int qmc_counters(qmc_ctx* c, qmc_stats* out) {
 }
 
 int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
-  if (!c || kernel_class < -1 || kernel_class > 3) return QMC_ERR_ARG;
+  if (!c || kernel_class < -1 || kernel_class > 4) return QMC_ERR_ARG;
   c->prof_class = kernel_class;
-  c->prof_ms = 0.0;
-  c->prof_launches = 0;
-  c->prof_cover = qmc_stats{};
+  for (int k = 0; k < kProfClasses; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_launches[k] = 0;
+    c->prof_cover[k] = qmc_stats{};
+  }
+  return QMC_OK;
+}
+
+int qmc_profile_read_class(qmc_ctx* c, int32_t kernel_class, double* ms, uint64_t* launches,
+                           qmc_stats* covered) {
+  if (!c || kernel_class < 0 || kernel_class >= kProfClasses) return QMC_ERR_ARG;
+  if (ms) *ms = c->prof_ms[kernel_class];
+  if (launches) *launches = c->prof_launches[kernel_class];
+  if (covered) *covered = c->prof_cover[kernel_class];
   return QMC_OK;
 }
 
 int qmc_profile_read(qmc_ctx* c, double* ms, uint64_t* launches, qmc_stats* covered) {
   if (!c) return QMC_ERR_ARG;
-  if (ms) *ms = c->prof_ms;
-  if (launches) *launches = c->prof_launches;
-  if (covered) *covered = c->prof_cover;
-  return QMC_OK;
+  if (c->prof_class < 0) {
+    if (ms) *ms = 0.0;
+    if (launches) *launches = 0;
+    if (covered) *covered = qmc_stats{};
+    return QMC_OK;
+  }
+  return qmc_profile_read_class(c, c->prof_class, ms, launches, covered);
 }
 
 int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double* s,

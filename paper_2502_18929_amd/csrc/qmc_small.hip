@@ -1,0 +1,543 @@
+// qmc_small.hip -- the population-dynamics step for stores small enough that one workgroup holds
+// a whole replica (gfx950, wave64).
+//
+// Replicas are independent samples (eq. (3)): walkers of one replica only ever spawn onto keys of
+// the same replica.  While every replica has at most kSmallCap occupied keys, workgroup r keeps
+// replica (store segment) r in LDS and advances it through a batch of steps alone -- no
+// grid-wide synchronization, no global memory traffic but the step tables.  One step of a
+// workgroup, for its sorted parents N(s):
+//   1. Philox once per parent (step s, its replica, stream 0): w0 (spawn comb), w1 (death comb);
+//      the parents whose death or spawn comb can fire are listed;
+//   2. each listed parent is taken by a team of T lanes (T = the largest power of two up to 64
+//      that gives every parent a team): the diagonal group's terms are split over the team and
+//      the partial coefficients added up (integer sums, exact); lane 0 applies the death comb
+//      started at w1 to N(s) (End Matter, spawn step, the walker's own key included).  The
+//      off-diagonal groups are split over the team in table order; a lane's comb starts at w0
+//      plus the amounts of the earlier lanes' groups, mod 2^32, which is where the single comb
+//      over all groups in order stands (a comb's remainder after any run of steps is its start
+//      plus their amounts, mod 2^32), so every child equals the one of the plain sequential comb.
+//      A child landing on an occupied key is added to that key's delta (binary search in LDS,
+//      LDS atomics); one landing elsewhere goes to a list of new records (dropped if its parent
+//      is not an initiator);
+//   3. the new records are sorted (rank by counting) and merged with the parents plus their
+//      deltas: int64 sums, int32 range check, (0, 0) dropped (annihilation, End Matter) -> N(s+1).
+// A workgroup whose replica outgrows the key limit, produces more than kSmallNew new records in
+// one step, or leaves int32 records the step in the chain's stop word and stops.  The host
+// launches a call's steps as a chain of batches of at most kSmallBatch steps, each reading the
+// segments the one before wrote, then the gather of the last batch's segments into the canonical
+// store and the commit of the statistics; every kernel of the chain does nothing once the stop
+// word is set, so after a stop the last complete batch's segments hold the state, and the host
+// gathers them, runs the steps up to the stop again from there (the results are the same, the
+// draws being keyed on the walkers) and continues with the other step paths.  The stop word is
+// (chain epoch << 32) | ~step, raised with atomicMax: it belongs to a chain only when it carries
+// that chain's epoch (no reset between chains), and within a chain it keeps the earliest step.
+#include "qmc_device.hpp"
+#include "qmc_persist.h"
+#include "qmc_small.h"
+
+namespace qmc {
+
+constexpr int kSBlock = 512;
+constexpr int kSWaves = kSBlock / kWave;
+constexpr int kSTab = kPersistTableBytes / 16;  // uint4 words of a step table
+constexpr uint32_t kActIdx = 0xFFFFu;           // active-list entry: parent index, comb flags
+constexpr uint32_t kActD = 1u << 16;
+constexpr uint32_t kActS = 1u << 17;
+static_assert(kSmallCap <= (int)kActIdx + 1, "parent index in 16 bits");
+static_assert(kSmallCap < 65536 && kSmallNew < 65536, "merge split points in 16 bits");
+
+struct SmallArgs {
+  const uint64_t* ck;       // canonical store (all segments, sorted), n_store[cur] records; or
+  const int2* cv;           // null: the input is segment `seg` of (ik, iv, in_n)
+  const Counters* cnt;
+  uint32_t cur;
+  const uint64_t* ik;       // input segments [R][segcap], counts in_n
+  const int2* iv;
+  const uint32_t* in_n;
+  uint64_t* ok;             // output segments [R][segcap], counts out_n
+  int2* ov;
+  uint32_t* out_n;
+  uint64_t segcap;
+  const uint8_t* tab_base;  // step k of circuit c at tab_base + tab_off[k * n_circuits + c]
+  const uint32_t* tab_off;
+  uint32_t n_circuits, rep_per;
+  uint32_t step0, nsteps;
+  uint64_t seed;
+  KeyLayout kl;
+  const int64_t* qshift;    // per-segment Q32 shifts
+  uint32_t cap_store;       // keys per replica allowed (at most kSmallCap)
+  uint64_t cap_spawn;       // records (children and death deltas) per replica and step allowed
+  unsigned long long* stop; // the chain's stop word (see above)
+  uint32_t epoch;
+  uint64_t* stats;          // [R][kSmallStats] of this batch
+};
+
+__device__ __forceinline__ bool chain_stopped(const unsigned long long* stop, uint32_t epoch) {
+  return (uint32_t)(__hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) ==
+         epoch;
+}
+
+__device__ __forceinline__ void chain_stop(unsigned long long* stop, uint32_t epoch,
+                                           uint32_t step) {
+  atomicMax(stop, ((unsigned long long)epoch << 32) | (0xFFFFFFFFu - step));
+}
+
+struct SmallShared {
+  uint64_t pk[2][kSmallCap];
+  int2 pv[2][kSmallCap];
+  unsigned long long dre[kSmallCap];   // int64 deltas (two's complement) of the parents
+  unsigned long long dim[kSmallCap];
+  uint2 w[kSmallCap];                  // Philox words of the parents: x spawn, y death
+  uint32_t act[kSmallCap];             // parents whose death or spawn comb can fire
+  uint64_t nk[kSmallNew];              // new records: composite key, value
+  int2 nv[kSmallNew];
+  uint64_t sk[kSmallNew];              // the same, sorted
+  int2 sv[kSmallNew];
+  uint4 tab[2][kSTab];
+  uint32_t xsplit[kSBlock];
+  uint32_t scan[kSWaves];
+  uint64_t red[kSWaves];
+  uint32_t nnew;
+  uint32_t nact;
+  uint32_t flag;                       // a limit was exceeded in this step
+};
+
+__device__ __forceinline__ void load_table(uint4* dst, const uint8_t* src) {
+  // a table area of kPersistTableBytes bytes (the device area has that much slack past its end),
+  // LDS-direct dword loads
+  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+  uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
+  constexpr uint32_t ndw = kPersistTableBytes / 4;
+  for (uint32_t c = wave; c * kWave < ndw; c += kSWaves)
+    __builtin_amdgcn_global_load_lds(s32 + c * kWave + lane, d32 + c * kWave, 4, 0, 0);
+}
+
+__global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
+  __shared__ SmallShared S;
+  const uint32_t t = threadIdx.x, wave = t / kWave, lane = __lane_id();
+  const uint32_t seg = blockIdx.x;
+  const KeyLayout kl = A.kl;
+  const uint32_t circ = seg / A.rep_per;
+  const int64_t qs = A.qshift[seg];
+  // this replica's input records; nothing at all once an earlier batch of the chain stopped
+  if (t == 0) {
+    const uint32_t stop = chain_stopped(A.stop, A.epoch);
+    uint64_t a = 0, e = 0;
+    if (!stop && A.ck) {
+      const uint64_t n_can = A.cnt->n_store[A.cur];
+      const uint64_t lo = kl.kbits >= 64 ? 0 : ((uint64_t)seg << kl.kbits);
+      uint64_t x = 0, y = n_can;
+      while (x < y) {
+        const uint64_t m = (x + y) >> 1;
+        if (A.ck[m] < lo) x = m + 1; else y = m;
+      }
+      a = x;
+      e = n_can;
+      if (kl.kbits < 64) {
+        const uint64_t hi = (uint64_t)(seg + 1) << kl.kbits;
+        y = n_can;
+        while (x < y) {
+          const uint64_t m = (x + y) >> 1;
+          if (A.ck[m] < hi) x = m + 1; else y = m;
+        }
+        e = x;
+      }
+    } else if (!stop) {
+      a = (uint64_t)seg * A.segcap;
+      e = a + A.in_n[seg];
+    }
+    S.red[0] = a;
+    S.red[1] = e;
+    S.flag = stop;
+  }
+  __syncthreads();
+  if (S.flag) return;
+  const uint64_t base = S.red[0];
+  if (S.red[1] - base > (uint64_t)A.cap_store) {
+    if (t == 0) chain_stop(A.stop, A.epoch, A.step0);
+    return;
+  }
+  uint32_t n = (uint32_t)(S.red[1] - base);
+  const uint64_t* srck = A.ck ? A.ck : A.ik;
+  const int2* srcv = A.ck ? A.cv : A.iv;
+  for (uint32_t i = t; i < n; i += kSBlock) {
+    S.pk[0][i] = srck[base + i];
+    S.pv[0][i] = srcv[base + i];
+  }
+  if (A.nsteps > 0) load_table(S.tab[0], A.tab_base + A.tab_off[circ]);
+  uint64_t st_w = 0, st_k = 0, st_c = 0, st_d = 0, st_o = 0;  // thread 0
+  uint32_t b = 0;  // parent buffer
+  uint32_t kdone = 0;
+  for (uint32_t k = 0; k < A.nsteps; ++k) {
+    const uint32_t s = A.step0 + k;
+    __builtin_amdgcn_s_waitcnt(0);  // the step table (and the parents on the first step)
+    if (t == 0) {
+      S.nnew = 0;
+      S.nact = 0;
+      S.flag = 0;
+    }
+    __syncthreads();
+    // the next step's table, in flight during this step
+    if (k + 1 < A.nsteps)
+      load_table(S.tab[(k + 1) & 1], A.tab_base + A.tab_off[(size_t)(k + 1) * A.n_circuits + circ]);
+    const TableViewT<lptr> tv = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab[k & 1]));
+    const uint32_t G = tv.h->n_groups;
+    const uint64_t q_off = G > 1 ? tv.h->q_off : 0, q_diag = tv.h->q_diag + uabs64(qs);
+    // 1: Philox, walker statistics, deltas cleared, list of the parents that can fire
+    uint64_t wsum = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += kSBlock) {  // block-uniform
+      const uint32_t i = i0 + t;
+      bool dact = false, sact = false;
+      if (i < n) {
+        const uint64_t ck = S.pk[b][i];
+        const int2 v = S.pv[b][i];
+        uint32_t r4[4];
+        walker_random(kl.key(ck), s, seg, A.seed, 0u, r4);
+        const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+        wsum += sab;
+        dact = !comb_all_zero(sab, q_diag, r4[1]);
+        sact = !comb_all_zero(sab, q_off, r4[0]);
+        S.w[i] = make_uint2(r4[0], r4[1]);
+        S.dre[i] = 0;
+        S.dim[i] = 0;
+      }
+      const bool act = dact || sact;
+      const uint64_t m = __ballot(act);
+      if (m) {  // wave-uniform
+        uint32_t at = 0;
+        if (lane == 0) at = atomicAdd(&S.nact, (uint32_t)__popcll(m));
+        at = __shfl(at, 0);
+        if (act)
+          S.act[at + (uint32_t)__popcll(m & lanemask_lt())] =
+              i | (dact ? kActD : 0u) | (sact ? kActS : 0u);
+      }
+    }
+    __syncthreads();
+    // 2: death deltas and children, a team of T lanes per listed parent
+    const uint32_t nact = S.nact;
+    uint32_t T = 1;
+    while (T < (uint32_t)kWave && 2 * T * nact <= (uint32_t)kSBlock) T *= 2;
+    const uint32_t lt = t & (T - 1), nteam = kSBlock / T, team = t / T;
+    const uint32_t nd = tv.gs[1] / kTermPad;
+    const uint32_t d0 = nd * lt / T * kTermPad, d1 = nd * (lt + 1) / T * kTermPad;
+    const uint32_t g0 = 1 + (G - 1) * lt / T, g1 = 1 + (G - 1) * (lt + 1) / T;
+    uint32_t ndeath = 0, nchild = 0;
+    for (uint32_t a0 = 0; a0 < nact; a0 += nteam) {  // block-uniform
+      const uint32_t ai = a0 + team;
+      const bool has = ai < nact;  // team-uniform
+      const uint32_t e = has ? S.act[ai] : 0u;
+      const uint32_t i = e & kActIdx;
+      const bool dact = (e & kActD) != 0, sact = (e & kActS) != 0;
+      const uint64_t ck = has ? S.pk[b][i] : 0;
+      const int2 v = has ? S.pv[b][i] : make_int2(0, 0);
+      const uint2 w = has ? S.w[i] : make_uint2(0, 0);
+      const uint64_t key = kl.key(ck);
+      // death: partial diagonal coefficients over the team's slices of the group 0 terms
+      int32_t pre = 0, pim = 0;
+      if (dact) group_coeff_part(tv.t, d0, d1, key, pre, pim);
+      for (uint32_t o = 1; o < T; o <<= 1) {
+        pre += __shfl_xor(pre, (int)o);
+        pim += __shfl_xor(pim, (int)o);
+      }
+      if (dact && lt == 0) {
+        int64_t xre, xim;
+        cmul_q32(v.x, v.y, pre + (int32_t)qs, pim, xre, xim);
+        uint64_t r = w.y;
+        const int64_t dx = comb_step(r, xre), dy = comb_step(r, xim);
+        if ((dx | dy) != 0) {
+          atomicAdd(&S.dre[i], (unsigned long long)dx);
+          atomicAdd(&S.dim[i], (unsigned long long)dy);
+          ++ndeath;
+        }
+      }
+      // spawn: the comb of lane lt starts after the amounts of the team's earlier lanes
+      uint32_t amt = 0;
+      if (sact && T > 1) {
+        for (uint32_t g = g0; g < g1; ++g) {
+          int32_t cre, cim;
+          group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+          int64_t xre, xim;
+          cmul_q32(v.x, v.y, cre, cim, xre, xim);
+          amt += (uint32_t)uabs64(xre) + (uint32_t)uabs64(xim);
+        }
+      }
+      uint32_t incl = amt;
+      for (uint32_t o = 1; o < T; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lt >= o) incl += y;
+      }
+      if (sact) {
+        const bool initiator = uabs64(v.x) + uabs64(v.y) >= kl.init_min;
+        uint64_t r = (uint32_t)(w.x + (incl - amt));
+        for (uint32_t g = g0; g < g1; ++g) {
+          int32_t cre, cim;
+          group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+          int64_t xre, xim;
+          cmul_q32(v.x, v.y, cre, cim, xre, xim);
+          const int64_t nre = comb_step(r, xre), nim = comb_step(r, xim);
+          if ((nre | nim) == 0) continue;
+          ++nchild;
+          const uint64_t tk = ck ^ tv.gx[g];
+          uint32_t lo = 0, hi = n;
+          while (lo < hi) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (S.pk[b][m] < tk) lo = m + 1; else hi = m;
+          }
+          if (lo < n && S.pk[b][lo] == tk) {
+            atomicAdd(&S.dre[lo], (unsigned long long)nre);
+            atomicAdd(&S.dim[lo], (unsigned long long)nim);
+          } else if (initiator) {
+            const uint32_t at = atomicAdd(&S.nnew, 1u);
+            if (at < (uint32_t)kSmallNew) {
+              S.nk[at] = tk;
+              S.nv[at] = make_int2((int32_t)nre, (int32_t)nim);
+            } else {
+              S.flag = 1;
+            }
+          }
+        }
+      }
+    }
+    // statistics of the step (block reductions)
+    for (int o = 32; o > 0; o >>= 1) {
+      wsum += __shfl_xor(wsum, o);
+      ndeath += __shfl_xor(ndeath, o);
+      nchild += __shfl_xor(nchild, o);
+    }
+    if (lane == 0) {
+      S.red[wave] = wsum;
+      S.xsplit[wave] = ndeath;
+      S.xsplit[kSWaves + wave] = nchild;
+    }
+    __syncthreads();
+    if (t == 0) {
+      for (int x = 0; x < kSWaves; ++x) {
+        st_w += S.red[x];
+        st_d += S.xsplit[x];
+        st_c += S.xsplit[kSWaves + x] + S.xsplit[x];
+      }
+      st_k += n;
+    }
+    const uint32_t nn = S.nnew < (uint32_t)kSmallNew ? S.nnew : (uint32_t)kSmallNew;
+    uint64_t nrec = 0;
+    for (int x = 0; x < kSWaves; ++x) nrec += S.xsplit[x] + S.xsplit[kSWaves + x];
+    if (S.flag || nrec > A.cap_spawn) break;  // block-uniform: the step does not fit
+    __syncthreads();
+    // 3a: the new records in key order (rank = smaller keys, then equal keys of smaller index)
+    for (uint32_t i = t; i < nn; i += kSBlock) {
+      const uint64_t ki = S.nk[i];
+      uint32_t rank = 0;
+      for (uint32_t j = 0; j < nn; ++j) {
+        const uint64_t kj = S.nk[j];
+        rank += (kj < ki || (kj == ki && j < i)) ? 1u : 0u;
+      }
+      S.sk[rank] = ki;
+      S.sv[rank] = S.nv[i];
+    }
+    __syncthreads();
+    // 3b: merge of the parents (plus deltas) with the sorted new records, split over the threads
+    // at run ends (a run is one parent or a run of new records of one key: at most one child of
+    // a key per off-diagonal group, fewer than the split's search window)
+    const uint32_t tot = n + nn;
+    const uint32_t per = (tot + kSBlock - 1) / kSBlock;
+    auto KA = [&](uint32_t x) { return S.pk[b][x]; };
+    auto KB = [&](uint32_t x) { return S.sk[x]; };
+    uint32_t d = t * per;
+    if (d > tot) d = tot;
+    uint32_t i0, j0;
+    run_split(KA, n, KB, nn, d, i0, j0);
+    S.xsplit[t] = i0 | (j0 << 16);
+    __syncthreads();
+    uint32_t i1, j1;
+    if (t + 1 < (uint32_t)kSBlock) {
+      i1 = S.xsplit[t + 1] & 0xFFFFu;
+      j1 = S.xsplit[t + 1] >> 16;
+    } else {
+      i1 = n;
+      j1 = nn;
+    }
+    auto walk = [&](auto&& out) __attribute__((always_inline)) {
+      uint32_t i = i0, j = j0;
+      while (i < i1 || j < j1) {
+        uint64_t key;
+        int64_t re, im;
+        if (j >= j1 || (i < i1 && S.pk[b][i] <= S.sk[j])) {
+          key = S.pk[b][i];
+          re = (int64_t)S.pv[b][i].x + (int64_t)S.dre[i];
+          im = (int64_t)S.pv[b][i].y + (int64_t)S.dim[i];
+          ++i;
+        } else {
+          key = S.sk[j];
+          re = im = 0;
+        }
+        while (j < j1 && S.sk[j] == key) {
+          re += S.sv[j].x;
+          im += S.sv[j].y;
+          ++j;
+        }
+        out(key, re, im);
+      }
+    };
+    uint32_t count = 0;
+    bool over = false;
+    walk([&](uint64_t, int64_t re, int64_t im) __attribute__((always_inline)) {
+      if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) over = true;
+      count += (re != 0 || im != 0) ? 1u : 0u;
+    });
+    uint32_t incl = count;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t x = __shfl_up(incl, o);
+      if (lane >= (uint32_t)o) incl += x;
+    }
+    if (over) S.flag = 2;
+    if (lane == kWave - 1) S.scan[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, agg = 0;
+    for (uint32_t x = 0; x < (uint32_t)kSWaves; ++x) {
+      wpre += x < wave ? S.scan[x] : 0u;
+      agg += S.scan[x];
+    }
+    if (S.flag || agg > A.cap_store) break;  // block-uniform
+    uint32_t o = wpre + incl - count;
+    walk([&](uint64_t key, int64_t re, int64_t im) __attribute__((always_inline)) {
+      if (re != 0 || im != 0) {
+        S.pk[b ^ 1][o] = key;
+        S.pv[b ^ 1][o] = make_int2((int32_t)re, (int32_t)im);
+        ++o;
+      }
+    });
+    if (t == 0) st_o += agg;
+    n = agg;
+    b ^= 1;
+    kdone = k + 1;
+    __syncthreads();
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if (kdone < A.nsteps) {
+    // this replica could not take step step0 + kdone (more keys or new records than the LDS
+    // holds, or a population outside int32)
+    if (t == 0) chain_stop(A.stop, A.epoch, A.step0 + kdone);
+    return;
+  }
+  uint64_t* ok = A.ok + (uint64_t)seg * A.segcap;
+  int2* ov = A.ov + (uint64_t)seg * A.segcap;
+  for (uint32_t i = t; i < n; i += kSBlock) {
+    ok[i] = S.pk[b][i];
+    ov[i] = S.pv[b][i];
+  }
+  if (t == 0) {
+    A.out_n[seg] = n;
+    uint64_t* st = A.stats + (uint64_t)seg * kSmallStats;
+    st[0] = st_w;
+    st[1] = st_k;
+    st[2] = st_c;
+    st[3] = st_o;
+    st[4] = st_d;
+  }
+}
+
+// The last batch's segments into the canonical store (one workgroup per segment), unless the
+// chain stopped (stop == null: always).
+__global__ __launch_bounds__(256) void k_small_gather(const uint64_t* __restrict__ sk,
+                                                      const int2* __restrict__ sv,
+                                                      const uint32_t* __restrict__ seg_n,
+                                                      uint64_t segcap, uint64_t* __restrict__ ck,
+                                                      int2* __restrict__ cv, uint64_t* count,
+                                                      const unsigned long long* stop,
+                                                      uint32_t epoch) {
+  __shared__ uint64_t s_off;
+  __shared__ uint32_t s_skip;
+  const uint32_t p = blockIdx.x, R = gridDim.x;
+  if (threadIdx.x == 0) {
+    s_skip = stop && chain_stopped(stop, epoch);
+    uint64_t o = 0;
+    for (uint32_t q = 0; q < p; ++q) o += seg_n[q];
+    s_off = o;
+    if (!s_skip && p == R - 1) *count = o + seg_n[p];
+  }
+  __syncthreads();
+  if (s_skip) return;
+  const uint64_t off = s_off, n = seg_n[p];
+  const uint64_t* k = sk + (uint64_t)p * segcap;
+  const int2* v = sv + (uint64_t)p * segcap;
+  for (uint64_t i = threadIdx.x; i < n; i += 256) {
+    ck[off + i] = k[i];
+    cv[off + i] = v[i];
+  }
+}
+
+// The statistics of the completed batches into the counters (one workgroup), unless the chain
+// stopped (stop == null: always).
+__global__ void k_small_commit(Counters* cnt, const uint64_t* stats, uint32_t nrows,
+                               const unsigned long long* stop, uint32_t epoch) {
+  __shared__ unsigned long long s_sum[kSmallStats];
+  if (stop && chain_stopped(stop, epoch)) return;  // one word, read the same by every thread
+  if (threadIdx.x < (uint32_t)kSmallStats) s_sum[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nrows * (uint32_t)kSmallStats; i += blockDim.x)
+    atomicAdd(&s_sum[i % kSmallStats], (unsigned long long)stats[i]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cnt->walker_steps += s_sum[0];
+    cnt->key_steps += s_sum[1];
+    cnt->child_steps += s_sum[2];
+    cnt->out_steps += s_sum[3];
+    cnt->death_steps += s_sum[4];
+  }
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" {
+
+int qmcs_launch(hipStream_t st, const SmallLaunch* L) {
+  SmallArgs a;
+  a.ck = L->ck;
+  a.cv = L->cv;
+  a.cnt = (const Counters*)L->counters;
+  a.cur = L->cur;
+  a.ik = L->ik;
+  a.iv = L->iv;
+  a.in_n = L->in_n;
+  a.ok = L->ok;
+  a.ov = L->ov;
+  a.out_n = L->out_n;
+  a.segcap = L->segcap;
+  a.tab_base = L->tab_base;
+  a.tab_off = L->tab_off;
+  a.n_circuits = L->n_circuits;
+  a.rep_per = L->rep_per;
+  a.step0 = L->step0;
+  a.nsteps = L->nsteps;
+  a.seed = L->seed;
+  a.kl = KeyLayout{L->kbits, L->kbits >= 64 ? ~0ull : ((1ull << L->kbits) - 1), 0u,
+                   L->init_min};
+  a.qshift = L->qshift;
+  a.cap_store = (uint32_t)(L->cap_store < (uint64_t)kSmallCap ? L->cap_store : kSmallCap);
+  a.cap_spawn = L->cap_spawn;
+  a.stop = L->stop;
+  a.epoch = L->epoch;
+  a.stats = L->stats;
+  hipLaunchKernelGGL(k_small, dim3(L->n_segments), dim3(kSBlock), 0, st, a);
+  return (int)hipGetLastError();
+}
+
+int qmcs_gather(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
+                uint64_t segcap, uint32_t n_segments, uint64_t* ck, int2* cv, uint64_t* count,
+                const unsigned long long* stop, uint32_t epoch) {
+  hipLaunchKernelGGL(k_small_gather, dim3(n_segments), dim3(256), 0, st, sk, sv, seg_n, segcap,
+                     ck, cv, count, stop, epoch);
+  return (int)hipGetLastError();
+}
+
+int qmcs_commit(hipStream_t st, void* counters, const uint64_t* stats, uint32_t nrows,
+                const unsigned long long* stop, uint32_t epoch) {
+  hipLaunchKernelGGL(k_small_commit, dim3(1), dim3(256), 0, st, (Counters*)counters, stats,
+                     nrows, stop, epoch);
+  return (int)hipGetLastError();
+}
+
+}  // extern "C"

@@ -36,6 +36,8 @@ KERNEL_SOURCES = ["paper_2502_18929_amd/csrc/qmc_persist.hip",
                   "paper_2502_18929_amd/csrc/qmc_device.hpp",
                   "paper_2502_18929_amd/csrc/qmc_persist.h",
                   "paper_2502_18929_amd/csrc/qmc_kernels.h",
+                  "paper_2502_18929_amd/csrc/qmc_small.hip",
+                  "paper_2502_18929_amd/csrc/qmc_small.h",
                   "paper_2502_18929_amd/csrc/qmc_host.cpp"]
 
 

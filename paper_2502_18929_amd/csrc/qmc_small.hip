@@ -67,6 +67,7 @@ struct SmallArgs {
   const int64_t* qshift;    // per-segment Q32 shifts
   uint32_t cap_store;       // keys per replica allowed (at most kSmallCap)
   uint64_t cap_spawn;       // records (children and death deltas) per replica and step allowed
+  uint32_t check_spawn;     // nonzero: cap_spawn can be reached, count each step's records
   unsigned long long* stop; // the chain's stop word (see above)
   uint32_t epoch;
   uint64_t* stats;          // [R][kSmallStats] of this batch
@@ -87,8 +88,10 @@ struct SmallShared {
   int2 pv[2][kSmallCap];
   unsigned long long dre[kSmallCap];   // int64 deltas (two's complement) of the parents
   unsigned long long dim[kSmallCap];
-  uint2 w[kSmallCap];                  // Philox words of the parents: x spawn, y death
-  uint32_t act[kSmallCap];             // parents whose death or spawn comb can fire
+  uint64_t ak[kSmallCap];              // parents whose death or spawn comb can fire: key,
+  int2 av[kSmallCap];                  // value, Philox words (x spawn, y death),
+  uint2 aw[kSmallCap];                 // index | comb flags
+  uint32_t ai[kSmallCap];
   uint64_t nk[kSmallNew];              // new records: composite key, value
   int2 nv[kSmallNew];
   uint64_t sk[kSmallNew];              // the same, sorted
@@ -96,21 +99,45 @@ struct SmallShared {
   uint4 tab[2][kSTab];
   uint32_t xsplit[kSBlock];
   uint32_t scan[kSWaves];
-  uint64_t red[kSWaves];
-  uint32_t nnew;
-  uint32_t nact;
-  uint32_t flag;                       // a limit was exceeded in this step
+  uint64_t red[3 * kSWaves];
+  // per step, by step parity (step k resets the words of step k + 1 after its first barrier,
+  // when every thread is done with those of step k - 1): new records, listed parents, records
+  // of the step (when the spawn capacity is checked), a limit exceeded
+  uint32_t nnew[2];
+  uint32_t nact[2];
+  uint32_t nrec[2];
+  uint32_t flag[2];
 };
+static_assert(kSTab == kSBlock, "one 16-byte word of a step table per thread");
 
-__device__ __forceinline__ void load_table(uint4* dst, const uint8_t* src) {
-  // a table area of kPersistTableBytes bytes (the device area has that much slack past its end),
-  // LDS-direct dword loads
-  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
-  uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
-  const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
-  constexpr uint32_t ndw = kPersistTableBytes / 4;
-  for (uint32_t c = wave; c * kWave < ndw; c += kSWaves)
-    __builtin_amdgcn_global_load_lds(s32 + c * kWave + lane, d32 + c * kWave, 4, 0, 0);
+// Lane exchanges inside rows of 16 lanes (DPP, gfx9 encodings); lanes with no source read 0.
+template <int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, Ctrl, RowMask, 0xF, false);
+}
+
+// Sum over aligned groups of T lanes (T a power of two <= 64, wave-uniform), in every lane of
+// the group; all lanes active.
+__device__ __forceinline__ uint32_t team_sum(uint32_t x, uint32_t T) {
+  if (T >= 2) x += dpp<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  if (T >= 4) x += dpp<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  if (T >= 8) x += dpp<0x141>(x);   // row_half_mirror: a lane of the other quad of its 8
+  if (T >= 16) x += dpp<0x140>(x);  // row_mirror: a lane of the other half of its row
+  if (T >= 32) x += (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);  // lane ^ 16
+  if (T >= 64) x += __shfl_xor(x, 32);
+  return x;
+}
+
+// Inclusive prefix sum over aligned groups of T lanes (lt = lane index in the group); all lanes
+// active.
+__device__ __forceinline__ uint32_t team_scan(uint32_t x, uint32_t T, uint32_t lt) {
+  if (T >= 2) { const uint32_t y = dpp<0x111>(x); if (lt >= 1) x += y; }  // row_shr 1
+  if (T >= 4) { const uint32_t y = dpp<0x112>(x); if (lt >= 2) x += y; }  // row_shr 2
+  if (T >= 8) { const uint32_t y = dpp<0x114>(x); if (lt >= 4) x += y; }  // row_shr 4
+  if (T >= 16) { const uint32_t y = dpp<0x118>(x); if (lt >= 8) x += y; } // row_shr 8
+  if (T >= 32) x += dpp<0x142, 0xA>(x);  // rows 1 and 3 add lane 15 of rows 0 and 2
+  if (T >= 64) x += dpp<0x143, 0xC>(x);  // rows 2 and 3 add lane 31
+  return x;
 }
 
 __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
@@ -149,10 +176,10 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
     }
     S.red[0] = a;
     S.red[1] = e;
-    S.flag = stop;
+    S.flag[0] = stop;
   }
   __syncthreads();
-  if (S.flag) return;
+  if (S.flag[0]) return;
   const uint64_t base = S.red[0];
   if (S.red[1] - base > (uint64_t)A.cap_store) {
     if (t == 0) chain_stop(A.stop, A.epoch, A.step0);
@@ -165,40 +192,59 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
     S.pk[0][i] = srck[base + i];
     S.pv[0][i] = srcv[base + i];
   }
-  if (A.nsteps > 0) load_table(S.tab[0], A.tab_base + A.tab_off[circ]);
-  uint64_t st_w = 0, st_k = 0, st_c = 0, st_d = 0, st_o = 0;  // thread 0
+  // Step tables go through registers: thread t loads the t-th 16 bytes of the next step's table
+  // (a table area of kPersistTableBytes bytes; the device area has that much slack past its end)
+  // at the start of a step and stores them to LDS at its end, so no LDS access of the step waits
+  // for the load.
+  auto table_word = [&](uint32_t kk) {
+    const uint4* src = reinterpret_cast<const uint4*>(
+        A.tab_base + A.tab_off[(size_t)kk * A.n_circuits + circ]);
+    return src[t];
+  };
+  if (A.nsteps > 0) S.tab[0][t] = table_word(0);
+  __syncthreads();  // every thread has read the start flag
+  if (t == 0) {
+    S.nnew[0] = 0;
+    S.nact[0] = 0;
+    S.nrec[0] = 0;
+    S.flag[0] = 0;
+  }
+  // statistics, per thread over the batch (walkers, death records, children); keys and outputs
+  // in thread 0
+  uint64_t st_w = 0, st_k = 0, st_o = 0;
+  uint32_t st_d = 0, st_c = 0;
   uint32_t b = 0;  // parent buffer
   uint32_t kdone = 0;
   for (uint32_t k = 0; k < A.nsteps; ++k) {
     const uint32_t s = A.step0 + k;
-    __builtin_amdgcn_s_waitcnt(0);  // the step table (and the parents on the first step)
+    const uint32_t p = k & 1;
+    __syncthreads();  // the parents, this step's table and counters
     if (t == 0) {
-      S.nnew = 0;
-      S.nact = 0;
-      S.flag = 0;
+      S.nnew[p ^ 1] = 0;
+      S.nact[p ^ 1] = 0;
+      S.nrec[p ^ 1] = 0;
+      S.flag[p ^ 1] = 0;
     }
-    __syncthreads();
-    // the next step's table, in flight during this step
-    if (k + 1 < A.nsteps)
-      load_table(S.tab[(k + 1) & 1], A.tab_base + A.tab_off[(size_t)(k + 1) * A.n_circuits + circ]);
+    const bool more = k + 1 < A.nsteps;
+    const uint4 tnext = more ? table_word(k + 1) : make_uint4(0, 0, 0, 0);
     const TableViewT<lptr> tv = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab[k & 1]));
     const uint32_t G = tv.h->n_groups;
     const uint64_t q_off = G > 1 ? tv.h->q_off : 0, q_diag = tv.h->q_diag + uabs64(qs);
     // 1: Philox, walker statistics, deltas cleared, list of the parents that can fire
-    uint64_t wsum = 0;
     for (uint32_t i0 = 0; i0 < n; i0 += kSBlock) {  // block-uniform
       const uint32_t i = i0 + t;
       bool dact = false, sact = false;
+      uint64_t ck = 0;
+      int2 v = make_int2(0, 0);
+      uint32_t r4[4] = {0, 0, 0, 0};
       if (i < n) {
-        const uint64_t ck = S.pk[b][i];
-        const int2 v = S.pv[b][i];
-        uint32_t r4[4];
+        ck = S.pk[b][i];
+        v = S.pv[b][i];
         walker_random(kl.key(ck), s, seg, A.seed, 0u, r4);
         const uint64_t sab = uabs64(v.x) + uabs64(v.y);
-        wsum += sab;
+        st_w += sab;
         dact = !comb_all_zero(sab, q_diag, r4[1]);
         sact = !comb_all_zero(sab, q_off, r4[0]);
-        S.w[i] = make_uint2(r4[0], r4[1]);
         S.dre[i] = 0;
         S.dim[i] = 0;
       }
@@ -206,40 +252,42 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
       const uint64_t m = __ballot(act);
       if (m) {  // wave-uniform
         uint32_t at = 0;
-        if (lane == 0) at = atomicAdd(&S.nact, (uint32_t)__popcll(m));
+        if (lane == 0) at = atomicAdd(&S.nact[p], (uint32_t)__popcll(m));
         at = __shfl(at, 0);
-        if (act)
-          S.act[at + (uint32_t)__popcll(m & lanemask_lt())] =
-              i | (dact ? kActD : 0u) | (sact ? kActS : 0u);
+        if (act) {
+          const uint32_t j = at + (uint32_t)__popcll(m & lanemask_lt());
+          S.ak[j] = ck;
+          S.av[j] = v;
+          S.aw[j] = make_uint2(r4[0], r4[1]);
+          S.ai[j] = i | (dact ? kActD : 0u) | (sact ? kActS : 0u);
+        }
       }
     }
     __syncthreads();
     // 2: death deltas and children, a team of T lanes per listed parent
-    const uint32_t nact = S.nact;
+    const uint32_t nact = S.nact[p];
     uint32_t T = 1;
     while (T < (uint32_t)kWave && 2 * T * nact <= (uint32_t)kSBlock) T *= 2;
     const uint32_t lt = t & (T - 1), nteam = kSBlock / T, team = t / T;
     const uint32_t nd = tv.gs[1] / kTermPad;
     const uint32_t d0 = nd * lt / T * kTermPad, d1 = nd * (lt + 1) / T * kTermPad;
     const uint32_t g0 = 1 + (G - 1) * lt / T, g1 = 1 + (G - 1) * (lt + 1) / T;
-    uint32_t ndeath = 0, nchild = 0;
+    uint32_t nrec = 0;  // records of this thread in this step
     for (uint32_t a0 = 0; a0 < nact; a0 += nteam) {  // block-uniform
       const uint32_t ai = a0 + team;
       const bool has = ai < nact;  // team-uniform
-      const uint32_t e = has ? S.act[ai] : 0u;
+      const uint32_t e = has ? S.ai[ai] : 0u;
       const uint32_t i = e & kActIdx;
       const bool dact = (e & kActD) != 0, sact = (e & kActS) != 0;
-      const uint64_t ck = has ? S.pk[b][i] : 0;
-      const int2 v = has ? S.pv[b][i] : make_int2(0, 0);
-      const uint2 w = has ? S.w[i] : make_uint2(0, 0);
+      const uint64_t ck = has ? S.ak[ai] : 0;
+      const int2 v = has ? S.av[ai] : make_int2(0, 0);
+      const uint2 w = has ? S.aw[ai] : make_uint2(0, 0);
       const uint64_t key = kl.key(ck);
       // death: partial diagonal coefficients over the team's slices of the group 0 terms
       int32_t pre = 0, pim = 0;
       if (dact) group_coeff_part(tv.t, d0, d1, key, pre, pim);
-      for (uint32_t o = 1; o < T; o <<= 1) {
-        pre += __shfl_xor(pre, (int)o);
-        pim += __shfl_xor(pim, (int)o);
-      }
+      pre = (int32_t)team_sum((uint32_t)pre, T);
+      pim = (int32_t)team_sum((uint32_t)pim, T);
       if (dact && lt == 0) {
         int64_t xre, xim;
         cmul_q32(v.x, v.y, pre + (int32_t)qs, pim, xre, xim);
@@ -248,10 +296,13 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
         if ((dx | dy) != 0) {
           atomicAdd(&S.dre[i], (unsigned long long)dx);
           atomicAdd(&S.dim[i], (unsigned long long)dy);
-          ++ndeath;
+          ++st_d;
+          ++nrec;
         }
       }
-      // spawn: the comb of lane lt starts after the amounts of the team's earlier lanes
+      // spawn: the comb of lane lt starts after the amounts of the team's earlier lanes; the
+      // lane's first group keeps its amounts from the first pass
+      int64_t x0re = 0, x0im = 0;
       uint32_t amt = 0;
       if (sact && T > 1) {
         for (uint32_t g = g0; g < g1; ++g) {
@@ -259,25 +310,31 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
           group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
           int64_t xre, xim;
           cmul_q32(v.x, v.y, cre, cim, xre, xim);
+          if (g == g0) {
+            x0re = xre;
+            x0im = xim;
+          }
           amt += (uint32_t)uabs64(xre) + (uint32_t)uabs64(xim);
         }
       }
-      uint32_t incl = amt;
-      for (uint32_t o = 1; o < T; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if (lt >= o) incl += y;
-      }
+      const uint32_t incl = team_scan(amt, T, lt);
       if (sact) {
         const bool initiator = uabs64(v.x) + uabs64(v.y) >= kl.init_min;
         uint64_t r = (uint32_t)(w.x + (incl - amt));
         for (uint32_t g = g0; g < g1; ++g) {
-          int32_t cre, cim;
-          group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
           int64_t xre, xim;
-          cmul_q32(v.x, v.y, cre, cim, xre, xim);
+          if (g == g0 && T > 1) {
+            xre = x0re;
+            xim = x0im;
+          } else {
+            int32_t cre, cim;
+            group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+            cmul_q32(v.x, v.y, cre, cim, xre, xim);
+          }
           const int64_t nre = comb_step(r, xre), nim = comb_step(r, xim);
           if ((nre | nim) == 0) continue;
-          ++nchild;
+          ++st_c;
+          ++nrec;
           const uint64_t tk = ck ^ tv.gx[g];
           uint32_t lo = 0, hi = n;
           while (lo < hi) {
@@ -288,42 +345,25 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
             atomicAdd(&S.dre[lo], (unsigned long long)nre);
             atomicAdd(&S.dim[lo], (unsigned long long)nim);
           } else if (initiator) {
-            const uint32_t at = atomicAdd(&S.nnew, 1u);
+            const uint32_t at = atomicAdd(&S.nnew[p], 1u);
             if (at < (uint32_t)kSmallNew) {
               S.nk[at] = tk;
               S.nv[at] = make_int2((int32_t)nre, (int32_t)nim);
             } else {
-              S.flag = 1;
+              S.flag[p] = 1;
             }
           }
         }
       }
     }
-    // statistics of the step (block reductions)
-    for (int o = 32; o > 0; o >>= 1) {
-      wsum += __shfl_xor(wsum, o);
-      ndeath += __shfl_xor(ndeath, o);
-      nchild += __shfl_xor(nchild, o);
+    if (A.check_spawn) {  // records of the step against the spawn capacity
+      const uint32_t wr = team_sum(nrec, kWave);
+      if (lane == 0 && wr) atomicAdd(&S.nrec[p], wr);
     }
-    if (lane == 0) {
-      S.red[wave] = wsum;
-      S.xsplit[wave] = ndeath;
-      S.xsplit[kSWaves + wave] = nchild;
-    }
+    if (t == 0) st_k += n;
     __syncthreads();
-    if (t == 0) {
-      for (int x = 0; x < kSWaves; ++x) {
-        st_w += S.red[x];
-        st_d += S.xsplit[x];
-        st_c += S.xsplit[kSWaves + x] + S.xsplit[x];
-      }
-      st_k += n;
-    }
-    const uint32_t nn = S.nnew < (uint32_t)kSmallNew ? S.nnew : (uint32_t)kSmallNew;
-    uint64_t nrec = 0;
-    for (int x = 0; x < kSWaves; ++x) nrec += S.xsplit[x] + S.xsplit[kSWaves + x];
-    if (S.flag || nrec > A.cap_spawn) break;  // block-uniform: the step does not fit
-    __syncthreads();
+    const uint32_t nn = S.nnew[p] < (uint32_t)kSmallNew ? S.nnew[p] : (uint32_t)kSmallNew;
+    if (S.flag[p] || S.nrec[p] > A.cap_spawn) break;  // block-uniform: the step does not fit
     // 3a: the new records in key order (rank = smaller keys, then equal keys of smaller index)
     for (uint32_t i = t; i < nn; i += kSBlock) {
       const uint64_t ki = S.nk[i];
@@ -385,12 +425,8 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
       if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) over = true;
       count += (re != 0 || im != 0) ? 1u : 0u;
     });
-    uint32_t incl = count;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t x = __shfl_up(incl, o);
-      if (lane >= (uint32_t)o) incl += x;
-    }
-    if (over) S.flag = 2;
+    const uint32_t incl = team_scan(count, kWave, lane);
+    if (over) S.flag[p] = 2;
     if (lane == kWave - 1) S.scan[wave] = incl;
     __syncthreads();
     uint32_t wpre = 0, agg = 0;
@@ -398,7 +434,7 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
       wpre += x < wave ? S.scan[x] : 0u;
       agg += S.scan[x];
     }
-    if (S.flag || agg > A.cap_store) break;  // block-uniform
+    if (S.flag[p] || agg > A.cap_store) break;  // block-uniform
     uint32_t o = wpre + incl - count;
     walk([&](uint64_t key, int64_t re, int64_t im) __attribute__((always_inline)) {
       if (re != 0 || im != 0) {
@@ -407,33 +443,51 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
         ++o;
       }
     });
+    if (more) S.tab[(k + 1) & 1][t] = tnext;
     if (t == 0) st_o += agg;
     n = agg;
     b ^= 1;
     kdone = k + 1;
-    __syncthreads();
   }
-  __builtin_amdgcn_s_waitcnt(0);
   if (kdone < A.nsteps) {
     // this replica could not take step step0 + kdone (more keys or new records than the LDS
-    // holds, or a population outside int32)
+    // holds, a population outside int32, or more records than the spawn capacity)
     if (t == 0) chain_stop(A.stop, A.epoch, A.step0 + kdone);
     return;
   }
+  __syncthreads();  // the last step's outputs
   uint64_t* ok = A.ok + (uint64_t)seg * A.segcap;
   int2* ov = A.ov + (uint64_t)seg * A.segcap;
   for (uint32_t i = t; i < n; i += kSBlock) {
     ok[i] = S.pk[b][i];
     ov[i] = S.pv[b][i];
   }
+  // the batch's statistics: block sums of the per-thread ones
+  for (int o = 32; o > 0; o >>= 1) {
+    st_w += __shfl_xor(st_w, o);
+    st_d += __shfl_xor(st_d, o);
+    st_c += __shfl_xor(st_c, o);
+  }
+  if (lane == 0) {
+    S.red[wave] = st_w;
+    S.red[kSWaves + wave] = st_d;
+    S.red[2 * kSWaves + wave] = st_c;
+  }
+  __syncthreads();
   if (t == 0) {
+    uint64_t w = 0, dd = 0, cc = 0;
+    for (int x = 0; x < kSWaves; ++x) {
+      w += S.red[x];
+      dd += S.red[kSWaves + x];
+      cc += S.red[2 * kSWaves + x];
+    }
     A.out_n[seg] = n;
     uint64_t* st = A.stats + (uint64_t)seg * kSmallStats;
-    st[0] = st_w;
+    st[0] = w;
     st[1] = st_k;
-    st[2] = st_c;
+    st[2] = cc + dd;
     st[3] = st_o;
-    st[4] = st_d;
+    st[4] = dd;
   }
 }
 
@@ -518,6 +572,8 @@ int qmcs_launch(hipStream_t st, const SmallLaunch* L) {
   a.qshift = L->qshift;
   a.cap_store = (uint32_t)(L->cap_store < (uint64_t)kSmallCap ? L->cap_store : kSmallCap);
   a.cap_spawn = L->cap_spawn;
+  // a step has at most (keys) x (groups) records: no count needed below that
+  a.check_spawn = L->cap_spawn < (uint64_t)a.cap_store * (uint64_t)(kMaxGroups + 1);
   a.stop = L->stop;
   a.epoch = L->epoch;
   a.stats = L->stats;

@@ -670,6 +670,7 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->pinned, c->at<uint8_t>(c->L.tab), kWarmCopy, hipMemcpyDeviceToHost,
                        c->stream);
+  if (e == hipSuccess) e = (hipError_t)qmcp_warm(c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     qmc_destroy(c);

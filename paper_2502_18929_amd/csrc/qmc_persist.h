@@ -54,6 +54,8 @@ int qmcp_max_segments(int* P);
 int qmcp_prepare(hipStream_t st, const PersistLaunch* L);
 // The cooperative launch of the persistent step kernel (after qmcp_prepare).
 int qmcp_launch(hipStream_t st, const PersistLaunch* L);
+// One empty cooperative launch (the runtime's one-time set-up of cooperative launches).
+int qmcp_warm(hipStream_t st);
 // Segment buffer `buf` (N(step0 + j) after j steps is in buffer j mod nbuf) -> the sorted store
 // (out_k, out_v) with its record count written to *out_count (device pointers).
 int qmcp_gather(hipStream_t st, const PersistLaunch* L, uint32_t buf, uint64_t* out_k,

@@ -85,6 +85,10 @@ def lib():
         L.orc_set_proposal.argtypes = [ctypes.c_void_p, u32, u32, i8p, P(ctypes.c_int32), i8p,
                                        P(ctypes.c_int32), u32]
         L.orc_mlp_scores.argtypes = [ctypes.c_void_p, u64, P(ctypes.c_int32)]
+        L.orc_set_proposal_deep.argtypes = [ctypes.c_void_p, u32, i8p, P(ctypes.c_int32), i8p,
+                                            P(ctypes.c_int32), i8p, P(ctypes.c_int32), u32, u32]
+        L.orc_deep_scores.argtypes = [ctypes.c_void_p, u64, P(u64), P(ctypes.c_int32)]
+        L.orc_step_active.argtypes = [ctypes.c_void_p, P(dbl), P(dbl), P(u64)]
         L.orc_proposal_thresholds.argtypes = [u32, P(u64), P(u64)]
         L.orc_proposal_draw.argtypes = [u32, P(i64), P(u64), u32, u32, u32, P(u32), P(i64)]
         L.orc_counters.argtypes = [ctypes.c_void_p, P(u64), P(u64), P(u64), P(u64)]
@@ -107,6 +111,7 @@ def lib():
 
 
 MLP_IN, MLP_HIDDEN, MLP_OUT = 64, 32, 64
+DEEP_IN, DEEP_HIDDEN, DEEP_OUT = 128, 128, 64
 
 
 def proposal_thresholds(W):
@@ -322,6 +327,42 @@ class Oracle:
             args = [_p(self._mlp[0], ctypes.c_int8), _p(self._mlp[1], ctypes.c_int32),
                     _p(self._mlp[2], ctypes.c_int8), _p(self._mlp[3], ctypes.c_int32), int(s1)]
         _check(lib().orc_set_proposal(self._ctx, kd, int(k) if kd else 0, *args), "set_proposal")
+
+    def set_proposal_deep(self, k, net):
+        """Proposal kind 4 (reading R21) with k samples per parent; net = (w1 int8 [128, 128],
+        b1 int32 [128], w2 int8 [128, 128], b2 int32 [128], w3 int8 [64, 128], b3 int32 [64],
+        s1, s2)."""
+        w1, b1, w2, b2, w3, b3, s1, s2 = net
+        arr = [np.ascontiguousarray(w1, dtype=np.int8), np.ascontiguousarray(b1, dtype=np.int32),
+               np.ascontiguousarray(w2, dtype=np.int8), np.ascontiguousarray(b2, dtype=np.int32),
+               np.ascontiguousarray(w3, dtype=np.int8), np.ascontiguousarray(b3, dtype=np.int32)]
+        assert arr[0].shape == (DEEP_HIDDEN, DEEP_IN) and arr[2].shape == (DEEP_HIDDEN, DEEP_HIDDEN)
+        assert arr[4].shape == (DEEP_OUT, DEEP_HIDDEN)
+        self._deep = arr
+        ct = [ctypes.c_int8, ctypes.c_int32] * 3
+        _check(lib().orc_set_proposal_deep(self._ctx, int(k),
+                                           *[_p(a, t) for a, t in zip(arr, ct)], int(s1), int(s2)),
+               "set_proposal_deep")
+
+    def deep_scores(self, key, active):
+        """Kind 4 scores of one key with the weight-channel indicator bits `active` (an int < 2^128:
+        bit m set where channel m is nonzero)."""
+        act = np.array([active & ((1 << 64) - 1), active >> 64], dtype=np.uint64)
+        out = np.zeros(DEEP_OUT, dtype=np.int32)
+        _check(lib().orc_deep_scores(self._ctx, int(key), _p(act, ctypes.c_uint64),
+                                     _p(out, ctypes.c_int32)), "deep_scores")
+        return out
+
+    def step_active(self, s, gamma):
+        """The step's weight-channel indicator bits (an int < 2^128) for weight rows s, gamma."""
+        s = np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(-1) if self.n_h
+                                 else np.zeros(1))
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(-1) if self.n_l
+                                 else np.zeros(1))
+        out = np.zeros(2, dtype=np.uint64)
+        _check(lib().orc_step_active(self._ctx, _p(s, ctypes.c_double), _p(g, ctypes.c_double),
+                                     _p(out, ctypes.c_uint64)), "step_active")
+        return int(out[0]) | (int(out[1]) << 64)
 
     def mlp_scores(self, key):
         out = np.zeros(MLP_OUT, dtype=np.int32)

@@ -43,6 +43,13 @@
  *      the sum of the off-diagonal |q| of the table, so W < 2^24: the paper's |L|-proportional
  *      choice for this parent) or the scores of a small int8 MLP of the key bits (one score per group, both
  *      components).  Death keeps its comb.  Euler only, no initiator; 0 = the plain comb.
+ *  R21 The learned proposal's inputs (2n key bits plus a one-hot over the model's terms, the
+ *      learned-proposal configuration): weight W of both components of group g is
+ *      min(2^24, max(0, score_{g-1})) of a network with inputs +1 / -1 for the 2n key bits,
+ *      then 1 / 0 for every weight channel of the step (H monomials, then Lindblad operators)
+ *      that is nonzero / zero -- on a gate circuit the one gate whose window holds the step over
+ *      a constant background of noise channels -- two hidden layers of 128 units,
+ *      h = min(127, max(0, b + w . x) >> s), and 64 group scores b3 + w3 . h2 (kind 4).
  *
  * Floating point: the only FP64 arithmetic is the coefficient quantization, done in a fixed
  * operation order (compile with -ffp-contract=off).  Everything the walkers touch is integer.
@@ -162,6 +169,14 @@ struct orc_ctx {
   int8_t mlp_w2[ORC_MLP_OUT][ORC_MLP_HIDDEN];
   int32_t mlp_b2[ORC_MLP_OUT];
   uint32_t mlp_s1;
+  /* the deeper network (kind 4, reading R21) */
+  int8_t deep_w1[ORC_DEEP_HIDDEN][ORC_DEEP_IN];
+  int32_t deep_b1[ORC_DEEP_HIDDEN];
+  int8_t deep_w2[ORC_DEEP_HIDDEN][ORC_DEEP_HIDDEN];
+  int32_t deep_b2[ORC_DEEP_HIDDEN];
+  int8_t deep_w3[ORC_DEEP_OUT][ORC_DEEP_HIDDEN];
+  int32_t deep_b3[ORC_DEEP_OUT];
+  uint32_t deep_s1, deep_s2;
 };
 
 /* Liouvillian source terms from eqs. (1)-(2) with reading R1.  Each term acts on a basis element
@@ -329,6 +344,8 @@ typedef struct {
   uint32_t* gs;        /* [n_groups + 1] */
   uint32_t n_terms;
   qterm_t* t;          /* [n_terms], grouped */
+  uint64_t active[2];  /* bit m: weight channel m of the step is nonzero (H monomials, then
+                          Lindblad operators; channels past 127 not kept) */
 } table_t;
 
 static int cmp_qterm(const void* a, const void* b) {
@@ -359,6 +376,10 @@ static int q32(double dt, double w, double k, double scale, int64_t* out) {
 static int build_table(const orc_ctx* c, const double* s, const double* gamma, double scale,
                        table_t* T) {
   memset(T, 0, sizeof(*T));
+  for (uint32_t m = 0; m < c->n_h + c->n_l && m < 128; ++m) {
+    const double w = m < c->n_h ? s[m] : gamma[m - c->n_h];
+    if (w != 0.0) T->active[m >> 6] |= 1ull << (m & 63);
+  }
   qterm_t* q = (qterm_t*)malloc((c->n_terms ? c->n_terms : 1) * sizeof(qterm_t));
   if (!q) return ORC_ERR_NOMEM;
   for (uint32_t i = 0; i < c->n_terms; ++i) {
@@ -590,6 +611,57 @@ int orc_mlp_scores(const orc_ctx* c, uint64_t key, int32_t* score) {
   return ORC_OK;
 }
 
+/* The deeper network (reading R21): input in_b = +1 / -1 where key bit b is set / clear for
+ * b < 2n, in_{2n+m} = 1 where weight channel m of the step is nonzero and 0 where it is zero, 0
+ * past; h1_j = min(127, max(0, b1_j + sum_i w1[j][i] in_i) >> s1), h2_j the same from h1 with
+ * w2, b2, s2; score_g = b3_g + sum_j w3[g][j] h2_j (int32, exact: |sums| < 2^31). */
+static void deep_scores(const orc_ctx* c, uint64_t key, const uint64_t* active, int32_t* score) {
+  int32_t in[ORC_DEEP_IN], h1[ORC_DEEP_HIDDEN], h2[ORC_DEEP_HIDDEN];
+  const uint32_t nb = 2 * c->n < ORC_DEEP_IN ? 2 * c->n : ORC_DEEP_IN;
+  for (uint32_t i = 0; i < ORC_DEEP_IN; ++i) {
+    if (i < nb) {
+      in[i] = ((key >> i) & 1u) ? 1 : -1;
+    } else {
+      const uint32_t m = i - nb;
+      in[i] = (active[m >> 6] >> (m & 63)) & 1u ? 1 : 0;
+    }
+  }
+  for (int j = 0; j < ORC_DEEP_HIDDEN; ++j) {
+    int32_t a = c->deep_b1[j];
+    for (int i = 0; i < ORC_DEEP_IN; ++i) a += (int32_t)c->deep_w1[j][i] * in[i];
+    const int32_t v = a > 0 ? (a >> c->deep_s1) : 0;
+    h1[j] = v > 127 ? 127 : v;
+  }
+  for (int j = 0; j < ORC_DEEP_HIDDEN; ++j) {
+    int32_t a = c->deep_b2[j];
+    for (int i = 0; i < ORC_DEEP_HIDDEN; ++i) a += (int32_t)c->deep_w2[j][i] * h1[i];
+    const int32_t v = a > 0 ? (a >> c->deep_s2) : 0;
+    h2[j] = v > 127 ? 127 : v;
+  }
+  for (int g = 0; g < ORC_DEEP_OUT; ++g) {
+    int32_t o = c->deep_b3[g];
+    for (int j = 0; j < ORC_DEEP_HIDDEN; ++j) o += (int32_t)c->deep_w3[g][j] * h2[j];
+    score[g] = o;
+  }
+}
+
+int orc_step_active(const orc_ctx* c, const double* s, const double* gamma, uint64_t* active) {
+  if (!c || !active) return ORC_ERR_ARG;
+  table_t T;
+  const int rc = build_table(c, s, gamma, 1.0, &T);
+  if (rc) return rc;
+  active[0] = T.active[0];
+  active[1] = T.active[1];
+  table_free(&T);
+  return ORC_OK;
+}
+
+int orc_deep_scores(const orc_ctx* c, uint64_t key, const uint64_t* active, int32_t* score) {
+  if (!c || !active || !score) return ORC_ERR_ARG;
+  deep_scores(c, key, active, score);
+  return ORC_OK;
+}
+
 /* Thresholds P[0..nch) (sum exactly 2^32, each >= 1) from weights W (each < 2^32). */
 int orc_proposal_thresholds(uint32_t nch, const uint64_t* W, uint64_t* P) {
   if (nch == 0 || nch > 2 * 255 || !W || !P) return ORC_ERR_ARG;
@@ -645,10 +717,15 @@ static int proposal_records(const orc_ctx* c, uint32_t r, const table_t* T, uint
     for (uint32_t i = 0; i < nch; ++i)
       W[i] = (xs[i] < 0 ? (uint64_t)(-xs[i]) : (uint64_t)xs[i]) >> sh;
   } else {
-    int32_t score[ORC_MLP_OUT];
-    mlp_scores(c, key, score);
+    /* kinds 3 and 4: both components of group g weigh min(2^24, max(0, score_{g-1})) */
+    int32_t score[ORC_MLP_OUT > ORC_DEEP_OUT ? ORC_MLP_OUT : ORC_DEEP_OUT];
+    if (c->prop_kind == 3)
+      mlp_scores(c, key, score);
+    else
+      deep_scores(c, key, T->active, score);
+    const uint32_t nout = c->prop_kind == 3 ? ORC_MLP_OUT : ORC_DEEP_OUT;
     for (uint32_t g = 1; g < G; ++g) {
-      const int32_t v = g - 1 < ORC_MLP_OUT ? score[g - 1] : 0;
+      const int32_t v = g - 1 < nout ? score[g - 1] : 0;
       const uint64_t w = v <= 0 ? 0 : (v > (1 << 24) ? (1u << 24) : (uint64_t)v);
       W[2 * (g - 1)] = W[2 * (g - 1) + 1] = w;
     }
@@ -1058,6 +1135,24 @@ int orc_set_proposal(orc_ctx* c, uint32_t kind, uint32_t k, const int8_t* w1, co
     memcpy(c->mlp_b2, b2, sizeof(c->mlp_b2));
     c->mlp_s1 = s1;
   }
+  return ORC_OK;
+}
+
+int orc_set_proposal_deep(orc_ctx* c, uint32_t k, const int8_t* w1, const int32_t* b1,
+                          const int8_t* w2, const int32_t* b2, const int8_t* w3,
+                          const int32_t* b3, uint32_t s1, uint32_t s2) {
+  if (k == 0 || k > 64 || (k & (k - 1)) || c->ab2 || c->init_min) return ORC_ERR_ARG;
+  if (!w1 || !b1 || !w2 || !b2 || !w3 || !b3 || s1 > 30 || s2 > 30) return ORC_ERR_ARG;
+  c->prop_kind = 4;
+  c->prop_k = k;
+  memcpy(c->deep_w1, w1, sizeof(c->deep_w1));
+  memcpy(c->deep_b1, b1, sizeof(c->deep_b1));
+  memcpy(c->deep_w2, w2, sizeof(c->deep_w2));
+  memcpy(c->deep_b2, b2, sizeof(c->deep_b2));
+  memcpy(c->deep_w3, w3, sizeof(c->deep_w3));
+  memcpy(c->deep_b3, b3, sizeof(c->deep_b3));
+  c->deep_s1 = s1;
+  c->deep_s2 = s2;
   return ORC_OK;
 }
 

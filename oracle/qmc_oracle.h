@@ -34,6 +34,11 @@ typedef struct orc_ctx orc_ctx;
 #define ORC_MLP_IN 64
 #define ORC_MLP_HIDDEN 32
 #define ORC_MLP_OUT 64
+/* The deeper proposal network (reading R21): inputs (2n key bits, then one per weight channel of
+ * the model), two hidden layers, group scores. */
+#define ORC_DEEP_IN 128
+#define ORC_DEEP_HIDDEN 128
+#define ORC_DEEP_OUT 64
 
 enum {
   ORC_OK = 0,
@@ -124,6 +129,19 @@ int orc_set_proposal(orc_ctx* c, uint32_t kind, uint32_t k, const int8_t* w1, co
                      const int8_t* w2, const int32_t* b2, uint32_t s1);
 /* The MLP scores of groups 1..ORC_MLP_OUT for one key (the context's weights). */
 int orc_mlp_scores(const orc_ctx* c, uint64_t key, int32_t* score);
+/* Proposal kind 4 (reading R21): the deeper network, k samples per parent; int8 weights
+ * w1[ORC_DEEP_HIDDEN][ORC_DEEP_IN], w2[ORC_DEEP_HIDDEN][ORC_DEEP_HIDDEN],
+ * w3[ORC_DEEP_OUT][ORC_DEEP_HIDDEN], int32 biases b1, b2 [ORC_DEEP_HIDDEN], b3 [ORC_DEEP_OUT], hidden
+ * shifts s1, s2 (copied).  Euler without initiators only. */
+int orc_set_proposal_deep(orc_ctx* c, uint32_t k, const int8_t* w1, const int32_t* b1,
+                          const int8_t* w2, const int32_t* b2, const int8_t* w3,
+                          const int32_t* b3, uint32_t s1, uint32_t s2);
+/* Its scores of groups 1..ORC_DEEP_OUT for one key, with the weight-channel indicators of a step
+ * given as the bits of active[0..1] (bit m of the 128-bit mask: channel m nonzero). */
+int orc_deep_scores(const orc_ctx* c, uint64_t key, const uint64_t* active, int32_t* score);
+/* The weight-channel indicators of the step with weights s, gamma (the network input past the key
+ * bits): bit m of active[0..1] set where channel m is nonzero. */
+int orc_step_active(const orc_ctx* c, const double* s, const double* gamma, uint64_t* active);
 /* Proposal thresholds (sum 2^32, each >= 1) from nch weights, and one draw from them. */
 int orc_proposal_thresholds(uint32_t nch, const uint64_t* W, uint64_t* P);
 int orc_proposal_draw(uint32_t nch, const int64_t* x, const uint64_t* P, uint32_t K, uint32_t u,

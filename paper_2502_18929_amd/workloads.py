@@ -371,6 +371,19 @@ def random_mlp(rng, hidden_shift=5, scale=40):
     return w1, b1, w2, b2, int(hidden_shift)
 
 
+def random_deep_mlp(rng, s1=6, s2=9, scale=40):
+    """Seeded weights of the deeper spawn-proposal network (shapes of the C ABI: w1 int8 [128, 128],
+    b1 int32 [128], w2 int8 [128, 128], b2 int32 [128], w3 int8 [64, 128], b3 int32 [64], hidden
+    shifts s1, s2): random inputs, not trained ones."""
+    w1 = rng.integers(-scale, scale + 1, size=(128, 128)).astype(np.int8)
+    b1 = rng.integers(-200, 800, size=128).astype(np.int32)
+    w2 = rng.integers(-scale, scale + 1, size=(128, 128)).astype(np.int8)
+    b2 = rng.integers(-500, 3000, size=128).astype(np.int32)
+    w3 = rng.integers(-scale, scale + 1, size=(64, 128)).astype(np.int8)
+    b3 = rng.integers(-2000, 6000, size=64).astype(np.int32)
+    return w1, b1, w2, b2, w3, b3, int(s1), int(s2)
+
+
 def random_records(n, rng, count, scale=50):
     """Sorted unique keys over 2n bits with nonzero Gaussian-integer populations."""
     K = 1 << (2 * n)

@@ -5,7 +5,10 @@ What fixes them independently of the oracle: the partition property of the thres
 channel lookup as numpy's searchsorted, the exact conditional expectation of the rounding by
 enumerating every (offset, sub-draw) pair of small channel intervals, the MLP as numpy integer
 matrix products, the diagonal-only special case (no channel, so the plain step), and the
-unbiasedness identity E[N(s+1)] = (I + dt L_q) N(s) as a z-test over many replicas.
+unbiasedness identity E[N(s+1)] = (I + dt L_q) N(s) as a z-test over many replicas.  The deeper
+network (reading R21) also by closed forms: identity layers that pass key bits and active
+channels through to known scores, saturated and shifted hidden layers, and the active channels
+as the nonzero weights of the step.
 """
 import math
 from fractions import Fraction
@@ -114,6 +117,111 @@ def test_mlp_scores_are_the_integer_network(orc, n):
         assert np.array_equal(o.mlp_scores(key), want)
 
 
+# ---- the deeper network (kind 4, reading R21) -------------------------------------------------
+
+def _deep_input(key, active, n):
+    """Network input: +1 / -1 for the 2n key bits, then 1 / 0 for the weight channels."""
+    nb = min(2 * n, 128)
+    x = np.zeros(128, dtype=np.int64)
+    for i in range(128):
+        x[i] = (1 if (key >> i) & 1 else -1) if i < nb else (active >> (i - nb)) & 1
+    return x
+
+
+@pytest.mark.parametrize("n", [1, 5, 20, 32])
+def test_deep_scores_are_the_integer_network(orc, n):
+    rng = np.random.default_rng(960 + n)
+    keys, re, im = W.random_records(min(n, 3), rng, 3)
+    o = orc.Oracle(n, 1, 1, 0.01, [], [], keys, re, im)
+    net = W.random_deep_mlp(rng)
+    w1, b1, w2, b2, w3, b3, s1, s2 = net
+    o.set_proposal_deep(2, net)
+    for _ in range(12):
+        key = int(rng.integers(0, 1 << min(2 * n, 63)))
+        active = int(rng.integers(0, 1 << 62)) | (int(rng.integers(0, 1 << 62)) << 64)
+        x = _deep_input(key, active, n)
+        a1 = w1.astype(np.int64) @ x + b1
+        h1 = np.minimum(np.where(a1 > 0, a1, 0) >> s1, 127)
+        a2 = w2.astype(np.int64) @ h1 + b2
+        h2 = np.minimum(np.where(a2 > 0, a2, 0) >> s2, 127)
+        assert np.array_equal(o.deep_scores(key, active), w3.astype(np.int64) @ h2 + b3)
+
+
+def test_deep_identity_network_reads_key_bits_then_channels(orc):
+    """Identity layers with no shift: unit j passes max(0, input j) on, so score g is 1 where key
+    bit g is set (g < 2n), or where channel g - 2n is active, plus its bias."""
+    n = 3
+    keys, re, im = W.random_records(n, np.random.default_rng(1), 2)
+    o = orc.Oracle(n, 1, 1, 0.01, [], [], keys, re, im)
+    eye = np.eye(128, dtype=np.int8)
+    w3 = np.zeros((64, 128), dtype=np.int8)
+    w3[np.arange(64), np.arange(64)] = 1
+    b3 = (1000 + np.arange(64)).astype(np.int32)
+    o.set_proposal_deep(1, (eye, np.zeros(128, np.int32), eye, np.zeros(128, np.int32), w3, b3,
+                            0, 0))
+    for key, active in [(0, 0), (0b101101, 0), (0, 0b1011), (0b111111, (1 << 57) | 1),
+                        (0b010010, (1 << 64) - 1)]:
+        want = [1000 + g + (((key >> g) & 1) if g < 6 else ((active >> (g - 6)) & 1))
+                for g in range(64)]
+        assert o.deep_scores(key, active).tolist() == want
+
+
+def test_deep_hidden_layers_clamp_and_shift(orc):
+    """Closed forms: all-127 first-layer weights saturate every hidden unit at 127; all-one second
+    weights with shift 7 give (128 x 127) >> 7 = 127; all-one output weights then 128 x 127.  A
+    bias-only first layer is shifted (5 >> 1 = 2) and a negative second-layer bias is cut to 0."""
+    n = 20
+    keys, re, im = W.random_records(3, np.random.default_rng(2), 2)
+    o = orc.Oracle(n, 1, 1, 0.01, [], [], keys, re, im)
+    full = np.full((128, 128), 127, np.int8)
+    ones = np.ones((128, 128), np.int8)
+    b3 = np.arange(64, dtype=np.int32) - 7
+    o.set_proposal_deep(1, (full, np.zeros(128, np.int32), ones, np.zeros(128, np.int32),
+                            np.ones((64, 128), np.int8), b3, 0, 7))
+    key = (1 << 40) - 1
+    assert o.deep_scores(key, (1 << 88) - 1).tolist() == (128 * 127 + b3).tolist()
+    zero = np.zeros((128, 128), np.int8)
+    o.set_proposal_deep(1, (zero, np.full(128, 5, np.int32), ones, np.full(128, -1000, np.int32),
+                            np.ones((64, 128), np.int8), b3, 1, 0))
+    assert o.deep_scores(12345, 77).tolist() == b3.tolist()
+    o.set_proposal_deep(1, (zero, np.full(128, 5, np.int32), ones, np.zeros(128, np.int32),
+                            np.ones((64, 128), np.int8), b3, 1, 3))
+    # h1 = 5 >> 1 = 2 everywhere, h2 = (128 x 2) >> 3 = 32, score = 128 x 32 + b3
+    assert o.deep_scores(0, 0).tolist() == (128 * 32 + b3).tolist()
+
+
+def test_deep_channels_are_the_nonzero_weights_of_the_step(orc):
+    rng = np.random.default_rng(970)
+    n = 3
+    h, lops = W.random_model(n, rng, n_h=5, n_l=3)
+    keys, re, im = W.random_records(n, rng, 3)
+    o = orc.Oracle(n, 1, 1, 0.01, h, lops, keys, re, im)
+    for _ in range(6):
+        s = np.where(rng.random(5) < 0.5, 0.0, rng.normal(size=5))
+        g = np.where(rng.random(3) < 0.5, 0.0, np.abs(rng.normal(size=3)))
+        want = sum(1 << m for m, w in enumerate(list(s) + list(g)) if w != 0.0)
+        assert o.step_active(s, g) == want
+
+
+def test_deep_refuses_bad_settings(orc):
+    rng = np.random.default_rng(971)
+    h, lops = W.random_model(2, rng)
+    keys, re, im = W.random_records(2, rng, 4)
+    o = orc.Oracle(2, 1, 1, 0.01, h, lops, keys, re, im)
+    net = W.random_deep_mlp(rng)
+    with pytest.raises(orc.OracleError):
+        o.set_proposal_deep(3, net)
+    bad = list(net)
+    bad[6] = 31
+    with pytest.raises(orc.OracleError):
+        o.set_proposal_deep(2, tuple(bad))
+    o.set_proposal_deep(2, net)
+    with pytest.raises(orc.OracleError):
+        o.set_integrator("ab2")
+    with pytest.raises(orc.OracleError):
+        o.set_initiator(5)
+
+
 # ---- the step --------------------------------------------------------------------------------
 
 def _store(o, r):
@@ -167,7 +275,7 @@ def _q_matrix(o, n, s, gamma):
 
 
 @pytest.mark.parametrize("kind,K", [("uniform", 1), ("uniform", 4), ("heatbath", 2),
-                                    ("mlp", 1), ("mlp", 8)])
+                                    ("mlp", 1), ("mlp", 8), ("deep", 1), ("deep", 4)])
 def test_one_step_unbiased(orc, kind, K):
     """Mean of many one-step samples (replicas draw independent streams) vs the exact
     (I + dt L_q) N: every component within 5 standard errors."""
@@ -180,7 +288,10 @@ def test_one_step_unbiased(orc, kind, K):
     keys, re, im = W.random_records(n, rng, 6, scale=40)
     R = 6000
     o = orc.Oracle(n, R, 777, dt, h, lops, keys, re, im)
-    o.set_proposal(kind, K, W.random_mlp(rng) if kind == "mlp" else None)
+    if kind == "deep":
+        o.set_proposal_deep(K, W.random_deep_mlp(rng, s1=2, s2=6))
+    else:
+        o.set_proposal(kind, K, W.random_mlp(rng) if kind == "mlp" else None)
     o.step(s[None, :], gamma[None, :])
     D2 = 1 << (2 * n)
     samples = np.zeros((R, D2), dtype=complex)

@@ -234,6 +234,22 @@ int qmc_set_proposal(qmc_ctx* ctx, int32_t kind, uint32_t samples, const int8_t*
                      const int32_t* b1, const int8_t* w2, const int32_t* b2,
                      uint32_t hidden_shift);
 
+/* Spawn proposal kind 4, the learned proposal's deeper network (End Matter, spawn step, as
+ * above; the learned-proposal configuration's inputs): channel weights W of both components of
+ * group g = min(2^24, max(0, score_{g-1})), 0 past 64 groups, from an int8 network with 128
+ * inputs -- +1 / -1 where key bit b is set / clear for b < 2n, then one input per weight channel
+ * of the step (the model's H monomials, then its Lindblad operators), 1 where that channel's
+ * weight is nonzero at the step and 0 where it is zero, 0 past -- two hidden layers of 128 units,
+ * h1 = min(127, max(0, b1 + w1 . x) >> shift1), h2 = min(127, max(0, b2 + w2 . h1) >> shift2), and
+ * score_g = b3[g] + w3[g] . h2.  w1 int8 [128][128], b1 int32 [128], w2 int8 [128][128],
+ * b2 int32 [128], w3 int8 [64][128], b3 int32 [64]: row-major host arrays, copied.  The hidden
+ * layers run as int8 MFMA products with int32 accumulation.  `samples` as above; the same
+ * refusals as qmc_set_proposal (QMC_ERR_ARG), and shifts above 30.  qmc_set_proposal(kind 0)
+ * switches it off. */
+int qmc_set_proposal_deep(qmc_ctx* ctx, uint32_t samples, const int8_t* w1, const int32_t* b1,
+                          const int8_t* w2, const int32_t* b2, const int8_t* w3,
+                          const int32_t* b3, uint32_t shift1, uint32_t shift2);
+
 /* Tile size of the streamed path's radix sort of child records (records per thread of a
  * 256-thread tile: 8, 12, 16 or 24; 16 by default).  records_per_thread = 0 autotunes: every size
  * is timed three times on synthetic records of this context's composite-key width and spawn

@@ -31,7 +31,7 @@ EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_profile", "qmc_profile_read", "qmc_profile_read_class", "qmc_coeff_table",
             "qmc_last_error",
             "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch",
-            "qmc_observe_noalloc", "qmc_small_limit"]
+            "qmc_observe_noalloc", "qmc_small_limit", "qmc_set_proposal_deep"]
 
 
 class Monomial(ctypes.Structure):
@@ -106,6 +106,8 @@ def lib():
         L.qmc_set_initiator.argtypes = [vp, ctypes.c_uint64]
         i8p = P(ctypes.c_int8)
         L.qmc_set_proposal.argtypes = [vp, i32, u32, i8p, P(i32), i8p, P(i32), u32]
+        L.qmc_set_proposal_deep.argtypes = [vp, u32, i8p, P(i32), i8p, P(i32), i8p, P(i32), u32,
+                                            u32]
         L.qmc_tune_sort.argtypes = [vp, u32, P(u32)]
         L.qmc_use_graphs.argtypes = [vp, i32]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
@@ -355,6 +357,22 @@ class QMC:
         else:
             self._check(lib().qmc_set_proposal(self._ctx, kd, int(samples) if kd else 0, None, None,
                                                None, None, 0))
+
+    def set_proposal_deep(self, samples, net):
+        """Spawn proposal kind 4 (the deeper int8 network of the key bits and the step's active
+        weight channels): net = (w1 int8 [128, 128], b1 int32 [128], w2 int8 [128, 128],
+        b2 int32 [128], w3 int8 [64, 128], b3 int32 [64], shift1, shift2)."""
+        w1, b1, w2, b2, w3, b3, s1, s2 = net
+        shapes = [(128, 128), (128,), (128, 128), (128,), (64, 128), (64,)]
+        types = [np.int8, np.int32] * 3
+        arrs = [np.ascontiguousarray(a, dtype=t) for a, t in zip((w1, b1, w2, b2, w3, b3), types)]
+        if [a.shape for a in arrs] != shapes:
+            raise ValueError("network shapes: w1 [128, 128], b1 [128], w2 [128, 128], b2 [128], "
+                             "w3 [64, 128], b3 [64]")
+        ct = [ctypes.c_int8, ctypes.c_int32] * 3
+        self._check(lib().qmc_set_proposal_deep(self._ctx, int(samples),
+                                                *[_ptr(a, t) for a, t in zip(arrs, ct)],
+                                                int(s1), int(s2)))
 
     def observe(self, pauli=(), psi=(), want_eps=False):
         spec, o, out, keep = _obs_args(self.R, pauli, psi, want_eps)

@@ -65,8 +65,11 @@ struct TableHeader {
   uint32_t bytes;
   uint64_t q_off;
   uint64_t q_diag;
+  uint64_t active[2];  // bit m: weight channel m of the step (H monomials, then Lindblad
+                       // operators of the circuit) is nonzero; channels past 127 not kept
   uint64_t pad;
 };
+static_assert(sizeof(TableHeader) % 16 == 0, "the group masks follow at a 16-byte offset");
 
 struct Counters {
   uint64_t n_store[2];     // occupied keys of the current / next store (by step parity)

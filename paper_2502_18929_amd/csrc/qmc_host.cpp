@@ -31,6 +31,11 @@ constexpr size_t kTableArea = 32u << 20;  // device bytes for the step tables of
 constexpr size_t kMlpW1 = (size_t)kPropHidden * kPropIn, kMlpB1 = (size_t)kPropHidden * 4,
                  kMlpW2 = (size_t)kPropOut * kPropHidden, kMlpB2 = (size_t)kPropOut * 4;
 constexpr size_t kMlpBytes = kMlpW1 + kMlpB1 + kMlpW2 + kMlpB2;
+// the deeper network (kind 4): w1, b1, w2, b2, w3, b3
+constexpr size_t kDeepW1 = (size_t)kDeepHidden * kDeepIn, kDeepB1 = (size_t)kDeepHidden * 4,
+                 kDeepW2 = (size_t)kDeepHidden * kDeepHidden, kDeepB2 = (size_t)kDeepHidden * 4,
+                 kDeepW3 = (size_t)kDeepOut * kDeepHidden, kDeepB3 = (size_t)kDeepOut * 4;
+constexpr size_t kDeepBytes = kDeepW1 + kDeepB1 + kDeepW2 + kDeepB2 + kDeepW3 + kDeepB3;
 // sort tiles: kBlock x (8, 12, 16 or 24) records; 16 unless qmc_tune_sort picks another
 constexpr uint64_t kSortTileMin = (uint64_t)qmc::kBlock * 8;
 constexpr uint32_t kSortIpts[] = {8, 12, 16, 24};
@@ -132,7 +137,7 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.slots = take((size_t)2 * P * 4 * 8);
   L.done = take(8);
   L.pulse = take((size_t)n_circuits * 16);
-  L.mlp = take(kMlpBytes);
+  L.mlp = take(kMlpBytes + kDeepBytes);
   L.small_fail = take(8);
   L.small_stats = take((size_t)kSmallBatches * c.n_replicas * kSmallStats * 8);
   L.total = o;
@@ -305,10 +310,17 @@ struct HostTable {
   std::vector<uint64_t> gx;      // group masks (gx[0] = 0)
   std::vector<uint32_t> gs;      // group starts, size n_groups + 1
   uint64_t q_off = 0, q_diag = 0;
+  uint64_t active[2] = {0, 0};   // nonzero weight channels of the step (proposal input)
 };
 
 int build_table(const std::vector<SrcTerm>& src, double dt, const double* s, const double* g,
-                double scale, HostTable& T, std::string& why) {
+                double scale, HostTable& T, std::string& why, uint32_t nh = 0, uint32_t nl = 0) {
+  // the step's weight channels that are nonzero: H monomials m < nh, then Lindblad operators
+  T.active[0] = T.active[1] = 0;
+  for (uint32_t m = 0; m < nh + nl && m < 128; ++m) {
+    const double w = m < nh ? s[m] : g[m - nh];
+    if (w != 0.0) T.active[m >> 6] |= 1ull << (m & 63);
+  }
   // src is sorted by (xmask, zmask): each run of equal terms is one merged Q32 term.
   T.t.clear();
   T.t.reserve(src.size());
@@ -382,6 +394,8 @@ size_t pack_table(const HostTable& T, uint8_t* dst) {
   h.bytes = (uint32_t)((h.t_off + sizeof(qmc::Term) * NT + 15) & ~15u);
   h.q_off = T.q_off;
   h.q_diag = T.q_diag;
+  h.active[0] = T.active[0];
+  h.active[1] = T.active[1];
   if (!dst) return h.bytes;
   std::memset(dst, 0, h.bytes);
   std::memcpy(dst, &h, sizeof(h));
@@ -1271,7 +1285,9 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     ws += c->wh_off[ci];
     wg += c->wl_off[ci];
     const bool two = ab2 && k >= euler_first;
-    int rc = build_table(c->terms[ci], c->cfg.dt, ws, wg, two ? 1.5 : 1.0, TA, why);
+    const uint32_t nh = (ci + 1 < NC ? c->wh_off[ci + 1] : c->n_h) - c->wh_off[ci];
+    const uint32_t nl = (ci + 1 < NC ? c->wl_off[ci + 1] : c->n_l) - c->wl_off[ci];
+    int rc = build_table(c->terms[ci], c->cfg.dt, ws, wg, two ? 1.5 : 1.0, TA, why, nh, nl);
     if (!rc && two) {
       const double *ps, *pg;
       if (k > 0) {
@@ -1645,6 +1661,45 @@ int qmc_set_proposal(qmc_ctx* c, int32_t kind, uint32_t samples, const int8_t* w
     p.w2 = reinterpret_cast<const int8_t*>(d + kMlpW1 + kMlpB1);
     p.b2 = reinterpret_cast<const int32_t*>(d + kMlpW1 + kMlpB1 + kMlpW2);
   }
+  c->prop = p;
+  return QMC_OK;
+}
+
+int qmc_set_proposal_deep(qmc_ctx* c, uint32_t samples, const int8_t* w1, const int32_t* b1,
+                          const int8_t* w2, const int32_t* b2, const int8_t* w3,
+                          const int32_t* b3, uint32_t shift1, uint32_t shift2) {
+  if (!c) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  if (samples == 0 || samples > 64 || (samples & (samples - 1)))
+    return fail(c, QMC_ERR_ARG, "proposal samples must be a power of two from 1 to 64");
+  if (c->integrator != 0 || c->init_min != 0 || c->C != 1)
+    return fail(c, QMC_ERR_ARG, "spawn proposals run with Euler, one circuit, no initiators");
+  if (2 * c->n > 64) return fail(c, QMC_ERR_ARG, "key wider than the network input");
+  if (!w1 || !b1 || !w2 || !b2 || !w3 || !b3 || shift1 > 30 || shift2 > 30)
+    return fail(c, QMC_ERR_ARG, "the network needs all its weights and shifts <= 30");
+  uint8_t* d = c->at<uint8_t>(c->L.mlp) + kMlpBytes;
+  const void* src[6] = {w1, b1, w2, b2, w3, b3};
+  const size_t len[6] = {kDeepW1, kDeepB1, kDeepW2, kDeepB2, kDeepW3, kDeepB3};
+  size_t off[6];
+  size_t o = 0;
+  for (int i = 0; i < 6; ++i) {
+    off[i] = o;
+    HIPCHK(c, hipMemcpyAsync(d + o, src[i], len[i], hipMemcpyHostToDevice, c->stream));
+    o += len[i];
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // the caller's arrays may go away
+  QmcProposal p{};
+  p.kind = 4;
+  p.k = samples;
+  p.nbits = 2 * c->n;
+  p.s1 = shift1;
+  p.s2 = shift2;
+  p.w1 = reinterpret_cast<const int8_t*>(d + off[0]);
+  p.b1 = reinterpret_cast<const int32_t*>(d + off[1]);
+  p.w2 = reinterpret_cast<const int8_t*>(d + off[2]);
+  p.b2 = reinterpret_cast<const int32_t*>(d + off[3]);
+  p.w3 = reinterpret_cast<const int8_t*>(d + off[4]);
+  p.b3 = reinterpret_cast<const int32_t*>(d + off[5]);
   c->prop = p;
   return QMC_OK;
 }

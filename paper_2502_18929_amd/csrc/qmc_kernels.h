@@ -6,18 +6,25 @@
 
 // Spawn proposal (End Matter, spawn step: the multinomial over a column's (target, Re/Im)
 // channels, importance weighted): kind 0 = the comb (no proposal), 1 uniform, 2 heat-bath, 3 the
-// int8 MLP scores of the key bits; k samples per parent (a power of two); MLP sizes
-// kPropIn x kPropHidden x kPropOut, weights in device memory (w1 [hidden][in], w2 [out][hidden]).
+// int8 MLP scores of the key bits, 4 the deeper int8 network of the key bits and the step's
+// active weight channels; k samples per parent (a power of two).  Kind 3: sizes
+// kPropIn x kPropHidden x kPropOut (w1 [hidden][in], w2 [out][hidden]).  Kind 4: kDeepIn inputs,
+// two layers of kDeepHidden units, kDeepOut scores (w1 [hidden][in], w2 [hidden][hidden],
+// w3 [out][hidden]).  Weights in device memory.
 constexpr int kPropIn = 64, kPropHidden = 32, kPropOut = 64;
+constexpr int kDeepIn = 128, kDeepHidden = 128, kDeepOut = 64;
 struct QmcProposal {
   uint32_t kind;
   uint32_t k;
-  uint32_t nbits;   // key bits fed to the MLP (2n)
-  uint32_t s1;      // hidden-layer shift
+  uint32_t nbits;   // key bits fed to the network (2n)
+  uint32_t s1;      // first hidden layer's shift
   const int8_t* w1;
   const int32_t* b1;
   const int8_t* w2;
   const int32_t* b2;
+  const int8_t* w3;   // kind 4: output layer, and the second hidden layer's shift
+  const int32_t* b3;
+  uint32_t s2;
 };
 
 extern "C" {

@@ -139,6 +139,74 @@ __device__ __forceinline__ void mlp_hidden(const QmcProposal& pr, uint64_t key, 
   wave_lds_fence();
 }
 
+// Hidden layers of the deeper proposal network (kind 4) for the 64 keys of a wave (lane l holds
+// key l; every lane calls).  Input of a key: +1 / -1 for key bits b < nbits, then 1 / 0 for the
+// step's weight channels that are nonzero / zero (bits of `active`), 0 past kDeepIn.  Layer 1:
+// h1 = min(127, max(0, b1 + w1 x) >> s1), 128 units, as int8 MFMA 32x32x16 products (32 keys x 16
+// inputs by 16 inputs x 32 units, eight input blocks per product) accumulated in int32; h1 goes
+// to LDS (64 x 128 bytes) and layer 2 reads it the same way: h2 = min(127, max(0, b2 + w2 h1) >>
+// s2) into the second 64 x 128 bytes.  Lane l of a product holds unit 32 cb + l % 32 of keys
+// 8 (i / 4) + 4 (l / 32) + i % 4 in its i-th accumulator.
+__device__ __forceinline__ void mlp_deep(const QmcProposal& pr, uint64_t key, uint64_t act0,
+                                         uint64_t act1, uint8_t* hid) {
+  const uint32_t lane = __lane_id(), col = lane & 31u, half = lane >> 5;
+  uint8_t* h1 = hid;
+  uint8_t* h2 = hid + kWave * kDeepHidden;
+  const uint32_t nb = pr.nbits < (uint32_t)kDeepIn ? pr.nbits : (uint32_t)kDeepIn;
+  auto layer = [&](const int8_t* w, const int32_t* bias, uint32_t sh, uint8_t* out,
+                   auto&& operand) __attribute__((always_inline)) {
+#pragma unroll 1
+    for (int rb = 0; rb < 2; ++rb) {
+      uint64_t a[kDeepIn / 16];
+#pragma unroll
+      for (int kb = 0; kb < kDeepIn / 16; ++kb) a[kb] = operand(rb, kb * 16 + half * 8);
+#pragma unroll 1
+      for (int cb = 0; cb < kDeepHidden / 32; ++cb) {
+        const uint32_t unit = cb * 32 + col;
+        v16i32 acc = {};
+#pragma unroll
+        for (int kb = 0; kb < kDeepIn / 16; ++kb) {
+          const uint64_t wv =
+              *reinterpret_cast<const uint64_t*>(w + unit * kDeepIn + kb * 16 + half * 8);
+          acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)a[kb], (long)wv, acc, 0, 0, 0);
+        }
+        const int32_t b = bias[unit];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const uint32_t row = 8 * (i / 4) + 4 * half + (i % 4);
+          const int32_t v = acc[i] + b;
+          int32_t h = v > 0 ? (v >> sh) : 0;
+          h = h > 127 ? 127 : h;
+          out[(rb * 32 + row) * kDeepHidden + unit] = (uint8_t)h;
+        }
+      }
+    }
+    wave_lds_fence();
+  };
+  // layer 1: the A operand of key row `col` of block rb, inputs b0 .. b0 + 7
+  layer(pr.w1, pr.b1, pr.s1, h1, [&](int rb, uint32_t b0) __attribute__((always_inline)) {
+    const uint64_t kr = __shfl(key, rb * 32 + (int)col);
+    uint64_t v = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t i = b0 + e;
+      uint64_t x;
+      if (i < nb) {
+        x = ((kr >> i) & 1u) ? 0x01ull : 0xFFull;
+      } else {
+        const uint32_t m = i - nb;
+        x = ((m < 64 ? act0 >> m : act1 >> (m - 64)) & 1u) ? 0x01ull : 0x00ull;
+      }
+      v |= x << (8 * e);
+    }
+    return v;
+  });
+  // layer 2: the A operand is a row of h1
+  layer(pr.w2, pr.b2, pr.s2, h2, [&](int rb, uint32_t b0) __attribute__((always_inline)) {
+    return *reinterpret_cast<const uint64_t*>(h1 + (rb * 32 + col) * kDeepHidden + b0);
+  });
+}
+
 __device__ __forceinline__ uint32_t bitlen64(uint64_t v) {
   return v ? 64u - (uint32_t)__clzll(v) : 0u;
 }
@@ -153,7 +221,7 @@ __device__ __forceinline__ uint32_t bitlen64(uint64_t v) {
 // |x| mod (K P), with the sign of x -- a uniform on [0, K P), so the rounding is exact.
 // Weights: uniform 1; heat-bath |x_ch| >> sh, sh = max(0, bitlen(|a| + |b|) + bitlen(q_off) - 24);
 // MLP min(2^24, max(0, score_g)) for both components, score_g = b2[g-1] + w2[g-1] . h (0 past
-// kPropOut groups).
+// kPropOut groups); kind 4 the same with score_g = b3[g-1] + w3[g-1] . h2 (0 past kDeepOut).
 __device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv, bool valid,
                                                uint64_t ck, int2 v, const KeyLayout& kl,
                                                const QmcProposal& pr, uint32_t step,
@@ -161,13 +229,17 @@ __device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv,
   const uint32_t lane = __lane_id();
   const uint64_t key = kl.key(ck);
   if (pr.kind == 3) mlp_hidden(pr, key, hid);
+  if (pr.kind == 4) mlp_deep(pr, key, tv.h->active[0], tv.h->active[1], hid);
   const uint32_t G = valid ? tv.h->n_groups : 0u;
   const bool act = valid && G > 1;
   if (__ballot(act) == 0) return;
+  // the lane's hidden units feeding the scores, four per word: kind 3 h in registers, kind 4 h2
+  // read from its LDS row as the scores need it
   uint32_t hw[kPropHidden / 4];
 #pragma unroll
   for (int q = 0; q < kPropHidden / 4; ++q)
     hw[q] = pr.kind == 3 ? reinterpret_cast<const uint32_t*>(hid + lane * kPropHidden)[q] : 0u;
+  const uint4* h2row = reinterpret_cast<const uint4*>(hid + (kWave + lane) * kDeepHidden);
   const uint64_t sab = uabs64(v.x) + uabs64(v.y);
   const uint32_t nch = act ? 2 * (G - 1) : 2u;
   const uint64_t T32 = 1ull << 32, F = T32 / (16ull * nch), M = T32 - (uint64_t)nch * F;
@@ -186,7 +258,20 @@ __device__ __forceinline__ void spawn_proposal(Emitter& em, const TableView& tv,
       wi = uabs64(xim) >> sh;
     } else {
       int32_t sc = 0;
-      if (g - 1 < (uint32_t)kPropOut) {
+      if (pr.kind == 4) {
+        if (g - 1 < (uint32_t)kDeepOut) {
+          const uint4* w3r = reinterpret_cast<const uint4*>(pr.w3 + (g - 1) * kDeepHidden);
+          sc = pr.b3[g - 1];
+#pragma unroll
+          for (int q = 0; q < kDeepHidden / 16; ++q) {
+            const uint4 h = h2row[q], w = w3r[q];
+            sc = __builtin_amdgcn_sdot4((int)h.x, (int)w.x, sc, false);
+            sc = __builtin_amdgcn_sdot4((int)h.y, (int)w.y, sc, false);
+            sc = __builtin_amdgcn_sdot4((int)h.z, (int)w.z, sc, false);
+            sc = __builtin_amdgcn_sdot4((int)h.w, (int)w.w, sc, false);
+          }
+        }
+      } else if (g - 1 < (uint32_t)kPropOut) {
         const uint32_t* w2r = reinterpret_cast<const uint32_t*>(pr.w2 + (g - 1) * kPropHidden);
         sc = pr.b2[g - 1];
 #pragma unroll
@@ -390,7 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
     uint32_t* __restrict__ ghist, uint32_t passes, QmcProposal pr) {
   __shared__ uint64_t s_key[kWaves][kSpawnSeg];
   __shared__ int2 s_val[kWaves][kSpawnSeg];
-  __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? kWave * kPropHidden : 4];
+  // proposal networks: kind 3 uses 64 x kPropHidden bytes per wave, kind 4 two 64 x kDeepHidden
+  __shared__ uint8_t s_hid[kProp ? kWaves : 1][kProp ? 2 * kWave * kDeepHidden : 4];
   __shared__ uint64_t s_ak[kMergeActive];  // queued parents: key, value, comb words
   __shared__ int2 s_av[kMergeActive];
   __shared__ uint2 s_aw[kMergeActive];

@@ -290,6 +290,10 @@ def main():
     ap.add_argument("--sequential-steps", type=int, default=0,
                     help="batch64: also time its first this many steps circuit by circuit, one "
                          "context each, against the batched step")
+    ap.add_argument("--compare-proposals", action="store_true",
+                    help="ghz20_nm: the learned proposal (the deeper int8 network, trained first on "
+                         "the spawn events of a plain run) against uniform, heat-bath and the "
+                         "comb: sign angle and the <Z0>(t) error bar at equal wall time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--progress", type=int, default=0,
                     help="print a line to stderr after every this many timed steps (runs the "
@@ -301,6 +305,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(replicas and key-space shards would each map to one GPU).", file=sys.stderr)
         sys.exit(2)
+    if args.compare_proposals:
+        return compare_proposals(args)
     dominant = DOMINANT_INITIATOR if args.initiator_xi else DOMINANT
     kind = args.roofline_kernel or ("merge" if args.path == "streamed" or
                                     args.proposal != "comb" else dominant[args.workload])
@@ -462,6 +468,52 @@ def cpu_baseline_batch(bw, K, budget_s=20.0):
             "key_steps_per_s": ks / dt, "host": host_description()}
 
 
+def batch_vs_oracle(g, bw, init, K, S=1):
+    """Per-circuit check of the batched run at its last step, by the CPU oracle: the context goes
+    back to the initial state and runs to step K - S, every circuit's replicas are imported into
+    an oracle of that circuit (stream ids c R + r, the state is (store, step) since the draws are
+    keyed on the walkers), and both take the last S steps.  A circuit's flag is true when every
+    one of its replicas' stores is identical (keys and both counts)."""
+    import numpy as np
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    R = bw.n_replicas
+    for r in range(g.R):
+        g.import_(r, *init[r], step=0)
+    g.run_batch_workload(bw, 0, K - S)
+    orcs = []
+    for c, w in enumerate(bw.circuits):
+        o = oracle.Oracle(bw.n, R, bw.seed, bw.dt, w.h, w.lops, w.init_keys, w.init_re,
+                          w.init_im)
+        o.set_replica_base(c * R)
+        for r in range(R):
+            o.import_(r, *g.export(c * R + r), step=K - S)
+        orcs.append(o)
+    t0 = time.perf_counter()
+    for a, b, masks in bw.segments():
+        if b <= K - S or a >= K:
+            continue
+        if a >= K - S and masks is not None:
+            for c, o in enumerate(orcs):
+                if masks[0][c] or masks[1][c]:
+                    o.pulse(int(masks[0][c]), int(masks[1][c]))
+        lo, hi = max(a, K - S), min(b, K)
+        for o, w in zip(orcs, bw.circuits):
+            o.step(w.s[lo:hi], w.gamma[lo:hi], threads=threads)
+    g.run_batch_workload(bw, K - S, K)
+    flags = []
+    for c, o in enumerate(orcs):
+        ok = True
+        for r in range(R):
+            x, y = g.export(c * R + r), o.export(r)
+            ok = ok and all(np.array_equal(u, v) for u, v in zip(x, y))
+        flags.append(bool(ok))
+        o.close()
+    return {"steps_checked": f"{K - S}..{K}", "circuits": len(flags),
+            "bit_exact": flags, "all_bit_exact": all(flags),
+            "oracle_s": time.perf_counter() - t0}
+
+
 def batch_vs_sequential(bw, S, path):
     """The first S steps of the batch twice: batched (all circuits in one context) and circuit by
     circuit (one context each, run one after another), wall times between device
@@ -549,7 +601,89 @@ def main_batch(args, kind):
                                                            args.path)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_batch(bw, K)
+        # the CPU leg also checks every circuit against the oracle at the end of the timed window
+        res["cpu_baseline"]["per_circuit_vs_oracle"] = batch_vs_oracle(g, bw, init, K)
     g.close()
+    print(json.dumps(res), flush=True)
+
+
+def _ci95(v, boot=2000, seed=0):
+    """Half-width of the 95 % bootstrap percentile interval of the mean of v over replicas."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    v = np.asarray(v, dtype=np.float64)
+    if len(v) < 2:
+        return float("nan")
+    m = v[rng.integers(0, len(v), size=(boot, len(v)))].mean(axis=1)
+    lo, hi = np.percentile(m, [2.5, 97.5])
+    return float(hi - lo) / 2
+
+
+def compare_proposals(args):
+    """The learned proposal against uniform, heat-bath and the plain comb on ghz20_nm (8 replicas,
+    3000 steps, K draws per parent): the deeper int8 network is trained first (untimed) on the
+    off-diagonal spawn events of a plain run; then each kind runs the whole trajectory from the
+    initial state, and at every 250 steps the replicas' sign angle theta = arg N^diag (End Matter
+    on sign-problem suppression), Re N^diag and <Z0> are read.  The <Z0>(t) error bar is the 95 %
+    bootstrap half-width over the replicas; at equal wall time it is scaled by
+    sqrt(time / time of the comb) (replicas cost time linearly, the error bar falls as their
+    square root)."""
+    import numpy as np
+    import torch
+    from paper_2502_18929_amd import binding, proposal as PR, workloads as W
+    torch.cuda.set_device(0)
+    w = W.config_ghz20_nm()
+    store, spawn = 1 << 17, 1 << 19
+    K = args.proposal_samples
+    t0 = time.perf_counter()
+    tr = binding.QMC.from_workload(w, store_capacity=store, spawn_capacity=spawn)
+    net, info = PR.train_deep(tr, w)
+    tr.close()
+    info["train_s"] = time.perf_counter() - t0
+    z0 = [i for i, (lab, _, _, _) in enumerate(w.pauli_obs) if lab == "Z0"][0]
+    pauli = [(x, z) for _, x, z, _ in w.pauli_obs]
+    ph = complex(w.pauli_obs[z0][3])
+    every = 250
+    out = {}
+    for kind in ("comb", "uniform", "heatbath", "learned"):
+        g = binding.QMC.from_workload(w, store_capacity=store, spawn_capacity=spawn)
+        if kind == "learned":
+            g.set_proposal_deep(K, net)
+        elif kind != "comb":
+            g.set_proposal(kind, K)
+        torch.cuda.synchronize()
+        el = 0.0
+        rows = []
+        for a in range(0, w.nsteps, every):
+            b = min(a + every, w.nsteps)
+            t1 = time.perf_counter()
+            g.run_workload(w, a, b)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t1
+            obs = g.observe(pauli=pauli, psi=w.psi)
+            zv = (ph * (obs["pauli_val"][:, z0, 0] + 1j * obs["pauli_val"][:, z0, 1])).real
+            nd = obs["ndiag"][:, 0].astype(np.float64)
+            rows.append({"step": b, "theta_abs_mean": float(np.abs(obs["theta"]).mean()),
+                         "theta_abs_max": float(np.abs(obs["theta"]).max()),
+                         "re_ndiag_rel": float(nd.mean() / w.walker_target),
+                         "z0_mean": float(zv.mean()), "z0_ci95": _ci95(zv),
+                         "fidelity_mean": float(obs["fidelity"][:, 0].mean())})
+        out[kind] = {"wall_s": el, "ms_per_step": el * 1e3 / w.nsteps, "series": rows}
+        g.close()
+    base = out["comb"]["wall_s"]
+    for kind, o in out.items():
+        scale = np.sqrt(o["wall_s"] / base)
+        cis = np.array([r["z0_ci95"] for r in o["series"]])
+        o["z0_ci95_at_tf"] = float(cis[-1])
+        o["z0_ci95_equal_time_at_tf"] = float(cis[-1] * scale)
+        o["z0_ci95_equal_time_max"] = float(np.nanmax(cis) * scale)
+        o["theta_abs_max"] = max(r["theta_abs_max"] for r in o["series"])
+    res = {"metric": "learned spawn proposal against uniform, heat-bath and the comb at equal "
+                     "wall time (sign angle, <Z0>(t) error bar)",
+           "workload": f"{w.name}: n={w.n}, {w.n_replicas} replicas x {w.walker_target:g} walkers, "
+                       f"dt={w.dt}, {w.nsteps} steps",
+           "samples_per_parent": K, "training": info, "kinds": out, "dtype": "int64",
+           "data": "synthetic"}
     print(json.dumps(res), flush=True)
 
 

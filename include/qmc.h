@@ -250,6 +250,18 @@ int qmc_set_proposal_deep(qmc_ctx* ctx, uint32_t samples, const int8_t* w1, cons
                           const int8_t* w2, const int32_t* b2, const int8_t* w3,
                           const int32_t* b3, uint32_t shift1, uint32_t shift2);
 
+/* Spawn-event log, the training data of a learned proposal (the learned-proposal configuration:
+ * spawn events of the plain method).  From the next qmc_step on, every nonzero off-diagonal child
+ * that the streamed path draws with the plain comb (End Matter, spawn step) is appended to
+ * d_events as 24 bytes {uint64 parent composite key (segment << 2n | key), uint32 step, uint32
+ * column group g >= 1 of that step's table, int32 re, int32 im} (device memory, caller-owned)
+ * while fewer than `capacity` are stored; *d_count (device uint64, caller-owned, set by the
+ * caller) counts every event, so a count above capacity means events were dropped.  Events of
+ * one step come in no particular order.  The fused and LDS-resident paths and proposals log
+ * nothing: use qmc_step_path(ctx, 2) while logging.  d_events = NULL switches it off.
+ * QMC_ERR_ARG when d_events is given without d_count. */
+int qmc_log_spawns(qmc_ctx* ctx, void* d_events, uint64_t capacity, uint64_t* d_count);
+
 /* Tile size of the streamed path's radix sort of child records (records per thread of a
  * 256-thread tile: 8, 12, 16 or 24; 16 by default).  records_per_thread = 0 autotunes: every size
  * is timed three times on synthetic records of this context's composite-key width and spawn

@@ -31,7 +31,7 @@ EXPORTED = ["qmc_workspace_bytes", "qmc_init", "qmc_step", "qmc_step_path",
             "qmc_profile", "qmc_profile_read", "qmc_profile_read_class", "qmc_coeff_table",
             "qmc_last_error",
             "qmc_destroy", "qmc_workspace_bytes_batch", "qmc_init_batch", "qmc_pulse_batch",
-            "qmc_observe_noalloc", "qmc_small_limit", "qmc_set_proposal_deep"]
+            "qmc_observe_noalloc", "qmc_small_limit", "qmc_set_proposal_deep", "qmc_log_spawns"]
 
 
 class Monomial(ctypes.Structure):
@@ -108,6 +108,7 @@ def lib():
         L.qmc_set_proposal.argtypes = [vp, i32, u32, i8p, P(i32), i8p, P(i32), u32]
         L.qmc_set_proposal_deep.argtypes = [vp, u32, i8p, P(i32), i8p, P(i32), i8p, P(i32), u32,
                                             u32]
+        L.qmc_log_spawns.argtypes = [vp, vp, u64, vp]
         L.qmc_tune_sort.argtypes = [vp, u32, P(u32)]
         L.qmc_use_graphs.argtypes = [vp, i32]
         L.qmc_observe.argtypes = [vp, P(ObsSpec), P(ObsOut)]
@@ -357,6 +358,35 @@ class QMC:
         else:
             self._check(lib().qmc_set_proposal(self._ctx, kd, int(samples) if kd else 0, None, None,
                                                None, None, 0))
+
+    def log_spawns(self, capacity):
+        """Start logging the plain comb's off-diagonal spawn events of the streamed path into a
+        device buffer of `capacity` events (the path is set to 'streamed'); log_read() returns
+        them.  capacity = 0 stops logging."""
+        import torch
+        if capacity <= 0:
+            self._check(lib().qmc_log_spawns(self._ctx, None, 0, None))
+            self._log = None
+            return
+        ev = torch.empty(int(capacity) * 24, dtype=torch.uint8, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self._log = (ev, cnt, int(capacity))
+        self.set_path("streamed")
+        self._check(lib().qmc_log_spawns(self._ctx, ctypes.c_void_p(ev.data_ptr()), int(capacity),
+                                         ctypes.c_void_p(cnt.data_ptr())))
+
+    def log_read(self):
+        """(events, total): the logged events as a numpy structured array (key, step, group, re,
+        im) and the number drawn (more than stored when the buffer filled up)."""
+        import torch
+        ev, cnt, cap = self._log
+        torch.cuda.synchronize()
+        total = int(cnt.item())
+        n = min(total, cap)
+        dt = np.dtype([("key", "<u8"), ("step", "<u4"), ("group", "<u4"), ("re", "<i4"),
+                       ("im", "<i4")])
+        raw = ev[:n * 24].cpu().numpy()
+        return raw.view(dt).copy(), total
 
     def set_proposal_deep(self, samples, net):
         """Spawn proposal kind 4 (the deeper int8 network of the key bits and the step's active

@@ -1633,7 +1633,11 @@ int qmc_set_proposal(qmc_ctx* c, int32_t kind, uint32_t samples, const int8_t* w
   if (!c || kind < 0 || kind > 3) return QMC_ERR_ARG;
   if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
   if (kind == 0) {
-    c->prop = QmcProposal{};
+    QmcProposal p{};
+    p.log = c->prop.log;
+    p.log_cap = c->prop.log_cap;
+    p.log_count = c->prop.log_count;
+    c->prop = p;
     return QMC_OK;
   }
   if (samples == 0 || samples > 64 || (samples & (samples - 1)))
@@ -1645,6 +1649,9 @@ int qmc_set_proposal(qmc_ctx* c, int32_t kind, uint32_t samples, const int8_t* w
   p.kind = (uint32_t)kind;
   p.k = samples;
   p.nbits = 2 * c->n;
+  p.log = c->prop.log;
+  p.log_cap = c->prop.log_cap;
+  p.log_count = c->prop.log_count;
   if (kind == 3) {
     if (!w1 || !b1 || !w2 || !b2 || hidden_shift > 30)
       return fail(c, QMC_ERR_ARG, "the MLP proposal needs its weights and a shift <= 30");
@@ -1691,6 +1698,9 @@ int qmc_set_proposal_deep(qmc_ctx* c, uint32_t samples, const int8_t* w1, const 
   QmcProposal p{};
   p.kind = 4;
   p.k = samples;
+  p.log = c->prop.log;
+  p.log_cap = c->prop.log_cap;
+  p.log_count = c->prop.log_count;
   p.nbits = 2 * c->n;
   p.s1 = shift1;
   p.s2 = shift2;
@@ -1701,6 +1711,15 @@ int qmc_set_proposal_deep(qmc_ctx* c, uint32_t samples, const int8_t* w1, const 
   p.w3 = reinterpret_cast<const int8_t*>(d + off[4]);
   p.b3 = reinterpret_cast<const int32_t*>(d + off[5]);
   c->prop = p;
+  return QMC_OK;
+}
+
+int qmc_log_spawns(qmc_ctx* c, void* d_events, uint64_t capacity, uint64_t* d_count) {
+  if (!c || (d_events && !d_count)) return QMC_ERR_ARG;
+  if (c->broken) return fail(c, QMC_ERR_STATE, "context unusable after a HIP error");
+  c->prop.log = reinterpret_cast<SpawnEvent*>(d_events);
+  c->prop.log_cap = d_events ? capacity : 0;
+  c->prop.log_count = d_events ? reinterpret_cast<unsigned long long*>(d_count) : nullptr;
   return QMC_OK;
 }
 

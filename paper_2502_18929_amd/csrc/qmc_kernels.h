@@ -25,7 +25,21 @@ struct QmcProposal {
   const int8_t* w3;   // kind 4: output layer, and the second hidden layer's shift
   const int32_t* b3;
   uint32_t s2;
+  // Spawn-event log of the plain comb (null: off): every nonzero off-diagonal child drawn is
+  // appended as one event while fewer than log_cap are stored; *log_count counts them all.
+  struct SpawnEvent* log;
+  uint64_t log_cap;
+  unsigned long long* log_count;
 };
+// One logged spawn: the parent's composite key, the step, the column group, the child's counts.
+struct SpawnEvent {
+  uint64_t key;
+  uint32_t step;
+  uint32_t group;
+  int32_t re;
+  int32_t im;
+};
+static_assert(sizeof(SpawnEvent) == 24, "24-byte events");
 
 extern "C" {
 uint32_t qmck_sort_passes(uint32_t key_bits);

@@ -423,6 +423,10 @@ __device__ __forceinline__ void spawn_records(Emitter& em, const TableView& tv, 
       child.x = (int32_t)comb_step(r, xre);
       child.y = (int32_t)comb_step(r, xim);
       target = ck ^ tv.gx[g];
+      if (pr.log && (child.x | child.y) != 0) {
+        const unsigned long long at = atomicAdd(pr.log_count, 1ull);
+        if (at < pr.log_cap) pr.log[at] = SpawnEvent{ck, step, g, child.x, child.y};
+      }
     }
     em.emit((child.x | child.y) != 0, kl.rkey(target, sab), child);
   }

@@ -151,3 +151,36 @@ def test_deep_refusals(B):
     with pytest.raises(B.QMCError) as e:
         g.set_proposal_deep(2, net)
     assert e.value.code == B.QMC_ERR_ARG
+
+
+def test_spawn_log_holds_the_plain_children(B, orc):
+    """The spawn-event log of a plain streamed run: one event per nonzero off-diagonal child, as
+    many as the oracle's child records over the same steps, each naming a column group of its
+    step's table and a parent of that step; logging changes no result; a full buffer keeps
+    counting."""
+    w = W.config_ghz4()
+    g = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    g.log_spawns(1 << 16)
+    o = orc.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
+                   w.init_im)
+    parents = {}
+    for k in range(60):
+        parents[k] = {int(key) | (r << (2 * w.n)) for r in range(w.n_replicas)
+                      for key in g.export(r)[0]}
+        g.step(w.s[k:k + 1], w.gamma[k:k + 1])
+        o.step(w.s[k:k + 1], w.gamma[k:k + 1])
+    _same(g, o, w.n_replicas, "step 60 with logging")
+    ev, total = g.log_read()
+    assert total == len(ev) == o.counters()["child_steps"] == g.counters()["spawn_steps"]
+    assert np.all((ev["re"] != 0) | (ev["im"] != 0))
+    for k in range(60):
+        sel = ev[ev["step"] == k]
+        G = len(B.coeff_table(w.n, w.dt, w.h, w.lops, w.s[k], w.gamma[k])["gxmask"])
+        assert np.all((sel["group"] >= 1) & (sel["group"] < G))
+        assert {int(x) for x in sel["key"]} <= parents[k]
+    g.log_spawns(10)
+    g.step(w.s[60:80], w.gamma[60:80])
+    ev2, total2 = g.log_read()
+    assert len(ev2) == 10 and total2 > 10
+    g.log_spawns(0)
+    g.step(w.s[80:90], w.gamma[80:90])

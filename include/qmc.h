@@ -150,7 +150,7 @@ int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma
  * per-step inbox, otherwise the streamed kernels (spawn, radix sort of the children, merge)
  * for the next 256 steps; and before both, while every replica (store segment) has at most
  * qmc_small_limit occupied keys, the Euler step with the comb runs LDS-resident: one workgroup
- * per segment holds it and takes batches of up to 128 steps with no grid-wide synchronization
+ * per segment holds it and takes batches of up to 64 steps with no grid-wide synchronization
  * (a segment that outgrows the limit, or whose step would need more than 1024 records on
  * unoccupied keys or exceed a capacity, hands the step over to the fused kernel for the rest of
  * the trajectory, until the next qmc_import, qmc_step_path or qmc_small_limit).  path 1: fused

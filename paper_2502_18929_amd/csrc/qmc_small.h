@@ -8,7 +8,7 @@ constexpr int kSmallCap = 1024;    // occupied keys of one replica the step hold
 constexpr int kSmallNew = 1024;    // records per replica and step landing on unoccupied keys
 constexpr int kSmallStats = 5;     // per-replica statistics: walkers, keys, records, outputs,
                                    // death records (summed over the batch's steps)
-constexpr uint32_t kSmallBatch = 128;  // steps per launch of a chain
+constexpr uint32_t kSmallBatch = 64;   // steps per launch of a chain
 
 struct SmallLaunch {
   const uint64_t* ck;       // canonical store, n_store[cur] records of all segments, or null:

@@ -215,10 +215,20 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
   uint32_t st_d = 0, st_c = 0;
   uint32_t b = 0;  // parent buffer
   uint32_t kdone = 0;
+  // The chain's stop word, read by thread 0 during each step and looked at one step later (the
+  // load's latency hidden): once another workgroup has stopped the chain, this batch's results
+  // are dropped anyway, so this workgroup halts too.
+  unsigned long long seen = 0;
+  bool halted = false;
   for (uint32_t k = 0; k < A.nsteps; ++k) {
     const uint32_t s = A.step0 + k;
     const uint32_t p = k & 1;
+    if (t == 0 && k > 0 && (uint32_t)(seen >> 32) == A.epoch) S.flag[p] = 3;
     __syncthreads();  // the parents, this step's table and counters
+    if (S.flag[p] == 3) {  // block-uniform
+      halted = true;
+      break;
+    }
     if (t == 0) {
       S.nnew[p ^ 1] = 0;
       S.nact[p ^ 1] = 0;
@@ -227,6 +237,7 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
     }
     const bool more = k + 1 < A.nsteps;
     const uint4 tnext = more ? table_word(k + 1) : make_uint4(0, 0, 0, 0);
+    if (t == 0) seen = __hip_atomic_load(A.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const TableViewT<lptr> tv = table_view<lptr>(reinterpret_cast<const uint8_t*>(S.tab[k & 1]));
     const uint32_t G = tv.h->n_groups;
     const uint64_t q_off = G > 1 ? tv.h->q_off : 0, q_diag = tv.h->q_diag + uabs64(qs);
@@ -451,8 +462,9 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
   }
   if (kdone < A.nsteps) {
     // this replica could not take step step0 + kdone (more keys or new records than the LDS
-    // holds, a population outside int32, or more records than the spawn capacity)
-    if (t == 0) chain_stop(A.stop, A.epoch, A.step0 + kdone);
+    // holds, a population outside int32, or more records than the spawn capacity), or another
+    // one stopped the chain first
+    if (t == 0 && !halted) chain_stop(A.stop, A.epoch, A.step0 + kdone);
     return;
   }
   __syncthreads();  // the last step's outputs

@@ -130,7 +130,7 @@ def test_small_hands_over_to_the_fused_kernel(B, orc):
 
 @pytest.mark.timeout(600)
 def test_small_limits_change_nothing(B, orc):
-    """One call over the whole ghz20_nm trajectory (a chain of 128-step batches that stops
+    """One call over the whole ghz20_nm trajectory (a chain of 64-step batches that stops
     inside a batch, which is run again up to the stop) at several key limits, and with the
     LDS-resident step off: the same final stores as the oracle, the same counters."""
     w = W.config_ghz20_nm()

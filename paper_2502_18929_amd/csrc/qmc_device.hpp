@@ -21,14 +21,14 @@ constexpr int kMergeCap = kMergeTile + kMergeSlack + 8;
 constexpr int kSpawnSeg = 256;       // per-wave LDS staging of child records in k_spawn
 constexpr int kSpawnRound = 1024;    // parents k_spawn loads at once
 constexpr int kMergeActive = kBlock + kWave;  // spawn queue of active parents: < 64 + one chunk
-constexpr int kMergeQueue = 2 * kBlock;  // merge's queue of next-step parents (flushed when full)
+constexpr int kMergeQueue = kBlock;  // merge's queue of next-step parents (flushed when full)
 constexpr int kRadixBits = 11;       // digit width of the onesweep passes
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kMaxPasses = 6;        // ceil(64 / 11)
 constexpr int kSortIpt = 16;         // records per thread of a sort tile
 constexpr int kSortTile = kBlock * kSortIpt;
 constexpr int kPersistBlocks = 512;  // grid of the persistent (tile-ticket) kernels
-constexpr int kMergeBlocks = 1536;   // k_merge: six workgroups per CU (about 23 KB of LDS each)
+constexpr int kMergeBlocks = 1536;   // k_merge: at most six workgroups per CU (26 KB of LDS each)
 constexpr int kMaxSegments = 512;    // key ranges (workgroups) of the segmented step
 constexpr int kMaxCircuits = kMaxSegments;  // circuits of one batch (each needs a key range)
 constexpr int kInboxMax = 4096;      // records per segment inbox (sorted in LDS)

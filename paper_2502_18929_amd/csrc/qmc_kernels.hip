@@ -1067,7 +1067,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   constexpr int CAP = kMergeCap;
   __shared__ uint64_t s_pk[CAP];   // parents, then the tile's records behind them
   __shared__ int2 s_pv[CAP];
-  __shared__ uint32_t s_scan[kBlock];
+  __shared__ uint32_t s_scan[kWaves];
   __shared__ uint32_t s_xsplit[kBlock];  // merge-path split of each thread: parent | child << 16
   __shared__ uint64_t s_ws[kWaves];
   __shared__ uint64_t s_qk[kMergeQueue];  // outputs that can fire in step s+1, not yet appended
@@ -1574,6 +1574,27 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t* __restrict__ 
   out[2 * t + 1] = b;
 }
 
+// Workgroups of k_merge that are resident on the whole device at once (at most kMergeBlocks): its
+// tiles are strided over the grid, so a workgroup that has to wait for a free slot would run all
+// of its tiles after the others finished theirs.  Taken once per device from the occupancy the
+// compiled kernel reaches (its LDS and registers).
+static uint32_t merge_blocks() {
+  constexpr int kDevices = 64;
+  static uint32_t cached[kDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return 256;
+  if (cached[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    uint32_t g = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_merge, kBlock, 0) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        per_cu > 0 && cus > 0)
+      g = (uint32_t)per_cu * (uint32_t)cus;
+    cached[dev] = g < (uint32_t)kMergeBlocks ? g : (uint32_t)kMergeBlocks;
+  }
+  return cached[dev];
+}
+
 static inline uint32_t grid_for(uint64_t n, uint32_t cap_blocks) {
   uint64_t g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
@@ -1749,9 +1770,8 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.seed = seed;
   a.act_k = act_k;
   a.act_v = act_v;
-  hipLaunchKernelGGL(k_merge,
-                     dim3(max_tiles < (uint32_t)kMergeBlocks ? (max_tiles ? max_tiles : 1)
-                                                             : (uint32_t)kMergeBlocks),
+  const uint32_t mb = merge_blocks();
+  hipLaunchKernelGGL(k_merge, dim3(max_tiles < mb ? (max_tiles ? max_tiles : 1) : mb),
                      dim3(kBlock), 0, st, a);
   return (int)hipGetLastError();
 }

@@ -94,6 +94,36 @@ __host__ __device__ inline uint32_t sort_epoch(uint32_t step, uint32_t pass) {
   return 1u + (step * 8u + pass) % 65535u;
 }
 
+// Lane exchanges inside rows of 16 lanes (DPP, gfx9 encodings); lanes with no source read 0.
+template <int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, Ctrl, RowMask, 0xF, false);
+}
+
+// Sum over aligned groups of T lanes (T a power of two <= 64, wave-uniform), in every lane of
+// the group; all lanes active.
+__device__ __forceinline__ uint32_t team_sum(uint32_t x, uint32_t T) {
+  if (T >= 2) x += dpp<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  if (T >= 4) x += dpp<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  if (T >= 8) x += dpp<0x141>(x);   // row_half_mirror: a lane of the other quad of its 8
+  if (T >= 16) x += dpp<0x140>(x);  // row_mirror: a lane of the other half of its row
+  if (T >= 32) x += (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);  // lane ^ 16
+  if (T >= 64) x += __shfl_xor(x, 32);
+  return x;
+}
+
+// Inclusive prefix sum over aligned groups of T lanes (lt = lane index in the group); all lanes
+// active.
+__device__ __forceinline__ uint32_t team_scan(uint32_t x, uint32_t T, uint32_t lt) {
+  if (T >= 2) { const uint32_t y = dpp<0x111>(x); if (lt >= 1) x += y; }  // row_shr 1
+  if (T >= 4) { const uint32_t y = dpp<0x112>(x); if (lt >= 2) x += y; }  // row_shr 2
+  if (T >= 8) { const uint32_t y = dpp<0x114>(x); if (lt >= 4) x += y; }  // row_shr 4
+  if (T >= 16) { const uint32_t y = dpp<0x118>(x); if (lt >= 8) x += y; } // row_shr 8
+  if (T >= 32) x += dpp<0x142, 0xA>(x);  // rows 1 and 3 add lane 15 of rows 0 and 2
+  if (T >= 64) x += dpp<0x143, 0xC>(x);  // rows 2 and 3 add lane 31
+  return x;
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
   // Salmon et al., SC'11: ten rounds, multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key bumps.

@@ -971,11 +971,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_count(const Counters* __restri
     if (s1.x >= s0.x && s1.y >= s0.y && s1.x <= np && s1.y <= nc)  // else k_merge reports it
       count = (uint32_t)((int32_t)(s1.x - s0.x) + tdelta[tile]);
   }
-  uint32_t incl = count;
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t x = __shfl_up(incl, o);
-    if (lane >= (uint32_t)o) incl += x;
-  }
+  const uint32_t incl = team_scan(count, kWave, lane);
   if (lane == kWave - 1) s_w[wave] = incl;
   __syncthreads();
   uint32_t wpre = 0;
@@ -1081,7 +1077,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   const uint32_t ntiles = (np + nc + kMergeTile - 1) / kMergeTile;
   const uint32_t wave = threadIdx.x / kWave, lane = __lane_id();
   const KeyLayout kl = A.kl;
-  uint64_t st_keys = 0, st_w = 0;  // parents and their walkers (thread 0), added once at the end
+  uint64_t st_keys = 0;  // parents (thread 0), added once at the end
+  uint64_t wsum = 0;     // walkers of the parents this thread's merge ranges held, over all tiles
   const bool draw = A.tab_next.valid();
   uint32_t nq = 0;  // queued outputs (block-uniform)
   // Appends the queue to the list of step s+1's parents (one atomic per flush).
@@ -1164,7 +1161,6 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     const uint64_t* const s_ck = s_pk + pn;
     const int2* const s_cv = s_pv + pn;
     if (threadIdx.x == 0) st_keys += pn;
-    uint64_t wsum = 0;  // walker sum of the parents this thread's merge range holds
 
     // Per-thread ranges of the local merge, cut only at run ends.
     auto KA = [&](uint32_t x) { return s_pk[x]; };
@@ -1240,40 +1236,55 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
       atomicMin(&cnt->err_step, A.step);
     }
     // Block exclusive scan of the counts: inclusive scan within each wave, then wave totals.
-    uint32_t incl = count;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t x = __shfl_up(incl, o);
-      if (lane >= (uint32_t)o) incl += x;
-    }
+    const uint32_t incl = team_scan(count, kWave, lane);
     if (lane == kWave - 1) s_scan[wave] = incl;
-    for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
-    if (lane == 0) s_ws[wave] = wsum;
     __syncthreads();  // also: every thread has finished reading the tile's LDS data
-    // the next tile's loads, in flight during the rest of this one
-    if (nok) issue(npa, npn, nca, ncn);
-    if (threadIdx.x == 0)
-      for (int w = 0; w < kWaves; ++w) st_w += s_ws[w];
     uint32_t wpre = 0, agg = 0;
     for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
       const uint32_t v = s_scan[x];
       wpre += x < wave ? v : 0u;
       agg += v;
     }
-    const uint32_t excl = wpre + incl - count;
-    // The tile's records to the new store at its offset (the count pass must agree with the
-    // merge; a disagreement is an internal error, reported rather than written); with the next
-    // step's tables, Philox once per record and the ones whose combs can fire are queued.
-    uint32_t nact = 0;
-    bool act[kMergeIpt];
+    // (the count pass must agree with the merge; a disagreement is an internal error, reported
+    // rather than written)
     if (agg != nout) {
       report();
-      count = 0;
+      agg = 0;
     }
+    // The tile's records go through LDS once more, in output order, so that each store below
+    // writes contiguous lanes (a thread's own records would leave gaps of its neighbours' counts
+    // between lanes).  At most kMergeTile of them: a thread's range holds at most kMergeIpt keys.
+    {
+      const uint32_t excl = wpre + incl - count;
+#pragma unroll
+      for (int u = 0; u < kMergeIpt; ++u)
+        if ((uint32_t)u < count && agg) {
+          s_pk[excl + u] = rk[u];
+          s_pv[excl + u] = rv[u];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMergeIpt; ++u) {
+      const uint32_t x = threadIdx.x + (uint32_t)u * kBlock;
+      if (x < agg) {
+        rk[u] = s_pk[x];
+        rv[u] = s_pv[x];
+      }
+    }
+    __syncthreads();  // the staged records are in registers
+    // the next tile's loads, in flight during the rest of this one
+    if (nok) issue(npa, npn, nca, ncn);
+    // The tile's records to the new store at its offset, record x of the tile by thread
+    // x mod kBlock; with the next step's tables, Philox once per record and the ones whose combs
+    // can fire are queued.
+    uint32_t nact = 0;
+    bool act[kMergeIpt];
 #pragma unroll
     for (int u = 0; u < kMergeIpt; ++u) {
       act[u] = false;
-      if ((uint32_t)u < count) {
-        const uint64_t o = gbase + excl + u;
+      if (threadIdx.x + (uint32_t)u * kBlock < agg) {
+        const uint64_t o = gbase + threadIdx.x + (uint32_t)u * kBlock;
         if (o < A.cap_store) {
           A.ok[o] = rk[u];
           A.ov[o] = rv[u];
@@ -1298,13 +1309,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     if (draw) {
       // block exclusive scan of the queued counts, then the records into the queue (or, when
       // more than it holds, straight into the list)
-      uint32_t ai = nact;
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t x = __shfl_up(ai, o);
-        if (lane >= (uint32_t)o) ai += x;
-      }
-      __syncthreads();  // s_scan is free again
-      if (lane == kWave - 1) s_scan[wave] = ai;
+      const uint32_t ai = team_scan(nact, kWave, lane);
+      if (lane == kWave - 1) s_scan[wave] = ai;  // (read for the counts two barriers ago)
       __syncthreads();
       uint32_t apre = 0, atot = 0;
       for (uint32_t x = 0; x < (uint32_t)kWaves; ++x) {
@@ -1346,7 +1352,13 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   }
   __syncthreads();
   if (draw && nq > 0) flush_queue();
+  // the block's walker sum: per wave, then thread 0 over the waves
+  for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+  if (lane == 0) s_ws[wave] = wsum;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    uint64_t st_w = 0;
+    for (int w = 0; w < kWaves; ++w) st_w += s_ws[w];
     if (st_keys) atomicAdd((unsigned long long*)&cnt->key_steps, (unsigned long long)st_keys);
     if (st_w) atomicAdd((unsigned long long*)&cnt->walker_steps, (unsigned long long)st_w);
   }

@@ -131,14 +131,18 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // three-way exclusive or in one instruction (bitop3 truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
     c2 = n2;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
+    // The key is wave-uniform (the run's seed): each round's key is bumped in scalar registers
+    // as the rounds go, rather than all twenty precomputed and held (or spilled) for the loop.
+    asm volatile("" : "+s"(k0), "+s"(k1));
   }
   out[0] = c0;
   out[1] = c1;

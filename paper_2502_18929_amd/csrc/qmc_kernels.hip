@@ -1056,9 +1056,10 @@ struct MergeArgs {
 // a wave instruction moves 256 contiguous bytes and no registers hold the data, so all of a
 // tile's loads are in flight at once), are merged with int64 sums per key, and the nonzero sums
 // are written to the new store at the tile's offset.  The tiles are independent (their offsets
-// come from k_merge_count and k_merge_scan): block b takes tiles b, b + G, b + 2G, ...  As soon as
-// a tile's merge has read its LDS data, the loads of the block's next tile are issued, so they
-// are in flight while this tile's records are written and its next-step draws are made.
+// come from k_merge_count and k_merge_scan): block b of G takes the contiguous tiles
+// [b T / G, (b + 1) T / G).  As soon as a tile's records are in registers, the loads of the
+// block's next tile are issued, so they are in flight while this tile's records are written and
+// its next-step draws are made.
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
   constexpr int CAP = kMergeCap;
   __shared__ uint64_t s_pk[CAP];   // parents, then the tile's records behind them
@@ -1133,25 +1134,29 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     }
   };
 
+  // this block's tiles: a contiguous run (a run crosses few replica boundaries, each of which
+  // costs its threads a table-header load)
+  const uint32_t t_end = (uint32_t)(((uint64_t)(blockIdx.x + 1) * ntiles) / gridDim.x);
   uint32_t pa = 0, pn = 0, ca = 0, cn = 0;
   bool ok = false;
-  if (blockIdx.x < ntiles) {
-    ok = geometry(A.splits[blockIdx.x], A.splits[blockIdx.x + 1], pa, pn, ca, cn);
+  uint32_t tile = (uint32_t)(((uint64_t)blockIdx.x * ntiles) / gridDim.x);
+  if (tile < t_end) {
+    ok = geometry(A.splits[tile], A.splits[tile + 1], pa, pn, ca, cn);
     if (ok) issue(pa, pn, ca, cn);
   }
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint32_t next = tile + gridDim.x;
+  for (; tile < t_end; ++tile) {
+    const uint32_t next = tile + 1;
     const uint64_t ti = A.tinfo[tile];
     const uint64_t gbase = A.boff[tile / kCountTiles] + (uint32_t)ti, nout = ti >> 32;
     uint2 n0 = make_uint2(0, 0), n1 = make_uint2(0, 0);
-    if (next < ntiles) {
+    if (next < t_end) {
       n0 = A.splits[next];
       n1 = A.splits[next + 1];
     }
     __builtin_amdgcn_s_waitcnt(0);  // this tile's LDS data (and the loads above)
     __syncthreads();
     uint32_t npa = 0, npn = 0, nca = 0, ncn = 0;
-    const bool nok = next < ntiles && geometry(n0, n1, npa, npn, nca, ncn);
+    const bool nok = next < t_end && geometry(n0, n1, npa, npn, nca, ncn);
     if (!ok) {
       report();
       if (nok) issue(npa, npn, nca, ncn);
@@ -1184,24 +1189,44 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
 
     // One pass: the annihilated records of this thread's range, held in registers.  A range is
     // kMergeIpt merged items moved to run ends, and only the run of its last key can extend it,
-    // so it holds at most kMergeIpt distinct keys.
+    // so it holds at most kMergeIpt distinct keys; its parents lie between merge-path splits
+    // kMergeIpt diagonals apart, so there are at most kMergeIpt of them, read up front.
     uint64_t rk[kMergeIpt];
     int2 rv[kMergeIpt];
     uint32_t count = 0;
     bool overflow = false, too_many = false;
-    {
+    if (i1 - i0 > (uint32_t)kMergeIpt) {
+      too_many = true;  // cannot happen (see above)
+    } else if (j0 == j1) {
+      // no records in the range (the usual case once records are sparse): its parents are its
+      // output, as the count pass has it
+      count = i1 - i0;
+#pragma unroll
+      for (int u = 0; u < kMergeIpt; ++u) {
+        const uint32_t x = i0 + u < (uint32_t)CAP ? i0 + (uint32_t)u : (uint32_t)CAP - 1;
+        rk[u] = s_pk[x];
+        rv[u] = s_pv[x];
+        if ((uint32_t)u < count) wsum += uabs64(rv[u].x) + uabs64(rv[u].y);
+      }
+    } else {
+      uint64_t qk[kMergeIpt];  // the range's parent keys
+#pragma unroll
+      for (int u = 0; u < kMergeIpt; ++u)
+        qk[u] = s_pk[i0 + u < (uint32_t)CAP ? i0 + (uint32_t)u : (uint32_t)CAP - 1];
       uint32_t i = i0, j = j0;
       while (i < i1 || j < j1) {
         uint64_t k;
         int64_t re = 0, im = 0;
         bool hp = false;
-        if (j >= j1 || (i < i1 && s_pk[i] <= kl.ckey(s_ck[j]))) {
-          k = s_pk[i];
+        if (j >= j1 || (i < i1 && qk[0] <= kl.ckey(s_ck[j]))) {
+          k = qk[0];
           re = s_pv[i].x;
           im = s_pv[i].y;
           wsum += uabs64(re) + uabs64(im);
           hp = true;
           ++i;
+#pragma unroll
+          for (int u = 0; u + 1 < kMergeIpt; ++u) qk[u] = qk[u + 1];
         } else {
           k = kl.ckey(s_ck[j]);
         }

@@ -169,15 +169,11 @@ __device__ __forceinline__ int64_t comb_step(uint64_t& r, int64_t x) {
 // s * q + U < 2^32 (s = |a| + |b|, q bounds the column coefficients) means every output of a
 // comb started at U is zero: the comb only emits when its running sum crosses 2^32.
 __device__ __forceinline__ bool comb_all_zero(uint64_t s, uint64_t q, uint32_t U) {
+  // the usual case: s q + U in one 32 x 32 + 32 -> 64 multiply-add (zero s or q give U < 2^32)
+  if (((s | q) >> 32) == 0) return (((uint64_t)(uint32_t)s * (uint32_t)q + U) >> 32) == 0;
   if (q == 0 || s == 0) return true;
-  uint64_t p;
-  if (((s | q) >> 32) == 0) {
-    p = (uint64_t)(uint32_t)s * (uint32_t)q;  // the usual case: one 32 x 32 -> 64 product
-  } else {
-    if (__umul64hi(s, q) != 0) return false;
-    p = s * q;
-  }
-  return p < (1ull << 32) - (uint64_t)U;
+  if (__umul64hi(s, q) != 0) return false;
+  return s * q < (1ull << 32) - (uint64_t)U;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

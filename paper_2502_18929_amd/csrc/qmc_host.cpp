@@ -67,7 +67,7 @@ struct QTerm {
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
-      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, total;
+      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, thist, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -140,6 +140,8 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.mlp = take(kMlpBytes + kDeepBytes);
   L.small_fail = take(8);
   L.small_stats = take((size_t)kSmallBatches * c.n_replicas * kSmallStats * 8);
+  // per-tile digit counts of the step sort, two buffers (a pass reads one, counts into the other)
+  L.thist = take((size_t)2 * qmck_step_sort_hist_words(C) * 4);
   L.total = o;
   return true;
 }
@@ -221,6 +223,9 @@ struct qmc_ctx {
   qmc::Counters* counters() const { return at<qmc::Counters>(L.counters); }
   uint32_t* ghist(uint32_t parity) const {
     return at<uint32_t>(L.ghist) + (size_t)parity * qmc::kMaxPasses * qmc::kRadixBins;
+  }
+  uint32_t* thist(uint32_t which) const {
+    return at<uint32_t>(L.thist) + (size_t)which * qmck_step_sort_hist_words(L.cap_child);
   }
 };
 
@@ -1058,9 +1063,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
       const uint32_t* toffB_next = more && c->integrator == 1 ? dB + (k + 1) : nullptr;
       const uint32_t csel = st & 1;
       ENQ(mark(1, k, 0));
-      ENQ(qmck_sort(st_q, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
-                          c->ghist(csel), c->at<uint64_t>(c->L.sort_status), st, cb,
-                          c->L.cap_child, c->sort_ipt));
+      ENQ(qmck_sort_step(st_q, c->ck(0), c->cv(0), c->ck(1), c->cv(1), dcnt, csel, passes,
+                         c->ghist(csel), c->thist(0), c->thist(1), st, cb, c->L.cap_child));
       ENQ(mark(1, k, 1));
       const uint32_t cf = cb ^ (passes & 1);  // sorted children
       // With the Euler step and the comb, the merge also queues the records of N(st + 1) whose

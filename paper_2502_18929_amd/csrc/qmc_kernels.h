@@ -62,6 +62,13 @@ int qmck_digit_hist(hipStream_t st, const uint64_t* keys, void* counters, uint32
 int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
               uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint64_t* sort_status,
               uint32_t step, uint32_t src, uint64_t max_items, uint32_t ipt);
+// The same sort of one step's records without look-back (per-tile digit counts, a scan over
+// tiles and a scatter per pass); hist_a and hist_b hold qmck_step_sort_hist_words(max_items)
+// words each and need no initial contents.  The result lands in pair src ^ (passes & 1).
+uint64_t qmck_step_sort_hist_words(uint64_t max_items);
+int qmck_sort_step(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
+                   uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint32_t* hist_a,
+                   uint32_t* hist_b, uint32_t step, uint32_t src, uint64_t max_items);
 // Records per thread of a sort tile that qmck_sort supports (8, 12, 16, 24): nonzero if ok.
 int qmck_sort_tile_ok(uint32_t ipt);
 // n synthetic records (keys masked to `mask`, values (1, 0)) for timing the sort.

@@ -659,6 +659,54 @@ __device__ uint32_t merge_path_wave(const KA& A, uint32_t na, const KB& B, uint3
   return lo + (uint32_t)__popcll(__ballot(t));
 }
 
+// Stable ranks of one wave's slice of a sort tile: record k of the lane is
+// kin[tbase + k * 64 + lane] (absent past n); rk[k] counts the slice's earlier records with the
+// same digit, and wcnt[d] (this wave's row of LDS counters, zero on entry) ends as the slice's
+// count of digit d.
+template <int IPT>
+__device__ __forceinline__ void rank_slice(const uint64_t* __restrict__ kin,
+                                           const int2* __restrict__ vin, uint64_t n,
+                                           uint64_t tbase, uint32_t shift, uint32_t* wcnt,
+                                           uint64_t (&key)[IPT], int2 (&val)[IPT],
+                                           uint32_t (&rk)[IPT]) {
+  const uint32_t lane = __lane_id();
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const uint64_t i = tbase + (uint64_t)k * kWave + lane;
+    const bool v = i < n;
+    key[k] = v ? kin[i] : 0;
+    val[k] = v ? vin[i] : make_int2(0, 0);
+    const uint32_t d = digit_of(key[k], shift);
+    const uint64_t peers = match_digit(d, __ballot(v));
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    uint32_t seen = 0;
+    if (v) seen = wcnt[d];
+    rk[k] = seen + before;
+    wave_lds_fence();
+    if (v && before == 0) wcnt[d] = seen + (uint32_t)__popcll(peers);
+    wave_lds_fence();
+  }
+}
+
+// Per digit of thread tid (digits tid * DPT ...): the waves' counts become exclusive prefixes
+// over the waves, and tot[i] the tile's count.
+template <int DPT>
+__device__ __forceinline__ void wave_digit_prefix(uint32_t (*wcnt)[kRadixBins], uint32_t tid,
+                                                  uint32_t (&tot)[DPT]) {
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const uint32_t d = tid * DPT + i;
+    uint32_t run = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wcnt[w][d];
+      wcnt[w][d] = run;
+      run += c;
+    }
+    tot[i] = run;
+  }
+}
+
 template <int IPT>
 __global__ __launch_bounds__(kBlock) void k_onesweep(
     const uint64_t* __restrict__ kin, const int2* __restrict__ vin, uint64_t* __restrict__ kout,
@@ -679,6 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
   const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = __lane_id();
   const uint32_t* gh = ghist + pass * kRadixBins;
   uint32_t* ticket = &cnt->sort_ticket[nsel][pass];
+  (void)lane;
 
   // First ticket before the prologue, so blocks without a tile leave at once.
   if (tid == 0) s_tile = atomicAdd(ticket, 1u);
@@ -707,7 +756,6 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
       run += loc[i];
     }
   }
-  const uint64_t lt = lanemask_lt();
   bool first_tile = true;
 
   while (true) {
@@ -723,36 +771,11 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
     uint64_t key[IPT];
     int2 val[IPT];
     uint32_t rk[IPT];
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      const uint64_t i = tbase + (uint64_t)k * kWave + lane;
-      const bool v = i < n;
-      key[k] = v ? kin[i] : 0;
-      val[k] = v ? vin[i] : make_int2(0, 0);
-      const uint32_t d = digit_of(key[k], shift);
-      const uint64_t peers = match_digit(d, __ballot(v));
-      const uint32_t before = (uint32_t)__popcll(peers & lt);
-      uint32_t seen = 0;
-      if (v) seen = s_wcnt[wave][d];
-      rk[k] = seen + before;
-      wave_lds_fence();
-      if (v && before == 0) s_wcnt[wave][d] = seen + (uint32_t)__popcll(peers);
-      wave_lds_fence();
-    }
+    rank_slice<IPT>(kin, vin, n, tbase, shift, s_wcnt[wave], key, val, rk);
     __syncthreads();
     // Per digit: exclusive prefix over waves, and the tile total.
     uint32_t tot[DPT];
-#pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-      const uint32_t d = tid * DPT + i;
-      uint32_t run = 0;
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = s_wcnt[w][d];
-        s_wcnt[w][d] = run;
-        run += c;
-      }
-      tot[i] = run;
-    }
+    wave_digit_prefix<DPT>(s_wcnt, tid, tot);
     // Publish and look back (all DPT digits of a thread advance through predecessors together).
     uint64_t* row = status + (uint64_t)tile * kRadixBins + tid * DPT;
 #pragma unroll
@@ -811,6 +834,152 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
           vout[pos] = val[k];
         } else {
           atomicOr(&cnt->err, kErrLookback);  // inconsistent digit histogram: refuse the write
+          atomicMin(&cnt->err_step, step);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Step sort without look-back.  A pass over tiles of kStepSortTile records needs, per tile and
+// digit, the number of the pass's records with that digit in earlier tiles.  k_tile_hist counts
+// the first pass's digits per tile; k_sort_scan turns a pass's per-tile counts into per-tile
+// offsets (digit base plus the earlier tiles' counts, one thread per digit and segment of
+// tiles) and clears the next pass's counts; k_sort_scatter ranks each tile in LDS, writes its
+// records at those offsets and counts the next pass's digits per output tile with one atomic
+// per record.  No tile waits for another, so a pass costs three short dependent launches
+// instead of a look-back chain through every tile.
+// ---------------------------------------------------------------------------------------------
+constexpr int kStepSortIpt = 8;
+constexpr int kStepSortTile = kBlock * kStepSortIpt;
+constexpr int kScanSegs = 16;  // tile segments per digit in k_sort_scan (one wave each)
+constexpr int kScanDigits = kWave;  // digits per block of k_sort_scan (one per lane)
+
+__global__ __launch_bounds__(kBlock) void k_tile_hist(const uint64_t* __restrict__ keys,
+                                                      const Counters* __restrict__ cnt,
+                                                      uint32_t nsel, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[kRadixBins];
+  if (cnt->err) return;
+  const uint64_t n = cnt->n_child[nsel];
+  const uint32_t ntiles = (uint32_t)((n + kStepSortTile - 1) / kStepSortTile);
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint32_t d = threadIdx.x; d < (uint32_t)kRadixBins; d += kBlock) s_h[d] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kStepSortIpt; ++k) {
+      const uint64_t i = (uint64_t)tile * kStepSortTile + (uint64_t)k * kBlock + threadIdx.x;
+      if (i < n) atomicAdd(&s_h[digit_of(keys[i], 0)], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = hist + (uint64_t)tile * kRadixBins;
+    for (uint32_t d = threadIdx.x; d < (uint32_t)kRadixBins; d += kBlock) row[d] = s_h[d];
+    __syncthreads();
+  }
+}
+
+// Block b: digits [64 b, 64 b + 64) (lane), wave w: tiles [w T / 16, (w + 1) T / 16).  In place,
+// hist[t][d] becomes base(d) + sum over t' < t of hist[t'][d], where base(d) is the count of
+// smaller digits in the pass (ghist); with next set, next[t][d] = 0 for every tile t.
+__global__ __launch_bounds__(kScanSegs * kScanDigits) void k_sort_scan(
+    const Counters* __restrict__ cnt, uint32_t nsel, const uint32_t* __restrict__ ghist,
+    uint32_t* __restrict__ hist, uint32_t* __restrict__ next) {
+  constexpr int kThreads = kScanSegs * kScanDigits;
+  constexpr int kBatch = 16;  // loads in flight per thread
+  __shared__ uint32_t s_seg[kScanSegs][kScanDigits];
+  __shared__ uint32_t s_below[kScanSegs];
+  if (cnt->err) return;
+  const uint64_t n = cnt->n_child[nsel];
+  const uint32_t ntiles = (uint32_t)((n + kStepSortTile - 1) / kStepSortTile);
+  const uint32_t seg = threadIdx.x / kScanDigits, lane = __lane_id();
+  const uint32_t d0 = blockIdx.x * kScanDigits, d = d0 + lane;
+  // base(d): the pass's records with digits below d0, then the lower lanes of this block
+  uint32_t below = 0;
+  for (uint32_t x = threadIdx.x; x < d0; x += kThreads) below += ghist[x];
+  below = team_sum(below, kWave);
+  if (lane == 0) s_below[seg] = below;
+  const uint32_t mine = ghist[d];
+  const uint32_t base_lane = team_scan(mine, kWave, lane) - mine;
+  // this segment's tiles and their column sum
+  const uint32_t t0 = (uint32_t)(((uint64_t)seg * ntiles) / kScanSegs);
+  const uint32_t t1 = (uint32_t)(((uint64_t)(seg + 1) * ntiles) / kScanSegs);
+  uint32_t sum = 0;
+  for (uint32_t t = t0; t < t1; t += kBatch) {
+    uint32_t h[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      h[u] = t + u < t1 ? hist[(uint64_t)(t + u) * kRadixBins + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) sum += h[u];
+  }
+  s_seg[seg][lane] = sum;
+  __syncthreads();
+  uint32_t run = base_lane;
+  for (int w = 0; w < kScanSegs; ++w) run += s_below[w];
+  for (uint32_t w = 0; w < seg; ++w) run += s_seg[w][lane];
+  for (uint32_t t = t0; t < t1; t += kBatch) {
+    uint32_t h[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      h[u] = t + u < t1 ? hist[(uint64_t)(t + u) * kRadixBins + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (t + u < t1) {
+        hist[(uint64_t)(t + u) * kRadixBins + d] = run;
+        if (next) next[(uint64_t)(t + u) * kRadixBins + d] = 0;
+      }
+      run += h[u];
+    }
+  }
+}
+
+// One pass: tile t's records ranked in LDS and written at off[t][digit] + rank; with next set,
+// next[output tile][digit of the next pass] counts every record written.
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(
+    const uint64_t* __restrict__ kin, const int2* __restrict__ vin, uint64_t* __restrict__ kout,
+    int2* __restrict__ vout, Counters* __restrict__ cnt, uint32_t nsel, uint32_t shift,
+    const uint32_t* __restrict__ off, uint32_t* __restrict__ next, uint32_t next_shift,
+    uint32_t step) {
+  constexpr int IPT = kStepSortIpt;
+  constexpr int DPT = kRadixBins / kBlock;
+  __shared__ uint32_t s_wcnt[kWaves][kRadixBins];
+  __shared__ uint32_t s_pref[kRadixBins];
+  if (cnt->err) return;
+  const uint64_t n = cnt->n_child[nsel];
+  const uint32_t ntiles = (uint32_t)((n + kStepSortTile - 1) / kStepSortTile);
+  const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = __lane_id();
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+    for (int i = 0; i < DPT; ++i)
+      for (int w = 0; w < kWaves; ++w) s_wcnt[w][tid * DPT + i] = 0;
+    __syncthreads();
+    const uint64_t tbase = (uint64_t)tile * kStepSortTile + (uint64_t)wave * (IPT * kWave);
+    uint64_t key[IPT];
+    int2 val[IPT];
+    uint32_t rk[IPT];
+    rank_slice<IPT>(kin, vin, n, tbase, shift, s_wcnt[wave], key, val, rk);
+    __syncthreads();
+    uint32_t tot[DPT];
+    wave_digit_prefix<DPT>(s_wcnt, tid, tot);
+    const uint32_t* orow = off + (uint64_t)tile * kRadixBins + tid * DPT;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) s_pref[tid * DPT + i] = orow[i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const uint64_t i = tbase + (uint64_t)k * kWave + lane;
+      if (i < n) {
+        const uint32_t d = digit_of(key[k], shift);
+        const uint64_t pos = (uint64_t)s_pref[d] + s_wcnt[wave][d] + rk[k];
+        if (pos < n) {
+          kout[pos] = key[k];
+          vout[pos] = val[k];
+          if (next)
+            atomicAdd(&next[(pos / kStepSortTile) * kRadixBins + digit_of(key[k], next_shift)],
+                      1u);
+        } else {
+          atomicOr(&cnt->err, kErrLookback);  // inconsistent digit counts: refuse the write
           atomicMin(&cnt->err_step, step);
         }
       }
@@ -1611,26 +1780,31 @@ __global__ __launch_bounds__(kBlock) void k_lookup(const uint64_t* __restrict__ 
   out[2 * t + 1] = b;
 }
 
-// Workgroups of k_merge that are resident on the whole device at once (at most kMergeBlocks): its
-// tiles are strided over the grid, so a workgroup that has to wait for a free slot would run all
-// of its tiles after the others finished theirs.  Taken once per device from the occupancy the
-// compiled kernel reaches (its LDS and registers).
-static uint32_t merge_blocks() {
-  constexpr int kDevices = 64;
-  static uint32_t cached[kDevices] = {};
+// Workgroups of a kernel with kBlock threads that are resident on the whole device at once (at
+// most cap): kernels whose tiles are strided over the grid launch no more, since a workgroup that
+// had to wait for a free slot would run all of its tiles after the others finished theirs.
+// Taken once per device and slot from the occupancy the compiled kernel reaches (its LDS and
+// registers).
+template <class K>
+static uint32_t resident_blocks(K kernel, int slot, uint32_t cap) {
+  constexpr int kDevices = 64, kSlots = 4;
+  static uint32_t cached[kSlots][kDevices] = {};
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return 256;
-  if (cached[dev] == 0) {
+  if (slot < 0 || slot >= kSlots || hipGetDevice(&dev) != hipSuccess || dev < 0 ||
+      dev >= kDevices)
+    return 256;
+  if (cached[slot][dev] == 0) {
     int per_cu = 0, cus = 0;
     uint32_t g = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_merge, kBlock, 0) == hipSuccess &&
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         per_cu > 0 && cus > 0)
       g = (uint32_t)per_cu * (uint32_t)cus;
-    cached[dev] = g < (uint32_t)kMergeBlocks ? g : (uint32_t)kMergeBlocks;
+    cached[slot][dev] = g < cap ? g : cap;
   }
-  return cached[dev];
+  return cached[slot][dev];
 }
+static uint32_t merge_blocks() { return resident_blocks(k_merge, 0, (uint32_t)kMergeBlocks); }
 
 static inline uint32_t grid_for(uint64_t n, uint32_t cap_blocks) {
   uint64_t g = (n + kBlock - 1) / kBlock;
@@ -1715,6 +1889,36 @@ static void sort_passes(hipStream_t st, uint64_t* const* kb, int2* const* vb, vo
                        sort_epoch(step, p), step);
     s ^= 1;
   }
+}
+
+uint64_t qmck_step_sort_hist_words(uint64_t max_items) {
+  return ((max_items + kStepSortTile - 1) / kStepSortTile + 1) * (uint64_t)kRadixBins;
+}
+
+int qmck_sort_step(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,
+                   uint32_t nsel, uint32_t passes, const uint32_t* ghist, uint32_t* hist_a,
+                   uint32_t* hist_b, uint32_t step, uint32_t src, uint64_t max_items) {
+  uint64_t* kb[2] = {k0, k1};
+  int2* vb[2] = {v0, v1};
+  const uint64_t max_tiles = (max_items + kStepSortTile - 1) / kStepSortTile;
+  const uint32_t cap = (uint32_t)(max_tiles ? (max_tiles < 4096 ? max_tiles : 4096) : 1);
+  const uint32_t gh = std::min(resident_blocks(k_tile_hist, 1, 4096), cap);
+  const uint32_t gs = std::min(resident_blocks(k_sort_scatter, 2, 4096), cap);
+  Counters* cnt = (Counters*)counters;
+  hipLaunchKernelGGL(k_tile_hist, dim3(gh), dim3(kBlock), 0, st, kb[src], cnt, nsel, hist_a);
+  uint32_t* h[2] = {hist_a, hist_b};
+  uint32_t s = src;
+  for (uint32_t p = 0; p < passes; ++p) {
+    uint32_t* nx = p + 1 < passes ? h[(p + 1) & 1] : nullptr;
+    hipLaunchKernelGGL(k_sort_scan, dim3(kRadixBins / kScanDigits),
+                       dim3(kScanSegs * kScanDigits), 0, st, cnt, nsel,
+                       ghist + (size_t)p * kRadixBins, h[p & 1], nx);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(gs), dim3(kBlock), 0, st, kb[s], vb[s], kb[s ^ 1],
+                       vb[s ^ 1], cnt, nsel, p * kRadixBits, h[p & 1], nx,
+                       (p + 1) * kRadixBits, step);
+    s ^= 1;
+  }
+  return (int)hipGetLastError();
 }
 
 int qmck_sort(hipStream_t st, uint64_t* k0, int2* v0, uint64_t* k1, int2* v1, void* counters,

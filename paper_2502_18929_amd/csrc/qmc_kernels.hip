@@ -524,12 +524,17 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
   // table bounds of the segment of the last parent seen (parents are sorted by segment)
   uint32_t h_seg = ~0u;
   uint64_t h_qoff = 0, h_qdiag = 0;
-  // Rounds of kSpawnRound parents: all of a round's loads in flight at once (LDS-direct dword
-  // loads, no registers), then kBlock parents at a time from LDS.
-  const uint64_t stride = (uint64_t)gridDim.x * kSpawnRound;
-  for (uint64_t rbase = (uint64_t)blockIdx.x * kSpawnRound; rbase < np; rbase += stride) {
-    const uint32_t rn = (uint32_t)(np - rbase < (uint64_t)kSpawnRound ? np - rbase
-                                                                      : (uint64_t)kSpawnRound);
+  // Rounds of R parents: all of a round's loads in flight at once (LDS-direct dword loads, no
+  // registers), then kBlock parents at a time from LDS.  R is kSpawnRound for long lists and
+  // shrinks (to kBlock) when the list would leave workgroups idle: a short list of parents that
+  // all emit (the merge's queue) is spread over the grid rather than over a few workgroups.
+  uint64_t R = (np + gridDim.x - 1) / gridDim.x;
+  R = (R + kBlock - 1) / kBlock * kBlock;
+  if (R > (uint64_t)kSpawnRound) R = kSpawnRound;
+  if (R < (uint64_t)kBlock) R = kBlock;
+  const uint64_t stride = (uint64_t)gridDim.x * R;
+  for (uint64_t rbase = (uint64_t)blockIdx.x * R; rbase < np; rbase += stride) {
+    const uint32_t rn = (uint32_t)(np - rbase < R ? np - rbase : R);
     {
       const uint32_t* ks = reinterpret_cast<const uint32_t*>(pk + rbase);
       const uint32_t* vs = reinterpret_cast<const uint32_t*>(pv + rbase);

@@ -1364,68 +1364,85 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     // One pass: the annihilated records of this thread's range, held in registers.  A range is
     // kMergeIpt merged items moved to run ends, and only the run of its last key can extend it,
     // so it holds at most kMergeIpt distinct keys; its parents lie between merge-path splits
-    // kMergeIpt diagonals apart, so there are at most kMergeIpt of them, read up front.
+    // kMergeIpt diagonals apart, so there are at most kMergeIpt of them.  The slots start as the
+    // range's parents in key order; each run of equal-key records then adds its kept sum to its
+    // key's parent or, with no parent and a nonzero sum, is inserted in key order.  Slots whose
+    // sum is zero drop out of `live` (bit u: slot u is an output).  With records sparse, most
+    // ranges hold none and their parents pass straight through.
     uint64_t rk[kMergeIpt];
     int2 rv[kMergeIpt];
-    uint32_t count = 0;
+    uint32_t live = 0;
     bool overflow = false, too_many = false;
     if (i1 - i0 > (uint32_t)kMergeIpt) {
       too_many = true;  // cannot happen (see above)
-    } else if (j0 == j1) {
-      // no records in the range (the usual case once records are sparse): its parents are its
-      // output, as the count pass has it
-      count = i1 - i0;
+    } else {
+      uint32_t used = i1 - i0;  // slots in use, in key order
 #pragma unroll
       for (int u = 0; u < kMergeIpt; ++u) {
         const uint32_t x = i0 + u < (uint32_t)CAP ? i0 + (uint32_t)u : (uint32_t)CAP - 1;
         rk[u] = s_pk[x];
         rv[u] = s_pv[x];
-        if ((uint32_t)u < count) wsum += uabs64(rv[u].x) + uabs64(rv[u].y);
+        if ((uint32_t)u < used) wsum += uabs64(rv[u].x) + uabs64(rv[u].y);
       }
-    } else {
-      uint64_t qk[kMergeIpt];  // the range's parent keys
+      live = (1u << used) - 1u;
+      uint32_t j = j0;
+      while (j < j1) {
+        const uint64_t key = kl.ckey(s_ck[j]);
+        // the key's parent among the slots (a record run never meets a key inserted by an
+        // earlier run: runs have distinct keys), and the slots below the key
+        uint32_t at = (uint32_t)kMergeIpt, below = 0;
 #pragma unroll
-      for (int u = 0; u < kMergeIpt; ++u)
-        qk[u] = s_pk[i0 + u < (uint32_t)CAP ? i0 + (uint32_t)u : (uint32_t)CAP - 1];
-      uint32_t i = i0, j = j0;
-      while (i < i1 || j < j1) {
-        uint64_t k;
+        for (int u = 0; u < kMergeIpt; ++u)
+          if ((uint32_t)u < used) {
+            if (rk[u] == key) at = (uint32_t)u;
+            below += rk[u] < key ? 1u : 0u;
+          }
+        const bool hp = at < (uint32_t)kMergeIpt;
         int64_t re = 0, im = 0;
-        bool hp = false;
-        if (j >= j1 || (i < i1 && qk[0] <= kl.ckey(s_ck[j]))) {
-          k = qk[0];
-          re = s_pv[i].x;
-          im = s_pv[i].y;
-          wsum += uabs64(re) + uabs64(im);
-          hp = true;
-          ++i;
-#pragma unroll
-          for (int u = 0; u + 1 < kMergeIpt; ++u) qk[u] = qk[u + 1];
-        } else {
-          k = kl.ckey(s_ck[j]);
-        }
-        while (j < j1 && kl.ckey(s_ck[j]) == k) {
-          if (kl.keep(s_ck[j], hp)) {
+        while (j < j1) {
+          const uint64_t r = s_ck[j];
+          if (kl.ckey(r) != key) break;
+          if (kl.keep(r, hp)) {
             re += s_cv[j].x;
             im += s_cv[j].y;
           }
           ++j;
         }
-        if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
-        if (re != 0 || im != 0) {
+        if (hp) {
 #pragma unroll
           for (int u = 0; u < kMergeIpt; ++u)
-            if ((uint32_t)u == count) {
-              rk[u] = k;
+            if ((uint32_t)u == at) {
+              re += rv[u].x;
+              im += rv[u].y;
               rv[u] = make_int2((int32_t)re, (int32_t)im);
             }
-          if (count < (uint32_t)kMergeIpt)
-            ++count;
-          else
-            too_many = true;
+          if (re == 0 && im == 0) live &= ~(1u << at);
+        } else if (re != 0 || im != 0) {
+          if (used == (uint32_t)kMergeIpt) {
+            too_many = true;  // cannot happen (see above); refuse rather than drop a record
+          } else {
+            // slots [below, used) move up by one, the new key takes slot `below`
+#pragma unroll
+            for (int u = kMergeIpt - 1; u > 0; --u)
+              if ((uint32_t)u > below && (uint32_t)u <= used) {
+                rk[u] = rk[u - 1];
+                rv[u] = rv[u - 1];
+              }
+#pragma unroll
+            for (int u = 0; u < kMergeIpt; ++u)
+              if ((uint32_t)u == below) {
+                rk[u] = key;
+                rv[u] = make_int2((int32_t)re, (int32_t)im);
+              }
+            const uint32_t lo = live & ((1u << below) - 1u);
+            live = lo | ((live & ~((1u << below) - 1u)) << 1) | (1u << below);
+            ++used;
+          }
         }
+        if (re < INT32_MIN || re > INT32_MAX || im < INT32_MIN || im > INT32_MAX) overflow = true;
       }
     }
+    const uint32_t count = (uint32_t)__popc(live);
     if (overflow) {
       atomicOr(&cnt->err, kErrOverflow);
       atomicMin(&cnt->err_step, A.step);
@@ -1453,13 +1470,14 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
     // The tile's records go through LDS once more, in output order, so that each store below
     // writes contiguous lanes (a thread's own records would leave gaps of its neighbours' counts
     // between lanes).  At most kMergeTile of them: a thread's range holds at most kMergeIpt keys.
-    {
-      const uint32_t excl = wpre + incl - count;
+    if (agg) {
+      uint32_t at = wpre + incl - count;
 #pragma unroll
       for (int u = 0; u < kMergeIpt; ++u)
-        if ((uint32_t)u < count && agg) {
-          s_pk[excl + u] = rk[u];
-          s_pv[excl + u] = rv[u];
+        if ((live >> u) & 1u) {
+          s_pk[at] = rk[u];
+          s_pv[at] = rv[u];
+          ++at;
         }
     }
     __syncthreads();

@@ -67,8 +67,8 @@ struct QTerm {
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
-      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, thist, total;
-  uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles;
+      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, thist, mpos, total;
+  uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles, status_words;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
   uint32_t incap;      // records per inbox
@@ -115,7 +115,8 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.sort_status = take(L.n_sort_status * 8);
   // merge tile counts and offsets (max_tiles words), the count blocks' sums and offsets (one
   // block per 256 tiles, plus the total), then the tiles' int32 count adjustments
-  L.status = take((L.max_tiles + (L.max_tiles + 255) / 256 + 1) * 8 + (L.max_tiles + 1) * 4);
+  L.status_words = (L.max_tiles + (L.max_tiles + 255) / 256 + 1) + (L.max_tiles + 2) / 2;
+  L.status = take(L.status_words * 8);
   L.splits = take((L.max_tiles + 1) * 8);
   L.tab = take(kTableArea + kPersistTableBytes);  // slack: the fused kernel reads 8 KB
   L.qshift = take((size_t)c.n_replicas * 2 * 8);  // first / only term, then the second AB2 term
@@ -142,6 +143,7 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   L.small_stats = take((size_t)kSmallBatches * c.n_replicas * kSmallStats * 8);
   // per-tile digit counts of the step sort, two buffers (a pass reads one, counts into the other)
   L.thist = take((size_t)2 * qmck_step_sort_hist_words(C) * 4);
+  L.mpos = take(C * 4);  // merged positions of one step's records
   L.total = o;
   return true;
 }
@@ -1036,8 +1038,11 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     const hipError_t e_ = (hipError_t)(x);       \
     if (e_ != hipSuccess) return e_;             \
   } while (0)
-    ENQ(qmck_batch_begin(st_q, dcnt, nullptr, 0, c->at<uint64_t>(c->L.sort_status),
-                         c->L.n_sort_status, c->ghist(0), 2 * qmc::kMaxPasses * qmc::kRadixBins));
+    // The merge class's tile counts and count adjustments start from zero (the adjustments are
+    // left zero by every completed step, not by one an error stopped).  The step sort uses no
+    // look-back words; the whole-store sort after a pulse clears its own.
+    ENQ(qmck_batch_begin(st_q, dcnt, c->at<uint64_t>(c->L.status), c->L.status_words, nullptr,
+                         0, c->ghist(0), 2 * qmc::kMaxPasses * qmc::kRadixBins));
     auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
       if (c->prof_class != cls) return hipSuccess;
       return hipEventRecord(c->prof_ev[2 * k + which], st_q);
@@ -1077,7 +1082,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
                      c->init_min, bk[(k + 1) % nb], bv[(k + 1) % nb], c->L.cap_store,
                      c->L.cap_store + c->L.cap_child, c->ghist(csel ^ 1), dtab,
                      queue ? toff_next : nullptr, c->Rc, qshA, c->cfg.seed, c->alt_k(1),
-                     c->alt_v(1)));
+                     c->alt_v(1), c->at<uint32_t>(c->L.mpos)));
       ENQ(mark(2, k, 1));
       cb = cf ^ 1;
       if (more) {

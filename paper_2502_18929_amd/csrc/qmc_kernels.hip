@@ -997,8 +997,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
 // Merge of parents (unique keys) with sorted children, split into tiles whose boundaries never
 // cut a key's run (parents win ties, so a run is [parent] children...).
 // ---------------------------------------------------------------------------------------------
-// Split points (one wave per tile boundary), plus the per-step resets of the counters the next
-// step's kernels use.
+// Split points (one thread per tile boundary, from the records' merged positions that
+// k_merge_delta wrote), plus the per-step resets of the counters the next step's kernels use.
 __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restrict__ pk,
                                                        const uint64_t* __restrict__ ckeys,
                                                        Counters* __restrict__ cnt, uint32_t cur,
@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
                                                        uint32_t max_tiles,
                                                        uint32_t* __restrict__ ghist_next,
                                                        uint32_t ish,
-                                                       int32_t* __restrict__ tdelta) {
+                                                       const uint32_t* __restrict__ mpos) {
   if (cnt->err) return;
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   // The next step's child counter, sort tickets and digit histograms were last used two steps
@@ -1024,23 +1024,23 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
   const uint32_t ntiles = (total + kMergeTile - 1) / kMergeTile;
   auto A = [&](uint32_t x) { return pk[x]; };
   auto B = [&](uint32_t x) { return ckeys[x] >> ish; };  // composite key of a routed record
-  // One thread per tile boundary: a binary search on the merge path (the upper levels of the
-  // searches are shared by neighbouring boundaries and stay in the caches), then the boundary
-  // moves past the records that continue the run of the last key before it.
+  // One thread per tile boundary: the records among the first d merged items are the ones whose
+  // merged position is below d (a binary search over the records' positions, a small array that
+  // stays in the caches, instead of one over the store), then the boundary moves past the
+  // records that continue the run of the last key before it.
   for (uint32_t t = gt; t <= ntiles && t <= max_tiles; t += gridDim.x * kBlock) {
     uint32_t d = t * kMergeTile;
     if (d > total) d = total;
-    // i = the number of parents among the first d merged items (parents first on equal keys)
-    uint32_t lo = d > nc ? d - nc : 0u, hi = d < np ? d : np;
+    uint32_t lo = 0, hi = nc;
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (A(mid) <= B(d - 1 - mid))
+      if (mpos[mid] < d)
         lo = mid + 1;
       else
         hi = mid;
     }
-    const uint32_t i = lo;
-    uint32_t j = d - i;
+    uint32_t j = lo;
+    const uint32_t i = d - j;
     if (d > 0 && d < total) {
       uint64_t last = 0;
       if (i > 0) last = A(i - 1);
@@ -1053,26 +1053,28 @@ __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restric
       while (j < jmax && B(j) <= last) ++j;
     }
     splits[t] = make_uint2(i, j);
-    tdelta[t] = 0;
   }
 }
 
 // Output count of every merge tile, from its records alone: each of the tile's parents survives
 // unless its records annihilate it, so the count is the parents, plus the record keys without a
 // parent whose sum is nonzero, minus the parents whose sum with their records is zero.
-// k_merge_delta: one thread per record; the one at the start of a key's run finds the run's tile
-// (split points) and the key's parent among the tile's parents (a key's parent and its records
-// always fall in one tile), sums the run, and adds +1 / -1 to tdelta[tile] (cleared by
-// k_merge_part).  k_merge_count: one thread per tile, count = parents + delta, and an exclusive
-// scan over the 256 tiles of each block: tinfo[tile] = (count << 32) | first output counted from
-// the block's first, bsum[b] = the block's outputs (k_merge_scan turns them into offsets).
+// k_merge_delta (first of the class): one thread per record; the one at the start of a key's run
+// finds the key's place a among the parents (binary search over the store), sums the run, writes
+// every record's merged position (a, plus one with a parent, plus its own index) for
+// k_merge_part, and adds +1 / -1 to tdelta[tile] for the tile of the run's first merged item,
+// a + j (tile boundaries move only to run ends, so a key's parent and its records fall in that
+// tile).  k_merge_count: one thread per tile, count = parents + delta (then clears the delta for
+// the next step), and an exclusive scan over the 256 tiles of each block: tinfo[tile] =
+// (count << 32) | first output counted from the block's first, bsum[b] = the block's outputs
+// (k_merge_scan turns them into offsets).
 __global__ __launch_bounds__(kBlock) void k_merge_delta(const uint64_t* __restrict__ pk,
                                                         const int2* __restrict__ pv,
                                                         const uint64_t* __restrict__ ckeys,
                                                         const int2* __restrict__ cvals,
                                                         const Counters* __restrict__ cnt,
                                                         uint32_t cur, uint32_t csel,
-                                                        const uint2* __restrict__ splits,
+                                                        uint32_t* __restrict__ mpos,
                                                         int32_t* __restrict__ tdelta,
                                                         KeyLayout kl) {
   if (cnt->err) return;
@@ -1082,19 +1084,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_delta(const uint64_t* __restri
   for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nc; j += gridDim.x * kBlock) {
     const uint64_t k = kl.ckey(ckeys[j]);
     if (j > 0 && kl.ckey(ckeys[j - 1]) == k) continue;  // not the start of its run
-    // the tile: the last t with splits[t].y <= j
-    uint32_t lo = 0, hi = ntiles;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (splits[mid].y <= j)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const uint32_t tile = lo;
-    if (tile >= ntiles) continue;  // inconsistent split points: k_merge reports them
-    const uint32_t p0 = splits[tile].x, p1 = splits[tile + 1].x;
-    uint32_t a = p0, b = p1 < np ? p1 : np;
+    uint32_t a = 0, b = np;  // parents below k
     while (a < b) {
       const uint32_t mid = (a + b) >> 1;
       if (pk[mid] < k)
@@ -1102,22 +1092,26 @@ __global__ __launch_bounds__(kBlock) void k_merge_delta(const uint64_t* __restri
       else
         b = mid;
     }
-    const bool hp = a < p1 && a < np && pk[a] == k;
+    const bool hp = a < np && pk[a] == k;
     int64_t re = 0, im = 0;
     if (hp) {
       const int2 v = pv[a];
       re = v.x;
       im = v.y;
     }
+    const uint32_t before = a + (hp ? 1u : 0u);  // parents ahead of each of the run's records
     for (uint32_t q = j; q < nc; ++q) {
       const uint64_t rk = ckeys[q];
       if (kl.ckey(rk) != k) break;
+      mpos[q] = before + q;
       if (kl.keep(rk, hp)) {
         const int2 v = cvals[q];
         re += v.x;
         im += v.y;
       }
     }
+    const uint32_t tile = (a + j) / kMergeTile;
+    if (tile >= ntiles) continue;  // cannot happen: a + j < np + nc
     const bool nz = re != 0 || im != 0;
     if (!hp && nz) atomicAdd(&tdelta[tile], 1);
     if (hp && !nz) atomicAdd(&tdelta[tile], -1);
@@ -1128,7 +1122,7 @@ constexpr int kCountTiles = kBlock;  // tiles per block of k_merge_count
 __global__ __launch_bounds__(kBlock) void k_merge_count(const Counters* __restrict__ cnt,
                                                         uint32_t cur, uint32_t csel,
                                                         const uint2* __restrict__ splits,
-                                                        const int32_t* __restrict__ tdelta,
+                                                        int32_t* __restrict__ tdelta,
                                                         uint64_t* __restrict__ tinfo,
                                                         uint64_t* __restrict__ bsum) {
   __shared__ uint32_t s_w[kWaves];
@@ -1144,6 +1138,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_count(const Counters* __restri
     const uint2 s0 = splits[tile], s1 = splits[tile + 1];
     if (s1.x >= s0.x && s1.y >= s0.y && s1.x <= np && s1.y <= nc)  // else k_merge reports it
       count = (uint32_t)((int32_t)(s1.x - s0.x) + tdelta[tile]);
+    tdelta[tile] = 0;  // zero again for the next step's k_merge_delta
   }
   const uint32_t incl = team_scan(count, kWave, lane);
   if (lane == kWave - 1) s_w[wave] = incl;
@@ -1997,18 +1992,19 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                uint64_t* tile_off, uint32_t step, uint32_t kbits, uint64_t init_min, uint64_t* ok,
                int2* ov, uint64_t cap_store, uint64_t max_items, uint32_t* ghist_next,
                const uint8_t* tab_base, const uint32_t* toff_next, uint32_t rep_per,
-               const int64_t* qshift, uint64_t seed, uint64_t* act_k, int2* act_v) {
+               const int64_t* qshift, uint64_t seed, uint64_t* act_k, int2* act_v,
+               uint32_t* mpos) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   const KeyLayout kl = key_layout(kbits, init_min);
   const uint32_t nblk = (max_tiles + kCountTiles - 1) / kCountTiles;
   uint64_t* bsum = tile_off + max_tiles;  // count blocks' sums, then offsets (nblk + 1 words)
   int32_t* tdelta = reinterpret_cast<int32_t*>(bsum + nblk + 1);  // max_tiles + 1 words
+  hipLaunchKernelGGL(k_merge_delta, dim3(grid_for(max_items, 2048)), dim3(kBlock), 0, st, pk,
+                     pv, ck, cv, (const Counters*)counters, cur, csel, mpos, tdelta, kl);
   hipLaunchKernelGGL(k_merge_part,
                      dim3(grid_for((uint64_t)max_tiles + 1, 2048)), dim3(kBlock), 0,
                      st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next,
-                     kl.ish, tdelta);
-  hipLaunchKernelGGL(k_merge_delta, dim3(grid_for(max_items, 2048)), dim3(kBlock), 0, st, pk,
-                     pv, ck, cv, (const Counters*)counters, cur, csel, splits, tdelta, kl);
+                     kl.ish, mpos);
   hipLaunchKernelGGL(k_merge_count, dim3(nblk ? nblk : 1), dim3(kBlock), 0, st,
                      (const Counters*)counters, cur, csel, splits, tdelta, tile_off, bsum);
   hipLaunchKernelGGL(k_merge_scan, dim3(1), dim3(kScanBlock), 0, st, bsum, (Counters*)counters,

@@ -1605,8 +1605,11 @@ int qmc_pulse_batch(qmc_ctx* c, const uint64_t* x, const uint64_t* z) {
   qmc::Counters* dcnt = c->counters();
   HIPCHK(c, hipMemcpyAsync(c->at<uint64_t>(c->L.pulse), pin, (size_t)c->C * 16,
                            hipMemcpyHostToDevice, c->stream));
+  // the look-back words are cleared only before the whole-store sort that a pulse with x != 0
+  // needs (a diagonal pulse sorts nothing)
   HIPCHK(c, qmck_batch_begin(c->stream, dcnt, nullptr, 0,
-                             c->at<uint64_t>(c->L.sort_status), c->L.n_sort_status, c->ghist(0),
+                             any_x ? c->at<uint64_t>(c->L.sort_status) : nullptr,
+                             any_x ? c->L.n_sort_status : 0, c->ghist(0),
                              2 * qmc::kMaxPasses * qmc::kRadixBins));
   HIPCHK(c, qmck_pulse(c->stream, c->sk(c->cur), c->sv(c->cur), dcnt, c->cur, c->n, c->kbits,
                        c->Rc, c->at<uint64_t>(c->L.pulse), any_x ? 1 : 0, c->ck(0), c->cv(0), 0,

@@ -462,6 +462,91 @@ __device__ __forceinline__ void spawn_batch(Emitter& em, const TabSet& ts, const
   spawn_records<kProp>(em, tv, valid, ck, v, w.x, w.y, kl, qsh, pr, step, seed, hid);
 }
 
+// Death/cloning records and children of the n <= 64 queued parents (one per lane) with all the
+// block's waves on the one batch: wave j takes the j-th of kWaves slices of each lane's diagonal
+// terms and of its off-diagonal groups.  The partial diagonal coefficients are summed over the
+// slices (integer sums, exact), and the comb of slice j starts where the comb over all earlier
+// groups would stand: the uniform plus their amounts, mod 2^32 (what a run of comb steps leaves),
+// so every record equals the one the single-wave comb in group order gives.  A short list of
+// parents that all emit (the merge's queue) then costs a quarter of the group loop per batch.
+// Block-uniform; dpart and cpart are kBlock entries of LDS that no one else uses meanwhile.
+__device__ __forceinline__ void spawn_team(Emitter& em, const TabSet& ts, const int64_t* qsh,
+                                           const uint64_t* ak, const int2* av, const uint2* aw,
+                                           uint32_t n, const KeyLayout& kl, const QmcProposal& pr,
+                                           uint32_t step, int2* dpart, uint32_t* cpart) {
+  constexpr uint32_t J = kWaves;
+  const uint32_t lane = __lane_id(), j = threadIdx.x / kWave;
+  const bool valid = lane < n;
+  const uint64_t ck = valid ? ak[lane] : 0;
+  const int2 v = valid ? av[lane] : make_int2(0, 0);
+  const uint2 w = valid ? aw[lane] : make_uint2(0, 0);
+  const TableView tv = table_view(ts.of_segment(valid ? kl.replica(ck) : 0u));
+  const uint64_t key = kl.key(ck);
+  const uint64_t sab = uabs64(v.x) + uabs64(v.y);
+  const int64_t qs = valid ? qsh[kl.replica(ck)] : 0;
+  const uint32_t G = valid ? tv.h->n_groups : 0u;
+  const bool dact = valid && !comb_all_zero(sab, tv.h->q_diag + uabs64(qs), w.y);
+  const bool act = valid && G > 1 && !comb_all_zero(sab, tv.h->q_off, w.x);
+  const uint32_t nd = valid ? tv.gs[1] / kTermPad : 0u;
+  const uint32_t d0 = nd * j / J * kTermPad, d1 = nd * (j + 1) / J * kTermPad;
+  const uint32_t g0 = G > 1 ? 1 + (G - 1) * j / J : 1u;
+  const uint32_t g1 = G > 1 ? 1 + (G - 1) * (j + 1) / J : 1u;
+  int32_t pre = 0, pim = 0;
+  if (dact) group_coeff_part(tv.t, d0, d1, key, pre, pim);
+  uint32_t amt = 0;  // this slice's comb amounts, mod 2^32
+  if (act) {
+    for (uint32_t g = g0; g < g1; ++g) {
+      int32_t cre, cim;
+      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      amt += (uint32_t)uabs64(xre) + (uint32_t)uabs64(xim);
+    }
+  }
+  dpart[threadIdx.x] = make_int2(pre, pim);
+  cpart[threadIdx.x] = amt;
+  __syncthreads();
+  if (j == 0 && __ballot(dact)) {
+    int2 d = make_int2(0, 0);
+    if (dact) {
+      int32_t dre = 0, dim = 0;
+      for (uint32_t jj = 0; jj < J; ++jj) {
+        const int2 pp = dpart[jj * kWave + lane];
+        dre += pp.x;
+        dim += pp.y;
+      }
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, dre + (int32_t)qs, dim, xre, xim);
+      uint64_t r = w.y;
+      d.x = (int32_t)comb_step(r, xre);
+      d.y = (int32_t)comb_step(r, xim);
+    }
+    em.emit_diag((d.x | d.y) != 0, kl.rkey(ck, sab), d);
+  }
+  uint32_t r0 = w.x;
+  for (uint32_t jj = 0; jj < j; ++jj) r0 += cpart[jj * kWave + lane];
+  uint64_t r = r0;
+  for (uint32_t g = g0; __ballot(act && g < g1) != 0; ++g) {
+    int2 child = make_int2(0, 0);
+    uint64_t target = ck;
+    if (act && g < g1) {
+      int32_t cre, cim;
+      group_coeff(tv.t, tv.gs[g], tv.gs[g + 1], key, cre, cim);
+      int64_t xre, xim;
+      cmul_q32(v.x, v.y, cre, cim, xre, xim);
+      child.x = (int32_t)comb_step(r, xre);
+      child.y = (int32_t)comb_step(r, xim);
+      target = ck ^ tv.gx[g];
+      if (pr.log && (child.x | child.y) != 0) {
+        const unsigned long long at = atomicAdd(pr.log_count, 1ull);
+        if (at < pr.log_cap) pr.log[at] = SpawnEvent{ck, step, g, child.x, child.y};
+      }
+    }
+    em.emit((child.x | child.y) != 0, kl.rkey(target, sab), child);
+  }
+  __syncthreads();  // every wave has read the partials
+}
+
 // ---------------------------------------------------------------------------------------------
 // k_spawn: the records of step `step` from the n = *count parents (pk, pv) and Philox stream
 // `stream` (0: N(s), the Euler step and the first AB2 term; 1: N(s-1), the second AB2 term):
@@ -526,12 +611,16 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
   uint64_t h_qoff = 0, h_qdiag = 0;
   // Rounds of R parents: all of a round's loads in flight at once (LDS-direct dword loads, no
   // registers), then kBlock parents at a time from LDS.  R is kSpawnRound for long lists and
-  // shrinks (to kBlock) when the list would leave workgroups idle: a short list of parents that
-  // all emit (the merge's queue) is spread over the grid rather than over a few workgroups.
+  // shrinks when the list would leave workgroups idle: a short list of parents that all emit
+  // (the merge's queue) is spread over the grid rather than over a few workgroups.  At most one
+  // 64-parent batch per workgroup (team): each drained at once with every wave of the workgroup
+  // on it (spawn_team).
   uint64_t R = (np + gridDim.x - 1) / gridDim.x;
+  const bool team = !kProp && R <= (uint64_t)kWave;
   R = (R + kBlock - 1) / kBlock * kBlock;
   if (R > (uint64_t)kSpawnRound) R = kSpawnRound;
   if (R < (uint64_t)kBlock) R = kBlock;
+  if (team) R = kWave;
   const uint64_t stride = (uint64_t)gridDim.x * R;
   for (uint64_t rbase = (uint64_t)blockIdx.x * R; rbase < np; rbase += stride) {
     const uint32_t rn = (uint32_t)(np - rbase < R ? np - rbase : R);
@@ -591,6 +680,11 @@ __global__ __launch_bounds__(kBlock) void k_spawn(
       }
       nl += tot;
       __syncthreads();
+    }
+    if (team && nl > 0) {  // the round's batch, drained at once (the round's LDS is free now)
+      spawn_team(em, ts, qsh, s_ak, s_av, s_aw, nl, kl, pr, step, s_pv,
+                 reinterpret_cast<uint32_t*>(s_pk));
+      nl = 0;
     }
   }
   if (nl > 0) drain((nl + kWave - 1) / kWave);

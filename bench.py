@@ -330,7 +330,8 @@ def main():
                 if args.initiator_xi else 0)
     g.set_initiator(init_min)
     init = [g.export(r) for r in range(w.n_replicas)]
-    # the sort tile of the streamed path, autotuned where that path carries the run
+    # the tile of the look-back sort that re-sorts the store after an x pulse, autotuned where
+    # the streamed path carries the run (the per-step sort has fixed tiles)
     sort_tile = g.tune_sort(0 if (args.path == "streamed" or args.proposal != "comb" or
                                   DOMINANT[args.workload] != "fused") else 16)
     prop, train_corr = None, None
@@ -405,7 +406,7 @@ def main():
             "initiator": ({"xi": args.initiator_xi, "min_walkers": init_min}
                           if init_min else None),
             "parallelism": "1 GPU, replicas batched in one store",
-            "sort_tile_records_per_thread": sort_tile,
+            "pulse_sort_tile_records_per_thread": sort_tile,
         },
         "key_steps_per_s": key_steps / elapsed,
         "rebalances": st1["rebalances"] - st0["rebalances"],
@@ -558,7 +559,7 @@ def main_batch(args, kind):
                           store_capacity=1 << 18, spawn_capacity=1 << 18)
     g.set_path(args.path)
     init = [g.export(r) for r in range(g.R)]
-    sort_tile = g.tune_sort(0)   # the streamed path carries most of this run
+    sort_tile = g.tune_sort(0)   # the store re-sort after an x pulse (streamed path)
     g.run_batch_workload(bw, 0, Wm)
     for r in range(g.R):
         g.import_(r, *init[r], step=0)
@@ -591,7 +592,7 @@ def main_batch(args, kind):
                    "circuits": len(bw.circuits), "replicas": bw.n_replicas, "dt": bw.dt,
                    "steps_timed": K, "step_path": args.path,
                    "parallelism": "1 GPU, all circuits and replicas in one store",
-                   "sort_tile_records_per_thread": sort_tile},
+                   "pulse_sort_tile_records_per_thread": sort_tile},
         "key_steps_per_s": (st1["key_steps"] - st0["key_steps"]) / elapsed,
         "roofline": roof,
         "final": {"n_occ_total": st1["n_occ"], "trace_mean": float(obs["trace"].mean())},

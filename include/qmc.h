@@ -262,8 +262,10 @@ int qmc_set_proposal_deep(qmc_ctx* ctx, uint32_t samples, const int8_t* w1, cons
  * QMC_ERR_ARG when d_events is given without d_count. */
 int qmc_log_spawns(qmc_ctx* ctx, void* d_events, uint64_t capacity, uint64_t* d_count);
 
-/* Tile size of the streamed path's radix sort of child records (records per thread of a
- * 256-thread tile: 8, 12, 16 or 24; 16 by default).  records_per_thread = 0 autotunes: every size
+/* Tile size of the look-back radix sort, which re-sorts the whole store after a pulse with x
+ * flips (records per thread of a 256-thread tile: 8, 12, 16 or 24; 16 by default; the sort of
+ * each streamed step's records uses tiles of 2048 and no look-back, whatever this is set to).
+ * The digit width is 11 bits in both.  records_per_thread = 0 autotunes: every size
  * is timed three times on synthetic records of this context's composite-key width and spawn
  * capacity (at most 4M records) in the child buffers, and the fastest is kept; nonzero sets it.
  * The sorted order, and so every result, is the same for every size.  *chosen (may be NULL)

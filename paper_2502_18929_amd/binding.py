@@ -332,8 +332,9 @@ class QMC:
         self._check(lib().qmc_use_graphs(self._ctx, 1 if on else 0))
 
     def tune_sort(self, records_per_thread=0):
-        """Sort tile size of the streamed path: 0 autotunes (times 8, 12, 16, 24 records per
-        thread and keeps the fastest), else sets it.  Returns the size in use."""
+        """Tile size of the look-back sort that re-sorts the store after a pulse with x flips
+        (the per-step sort has its own): 0 autotunes (times 8, 12, 16, 24 records per thread and
+        keeps the fastest), else sets it.  Returns the size in use."""
         out = ctypes.c_uint32()
         self._check(lib().qmc_tune_sort(self._ctx, int(records_per_thread), ctypes.byref(out)))
         return int(out.value)

@@ -23,11 +23,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {"fused": "k_persist", "small": "k_small", "sort": "k_onesweep",
-                "merge": "k_merge"}
+                "merge": "k_merge", "step": "streamed_step"}
 # the dominant kernel of each workload on the automatic path (with the initiator approximation
 # the dd12 store stays small enough for the fused kernel throughout); "fused" stands for the two
-# whole-step kernels, timed together, of which the one that ran longer is reported
-DOMINANT = {"ghz20_nm": "fused", "dd12": "merge", "ghz4": "fused", "batch64": "merge"}
+# whole-step kernels, timed together, of which the one that ran longer is reported; "step" is
+# the whole streamed step (draws, record sort and merge class of every step, timed per chunk of
+# steps), reported with the merge class beside it
+DOMINANT = {"ghz20_nm": "fused", "dd12": "step", "ghz4": "fused", "batch64": "step"}
 DOMINANT_INITIATOR = {"ghz20_nm": "fused", "dd12": "fused", "ghz4": "fused", "batch64": "fused"}
 # every source whose change can alter a kernel's launches or traffic (the host sets the launch
 # configuration), so committed counter numbers are dropped as soon as one of them changes
@@ -52,13 +54,13 @@ def step_bytes(cov):
 
 def algorithmic_bytes(kind, cov):
     """Algorithmic bytes of the steps a kernel class ran.
-    fused, small: the kernel runs whole steps, so all of step_bytes;
+    fused, small, step: whole steps, so all of step_bytes;
     merge: its annihilation share alone, parents and children read and the store written,
       16 (N_occ + N_sp + N_occ') (the draws of the next step, which it also makes, are left out:
       a lower bound);
     sort: every child read and written once, 32 N_sp."""
     keys, sp, out = cov["key_steps"], cov["spawn_steps"], cov["out_steps"]
-    if kind in ("fused", "small"):
+    if kind in ("fused", "small", "step"):
         return step_bytes(cov)
     if kind == "merge":
         return 16 * (keys + sp + out)
@@ -192,7 +194,15 @@ def cpu_baseline(w, K, integrator="euler", init_min=0, budget_s=10.0, proposal=N
 def whole_step_class(g, kind):
     """The timed class's totals.  The two whole-step kernels (fused persistent, LDS-resident) are
     timed together: the one that ran longer is the one reported, the other's time and launches
-    are returned beside it."""
+    are returned beside it.  The whole streamed step comes with the merge class's own roofline
+    (its annihilation bytes alone) beside it."""
+    if kind == "step":
+        ms, n, cov = g.profile_read("step")
+        mms, mn, mcov = g.profile_read("merge")
+        m = roofline("merge", None, mms, mn, mcov)
+        other = {"merge_class": {k: m[k] for k in ("achieved", "frac", "avg_launch_ms",
+                                                   "launches", "algorithmic_bytes_per_launch")}}
+        return kind, ms, n, cov, other
     if kind not in ("fused", "small"):
         ms, n, cov = g.profile_read()
         return kind, ms, n, cov, None
@@ -308,7 +318,7 @@ def main():
     if args.compare_proposals:
         return compare_proposals(args)
     dominant = DOMINANT_INITIATOR if args.initiator_xi else DOMINANT
-    kind = args.roofline_kernel or ("merge" if args.path == "streamed" or
+    kind = args.roofline_kernel or ("step" if args.path == "streamed" or
                                     args.proposal != "comb" else dominant[args.workload])
 
     import torch
@@ -381,7 +391,9 @@ def main():
     key_steps = st1["key_steps"] - st0["key_steps"]
     value = walker_steps / elapsed
     roof = roofline(kind, w.name, prof_ms, prof_n, cov)
-    if other:
+    if other and kind == "step":
+        roof.update(other)
+    elif other:
         roof["other_whole_step_kernel"] = other
     obs = g.observe(pauli=[(x, z) for _, x, z, _ in w.pauli_obs], psi=w.psi)
     res = {
@@ -577,7 +589,9 @@ def main_batch(args, kind):
     elapsed = t1 - t0
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
     roof = roofline(kind, bw.name, prof_ms, prof_n, cov)
-    if other:
+    if other and kind == "step":
+        roof.update(other)
+    elif other:
         roof["other_whole_step_kernel"] = other
     obs = g.observe()
     res = {

@@ -381,15 +381,17 @@ int qmc_counters(qmc_ctx* ctx, qmc_stats* out);
  * step from its parents: death/cloning and children), 1 = streamed record sort (all radix
  * passes), 2 = streamed annihilation (tile split points, tile output counts and offsets, and the
  * merge), 3 = one launch of the fused persistent kernel (a batch of whole steps), 4 = one
- * launch of the LDS-resident step (a batch of whole steps), -1 = off.
+ * launch of the LDS-resident step (a batch of whole steps), 5 = one chunk of whole streamed
+ * steps (from the chunk's first draws to its last merge: draws, sorts and merges of every step,
+ * End Matter spawn and annihilation steps), -1 = off.
  * qmc_profile resets the totals.  qmc_profile_read returns the summed milliseconds, the number of
  * timed launches and, in `covered` (may be NULL), the counter sums (walker_steps, key_steps,
  * child_steps, out_steps, spawn_steps, and in `step` the number of steps) of exactly the steps
  * that the timed launches ran -- for classes 1 to 4; zeros for class 0.  The algorithmic
  * bytes of the timed kernels follow from these sums.  The two whole-step classes are timed
  * together: with class 3 or 4 selected, launches of both are timed, each into its own totals,
- * which qmc_profile_read_class returns for any class (zeros for a class not timed);
- * QMC_ERR_ARG for a class outside 0..4. */
+ * which qmc_profile_read_class returns for any class (zeros for a class not timed); class 5
+ * also times class 2 into its own totals; QMC_ERR_ARG for a class outside 0..5. */
 int qmc_profile(qmc_ctx* ctx, int32_t kernel_class);
 int qmc_profile_read(qmc_ctx* ctx, double* ms, uint64_t* launches, qmc_stats* covered);
 int qmc_profile_read_class(qmc_ctx* ctx, int32_t kernel_class, double* ms, uint64_t* launches,

@@ -483,13 +483,15 @@ class QMC:
         at most 1024)."""
         self._check(lib().qmc_small_limit(self._ctx, int(keys)))
 
-    _PROF_CLASSES = {None: -1, "spawn": 0, "sort": 1, "merge": 2, "fused": 3, "small": 4}
+    _PROF_CLASSES = {None: -1, "spawn": 0, "sort": 1, "merge": 2, "fused": 3, "small": 4,
+                     "step": 5}
 
     def profile(self, kernel_class):
         """Time one kernel class with HIP events: 'spawn' (the draws of each step's records),
         'sort', 'merge' (streamed path), 'fused' (one persistent launch), 'small' (one
-        LDS-resident launch) or None.  'fused' and 'small' are timed together, each into its
-        own totals (profile_read(kind))."""
+        LDS-resident launch), 'step' (one chunk of whole streamed steps) or None.  'fused' and
+        'small' are timed together, each into its own totals (profile_read(kind)); 'step' times
+        'merge' beside it."""
         self._check(lib().qmc_profile(self._ctx, self._PROF_CLASSES[kernel_class]))
 
     def profile_read(self, kernel_class=None):

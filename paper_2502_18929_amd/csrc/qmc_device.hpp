@@ -17,6 +17,8 @@ constexpr int kMaxTerms = 4096;      // merged terms per step table
 constexpr int kMergeIpt = 4;         // merged items per thread
 constexpr int kMergeTile = kBlock * kMergeIpt;
 constexpr int kMergeSlack = kMaxGroups + 1;  // a key's run of children is at most one per group
+constexpr int kIdxShift = 8;                  // the store's search index: every 256th key
+constexpr uint32_t kIdxStride = 1u << kIdxShift;
 constexpr int kMergeCap = kMergeTile + kMergeSlack + 8;
 constexpr int kSpawnSeg = 256;       // per-wave LDS staging of child records in k_spawn
 constexpr int kSpawnRound = 1024;    // parents k_spawn loads at once

@@ -42,7 +42,7 @@ constexpr uint32_t kSortIpts[] = {8, 12, 16, 24};
 constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct within a chunk
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
-constexpr int kProfClasses = 5;            // kernel classes qmc_profile times
+constexpr int kProfClasses = 6;            // kernel classes qmc_profile times
 constexpr uint32_t kSmallAutoKeys = 256;   // default of qmc_small_limit
 // batches of the LDS-resident step in one chain (a window of steps)
 constexpr uint32_t kSmallBatches = (kMaxChunkSteps + kSmallBatch - 1) / kSmallBatch;
@@ -64,10 +64,24 @@ struct QTerm {
   int64_t qre, qim;
 };
 
+// A model's source terms laid out for the per-step table build (the same table as build_table,
+// faster): per term its constant and its weight channel (H monomials first, then Lindblad
+// operators), and the runs of terms with equal (xmask, zmask).
+struct TermPlan {
+  const std::vector<SrcTerm>* src = nullptr;
+  uint32_t nh = 0;                    // channels below nh are H weights, the rest rates
+  std::vector<double> kre, kim;
+  std::vector<uint32_t> ch;           // weight channel of each term
+  std::vector<uint32_t> run;          // run r: terms [run[r], run[r + 1])
+  std::vector<uint64_t> rx, rz;       // masks of run r
+  std::vector<uint32_t> used;         // the channels some term reads
+};
+
+
 struct Layout {
   size_t counters, sk0, sv0, ck0, ck1, cv0, cv1, ghist, sort_status, status, splits, tab, qshift,
       obs_out, obs_in, look_keys, look_out, seg_k, seg_v, seg_n, pk, pv, in_k, in_v, in_n, split,
-      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, thist, mpos, total;
+      tab_off, tabB_off, slots, done, pulse, mlp, small_fail, small_stats, thist, mpos, sidx, total;
   uint64_t cap_store, cap_child, cap_sort, n_sort_status, max_tiles, status_words;
   uint32_t P;          // key ranges / workgroups of the persistent step
   uint64_t segcap;     // records per segment
@@ -144,6 +158,7 @@ bool compute_layout(const qmc_config& c, uint32_t P, uint32_t n_circuits, Layout
   // per-tile digit counts of the step sort, two buffers (a pass reads one, counts into the other)
   L.thist = take((size_t)2 * qmck_step_sort_hist_words(C) * 4);
   L.mpos = take(C * 4);  // merged positions of one step's records
+  L.sidx = take(((S >> 8) + 2) * 8);  // the store's search index (every 256th key)
   L.total = o;
   return true;
 }
@@ -165,6 +180,7 @@ struct qmc_ctx {
   uint32_t C = 1, Rc = 0;           // circuits of a batch, replicas per circuit
   uint32_t n_h = 0, n_l = 0;        // weights per step, all circuits together
   std::vector<std::vector<SrcTerm>> terms;  // per circuit
+  std::vector<TermPlan> plans;               // per circuit, over `terms`
   std::vector<uint32_t> wh_off, wl_off;      // a circuit's first weight in a step's s / gamma
   Layout L{};
   uint8_t* ws = nullptr;
@@ -320,14 +336,21 @@ struct HostTable {
   uint64_t active[2] = {0, 0};   // nonzero weight channels of the step (proposal input)
 };
 
-int build_table(const std::vector<SrcTerm>& src, double dt, const double* s, const double* g,
-                double scale, HostTable& T, std::string& why, uint32_t nh = 0, uint32_t nl = 0) {
-  // the step's weight channels that are nonzero: H monomials m < nh, then Lindblad operators
+int group_table(HostTable& T, std::string& why);
+
+// The step's weight channels that are nonzero (the proposal network's input): H monomials
+// m < nh, then Lindblad operators.
+void active_channels(const double* s, const double* g, uint32_t nh, uint32_t nl, HostTable& T) {
   T.active[0] = T.active[1] = 0;
   for (uint32_t m = 0; m < nh + nl && m < 128; ++m) {
     const double w = m < nh ? s[m] : g[m - nh];
     if (w != 0.0) T.active[m >> 6] |= 1ull << (m & 63);
   }
+}
+
+int build_table(const std::vector<SrcTerm>& src, double dt, const double* s, const double* g,
+                double scale, HostTable& T, std::string& why, uint32_t nh = 0, uint32_t nl = 0) {
+  active_channels(s, g, nh, nl, T);
   // src is sorted by (xmask, zmask): each run of equal terms is one merged Q32 term.
   T.t.clear();
   T.t.reserve(src.size());
@@ -352,6 +375,12 @@ int build_table(const std::vector<SrcTerm>& src, double dt, const double* s, con
     if (acc.qre != 0 || acc.qim != 0) T.t.push_back(acc);
     i = j;
   }
+  return group_table(T, why);
+}
+
+// Groups of a table's merged terms (diagonal first, then xmask ascending), their bound check and
+// the Q32 sums of the diagonal and the off-diagonal groups.
+int group_table(HostTable& T, std::string& why) {
   T.gx.assign(1, 0);
   T.gs.assign(1, 0);
   for (size_t i = 0; i < T.t.size(); ++i) {
@@ -422,6 +451,92 @@ size_t pack_table(const HostTable& T, uint8_t* dst) {
   }
   gs[G] = at;
   return h.bytes;
+}
+
+void make_plan(const std::vector<SrcTerm>& src, uint32_t nh, TermPlan& P) {
+  P.src = &src;
+  P.nh = nh;
+  P.kre.clear();
+  P.kim.clear();
+  P.ch.clear();
+  P.run.clear();
+  P.rx.clear();
+  P.rz.clear();
+  std::vector<uint32_t> ch;
+  for (size_t i = 0; i < src.size(); ++i) {
+    const SrcTerm& t = src[i];
+    P.kre.push_back(t.kre);
+    P.kim.push_back(t.kim);
+    P.ch.push_back(t.weight_kind == 0 ? t.weight_index : nh + t.weight_index);
+    if (i == 0 || t.xmask != src[i - 1].xmask || t.zmask != src[i - 1].zmask) {
+      P.run.push_back((uint32_t)i);
+      P.rx.push_back(t.xmask);
+      P.rz.push_back(t.zmask);
+    }
+  }
+  P.run.push_back((uint32_t)src.size());
+  P.used = P.ch;
+  std::sort(P.used.begin(), P.used.end());
+  P.used.erase(std::unique(P.used.begin(), P.used.end()), P.used.end());
+}
+
+// build_table through the plan: the weights of the used channels checked once, every term
+// quantized in one pass (the same FP64 expression; round half to even by the bit pattern of
+// v + 1.5 * 2^52, exact for |v| < 2^51), run sums, then the same grouping.  A non-finite weight
+// or a coefficient of 2^51 or more goes through build_table itself (the same result and error).
+int build_table_plan(const TermPlan& P, double dt, const double* s, const double* g,
+                     double scale, HostTable& T, std::string& why, uint32_t nh = 0,
+                     uint32_t nl = 0) {
+  thread_local std::vector<double> W;
+  thread_local std::vector<int64_t> Q;
+  const uint32_t nch = P.used.empty() ? 0u : P.used.back() + 1;
+  W.resize(nch);
+  bool slow = false;
+  for (const uint32_t c : P.used) {
+    const double w = c < P.nh ? s[c] : g[c - P.nh];
+    W[c] = w;
+    slow |= !std::isfinite(w);
+  }
+  const size_t M = P.kre.size();
+  Q.resize(2 * M);
+  if (!slow) {
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    int64_t mbits;
+    std::memcpy(&mbits, &kMagic, 8);
+    const double* kre = P.kre.data();
+    const double* kim = P.kim.data();
+    const uint32_t* ch = P.ch.data();
+    int64_t* q = Q.data();
+    const double* w = W.data();
+    uint32_t big = 0;
+    for (size_t i = 0; i < M; ++i) {
+      const double wi = w[ch[i]];
+      const double vr = scale * (dt * (wi * kre[i])) * 4294967296.0;
+      const double vi = scale * (dt * (wi * kim[i])) * 4294967296.0;
+      big |= !(std::fabs(vr) < 2251799813685248.0) | !(std::fabs(vi) < 2251799813685248.0);
+      const double rr = vr + kMagic, ri = vi + kMagic;
+      int64_t br, bi;
+      std::memcpy(&br, &rr, 8);
+      std::memcpy(&bi, &ri, 8);
+      q[2 * i] = br - mbits;
+      q[2 * i + 1] = bi - mbits;
+    }
+    slow = big != 0;
+  }
+  if (slow) return build_table(*P.src, dt, s, g, scale, T, why, nh, nl);
+  active_channels(s, g, nh, nl, T);
+  T.t.clear();
+  T.t.reserve(P.rx.size());
+  const int64_t* q = Q.data();
+  for (size_t r = 0; r + 1 < P.run.size(); ++r) {
+    int64_t re = 0, im = 0;
+    for (uint32_t i = P.run[r]; i < P.run[r + 1]; ++i) {
+      re += q[2 * i];
+      im += q[2 * i + 1];
+    }
+    if (re != 0 || im != 0) T.t.push_back(QTerm{P.rx[r], P.rz[r], re, im});
+  }
+  return group_table(T, why);
 }
 
 int check_records(uint32_t n, const uint64_t* keys, const int32_t* re, const int32_t* im,
@@ -643,6 +758,8 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
     c->n_l += models[ci].n_l;
     compile_model(models[ci], c->n, c->terms[ci]);
   }
+  c->plans.resize(c->C);
+  for (uint32_t ci = 0; ci < c->C; ++ci) make_plan(c->terms[ci], models[ci].n_h, c->plans[ci]);
   compute_layout(c->cfg, P, c->C, c->L);
   if (!d_workspace || ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) {
     delete c;
@@ -1023,8 +1140,12 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   const int64_t* qshA = c->at<int64_t>(c->L.qshift);
   const int64_t* qshB = qshA + c->R;
   const uint8_t* dtab = ch.dtab;
-  const uint32_t nev = 2 * nst;
-  if (c->prof_class >= 0 && c->prof_class <= 2) {
+  // Class 5 (the whole streamed step) is one interval per chunk, from before its first draws to
+  // after its last merge, and times the merge class (2) beside it.
+  const bool prof_step = c->prof_class == 5;
+  const int32_t prof_k = prof_step ? 2 : c->prof_class;  // the class with per-step events
+  const uint32_t nev = 2 * nst + 2;
+  if ((prof_k >= 0 && prof_k <= 2) || prof_step) {
     while (c->prof_ev.size() < nev) {
       hipEvent_t ev;
       HIPCHK(c, hipEventCreate(&ev));
@@ -1041,12 +1162,16 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     // The merge class's tile counts and count adjustments start from zero (the adjustments are
     // left zero by every completed step, not by one an error stopped).  The step sort uses no
     // look-back words; the whole-store sort after a pulse clears its own.
+    if (prof_step) ENQ(hipEventRecord(c->prof_ev[2 * nst], st_q));
     ENQ(qmck_batch_begin(st_q, dcnt, c->at<uint64_t>(c->L.status), c->L.status_words, nullptr,
                          0, c->ghist(0), 2 * qmc::kMaxPasses * qmc::kRadixBins));
     auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
-      if (c->prof_class != cls) return hipSuccess;
+      if (prof_k != cls) return hipSuccess;
       return hipEventRecord(c->prof_ev[2 * k + which], st_q);
     };
+    // the search index of the first step's parents (each merge writes the next one's)
+    uint64_t* sidx = c->at<uint64_t>(c->L.sidx);
+    ENQ(qmck_store_index(st_q, bk[0], &dcnt->n_store[cur0], sidx, c->L.cap_store));
     uint32_t cb = 0;  // child buffer pair holding the unsorted children of the current step
     ENQ(mark(0, 0, 0));
     // device table offsets of step k of the chunk: [circuit] (A), and the AB2 B term
@@ -1082,7 +1207,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
                      c->init_min, bk[(k + 1) % nb], bv[(k + 1) % nb], c->L.cap_store,
                      c->L.cap_store + c->L.cap_child, c->ghist(csel ^ 1), dtab,
                      queue ? toff_next : nullptr, c->Rc, qshA, c->cfg.seed, c->alt_k(1),
-                     c->alt_v(1), c->at<uint32_t>(c->L.mpos)));
+                     c->alt_v(1), c->at<uint32_t>(c->L.mpos), sidx));
       ENQ(mark(2, k, 1));
       cb = cf ^ 1;
       if (more) {
@@ -1107,6 +1232,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
         ENQ(mark(0, k + 1, 1));
       }
     }
+    if (prof_step) ENQ(hipEventRecord(c->prof_ev[2 * nst + 1], st_q));
 #undef ENQ
     return hipSuccess;
   };
@@ -1149,13 +1275,19 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   }
   int rc = read_counters(c, hc);
   if (rc) return rc;
-  if (c->prof_class >= 0 && c->prof_class <= 2) {
+  if (prof_k >= 0 && prof_k <= 2) {
     for (uint32_t k = 0; k < nst; ++k) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
-      c->prof_ms[c->prof_class] += ms;
-      c->prof_launches[c->prof_class] += 1;
+      c->prof_ms[prof_k] += ms;
+      c->prof_launches[prof_k] += 1;
     }
+  }
+  if (prof_step) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * nst], c->prof_ev[2 * nst + 1]));
+    c->prof_ms[5] += ms;
+    c->prof_launches[5] += 1;
   }
   kd = nst;
   if (hc.err) {
@@ -1186,7 +1318,8 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   c->cur = cur;
   c->step = step0 + kd;
   c->n_occ = hc.n_store[cur];
-  if (c->prof_class == 1 || c->prof_class == 2) add_cover(c, c->prof_class, before, hc, kd);
+  if (prof_k == 1 || prof_k == 2) add_cover(c, prof_k, before, hc, kd);
+  if (prof_step) add_cover(c, 5, before, hc, kd);
   return QMC_OK;
 }
 
@@ -1296,7 +1429,7 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     const bool two = ab2 && k >= euler_first;
     const uint32_t nh = (ci + 1 < NC ? c->wh_off[ci + 1] : c->n_h) - c->wh_off[ci];
     const uint32_t nl = (ci + 1 < NC ? c->wl_off[ci + 1] : c->n_l) - c->wl_off[ci];
-    int rc = build_table(c->terms[ci], c->cfg.dt, ws, wg, two ? 1.5 : 1.0, TA, why, nh, nl);
+    int rc = build_table_plan(c->plans[ci], c->cfg.dt, ws, wg, two ? 1.5 : 1.0, TA, why, nh, nl);
     if (!rc && two) {
       const double *ps, *pg;
       if (k > 0) {
@@ -1305,7 +1438,7 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
         ps = c->w_prev.data();
         pg = c->w_prev.data() + c->n_h;
       }
-      rc = build_table(c->terms[ci], c->cfg.dt, ps, pg, -0.5, TB, why);
+      rc = build_table_plan(c->plans[ci], c->cfg.dt, ps, pg, -0.5, TB, why);
       if (!rc && TB.q_diag + max_qb >= (1ull << 31)) {
         rc = QMC_ERR_DT;
         why = "diagonal group with shift violates the Q32 bound";
@@ -2126,7 +2259,7 @@ int qmc_counters(qmc_ctx* c, qmc_stats* out) {
 }
 
 int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
-  if (!c || kernel_class < -1 || kernel_class > 4) return QMC_ERR_ARG;
+  if (!c || kernel_class < -1 || kernel_class >= kProfClasses) return QMC_ERR_ARG;
   c->prof_class = kernel_class;
   for (int k = 0; k < kProfClasses; ++k) {
     c->prof_ms[k] = 0.0;
@@ -2165,9 +2298,11 @@ int qmc_coeff_table(const qmc_config* cfg, const qmc_model* model, const double*
   if (rc) return rc;
   std::vector<SrcTerm> terms;
   compile_model(*model, cfg->n_qubits, terms);
+  TermPlan P;
+  make_plan(terms, model->n_h, P);
   HostTable T;
   if (!std::isfinite(scale)) return QMC_ERR_ARG;
-  rc = build_table(terms, cfg->dt, s, gamma, scale, T, why);
+  rc = build_table_plan(P, cfg->dt, s, gamma, scale, T, why);
   if (rc) return rc;
   *n_groups = (uint32_t)T.gx.size();
   *n_terms = (uint32_t)T.t.size();

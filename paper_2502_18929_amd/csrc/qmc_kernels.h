@@ -80,7 +80,7 @@ int qmck_fill_sort_probe(hipStream_t st, uint64_t* k, int2* v, uint64_t n, uint6
 // (tile_off: max tiles words, max tiles / 256 + 1 words of block offsets, then max tiles + 1
 // int32 count adjustments, which must hold zeros on entry and hold zeros again on return),
 // with mpos (room for max_items - cap_store words) the records' merged positions, then the
-// tiles.  Also clears the next step's record counter
+// tiles; sidx holds the parents' search index on entry and the new store's on return.  Also clears the next step's record counter
 // and digit histograms (ghist_next), which the records of step + 1 (qmck_spawn) fill.  With
 // toff_next (the tables of step + 1 for circuit c at tab_base + toff_next[c], shifts qshift),
 // every new store record whose comb can fire in step + 1 (Philox stream 0) is appended to
@@ -92,7 +92,12 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                int2* ov, uint64_t cap_store, uint64_t max_items, uint32_t* ghist_next,
                const uint8_t* tab_base, const uint32_t* toff_next, uint32_t rep_per,
                const int64_t* qshift, uint64_t seed, uint64_t* act_k, int2* act_v,
-               uint32_t* mpos);
+               uint32_t* mpos, uint64_t* sidx);
+// The search index of the sorted keys[0, *count): sidx[i] = keys[256 i] (room for
+// max_items / 256 + 1 words).  qmck_merge reads the index of its parents from sidx (its
+// k_merge_delta searches the store through it) and then writes the index of the new store there.
+int qmck_store_index(hipStream_t st, const uint64_t* keys, const uint64_t* count,
+                     uint64_t* sidx, uint64_t max_items);
 // out[0..1] (device) = the index range of the sorted keys[0, *count) within [lo, hi].
 int qmck_key_range(hipStream_t st, const uint64_t* keys, const uint64_t* count, uint64_t lo,
                    uint64_t hi, uint64_t* out);

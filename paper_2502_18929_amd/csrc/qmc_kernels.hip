@@ -1091,6 +1091,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(
 // Merge of parents (unique keys) with sorted children, split into tiles whose boundaries never
 // cut a key's run (parents win ties, so a run is [parent] children...).
 // ---------------------------------------------------------------------------------------------
+// The search index of a sorted store: sidx[i] = keys[i kIdxStride] for every i kIdxStride below
+// *count.  k_merge writes it for the store it produces; this kernel builds it for a store that
+// came from elsewhere (the first step of a streamed run).
+__global__ __launch_bounds__(kBlock) void k_store_index(const uint64_t* __restrict__ keys,
+                                                        const uint64_t* __restrict__ count,
+                                                        uint64_t* __restrict__ sidx) {
+  const uint64_t n = *count, m = (n + kIdxStride - 1) >> kIdxShift;
+  for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * kBlock)
+    sidx[i] = keys[i << kIdxShift];
+}
+
 // Split points (one thread per tile boundary, from the records' merged positions that
 // k_merge_delta wrote), plus the per-step resets of the counters the next step's kernels use.
 __global__ __launch_bounds__(kBlock) void k_merge_part(const uint64_t* __restrict__ pk,
@@ -1170,15 +1182,30 @@ __global__ __launch_bounds__(kBlock) void k_merge_delta(const uint64_t* __restri
                                                         uint32_t cur, uint32_t csel,
                                                         uint32_t* __restrict__ mpos,
                                                         int32_t* __restrict__ tdelta,
-                                                        KeyLayout kl) {
+                                                        KeyLayout kl,
+                                                        const uint64_t* __restrict__ sidx) {
   if (cnt->err) return;
   const uint32_t np = (uint32_t)cnt->n_store[cur];
   const uint32_t nc = (uint32_t)cnt->n_child[csel];
   const uint32_t ntiles = (np + nc + kMergeTile - 1) / kMergeTile;
+  const uint32_t nidx = (np + kIdxStride - 1) >> kIdxShift;  // entries of the store's index
   for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < nc; j += gridDim.x * kBlock) {
     const uint64_t k = kl.ckey(ckeys[j]);
     if (j > 0 && kl.ckey(ckeys[j - 1]) == k) continue;  // not the start of its run
-    uint32_t a = 0, b = np;  // parents below k
+    // The index (every kIdxStride-th parent key, a few MB that stay in the caches) narrows the
+    // search to one block of parents: with x entries below k, the parents below k number more
+    // than (x - 1) kIdxStride (entry x - 1 is one of them) and at most x kIdxStride (entry x,
+    // if any, is not).
+    uint32_t x = 0, y = nidx;
+    while (x < y) {
+      const uint32_t mid = (x + y) >> 1;
+      if (sidx[mid] < k)
+        x = mid + 1;
+      else
+        y = mid;
+    }
+    uint32_t a = x == 0 ? 0u : ((x - 1) << kIdxShift) + 1;  // parents below k
+    uint32_t b = (x << kIdxShift) < np ? (x << kIdxShift) : np;
     while (a < b) {
       const uint32_t mid = (a + b) >> 1;
       if (pk[mid] < k)
@@ -1313,6 +1340,7 @@ struct MergeArgs {
   uint64_t seed;
   uint64_t* act_k;
   int2* act_v;
+  uint64_t* sidx;  // index of the new store: key of every kIdxStride-th record
 };
 
 // Annihilation: every tile's parents and sorted records go to LDS together (LDS-direct loads:
@@ -1594,6 +1622,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs A) {
         if (o < A.cap_store) {
           A.ok[o] = rk[u];
           A.ov[o] = rv[u];
+          if ((o & (kIdxStride - 1)) == 0) A.sidx[o >> kIdxShift] = rk[u];
         }
         if (draw) {
           const uint32_t rep = kl.replica(rk[u]);
@@ -2087,14 +2116,14 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
                int2* ov, uint64_t cap_store, uint64_t max_items, uint32_t* ghist_next,
                const uint8_t* tab_base, const uint32_t* toff_next, uint32_t rep_per,
                const int64_t* qshift, uint64_t seed, uint64_t* act_k, int2* act_v,
-               uint32_t* mpos) {
+               uint32_t* mpos, uint64_t* sidx) {
   const uint32_t max_tiles = (uint32_t)((max_items + kMergeTile - 1) / kMergeTile);
   const KeyLayout kl = key_layout(kbits, init_min);
   const uint32_t nblk = (max_tiles + kCountTiles - 1) / kCountTiles;
   uint64_t* bsum = tile_off + max_tiles;  // count blocks' sums, then offsets (nblk + 1 words)
   int32_t* tdelta = reinterpret_cast<int32_t*>(bsum + nblk + 1);  // max_tiles + 1 words
   hipLaunchKernelGGL(k_merge_delta, dim3(grid_for(max_items, 2048)), dim3(kBlock), 0, st, pk,
-                     pv, ck, cv, (const Counters*)counters, cur, csel, mpos, tdelta, kl);
+                     pv, ck, cv, (const Counters*)counters, cur, csel, mpos, tdelta, kl, sidx);
   hipLaunchKernelGGL(k_merge_part,
                      dim3(grid_for((uint64_t)max_tiles + 1, 2048)), dim3(kBlock), 0,
                      st, pk, ck, (Counters*)counters, cur, csel, splits, max_tiles, ghist_next,
@@ -2124,9 +2153,17 @@ int qmck_merge(hipStream_t st, const uint64_t* pk, const int2* pv, const uint64_
   a.seed = seed;
   a.act_k = act_k;
   a.act_v = act_v;
+  a.sidx = sidx;
   const uint32_t mb = merge_blocks();
   hipLaunchKernelGGL(k_merge, dim3(max_tiles < mb ? (max_tiles ? max_tiles : 1) : mb),
                      dim3(kBlock), 0, st, a);
+  return (int)hipGetLastError();
+}
+
+int qmck_store_index(hipStream_t st, const uint64_t* keys, const uint64_t* count,
+                     uint64_t* sidx, uint64_t max_items) {
+  hipLaunchKernelGGL(k_store_index, dim3(grid_for((max_items >> kIdxShift) + 1, 1024)),
+                     dim3(kBlock), 0, st, keys, count, sidx);
   return (int)hipGetLastError();
 }
 

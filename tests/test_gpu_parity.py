@@ -198,6 +198,25 @@ def test_dd12_full_size_first_steps(B, orc, path):
     _assert_same(g, o, 16, "step 600")
 
 
+def test_whole_step_timing_changes_nothing(B, orc):
+    """Timing whole streamed steps (class 'step', which times the merge class beside it) covers
+    exactly the steps run, in chunks, and leaves the stores equal to the oracle's."""
+    w = W.config_dd12()
+    g = B.QMC.from_workload(w, store_capacity=1 << 20, spawn_capacity=1 << 18)
+    g.set_path("streamed")
+    o = orc.Oracle(w.n, 16, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+    g.profile("step")
+    _run_both(g, o, w, 0, 300, threads=16)
+    _assert_same(g, o, 16, "step 300")
+    ms, n, cov = g.profile_read()
+    assert cov["steps"] == 300 and 1 <= n < 300 and ms > 0
+    ms2, n2, cov2 = g.profile_read("merge")
+    assert n2 == 300 and cov2 == cov and 0 < ms2 < ms
+    oc = o.counters()
+    assert cov["walker_steps"] == oc["walker_steps"] and cov["key_steps"] == oc["key_steps"]
+    g.profile(None)
+
+
 # ---- estimators ------------------------------------------------------------------------------
 
 def test_observe_matches_oracle(B, orc):

@@ -89,6 +89,7 @@ struct Counters {
   uint32_t tile_counter;   // (unused)
   uint32_t resplits;       // key ranges re-cut inside the fused kernel (running sum)
   uint32_t sort_ticket[2][kMaxPasses + 2];  // onesweep tile tickets per step parity and pass
+  uint64_t small_stop;     // the LDS-resident chain's stop word, as its finishing kernel saw it
 };
 
 // Epoch tags of the look-back status words (never 0, distinct within a batch of <= 8000 steps).

@@ -215,6 +215,16 @@ struct qmc_ctx {
   uint32_t small_limit = kSmallAutoKeys;  // automatic mode: keys per replica it runs up to
   uint32_t small_epoch = 0;         // epoch of the last LDS-resident chain
   std::vector<hipEvent_t> prof_ev;   // start/stop pairs, one pair per step of a chunk
+  // Whole-launch timings are read back lazily (qmc_profile_read): reading an event's time right
+  // after the launch costs the step call up to tens of microseconds.  Each entry: class, start
+  // and stop event, launches; the events return to ev_free once read.
+  struct PendingTime {
+    int cls;
+    hipEvent_t a, b;
+    uint64_t launches;
+  };
+  std::vector<PendingTime> ev_pending;
+  std::vector<hipEvent_t> ev_free;
   // per kernel class: summed milliseconds and launches of the timed launches
   double prof_ms[kProfClasses] = {};
   uint64_t prof_launches[kProfClasses] = {};
@@ -860,6 +870,41 @@ void add_cover(qmc_ctx* c, int cls, const qmc::Counters& a, const qmc::Counters&
   v.rebalances += b.resplits - a.resplits;
 }
 
+// Two events for a deferred whole-launch timing.
+int timing_pair(qmc_ctx* c, hipEvent_t& a, hipEvent_t& b) {
+  while (c->ev_free.size() < 2) {
+    hipEvent_t ev;
+    HIPCHK(c, hipEventCreate(&ev));
+    c->ev_free.push_back(ev);
+  }
+  a = c->ev_free.back();
+  c->ev_free.pop_back();
+  b = c->ev_free.back();
+  c->ev_free.pop_back();
+  return QMC_OK;
+}
+
+// The pending timings into the class totals (the events completed: every step call ends with a
+// stream synchronization).
+int settle_timings(qmc_ctx* c) {
+  for (const qmc_ctx::PendingTime& t : c->ev_pending) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, t.a, t.b));
+    c->prof_ms[t.cls] += ms;
+    c->prof_launches[t.cls] += t.launches;
+    c->ev_free.push_back(t.a);
+    c->ev_free.push_back(t.b);
+  }
+  c->ev_pending.clear();
+  return QMC_OK;
+}
+
+// Records a timing to be read later; many of them are settled at once.
+void defer_timing(qmc_ctx* c, int cls, hipEvent_t a, hipEvent_t b, uint64_t launches) {
+  c->ev_pending.push_back(qmc_ctx::PendingTime{cls, a, b, launches});
+  if (c->ev_pending.size() >= 256) (void)settle_timings(c);
+}
+
 constexpr uint64_t kFusedKeysPerSegment = 8192;  // automatic mode: larger stores run streamed
 constexpr uint32_t kStreamedWindow = 256;         // steps run streamed after a fused overflow
 constexpr uint32_t kKernelResplits = 64;          // re-splits the fused kernel does by itself
@@ -927,26 +972,19 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   pl.rebal_min = 64;
   pl.done = c->at<uint32_t>(c->L.done);
   const bool prof = c->prof_whole();
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (prof) {
-    while (c->prof_ev.size() < 2) {
-      hipEvent_t ev;
-      HIPCHK(c, hipEventCreate(&ev));
-      c->prof_ev.push_back(ev);
-    }
+    int rc = timing_pair(c, ev0, ev1);
+    if (rc) return rc;
   }
   HIPCHK(c, qmcp_prepare(c->stream, &pl));
-  if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[0], c->stream));
+  if (prof) HIPCHK(c, hipEventRecord(ev0, c->stream));
   HIPCHK(c, qmcp_launch(c->stream, &pl));
-  if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[1], c->stream));
+  if (prof) HIPCHK(c, hipEventRecord(ev1, c->stream));
   HIPCHK(c, hipMemcpyAsync(pin_done, pl.done, 8, hipMemcpyDeviceToHost, c->stream));
   int rc = read_counters(c, hc);  // synchronizes the stream
   if (rc) return rc;
-  if (prof) {
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]));
-    c->prof_ms[3] += ms;
-    c->prof_launches[3] += 1;
-  }
+  if (prof) defer_timing(c, 3, ev0, ev1, 1);
   kd = pin_done[0];
   reason = pin_done[1];
   if (reason == 1) {
@@ -982,27 +1020,22 @@ int run_fused(qmc_ctx* c, const Chunk& ch, uint32_t& kd, uint32_t& reason, qmc::
   return QMC_OK;
 }
 
-// Steps of the chunk with the LDS-resident step, one workgroup per store segment (Euler, the
-// comb).  A segment that outgrows what the step holds stops the launch at the first such step F;
-// the steps before F are then run again from the unchanged canonical store (the results are the
-// same) and the automatic mode leaves the small step for this trajectory.  On return kd =
-// completed steps (0 if not even the first step fits) and the store reflects them.
-int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
-  const qmc::Counters before = c->last_hc;
-  const uint32_t step0 = c->step, nst = ch.nst;
-  const uint64_t segcap = c->L.segcap, P = c->L.P;
-  uint64_t* seg_k = c->at<uint64_t>(c->L.seg_k);
-  int2* seg_v = c->at<int2>(c->L.seg_v);
-  uint32_t* seg_n = c->at<uint32_t>(c->L.seg_n);
-  unsigned long long* dstop = c->at<unsigned long long>(c->L.small_fail);
-  uint64_t* dstats = c->at<uint64_t>(c->L.small_stats);
-  const uint64_t rows = (uint64_t)c->R;  // statistics rows of one batch
-  qmc::Counters* dcnt = c->counters();
-  SmallLaunch sl{};
-  sl.counters = dcnt;
+// The first batch of a small chain, launched while the rest of the call's tables are still being
+// built (the host's table build overlaps the batch): steps [0, steps) of the first chunk, chain
+// epoch `epoch`, the profiling events around it (or null).
+struct SmallHead {
+  uint32_t steps = 0;
+  uint32_t epoch = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// The launch fields of the LDS-resident step that stay the same over a chain.
+void small_setup(qmc_ctx* c, const uint8_t* dtab, SmallLaunch& sl) {
+  sl = SmallLaunch{};
+  sl.counters = c->counters();
   sl.cur = c->cur;
-  sl.segcap = segcap;
-  sl.tab_base = ch.dtab;
+  sl.segcap = c->L.segcap;
+  sl.tab_base = dtab;
   sl.n_circuits = c->C;
   sl.rep_per = c->Rc;
   sl.n_segments = c->R;
@@ -1013,71 +1046,100 @@ int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   sl.cap_store = std::min<uint64_t>(c->cfg.store_capacity,
                                     c->path == 3 ? (uint64_t)kSmallCap : c->small_limit);
   sl.cap_spawn = c->cfg.spawn_capacity;
-  sl.stop = dstop;
-  // batch j of a chain: steps [first + j B, ...), from the canonical store (j = 0) or from
-  // segment buffer (j - 1) & 1, into segment buffer j & 1, statistics into row block j
+  sl.stop = c->at<unsigned long long>(c->L.small_fail);
+}
+
+// Batch j of a chain: steps [first, first + steps) of the chunk whose first table is entry
+// tfirst of the offsets and whose first step is step0, from the canonical store (j = 0) or from
+// segment buffer (j - 1) & 1, into segment buffer j & 1, statistics into row block j.
+int small_batch(qmc_ctx* c, SmallLaunch& sl, uint32_t tfirst, uint32_t step0, uint32_t j,
+                uint32_t first, uint32_t steps) {
+  const uint64_t segcap = c->L.segcap, P = c->L.P;
+  uint64_t* seg_k = c->at<uint64_t>(c->L.seg_k);
+  int2* seg_v = c->at<int2>(c->L.seg_v);
+  uint32_t* seg_n = c->at<uint32_t>(c->L.seg_n);
+  const uint32_t ib = (j + 1) & 1, ob = j & 1;
+  sl.ck = j == 0 ? c->sk(0) : nullptr;
+  sl.cv = j == 0 ? c->sv(0) : nullptr;
+  sl.ik = seg_k + ib * P * segcap;
+  sl.iv = seg_v + ib * P * segcap;
+  sl.in_n = seg_n + ib * P;
+  sl.ok = seg_k + ob * P * segcap;
+  sl.ov = seg_v + ob * P * segcap;
+  sl.out_n = seg_n + ob * P;
+  sl.tab_off = c->at<uint32_t>(c->L.tab_off) + (size_t)(tfirst + first) * c->C;
+  sl.step0 = step0 + first;
+  sl.nsteps = steps;
+  sl.stats = c->at<uint64_t>(c->L.small_stats) + (size_t)j * c->R * kSmallStats;
+  return qmcs_launch(c->stream, &sl);
+}
+
+// Steps of the chunk with the LDS-resident step, one workgroup per store segment (Euler, the
+// comb).  A segment that outgrows what the step holds stops the launch at the first such step F;
+// the steps before F are then run again from the unchanged canonical store (the results are the
+// same) and the automatic mode leaves the small step for this trajectory.  On return kd =
+// completed steps (0 if not even the first step fits) and the store reflects them.  A head batch
+// (head->steps > 0) is the chain's first batch, already launched.
+int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc,
+              const SmallHead* head) {
+  const qmc::Counters before = c->last_hc;
+  const uint32_t step0 = c->step, nst = ch.nst;
+  const uint64_t segcap = c->L.segcap, P = c->L.P;
+  uint64_t* seg_k = c->at<uint64_t>(c->L.seg_k);
+  int2* seg_v = c->at<int2>(c->L.seg_v);
+  uint32_t* seg_n = c->at<uint32_t>(c->L.seg_n);
+  unsigned long long* dstop = c->at<unsigned long long>(c->L.small_fail);
+  uint64_t* dstats = c->at<uint64_t>(c->L.small_stats);
+  const uint64_t rows = (uint64_t)c->R;  // statistics rows of one batch
+  qmc::Counters* dcnt = c->counters();
+  SmallLaunch sl;
+  small_setup(c, ch.dtab, sl);
   auto batch = [&](uint32_t j, uint32_t first, uint32_t steps) {
-    const uint32_t ib = (j + 1) & 1, ob = j & 1;
-    sl.ck = j == 0 ? c->sk(0) : nullptr;
-    sl.cv = j == 0 ? c->sv(0) : nullptr;
-    sl.ik = seg_k + ib * P * segcap;
-    sl.iv = seg_v + ib * P * segcap;
-    sl.in_n = seg_n + ib * P;
-    sl.ok = seg_k + ob * P * segcap;
-    sl.ov = seg_v + ob * P * segcap;
-    sl.out_n = seg_n + ob * P;
-    sl.tab_off = c->at<uint32_t>(c->L.tab_off) + (size_t)(ch.first + first) * c->C;
-    sl.step0 = step0 + first;
-    sl.nsteps = steps;
-    sl.stats = dstats + (size_t)j * rows * kSmallStats;
-    return qmcs_launch(c->stream, &sl);
+    return small_batch(c, sl, ch.first, step0, j, first, steps);
   };
   // the segments batch jd - 1 wrote into the canonical store and the statistics of batches
   // [0, jd) into the counters; gated on the stop word of `epoch` when stop is given
   auto finish = [&](uint32_t jd, const unsigned long long* stop, uint32_t epoch) -> int {
     const uint32_t ob = (jd - 1) & 1;
-    HIPCHK(c, qmcs_gather(c->stream, seg_k + ob * P * segcap, seg_v + ob * P * segcap,
+    HIPCHK(c, qmcs_finish(c->stream, seg_k + ob * P * segcap, seg_v + ob * P * segcap,
                           seg_n + ob * P, segcap, c->R, c->sk(0), c->sv(0),
-                          &dcnt->n_store[c->cur], stop, epoch));
-    HIPCHK(c, qmcs_commit(c->stream, dcnt, dstats, (uint32_t)(jd * rows), stop, epoch));
+                          &dcnt->n_store[c->cur], dcnt, dstats, (uint32_t)(jd * rows), stop,
+                          epoch));
     return 0;
   };
   const bool prof = c->prof_whole();
-  if (prof) {
-    while (c->prof_ev.size() < 2) {
-      hipEvent_t ev;
-      HIPCHK(c, hipEventCreate(&ev));
-      c->prof_ev.push_back(ev);
-    }
-  }
-  uint64_t* pin_stop = reinterpret_cast<uint64_t*>(c->pinned_small + 4096);
   // One chain over steps [first, first + steps) with its gated gather and commit, then one
-  // synchronization (with the counters); jd = the batches whose results are committed, stop =
-  // the first step not taken, or ~0.
-  auto run_chain = [&](uint32_t first, uint32_t steps, uint32_t& jd, uint32_t& stop) -> int {
-    const uint32_t nb = (steps + kSmallBatch - 1) / kSmallBatch;
-    const uint32_t epoch = ++c->small_epoch;
-    sl.epoch = epoch;
-    if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[0], c->stream));
-    for (uint32_t j = 0; j < nb; ++j) {
-      const uint32_t a = j * kSmallBatch;
-      HIPCHK(c, batch(j, first + a, std::min(kSmallBatch, steps - a)));
+  // synchronization (with the counters); jd = the batches whose results are committed, done =
+  // their steps, stop = the first step not taken, or ~0.  With hd, its batch is the chain's
+  // first, already launched.
+  auto run_chain = [&](uint32_t first, uint32_t steps, uint32_t& jd, uint32_t& done,
+                       uint32_t& stop, const SmallHead* hd) -> int {
+    std::vector<uint32_t> bnd(1, 0);  // batch boundaries, relative to `first`
+    if (hd) bnd.push_back(std::min(hd->steps, steps));
+    while (bnd.back() < steps) bnd.push_back(std::min(bnd.back() + kSmallBatch, steps));
+    const uint32_t nb = (uint32_t)bnd.size() - 1;
+    const uint32_t epoch = hd ? hd->epoch : ++c->small_epoch;
+    const uint32_t j0 = hd ? 1u : 0u;  // the first batch launched here
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (prof && j0 < nb) {
+      int rc = timing_pair(c, ev0, ev1);
+      if (rc) return rc;
+      HIPCHK(c, hipEventRecord(ev0, c->stream));
     }
-    if (prof) HIPCHK(c, hipEventRecord(c->prof_ev[1], c->stream));
-    int rc = finish(nb, dstop, epoch);
+    sl.epoch = epoch;
+    for (uint32_t j = j0; j < nb; ++j) HIPCHK(c, batch(j, first + bnd[j], bnd[j + 1] - bnd[j]));
+    if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
+    int rc = finish(nb, dstop, epoch);  // also copies the stop word into the counters
     if (rc) return rc;
-    HIPCHK(c, hipMemcpyAsync(pin_stop, dstop, 8, hipMemcpyDeviceToHost, c->stream));
     rc = read_counters(c, hc);  // synchronizes the stream
     if (rc) return rc;
-    if (prof) {
-      float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]));
-      c->prof_ms[4] += ms;
-      c->prof_launches[4] += nb;
-    }
-    const uint64_t w = *pin_stop;
+    // the head batch and the rest are timed apart: the GPU may wait for the host between them
+    if (hd && hd->ev0) defer_timing(c, 4, hd->ev0, hd->ev1, 1);
+    if (ev0) defer_timing(c, 4, ev0, ev1, nb - j0);
+    const uint64_t w = hc.small_stop;
     if ((uint32_t)(w >> 32) != epoch) {
       jd = nb;
+      done = steps;
       stop = 0xFFFFFFFFu;
       return 0;
     }
@@ -1087,7 +1149,9 @@ int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
       c->broken = true;
       return fail(c, QMC_ERR_HIP, "small step: stop outside the chain");
     }
-    jd = (stop - s0) / kSmallBatch;  // complete batches, not committed yet
+    jd = 0;  // complete batches, not committed yet
+    while (jd < nb && bnd[jd + 1] <= stop - s0) ++jd;
+    done = bnd[jd];
     if (jd > 0) {
       rc = finish(jd, nullptr, 0);
       if (rc) return rc;
@@ -1096,15 +1160,14 @@ int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   };
   kd = 0;
   uint32_t jd = 0, stop = 0;
-  int rc = run_chain(0, nst, jd, stop);
+  int rc = run_chain(0, nst, jd, kd, stop, head && head->steps ? head : nullptr);
   if (rc) return rc;
-  kd = std::min<uint32_t>(jd * kSmallBatch, nst);
   if (stop != 0xFFFFFFFFu) {
     c->small_off = true;
     const uint32_t rest = stop - step0 - kd;  // steps of the stopped batch that every replica took
     if (rest > 0) {
-      uint32_t jd2 = 0, stop2 = 0;
-      rc = run_chain(kd, rest, jd2, stop2);
+      uint32_t jd2 = 0, done2 = 0, stop2 = 0;
+      rc = run_chain(kd, rest, jd2, done2, stop2, nullptr);
       if (rc) return rc;
       if (stop2 != 0xFFFFFFFFu) {
         c->broken = true;
@@ -1144,8 +1207,13 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
   // after its last merge, and times the merge class (2) beside it.
   const bool prof_step = c->prof_class == 5;
   const int32_t prof_k = prof_step ? 2 : c->prof_class;  // the class with per-step events
-  const uint32_t nev = 2 * nst + 2;
-  if ((prof_k >= 0 && prof_k <= 2) || prof_step) {
+  const uint32_t nev = 2 * nst;
+  hipEvent_t sev0 = nullptr, sev1 = nullptr;
+  if (prof_step) {
+    int rc = timing_pair(c, sev0, sev1);
+    if (rc) return rc;
+  }
+  if (prof_k >= 0 && prof_k <= 2) {
     while (c->prof_ev.size() < nev) {
       hipEvent_t ev;
       HIPCHK(c, hipEventCreate(&ev));
@@ -1162,7 +1230,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
     // The merge class's tile counts and count adjustments start from zero (the adjustments are
     // left zero by every completed step, not by one an error stopped).  The step sort uses no
     // look-back words; the whole-store sort after a pulse clears its own.
-    if (prof_step) ENQ(hipEventRecord(c->prof_ev[2 * nst], st_q));
+    if (prof_step) ENQ(hipEventRecord(sev0, st_q));
     ENQ(qmck_batch_begin(st_q, dcnt, c->at<uint64_t>(c->L.status), c->L.status_words, nullptr,
                          0, c->ghist(0), 2 * qmc::kMaxPasses * qmc::kRadixBins));
     auto mark = [&](int32_t cls, uint32_t k, int which) -> hipError_t {
@@ -1232,7 +1300,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
         ENQ(mark(0, k + 1, 1));
       }
     }
-    if (prof_step) ENQ(hipEventRecord(c->prof_ev[2 * nst + 1], st_q));
+    if (prof_step) ENQ(hipEventRecord(sev1, st_q));
 #undef ENQ
     return hipSuccess;
   };
@@ -1283,12 +1351,7 @@ int run_streamed(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc) {
       c->prof_launches[prof_k] += 1;
     }
   }
-  if (prof_step) {
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[2 * nst], c->prof_ev[2 * nst + 1]));
-    c->prof_ms[5] += ms;
-    c->prof_launches[5] += 1;
-  }
+  if (prof_step) defer_timing(c, 5, sev0, sev1, 1);
   kd = nst;
   if (hc.err) {
     const uint32_t es = hc.err_step;
@@ -1506,6 +1569,58 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     }
     return true;
   };
+  const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
+  // The LDS-resident step can start before every table of the call is built: its first batch
+  // (steps [0, B0)) is launched as soon as their tables are packed, and the host builds the rest
+  // while it runs.  A later table that fails, or that the step cannot take, only cancels that
+  // batch: it writes scratch segments, never the store or the counters.
+  SmallHead head;
+  size_t head_bytes = 0;
+  const uint32_t B0 = std::max<uint32_t>(2, std::min<uint32_t>(16, nsteps / 4));
+  const bool pipe = nsteps >= 8 && nsteps < 512 && !ab2 && !c->prop.kind && c->R <= c->L.P &&
+                    (c->path == 3 ||
+                     (c->path == 0 && !c->small_off && c->step >= c->streamed_until &&
+                      c->n_occ <= fused_max_keys && c->small_limit > 0 &&
+                      c->n_occ <= (uint64_t)c->R * c->small_limit));
+  auto prelaunch = [&](size_t used) -> int {
+    HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab), c->pinned, used, hipMemcpyHostToDevice,
+                             c->stream));
+    uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
+    std::memcpy(po, offA.data(), (size_t)B0 * NC * 4);
+    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), po, (size_t)B0 * NC * 4,
+                             hipMemcpyHostToDevice, c->stream));
+    std::vector<int64_t> q(2 * (size_t)c->R, 0);
+    for (uint32_t r = 0; r < c->R; ++r) q[r] = qs1[r];
+    int rc = upload_qshift(c, q);
+    if (rc) return rc;
+    SmallLaunch sl;
+    small_setup(c, c->at<uint8_t>(c->L.tab), sl);
+    head.epoch = ++c->small_epoch;
+    sl.epoch = head.epoch;
+    if (c->prof_whole()) {
+      rc = timing_pair(c, head.ev0, head.ev1);
+      if (rc) return rc;
+      HIPCHK(c, hipEventRecord(head.ev0, c->stream));
+    }
+    HIPCHK(c, small_batch(c, sl, 0, c->step, 0, 0, B0));
+    if (head.ev1) HIPCHK(c, hipEventRecord(head.ev1, c->stream));
+    head.steps = B0;
+    head_bytes = used;
+    return QMC_OK;
+  };
+  // A launched first batch that will not be continued: wait for it, return its events.
+  auto drop_head = [&]() -> int {
+    if (!head.steps) return QMC_OK;
+    head.steps = 0;
+    if (head.ev0) {
+      c->ev_free.push_back(head.ev0);
+      c->ev_free.push_back(head.ev1);
+      head.ev0 = head.ev1 = nullptr;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return QMC_OK;
+  };
+  int pre_rc = QMC_OK;
   {
     // Long calls build on a few host threads (tables are independent), each packing its run of
     // steps into its own slice of the staging area while it fits (the first window); every
@@ -1546,6 +1661,11 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
         if (ab2 && k >= euler_first) q.max_bytes = std::max(q.max_bytes, pack_table(TB, nullptr));
         if (q.stored == k && k < wmax && pack_step(k, k, TA, TB, q.base, q.used, slice))
           q.stored = k + 1;
+        if (pipe && nth == 1 && k + 1 == B0 && q.stored == B0 &&
+            q.max_bytes <= kPersistTableBytes) {
+          pre_rc = prelaunch(q.used);
+          if (pre_rc) return;
+        }
       }
     };
     std::vector<std::thread> pool;
@@ -1558,8 +1678,13 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     }
     part(0);
     for (std::thread& th : pool) th.join();
+    if (pre_rc) return pre_rc;
     for (const Part& q : parts)
-      if (q.code) return fail(c, q.code, "step " + std::to_string(c->step + q.bad) + ": " + q.why);
+      if (q.code) {
+        int rc = drop_head();
+        if (rc) return rc;
+        return fail(c, q.code, "step " + std::to_string(c->step + q.bad) + ": " + q.why);
+      }
     // the first window: every step up to the first part that could not store all of its steps
     std::vector<std::pair<size_t, size_t>> spans;
     win1 = 0;
@@ -1571,20 +1696,35 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
       }
     }
     if (win1 == 0) return fail(c, QMC_ERR_ARG, "step tables larger than the table area");
-    int rc = upload_window(spans);
-    if (rc) return rc;
+    if (head.steps) {
+      // the head batch's tables and offsets are on the device: the rest of the window
+      const Part& q = parts[0];
+      if (q.used > head_bytes)
+        HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab) + head_bytes, c->pinned + head_bytes,
+                                 q.used - head_bytes, hipMemcpyHostToDevice, c->stream));
+      uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
+      const size_t n0 = (size_t)B0 * NC, nw = (size_t)(win1 - win0) * NC;
+      std::memcpy(po + n0, offA.data() + n0, (nw - n0) * 4);
+      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off) + n0, po + n0, (nw - n0) * 4,
+                               hipMemcpyHostToDevice, c->stream));
+    } else {
+      int rc = upload_window(spans);
+      if (rc) return rc;
+    }
   }
   const uint32_t first_step = c->step;
-  const uint64_t fused_max_keys = (uint64_t)c->L.P * kFusedKeysPerSegment;
   const bool fused_fits = max_tbytes <= kPersistTableBytes;
   if (c->path == 1 && !fused_fits)
     return fail(c, QMC_ERR_ARG, "step table larger than the fused kernel takes; use the "
                                 "automatic or streamed path");
   if (c->path == 1 && c->prop.kind)
     return fail(c, QMC_ERR_ARG, "spawn proposals run on the streamed path");
-  if (c->path == 3 && (ab2 || c->prop.kind || !fused_fits || c->R > c->L.P))
+  if (c->path == 3 && (ab2 || c->prop.kind || !fused_fits || c->R > c->L.P)) {
+    int rc = drop_head();
+    if (rc) return rc;
     return fail(c, QMC_ERR_ARG, "the LDS-resident step runs the Euler step and the comb with "
                                 "step tables of at most 8 KB, one workgroup per segment");
+  }
   uint32_t last_local_fail = 0xFFFFFFFFu;
   int32_t shift_mode = -1;  // shifts on the device: 0 single Euler term, 1 both AB2 terms
   while (c->step < first_step + nsteps) {
@@ -1598,6 +1738,10 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     const bool small = c->path == 3 ||
                        (c->path == 0 && fused && !ab2 && !c->small_off && c->R <= c->L.P &&
                         c->small_limit > 0 && c->n_occ <= (uint64_t)c->R * c->small_limit);
+    if (head.steps && !(small && k0 == 0)) {
+      int rc = drop_head();
+      if (rc) return rc;
+    }
     if (shift_mode != (int32_t)two) {
       // shifts of this chunk's tables
       std::vector<int64_t> q(2 * (size_t)c->R, 0);
@@ -1642,7 +1786,9 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     qmc::Counters hc;
     uint32_t kd = 0, reason = 0;
     if (small) {
-      int rc = run_small(c, ch, kd, hc);
+      const SmallHead hd = head;
+      head = SmallHead{};
+      int rc = run_small(c, ch, kd, hc, hd.steps ? &hd : nullptr);
       if (rc) return rc;
       if (kd == 0) {
         if (c->path == 3)
@@ -2260,6 +2406,8 @@ int qmc_counters(qmc_ctx* c, qmc_stats* out) {
 
 int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
   if (!c || kernel_class < -1 || kernel_class >= kProfClasses) return QMC_ERR_ARG;
+  int rc = settle_timings(c);  // (discarded below)
+  if (rc) return rc;
   c->prof_class = kernel_class;
   for (int k = 0; k < kProfClasses; ++k) {
     c->prof_ms[k] = 0.0;
@@ -2272,6 +2420,8 @@ int qmc_profile(qmc_ctx* c, int32_t kernel_class) {
 int qmc_profile_read_class(qmc_ctx* c, int32_t kernel_class, double* ms, uint64_t* launches,
                            qmc_stats* covered) {
   if (!c || kernel_class < 0 || kernel_class >= kProfClasses) return QMC_ERR_ARG;
+  int rc = settle_timings(c);
+  if (rc) return rc;
   if (ms) *ms = c->prof_ms[kernel_class];
   if (launches) *launches = c->prof_launches[kernel_class];
   if (covered) *covered = c->prof_cover[kernel_class];
@@ -2329,6 +2479,11 @@ void qmc_destroy(qmc_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : c->ev_free) (void)hipEventDestroy(ev);
+  for (const qmc_ctx::PendingTime& t : c->ev_pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);

@@ -40,12 +40,13 @@ struct SmallLaunch {
 extern "C" {
 // Launches one batch (one workgroup per segment); it does nothing once the chain stopped.
 int qmcs_launch(hipStream_t st, const SmallLaunch* L);
-// Gathers segments [0, n_segments) (stride segcap, counts seg_n) into the canonical store and
-// writes its size to *count; adds nrows rows of per-segment batch statistics to the counters.
-// Both do nothing when the chain of `epoch` stopped (stop == null: they always run).
-int qmcs_gather(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
+// The end of a chain: gathers segments [0, n_segments) (stride segcap, counts seg_n) into the
+// canonical store, writes its size to *count and adds nrows rows of per-segment batch statistics
+// to the counters, unless the chain of `epoch` stopped (stop == null: always); with stop given it
+// also copies the stop word into the counters (Counters::small_stop), so that one read of the
+// counters returns both.
+int qmcs_finish(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
                 uint64_t segcap, uint32_t n_segments, uint64_t* ck, int2* cv, uint64_t* count,
-                const unsigned long long* stop, uint32_t epoch);
-int qmcs_commit(hipStream_t st, void* counters, const uint64_t* stats, uint32_t nrows,
+                void* counters, const uint64_t* stats, uint32_t nrows,
                 const unsigned long long* stop, uint32_t epoch);
 }

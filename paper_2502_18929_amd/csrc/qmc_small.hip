@@ -473,17 +473,22 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
   }
 }
 
-// The last batch's segments into the canonical store (one workgroup per segment), unless the
-// chain stopped (stop == null: always).
-__global__ __launch_bounds__(256) void k_small_gather(const uint64_t* __restrict__ sk,
+// The end of a chain (one launch): the last batch's segments into the canonical store, one
+// workgroup per segment, and the statistics of the completed batches into the counters by
+// workgroup 0 -- neither when the chain stopped (stop == null: always); workgroup 0 also copies
+// the stop word into the counters, for the host's one read of them.
+__global__ __launch_bounds__(256) void k_small_finish(const uint64_t* __restrict__ sk,
                                                       const int2* __restrict__ sv,
                                                       const uint32_t* __restrict__ seg_n,
                                                       uint64_t segcap, uint64_t* __restrict__ ck,
                                                       int2* __restrict__ cv, uint64_t* count,
+                                                      Counters* cnt, const uint64_t* stats,
+                                                      uint32_t nrows,
                                                       const unsigned long long* stop,
                                                       uint32_t epoch) {
   __shared__ uint64_t s_off;
   __shared__ uint32_t s_skip;
+  __shared__ unsigned long long s_sum[kSmallStats];
   const uint32_t p = blockIdx.x, R = gridDim.x;
   if (threadIdx.x == 0) {
     s_skip = stop && chain_stopped(stop, epoch);
@@ -491,7 +496,9 @@ __global__ __launch_bounds__(256) void k_small_gather(const uint64_t* __restrict
     for (uint32_t q = 0; q < p; ++q) o += seg_n[q];
     s_off = o;
     if (!s_skip && p == R - 1) *count = o + seg_n[p];
+    if (stop && p == 0) cnt->small_stop = *stop;
   }
+  if (p == 0 && threadIdx.x < (uint32_t)kSmallStats) s_sum[threadIdx.x] = 0;
   __syncthreads();
   if (s_skip) return;
   const uint64_t off = s_off, n = seg_n[p];
@@ -501,16 +508,7 @@ __global__ __launch_bounds__(256) void k_small_gather(const uint64_t* __restrict
     ck[off + i] = k[i];
     cv[off + i] = v[i];
   }
-}
-
-// The statistics of the completed batches into the counters (one workgroup), unless the chain
-// stopped (stop == null: always).
-__global__ void k_small_commit(Counters* cnt, const uint64_t* stats, uint32_t nrows,
-                               const unsigned long long* stop, uint32_t epoch) {
-  __shared__ unsigned long long s_sum[kSmallStats];
-  if (stop && chain_stopped(stop, epoch)) return;  // one word, read the same by every thread
-  if (threadIdx.x < (uint32_t)kSmallStats) s_sum[threadIdx.x] = 0;
-  __syncthreads();
+  if (p != 0) return;  // block-uniform
   for (uint32_t i = threadIdx.x; i < nrows * (uint32_t)kSmallStats; i += blockDim.x)
     atomicAdd(&s_sum[i % kSmallStats], (unsigned long long)stats[i]);
   __syncthreads();
@@ -563,18 +561,12 @@ int qmcs_launch(hipStream_t st, const SmallLaunch* L) {
   return (int)hipGetLastError();
 }
 
-int qmcs_gather(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
+int qmcs_finish(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
                 uint64_t segcap, uint32_t n_segments, uint64_t* ck, int2* cv, uint64_t* count,
+                void* counters, const uint64_t* stats, uint32_t nrows,
                 const unsigned long long* stop, uint32_t epoch) {
-  hipLaunchKernelGGL(k_small_gather, dim3(n_segments), dim3(256), 0, st, sk, sv, seg_n, segcap,
-                     ck, cv, count, stop, epoch);
-  return (int)hipGetLastError();
-}
-
-int qmcs_commit(hipStream_t st, void* counters, const uint64_t* stats, uint32_t nrows,
-                const unsigned long long* stop, uint32_t epoch) {
-  hipLaunchKernelGGL(k_small_commit, dim3(1), dim3(256), 0, st, (Counters*)counters, stats,
-                     nrows, stop, epoch);
+  hipLaunchKernelGGL(k_small_finish, dim3(n_segments), dim3(256), 0, st, sk, sv, seg_n, segcap,
+                     ck, cv, count, (Counters*)counters, stats, nrows, stop, epoch);
   return (int)hipGetLastError();
 }
 

@@ -154,3 +154,51 @@ def test_small_limits_change_nothing(B, orc):
         g = B.QMC.from_workload(w, store_capacity=1 << 17, spawn_capacity=1 << 19)
         g.small_limit(1025)
     assert e.value.code == B.QMC_ERR_ARG
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("lim", [4, 16, 60])
+def test_small_head_batch_calls(B, orc, lim):
+    """Calls of 8 to 511 steps, whose first batch is launched while the rest of the call's tables
+    are built, on ghz20_nm with key limits that stop the chain inside that first batch or in a
+    later one (the steps up to the stop are run again, the rest go to the fused kernel): the
+    stores equal the oracle's after every call, and so do the counters."""
+    w = W.config_ghz20_nm()
+    g = B.QMC.from_workload(w, store_capacity=1 << 17, spawn_capacity=1 << 19)
+    g.small_limit(lim)
+    o = orc.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
+                   w.init_im)
+    g.profile("small")
+    a = 0
+    for k in (8, 9, 20, 37, 100, 200, 511):
+        g.step(w.s[a:a + k], w.gamma[a:a + k])
+        o.step(w.s[a:a + k], w.gamma[a:a + k], threads=16)
+        a += k
+        _same(g, o, w.n_replicas, f"limit {lim}, step {a}")
+    ms, n, cov = g.profile_read()
+    assert n > 0 and 0 < cov["steps"] < a
+    gc, oc = g.counters(), o.counters()
+    assert gc["walker_steps"] == oc["walker_steps"] and gc["key_steps"] == oc["key_steps"]
+    assert gc["spawn_steps"] == oc["child_steps"]
+
+
+def test_small_head_batch_cancelled_by_a_later_table(B, orc):
+    """A bad weight in a table built after the first batch was launched: the call fails naming
+    that step, and the store and counters are those before the call."""
+    w = W.config_ghz4()
+    g = B.QMC.from_workload(w, store_capacity=256, spawn_capacity=4096)
+    o = orc.Oracle(w.n, w.n_replicas, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re,
+                   w.init_im)
+    g.step(w.s[:10], w.gamma[:10])
+    o.step(w.s[:10], w.gamma[:10])
+    before = g.counters()
+    s = np.array(w.s[10:50])
+    s[30, 0] = np.nan
+    with pytest.raises(B.QMCError) as e:
+        g.step(s, w.gamma[10:50])
+    assert e.value.code == B.QMC_ERR_ARG and "step 40" in str(e.value)
+    _same(g, o, w.n_replicas, "after the failed call")
+    assert g.counters() == before
+    g.step(w.s[10:50], w.gamma[10:50])
+    o.step(w.s[10:50], w.gamma[10:50])
+    _same(g, o, w.n_replicas, "step 50")

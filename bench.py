@@ -351,7 +351,7 @@ def main():
             # statistics of the method's own plain run (untimed), then back to the initial state
             from paper_2502_18929_amd import proposal as PR
             at = list(range(w.nsteps // 16, w.nsteps, w.nsteps // 16))
-            mlp, train_corr = PR.train(g, w, at[-1], at)
+            mlp, train_corr = PR.train(g, w, at[-1])
             for r in range(w.n_replicas):
                 g.import_(r, *init[r], step=0)
         prop = (args.proposal, args.proposal_samples, mlp)

@@ -103,8 +103,11 @@ typedef struct {
 
 typedef struct qmc_ctx qmc_ctx;
 
-/* Bytes of device workspace a context with this configuration needs.  QMC_ERR_ARG on an
- * invalid configuration. */
+/* Bytes of device workspace a context with this configuration needs: the population vectors
+ * N(t) of eq. (3) for every replica (16 bytes per occupied key of the column-stacked density
+ * matrix of eq. (2), store_capacity keys per replica, in two buffers), one step's child records
+ * (spawn_capacity per replica) and the per-step working areas.  QMC_ERR_ARG on an invalid
+ * configuration. */
 int qmc_workspace_bytes(const qmc_config* cfg, const qmc_model* model, size_t* bytes);
 
 /* Create a context (eq. (3) paragraph: N(0) := N^diag rho(0)).  keys/re/im are the n0 initial
@@ -343,13 +346,16 @@ int qmc_observe_noalloc(uint32_t n_qubits, uint32_t n_replicas, const uint64_t* 
                         const int32_t* d_vals, uint64_t n, const int64_t* nd0_re,
                         const qmc_obs_spec* spec, qmc_obs_out* out, void* hip_stream);
 
-/* Copy one replica's store to host arrays (keys ascending).  *n receives the size; if it
- * exceeds cap nothing is copied and QMC_ERR_ARG is returned. */
+/* Copy one replica's store -- its population vector N(t) of eq. (3), the occupied keys of the
+ * column-stacked density matrix of eq. (2) with their Gaussian-integer walker counts -- to host
+ * arrays (keys ascending).  *n receives the size; if it exceeds cap nothing is copied and
+ * QMC_ERR_ARG is returned. */
 int qmc_export(qmc_ctx* ctx, uint32_t replica, uint64_t* keys, int32_t* re, int32_t* im,
                uint64_t cap, uint64_t* n);
 
-/* Replace one replica's store (same rules as qmc_init's records) and set the step counter
- * of the context to `step` (the Philox counter of the next step).  N(s-1) (AB2) is left as it
+/* Replace one replica's store (its population vector N(t) of eq. (3); same rules as qmc_init's
+ * records) and set the step counter of the context to `step` (the Philox counter of the next
+ * step: the draws are keyed on the walkers, so (store, step) is the whole state of a replica).  N(s-1) (AB2) is left as it
  * is; qmc_set_prev replaces it. */
 int qmc_import(qmc_ctx* ctx, uint32_t replica, const uint64_t* keys, const int32_t* re,
                const int32_t* im, uint64_t n, uint32_t step);

@@ -3,13 +3,13 @@
 The proposal (C ABI qmc_set_proposal, kind 3) draws a parent's channels with probabilities from
 integer scores of an int8 MLP of the key bits.  Its ideal target is the heat-bath choice of the
 End Matter's spawn step: a channel's probability proportional to |L| of that column entry.  The
-statistics come from the library itself: a plain run of the workload, the keys its walkers
-occupy at a few steps, and at each such key the magnitude |Re c_g| + |Im c_g| of every
-off-diagonal column group's Q32 coefficient under that step's quantized table (the per-walker
-spawn amount of the group).  A float MLP with the network's shape is fitted to these targets
-(mean squared error, Adam) and then quantized to the ABI's integers: w1 int8 [32, 64],
-b1 int32 [32], the hidden shift, w2 int8 [64, 32], b2 int32 [64].  Scores are only compared with
-each other, so the overall scale of the quantized network is free.
+statistics come from the library itself: a plain run of the workload with the library's
+spawn-event log on, whose off-diagonal events are pooled per parent key into the walkers spawned
+into each column group, as fractions of the key's total.  A float MLP with the network's shape
+is fitted to these targets (mean squared error, Adam) and then quantized to the ABI's integers:
+w1 int8 [32, 64], b1 int32 [32], the hidden shift, w2 int8 [64, 32], b2 int32 [64].  Scores are
+only compared with each other, so the overall scale of the quantized network is free.  The
+deeper network (kind 4, below) is trained on the same log, pooled per (key, step channels).
 """
 import numpy as np
 
@@ -28,47 +28,35 @@ def features(keys, nbits):
     return x
 
 
-def group_magnitudes(table, keys):
-    """|Re c_g(key)| + |Im c_g(key)| of the off-diagonal groups g = 1.. of a quantized table, for
-    every key: c_g = sum over the group's terms of (-1)^popcount(zmask & key) q."""
-    keys = np.asarray(keys, dtype=np.uint64)
-    gs = table["gstart"].astype(np.int64)
-    G = len(table["gxmask"])
-    out = np.zeros((len(keys), max(G - 1, 0)), dtype=np.float64)
-    for g in range(1, G):
-        cre = np.zeros(len(keys), dtype=np.int64)
-        cim = np.zeros(len(keys), dtype=np.int64)
-        for t in range(gs[g], gs[g + 1]):
-            par = np.bitwise_count(keys & np.uint64(table["zmask"][t])) & 1
-            sgn = 1 - 2 * par.astype(np.int64)
-            cre += sgn * int(table["q"][t, 0])
-            cim += sgn * int(table["q"][t, 1])
-        out[:, g - 1] = np.abs(cre) + np.abs(cim)
-    return out
+def pooled_fractions(events, n):
+    """Per parent key of logged spawn events (the library's event log), the walkers (|re| + |im|)
+    spawned into each of the first N_OUT column groups, as fractions of the key's total over
+    those groups; returns (keys, fractions, totals)."""
+    kmask = np.uint64((1 << (2 * n)) - 1) if 2 * n < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    keep = (events["group"] >= 1) & (events["group"] <= N_OUT)
+    ev = events[keep]
+    key = ev["key"] & kmask
+    walkers = np.abs(ev["re"].astype(np.int64)) + np.abs(ev["im"].astype(np.int64))
+    uk, inv = np.unique(key, return_inverse=True)
+    Y = np.zeros((len(uk), N_OUT))
+    np.add.at(Y, (inv, ev["group"].astype(np.int64) - 1), walkers)
+    tot = Y.sum(axis=1)
+    Y /= np.maximum(tot, 1)[:, None]
+    return uk, Y, tot
 
 
-def spawn_statistics(ctx, w, stop, at, replica=0):
-    """Run the plain step of workload `w` on context `ctx` from its current state up to `stop`
-    and collect (keys, targets) at the steps in `at`: the occupied keys of one replica and the
-    per-group magnitudes of that step's table there (first N_OUT groups, zero-padded)."""
-    keys_all, tgt_all = [], []
+def spawn_statistics(ctx, w, stop, capacity=16_000_000):
+    """Run the plain step of workload `w` on context `ctx` (streamed, with the library's spawn
+    event log) from its current state up to `stop`, and pool the logged events per parent key
+    (pooled_fractions): the training keys and targets of the network."""
+    ctx.log_spawns(capacity)
     s0 = ctx.counters()["step"]
-    for a in sorted(at):
-        if a > s0:
-            ctx.run_workload(w, s0, a)
-            s0 = a
-        k, _, _ = ctx.export(replica)
-        if len(k) == 0:
-            continue
-        tab = binding.coeff_table(w.n, w.dt, w.h, w.lops, w.s[a], w.gamma[a])
-        m = group_magnitudes(tab, k)[:, :N_OUT]
-        t = np.zeros((len(k), N_OUT))
-        t[:, :m.shape[1]] = m
-        keys_all.append(k)
-        tgt_all.append(t)
-    if s0 < stop:
+    if stop > s0:
         ctx.run_workload(w, s0, stop)
-    return np.concatenate(keys_all), np.concatenate(tgt_all)
+    ev, _ = ctx.log_read()
+    ctx.log_spawns(0)
+    keys, Y, _ = pooled_fractions(ev, w.n)
+    return keys, Y
 
 
 def fit(keys, targets, nbits, iters=400, lr=3e-3, batch=2048, seed=0):
@@ -124,11 +112,11 @@ def scores(mlp, keys, nbits):
     return h @ w2.T.astype(np.int64) + b2
 
 
-def train(ctx, w, stop, at, seed=0):
-    """Statistics from a plain run of `w` on `ctx` (advanced to `stop`), then fit and quantize.
-    Returns the MLP tuple for QMC.set_proposal('mlp', ...) and the fit's correlation between
-    the integer scores and the targets on the training keys."""
-    keys, tgt = spawn_statistics(ctx, w, stop, at)
+def train(ctx, w, stop, seed=0):
+    """Spawn statistics of a plain run of `w` on `ctx` (advanced to `stop`), then fit and
+    quantize.  Returns the MLP tuple for QMC.set_proposal('mlp', ...) and the fit's correlation
+    between the integer scores and the targets on the training keys."""
+    keys, tgt = spawn_statistics(ctx, w, stop)
     nbits = 2 * w.n
     params = fit(keys, tgt, nbits, seed=seed)
     mlp = quantize(params, keys, nbits)

@@ -1,10 +1,12 @@
-"""Host-side helpers of the proposal trainer (paper_2502_18929_amd.proposal) against the oracle:
-the per-group coefficient magnitudes are the oracle's quantized column entries, and the
-quantized network's integer scores are the oracle's MLP scores."""
+"""Host-side helpers of the proposal trainer (paper_2502_18929_amd.proposal): spawn events pooled
+per parent key against a count event by event, and the quantized network's integer scores
+against the oracle's MLP scores."""
 import numpy as np
 import pytest
 
 from paper_2502_18929_amd import binding, proposal as PR, workloads as W
+
+_EV = np.dtype([("key", "<u8"), ("step", "<u4"), ("group", "<u4"), ("re", "<i4"), ("im", "<i4")])
 
 
 @pytest.fixture(scope="module")
@@ -15,23 +17,31 @@ def lib_built():
     binding.lib()
 
 
-@pytest.mark.parametrize("seed", range(3))
-def test_group_magnitudes_are_the_column_entries(orc, lib_built, seed):
-    rng = np.random.default_rng(1700 + seed)
-    n = 3
-    h, lops = W.random_model(n, rng, n_h=5, n_l=3)
-    s = rng.normal(size=len(h))
-    gam = np.abs(rng.normal(size=len(lops)))
-    tab = binding.coeff_table(n, 0.01, h, lops, s, gam)
-    keys = np.arange(1 << (2 * n), dtype=np.uint64)
-    m = PR.group_magnitudes(tab, keys)
-    o = orc.Oracle(n, 1, 1, 0.01, h, lops, keys[:1], np.ones(1, np.int32), np.zeros(1, np.int32))
-    for key in keys[::5]:
-        tk, v = o.column_q(s, gam, int(key))
-        col = {int(t): abs(int(a)) + abs(int(b)) for t, (a, b) in zip(tk, v)}
-        for g in range(1, len(tab["gxmask"])):
-            want = col.get(int(key) ^ int(tab["gxmask"][g]), 0)
-            assert m[int(key), g - 1] == want
+def test_pooled_fractions_by_brute_force():
+    """Spawn events pooled per parent key: walkers per column group over the key's total,
+    counted here event by event; groups past N_OUT and the diagonal are left out."""
+    rng = np.random.default_rng(1700)
+    n = 5
+    m = 4000
+    ev = np.zeros(m, dtype=_EV)
+    ev["key"] = (rng.integers(0, 40, size=m).astype(np.uint64) |
+                 (rng.integers(0, 4, size=m).astype(np.uint64) << np.uint64(2 * n)))
+    ev["step"] = rng.integers(0, 100, size=m)
+    ev["group"] = rng.integers(0, PR.N_OUT + 3, size=m)
+    ev["re"] = rng.integers(-5, 6, size=m)
+    ev["im"] = rng.integers(-5, 6, size=m)
+    keys, Y, tot = PR.pooled_fractions(ev, n)
+    want = {}
+    for e in ev:
+        g = int(e["group"])
+        if 1 <= g <= PR.N_OUT:
+            k = int(e["key"]) & ((1 << (2 * n)) - 1)
+            want.setdefault(k, np.zeros(PR.N_OUT))[g - 1] += abs(int(e["re"])) + abs(int(e["im"]))
+    assert sorted(want) == [int(k) for k in keys]
+    for i, k in enumerate(keys):
+        row = want[int(k)]
+        assert tot[i] == row.sum()
+        assert np.allclose(Y[i], row / max(row.sum(), 1))
 
 
 def test_quantized_scores_are_the_oracle_network(orc, lib_built):
@@ -53,7 +63,6 @@ def test_quantized_scores_are_the_oracle_network(orc, lib_built):
 
 # ---- the deeper network's trainer ------------------------------------------------------------
 
-_EV = np.dtype([("key", "<u8"), ("step", "<u4"), ("group", "<u4"), ("re", "<i4"), ("im", "<i4")])
 
 
 def test_deep_features_are_key_signs_then_channel_bits():

@@ -31,7 +31,7 @@ def features(keys, nbits):
 def pooled_fractions(events, n):
     """Per parent key of logged spawn events (the library's event log), the walkers (|re| + |im|)
     spawned into each of the first N_OUT column groups, as fractions of the key's total over
-    those groups; returns (keys, fractions, totals)."""
+    those groups; returns (keys, fractions, totals, events per key)."""
     kmask = np.uint64((1 << (2 * n)) - 1) if 2 * n < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
     keep = (events["group"] >= 1) & (events["group"] <= N_OUT)
     ev = events[keep]
@@ -42,7 +42,7 @@ def pooled_fractions(events, n):
     np.add.at(Y, (inv, ev["group"].astype(np.int64) - 1), walkers)
     tot = Y.sum(axis=1)
     Y /= np.maximum(tot, 1)[:, None]
-    return uk, Y, tot
+    return uk, Y, tot, np.bincount(inv, minlength=len(uk))
 
 
 def spawn_statistics(ctx, w, stop, capacity=16_000_000):
@@ -55,13 +55,21 @@ def spawn_statistics(ctx, w, stop, capacity=16_000_000):
         ctx.run_workload(w, s0, stop)
     ev, _ = ctx.log_read()
     ctx.log_spawns(0)
-    keys, Y, _ = pooled_fractions(ev, w.n)
-    return keys, Y
+    keys, Y, _, nev = pooled_fractions(ev, w.n)
+    return keys, Y, nev
 
 
-def fit(keys, targets, nbits, iters=400, lr=3e-3, batch=2048, seed=0):
-    """Float MLP (N_IN -> N_HIDDEN relu -> N_OUT) fitted to targets scaled to [0, 1]."""
+def fit(keys, targets, nbits, iters=400, lr=3e-3, batch=2048, seed=0, weights=None):
+    """Float MLP (N_IN -> N_HIDDEN relu -> N_OUT) fitted to targets scaled to [0, 1], each key
+    drawn into the minibatches in proportion to its weight (default: all alike).  With a key's
+    fractions pooled from its spawn events and the weight its number of events, this is the
+    least-squares fit over the individual events, whose expectation is the key's spawn
+    fractions."""
     rng = np.random.default_rng(seed)
+    prob = None
+    if weights is not None:
+        prob = np.asarray(weights, dtype=np.float64)
+        prob = prob / prob.sum()
     X = features(keys, nbits).astype(np.float64)
     Y = targets / max(float(targets.max()), 1e-300)
     params = [rng.normal(0, 1 / np.sqrt(max(nbits, 1)), (N_HIDDEN, N_IN)), np.zeros(N_HIDDEN),
@@ -69,7 +77,8 @@ def fit(keys, targets, nbits, iters=400, lr=3e-3, batch=2048, seed=0):
     m = [np.zeros_like(p) for p in params]
     v = [np.zeros_like(p) for p in params]
     for it in range(1, iters + 1):
-        idx = rng.integers(0, len(X), size=min(batch, len(X)))
+        idx = (rng.integers(0, len(X), size=min(batch, len(X))) if prob is None else
+               rng.choice(len(X), size=min(batch, len(X)), p=prob))
         x, y = X[idx], Y[idx]
         W1, b1, W2, b2 = params
         a = x @ W1.T + b1
@@ -116,9 +125,9 @@ def train(ctx, w, stop, seed=0):
     """Spawn statistics of a plain run of `w` on `ctx` (advanced to `stop`), then fit and
     quantize.  Returns the MLP tuple for QMC.set_proposal('mlp', ...) and the fit's correlation
     between the integer scores and the targets on the training keys."""
-    keys, tgt = spawn_statistics(ctx, w, stop)
+    keys, tgt, nev = spawn_statistics(ctx, w, stop)
     nbits = 2 * w.n
-    params = fit(keys, tgt, nbits, seed=seed)
+    params = fit(keys, tgt, nbits, seed=seed, weights=nev)
     mlp = quantize(params, keys, nbits)
     sc = scores(mlp, keys, nbits)[:, :tgt.shape[1]].astype(np.float64).ravel()
     tv = tgt.ravel()

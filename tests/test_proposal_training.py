@@ -30,17 +30,18 @@ def test_pooled_fractions_by_brute_force():
     ev["group"] = rng.integers(0, PR.N_OUT + 3, size=m)
     ev["re"] = rng.integers(-5, 6, size=m)
     ev["im"] = rng.integers(-5, 6, size=m)
-    keys, Y, tot = PR.pooled_fractions(ev, n)
-    want = {}
+    keys, Y, tot, nev = PR.pooled_fractions(ev, n)
+    want, cnt = {}, {}
     for e in ev:
         g = int(e["group"])
         if 1 <= g <= PR.N_OUT:
             k = int(e["key"]) & ((1 << (2 * n)) - 1)
             want.setdefault(k, np.zeros(PR.N_OUT))[g - 1] += abs(int(e["re"])) + abs(int(e["im"]))
+            cnt[k] = cnt.get(k, 0) + 1
     assert sorted(want) == [int(k) for k in keys]
     for i, k in enumerate(keys):
         row = want[int(k)]
-        assert tot[i] == row.sum()
+        assert tot[i] == row.sum() and nev[i] == cnt[int(k)]
         assert np.allclose(Y[i], row / max(row.sum(), 1))
 
 

@@ -224,9 +224,13 @@ def roofline(kind, workload, prof_ms, prof_n, cov):
     avg_ms = prof_ms / prof_n if prof_n else None
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if prof_n and prof_ms > 0 else 0.0
     spl = cov["steps"] / prof_n if prof_n else None
+    # the per-step latency of the class (the honest measure where a step's bytes take far less
+    # HBM time than its chain of dependent operations)
+    us_step = avg_ms * 1e3 / spl if prof_n and spl else None
     return {"bound": "hbm", "kernel": KERNEL_NAMES[kind], "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": profiled_traffic(kind, workload, spl), "avg_launch_ms": avg_ms,
+            "kernel_us_per_step": us_step,
             "launches": prof_n, "steps_covered": cov["steps"], "steps_per_launch": spl,
             "algorithmic_bytes_per_launch": per_launch,
             "step_bytes_per_launch": step_bytes(cov) / prof_n if prof_n else None,

@@ -163,7 +163,7 @@ int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma
  * tables above 8 KB or more segments than co-resident workgroups).  QMC_ERR_ARG otherwise. */
 int qmc_step_path(qmc_ctx* ctx, int32_t path);
 
-/* Keys per replica up to which the automatic path takes the LDS-resident step (default 256;
+/* Keys per replica up to which the automatic path takes the LDS-resident step (default 384;
  * 0 = never; at most QMC_SMALL_MAX_KEYS, else QMC_ERR_ARG).  One workgroup then carries a whole
  * replica, so the limit trades the fused kernel's per-step grid synchronization against the
  * work of one workgroup; it changes no result. */

@@ -43,7 +43,7 @@ constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct wit
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
 constexpr int kProfClasses = 6;            // kernel classes qmc_profile times
-constexpr uint32_t kSmallAutoKeys = 256;   // default of qmc_small_limit
+constexpr uint32_t kSmallAutoKeys = 384;   // default of qmc_small_limit
 // batches of the LDS-resident step in one chain (a window of steps)
 constexpr uint32_t kSmallBatches = (kMaxChunkSteps + kSmallBatch - 1) / kSmallBatch;
 

@@ -6,7 +6,7 @@ trajectory.  A step is one Euler step of the population dynamics for all replica
 coefficient table, death/cloning, spawn, annihilation by key).  Synthetic inputs; the initial
 state is resident on the GPU before timing starts.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the step runs on one GPU.
 """
 from __future__ import annotations
 
@@ -316,7 +316,7 @@ def main():
     if args.pulse_width is not None and (args.workload != "dd12" or args.integrator != "euler"):
         ap.error("--pulse-width applies to dd12 with the Euler step (AB2 needs a uniform step)")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(replicas and key-space shards would each map to one GPU).", file=sys.stderr)
         sys.exit(2)
     if args.compare_proposals:

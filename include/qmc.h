@@ -141,7 +141,9 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
 /* Advance every replica by nsteps Euler steps (End Matter, spawn and annihilation steps,
  * Euler solver).  s is [nsteps][n_h] and gamma is [nsteps][n_l], row k holding the weights at
  * the left end t = (step0 + k) * dt of step k.  Tables are quantized and bound-checked on the
- * host before anything is launched (QMC_ERR_DT leaves the state untouched); device errors
+ * host before the call changes any state (QMC_ERR_DT or QMC_ERR_ARG for a table leaves the state
+ * untouched; the LDS-resident step may start its first batch into scratch segments while the
+ * later tables are checked, and a failing table cancels it); device errors
  * (QMC_ERR_STORE_CAP, QMC_ERR_SPAWN_CAP, QMC_ERR_COUNT_OVERFLOW) roll the context back to the
  * last good step.  Synchronizes the stream once at the end. */
 int qmc_step(qmc_ctx* ctx, uint32_t nsteps, const double* s, const double* gamma);

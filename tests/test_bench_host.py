@@ -1,6 +1,7 @@
 """Host-side pieces of the benchmark: the error bar behind the time-to-error-bar half of the
 metric, a 95 % bootstrap confidence interval over the replicas (the paper's error bars, End Matter
-on simulation methodology)."""
+on simulation methodology), and the roofline object (the per-step algorithmic bytes, the timed
+class and the class reported beside it)."""
 import numpy as np
 import pytest
 
@@ -47,3 +48,60 @@ def test_error_bar_widest_observable_and_extrapolation():
 
 def test_error_bar_needs_two_replicas():
     assert bench.error_bar(_obs(np.array([0.5]), np.zeros((1, 1))), _W(["Z0"]), 1.0) is None
+
+
+# ---- the roofline object: algorithmic bytes of the survey's per-step unit ----------------------
+
+_COV = dict(steps=100, walker_steps=10 ** 9, key_steps=4_000_000, child_steps=300_000,
+            out_steps=4_100_000, spawn_steps=250_000)
+
+
+def test_step_bytes_are_the_per_step_formula():
+    # 16 B per record: read to spawn, diagonal write-back (8 B), children written and read, read to
+    # annihilate, survivors written
+    want = 16 * 4_000_000 + 8 * 4_000_000 + 2 * 16 * 250_000 + 16 * 4_000_000 + 16 * 4_100_000
+    assert bench.step_bytes(_COV) == want
+    for kind in ("fused", "small", "step"):
+        assert bench.algorithmic_bytes(kind, _COV) == want
+    assert bench.algorithmic_bytes("merge", _COV) == 16 * (4_000_000 + 250_000 + 4_100_000)
+
+
+def test_roofline_of_a_timed_class():
+    r = bench.roofline("step", "no_such_workload", 20.0, 4, _COV)
+    per = bench.step_bytes(_COV) / 4
+    assert r["algorithmic_bytes_per_launch"] == per
+    assert r["avg_launch_ms"] == 5.0 and r["steps_per_launch"] == 25.0
+    assert r["achieved"] == pytest.approx(per / 5e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / bench.HBM_PEAK_GBS)
+    assert r["kernel_us_per_step"] == pytest.approx(200.0)
+    assert r["kernel"] == "streamed_step" and r["traffic"] is None  # no committed summary
+    empty = bench.roofline("small", "no_such_workload", 0.0, 0, dict(_COV, steps=0))
+    assert empty["achieved"] == 0.0 and empty["kernel_us_per_step"] is None
+
+
+class _Ctx:
+    """Stands in for a context's profile totals: (ms, launches, covered) per class."""
+    def __init__(self, totals):
+        self.totals = totals
+
+    def profile_read(self, kind=None):
+        return self.totals[kind]
+
+
+def test_whole_step_class_reports_the_longer_whole_step_kernel():
+    cov_f, cov_s = dict(_COV, steps=1800), dict(_COV, steps=1200)
+    g = _Ctx({"fused": (39.0, 1, cov_f), "small": (10.8, 48, cov_s)})
+    kind, ms, n, cov, other = bench.whole_step_class(g, "small")
+    assert kind == "fused" and ms == 39.0 and n == 1 and cov["steps"] == 1800
+    assert other == {"kernel": "k_small", "ms": 10.8, "launches": 48, "steps_covered": 1200}
+
+
+def test_whole_streamed_step_carries_the_merge_class():
+    g = _Ctx({"step": (50.0, 25, dict(_COV, steps=2500)), "merge": (34.0, 2500,
+                                                                    dict(_COV, steps=2500))})
+    kind, ms, n, cov, other = bench.whole_step_class(g, "step")
+    assert kind == "step" and ms == 50.0 and n == 25
+    m = other["merge_class"]
+    assert m["launches"] == 2500 and m["avg_launch_ms"] == pytest.approx(34.0 / 2500)
+    assert m["algorithmic_bytes_per_launch"] == pytest.approx(
+        bench.algorithmic_bytes("merge", dict(_COV, steps=2500)) / 2500)

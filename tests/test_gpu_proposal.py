@@ -1,6 +1,7 @@
 """GPU parity of the spawn proposals (uniform, heat-bath, int8 MLP scores): the HIP streamed step
 through the C ABI against the CPU oracle, bit for bit, on seeded synthetic inputs.  Both sides
-run their own trajectories from the same initial records and the same MLP weights."""
+run their own trajectories from the same initial records and the same MLP weights, or the oracle
+takes a few steps from states imported from the GPU (the whole ghz20_nm trajectory)."""
 import sys
 
 import numpy as np
@@ -111,6 +112,41 @@ def test_ghz20_nm_mlp_first_steps(B, orc):
         g.step(w.s[k0:k0 + 100], w.gamma[k0:k0 + 100])
         o.step(w.s[k0:k0 + 100], w.gamma[k0:k0 + 100], threads=2)
         _assert_same(g, o, R, f"step {k0 + 100}")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("kind", ["uniform", "heatbath", "mlp"])
+def test_ghz20_nm_all_steps_from_imported_states(B, orc, kind):
+    """The n=20 GHZ workload with each proposal over all 3000 steps (two replicas, K = 4): the GPU
+    runs the whole trajectory; every 250 steps its state is imported into the oracle and both take
+    three steps from there (the draws are keyed on the walkers, so (store, step) is the whole
+    state)."""
+    w = W.config_ghz20_nm()
+    rng = np.random.default_rng(1510)
+    mlp = None
+    if kind == "mlp":
+        # output biases well above the hidden layer's contribution: weights within a small factor
+        # of uniform (a network far from uniform drives the importance weights, and with them the
+        # populations, out of int32 long before t_f -- reported, but not a parity case)
+        w1, b1, w2, b2, sh = W.random_mlp(rng)
+        mlp = (w1, b1, w2, (np.abs(b2) + 4000).astype(np.int32), sh)
+    R = 2
+    g = B.QMC.from_workload(w, store_capacity=1 << 17, spawn_capacity=1 << 20, n_replicas=R)
+    g.set_proposal(kind, 4, mlp)
+    at = 0
+    for T in list(range(250, w.nsteps, 250)) + [w.nsteps - 3]:
+        g.step(w.s[at:T], w.gamma[at:T])
+        o = orc.Oracle(w.n, R, w.seed, w.dt, w.h, w.lops, w.init_keys, w.init_re, w.init_im)
+        o.set_proposal(kind, 4, mlp)
+        for r in range(R):
+            o.import_(r, *g.export(r), step=T)
+        g.step(w.s[T:T + 3], w.gamma[T:T + 3])
+        o.step(w.s[T:T + 3], w.gamma[T:T + 3], threads=2)
+        _assert_same(g, o, R, f"{kind}: steps {T}..{T + 3}")
+        _say(f"  {kind} ghz20_nm steps {T}..{T + 3} equal, {g.counters()['n_occ']} keys")
+        o.close()
+        at = T + 3
+    assert at == w.nsteps
 
 
 def test_overflowing_record_is_reported_like_the_oracle(B, orc):

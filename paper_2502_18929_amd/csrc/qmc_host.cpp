@@ -43,6 +43,10 @@ constexpr uint32_t kMaxChunkSteps = 8000;  // look-back epochs stay distinct wit
 constexpr uint32_t kTableThreads = 8;      // host threads building the step tables of a call
 constexpr uint32_t kSegBuffers = 3;        // segment buffers: N(s-1), N(s), N(s+1) for AB2
 constexpr int kProfClasses = 6;            // kernel classes qmc_profile times
+constexpr size_t kPinMirror = 1024;        // pinned bytes of the counters' copy
+static_assert(sizeof(qmc::Counters) <= kPinMirror && sizeof(qmc::Counters) % 8 == 0,
+              "the counters' copy is written in 8-byte words");
+constexpr uint32_t kFinishOne = 16;        // segments up to which one workgroup ends a chain
 constexpr uint32_t kSmallAutoKeys = 384;   // default of qmc_small_limit
 // batches of the LDS-resident step in one chain (a window of steps)
 constexpr uint32_t kSmallBatches = (kMaxChunkSteps + kSmallBatch - 1) / kSmallBatch;
@@ -194,6 +198,12 @@ struct qmc_ctx {
   std::vector<uint64_t> shift_ref;   // variable shift: N^tot at the last update
   uint8_t* pinned = nullptr;     // table staging: kTableArea bytes, then the window offsets
   uint8_t* pinned_small = nullptr;  // counters and estimator staging
+  // Device addresses of the two pinned buffers: the LDS-resident step reads its step tables
+  // straight from the staging area, and its finishing kernel writes a copy of the counters into
+  // the last kPinMirror bytes of pinned_small (pin_mirror), so neither needs a copy on the stream.
+  uint8_t* pinned_dev = nullptr;
+  uint8_t* pinned_small_dev = nullptr;
+  size_t pin_mirror = 0;
   size_t pinned_small_bytes = 0;
   std::string err;
   bool broken = false;
@@ -660,6 +670,14 @@ int read_counters(qmc_ctx* c, qmc::Counters& out) {
   return QMC_OK;
 }
 
+// The counters as the last finishing kernel of the LDS-resident step left them in pinned memory.
+int read_mirror(qmc_ctx* c, qmc::Counters& out) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(&out, c->pinned_small + c->pin_mirror, sizeof(out));
+  c->last_hc = out;
+  return QMC_OK;
+}
+
 int upload_qshift(qmc_ctx* c, const std::vector<int64_t>& qs) {
   if (qs == c->qshift_dev) return QMC_OK;  // the device already holds these shifts
   c->qshift_dev.clear();
@@ -796,8 +814,12 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
                                hipHostMallocDefault);
   c->pinned_small_bytes = std::max<size_t>(1 << 16, (size_t)c->R * kMaxLookup * 16 + 4096);
   c->pinned_small_bytes = std::max<size_t>(c->pinned_small_bytes, (size_t)c->C * 16 + 4096);
+  c->pin_mirror = align256(c->pinned_small_bytes);
   if (e == hipSuccess)
-    e = hipHostMalloc((void**)&c->pinned_small, c->pinned_small_bytes, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&c->pinned_small, c->pin_mirror + kPinMirror, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0);
+  if (e == hipSuccess)
+    e = hipHostGetDevicePointer((void**)&c->pinned_small_dev, c->pinned_small, 0);
   if (e != hipSuccess) {
     qmc_destroy(c);
     return QMC_ERR_HIP;
@@ -1029,7 +1051,8 @@ struct SmallHead {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
-// The launch fields of the LDS-resident step that stay the same over a chain.
+// The launch fields of the LDS-resident step that stay the same over a chain; its step tables
+// are read from the pinned staging area (dtab, device address).
 void small_setup(qmc_ctx* c, const uint8_t* dtab, SmallLaunch& sl) {
   sl = SmallLaunch{};
   sl.counters = c->counters();
@@ -1067,7 +1090,9 @@ int small_batch(qmc_ctx* c, SmallLaunch& sl, uint32_t tfirst, uint32_t step0, ui
   sl.ok = seg_k + ob * P * segcap;
   sl.ov = seg_v + ob * P * segcap;
   sl.out_n = seg_n + ob * P;
-  sl.tab_off = c->at<uint32_t>(c->L.tab_off) + (size_t)(tfirst + first) * c->C;
+  // the window's table offsets, staged in pinned memory right after the table staging area
+  sl.tab_off = reinterpret_cast<const uint32_t*>(c->pinned_dev + kTableArea) +
+               (size_t)(tfirst + first) * c->C;
   sl.step0 = step0 + first;
   sl.nsteps = steps;
   sl.stats = c->at<uint64_t>(c->L.small_stats) + (size_t)j * c->R * kSmallStats;
@@ -1093,19 +1118,26 @@ int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc,
   const uint64_t rows = (uint64_t)c->R;  // statistics rows of one batch
   qmc::Counters* dcnt = c->counters();
   SmallLaunch sl;
-  small_setup(c, ch.dtab, sl);
+  small_setup(c, c->pinned_dev, sl);
   auto batch = [&](uint32_t j, uint32_t first, uint32_t steps) {
     return small_batch(c, sl, ch.first, step0, j, first, steps);
   };
   // the segments batch jd - 1 wrote into the canonical store and the statistics of batches
   // [0, jd) into the counters; gated on the stop word of `epoch` when stop is given
+  // With few segments one workgroup does it all and leaves a copy of the counters in pinned
+  // memory (read_mirror), so the call's end needs no copy on the stream.
+  const bool one = c->R <= kFinishOne;
   auto finish = [&](uint32_t jd, const unsigned long long* stop, uint32_t epoch) -> int {
     const uint32_t ob = (jd - 1) & 1;
     HIPCHK(c, qmcs_finish(c->stream, seg_k + ob * P * segcap, seg_v + ob * P * segcap,
                           seg_n + ob * P, segcap, c->R, c->sk(0), c->sv(0),
                           &dcnt->n_store[c->cur], dcnt, dstats, (uint32_t)(jd * rows), stop,
-                          epoch));
+                          epoch, one ? 1u : c->R,
+                          one ? c->pinned_small_dev + c->pin_mirror : nullptr));
     return 0;
+  };
+  auto counters_after_finish = [&](qmc::Counters& out) -> int {
+    return one ? read_mirror(c, out) : read_counters(c, out);
   };
   const bool prof = c->prof_whole();
   // One chain over steps [first, first + steps) with its gated gather and commit, then one
@@ -1131,7 +1163,7 @@ int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc,
     if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
     int rc = finish(nb, dstop, epoch);  // also copies the stop word into the counters
     if (rc) return rc;
-    rc = read_counters(c, hc);  // synchronizes the stream
+    rc = counters_after_finish(hc);  // synchronizes the stream
     if (rc) return rc;
     // the head batch and the rest are timed apart: the GPU may wait for the host between them
     if (hd && hd->ev0) defer_timing(c, 4, hd->ev0, hd->ev1, 1);
@@ -1175,7 +1207,7 @@ int run_small(qmc_ctx* c, const Chunk& ch, uint32_t& kd, qmc::Counters& hc,
       }
       kd += rest;
     } else if (jd > 0) {
-      rc = read_counters(c, hc);  // the committed batches
+      rc = counters_after_finish(hc);  // the committed batches
       if (rc) return rc;
     }
   }
@@ -1527,28 +1559,39 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     return rc;
   };
   // Table windows: steps [win0, win1) of this call have their packed tables (all circuits) in
-  // the device table area, at the same offsets as in the pinned staging area, and their offsets
-  // in tab_off ([step][circuit]) / tabB_off; every launch of those steps reuses them.
+  // the pinned staging area and their offsets ([step][circuit], and the AB2 B term's) staged
+  // right after it; the LDS-resident step reads them there.  The fused and streamed kernels read
+  // copies in the device table area (the same offsets) and tab_off / tabB_off, made when a chunk
+  // on those paths first needs them; every launch of those steps reuses them.
   const uint32_t wmax = std::min<uint32_t>(nsteps, kMaxChunkSteps);
   std::vector<uint32_t> offA((size_t)wmax * NC, 0), offB(ab2 ? wmax : 0, 0);
   uint32_t win0 = 0, win1 = 0;
   size_t max_tbytes = 0;
-  auto upload_window = [&](const std::vector<std::pair<size_t, size_t>>& spans) -> int {
-    for (const auto& sp : spans)
+  uint32_t* const po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
+  uint32_t* const pb = po + (size_t)kMaxChunkSteps * NC;
+  std::vector<std::pair<size_t, size_t>> dev_spans;  // staged table bytes to copy to the device
+  bool dev_ready = true;
+  // offsets of steps [from, win1 - win0) of the window into pinned staging
+  auto stage_window = [&](const std::vector<std::pair<size_t, size_t>>& spans, uint32_t from) {
+    const size_t a = (size_t)from * NC, nw = (size_t)(win1 - win0) * NC;
+    if (nw > a) std::memcpy(po + a, offA.data() + a, (nw - a) * 4);
+    if (ab2) std::memcpy(pb, offB.data(), (size_t)(win1 - win0) * 4);
+    dev_spans = spans;
+    dev_ready = false;
+  };
+  auto ensure_device = [&]() -> int {
+    if (dev_ready) return QMC_OK;
+    for (const auto& sp : dev_spans)
       if (sp.second)
         HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab) + sp.first, c->pinned + sp.first,
                                  sp.second, hipMemcpyHostToDevice, c->stream));
-    uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
     const size_t nw = (size_t)(win1 - win0) * NC;
-    std::memcpy(po, offA.data(), nw * 4);
     HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), po, nw * 4, hipMemcpyHostToDevice,
                              c->stream));
-    if (ab2) {
-      uint32_t* pb = po + (size_t)kMaxChunkSteps * NC;
-      std::memcpy(pb, offB.data(), (size_t)(win1 - win0) * 4);
+    if (ab2)
       HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tabB_off), pb, (size_t)(win1 - win0) * 4,
                                hipMemcpyHostToDevice, c->stream));
-    }
+    dev_ready = true;
     return QMC_OK;
   };
   // Packs the tables of step k (all circuits, both AB2 terms) at `bytes` of the staging area
@@ -1575,26 +1618,21 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
   // while it runs.  A later table that fails, or that the step cannot take, only cancels that
   // batch: it writes scratch segments, never the store or the counters.
   SmallHead head;
-  size_t head_bytes = 0;
   const uint32_t B0 = std::max<uint32_t>(2, std::min<uint32_t>(16, nsteps / 4));
   const bool pipe = nsteps >= 8 && nsteps < 512 && !ab2 && !c->prop.kind && c->R <= c->L.P &&
                     (c->path == 3 ||
                      (c->path == 0 && !c->small_off && c->step >= c->streamed_until &&
                       c->n_occ <= fused_max_keys && c->small_limit > 0 &&
                       c->n_occ <= (uint64_t)c->R * c->small_limit));
-  auto prelaunch = [&](size_t used) -> int {
-    HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab), c->pinned, used, hipMemcpyHostToDevice,
-                             c->stream));
-    uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
+  auto prelaunch = [&]() -> int {
+    // the batch reads its tables and offsets from pinned staging
     std::memcpy(po, offA.data(), (size_t)B0 * NC * 4);
-    HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off), po, (size_t)B0 * NC * 4,
-                             hipMemcpyHostToDevice, c->stream));
     std::vector<int64_t> q(2 * (size_t)c->R, 0);
     for (uint32_t r = 0; r < c->R; ++r) q[r] = qs1[r];
     int rc = upload_qshift(c, q);
     if (rc) return rc;
     SmallLaunch sl;
-    small_setup(c, c->at<uint8_t>(c->L.tab), sl);
+    small_setup(c, c->pinned_dev, sl);
     head.epoch = ++c->small_epoch;
     sl.epoch = head.epoch;
     if (c->prof_whole()) {
@@ -1605,7 +1643,6 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
     HIPCHK(c, small_batch(c, sl, 0, c->step, 0, 0, B0));
     if (head.ev1) HIPCHK(c, hipEventRecord(head.ev1, c->stream));
     head.steps = B0;
-    head_bytes = used;
     return QMC_OK;
   };
   // A launched first batch that will not be continued: wait for it, return its events.
@@ -1663,7 +1700,7 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
           q.stored = k + 1;
         if (pipe && nth == 1 && k + 1 == B0 && q.stored == B0 &&
             q.max_bytes <= kPersistTableBytes) {
-          pre_rc = prelaunch(q.used);
+          pre_rc = prelaunch();
           if (pre_rc) return;
         }
       }
@@ -1696,21 +1733,8 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
       }
     }
     if (win1 == 0) return fail(c, QMC_ERR_ARG, "step tables larger than the table area");
-    if (head.steps) {
-      // the head batch's tables and offsets are on the device: the rest of the window
-      const Part& q = parts[0];
-      if (q.used > head_bytes)
-        HIPCHK(c, hipMemcpyAsync(c->at<uint8_t>(c->L.tab) + head_bytes, c->pinned + head_bytes,
-                                 q.used - head_bytes, hipMemcpyHostToDevice, c->stream));
-      uint32_t* po = reinterpret_cast<uint32_t*>(c->pinned + kTableArea);
-      const size_t n0 = (size_t)B0 * NC, nw = (size_t)(win1 - win0) * NC;
-      std::memcpy(po + n0, offA.data() + n0, (nw - n0) * 4);
-      HIPCHK(c, hipMemcpyAsync(c->at<uint32_t>(c->L.tab_off) + n0, po + n0, (nw - n0) * 4,
-                               hipMemcpyHostToDevice, c->stream));
-    } else {
-      int rc = upload_window(spans);
-      if (rc) return rc;
-    }
+    // (the head batch's offsets are staged already and may be read right now)
+    stage_window(spans, head.steps ? B0 : 0u);
   }
   const uint32_t first_step = c->step;
   const bool fused_fits = max_tbytes <= kPersistTableBytes;
@@ -1774,8 +1798,7 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
         ++win1;
       }
       if (win1 == k0) return fail(c, QMC_ERR_ARG, "step tables larger than the table area");
-      int rc = upload_window({{0, bytes}});
-      if (rc) return rc;
+      stage_window({{0, bytes}}, 0u);
     }
     Chunk ch;
     ch.dtab = c->at<uint8_t>(c->L.tab);
@@ -1798,7 +1821,9 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
       }
       continue;
     }
-    int rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);
+    int rc = ensure_device();
+    if (rc) return rc;
+    rc = fused ? run_fused(c, ch, kd, reason, hc) : run_streamed(c, ch, kd, hc);
     if (rc) return rc;
     if (ab2 && kd > 0) {
       // N(s-1) is now on the device; remember the weights of step s-1.

@@ -44,9 +44,12 @@ int qmcs_launch(hipStream_t st, const SmallLaunch* L);
 // canonical store, writes its size to *count and adds nrows rows of per-segment batch statistics
 // to the counters, unless the chain of `epoch` stopped (stop == null: always); with stop given it
 // also copies the stop word into the counters (Counters::small_stop), so that one read of the
-// counters returns both.
+// counters returns both.  n_blocks = 1 (at most 64 segments): one workgroup, and with a mirror
+// (device address of host-visible memory, room for a Counters) the workgroup then writes
+// a copy of the whole Counters there, which the host reads after the stream synchronization.
 int qmcs_finish(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
                 uint64_t segcap, uint32_t n_segments, uint64_t* ck, int2* cv, uint64_t* count,
                 void* counters, const uint64_t* stats, uint32_t nrows,
-                const unsigned long long* stop, uint32_t epoch);
+                const unsigned long long* stop, uint32_t epoch, uint32_t n_blocks,
+                void* mirror);
 }

@@ -473,51 +473,98 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
   }
 }
 
-// The end of a chain (one launch): the last batch's segments into the canonical store, one
-// workgroup per segment, and the statistics of the completed batches into the counters by
-// workgroup 0 -- neither when the chain stopped (stop == null: always); workgroup 0 also copies
-// the stop word into the counters, for the host's one read of them.
+// The end of a chain (one launch): the last batch's segments into the canonical store and the
+// statistics of the completed batches into the counters (by workgroup 0) -- neither when the
+// chain stopped (stop == null: always); workgroup 0 also copies the stop word into the counters,
+// for the host's one read of them.  Either one workgroup per segment, or one workgroup for all
+// of at most kFinishSegs segments (their records copied in one flattened pass), which, given a
+// mirror, then writes the whole counters there (host-visible memory, system-scope stores).
+constexpr uint32_t kFinishSegs = 64;
+
 __global__ __launch_bounds__(256) void k_small_finish(const uint64_t* __restrict__ sk,
                                                       const int2* __restrict__ sv,
                                                       const uint32_t* __restrict__ seg_n,
-                                                      uint64_t segcap, uint64_t* __restrict__ ck,
+                                                      uint64_t segcap, uint32_t n_seg,
+                                                      uint64_t* __restrict__ ck,
                                                       int2* __restrict__ cv, uint64_t* count,
                                                       Counters* cnt, const uint64_t* stats,
                                                       uint32_t nrows,
                                                       const unsigned long long* stop,
-                                                      uint32_t epoch) {
-  __shared__ uint64_t s_off;
+                                                      uint32_t epoch, uint64_t* mirror) {
+  __shared__ uint64_t s_pre[kFinishSegs + 1];
   __shared__ uint32_t s_skip;
   __shared__ unsigned long long s_sum[kSmallStats];
-  const uint32_t p = blockIdx.x, R = gridDim.x;
-  if (threadIdx.x == 0) {
+  const uint32_t b = blockIdx.x, t = threadIdx.x;
+  if (t == 0) {
     s_skip = stop && chain_stopped(stop, epoch);
-    uint64_t o = 0;
-    for (uint32_t q = 0; q < p; ++q) o += seg_n[q];
-    s_off = o;
-    if (!s_skip && p == R - 1) *count = o + seg_n[p];
-    if (stop && p == 0) cnt->small_stop = *stop;
+    if (stop && b == 0) cnt->small_stop = *stop;
   }
-  if (p == 0 && threadIdx.x < (uint32_t)kSmallStats) s_sum[threadIdx.x] = 0;
+  if (b == 0 && t < (uint32_t)kSmallStats) s_sum[t] = 0;
+  if (gridDim.x == 1 && t < n_seg) s_pre[t + 1] = seg_n[t];
   __syncthreads();
-  if (s_skip) return;
-  const uint64_t off = s_off, n = seg_n[p];
-  const uint64_t* k = sk + (uint64_t)p * segcap;
-  const int2* v = sv + (uint64_t)p * segcap;
-  for (uint64_t i = threadIdx.x; i < n; i += 256) {
-    ck[off + i] = k[i];
-    cv[off + i] = v[i];
+  const bool skip = s_skip;
+  if (!skip && gridDim.x == 1) {
+    // all segments here: offsets first, then every record of every segment at once
+    if (t == 0) {
+      s_pre[0] = 0;
+      for (uint32_t q = 0; q < n_seg; ++q) s_pre[q + 1] += s_pre[q];
+      *count = s_pre[n_seg];
+    }
+    __syncthreads();
+    const uint64_t total = s_pre[n_seg];
+    for (uint64_t i = t; i < total; i += 256) {
+      uint32_t lo = 0, hi = n_seg;  // the segment q with s_pre[q] <= i < s_pre[q + 1]
+      while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (s_pre[m] <= i) lo = m; else hi = m;
+      }
+      const uint64_t src = (uint64_t)lo * segcap + (i - s_pre[lo]);
+      ck[i] = sk[src];
+      cv[i] = sv[src];
+    }
+  } else if (!skip) {
+    // segment b: its offset is the sum of the counts before it
+    const uint32_t p = b;
+    __shared__ uint64_t s_off;
+    if (t == 0) {
+      uint64_t o = 0;
+      for (uint32_t q = 0; q < p; ++q) o += seg_n[q];
+      s_off = o;
+      if (p == n_seg - 1) *count = o + seg_n[p];
+    }
+    __syncthreads();
+    const uint64_t off = s_off, n = seg_n[p];
+    const uint64_t* k = sk + (uint64_t)p * segcap;
+    const int2* v = sv + (uint64_t)p * segcap;
+    for (uint64_t i = t; i < n; i += 256) {
+      ck[off + i] = k[i];
+      cv[off + i] = v[i];
+    }
   }
-  if (p != 0) return;  // block-uniform
-  for (uint32_t i = threadIdx.x; i < nrows * (uint32_t)kSmallStats; i += blockDim.x)
-    atomicAdd(&s_sum[i % kSmallStats], (unsigned long long)stats[i]);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    cnt->walker_steps += s_sum[0];
-    cnt->key_steps += s_sum[1];
-    cnt->child_steps += s_sum[2];
-    cnt->out_steps += s_sum[3];
-    cnt->death_steps += s_sum[4];
+  if (b != 0) return;  // block-uniform
+  if (!skip) {
+    for (uint32_t i = t; i < nrows * (uint32_t)kSmallStats; i += blockDim.x)
+      atomicAdd(&s_sum[i % kSmallStats], (unsigned long long)stats[i]);
+    __syncthreads();
+    if (t == 0) {
+      cnt->walker_steps += s_sum[0];
+      cnt->key_steps += s_sum[1];
+      cnt->child_steps += s_sum[2];
+      cnt->out_steps += s_sum[3];
+      cnt->death_steps += s_sum[4];
+    }
+  }
+  if (mirror && gridDim.x == 1) {
+    // every counter write of the chain is done: the earlier kernels', and thread 0's here
+    // (fenced at device scope before the barrier)
+    __threadfence();
+    __syncthreads();
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(cnt);
+    constexpr uint32_t kWords = (uint32_t)(sizeof(Counters) / 8);
+    for (uint32_t i = t; i < kWords; i += blockDim.x)
+      __hip_atomic_store(&mirror[i],
+                         __hip_atomic_load(&w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -564,9 +611,13 @@ int qmcs_launch(hipStream_t st, const SmallLaunch* L) {
 int qmcs_finish(hipStream_t st, const uint64_t* sk, const int2* sv, const uint32_t* seg_n,
                 uint64_t segcap, uint32_t n_segments, uint64_t* ck, int2* cv, uint64_t* count,
                 void* counters, const uint64_t* stats, uint32_t nrows,
-                const unsigned long long* stop, uint32_t epoch) {
-  hipLaunchKernelGGL(k_small_finish, dim3(n_segments), dim3(256), 0, st, sk, sv, seg_n, segcap,
-                     ck, cv, count, (Counters*)counters, stats, nrows, stop, epoch);
+                const unsigned long long* stop, uint32_t epoch, uint32_t n_blocks,
+                void* mirror) {
+  // one workgroup for all only up to kFinishSegs segments, else one per segment
+  const uint32_t g = n_blocks == 1 && n_segments <= kFinishSegs ? 1u : n_segments;
+  hipLaunchKernelGGL(k_small_finish, dim3(g), dim3(256), 0, st, sk, sv, seg_n, segcap,
+                     n_segments, ck, cv, count, (Counters*)counters, stats, nrows, stop, epoch,
+                     g == 1 ? (uint64_t*)mirror : nullptr);
   return (int)hipGetLastError();
 }
 

@@ -107,6 +107,7 @@ struct SmallShared {
   uint32_t nact[2];
   uint32_t nrec[2];
   uint32_t flag[2];
+  uint32_t toff[kSmallBatch];          // table offsets of the batch's steps (this circuit)
 };
 static_assert(kSTab == kSBlock, "one 16-byte word of a step table per thread");
 
@@ -163,16 +164,16 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
     S.pv[0][i] = srcv[base + i];
   }
   // Step tables go through registers: thread t loads the t-th 16 bytes of the next step's table
-  // (a table area of kPersistTableBytes bytes; the device area has that much slack past its end)
-  // at the start of a step and stores them to LDS at its end, so no LDS access of the step waits
-  // for the load.
+  // (a table area of kPersistTableBytes bytes; the table memory has that much slack past its
+  // end) at the start of a step and stores them to LDS at its end, so no LDS access of the step
+  // waits for the load.  The tables may sit in host memory: the batch's table offsets are read
+  // once, into LDS, so each step's prefetch is one read.
+  if (t < A.nsteps) S.toff[t] = A.tab_off[(size_t)t * A.n_circuits + circ];
   auto table_word = [&](uint32_t kk) {
-    const uint4* src = reinterpret_cast<const uint4*>(
-        A.tab_base + A.tab_off[(size_t)kk * A.n_circuits + circ]);
-    return src[t];
+    return reinterpret_cast<const uint4*>(A.tab_base + S.toff[kk])[t];
   };
-  if (A.nsteps > 0) S.tab[0][t] = table_word(0);
-  __syncthreads();  // every thread has read the start flag
+  if (A.nsteps > 0) S.tab[0][t] = reinterpret_cast<const uint4*>(A.tab_base + A.tab_off[circ])[t];
+  __syncthreads();  // every thread has read the start flag; the table offsets are in LDS
   if (t == 0) {
     S.nnew[0] = 0;
     S.nact[0] = 0;
@@ -575,6 +576,7 @@ using namespace qmc;
 extern "C" {
 
 int qmcs_launch(hipStream_t st, const SmallLaunch* L) {
+  if (L->nsteps > kSmallBatch) return (int)hipErrorInvalidValue;  // the batch's offsets in LDS
   SmallArgs a;
   a.ck = L->ck;
   a.cv = L->cv;

@@ -31,16 +31,17 @@ KERNEL_NAMES = {"fused": "k_persist", "small": "k_small", "sort": "k_onesweep",
 # steps), reported with the merge class beside it
 DOMINANT = {"ghz20_nm": "fused", "dd12": "step", "ghz4": "fused", "batch64": "step"}
 DOMINANT_INITIATOR = {"ghz20_nm": "fused", "dd12": "fused", "ghz4": "fused", "batch64": "fused"}
-# every source whose change can alter a kernel's launches or traffic (the host sets the launch
-# configuration), so committed counter numbers are dropped as soon as one of them changes
-KERNEL_SOURCES = ["paper_2502_18929_amd/csrc/qmc_persist.hip",
-                  "paper_2502_18929_amd/csrc/qmc_kernels.hip",
-                  "paper_2502_18929_amd/csrc/qmc_device.hpp",
-                  "paper_2502_18929_amd/csrc/qmc_persist.h",
-                  "paper_2502_18929_amd/csrc/qmc_kernels.h",
-                  "paper_2502_18929_amd/csrc/qmc_small.hip",
-                  "paper_2502_18929_amd/csrc/qmc_small.h",
-                  "paper_2502_18929_amd/csrc/qmc_host.cpp"]
+# every source whose change can alter a kernel class's launches or traffic (the host sets the
+# launch configuration), so committed counter numbers of a class are dropped as soon as one of
+# them changes; which steps a class covered is checked apart (steps per launch)
+_CSRC = "paper_2502_18929_amd/csrc/"
+_SHARED = [_CSRC + "qmc_device.hpp", _CSRC + "qmc_host.cpp"]
+_STREAMED = [_CSRC + "qmc_kernels.hip", _CSRC + "qmc_kernels.h"] + _SHARED
+KERNEL_SOURCES = {
+    "fused": [_CSRC + "qmc_persist.hip", _CSRC + "qmc_persist.h"] + _SHARED,
+    "small": [_CSRC + "qmc_small.hip", _CSRC + "qmc_small.h", _CSRC + "qmc_persist.h"] + _SHARED,
+    "step": _STREAMED, "merge": _STREAMED, "sort": _STREAMED,
+}
 
 
 def step_bytes(cov):
@@ -100,9 +101,9 @@ def error_bar(obs, w, elapsed, seed=0, boot=2000):
             "basis": "measured run" if reached else "extrapolated: replicas x (h / target)^2"}
 
 
-def sources_digest():
+def sources_digest(kind):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kind]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -120,7 +121,7 @@ def profiled_traffic(kind, workload, steps_per_launch):
     m = re.search(r"sources_digest:\s*([0-9a-f]+)", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     c = re.search(r"steps_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or not c or m.group(1) != sources_digest():
+    if not m or not b or not c or m.group(1) != sources_digest(kind):
         return None
     if steps_per_launch is None or abs(float(c.group(1)) - steps_per_launch) > 1e-9:
         return None

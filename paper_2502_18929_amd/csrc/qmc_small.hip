@@ -25,10 +25,12 @@
 // one step, or leaves int32 records the step in the chain's stop word and stops.  The host
 // launches a call's steps as a chain of batches of at most kSmallBatch steps, each reading the
 // segments the one before wrote, then the gather of the last batch's segments into the canonical
-// store and the commit of the statistics; every kernel of the chain does nothing once the stop
-// word is set, so after a stop the last complete batch's segments hold the state, and the host
-// gathers them, runs the steps up to the stop again from there (the results are the same, the
-// draws being keyed on the walkers) and continues with the other step paths.  The stop word is
+// store and the commit of the statistics; a workgroup takes no step at or after the step the stop
+// word records, and the chain's gather and commit do nothing once it is set, so after a stop the
+// recorded step is the earliest at which any replica failed, the last complete batch's segments
+// hold the state, and the host gathers them, runs the steps up to the stop again from there (the
+// results are the same, the draws being keyed on the walkers) and continues with the other step
+// paths.  The stop word is
 // (chain epoch << 32) | ~step, raised with atomicMax: it belongs to a chain only when it carries
 // that chain's epoch (no reset between chains), and within a chain it keeps the earliest step.
 #include "qmc_device.hpp"
@@ -83,6 +85,13 @@ __device__ __forceinline__ void chain_stop(unsigned long long* stop, uint32_t ep
   atomicMax(stop, ((unsigned long long)epoch << 32) | (0xFFFFFFFFu - step));
 }
 
+// Whether stop word `w` stops this chain at or before step s: step s and the later ones are then
+// dropped anyway.  A workgroup still before the recorded step must go on, since one of its own
+// steps before it may be the chain's earliest stop (workgroups advance at different speeds).
+__device__ __forceinline__ bool stopped_by(unsigned long long w, uint32_t epoch, uint32_t s) {
+  return (uint32_t)(w >> 32) == epoch && 0xFFFFFFFFu - (uint32_t)w <= s;
+}
+
 struct SmallShared {
   uint64_t pk[2][kSmallCap];
   int2 pv[2][kSmallCap];
@@ -118,9 +127,11 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
   const KeyLayout kl = A.kl;
   const uint32_t circ = seg / A.rep_per;
   const int64_t qs = A.qshift[seg];
-  // this replica's input records; nothing at all once an earlier batch of the chain stopped
+  // this replica's input records; nothing at all once the chain stopped at or before the first
+  // step of this batch
   if (t == 0) {
-    const uint32_t stop = chain_stopped(A.stop, A.epoch);
+    const uint32_t stop = stopped_by(
+        __hip_atomic_load(A.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), A.epoch, A.step0);
     uint64_t a = 0, e = 0;
     if (!stop && A.ck) {
       const uint64_t n_can = A.cnt->n_store[A.cur];
@@ -187,14 +198,15 @@ __global__ __launch_bounds__(kSBlock) void k_small(SmallArgs A) {
   uint32_t b = 0;  // parent buffer
   uint32_t kdone = 0;
   // The chain's stop word, read by thread 0 during each step and looked at one step later (the
-  // load's latency hidden): once another workgroup has stopped the chain, this batch's results
-  // are dropped anyway, so this workgroup halts too.
+  // load's latency hidden; the recorded step only moves earlier, so an old value is safe): once
+  // another workgroup has stopped the chain at or before the step this one is about to take,
+  // the rest of this workgroup's batch is dropped anyway, so it halts.
   unsigned long long seen = 0;
   bool halted = false;
   for (uint32_t k = 0; k < A.nsteps; ++k) {
     const uint32_t s = A.step0 + k;
     const uint32_t p = k & 1;
-    if (t == 0 && k > 0 && (uint32_t)(seen >> 32) == A.epoch) S.flag[p] = 3;
+    if (t == 0 && k > 0 && stopped_by(seen, A.epoch, s)) S.flag[p] = 3;
     __syncthreads();  // the parents, this step's table and counters
     if (S.flag[p] == 3) {  // block-uniform
       halted = true;

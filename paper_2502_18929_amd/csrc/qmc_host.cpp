@@ -47,6 +47,7 @@ constexpr size_t kPinMirror = 1024;        // pinned bytes of the counters' copy
 static_assert(sizeof(qmc::Counters) <= kPinMirror && sizeof(qmc::Counters) % 8 == 0,
               "the counters' copy is written in 8-byte words");
 constexpr uint32_t kFinishOne = 16;        // segments up to which one workgroup ends a chain
+constexpr uint32_t kHeadMax = 16;          // steps of a chain's early first batch, at most
 constexpr uint32_t kSmallAutoKeys = 384;   // default of qmc_small_limit
 // batches of the LDS-resident step in one chain (a window of steps)
 constexpr uint32_t kSmallBatches = (kMaxChunkSteps + kSmallBatch - 1) / kSmallBatch;
@@ -204,6 +205,10 @@ struct qmc_ctx {
   uint8_t* pinned_dev = nullptr;
   uint8_t* pinned_small_dev = nullptr;
   size_t pin_mirror = 0;
+  // The table offsets of a chain's early first batch (kHeadMax steps x C circuits), in pinned
+  // memory of their own right after the counters' copy: that batch runs while the host still
+  // writes the call's other offsets, and no cache line it reads may hold any of those.
+  size_t pin_head = 0;
   size_t pinned_small_bytes = 0;
   std::string err;
   bool broken = false;
@@ -815,8 +820,10 @@ int qmc_init_batch(const qmc_config* cfg, uint32_t n_circuits, const qmc_model* 
   c->pinned_small_bytes = std::max<size_t>(1 << 16, (size_t)c->R * kMaxLookup * 16 + 4096);
   c->pinned_small_bytes = std::max<size_t>(c->pinned_small_bytes, (size_t)c->C * 16 + 4096);
   c->pin_mirror = align256(c->pinned_small_bytes);
+  c->pin_head = c->pin_mirror + kPinMirror;
   if (e == hipSuccess)
-    e = hipHostMalloc((void**)&c->pinned_small, c->pin_mirror + kPinMirror, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&c->pinned_small,
+                      c->pin_head + align256((size_t)kHeadMax * c->C * 4), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0);
   if (e == hipSuccess)
     e = hipHostGetDevicePointer((void**)&c->pinned_small_dev, c->pinned_small, 0);
@@ -1074,9 +1081,11 @@ void small_setup(qmc_ctx* c, const uint8_t* dtab, SmallLaunch& sl) {
 
 // Batch j of a chain: steps [first, first + steps) of the chunk whose first table is entry
 // tfirst of the offsets and whose first step is step0, from the canonical store (j = 0) or from
-// segment buffer (j - 1) & 1, into segment buffer j & 1, statistics into row block j.
+// segment buffer (j - 1) & 1, into segment buffer j & 1, statistics into row block j.  The
+// table offsets are the window's in pinned staging, or those at head_off (device address, the
+// batch's own steps from its first) when given.
 int small_batch(qmc_ctx* c, SmallLaunch& sl, uint32_t tfirst, uint32_t step0, uint32_t j,
-                uint32_t first, uint32_t steps) {
+                uint32_t first, uint32_t steps, const uint32_t* head_off = nullptr) {
   const uint64_t segcap = c->L.segcap, P = c->L.P;
   uint64_t* seg_k = c->at<uint64_t>(c->L.seg_k);
   int2* seg_v = c->at<int2>(c->L.seg_v);
@@ -1091,8 +1100,9 @@ int small_batch(qmc_ctx* c, SmallLaunch& sl, uint32_t tfirst, uint32_t step0, ui
   sl.ov = seg_v + ob * P * segcap;
   sl.out_n = seg_n + ob * P;
   // the window's table offsets, staged in pinned memory right after the table staging area
-  sl.tab_off = reinterpret_cast<const uint32_t*>(c->pinned_dev + kTableArea) +
-               (size_t)(tfirst + first) * c->C;
+  sl.tab_off = head_off ? head_off
+                       : reinterpret_cast<const uint32_t*>(c->pinned_dev + kTableArea) +
+                             (size_t)(tfirst + first) * c->C;
   sl.step0 = step0 + first;
   sl.nsteps = steps;
   sl.stats = c->at<uint64_t>(c->L.small_stats) + (size_t)j * c->R * kSmallStats;
@@ -1618,15 +1628,16 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
   // while it runs.  A later table that fails, or that the step cannot take, only cancels that
   // batch: it writes scratch segments, never the store or the counters.
   SmallHead head;
-  const uint32_t B0 = std::max<uint32_t>(2, std::min<uint32_t>(16, nsteps / 4));
+  const uint32_t B0 = std::max<uint32_t>(2, std::min<uint32_t>(kHeadMax, nsteps / 4));
   const bool pipe = nsteps >= 8 && nsteps < 512 && !ab2 && !c->prop.kind && c->R <= c->L.P &&
                     (c->path == 3 ||
                      (c->path == 0 && !c->small_off && c->step >= c->streamed_until &&
                       c->n_occ <= fused_max_keys && c->small_limit > 0 &&
                       c->n_occ <= (uint64_t)c->R * c->small_limit));
   auto prelaunch = [&]() -> int {
-    // the batch reads its tables and offsets from pinned staging
-    std::memcpy(po, offA.data(), (size_t)B0 * NC * 4);
+    // the batch reads its tables from pinned staging and its offsets from a pinned area of their
+    // own (pin_head), whose cache lines hold none of the offsets the host is about to write
+    std::memcpy(c->pinned_small + c->pin_head, offA.data(), (size_t)B0 * NC * 4);
     std::vector<int64_t> q(2 * (size_t)c->R, 0);
     for (uint32_t r = 0; r < c->R; ++r) q[r] = qs1[r];
     int rc = upload_qshift(c, q);
@@ -1640,7 +1651,8 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(head.ev0, c->stream));
     }
-    HIPCHK(c, small_batch(c, sl, 0, c->step, 0, 0, B0));
+    HIPCHK(c, small_batch(c, sl, 0, c->step, 0, 0, B0,
+                          reinterpret_cast<const uint32_t*>(c->pinned_small_dev + c->pin_head)));
     if (head.ev1) HIPCHK(c, hipEventRecord(head.ev1, c->stream));
     head.steps = B0;
     return QMC_OK;
@@ -1702,6 +1714,10 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
             q.max_bytes <= kPersistTableBytes) {
           pre_rc = prelaunch();
           if (pre_rc) return;
+          // The launched batch reads kPersistTableBytes from the start of each of its tables
+          // while the host packs the later ones: those start past the last such read, on a cache
+          // line of their own, so no line it brings into the caches holds bytes written later.
+          q.used = (q.used + kPersistTableBytes + 255) & ~(size_t)255;
         }
       }
     };
@@ -1733,8 +1749,8 @@ int step_impl(qmc_ctx* c, uint32_t nsteps, const double* s, const double* gamma)
       }
     }
     if (win1 == 0) return fail(c, QMC_ERR_ARG, "step tables larger than the table area");
-    // (the head batch's offsets are staged already and may be read right now)
-    stage_window(spans, head.steps ? B0 : 0u);
+    // (the head batch reads its own copy of its offsets)
+    stage_window(spans, 0u);
   }
   const uint32_t first_step = c->step;
   const bool fused_fits = max_tbytes <= kPersistTableBytes;

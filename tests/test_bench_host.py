@@ -105,3 +105,25 @@ def test_whole_streamed_step_carries_the_merge_class():
     assert m["launches"] == 2500 and m["avg_launch_ms"] == pytest.approx(34.0 / 2500)
     assert m["algorithmic_bytes_per_launch"] == pytest.approx(
         bench.algorithmic_bytes("merge", dict(_COV, steps=2500)) / 2500)
+
+
+def test_traffic_only_for_the_profiled_steps_and_sources(tmp_path, monkeypatch):
+    """The committed counter bytes of a kernel class are printed only while the class's own
+    sources are the ones profiled and the timed launches cover as many steps each; a change to
+    another class's sources leaves them valid."""
+    for rel in {r for v in bench.KERNEL_SOURCES.values() for r in v}:
+        f = tmp_path / rel
+        f.parent.mkdir(parents=True, exist_ok=True)
+        f.write_text("source of " + rel)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    summary = tmp_path / "profiles" / "k_persist_ghz20_nm_traffic.md"
+    summary.write_text("hbm_bytes_per_launch: 1.5e+09\nsteps_per_launch: 1777\n"
+                       f"sources_digest: {bench.sources_digest('fused')}\n")
+    assert bench.profiled_traffic("fused", "ghz20_nm", 1777.0) == 1.5e9
+    assert bench.profiled_traffic("fused", "ghz20_nm", 20.0) is None
+    assert bench.profiled_traffic("fused", "dd12", 1777.0) is None
+    (tmp_path / "paper_2502_18929_amd/csrc/qmc_small.hip").write_text("changed")
+    assert bench.profiled_traffic("fused", "ghz20_nm", 1777.0) == 1.5e9
+    (tmp_path / "paper_2502_18929_amd/csrc/qmc_host.cpp").write_text("changed")
+    assert bench.profiled_traffic("fused", "ghz20_nm", 1777.0) is None

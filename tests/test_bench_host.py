@@ -50,7 +50,7 @@ def test_error_bar_needs_two_replicas():
     assert bench.error_bar(_obs(np.array([0.5]), np.zeros((1, 1))), _W(["Z0"]), 1.0) is None
 
 
-# ---- the roofline object: algorithmic bytes of the survey's per-step unit ----------------------
+# ---- the roofline object: algorithmic bytes of the per-step unit ---------------------------------
 
 _COV = dict(steps=100, walker_steps=10 ** 9, key_steps=4_000_000, child_steps=300_000,
             out_steps=4_100_000, spawn_steps=250_000)

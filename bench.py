@@ -310,6 +310,8 @@ def main():
                          "the spawn events of a plain run) against uniform, heat-bath and the "
                          "comb: sign angle and the <Z0>(t) error bar at equal wall time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--graphs", action="store_true",
+                    help="capture each chunk of streamed steps into a HIP graph and replay it")
     ap.add_argument("--progress", type=int, default=0,
                     help="print a line to stderr after every this many timed steps (runs the "
                          "timed region in calls of that many steps; 0: one call)")
@@ -340,6 +342,7 @@ def main():
     torch.cuda.set_device(0)
     g = binding.QMC.from_workload(w, store_capacity=store_cap, spawn_capacity=spawn_cap)
     g.set_path(args.path)
+    g.use_graphs(args.graphs)
     g.set_integrator(args.integrator)
     init_min = (binding.initiator_threshold(args.initiator_xi, w.walker_target)
                 if args.initiator_xi else 0)
@@ -365,7 +368,10 @@ def main():
     # warmup: W steps from the initial state under the same instrumentation as the timed steps
     # (the first timed launches of a process otherwise pay the event set-up), then restore the
     # initial state (untimed); the timing totals start again below
-    g.profile(kind)
+    # per-class timing events are not recorded inside captured graphs: with --graphs the chunks
+    # run captured and uninstrumented, and the line carries no roofline
+    prof = None if args.graphs else kind
+    g.profile(prof)
     g.run_workload(w, 0, Wm)
     for r in range(w.n_replicas):
         g.import_(r, *init[r], step=0)
@@ -379,7 +385,7 @@ def main():
     torch.cuda.synchronize()
 
     st0 = g.counters()
-    g.profile(kind)
+    g.profile(prof)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if args.progress > 0:
@@ -391,18 +397,20 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = g.counters()
-    kind, prof_ms, prof_n, cov, other = whole_step_class(g, kind)
-    g.profile(None)
-
     elapsed = t1 - t0
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
     key_steps = st1["key_steps"] - st0["key_steps"]
     value = walker_steps / elapsed
-    roof = roofline(kind, w.name, prof_ms, prof_n, cov)
-    if other and kind == "step":
-        roof.update(other)
-    elif other:
-        roof["other_whole_step_kernel"] = other
+    if prof:
+        kind, prof_ms, prof_n, cov, other = whole_step_class(g, kind)
+        g.profile(None)
+        roof = roofline(kind, w.name, prof_ms, prof_n, cov)
+        if other and kind == "step":
+            roof.update(other)
+        elif other:
+            roof["other_whole_step_kernel"] = other
+    else:
+        roof = None
     obs = g.observe(pauli=[(x, z) for _, x, z, _ in w.pauli_obs], psi=w.psi)
     res = {
         "metric": "walker-steps/sec on 1 GPU at n=20; wall time to fixed error bar vs exact",
@@ -421,7 +429,8 @@ def main():
             "workload": f"{w.name}: n={w.n}, {w.n_replicas} replicas x {w.walker_target:g} "
                         f"walkers, dt={w.dt}, {w.nsteps} steps",
             "n_qubits": w.n, "replicas": w.n_replicas, "walker_target": w.walker_target,
-            "dt": w.dt, "steps_timed": K, "step_path": args.path, "notes": w.notes,
+            "dt": w.dt, "steps_timed": K, "step_path": args.path, "graphs": args.graphs,
+            "notes": w.notes,
             "integrator": args.integrator,
             "initiator": ({"xi": args.initiator_xi, "min_walkers": init_min}
                           if init_min else None),
@@ -578,30 +587,34 @@ def main_batch(args, kind):
     g = binding.QMC.batch(bw.n, bw.n_replicas, bw.seed, bw.dt, circuits,
                           store_capacity=1 << 18, spawn_capacity=1 << 18)
     g.set_path(args.path)
+    g.use_graphs(args.graphs)
     init = [g.export(r) for r in range(g.R)]
     sort_tile = g.tune_sort(0)   # the store re-sort after an x pulse (streamed path)
-    g.profile(kind)              # the warmup under the timed steps' instrumentation
+    prof = None if args.graphs else kind  # captured graphs carry no per-class timing events
+    g.profile(prof)              # the warmup under the timed steps' instrumentation
     g.run_batch_workload(bw, 0, Wm)
     for r in range(g.R):
         g.import_(r, *init[r], step=0)
     torch.cuda.synchronize()
     st0 = g.counters()
-    g.profile(kind)
+    g.profile(prof)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.run_batch_workload(bw, 0, K)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = g.counters()
-    kind, prof_ms, prof_n, cov, other = whole_step_class(g, kind)
-    g.profile(None)
     elapsed = t1 - t0
     walker_steps = st1["walker_steps"] - st0["walker_steps"]
-    roof = roofline(kind, bw.name, prof_ms, prof_n, cov)
-    if other and kind == "step":
-        roof.update(other)
-    elif other:
-        roof["other_whole_step_kernel"] = other
+    roof = None
+    if prof:
+        kind, prof_ms, prof_n, cov, other = whole_step_class(g, kind)
+        g.profile(None)
+        roof = roofline(kind, bw.name, prof_ms, prof_n, cov)
+        if other and kind == "step":
+            roof.update(other)
+        elif other:
+            roof["other_whole_step_kernel"] = other
     obs = g.observe()
     res = {
         "metric": "walker-steps/sec on 1 GPU (batched circuits)",
@@ -613,7 +626,7 @@ def main_batch(args, kind):
                                f" (DD or GHZ), {bw.n_replicas} replicas each, walker targets "
                                f"1e4..1e6, dt={bw.dt}, {bw.nsteps} steps",
                    "circuits": len(bw.circuits), "replicas": bw.n_replicas, "dt": bw.dt,
-                   "steps_timed": K, "step_path": args.path,
+                   "steps_timed": K, "step_path": args.path, "graphs": args.graphs,
                    "parallelism": "1 GPU, all circuits and replicas in one store",
                    "pulse_sort_tile_records_per_thread": sort_tile},
         "key_steps_per_s": (st1["key_steps"] - st0["key_steps"]) / elapsed,
